@@ -1,0 +1,111 @@
+"""Gauss-Seidel smoother, auxiliary V-cycle and the multiplicative ASMG preconditioner (oracle).
+
+* Smoother (Section 4.1): Gauss-Seidel S = (D - L)^(-1), applied in the
+  colour-major ordering of ``colour``. A forward sweep visits colours
+  0..C-1 and updates every unknown i of the colour with
+  x_i <- x_i + (b_i - (A x)_i) / a_ii. The backward sweep (S^T) visits the
+  colours in reverse order.
+* V-cycle (Algorithm 2) on the auxiliary hierarchy. Readings: the residual
+  equation uses f (the paper writes g); the post-smoothing runs nu backward
+  sweeps, so the cycle uses symmetric Gauss-Seidel (Section 5.1, nu = 2); the
+  bottom level l_c is the finest level with at most N_c unknowns, and it is
+  solved exactly with the Cholesky factor (B_0 = A_0^(-1)).
+* ASMG preconditioner B_co (Algorithm 1, eq. (fasp2)), with the update signs read
+  as + (the algorithm prints -; Algorithm 2 uses +):
+      u1 = S r                              (nu_fine forward sweeps from 0)
+      u2 = u1 + Pi Vcycle_J(Pi^T (r - A u1))
+      z  = u2 + S^T (r - A u2)              (nu_fine backward sweeps from u2)
+  This makes I - B_co A = (I - S^T A)(I - Pi B~ Pi^T A)(I - S A). Because
+  S^(-1) + S^(-T) - A = D, B_co = S^T D S + (I - S^T A) Pi B~ Pi^T (I - A S)
+  is symmetric positive definite whenever B~ is.
+
+Pins: on small meshes B_co, formed densely, is symmetric (1e-13) and positive
+definite, and matches the closed form above; a V-cycle on the uniform hierarchy
+of the square is the textbook geometric multigrid of Section 5.1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class Smoother:
+    """Multicolour Gauss-Seidel for one matrix (rows of each colour pre-sliced)."""
+
+    def __init__(self, A, colour, dtype=np.float64):
+        A = A.tocsr().astype(dtype)
+        self.A = A
+        self.dtype = dtype
+        self.diag = A.diagonal().astype(dtype)
+        C = int(colour.max()) + 1 if len(colour) else 0
+        self.rows = [np.nonzero(colour == c)[0] for c in range(C)]
+        self.blocks = [A[r] for r in self.rows]
+        self.dblk = [self.diag[r] for r in self.rows]
+
+    def _pass(self, c, x, b):
+        r = self.rows[c]
+        x[r] = x[r] + (b[r] - self.blocks[c] @ x) / self.dblk[c]
+
+    def forward(self, x, b):
+        for c in range(len(self.rows)):
+            self._pass(c, x, b)
+
+    def backward(self, x, b):
+        for c in range(len(self.rows) - 1, -1, -1):
+            self._pass(c, x, b)
+
+
+class ASMGPreconditioner:
+    """B_co of Algorithm 1 with the V-cycle of Algorithm 2 on the auxiliary levels."""
+
+    def __init__(self, hier, dtype=np.float64, nu_aux=2, nu_fine=1):
+        self.h = hier
+        self.dtype = dtype
+        self.nu_aux = nu_aux
+        self.nu_fine = nu_fine
+        ops = hier.aux
+        self.lc = ops.lc
+        self.J = ops.J
+        self.fine = Smoother(hier.A, hier.colour_fine, dtype)
+        self.aux = {l: Smoother(ops.A[l], hier.colour_aux[l], dtype) for l in range(self.lc + 1, self.J + 1)}
+        self.Aaux = {l: ops.A[l].astype(dtype) for l in ops.A}
+        self.P = {l: ops.P[l].astype(dtype) for l in ops.P}
+        self.PT = {l: ops.P[l].T.tocsr().astype(dtype) for l in ops.P}
+        self.Pi = hier.Pi.astype(dtype)
+        self.PiT = hier.Pi.T.tocsr().astype(dtype)
+        if dtype == np.float64:
+            self._coarse = ops.coarse_solve
+        else:
+            Ac = ops.A[self.lc].toarray()
+            inv = np.linalg.inv(Ac).astype(dtype) if Ac.shape[0] else np.zeros((0, 0), dtype)
+            self._coarse = lambda g: inv @ g
+
+    def vcycle(self, level, g):
+        """Algorithm 2 (B_l applied to g)."""
+        if level == self.lc:
+            return self._coarse(g).astype(self.dtype)
+        S = self.aux[level]
+        A = self.Aaux[level]
+        e = np.zeros_like(g)
+        for _ in range(self.nu_aux):
+            S.forward(e, g)
+        r = g - A @ e
+        e = e + self.P[level] @ self.vcycle(level - 1, self.PT[level] @ r)
+        for _ in range(self.nu_aux):
+            S.backward(e, g)
+        return e
+
+    def apply(self, r):
+        """z = B_co r (Algorithm 1 from u = 0)."""
+        dt = self.dtype
+        r = np.asarray(r).astype(dt)
+        A = self.fine.A
+        u = np.zeros_like(r)
+        for _ in range(self.nu_fine):
+            self.fine.forward(u, r)
+        r1 = r - A @ u
+        u = u + self.Pi @ self.vcycle(self.J, self.PiT @ r1)
+        for _ in range(self.nu_fine):
+            self.fine.backward(u, r)
+        return u
+
+    __call__ = apply

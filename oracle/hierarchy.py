@@ -1,0 +1,54 @@
+"""Everything the solve needs for one mesh, assembled by the oracle modules.
+
+``Hierarchy(coords, elems, kappa)`` builds the fine matrix (``fem``), the closed
+box tree (``cluster``), the level meshes (``auxgrid``), the auxiliary operators
+(``auxops``), the transfer Pi (``transfer``) and the colourings (``colour``).
+``solve(f, tol)`` runs PCG (``pcg``) with B_co (``asmg``).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import asmg, auxgrid, auxops, cluster, colour, fem, pcg, transfer
+
+
+class Hierarchy:
+    def __init__(self, coords, elems, kappa, dirichlet=None, n_min=None, coarse_max_dofs=1024,
+                 colour_seed=0, check_literal=False):
+        coords = np.asarray(coords, dtype=np.float64)
+        elems = np.asarray(elems, dtype=np.int64)
+        self.coords = coords
+        self.elems = elems
+        self.kappa = np.asarray(kappa, dtype=np.float64)
+        self.d = coords.shape[1]
+        self.A, self.dofs = fem.assemble(coords, elems, self.kappa, dirichlet)
+        self.tree = cluster.BoxTree(coords, elems, n_min, check_literal=check_literal)
+        self.meshes = auxgrid.AuxMeshes(self.tree)
+        self.aux = auxops.AuxOperators(self.tree, self.meshes, self.kappa, coarse_max_dofs)
+        self.Pi = transfer.transfer(self.tree, self.meshes, coords, elems, self.dofs)
+        self.colour_fine = colour.greedy_colouring(self.A, colour_seed)
+        self.colour_aux = {l: colour.greedy_colouring(self.aux.A[l], colour_seed)
+                           for l in range(self.aux.lc + 1, self.aux.J + 1)}
+        self._B = {}
+
+    @property
+    def n(self):
+        return len(self.dofs)
+
+    def preconditioner(self, dtype=np.float64, nu_aux=2, nu_fine=1):
+        key = (np.dtype(dtype).name, nu_aux, nu_fine)
+        if key not in self._B:
+            self._B[key] = asmg.ASMGPreconditioner(self, dtype, nu_aux, nu_fine)
+        return self._B[key]
+
+    def solve(self, f, tol=1e-8, max_iter=1000, mixed=False, record=False, nu_aux=2, nu_fine=1):
+        B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine)
+        if mixed:
+            def Bm(r):
+                return B(r.astype(np.float32)).astype(np.float64)
+        else:
+            Bm = B
+        return pcg.pcg(self.A, f, Bm, tol, max_iter, record)
+
+    def level_sizes(self):
+        return {l: self.meshes.level(l).n for l in range(1, self.tree.J + 1)}
