@@ -1,0 +1,173 @@
+/*
+ * asmg.h -- C ABI of the MI355X auxiliary-space multigrid (ASMG) PCG solver.
+ *
+ * Method: Grasedyck, Wang, Xu, "A Nearly Optimal Multigrid Method for General
+ * Unstructured Grids" (arXiv:1410.2153).
+ *   - problem: A u = f, A the P1 stiffness matrix of -div(kappa grad u) with
+ *     homogeneous Dirichlet data (Section 2, eq. (1)-(2));
+ *   - setup: cluster tree of element barycenters (Section 3.1), closure
+ *     (Section 3.2), nested conforming auxiliary grids (Section 3.3), Dirichlet
+ *     auxiliary grids (Section 3.4), auxiliary matrices A_l, prolongations P_l and
+ *     the Scott-Zhang transfer Pi (Section 4.1);
+ *   - solve: CG (Section 5.2) preconditioned by one multiplicative auxiliary
+ *     space cycle (Algorithm 1): Gauss-Seidel on the original grid, transfer
+ *     Pi^T, a V-cycle (Algorithm 2) down the auxiliary hierarchy with a dense
+ *     Cholesky solve at the bottom, transfer Pi, Gauss-Seidel back.
+ *
+ * Conventions
+ *   - All functions return 0 on success or a negative ASMG_E* code; they never
+ *     throw. asmg_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.
+ *   - The caller owns every input buffer; setup copies what it needs and keeps
+ *     no caller pointer. Outputs go to caller-allocated buffers.
+ *   - Host-pointer calls (asmg_solve) copy through the handle's staging buffers.
+ *     *_device calls take device pointers and are ordered on the caller's HIP
+ *     stream (passed as void*; NULL = the null stream); they return once the
+ *     results are in device memory.
+ *   - A handle owns all device memory it uses. It is not thread-safe; distinct
+ *     handles are independent.
+ *   - Unknowns ("DOFs") are the non-Dirichlet vertices in ascending vertex id.
+ *     Vectors f and u have one entry per unknown in that order.
+ */
+#ifndef ASMG_H
+#define ASMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASMG_OK 0
+#define ASMG_EINVAL (-1)    /* invalid argument (shape, index range, kappa <= 0 or NaN, tol <= 0) */
+#define ASMG_ENOCONV (-2)   /* max_iter reached; u holds the last iterate */
+#define ASMG_ENOTSPD (-3)   /* p.Ap <= 0 or r.z <= 0 during CG */
+#define ASMG_ENAN (-4)      /* a NaN/Inf appeared in the iteration */
+#define ASMG_EDEVICE (-5)   /* HIP runtime error, or a device call on a host-only handle */
+#define ASMG_ENOMEM (-6)    /* host or device allocation failed */
+
+#define ASMG_PREC_FP64 0    /* whole solve in FP64 */
+#define ASMG_PREC_MIXED 1   /* B_co (smoothers, transfers, aux V-cycle) in FP32 inside FP64 CG */
+
+typedef struct asmg_s *asmg_handle;
+
+typedef struct {
+  int n_min;           /* cluster leaf size; 0 = 3 in 2-D (Section 3.1), 7 in 3-D */
+  int nu_aux;          /* Gauss-Seidel sweeps before and after the coarse correction (Section 5.1: 2) */
+  int nu_fine;         /* fine Gauss-Seidel sweeps per side of Algorithm 1 (1) */
+  int coarse_max_dofs; /* the V-cycle bottom is the finest level with at most this many unknowns (1024) */
+  int max_iter;        /* PCG iteration cap (1000) */
+  int precision;       /* ASMG_PREC_FP64 or ASMG_PREC_MIXED */
+  uint32_t colour_seed;/* seed of the multicolour ordering (0) */
+  int device;          /* HIP device ordinal; -1 = host-only handle (setup and exports, no solve) */
+  int check_every;     /* PCG iterations between host reads of the device convergence flag (0 = auto) */
+} asmg_options;
+
+/* Fill *opt with the defaults listed above. */
+int asmg_default_options(asmg_options *opt);
+
+/*
+ * Build the hierarchy for one mesh (Sections 3.1-3.4, 4.1) and upload it.
+ *   dim          2 (triangles) or 3 (tetrahedra)
+ *   coords       n_vertices * dim doubles, row-major (vertex-major)
+ *   elems        n_elements * (dim+1) int32, 0-based vertex ids; any orientation;
+ *                a zero-volume element is an error
+ *   kappa        n_elements doubles, finite and > 0 (piecewise constant coefficient)
+ *   dirichlet    n_vertices bytes (nonzero = Dirichlet vertex) or NULL: the
+ *                vertices with a coordinate equal to the bounding-box min or max
+ *   opt          options or NULL for the defaults
+ *   out          receives the handle (NULL on failure)
+ * The auxiliary Dirichlet grids cover the root box, so the domain is expected
+ * to be the bounding box (square/cube), as in the paper's test problem.
+ */
+int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elements,
+               const int32_t *elems, const double *kappa, const uint8_t *dirichlet,
+               const asmg_options *opt, asmg_handle *out);
+
+/* Replace kappa (n_elements, finite, > 0) keeping the tree, grids and patterns:
+ * re-assembles A, A_l and the coarse inverse (Section 4.1), uploads values. */
+int asmg_update_coefficient(asmg_handle h, const double *kappa);
+
+/* Number of unknowns, and the vertex id of each unknown (n int32). */
+int asmg_num_dofs(asmg_handle h, int64_t *n);
+int asmg_dof_vertex(asmg_handle h, int32_t *map);
+
+/*
+ * PCG solve from u_0 = 0 until ||f - A u||_2 <= tol ||f||_2 (recursively updated
+ * residual; the true residual is recomputed in FP64 at exit and, in mixed
+ * precision, CG restarts from it while it is above tol).
+ *   f, u                 n doubles (host pointers)
+ *   iterations           number of products with A (may be NULL)
+ *   true_rel_residual    ||f - A u|| / ||f|| recomputed at exit (may be NULL)
+ * f = 0 returns u = 0 and 0 iterations. Returns ASMG_ENOCONV if max_iter is hit.
+ */
+int asmg_solve(asmg_handle h, const double *f, double tol, double *u, int *iterations,
+               double *true_rel_residual);
+
+/* As asmg_solve with device pointers d_f, d_u (n doubles each) on `stream`. */
+int asmg_solve_device(asmg_handle h, const double *d_f, double tol, double *d_u, int *iterations,
+                      double *true_rel_residual, void *stream);
+
+/* z = B_co r (Algorithm 1 with u_0 = 0): one preconditioner application on
+ * device vectors in unknown order; precision as in asmg_options. */
+int asmg_apply_preconditioner_device(asmg_handle h, const double *d_r, double *d_z, int precision,
+                                     void *stream);
+
+/* y = A x on device vectors in unknown order (FP64; Section 2, eq. (2)). */
+int asmg_matvec_device(asmg_handle h, const double *d_x, double *d_y, void *stream);
+
+/*
+ * Per-element derivative of lam^T A u w.r.t. the log-coefficient m_e
+ * (kappa_e = exp(m_e)): g_e = kappa_e lam_e^T K1_e u_e, K1_e the element
+ * stiffness at kappa = 1 (Section 2). d_u, d_lam: n doubles in unknown order
+ * (Dirichlet values 0); d_g: n_elements doubles. The gradient of
+ * J = 1/2 ||u - u_obs||^2 with A lam = u - u_obs is -g.
+ */
+int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double *d_lam, double *d_g,
+                                 void *stream);
+
+/*
+ * Kernel timing for the bandwidth report: launches kernel `which` `reps` times
+ * on `stream` between two HIP events and returns the mean duration in ms and
+ * the algorithmic bytes one launch moves.
+ *   which: 0 = fine SpMV q = A p (FP64), 1 = fine Gauss-Seidel sweep (all colours),
+ *          2 = one full B_co application, 3 = same as 2 in the precision set at setup
+ */
+int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *stream, double *ms,
+                     double *bytes);
+
+/*
+ * Export of setup objects for checking (works on host-only handles).
+ * `name` selects the array, `level` the auxiliary level where relevant.
+ * If buf is NULL, *count receives the number of elements; otherwise up to
+ * *count elements are written. Element types per name:
+ *   "info"          int64[16]: dim, n_dofs, J, lc, n_levels, nnz(A), nnz(Pi),
+ *                   n_refined, n_leaves, n_colours_fine, n_elements, n_vertices
+ *   "refined"       int64 (level, i_0..i_{d-1}) per refined box, sorted
+ *   "leaves"        int64 (level, i_0..i_{d-1}) per leaf box, sorted
+ *   "keys"          int64 per element and axis (n_elements*dim)
+ *   "level_n"       int64 number of unknowns of every level 1..J
+ *   "level_verts"   int64 integer coordinates (n_verts*dim) of sigma^(level)
+ *   "level_simp"    int64 vertex indices (n_simp*(dim+1)) of sigma^(level)
+ *   "level_dofs"    int64 vertex index of every unknown of sigma^(level)
+ *   "A_rowptr","A_col" int64, "A_val" double      fine matrix, unknown order
+ *   "Al_rowptr","Al_col" int64, "Al_val" double   A_level (lc <= level <= J)
+ *   "P_rowptr","P_col" int64, "P_val" double      P_level (lc < level <= J)
+ *   "Pi_rowptr","Pi_col" int64, "Pi_val" double   Pi (fine unknowns x aux unknowns of level J)
+ *   "colour_fine"   int64 colour of every fine unknown
+ *   "colour_aux"    int64 colour of every unknown of A_level (lc < level <= J)
+ * Returns ASMG_EINVAL for an unknown name or level.
+ */
+int asmg_export(asmg_handle h, const char *name, int level, void *buf, int64_t *count);
+
+/* Free the handle and all its device memory. NULL is ignored. */
+void asmg_destroy(asmg_handle h);
+
+/* Thread-local message of the last failure ("" if none). */
+const char *asmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASMG_H */

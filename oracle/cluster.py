@@ -274,6 +274,7 @@ class BoxTree:
         cluster.
         """
         d = self.d
+        mult = 1 << (KEY_BITS[d] + 1)   # box indices < 2^KEY_BITS: packed codes stay below 2^63
         sums = {}
         levels = sorted({b[0] for b in self.leaves})
         needed = set(range(1, self.J + 1))
@@ -281,7 +282,7 @@ class BoxTree:
             idx = box_of(self.keys, lev, d)
             codes = idx[:, 0].copy()
             for k in range(1, d):
-                codes = codes * (1 << 31) + idx[:, k]
+                codes = codes * mult + idx[:, k]
             u, inv = np.unique(codes, return_inverse=True)
             s = np.zeros(len(u))
             np.add.at(s, inv, kappa)
@@ -293,7 +294,7 @@ class BoxTree:
         def code(b):
             v = b[1]
             for k in range(2, d + 1):
-                v = v * (1 << 31) + b[k]
+                v = v * mult + b[k]
             return v
 
         out = {}

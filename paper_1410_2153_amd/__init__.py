@@ -1,0 +1,243 @@
+"""Python binding of libasmg (include/asmg.h): argument marshalling only.
+
+Every step of the setup and the solve runs in the C++/HIP library. PyTorch is
+used for device memory and streams: device entry points take CUDA/HIP tensors
+and run on torch's current stream. The library must have been built
+(``python -m paper_1410_2153_amd.build`` or ``__graft_entry__.build()``); if it
+is missing, importing this module raises, so a missing extension cannot fall
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libasmg.so")
+
+OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_MIXED = 0, 1
+
+EXPORTED = [
+    "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_num_dofs", "asmg_dof_vertex",
+    "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
+    "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
+]
+
+
+class AsmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"asmg error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_min", ctypes.c_int), ("nu_aux", ctypes.c_int), ("nu_fine", ctypes.c_int),
+                ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libasmg.so not built ({LIB_PATH}); run paper_1410_2153_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    lib.asmg_last_error.restype = ctypes.c_char_p
+    lib.asmg_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.asmg_setup.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.asmg_update_coefficient.argtypes = [P, P]
+    lib.asmg_num_dofs.argtypes = [P, ctypes.POINTER(I64)]
+    lib.asmg_dof_vertex.argtypes = [P, P]
+    lib.asmg_solve.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    lib.asmg_solve_device.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double), P]
+    lib.asmg_apply_preconditioner_device.argtypes = [P, P, P, ctypes.c_int, P]
+    lib.asmg_matvec_device.argtypes = [P, P, P, P]
+    lib.asmg_element_gradient_device.argtypes = [P, P, P, P, P]
+    lib.asmg_time_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.asmg_export.argtypes = [P, ctypes.c_char_p, ctypes.c_int, P, ctypes.POINTER(I64)]
+    lib.asmg_destroy.argtypes = [P]
+    lib.asmg_destroy.restype = None
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise AsmgError(rc, lib.asmg_last_error().decode())
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One mesh: ``asmg_setup`` on construction, ``asmg_destroy`` on close/garbage collection."""
+
+    def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
+                 nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0):
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        elems = np.ascontiguousarray(elems, dtype=np.int32)
+        kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        self.dim = coords.shape[1]
+        self.n_vertices = coords.shape[0]
+        self.n_elements = elems.shape[0]
+        opt = Options()
+        lib.asmg_default_options(ctypes.byref(opt))
+        opt.n_min, opt.nu_aux, opt.nu_fine = n_min, nu_aux, nu_fine
+        opt.coarse_max_dofs, opt.max_iter, opt.precision = coarse_max_dofs, max_iter, precision
+        opt.colour_seed, opt.device, opt.check_every = colour_seed, device, check_every
+        self.precision = precision
+        self.device = device
+        dptr = None
+        if dirichlet is not None:
+            self._dir = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+            dptr = _ptr(self._dir)
+        h = ctypes.c_void_p()
+        _check(lib.asmg_setup(self.dim, self.n_vertices, _ptr(coords), self.n_elements, _ptr(elems), _ptr(kappa),
+                              dptr, ctypes.byref(opt), ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        _check(lib.asmg_num_dofs(self.h, ctypes.byref(n)))
+        self.n = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.asmg_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    # -- host vectors -------------------------------------------------------
+    def dof_vertex(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        _check(lib.asmg_dof_vertex(self.h, _ptr(out)))
+        return out
+
+    def solve(self, f, tol=1e-8, allow_noconv=False):
+        """Host arrays: returns (u, iterations, true relative residual)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        u = np.empty(self.n)
+        it = ctypes.c_int()
+        tr = ctypes.c_double()
+        _check(lib.asmg_solve(self.h, _ptr(f), tol, _ptr(u), ctypes.byref(it), ctypes.byref(tr)),
+               (ENOCONV,) if allow_noconv else ())
+        return u, it.value, tr.value
+
+    def update_coefficient(self, kappa):
+        kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        _check(lib.asmg_update_coefficient(self.h, _ptr(kappa)))
+
+    # -- device tensors (torch) ---------------------------------------------
+    def solve_device(self, f, tol=1e-8, out=None, allow_noconv=False):
+        import torch
+        assert f.is_cuda and f.dtype == torch.float64 and f.is_contiguous() and f.numel() == self.n
+        u = torch.empty_like(f) if out is None else out
+        it = ctypes.c_int()
+        tr = ctypes.c_double()
+        _check(lib.asmg_solve_device(self.h, _tptr(f), tol, _tptr(u), ctypes.byref(it), ctypes.byref(tr), _stream()),
+               (ENOCONV,) if allow_noconv else ())
+        return u, it.value, tr.value
+
+    def apply_preconditioner(self, r, precision=None):
+        import torch
+        assert r.is_cuda and r.dtype == torch.float64 and r.is_contiguous() and r.numel() == self.n
+        z = torch.empty_like(r)
+        prec = self.precision if precision is None else precision
+        _check(lib.asmg_apply_preconditioner_device(self.h, _tptr(r), _tptr(z), prec, _stream()))
+        return z
+
+    def matvec(self, x):
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n
+        y = torch.empty_like(x)
+        _check(lib.asmg_matvec_device(self.h, _tptr(x), _tptr(y), _stream()))
+        return y
+
+    def element_gradient(self, u, lam):
+        import torch
+        g = torch.empty(self.n_elements, dtype=torch.float64, device=u.device)
+        _check(lib.asmg_element_gradient_device(self.h, _tptr(u), _tptr(lam), _tptr(g), _stream()))
+        return g
+
+    def time_kernel(self, which, reps=20, precision=None):
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        prec = self.precision if precision is None else precision
+        _check(lib.asmg_time_kernel(self.h, which, reps, prec, _stream(), ctypes.byref(ms), ctypes.byref(by)))
+        return ms.value, by.value
+
+    # -- exports --------------------------------------------------------------
+    def export(self, name, level=0, dtype=None):
+        cnt = ctypes.c_int64()
+        _check(lib.asmg_export(self.h, name.encode(), level, None, ctypes.byref(cnt)))
+        if dtype is None:
+            dtype = np.float64 if name.endswith("_val") else np.int64
+        buf = np.empty(cnt.value, dtype=dtype)
+        if cnt.value:
+            _check(lib.asmg_export(self.h, name.encode(), level, _ptr(buf), ctypes.byref(cnt)))
+        return buf
+
+    def info(self):
+        v = self.export("info")
+        keys = ["dim", "n", "J", "lc", "n_levels", "nnz_A", "nnz_Pi", "n_refined", "n_leaves", "n_colours_fine",
+                "n_elements", "n_vertices"]
+        return {k: int(x) for k, x in zip(keys, v)}
+
+    def export_csr(self, mat, level=0, shape=None):
+        import scipy.sparse as sp
+        rp = self.export(f"{mat}_rowptr", level)
+        ci = self.export(f"{mat}_col", level)
+        v = self.export(f"{mat}_val", level)
+        n = len(rp) - 1
+        if shape is None:
+            shape = (n, int(ci.max()) + 1 if len(ci) else 0)
+        return sp.csr_matrix((v, ci, rp), shape=shape)
+
+
+class LogCoefficientSolve:
+    """u(m) = A(exp(m))^{-1} f as a torch.autograd.Function over per-element log-coefficients m.
+
+    Forward: coefficient update + PCG solve. Backward: one more PCG solve with the
+    same (symmetric) matrix, A lam = dJ/du, then the element kernel
+    dJ/dm_e = -kappa_e lam_e^T K1_e u_e.
+    """
+
+    @staticmethod
+    def function():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, m, f, solver, tol):
+                solver.update_coefficient(torch.exp(m).detach().cpu().numpy())
+                u, _, _ = solver.solve_device(f.contiguous(), tol)
+                ctx.solver = solver
+                ctx.tol = tol
+                ctx.save_for_backward(u)
+                return u
+
+            @staticmethod
+            def backward(ctx, gu):
+                (u,) = ctx.saved_tensors
+                lam, _, _ = ctx.solver.solve_device(gu.contiguous(), ctx.tol)
+                g = ctx.solver.element_gradient(u, lam)
+                return -g, None, None, None
+
+        return _Fn

@@ -1,0 +1,48 @@
+"""Build the HIP/C++ shared library libasmg.so for gfx950 (in-tree, under _lib/).
+
+Sources: csrc/setup.cpp (host setup), csrc/api.cpp (C ABI), csrc/device.hip
+(kernels and PCG driver). The host setup is compiled without floating-point
+contraction, so barycenters and box keys are plain IEEE operations.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_lib")
+LIB = os.path.join(OUT_DIR, "libasmg.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+# packed FP32 instructions are disabled for device code (hipcc makes them from plain float code)
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    objs = []
+    for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("api.cpp", [])):
+        obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
+        _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    obj = os.path.join(OUT_DIR, "device.o")
+    _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", os.path.join(CSRC, "device.hip"), "-o", obj])
+    objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,294 @@
+// C ABI (include/asmg.h): argument checks, error codes, exports of setup objects.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/asmg.h"
+#include "device.hpp"
+#include "setup.hpp"
+
+using namespace asmg;
+
+struct asmg_s {
+  Hierarchy h;
+  Device *dev = nullptr;
+};
+
+static thread_local std::string g_err;
+
+static int set_err(int code, const std::string &m) {
+  g_err = m;
+  return code;
+}
+
+#define ASMG_TRY(...)                                       \
+  try {                                                     \
+    __VA_ARGS__                                             \
+  } catch (const AsmgError &e) {                            \
+    return set_err(e.code, e.msg);                          \
+  } catch (const std::bad_alloc &) {                        \
+    return set_err(ASMG_ENOMEM, "host allocation failed");  \
+  } catch (const std::exception &e) {                       \
+    return set_err(ASMG_EDEVICE, e.what());                 \
+  }
+
+// --------------------------------------------------------------------------
+// exports
+// --------------------------------------------------------------------------
+
+template <class T>
+static int put(const std::vector<T> &src, void *buf, int64_t *count) {
+  if (!buf) {
+    *count = (int64_t)src.size();
+    return ASMG_OK;
+  }
+  int64_t m = std::min<int64_t>(*count, (int64_t)src.size());
+  std::memcpy(buf, src.data(), (size_t)m * sizeof(T));
+  *count = m;
+  return ASMG_OK;
+}
+
+static std::vector<int64_t> boxes_tuples(const Hierarchy &h, std::vector<BoxCode> v) {
+  const int d = h.d;
+  std::vector<std::vector<int64_t>> t;
+  for (BoxCode b : v) {
+    std::vector<int64_t> x(d + 1);
+    x[0] = box_level(b, d);
+    box_index(b, d, &x[1]);
+    t.push_back(x);
+  }
+  std::sort(t.begin(), t.end());
+  std::vector<int64_t> out;
+  for (auto &x : t) out.insert(out.end(), x.begin(), x.end());
+  return out;
+}
+
+static int put_csr(const Csr &A, const std::string &part, void *buf, int64_t *count) {
+  if (part == "rowptr") return put(A.rp, buf, count);
+  if (part == "col") {
+    std::vector<int64_t> c(A.ci.begin(), A.ci.end());
+    return put(c, buf, count);
+  }
+  return put(A.v, buf, count);
+}
+
+
+extern "C" {
+
+const char *asmg_last_error(void) { return g_err.c_str(); }
+
+int asmg_default_options(asmg_options *o) {
+  if (!o) return set_err(ASMG_EINVAL, "null options");
+  o->n_min = 0;
+  o->nu_aux = 2;
+  o->nu_fine = 1;
+  o->coarse_max_dofs = 1024;
+  o->max_iter = 1000;
+  o->precision = ASMG_PREC_FP64;
+  o->colour_seed = 0;
+  o->device = 0;
+  o->check_every = 0;
+  return ASMG_OK;
+}
+
+int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elements, const int32_t *elems,
+               const double *kappa, const uint8_t *dirichlet, const asmg_options *opt, asmg_handle *out) {
+  if (!out) return set_err(ASMG_EINVAL, "null output handle");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return set_err(ASMG_EINVAL, "dim must be 2 or 3");
+  if (n_vertices <= 0 || n_elements <= 0 || !coords || !elems || !kappa)
+    return set_err(ASMG_EINVAL, "empty mesh or null array");
+  if (n_vertices > INT32_MAX) return set_err(ASMG_EINVAL, "too many vertices");
+  asmg_options o;
+  asmg_default_options(&o);
+  if (opt) o = *opt;
+  if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
+      (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0)
+    return set_err(ASMG_EINVAL, "invalid options");
+  for (int64_t i = 0; i < n_vertices * dim; ++i)
+    if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
+  for (int64_t i = 0; i < n_elements * (dim + 1); ++i)
+    if (elems[i] < 0 || elems[i] >= n_vertices) return set_err(ASMG_EINVAL, "element vertex id out of range");
+  for (int64_t e = 0; e < n_elements; ++e)
+    if (!(kappa[e] > 0) || !std::isfinite(kappa[e])) return set_err(ASMG_EINVAL, "kappa must be finite and > 0");
+  asmg_s *H = nullptr;
+  ASMG_TRY({
+    H = new asmg_s();
+    Hierarchy &h = H->h;
+    h.d = dim;
+    h.nv = n_vertices;
+    h.ne = n_elements;
+    h.opt = o;
+    h.coords.assign(coords, coords + n_vertices * dim);
+    h.elems.assign(elems, elems + n_elements * (dim + 1));
+    h.kappa.assign(kappa, kappa + n_elements);
+    if (dirichlet) h.dirichlet.assign(dirichlet, dirichlet + n_vertices);
+    build_fine(h);
+    build_tree(h);
+    build_levels(h);
+    build_transfer(h);
+    build_colourings(h);
+    build_coarse(h);
+    if (o.device >= 0) H->dev = device_create(h, o.device);
+    *out = H;
+    return ASMG_OK;
+  })
+}
+
+int asmg_update_coefficient(asmg_handle H, const double *kappa) {
+  if (!H || !kappa) return set_err(ASMG_EINVAL, "null argument");
+  Hierarchy &h = H->h;
+  for (int64_t e = 0; e < h.ne; ++e)
+    if (!(kappa[e] > 0) || !std::isfinite(kappa[e])) return set_err(ASMG_EINVAL, "kappa must be finite and > 0");
+  ASMG_TRY({
+    h.kappa.assign(kappa, kappa + h.ne);
+    assemble_fine_values(h);
+    assemble_aux_values(h);
+    build_coarse(h);
+    if (H->dev) device_update_values(H->dev, h);
+    return ASMG_OK;
+  })
+}
+
+int asmg_num_dofs(asmg_handle H, int64_t *n) {
+  if (!H || !n) return set_err(ASMG_EINVAL, "null argument");
+  *n = H->h.n();
+  return ASMG_OK;
+}
+
+int asmg_dof_vertex(asmg_handle H, int32_t *map) {
+  if (!H || !map) return set_err(ASMG_EINVAL, "null argument");
+  for (int64_t i = 0; i < H->h.n(); ++i) map[i] = (int32_t)H->h.dofs[i];
+  return ASMG_OK;
+}
+
+static int need_dev(asmg_handle H) {
+  if (!H) return set_err(ASMG_EINVAL, "null handle");
+  if (!H->dev) return set_err(ASMG_EDEVICE, "host-only handle (options.device = -1)");
+  return ASMG_OK;
+}
+
+int asmg_solve(asmg_handle H, const double *f, double tol, double *u, int *iterations, double *true_rel) {
+  if (int r = need_dev(H)) return r;
+  if (!f || !u) return set_err(ASMG_EINVAL, "null vector");
+  if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
+  ASMG_TRY({
+    int rc = device_solve_host(H->dev, f, tol, u, iterations, true_rel);
+    if (rc) set_err(rc, "solve did not converge or broke down");
+    return rc;
+  })
+}
+
+int asmg_solve_device(asmg_handle H, const double *d_f, double tol, double *d_u, int *iterations, double *true_rel,
+                      void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_f || !d_u) return set_err(ASMG_EINVAL, "null vector");
+  if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
+  ASMG_TRY({
+    int rc = device_solve(H->dev, d_f, tol, d_u, iterations, true_rel, stream);
+    if (rc) set_err(rc, "solve did not converge or broke down");
+    return rc;
+  })
+}
+
+int asmg_apply_preconditioner_device(asmg_handle H, const double *d_r, double *d_z, int precision, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_r || !d_z || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED))
+    return set_err(ASMG_EINVAL, "bad argument");
+  ASMG_TRY({ return device_apply_B(H->dev, d_r, d_z, precision, stream); })
+}
+
+int asmg_matvec_device(asmg_handle H, const double *d_x, double *d_y, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_x || !d_y) return set_err(ASMG_EINVAL, "null vector");
+  ASMG_TRY({ return device_matvec(H->dev, d_x, d_y, stream); })
+}
+
+int asmg_element_gradient_device(asmg_handle H, const double *d_u, const double *d_lam, double *d_g, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_u || !d_lam || !d_g) return set_err(ASMG_EINVAL, "null vector");
+  ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, stream); })
+}
+
+int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
+  if (int r = need_dev(H)) return r;
+  if (which < 0 || which > 3 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
+  ASMG_TRY({ return device_time_kernel(H->dev, which, reps, precision, stream, ms, bytes); })
+}
+
+void asmg_destroy(asmg_handle H) {
+  if (!H) return;
+  if (H->dev) device_destroy(H->dev);
+  delete H;
+}
+
+int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t *count) {
+  if (!H || !name_c || !count) return set_err(ASMG_EINVAL, "null argument");
+  Hierarchy &h = H->h;
+  const std::string name(name_c);
+  ASMG_TRY({
+    if (name == "info") {
+      std::vector<int64_t> v(16, 0);
+      v[0] = h.d;
+      v[1] = h.n();
+      v[2] = h.J;
+      v[3] = h.lc;
+      v[4] = h.J - h.lc + 1;
+      v[5] = h.A.nnz();
+      v[6] = h.Pi.nnz();
+      v[7] = (int64_t)h.R.size();
+      v[8] = (int64_t)h.leaves.size();
+      v[9] = h.colour_fine.empty() ? 0 : *std::max_element(h.colour_fine.begin(), h.colour_fine.end()) + 1;
+      v[10] = h.ne;
+      v[11] = h.nv;
+      return put(v, buf, count);
+    }
+    if (name == "refined") return put(boxes_tuples(h, std::vector<BoxCode>(h.R.begin(), h.R.end())), buf, count);
+    if (name == "leaves") return put(boxes_tuples(h, h.leaves), buf, count);
+    if (name == "keys") return put(h.keys, buf, count);
+    if (name == "level_n") {
+      std::vector<int64_t> v(h.J);
+      for (int l = 1; l <= h.J; ++l) v[l - 1] = level_mesh(h, l).n();
+      return put(v, buf, count);
+    }
+    if (name == "colour_fine") {
+      std::vector<int64_t> c(h.colour_fine.begin(), h.colour_fine.end());
+      return put(c, buf, count);
+    }
+    if (name.rfind("level_", 0) == 0 || name == "colour_aux" || name.rfind("Al_", 0) == 0 ||
+        name.rfind("P_", 0) == 0) {
+      if (level < 1 || level > h.J) return set_err(ASMG_EINVAL, "level out of range");
+    }
+    if (name == "level_verts") return put(level_mesh(h, level).verts, buf, count);
+    if (name == "level_simp") return put(level_mesh(h, level).simp, buf, count);
+    if (name == "level_dofs") return put(level_mesh(h, level).dof_vert, buf, count);
+    if (name == "colour_aux") {
+      auto it = h.colour_aux.find(level);
+      if (it == h.colour_aux.end()) return set_err(ASMG_EINVAL, "no colouring on that level");
+      std::vector<int64_t> c(it->second.begin(), it->second.end());
+      return put(c, buf, count);
+    }
+    auto us = name.find('_');
+    if (us != std::string::npos) {
+      const std::string mat = name.substr(0, us), part = name.substr(us + 1);
+      if (part == "rowptr" || part == "col" || part == "val") {
+        if (mat == "A") return put_csr(h.A, part, buf, count);
+        if (mat == "Pi") return put_csr(h.Pi, part, buf, count);
+        if (mat == "Al") {
+          auto it = h.Al.find(level);
+          if (it == h.Al.end()) return set_err(ASMG_EINVAL, "no A_l on that level");
+          return put_csr(it->second, part, buf, count);
+        }
+        if (mat == "P") {
+          auto it = h.P.find(level);
+          if (it == h.P.end()) return set_err(ASMG_EINVAL, "no P_l on that level");
+          return put_csr(it->second, part, buf, count);
+        }
+      }
+    }
+    return set_err(ASMG_EINVAL, "unknown export name: " + name);
+  })
+}
+
+}  // extern "C"

@@ -1,0 +1,1199 @@
+// Device side of the ASMG-PCG solve on gfx950 (CDNA4, wave64).
+//
+// Layout: every level (the original grid and the auxiliary levels above the
+// bottom) is renumbered colour-major (rows of colour 0 first, ascending unknown
+// id inside a colour), so one Gauss-Seidel colour pass is a contiguous row range.
+// Matrices are CSR with int32 row pointers and columns, the diagonal held apart
+// (diag and 1/diag), values in FP64 and FP32 copies. Transfers (Pi, Pi^T, P_l,
+// P_l^T) are stored explicitly in the internal numbering. The bottom level keeps
+// the unknown order and holds the explicit inverse of its matrix (from the
+// Cholesky factor built on the host).
+//
+// Kernels: row-group CSR (LPR lanes per row, LPR in {2,4,8,16}, 256-thread
+// blocks) for the Gauss-Seidel colour pass, the residual and the transfer
+// products; wave-per-row dense GEMV at the bottom; fused CG vector kernels
+// whose block partial sums are reduced by the last block to finish (fixed
+// summation order, so results are reproducible run to run). Every kernel of an
+// iteration reads a device-side `done` flag first and returns if it is set, so
+// the host may enqueue several iterations ahead and the iteration count stays
+// exact.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "device.hpp"
+
+namespace asmg {
+
+#define HIPCHECK(x)                                                                                    \
+  do {                                                                                                 \
+    hipError_t e_ = (x);                                                                               \
+    if (e_ != hipSuccess) throw AsmgError{ASMG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+static constexpr int BS = 256;
+
+// ---------------------------------------------------------------------------
+// device control block for PCG
+// ---------------------------------------------------------------------------
+
+struct Ctl {
+  double rho, pq, rr, alpha, beta, fnorm2, tol2, rz, tr;
+  int iter, done, status, maxit, first, pad;
+  unsigned ticket;
+};
+
+enum { ST_OK = 0, ST_NOTSPD = 1, ST_NAN = 2, ST_NOCONV = 3 };
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+template <int W, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
+// sum over a 256-thread block; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sm[BS / 64];
+  v = group_sum<64>(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < BS / 64; ++i) r += sm[i];
+  }
+  return r;
+}
+
+// Store this block's partial; return true in every thread of the last block to
+// finish. The last block then reads all partials (agent-scope acquire).
+__device__ __forceinline__ bool publish_partial(double v, double *partials, unsigned *ticket) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return last;
+}
+
+// deterministic sum of nb partials by one block; valid in thread 0
+__device__ __forceinline__ double reduce_partials(const double *partials, int nb) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS)
+    s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum(s);
+}
+
+// ---------------------------------------------------------------------------
+// sparse kernels
+// ---------------------------------------------------------------------------
+
+template <int LPR, class T>
+__device__ __forceinline__ T row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                     const T *__restrict__ av, const T *__restrict__ x, int row, bool act,
+                                     int lane) {
+  T s = 0;
+  if (act) {
+    const int b = rp[row], e = rp[row + 1];
+    for (int k = b + lane; k < e; k += LPR) s += av[k] * x[ci[k]];
+  }
+  return group_sum<LPR>(s);
+}
+
+// one Gauss-Seidel colour pass: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii for rows [r0, r1)
+template <int LPR, class T>
+__global__ __launch_bounds__(BS) void k_gs(int r0, int r1, const int *__restrict__ rp, const int *__restrict__ ci,
+                                           const T *__restrict__ av, const T *__restrict__ invd,
+                                           const T *__restrict__ b, T *__restrict__ x, const int *__restrict__ done) {
+  if (*done) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = r0 + t / LPR, lane = t % LPR;
+  const bool act = row < r1;
+  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
+  if (act && lane == 0) x[row] = (b[row] - s) * invd[row];
+}
+
+// first colour pass of a sweep that starts from x = 0: colour-0 rows get b_i / a_ii, all other rows 0
+template <class T>
+__global__ __launch_bounds__(BS) void k_gs_first(int n, int c0, const T *__restrict__ b, const T *__restrict__ invd,
+                                                 T *__restrict__ x, const int *__restrict__ done) {
+  if (*done) return;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) x[i] = i < c0 ? b[i] * invd[i] : T(0);
+}
+
+// mixed precision: first pass of the fine sweep also rounds the FP64 right-hand side to FP32
+__global__ __launch_bounds__(BS) void k_gs_first_cvt(int n, int c0, const double *__restrict__ r64,
+                                                     float *__restrict__ b32, const float *__restrict__ invd,
+                                                     float *__restrict__ x, const int *__restrict__ done) {
+  if (*done) return;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) {
+    const float bi = (float)r64[i];
+    b32[i] = bi;
+    x[i] = i < c0 ? bi * invd[i] : 0.0f;
+  }
+}
+
+// residual r = b - D x - A_off x
+template <int LPR, class T>
+__global__ __launch_bounds__(BS) void k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const T *__restrict__ av, const T *__restrict__ dg,
+                                                 const T *__restrict__ b, const T *__restrict__ x,
+                                                 T *__restrict__ r, const int *__restrict__ done) {
+  if (*done) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
+  if (act && lane == 0) r[row] = b[row] - dg[row] * x[row] - s;
+}
+
+// y = A x (ADD = 0) or y += A x (ADD = 1), A a transfer matrix (no diagonal part)
+template <int LPR, int ADD, class T>
+__global__ __launch_bounds__(BS) void k_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                             const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y,
+                                             const int *__restrict__ done) {
+  if (*done) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
+  if (act && lane == 0) y[row] = ADD ? y[row] + s : s;
+}
+
+// dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
+template <class T>
+__global__ __launch_bounds__(BS) void k_gemv(int n, const T *__restrict__ M, const T *__restrict__ g,
+                                             T *__restrict__ y, const int *__restrict__ done) {
+  if (*done) return;
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  T s = 0;
+  if (row < n) {
+    const T *m = M + (size_t)row * n;
+    for (int j = lane; j < n; j += 64) s += m[j] * g[j];
+  }
+  s = group_sum<64>(s);
+  if (row < n && lane == 0) y[row] = s;
+}
+
+// ---------------------------------------------------------------------------
+// PCG kernels (FP64 on the original grid)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BS) void k_gather(int n, const int *__restrict__ perm, const double *__restrict__ src,
+                                               double *__restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ __launch_bounds__(BS) void k_scatter(int n, const int *__restrict__ perm, const double *__restrict__ src,
+                                                double *__restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) dst[perm[i]] = src[i];
+}
+
+template <class T>
+__global__ __launch_bounds__(BS) void k_scatter_cvt(int n, const int *__restrict__ perm, const T *__restrict__ src,
+                                                    double *__restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) dst[perm[i]] = (double)src[i];
+}
+
+// r = f, u = 0, p = 0, ||f||^2 -> ctl
+__global__ __launch_bounds__(BS) void k_cg_init(int n, const double *__restrict__ f, double *__restrict__ r,
+                                                double *__restrict__ u, double *__restrict__ p, double tol,
+                                                int maxit, Ctl *ctl, double *partials) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double fi = f[i];
+    r[i] = fi;
+    u[i] = 0.0;
+    p[i] = 0.0;
+    v = fi * fi;
+  }
+  const double s = block_sum(v);
+  if (publish_partial(s, partials, &ctl->ticket)) {
+    const double t = reduce_partials(partials, gridDim.x);
+    if (threadIdx.x == 0) {
+      ctl->fnorm2 = t;
+      ctl->tol2 = tol * tol * t;
+      ctl->iter = 0;
+      ctl->status = ST_OK;
+      ctl->done = (t == 0.0) ? 1 : 0;
+      ctl->first = 1;
+      ctl->maxit = maxit;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// restart from the true residual: r = f - A u, p = 0 (mixed precision)
+template <int LPR>
+__global__ __launch_bounds__(BS) void k_cg_restart(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                   const double *__restrict__ av, const double *__restrict__ dg,
+                                                   const double *__restrict__ f, const double *__restrict__ u,
+                                                   double *__restrict__ r, double *__restrict__ p, Ctl *ctl) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const double s = row_dot<LPR>(rp, ci, av, u, row, act, lane);
+  if (act && lane == 0) {
+    r[row] = f[row] - dg[row] * u[row] - s;
+    p[row] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->done = 0;
+    ctl->first = 1;
+  }
+}
+
+// ||f - A u||^2 -> ctl->tr
+template <int LPR>
+__global__ __launch_bounds__(BS) void k_true_res(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const double *__restrict__ av, const double *__restrict__ dg,
+                                                 const double *__restrict__ f, const double *__restrict__ u,
+                                                 Ctl *ctl, double *partials) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const double s = row_dot<LPR>(rp, ci, av, u, row, act, lane);
+  double v = 0.0;
+  if (act && lane == 0) {
+    const double e = f[row] - dg[row] * u[row] - s;
+    v = e * e;
+  }
+  const double bsum = block_sum(v);
+  if (publish_partial(bsum, partials, &ctl->ticket)) {
+    const double tt = reduce_partials(partials, gridDim.x);
+    if (threadIdx.x == 0) {
+      ctl->tr = tt;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// q = A p, p.q -> alpha = rho / p.q, iteration count
+template <int LPR>
+__global__ __launch_bounds__(BS) void k_cg_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                const double *__restrict__ av, const double *__restrict__ dg,
+                                                const double *__restrict__ p, double *__restrict__ q, Ctl *ctl,
+                                                double *partials) {
+  if (ctl->done) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const double s = row_dot<LPR>(rp, ci, av, p, row, act, lane);
+  double v = 0.0;
+  if (act && lane == 0) {
+    const double pi = p[row];
+    const double qi = dg[row] * pi + s;
+    q[row] = qi;
+    v = pi * qi;
+  }
+  const double bsum = block_sum(v);
+  if (publish_partial(bsum, partials, &ctl->ticket)) {
+    const double pq = reduce_partials(partials, gridDim.x);
+    if (threadIdx.x == 0) {
+      ctl->pq = pq;
+      ctl->iter += 1;
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        ctl->status = isfinite(pq) ? ST_NOTSPD : ST_NAN;
+        ctl->done = 1;
+      } else {
+        ctl->alpha = ctl->rho / pq;
+      }
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// u += alpha p, r -= alpha q, ||r||^2 -> convergence flag
+__global__ __launch_bounds__(BS) void k_cg_axpy(int n, double *__restrict__ u, double *__restrict__ r,
+                                                const double *__restrict__ p, const double *__restrict__ q, Ctl *ctl,
+                                                double *partials) {
+  if (ctl->done) return;
+  const double alpha = ctl->alpha;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    u[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v = ri * ri;
+  }
+  const double bsum = block_sum(v);
+  if (publish_partial(bsum, partials, &ctl->ticket)) {
+    const double rr = reduce_partials(partials, gridDim.x);
+    if (threadIdx.x == 0) {
+      ctl->rr = rr;
+      if (!isfinite(rr)) {
+        ctl->status = ST_NAN;
+        ctl->done = 1;
+      } else if (rr <= ctl->tol2) {
+        ctl->done = 1;
+      } else if (ctl->iter >= ctl->maxit) {
+        ctl->status = ST_NOCONV;
+        ctl->done = 1;
+      }
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// rho' = r.z (z = B_co r in precision T) -> beta
+template <class T>
+__global__ __launch_bounds__(BS) void k_cg_rz(int n, const double *__restrict__ r, const T *__restrict__ z, Ctl *ctl,
+                                              double *partials) {
+  if (ctl->done) return;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  const double v = i < n ? r[i] * (double)z[i] : 0.0;
+  const double bsum = block_sum(v);
+  if (publish_partial(bsum, partials, &ctl->ticket)) {
+    const double rz = reduce_partials(partials, gridDim.x);
+    if (threadIdx.x == 0) {
+      ctl->rz = rz;
+      if (!(rz > 0.0) || !isfinite(rz)) {
+        ctl->status = isfinite(rz) ? ST_NOTSPD : ST_NAN;
+        ctl->done = 1;
+      } else if (ctl->first) {
+        ctl->beta = 0.0;
+        ctl->rho = rz;
+        ctl->first = 0;
+      } else {
+        ctl->beta = rz / ctl->rho;
+        ctl->rho = rz;
+      }
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// p = z + beta p
+template <class T>
+__global__ __launch_bounds__(BS) void k_cg_p(int n, const T *__restrict__ z, double *__restrict__ p, const Ctl *ctl) {
+  if (ctl->done) return;
+  const double beta = ctl->beta;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) p[i] = (double)z[i] + beta * p[i];
+}
+
+// plain y = A x (diag + off), for the matvec entry point
+template <int LPR>
+__global__ __launch_bounds__(BS) void k_matvec(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                               const double *__restrict__ av, const double *__restrict__ dg,
+                                               const double *__restrict__ x, double *__restrict__ y) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int row = t / LPR, lane = t % LPR;
+  const bool act = row < n;
+  const double s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
+  if (act && lane == 0) y[row] = dg[row] * x[row] + s;
+}
+
+// per-element g_e = kappa_e lam_e^T K1_e u_e (u, lam per unknown in unknown order)
+template <int D>
+__global__ __launch_bounds__(BS) void k_elem_grad(int ne, const double *__restrict__ coords,
+                                                  const int *__restrict__ elems, const double *__restrict__ kappa,
+                                                  const int *__restrict__ dof_of_vertex, const double *__restrict__ u,
+                                                  const double *__restrict__ lam, double *__restrict__ g) {
+  const int e = blockIdx.x * BS + threadIdx.x;
+  if (e >= ne) return;
+  constexpr int K = D + 1;
+  int v[K];
+  double ue[K], le[K];
+  for (int i = 0; i < K; ++i) {
+    v[i] = elems[(size_t)e * K + i];
+    const int di = dof_of_vertex[v[i]];
+    ue[i] = di >= 0 ? u[di] : 0.0;
+    le[i] = di >= 0 ? lam[di] : 0.0;
+  }
+  double M[3][3], G[K][3];
+  for (int k = 0; k < D; ++k)
+    for (int r = 0; r < D; ++r) M[r][k] = coords[(size_t)v[k + 1] * D + r] - coords[(size_t)v[0] * D + r];
+  double det;
+  double inv[3][3];
+  if (D == 2) {
+    det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    inv[0][0] = M[1][1] / det;
+    inv[0][1] = -M[0][1] / det;
+    inv[1][0] = -M[1][0] / det;
+    inv[1][1] = M[0][0] / det;
+  } else {
+    double c[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+        c[i][j] = M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0];
+      }
+    det = M[0][0] * c[0][0] + M[0][1] * c[1][0] + M[0][2] * c[2][0];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) inv[i][j] = c[i][j] / det;
+  }
+  for (int k = 0; k < D; ++k)
+    for (int r = 0; r < D; ++r) G[k + 1][r] = inv[k][r];
+  for (int r = 0; r < D; ++r) {
+    double s = 0;
+    for (int k = 0; k < D; ++k) s += inv[k][r];
+    G[0][r] = -s;
+  }
+  const double vol = fabs(det) / (D == 2 ? 2.0 : 6.0);
+  // lam^T G G^T u = (G^T lam) . (G^T u)
+  double gl[3] = {0, 0, 0}, gu[3] = {0, 0, 0};
+  for (int i = 0; i < K; ++i)
+    for (int r = 0; r < D; ++r) {
+      gl[r] += G[i][r] * le[i];
+      gu[r] += G[i][r] * ue[i];
+    }
+  double s = 0;
+  for (int r = 0; r < D; ++r) s += gl[r] * gu[r];
+  g[e] = kappa[e] * vol * s;
+}
+
+// ---------------------------------------------------------------------------
+// device data
+// ---------------------------------------------------------------------------
+
+struct DCsr {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  int *rp = nullptr, *ci = nullptr;
+  double *v64 = nullptr;
+  float *v32 = nullptr;
+  int lpr = 4;
+};
+
+struct DLevel {
+  int n = 0;
+  std::vector<int> coff;      // colour offsets, C + 1
+  std::vector<int> perm;      // internal -> unknown
+  std::vector<int> iperm;     // unknown -> internal
+  DCsr A;                     // off-diagonal part
+  double *dg64 = nullptr, *id64 = nullptr;
+  float *dg32 = nullptr, *id32 = nullptr;
+  double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
+  float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+  DCsr P, PT;                 // from the next coarser level (aux levels only)
+};
+
+struct Device {
+  int ordinal = 0;
+  int d = 2;
+  int J = 1, lc = 1;
+  int nu_aux = 2, nu_fine = 1, maxit = 1000, precision = 0, check_every = 0;
+  std::vector<void *> allocs;
+  DLevel fine;
+  std::vector<DLevel> aux;    // index l (lc+1..J used)
+  DCsr Pi, PiT;
+  int nc = 0;
+  double *cinv64 = nullptr, *cb64 = nullptr, *cx64 = nullptr;
+  float *cinv32 = nullptr, *cb32 = nullptr, *cx32 = nullptr;
+  int *perm_d = nullptr;      // fine internal -> unknown
+  // PCG vectors (internal order, FP64)
+  double *f = nullptr, *u = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double *io_in = nullptr, *io_out = nullptr;   // staging for host-pointer calls
+  Ctl *ctl = nullptr;
+  Ctl *ctl_host = nullptr;    // pinned
+  int *zero_flag = nullptr;   // always 0 (for kernels run outside a PCG)
+  double *partials = nullptr;
+  int max_blocks = 1;
+  // element data for the gradient
+  double *coords = nullptr, *kappa = nullptr;
+  int *elems = nullptr, *dof_of_vertex = nullptr;
+  int64_t ne = 0, nv = 0;
+  // byte model accumulation
+  bool count_bytes = false;
+  double bytes = 0.0;
+  std::string last_kernel;
+};
+
+template <class T>
+static T *dalloc(Device *dv, int64_t n) {
+  if (n <= 0) n = 1;
+  void *p = nullptr;
+  HIPCHECK(hipMalloc(&p, (size_t)n * sizeof(T)));
+  dv->allocs.push_back(p);
+  return (T *)p;
+}
+
+template <class T>
+static T *dupload(Device *dv, const std::vector<T> &v) {
+  T *p = dalloc<T>(dv, (int64_t)v.size());
+  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+static int pick_lpr(int64_t nnz, int64_t rows) {
+  if (rows <= 0) return 4;
+  const double avg = (double)nnz / (double)rows;
+  if (avg <= 2.0) return 2;
+  if (avg <= 4.0) return 4;
+  if (avg <= 8.0) return 8;
+  return 16;
+}
+
+// host CSR triple in an internal numbering
+struct HCsr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+};
+
+// permute rows/cols of a host CSR: new row i = old row rperm[i]; column c -> cmap[c]; optional diagonal split
+static HCsr permute(const Csr &A, const std::vector<int> &rperm, const std::vector<int> *cmap, bool split_diag,
+                    std::vector<double> *diag) {
+  HCsr B;
+  B.nrows = (int)rperm.size();
+  B.ncols = (int)A.ncols;
+  B.rp.assign(B.nrows + 1, 0);
+  if (diag) diag->assign(B.nrows, 0.0);
+  std::vector<std::pair<int, double>> row;
+  for (int i = 0; i < B.nrows; ++i) {
+    const int64_t o = rperm[i];
+    row.clear();
+    for (int64_t p = A.rp[o]; p < A.rp[o + 1]; ++p) {
+      if (split_diag && A.ci[p] == o) {
+        (*diag)[i] = A.v[p];
+        continue;
+      }
+      const int c = cmap ? (*cmap)[A.ci[p]] : A.ci[p];
+      row.push_back({c, A.v[p]});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto &e : row) {
+      B.ci.push_back(e.first);
+      B.v.push_back(e.second);
+    }
+    B.rp[i + 1] = (int)B.ci.size();
+  }
+  return B;
+}
+
+static HCsr transpose(const HCsr &A) {
+  HCsr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rp.assign(T.nrows + 1, 0);
+  for (int c : A.ci) T.rp[c + 1]++;
+  for (int i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.ci.size());
+  T.v.resize(A.v.size());
+  std::vector<int> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < A.nrows; ++i)
+    for (int p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      const int q = pos[A.ci[p]]++;
+      T.ci[q] = i;
+      T.v[q] = A.v[p];
+    }
+  return T;
+}
+
+static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
+  D.nrows = H.nrows;
+  D.ncols = H.ncols;
+  D.nnz = (int64_t)H.ci.size();
+  D.rp = dupload(dv, H.rp);
+  D.ci = dupload(dv, H.ci);
+  D.v64 = dupload(dv, H.v);
+  std::vector<float> f(H.v.begin(), H.v.end());
+  D.v32 = dupload(dv, f);
+  D.lpr = pick_lpr(D.nnz, D.nrows);
+}
+
+static void upload_values(DCsr &D, const HCsr &H) {
+  if (H.v.empty()) return;
+  HIPCHECK(hipMemcpy(D.v64, H.v.data(), H.v.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<float> f(H.v.begin(), H.v.end());
+  HIPCHECK(hipMemcpy(D.v32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+static void colour_order(const std::vector<int32_t> &col, DLevel &L) {
+  const int n = (int)col.size();
+  L.n = n;
+  int C = 0;
+  for (int c : col) C = std::max(C, c + 1);
+  L.coff.assign(C + 1, 0);
+  for (int c : col) L.coff[c + 1]++;
+  for (int c = 0; c < C; ++c) L.coff[c + 1] += L.coff[c];
+  L.perm.resize(n);
+  std::vector<int> pos(L.coff.begin(), L.coff.end() - 1);
+  for (int i = 0; i < n; ++i) L.perm[pos[col[i]]++] = i;  // ascending id inside a colour
+  L.iperm.resize(n);
+  for (int i = 0; i < n; ++i) L.iperm[L.perm[i]] = i;
+}
+
+static void alloc_vectors(Device *dv, DLevel &L) {
+  L.x64 = dalloc<double>(dv, L.n);
+  L.b64 = dalloc<double>(dv, L.n);
+  L.r64 = dalloc<double>(dv, L.n);
+  L.x32 = dalloc<float>(dv, L.n);
+  L.b32 = dalloc<float>(dv, L.n);
+  L.r32 = dalloc<float>(dv, L.n);
+}
+
+static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time) {
+  std::vector<double> diag;
+  HCsr H = permute(A, L.perm, &L.iperm, true, &diag);
+  std::vector<double> inv(diag.size());
+  for (size_t i = 0; i < diag.size(); ++i) inv[i] = 1.0 / diag[i];
+  std::vector<float> d32(diag.begin(), diag.end()), i32(diag.size());
+  for (size_t i = 0; i < diag.size(); ++i) i32[i] = 1.0f / (float)diag[i];
+  if (first_time) {
+    upload_csr(dv, H, L.A);
+    L.dg64 = dupload(dv, diag);
+    L.id64 = dupload(dv, inv);
+    L.dg32 = dupload(dv, d32);
+    L.id32 = dupload(dv, i32);
+  } else {
+    upload_values(L.A, H);
+    HIPCHECK(hipMemcpy(L.dg64, diag.data(), diag.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.id64, inv.data(), inv.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dg32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.id32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice));
+  }
+}
+
+static void upload_coarse(Device *dv, Hierarchy &h, bool first_time) {
+  const int64_t n = h.nc;
+  std::vector<float> f(h.coarse_inv.begin(), h.coarse_inv.end());
+  if (first_time) {
+    dv->nc = (int)n;
+    dv->cinv64 = dupload(dv, h.coarse_inv);
+    dv->cinv32 = dupload(dv, f);
+    dv->cb64 = dalloc<double>(dv, n);
+    dv->cx64 = dalloc<double>(dv, n);
+    dv->cb32 = dalloc<float>(dv, n);
+    dv->cx32 = dalloc<float>(dv, n);
+  } else if (n > 0) {
+    HIPCHECK(hipMemcpy(dv->cinv64, h.coarse_inv.data(), n * n * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dv->cinv32, f.data(), n * n * 4, hipMemcpyHostToDevice));
+  }
+}
+
+Device *device_create(Hierarchy &h, int ordinal) {
+  int count = 0;
+  HIPCHECK(hipGetDeviceCount(&count));
+  if (ordinal < 0 || ordinal >= count) throw AsmgError{ASMG_EDEVICE, "no such HIP device"};
+  HIPCHECK(hipSetDevice(ordinal));
+  Device *dv = new Device();
+  try {
+    dv->ordinal = ordinal;
+    dv->d = h.d;
+    dv->J = h.J;
+    dv->lc = h.lc;
+    dv->nu_aux = h.opt.nu_aux;
+    dv->nu_fine = h.opt.nu_fine;
+    dv->maxit = h.opt.max_iter;
+    dv->precision = h.opt.precision;
+    dv->check_every = h.opt.check_every;
+    // fine level
+    colour_order(h.colour_fine, dv->fine);
+    upload_level_matrix(dv, dv->fine, h.A, true);
+    alloc_vectors(dv, dv->fine);
+    dv->perm_d = dupload(dv, dv->fine.perm);
+    // auxiliary levels
+    dv->aux.resize(h.J + 1);
+    for (int l = h.J; l > h.lc; --l) {
+      DLevel &L = dv->aux[l];
+      colour_order(h.colour_aux.at(l), L);
+      upload_level_matrix(dv, L, h.Al.at(l), true);
+      alloc_vectors(dv, L);
+    }
+    // prolongations in internal numbering
+    for (int l = h.J; l > h.lc; --l) {
+      DLevel &L = dv->aux[l];
+      std::vector<int> ident;
+      const std::vector<int> *cmap = nullptr;
+      if (l - 1 > h.lc) cmap = &dv->aux[l - 1].iperm;
+      HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
+      upload_csr(dv, P, L.P);
+      upload_csr(dv, transpose(P), L.PT);
+    }
+    // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom)
+    {
+      const std::vector<int> *cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
+      HCsr Pi = permute(h.Pi, dv->fine.perm, cmap, false, nullptr);
+      upload_csr(dv, Pi, dv->Pi);
+      upload_csr(dv, transpose(Pi), dv->PiT);
+    }
+    upload_coarse(dv, h, true);
+    const int n = dv->fine.n;
+    dv->f = dalloc<double>(dv, n);
+    dv->u = dalloc<double>(dv, n);
+    dv->r = dalloc<double>(dv, n);
+    dv->p = dalloc<double>(dv, n);
+    dv->q = dalloc<double>(dv, n);
+    dv->io_in = dalloc<double>(dv, n);
+    dv->io_out = dalloc<double>(dv, n);
+    dv->ctl = dalloc<Ctl>(dv, 1);
+    HIPCHECK(hipMemset(dv->ctl, 0, sizeof(Ctl)));
+    HIPCHECK(hipHostMalloc((void **)&dv->ctl_host, sizeof(Ctl), hipHostMallocDefault));
+    dv->zero_flag = dalloc<int>(dv, 1);
+    HIPCHECK(hipMemset(dv->zero_flag, 0, sizeof(int)));
+    dv->max_blocks = std::max(1, (int)(((int64_t)n * 16 + BS - 1) / BS));
+    dv->partials = dalloc<double>(dv, dv->max_blocks);
+    // element data for the gradient kernel
+    dv->ne = h.ne;
+    dv->nv = h.nv;
+    dv->coords = dupload(dv, h.coords);
+    std::vector<int> el(h.elems.begin(), h.elems.end());
+    dv->elems = dupload(dv, el);
+    dv->kappa = dupload(dv, h.kappa);
+    std::vector<int> dov(h.dof_of_vertex.begin(), h.dof_of_vertex.end());
+    dv->dof_of_vertex = dupload(dv, dov);
+    HIPCHECK(hipDeviceSynchronize());
+  } catch (...) {
+    device_destroy(dv);
+    throw;
+  }
+  return dv;
+}
+
+void device_update_values(Device *dv, Hierarchy &h) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  upload_level_matrix(dv, dv->fine, h.A, false);
+  for (int l = h.J; l > h.lc; --l) upload_level_matrix(dv, dv->aux[l], h.Al.at(l), false);
+  upload_coarse(dv, h, false);
+  HIPCHECK(hipMemcpy(dv->kappa, h.kappa.data(), h.kappa.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipDeviceSynchronize());
+}
+
+void device_destroy(Device *dv) {
+  if (!dv) return;
+  hipSetDevice(dv->ordinal);
+  for (void *p : dv->allocs) hipFree(p);
+  if (dv->ctl_host) hipHostFree(dv->ctl_host);
+  delete dv;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+
+static inline int nblk(int64_t threads) { return (int)std::max<int64_t>(1, (threads + BS - 1) / BS); }
+
+static inline double csr_bytes(const DCsr &A, int vbytes) {
+  return (double)A.nnz * (vbytes + 4) + 4.0 * (A.nrows + 1);
+}
+
+template <class T>
+static const T *vals(const DCsr &A);
+template <>
+const double *vals<double>(const DCsr &A) { return A.v64; }
+template <>
+const float *vals<float>(const DCsr &A) { return A.v32; }
+
+template <class T>
+struct LV {
+  static T *x(DLevel &L);
+  static T *b(DLevel &L);
+  static T *r(DLevel &L);
+  static const T *dg(DLevel &L);
+  static const T *id(DLevel &L);
+};
+template <>
+struct LV<double> {
+  static double *x(DLevel &L) { return L.x64; }
+  static double *b(DLevel &L) { return L.b64; }
+  static double *r(DLevel &L) { return L.r64; }
+  static const double *dg(DLevel &L) { return L.dg64; }
+  static const double *id(DLevel &L) { return L.id64; }
+};
+template <>
+struct LV<float> {
+  static float *x(DLevel &L) { return L.x32; }
+  static float *b(DLevel &L) { return L.b32; }
+  static float *r(DLevel &L) { return L.r32; }
+  static const float *dg(DLevel &L) { return L.dg32; }
+  static const float *id(DLevel &L) { return L.id32; }
+};
+
+template <class F>
+static void with_lpr(int lpr, F &&f) {
+  switch (lpr) {
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    default: f(std::integral_constant<int, 16>()); break;
+  }
+}
+
+template <int LPR, class T>
+static void launch_gs(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
+  const int r0 = L.coff[c], r1 = L.coff[c + 1];
+  if (r1 <= r0) return;
+  hipLaunchKernelGGL((k_gs<LPR, T>), dim3(nblk((int64_t)(r1 - r0) * LPR)), dim3(BS), 0, s, r0, r1, L.A.rp, L.A.ci,
+                     vals<T>(L.A), LV<T>::id(L), b, x, done);
+}
+
+template <class T>
+static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
+  switch (L.A.lpr) {
+    case 2: launch_gs<2, T>(dv, L, c, x, b, done, s); break;
+    case 4: launch_gs<4, T>(dv, L, c, x, b, done, s); break;
+    case 8: launch_gs<8, T>(dv, L, c, x, b, done, s); break;
+    default: launch_gs<16, T>(dv, L, c, x, b, done, s); break;
+  }
+  if (dv->count_bytes) {
+    const int rows = L.coff[c + 1] - L.coff[c];
+    // rows of this colour: matrix rows + b, 1/diag, x write; gathers of x counted once per sweep
+    double nnz = 0;  // approximated by the colour's share of the nonzeros
+    nnz = (double)L.A.nnz * rows / std::max(1, L.n);
+    dv->bytes += nnz * (sizeof(T) + 4) + 4.0 * rows + rows * 3.0 * sizeof(T);
+  }
+}
+
+template <class T>
+static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool forward, const int *done,
+                  hipStream_t s) {
+  const int C = (int)L.coff.size() - 1;
+  if (forward) {
+    int c = 0;
+    if (from_zero) {
+      hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.coff[1], b, LV<T>::id(L), x, done);
+      if (dv->count_bytes) dv->bytes += (double)L.n * sizeof(T) + (double)L.coff[1] * 2 * sizeof(T);
+      c = 1;
+    }
+    for (; c < C; ++c) gs_pass<T>(dv, L, c, x, b, done, s);
+  } else {
+    for (int c = C - 1; c >= 0; --c) gs_pass<T>(dv, L, c, x, b, done, s);
+  }
+  if (dv->count_bytes) dv->bytes += (double)L.n * sizeof(T);  // one read of x per sweep for the gathers
+}
+
+template <class T>
+static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, const int *done, hipStream_t s) {
+  const int n = L.n;
+  with_lpr(L.A.lpr, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    hipLaunchKernelGGL((k_residual<LP, T>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, L.A.rp, L.A.ci,
+                       vals<T>(L.A), LV<T>::dg(L), b, x, r, done);
+  });
+  if (dv->count_bytes) dv->bytes += csr_bytes(L.A, sizeof(T)) + 4.0 * n * sizeof(T);
+}
+
+template <class T, int ADD>
+static void spmv(Device *dv, const DCsr &A, const T *x, T *y, const int *done, hipStream_t s) {
+  if (A.nrows == 0) return;
+  switch (A.lpr) {
+    case 2:
+      hipLaunchKernelGGL((k_spmv<2, ADD, T>), dim3(nblk((int64_t)A.nrows * 2)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
+                         vals<T>(A), x, y, done);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_spmv<4, ADD, T>), dim3(nblk((int64_t)A.nrows * 4)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
+                         vals<T>(A), x, y, done);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_spmv<8, ADD, T>), dim3(nblk((int64_t)A.nrows * 8)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
+                         vals<T>(A), x, y, done);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv<16, ADD, T>), dim3(nblk((int64_t)A.nrows * 16)), dim3(BS), 0, s, A.nrows, A.rp,
+                         A.ci, vals<T>(A), x, y, done);
+      break;
+  }
+  if (dv->count_bytes) dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
+}
+
+template <class T>
+static T *cvec_b(Device *dv);
+template <>
+double *cvec_b<double>(Device *dv) { return dv->cb64; }
+template <>
+float *cvec_b<float>(Device *dv) { return dv->cb32; }
+template <class T>
+static T *cvec_x(Device *dv);
+template <>
+double *cvec_x<double>(Device *dv) { return dv->cx64; }
+template <>
+float *cvec_x<float>(Device *dv) { return dv->cx32; }
+template <class T>
+static const T *cinv(Device *dv);
+template <>
+const double *cinv<double>(Device *dv) { return dv->cinv64; }
+template <>
+const float *cinv<float>(Device *dv) { return dv->cinv32; }
+
+// rhs / solution vectors of level l (the bottom level has its own)
+template <class T>
+static T *lvl_b(Device *dv, int l) { return l == dv->lc ? cvec_b<T>(dv) : LV<T>::b(dv->aux[l]); }
+template <class T>
+static T *lvl_x(Device *dv, int l) { return l == dv->lc ? cvec_x<T>(dv) : LV<T>::x(dv->aux[l]); }
+
+// Algorithm 2: B_l applied to the level's b, result in the level's x
+template <class T>
+static void vcycle(Device *dv, int l, const int *done, hipStream_t s) {
+  if (l == dv->lc) {
+    if (dv->nc > 0) {
+      hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)dv->nc * 64)), dim3(BS), 0, s, dv->nc, cinv<T>(dv),
+                         cvec_b<T>(dv), cvec_x<T>(dv), done);
+      if (dv->count_bytes) dv->bytes += (double)dv->nc * dv->nc * sizeof(T) + 2.0 * dv->nc * sizeof(T);
+    }
+    return;
+  }
+  DLevel &L = dv->aux[l];
+  T *x = LV<T>::x(L);
+  T *b = LV<T>::b(L);
+  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, k == 0, true, done, s);
+  residual<T>(dv, L, b, x, LV<T>::r(L), done, s);
+  spmv<T, 0>(dv, L.PT, LV<T>::r(L), lvl_b<T>(dv, l - 1), done, s);
+  vcycle<T>(dv, l - 1, done, s);
+  spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, done, s);
+  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, false, false, done, s);
+}
+
+// Algorithm 1 (u_0 = 0): x_fine = B_co r; r in FP64 (internal order), result in fine.x{64,32}
+template <class T>
+static void apply_Bco(Device *dv, const double *r, const int *done, hipStream_t s) {
+  DLevel &F = dv->fine;
+  T *x = LV<T>::x(F);
+  const T *b;
+  if constexpr (sizeof(T) == 8) {
+    b = r;
+    for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, k == 0, true, done, s);
+  } else {
+    hipLaunchKernelGGL(k_gs_first_cvt, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, F.coff.size() > 1 ? F.coff[1] : 0, r,
+                       F.b32, F.id32, F.x32, done);
+    if (dv->count_bytes) dv->bytes += (double)F.n * (8 + 4 + 4) + (double)F.coff[1] * 4;
+    b = F.b32;
+    const int C = (int)F.coff.size() - 1;
+    for (int c = 1; c < C; ++c) gs_pass<T>(dv, F, c, x, b, done, s);
+    if (dv->count_bytes) dv->bytes += (double)F.n * sizeof(T);
+    for (int k = 1; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, true, done, s);
+  }
+  residual<T>(dv, F, b, x, LV<T>::r(F), done, s);
+  spmv<T, 0>(dv, dv->PiT, LV<T>::r(F), lvl_b<T>(dv, dv->J), done, s);
+  vcycle<T>(dv, dv->J, done, s);
+  spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, done, s);
+  for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, false, done, s);
+}
+
+// ---------------------------------------------------------------------------
+// PCG driver
+// ---------------------------------------------------------------------------
+
+template <class T>
+static void pcg_tail(Device *dv, hipStream_t s) {
+  // z = B_co r, rho/beta, p = z + beta p
+  const int n = dv->fine.n;
+  apply_Bco<T>(dv, dv->r, &dv->ctl->done, s);
+  hipLaunchKernelGGL((k_cg_rz<T>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->r, (const T *)LV<T>::x(dv->fine), dv->ctl,
+                     dv->partials);
+  hipLaunchKernelGGL((k_cg_p<T>), dim3(nblk(n)), dim3(BS), 0, s, n, (const T *)LV<T>::x(dv->fine), dv->p, dv->ctl);
+}
+
+template <class T>
+static void pcg_iteration(Device *dv, hipStream_t s) {
+  const int n = dv->fine.n;
+  DLevel &F = dv->fine;
+  with_lpr(F.A.lpr, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    hipLaunchKernelGGL((k_cg_spmv<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
+                       F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
+  });
+  hipLaunchKernelGGL(k_cg_axpy, dim3(nblk(n)), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials);
+  pcg_tail<T>(dv, s);
+}
+
+static void read_ctl(Device *dv, hipStream_t s) {
+  HIPCHECK(hipMemcpyAsync(dv->ctl_host, dv->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+template <class T>
+static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t s) {
+  const int n = dv->fine.n;
+  DLevel &F = dv->fine;
+  hipLaunchKernelGGL(k_cg_init, dim3(nblk(n)), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, tol, dv->maxit, dv->ctl,
+                     dv->partials);
+  pcg_tail<T>(dv, s);
+  int K = dv->check_every > 0 ? dv->check_every : 4;
+  int restarts = 0;
+  while (true) {
+    read_ctl(dv, s);
+    if (!dv->ctl_host->done) {
+      for (int k = 0; k < K; ++k) pcg_iteration<T>(dv, s);
+      continue;
+    }
+    // converged, broke down or hit max_iter: true residual in FP64
+    with_lpr(F.A.lpr, [&](auto c) {
+      constexpr int LP = decltype(c)::value;
+      hipLaunchKernelGGL((k_true_res<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
+                         F.dg64, dv->f, dv->u, dv->ctl, dv->partials);
+    });
+    read_ctl(dv, s);
+    const Ctl &c = *dv->ctl_host;
+    const double rel = c.fnorm2 > 0 ? std::sqrt(c.tr / c.fnorm2) : 0.0;
+    if (c.status == ST_OK && sizeof(T) == 4 && rel > tol && restarts < 3 && c.iter < dv->maxit) {
+      ++restarts;
+      with_lpr(F.A.lpr, [&](auto c) {
+        constexpr int LP = decltype(c)::value;
+        hipLaunchKernelGGL((k_cg_restart<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci,
+                           F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->ctl);
+      });
+      pcg_tail<T>(dv, s);
+      continue;
+    }
+    if (iters) *iters = c.iter;
+    if (true_rel) *true_rel = rel;
+    switch (c.status) {
+      case ST_OK: return ASMG_OK;
+      case ST_NOTSPD: return ASMG_ENOTSPD;
+      case ST_NAN: return ASMG_ENAN;
+      default: return ASMG_ENOCONV;
+    }
+  }
+}
+
+int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = dv->fine.n;
+  if (n == 0) {
+    if (iters) *iters = 0;
+    if (true_rel) *true_rel = 0;
+    return ASMG_OK;
+  }
+  hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_f, dv->f);
+  const int rc = dv->precision == ASMG_PREC_MIXED ? pcg<float>(dv, tol, iters, true_rel, s)
+                                                   : pcg<double>(dv, tol, iters, true_rel, s);
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, dv->u, d_u);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  return rc;
+}
+
+int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  const int n = dv->fine.n;
+  if (n > 0) HIPCHECK(hipMemcpy(dv->io_in, f, (size_t)n * 8, hipMemcpyHostToDevice));
+  const int rc = device_solve(dv, dv->io_in, tol, dv->io_out, iters, true_rel, nullptr);
+  if (n > 0) HIPCHECK(hipMemcpy(u, dv->io_out, (size_t)n * 8, hipMemcpyDeviceToHost));
+  return rc;
+}
+
+int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = dv->fine.n;
+  if (n == 0) return ASMG_OK;
+  hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_r, dv->f);
+  if (precision == ASMG_PREC_MIXED) {
+    apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
+    hipLaunchKernelGGL((k_scatter_cvt<float>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d,
+                       (const float *)dv->fine.x32, d_z);
+  } else {
+    apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+    hipLaunchKernelGGL((k_scatter_cvt<double>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d,
+                       (const double *)dv->fine.x64, d_z);
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  return ASMG_OK;
+}
+
+int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = dv->fine.n;
+  if (n == 0) return ASMG_OK;
+  DLevel &F = dv->fine;
+  hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_x, dv->p);
+  with_lpr(F.A.lpr, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    hipLaunchKernelGGL((k_matvec<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
+                       F.dg64, dv->p, dv->q);
+  });
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, dv->q, d_y);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  return ASMG_OK;
+}
+
+int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  if (dv->d == 2)
+    hipLaunchKernelGGL((k_elem_grad<2>), dim3(nblk(dv->ne)), dim3(BS), 0, s, (int)dv->ne, dv->coords, dv->elems,
+                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g);
+  else
+    hipLaunchKernelGGL((k_elem_grad<3>), dim3(nblk(dv->ne)), dim3(BS), 0, s, (int)dv->ne, dv->coords, dv->elems,
+                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  return ASMG_OK;
+}
+
+int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  DLevel &F = dv->fine;
+  const int n = F.n;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  const bool mixed = which == 3 ? dv->precision == ASMG_PREC_MIXED : precision == ASMG_PREC_MIXED;
+  auto one = [&]() {
+    if (which == 0) {
+      with_lpr(F.A.lpr, [&](auto c) {
+        constexpr int LP = decltype(c)::value;
+        hipLaunchKernelGGL((k_matvec<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
+                           F.dg64, dv->p, dv->q);
+      });
+    } else if (which == 1) {
+      if (mixed)
+        sweep<float>(dv, F, F.x32, F.b32, false, true, dv->zero_flag, s);
+      else
+        sweep<double>(dv, F, F.x64, F.b64, false, true, dv->zero_flag, s);
+    } else {
+      if (mixed)
+        apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
+      else
+        apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+    }
+  };
+  // byte model of one launch
+  dv->count_bytes = true;
+  dv->bytes = 0;
+  if (which == 0)
+    dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 3;
+  else
+    one();
+  dv->count_bytes = false;
+  *bytes = dv->bytes;
+  HIPCHECK(hipMemsetAsync(dv->p, 0, (size_t)n * 8, s));
+  HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)n * 8, s));
+  HIPCHECK(hipMemsetAsync(F.b64, 0, (size_t)n * 8, s));
+  HIPCHECK(hipMemsetAsync(F.b32, 0, (size_t)n * 4, s));
+  one();  // warm-up
+  HIPCHECK(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) one();
+  HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+  *ms = (double)t / reps;
+  HIPCHECK(hipEventDestroy(e0));
+  HIPCHECK(hipEventDestroy(e1));
+  HIPCHECK(hipGetLastError());
+  return ASMG_OK;
+}
+
+}  // namespace asmg

@@ -1,0 +1,26 @@
+// Device side of the solver: uploaded hierarchy, kernels and the PCG driver (device.hip).
+#pragma once
+
+#include <cstdint>
+
+#include "setup.hpp"
+
+namespace asmg {
+
+struct Device;
+
+// Upload the hierarchy (internal colour-major numbering) to device `ordinal`.
+Device *device_create(Hierarchy &h, int ordinal);
+// Re-upload matrix values after a coefficient update (patterns unchanged).
+void device_update_values(Device *dv, Hierarchy &h);
+void device_destroy(Device *dv);
+
+int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream);
+int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, void *stream);
+int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream);
+int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, void *stream);
+int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes);
+// host-pointer solve through device staging buffers
+int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel);
+
+}  // namespace asmg

@@ -1,0 +1,1173 @@
+// Host-side construction of the ASMG hierarchy.
+//
+//   build_fine        P1 stiffness pattern and values, Dirichlet elimination (Section 2, eq. (2))
+//   build_tree        barycenters, box keys, cluster tree and closure (Sections 3.1-3.2)
+//   level_mesh        nested conforming auxiliary triangulations sigma^(l) (Section 3.3),
+//                     Dirichlet auxiliary grids of a box domain (Section 3.4)
+//   build_levels      choice of the V-cycle bottom, A_l and P_l patterns (Section 4.1)
+//   build_transfer    Scott-Zhang transfer Pi (Section 4.1)
+//   build_colourings  multicolour orderings for Gauss-Seidel
+//   build_coarse      Cholesky factor and explicit inverse of the bottom matrix (Algorithm 2, B_0)
+//
+// Index maps (keys, refined boxes, vertices, simplices, unknown numbering, patterns,
+// colourings) are exact integer computations. The floating-point steps that feed
+// them (barycenters, keys) use plain IEEE operations in a fixed order and are
+// compiled without floating-point contraction.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace asmg {
+
+[[noreturn]] static void fail(int code, const std::string &m) { throw AsmgError{code, m}; }
+
+static constexpr int key_bits(int d) { return d == 2 ? 30 : 20; }
+
+// ---------------------------------------------------------------------------
+// box codes
+// ---------------------------------------------------------------------------
+
+BoxCode box_code(int level, const int64_t *idx, int d) {
+  BoxCode m = 0;
+  const int bits = level - 1;
+  for (int b = 0; b < bits; ++b)
+    for (int k = 0; k < d; ++k) m |= (BoxCode)((idx[k] >> b) & 1) << (b * d + (d - 1 - k));
+  return m | ((BoxCode)1 << (d * bits));
+}
+
+int box_level(BoxCode c, int d) { return (63 - __builtin_clzll(c)) / d + 1; }
+
+void box_index(BoxCode c, int d, int64_t *idx) {
+  const int bits = box_level(c, d) - 1;
+  for (int k = 0; k < d; ++k) idx[k] = 0;
+  for (int b = 0; b < bits; ++b)
+    for (int k = 0; k < d; ++k) idx[k] |= (int64_t)((c >> (b * d + (d - 1 - k))) & 1) << b;
+}
+
+// same-level offsets of boxes sharing a facet, or (3-D) an edge
+static std::vector<std::array<int, 3>> touch_offsets(int d) {
+  std::vector<std::array<int, 3>> out;
+  for (int x = -1; x <= 1; ++x)
+    for (int y = -1; y <= 1; ++y)
+      for (int z = (d == 3 ? -1 : 0); z <= (d == 3 ? 1 : 0); ++z) {
+        int nz = (x != 0) + (y != 0) + (z != 0);
+        if (nz == 1 || (d == 3 && nz == 2)) out.push_back({x, y, z});
+      }
+  return out;
+}
+
+static inline bool offset_box(BoxCode b, const std::array<int, 3> &o, int d, BoxCode *out) {
+  int64_t idx[3];
+  box_index(b, d, idx);
+  const int lev = box_level(b, d);
+  const int64_t n = (int64_t)1 << (lev - 1);
+  for (int k = 0; k < d; ++k) {
+    idx[k] += o[k];
+    if (idx[k] < 0 || idx[k] >= n) return false;
+  }
+  *out = box_code(lev, idx, d);
+  return true;
+}
+
+// Morton key of integer points with `bits` bits per axis (axis 0 most significant)
+static inline unsigned __int128 morton_point(const int64_t *X, int d, int bits) {
+  unsigned __int128 m = 0;
+  for (int b = 0; b < bits; ++b)
+    for (int k = 0; k < d; ++k) m |= (unsigned __int128)((X[k] >> b) & 1) << (b * d + (d - 1 - k));
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// fine problem (Section 2)
+// ---------------------------------------------------------------------------
+
+// gradients of the barycentric coordinates and |det| of one element
+static double element_grads(const Hierarchy &h, int64_t e, double G[4][3]) {
+  const int d = h.d;
+  const int32_t *ev = &h.elems[e * (d + 1)];
+  const double *p0 = &h.coords[(int64_t)ev[0] * d];
+  double M[3][3];  // columns = edges p_k - p_0
+  for (int k = 0; k < d; ++k) {
+    const double *pk = &h.coords[(int64_t)ev[k + 1] * d];
+    for (int r = 0; r < d; ++r) M[r][k] = pk[r] - p0[r];
+  }
+  double det, inv[3][3];
+  if (d == 2) {
+    det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    inv[0][0] = M[1][1] / det;
+    inv[0][1] = -M[0][1] / det;
+    inv[1][0] = -M[1][0] / det;
+    inv[1][1] = M[0][0] / det;
+  } else {
+    double c[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+        c[i][j] = M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0];  // cofactor (j,i) -> adj(i,j)
+      }
+    det = M[0][0] * c[0][0] + M[0][1] * c[1][0] + M[0][2] * c[2][0];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) inv[i][j] = c[i][j] / det;
+  }
+  if (!(det != 0.0) || !std::isfinite(det)) fail(ASMG_EINVAL, "degenerate element " + std::to_string(e));
+  for (int k = 0; k < d; ++k)
+    for (int r = 0; r < d; ++r) G[k + 1][r] = inv[k][r];
+  for (int r = 0; r < d; ++r) {
+    double s = 0;
+    for (int k = 0; k < d; ++k) s += inv[k][r];
+    G[0][r] = -s;
+  }
+  return std::fabs(det);
+}
+
+// CSR pattern from element lists: rows = unknowns; `ev` maps element-local slots to unknowns (-1 = none)
+template <class F>
+static void pattern_from_elements(int64_t n, int64_t ne, int k, F unknown_of, Csr &A) {
+  A.nrows = A.ncols = n;
+  std::vector<int64_t> cnt(n + 1, 0);
+  std::vector<int64_t> u(k);
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int i = 0; i < k; ++i) u[i] = unknown_of(e, i);
+    for (int i = 0; i < k; ++i)
+      if (u[i] >= 0)
+        for (int j = 0; j < k; ++j)
+          if (u[j] >= 0) cnt[u[i] + 1]++;
+  }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> tmp(cnt[n]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int i = 0; i < k; ++i) u[i] = unknown_of(e, i);
+    for (int i = 0; i < k; ++i)
+      if (u[i] >= 0)
+        for (int j = 0; j < k; ++j)
+          if (u[j] >= 0) tmp[pos[u[i]]++] = (int32_t)u[j];
+  }
+  A.rp.assign(n + 1, 0);
+  A.ci.clear();
+  A.ci.reserve(cnt[n] / 3 + n);
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
+    std::sort(b, e);
+    auto last = std::unique(b, e);
+    A.ci.insert(A.ci.end(), b, last);
+    A.rp[i + 1] = (int64_t)A.ci.size();
+  }
+  A.v.assign(A.ci.size(), 0.0);
+}
+
+static inline int64_t find_col(const Csr &A, int64_t row, int32_t col) {
+  const int32_t *b = A.ci.data() + A.rp[row], *e = A.ci.data() + A.rp[row + 1];
+  const int32_t *p = std::lower_bound(b, e, col);
+  return (int64_t)(p - A.ci.data());
+}
+
+void build_fine(Hierarchy &h) {
+  const int d = h.d;
+  if (h.dirichlet.empty()) {
+    double lo[3], hi[3];
+    for (int k = 0; k < d; ++k) lo[k] = hi[k] = h.coords[k];
+    for (int64_t v = 0; v < h.nv; ++v)
+      for (int k = 0; k < d; ++k) {
+        lo[k] = std::min(lo[k], h.coords[v * d + k]);
+        hi[k] = std::max(hi[k], h.coords[v * d + k]);
+      }
+    h.dirichlet.assign(h.nv, 0);
+    for (int64_t v = 0; v < h.nv; ++v)
+      for (int k = 0; k < d; ++k) {
+        double x = h.coords[v * d + k];
+        if (x == lo[k] || x == hi[k]) h.dirichlet[v] = 1;
+      }
+  }
+  h.dof_of_vertex.assign(h.nv, -1);
+  h.dofs.clear();
+  for (int64_t v = 0; v < h.nv; ++v)
+    if (!h.dirichlet[v]) {
+      h.dof_of_vertex[v] = (int64_t)h.dofs.size();
+      h.dofs.push_back(v);
+    }
+  pattern_from_elements(h.n(), h.ne, d + 1,
+                        [&](int64_t e, int i) { return h.dof_of_vertex[h.elems[e * (d + 1) + i]]; }, h.A);
+  assemble_fine_values(h);
+}
+
+void assemble_fine_values(Hierarchy &h) {
+  const int d = h.d, k = d + 1;
+  std::fill(h.A.v.begin(), h.A.v.end(), 0.0);
+  const double fact = d == 2 ? 2.0 : 6.0;
+  double G[4][3];
+  for (int64_t e = 0; e < h.ne; ++e) {
+    const double vol = element_grads(h, e, G) / fact;
+    const double w = h.kappa[e] * vol;
+    const int32_t *ev = &h.elems[e * k];
+    for (int i = 0; i < k; ++i) {
+      int64_t ui = h.dof_of_vertex[ev[i]];
+      if (ui < 0) continue;
+      for (int j = 0; j < k; ++j) {
+        int64_t uj = h.dof_of_vertex[ev[j]];
+        if (uj < 0) continue;
+        double g = 0;
+        for (int r = 0; r < d; ++r) g += G[i][r] * G[j][r];
+        h.A.v[find_col(h.A, ui, (int32_t)uj)] += w * g;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cluster tree and closure (Sections 3.1-3.2)
+// ---------------------------------------------------------------------------
+
+static void split_clusters(Hierarchy &h, const std::vector<BoxCode> &mc, BoxCode b, int level, int64_t lo,
+                           int64_t hi, int n_min) {
+  const int d = h.d, D = key_bits(d);
+  if (hi - lo <= n_min || level > D) return;
+  h.R0.insert(b);
+  const int sh = d * (D - level);  // shift of a level-(level+1) code inside a max-level code
+  int64_t start = lo;
+  for (int ci = 0; ci < (1 << d); ++ci) {
+    BoxCode cb = (b << d) | (BoxCode)ci;
+    BoxCode upper = (cb + 1) << sh;
+    int64_t end = std::lower_bound(mc.begin() + start, mc.begin() + hi, upper) - mc.begin();
+    if (end > start) split_clusters(h, mc, cb, level + 1, start, end, n_min);
+    start = end;
+  }
+}
+
+static bool in_tree(const Hierarchy &h, BoxCode b) {
+  return box_level(b, h.d) == 1 || h.R.count(b >> h.d);
+}
+
+void build_tree(Hierarchy &h) {
+  const int d = h.d, D = key_bits(d), k = d + 1;
+  const int n_min = h.opt.n_min > 0 ? h.opt.n_min : (d == 2 ? 3 : 7);
+  // root box B^1: anchored at the minimum corner, side = largest extent
+  double lo[3], hi[3];
+  for (int q = 0; q < d; ++q) lo[q] = hi[q] = h.coords[q];
+  for (int64_t v = 0; v < h.nv; ++v)
+    for (int q = 0; q < d; ++q) {
+      lo[q] = std::min(lo[q], h.coords[v * d + q]);
+      hi[q] = std::max(hi[q], h.coords[v * d + q]);
+    }
+  h.L = 0;
+  for (int q = 0; q < d; ++q) {
+    h.a[q] = lo[q];
+    h.L = std::max(h.L, hi[q] - lo[q]);
+  }
+  if (!(h.L > 0)) fail(ASMG_EINVAL, "mesh has zero extent");
+  // barycenters and integer keys
+  h.keys.assign(h.ne * d, 0);
+  const double scale = std::ldexp(1.0, D);
+  const int64_t kmax = ((int64_t)1 << D) - 1;
+  std::vector<BoxCode> code(h.ne);
+  for (int64_t e = 0; e < h.ne; ++e) {
+    const int32_t *ev = &h.elems[e * k];
+    int64_t kk[3];
+    for (int q = 0; q < d; ++q) {
+      volatile double s = h.coords[(int64_t)ev[0] * d + q] + h.coords[(int64_t)ev[1] * d + q];
+      for (int m = 2; m < k; ++m) s = s + h.coords[(int64_t)ev[m] * d + q];
+      volatile double xi = s / (double)k;
+      volatile double t = (xi - h.a[q]) / h.L;
+      volatile double ts = t * scale;
+      double f = std::floor(ts);
+      int64_t ki = f < 0 ? 0 : (int64_t)f;
+      if (ki > kmax) ki = kmax;
+      kk[q] = ki;
+      h.keys[e * d + q] = ki;
+    }
+    code[e] = box_code(D + 1, kk, d);
+  }
+  std::vector<int64_t> order(h.ne);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return code[x] < code[y] || (code[x] == code[y] && x < y);
+  });
+  std::vector<BoxCode> mc(h.ne);
+  std::vector<double> ksorted(h.ne);
+  for (int64_t i = 0; i < h.ne; ++i) {
+    mc[i] = code[order[i]];
+    ksorted[i] = h.kappa[order[i]];
+  }
+  h.R0.clear();
+  split_clusters(h, mc, (BoxCode)1, 1, 0, h.ne, n_min);
+
+  // closure: the paper's level-by-level Mark / Close / Refine (Section 3.2)
+  std::vector<std::vector<BoxCode>> byLevel(D + 2);
+  for (BoxCode b : h.R0) byLevel[box_level(b, d)].push_back(b);
+  for (auto &v : byLevel) std::sort(v.begin(), v.end());
+  const auto offs = touch_offsets(d);
+  h.R.clear();
+  for (int lev = 1; lev <= D + 1; ++lev) {
+    const std::vector<BoxCode> &marked = byLevel[lev];
+    if (marked.empty()) continue;
+    std::unordered_set<BoxCode> allm(marked.begin(), marked.end());
+    std::vector<BoxCode> newly(marked.begin(), marked.end());
+    while (!newly.empty()) {
+      std::vector<BoxCode> lst;
+      for (BoxCode b : newly) {
+        if (box_level(b, d) < 2) continue;
+        for (const auto &o : offs) {
+          BoxCode q;
+          if (!offset_box(b, o, d, &q)) continue;
+          BoxCode p = q >> d;
+          if (h.R.count(p) || allm.count(p) || !in_tree(h, p)) continue;
+          allm.insert(p);
+          lst.push_back(p);
+        }
+      }
+      newly.swap(lst);
+    }
+    h.R.insert(allm.begin(), allm.end());
+  }
+  // leaves
+  h.leaves.clear();
+  if (h.R.empty()) {
+    h.leaves.push_back((BoxCode)1);
+  } else {
+    for (BoxCode b : h.R)
+      for (int ci = 0; ci < (1 << d); ++ci) {
+        BoxCode c = (b << d) | (BoxCode)ci;
+        if (!h.R.count(c)) h.leaves.push_back(c);
+      }
+  }
+  auto tuple_less = [d](BoxCode x, BoxCode y) {
+    int lx = box_level(x, d), ly = box_level(y, d);
+    if (lx != ly) return lx < ly;
+    int64_t ix[3], iy[3];
+    box_index(x, d, ix);
+    box_index(y, d, iy);
+    for (int q = 0; q < d; ++q)
+      if (ix[q] != iy[q]) return ix[q] < iy[q];
+    return false;
+  };
+  std::sort(h.leaves.begin(), h.leaves.end(), tuple_less);
+  h.J = 1;
+  for (BoxCode b : h.leaves) h.J = std::max(h.J, box_level(b, d));
+  if (h.J > 31 || (d == 3 && h.J > 21)) fail(ASMG_EINVAL, "tree too deep");
+
+  // kappa~ per leaf: mean over the cluster, or over the nearest non-empty ancestor cluster
+  h.leaf_kappa.clear();
+  for (BoxCode b : h.leaves) {
+    BoxCode q = b;
+    while (true) {
+      int lev = box_level(q, d);
+      int sh = d * (D + 1 - lev);
+      int64_t s = std::lower_bound(mc.begin(), mc.end(), q << sh) - mc.begin();
+      int64_t e = std::lower_bound(mc.begin(), mc.end(), (q + 1) << sh) - mc.begin();
+      if (e > s) {
+        double sum = 0;
+        for (int64_t i = s; i < e; ++i) sum += ksorted[i];
+        h.leaf_kappa[b] = sum / (double)(e - s);
+        break;
+      }
+      q >>= d;
+    }
+  }
+}
+
+// mean coefficient of every Kuhn simplex of every box (leaf: kappa~; refined: mean of the
+// 2^d child Kuhn simplices inside)
+static const int PERM2[2][2] = {{0, 1}, {1, 0}};
+static const int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+static inline int perm_at(int d, int t, int m) { return d == 2 ? PERM2[t][m] : PERM3[t][m]; }
+
+static void compute_kuhn_means(Hierarchy &h) {
+  const int d = h.d, nperm = d == 2 ? 2 : 6;
+  // child Kuhn simplices inside each parent Kuhn simplex: child position a in {0,1}^d, child simplex s
+  std::vector<std::vector<std::pair<int, int>>> inside(nperm);
+  for (int t = 0; t < nperm; ++t)
+    for (int ci = 0; ci < (1 << d); ++ci) {
+      int a[3];
+      for (int q = 0; q < d; ++q) a[q] = (ci >> (d - 1 - q)) & 1;
+      for (int s = 0; s < nperm; ++s) {
+        bool ok = true;
+        for (int m = 0; m + 1 < d && ok; ++m) {
+          int p = perm_at(d, t, m), q = perm_at(d, t, m + 1);
+          if (a[p] > a[q]) continue;
+          if (a[p] < a[q]) { ok = false; break; }
+          int ip = -1, iq = -1;
+          for (int r = 0; r < d; ++r) {
+            if (perm_at(d, s, r) == p) ip = r;
+            if (perm_at(d, s, r) == q) iq = r;
+          }
+          if (ip > iq) ok = false;
+        }
+        if (ok) inside[t].push_back({ci, s});
+      }
+    }
+  h.kuhn_w.clear();
+  for (auto &kv : h.leaf_kappa) h.kuhn_w[kv.first] = std::vector<double>(nperm, kv.second);
+  std::vector<BoxCode> Rs(h.R.begin(), h.R.end());
+  std::sort(Rs.begin(), Rs.end(), [d](BoxCode x, BoxCode y) { return box_level(x, d) > box_level(y, d); });
+  for (BoxCode b : Rs) {
+    std::vector<double> w(nperm);
+    for (int t = 0; t < nperm; ++t) {
+      double s = 0;
+      for (auto &cs : inside[t]) s += h.kuhn_w[(b << d) | (BoxCode)cs.first][cs.second];
+      w[t] = s / (double)(1 << d);
+    }
+    h.kuhn_w[b] = std::move(w);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// level meshes (Section 3.3)
+// ---------------------------------------------------------------------------
+
+struct SimpBuilder {
+  int d;
+  std::vector<int64_t> pts;  // (d+1)*d per simplex
+  std::vector<int32_t> box;
+  std::vector<int8_t> tmpl;
+  void add(const int64_t *v, int nvtx, int32_t b, int t) {
+    pts.insert(pts.end(), v, v + nvtx * d);
+    box.push_back(b);
+    tmpl.push_back((int8_t)t);
+  }
+};
+
+static void kuhn_simplices(int d, const int64_t *c, int64_t S, int32_t bi, SimpBuilder &sb) {
+  const int nperm = d == 2 ? 2 : 6;
+  for (int t = 0; t < nperm; ++t) {
+    int64_t v[4][3];
+    for (int q = 0; q < d; ++q) v[0][q] = c[q];
+    for (int m = 0; m < d - 1; ++m) {
+      for (int q = 0; q < d; ++q) v[m + 1][q] = v[m][q];
+      v[m + 1][perm_at(d, t, m)] += S;
+    }
+    for (int q = 0; q < d; ++q) v[d][q] = c[q] + S;
+    int64_t flat[12];
+    for (int m = 0; m <= d; ++m)
+      for (int q = 0; q < d; ++q) flat[m * d + q] = v[m][q];
+    sb.add(flat, d + 1, bi, t);
+  }
+}
+
+static bool neighbour_refined(const Hierarchy &h, BoxCode b, int ox, int oy, int oz) {
+  BoxCode nb;
+  std::array<int, 3> o{ox, oy, oz};
+  if (!offset_box(b, o, h.d, &nb)) return false;
+  return h.R.count(nb) > 0;
+}
+
+static void fan2(const Hierarchy &h, BoxCode b, const int64_t *c, int64_t S, int32_t bi, SimpBuilder &sb) {
+  const int64_t H = S / 2;
+  int64_t LL[2] = {c[0], c[1]}, LR[2] = {c[0] + S, c[1]}, UR[2] = {c[0] + S, c[1] + S}, UL[2] = {c[0], c[1] + S};
+  int64_t C[2] = {c[0] + H, c[1] + H};
+  const int64_t *E[4][2] = {{LL, LR}, {LR, UR}, {UR, UL}, {UL, LL}};
+  const int O[4][2] = {{0, -1}, {1, 0}, {0, 1}, {-1, 0}};
+  int t = 0;
+  for (int e = 0; e < 4; ++e) {
+    const int64_t *v0 = E[e][0], *v1 = E[e][1];
+    if (neighbour_refined(h, b, O[e][0], O[e][1], 0)) {
+      int64_t m[2] = {(v0[0] + v1[0]) / 2, (v0[1] + v1[1]) / 2};
+      int64_t t1[6] = {v0[0], v0[1], m[0], m[1], C[0], C[1]};
+      int64_t t2[6] = {m[0], m[1], v1[0], v1[1], C[0], C[1]};
+      sb.add(t1, 3, bi, t++);
+      sb.add(t2, 3, bi, t++);
+    } else {
+      int64_t t1[6] = {v0[0], v0[1], v1[0], v1[1], C[0], C[1]};
+      sb.add(t1, 3, bi, t++);
+    }
+  }
+}
+
+static void fan3(const Hierarchy &h, BoxCode b, const int64_t *c, int64_t S, int32_t bi, SimpBuilder &sb) {
+  const int64_t H = S / 2;
+  int64_t C[3] = {c[0] + H, c[1] + H, c[2] + H};
+  int t = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+    for (int s = 0; s < 2; ++s) {
+      int of[3] = {0, 0, 0};
+      of[ax] = 2 * s - 1;
+      int64_t base[3] = {c[0], c[1], c[2]};
+      base[ax] += s * S;
+      auto P = [&](int al2, int be2, int64_t *out) {
+        for (int q = 0; q < 3; ++q) out[q] = base[q];
+        out[u] += al2 * H;
+        out[v] += be2 * H;
+      };
+      auto inR = [&](const int *o) { return neighbour_refined(h, b, o[0], o[1], o[2]); };
+      // face edges counter-clockwise in (u, v): bottom, right, top, left (half-units)
+      const int ea[4][4] = {{0, 0, 2, 0}, {2, 0, 2, 2}, {2, 2, 0, 2}, {0, 2, 0, 0}};
+      int ip[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      ip[0][v] = -1;
+      ip[1][u] = 1;
+      ip[2][v] = 1;
+      ip[3][u] = -1;
+      bool mid[4], anymid = false;
+      for (int e = 0; e < 4; ++e) {
+        int both[3] = {of[0] + ip[e][0], of[1] + ip[e][1], of[2] + ip[e][2]};
+        mid[e] = inR(of) || inR(ip[e]) || inR(both);
+        anymid = anymid || mid[e];
+      }
+      std::vector<std::array<int64_t, 9>> tris;
+      auto push = [&](const int64_t *p, const int64_t *q, const int64_t *r) {
+        std::array<int64_t, 9> a{p[0], p[1], p[2], q[0], q[1], q[2], r[0], r[1], r[2]};
+        tris.push_back(a);
+      };
+      if (inR(of)) {
+        for (int be0 = 0; be0 < 2; ++be0)
+          for (int al0 = 0; al0 < 2; ++al0) {
+            int64_t p00[3], p10[3], p11[3], p01[3];
+            P(al0, be0, p00);
+            P(al0 + 1, be0, p10);
+            P(al0 + 1, be0 + 1, p11);
+            P(al0, be0 + 1, p01);
+            push(p00, p10, p11);
+            push(p00, p01, p11);
+          }
+      } else if (anymid) {
+        int64_t FC[3];
+        P(1, 1, FC);
+        for (int e = 0; e < 4; ++e) {
+          int64_t p0[3], p1[3];
+          P(ea[e][0], ea[e][1], p0);
+          P(ea[e][2], ea[e][3], p1);
+          if (mid[e]) {
+            int64_t pm[3] = {(p0[0] + p1[0]) / 2, (p0[1] + p1[1]) / 2, (p0[2] + p1[2]) / 2};
+            push(p0, pm, FC);
+            push(pm, p1, FC);
+          } else {
+            push(p0, p1, FC);
+          }
+        }
+      } else {
+        int64_t p00[3], p20[3], p22[3], p02[3];
+        P(0, 0, p00);
+        P(2, 0, p20);
+        P(2, 2, p22);
+        P(0, 2, p02);
+        push(p00, p20, p22);
+        push(p00, p02, p22);
+      }
+      for (auto &tr : tris) {
+        int64_t flat[12];
+        for (int q = 0; q < 9; ++q) flat[q] = tr[q];
+        for (int q = 0; q < 3; ++q) flat[9 + q] = C[q];
+        sb.add(flat, 4, bi, t++);
+      }
+    }
+  }
+}
+
+static bool is_fan(const Hierarchy &h, BoxCode b, int level) {
+  if (box_level(b, h.d) >= level) return false;
+  static thread_local std::vector<std::array<int, 3>> offs2 = touch_offsets(2), offs3 = touch_offsets(3);
+  const auto &offs = h.d == 2 ? offs2 : offs3;
+  for (const auto &o : offs) {
+    BoxCode nb;
+    if (offset_box(b, o, h.d, &nb) && h.R.count(nb)) return true;
+  }
+  return false;
+}
+
+const LevelMesh &level_mesh(Hierarchy &h, int level) {
+  auto it = h.meshes.find(level);
+  if (it != h.meshes.end()) return it->second;
+  const int d = h.d, J = h.J;
+  LevelMesh lm;
+  lm.level = level;
+  // active boxes: tree boxes of this level, leaves of coarser levels
+  std::vector<BoxCode> act;
+  for (BoxCode b : h.leaves)
+    if (box_level(b, d) < level) act.push_back(b);
+  if (level == 1) {
+    act.push_back((BoxCode)1);
+  } else {
+    for (BoxCode b : h.R)
+      if (box_level(b, d) == level - 1)
+        for (int ci = 0; ci < (1 << d); ++ci) act.push_back((b << d) | (BoxCode)ci);
+  }
+  std::vector<std::pair<unsigned __int128, BoxCode>> keyed(act.size());
+  for (size_t i = 0; i < act.size(); ++i) {
+    int64_t idx[3], cor[3];
+    box_index(act[i], d, idx);
+    const int sh = J - box_level(act[i], d) + 1;
+    for (int q = 0; q < d; ++q) cor[q] = idx[q] << sh;
+    keyed[i] = {morton_point(cor, d, J + 1), act[i]};
+  }
+  std::sort(keyed.begin(), keyed.end());
+  lm.boxes.resize(act.size());
+  lm.fan.resize(act.size());
+  SimpBuilder sb{d, {}, {}, {}};
+  for (size_t i = 0; i < keyed.size(); ++i) {
+    BoxCode b = keyed[i].second;
+    lm.boxes[i] = b;
+    lm.box_index[b] = (int32_t)i;
+    int64_t idx[3], cor[3];
+    box_index(b, d, idx);
+    const int64_t S = (int64_t)1 << (J - box_level(b, d) + 1);
+    for (int q = 0; q < d; ++q) cor[q] = idx[q] * S;
+    bool f = is_fan(h, b, level);
+    lm.fan[i] = f;
+    if (!f)
+      kuhn_simplices(d, cor, S, (int32_t)i, sb);
+    else if (d == 2)
+      fan2(h, b, cor, S, (int32_t)i, sb);
+    else
+      fan3(h, b, cor, S, (int32_t)i, sb);
+  }
+  const int64_t ns = (int64_t)sb.box.size(), nvtx = ns * (d + 1);
+  std::vector<unsigned __int128> vk(nvtx);
+  for (int64_t i = 0; i < nvtx; ++i) vk[i] = morton_point(&sb.pts[i * d], d, J + 1);
+  std::vector<unsigned __int128> uk(vk);
+  std::sort(uk.begin(), uk.end());
+  uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+  lm.simp.resize(nvtx);
+  const int64_t nv = (int64_t)uk.size();
+  lm.verts.assign(nv * d, 0);
+  for (int64_t i = 0; i < nvtx; ++i) {
+    int64_t r = std::lower_bound(uk.begin(), uk.end(), vk[i]) - uk.begin();
+    lm.simp[i] = r;
+    for (int q = 0; q < d; ++q) lm.verts[r * d + q] = sb.pts[i * d + q];
+  }
+  lm.simp_box = std::move(sb.box);
+  lm.simp_tmpl = std::move(sb.tmpl);
+  lm.box_simp.assign(lm.boxes.size() + 1, 0);
+  for (int64_t s = 0; s < ns; ++s) lm.box_simp[lm.simp_box[s] + 1]++;
+  for (size_t i = 0; i < lm.boxes.size(); ++i) lm.box_simp[i + 1] += lm.box_simp[i];
+  const int64_t top = (int64_t)1 << J;
+  lm.dof_of_vert.assign(nv, -1);
+  for (int64_t v = 0; v < nv; ++v) {
+    bool in = true;
+    for (int q = 0; q < d; ++q) {
+      int64_t x = lm.verts[v * d + q];
+      in = in && x > 0 && x < top;
+    }
+    if (in) {
+      lm.dof_of_vert[v] = (int64_t)lm.dof_vert.size();
+      lm.dof_vert.push_back(v);
+    }
+  }
+  return h.meshes.emplace(level, std::move(lm)).first->second;
+}
+
+// ---------------------------------------------------------------------------
+// auxiliary operators (Section 4.1)
+// ---------------------------------------------------------------------------
+
+static int64_t idet(int d, const int64_t E[3][3]) {
+  if (d == 2) return E[0][0] * E[1][1] - E[0][1] * E[1][0];
+  return E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) - E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+         E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+}
+
+// integer cofactor vectors a_0..a_d of a simplex in units of half its box side
+static int64_t aux_cofactors(const Hierarchy &h, const LevelMesh &lm, int64_t s, int64_t a[4][3], int64_t *half) {
+  const int d = h.d;
+  BoxCode b = lm.boxes[lm.simp_box[s]];
+  *half = (int64_t)1 << (h.J - box_level(b, d));
+  const int64_t *v0 = &lm.verts[lm.simp[s * (d + 1)] * d];
+  int64_t M[3][3];  // M[r][k] = component r of edge k
+  for (int k = 0; k < d; ++k) {
+    const int64_t *vk = &lm.verts[lm.simp[s * (d + 1) + k + 1] * d];
+    for (int r = 0; r < d; ++r) M[r][k] = (vk[r] - v0[r]) / *half;
+  }
+  const int64_t det = idet(d, M);
+  // rows of adj(M): a_{k+1}
+  if (d == 2) {
+    a[1][0] = M[1][1];
+    a[1][1] = -M[0][1];
+    a[2][0] = -M[1][0];
+    a[2][1] = M[0][0];
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+        a[i + 1][j] = M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0];
+      }
+  }
+  for (int r = 0; r < d; ++r) {
+    int64_t sum = 0;
+    for (int k = 1; k <= d; ++k) sum += a[k][r];
+    a[0][r] = -sum;
+  }
+  return det;
+}
+
+static void assemble_level(Hierarchy &h, int level, Csr &A, bool pattern) {
+  const int d = h.d, k = d + 1;
+  const LevelMesh &lm = h.meshes.at(level);
+  const int64_t ns = (int64_t)lm.simp_box.size();
+  if (pattern)
+    pattern_from_elements(lm.n(), ns, k, [&](int64_t s, int i) { return lm.dof_of_vert[lm.simp[s * k + i]]; }, A);
+  else
+    std::fill(A.v.begin(), A.v.end(), 0.0);
+  const double fact = d == 2 ? 2.0 : 6.0;
+  const double unit = std::ldexp(h.L, -h.J);
+  for (int64_t s = 0; s < ns; ++s) {
+    int64_t a[4][3], half;
+    const int64_t det = aux_cofactors(h, lm, s, a, &half);
+    const double denom = fact * (double)std::llabs(det);
+    BoxCode b = lm.boxes[lm.simp_box[s]];
+    const std::vector<double> &w = h.kuhn_w.at(b);
+    const double kap = lm.fan[lm.simp_box[s]] ? w[0] : w[lm.simp_tmpl[s]];
+    for (int i = 0; i < k; ++i) {
+      int64_t ui = lm.dof_of_vert[lm.simp[s * k + i]];
+      if (ui < 0) continue;
+      for (int j = 0; j < k; ++j) {
+        int64_t uj = lm.dof_of_vert[lm.simp[s * k + j]];
+        if (uj < 0) continue;
+        int64_t dot = 0;
+        for (int r = 0; r < d; ++r) dot += a[i][r] * a[j][r];
+        double val = (double)dot / denom;
+        if (d == 3) val = val * ((double)half * unit);
+        val = val * kap;
+        A.v[find_col(A, ui, (int32_t)uj)] += val;
+      }
+    }
+  }
+  if (pattern) {
+    // drop couplings that are exactly zero (right angles): the pattern is geometric
+    Csr B;
+    B.nrows = A.nrows;
+    B.ncols = A.ncols;
+    B.rp.assign(A.nrows + 1, 0);
+    for (int64_t i = 0; i < A.nrows; ++i) {
+      for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+        if (A.v[p] != 0.0 || A.ci[p] == i) {
+          B.ci.push_back(A.ci[p]);
+          B.v.push_back(A.v[p]);
+        }
+      B.rp[i + 1] = (int64_t)B.ci.size();
+    }
+    A = std::move(B);
+  }
+}
+
+// exact barycentric coordinates of integer point X in simplex s; false if outside
+static bool bary_exact(const LevelMesh &lm, int d, int64_t s, const int64_t *X, double *lam) {
+  const int64_t *V[4];
+  for (int m = 0; m <= d; ++m) V[m] = &lm.verts[lm.simp[s * (d + 1) + m] * d];
+  auto det = [&](const int64_t *P[4]) -> __int128 {
+    __int128 E[3][3];
+    for (int k = 0; k < d; ++k)
+      for (int r = 0; r < d; ++r) E[r][k] = (__int128)(P[k + 1][r] - P[0][r]);
+    if (d == 2) return E[0][0] * E[1][1] - E[0][1] * E[1][0];
+    return E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) - E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+           E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  };
+  __int128 tot = det(V);
+  __int128 num[4];
+  for (int m = 0; m <= d; ++m) {
+    const int64_t *Q[4];
+    for (int r = 0; r <= d; ++r) Q[r] = r == m ? X : V[r];
+    num[m] = det(Q);
+    if (tot < 0) num[m] = -num[m];
+    if (num[m] < 0) return false;
+  }
+  if (tot < 0) tot = -tot;
+  for (int m = 0; m <= d; ++m) lam[m] = (double)num[m] / (double)tot;
+  return true;
+}
+
+static void build_prolongation(Hierarchy &h, int level, Csr &P) {
+  const int d = h.d, J = h.J;
+  const LevelMesh &fine = h.meshes.at(level);
+  const LevelMesh &coarse = h.meshes.at(level - 1);
+  P.nrows = fine.n();
+  P.ncols = coarse.n();
+  P.rp.assign(P.nrows + 1, 0);
+  P.ci.clear();
+  P.v.clear();
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < fine.n(); ++i) {
+    const int64_t *X = &fine.verts[fine.dof_vert[i] * d];
+    int32_t bi = -1;
+    for (int k = 1; k <= level - 1 && bi < 0; ++k) {
+      int64_t idx[3];
+      const int sh = J - k + 1;
+      const int64_t nmax = ((int64_t)1 << (k - 1)) - 1;
+      for (int q = 0; q < d; ++q) idx[q] = std::min(X[q] >> sh, nmax);
+      auto it = coarse.box_index.find(box_code(k, idx, d));
+      if (it != coarse.box_index.end()) bi = it->second;
+    }
+    if (bi < 0) fail(ASMG_EINVAL, "prolongation: point location failed");
+    double lam[4];
+    int64_t sfound = -1;
+    for (int64_t s = coarse.box_simp[bi]; s < coarse.box_simp[bi + 1]; ++s)
+      if (bary_exact(coarse, d, s, X, lam)) {
+        sfound = s;
+        break;
+      }
+    if (sfound < 0) fail(ASMG_EINVAL, "prolongation: no containing simplex");
+    row.clear();
+    for (int m = 0; m <= d; ++m) {
+      if (lam[m] == 0.0) continue;
+      int64_t j = coarse.dof_of_vert[coarse.simp[sfound * (d + 1) + m]];
+      if (j < 0) continue;
+      row.push_back({(int32_t)j, lam[m]});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto &e : row) {
+      if (!P.ci.empty() && (int64_t)P.ci.size() > P.rp[i] && P.ci.back() == e.first) {
+        P.v.back() += e.second;
+      } else {
+        P.ci.push_back(e.first);
+        P.v.push_back(e.second);
+      }
+    }
+    P.rp[i + 1] = (int64_t)P.ci.size();
+  }
+}
+
+void build_levels(Hierarchy &h) {
+  compute_kuhn_means(h);
+  const int J = h.J;
+  const int Nc = h.opt.coarse_max_dofs > 0 ? h.opt.coarse_max_dofs : 1024;
+  h.level_n.assign(J, -1);
+  h.lc = 1;
+  for (int l = J; l >= 1; --l) {
+    const LevelMesh &lm = level_mesh(h, l);
+    h.level_n[l - 1] = lm.n();
+    if (lm.n() <= Nc) {
+      h.lc = l;
+      break;
+    }
+  }
+  h.Al.clear();
+  h.P.clear();
+  for (int l = J; l >= h.lc; --l) assemble_level(h, l, h.Al[l], true);
+  for (int l = J; l > h.lc; --l) build_prolongation(h, l, h.P[l]);
+}
+
+void assemble_aux_values(Hierarchy &h) {
+  h.leaf_kappa.clear();
+  // recompute kappa~ from the sorted clusters: rebuilt by build_tree's logic on the new kappa
+  const int d = h.d, D = key_bits(d);
+  std::vector<BoxCode> code(h.ne);
+  for (int64_t e = 0; e < h.ne; ++e) code[e] = box_code(D + 1, &h.keys[e * d], d);
+  std::vector<int64_t> order(h.ne);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return code[x] < code[y] || (code[x] == code[y] && x < y);
+  });
+  std::vector<BoxCode> mc(h.ne);
+  for (int64_t i = 0; i < h.ne; ++i) mc[i] = code[order[i]];
+  for (BoxCode b : h.leaves) {
+    BoxCode q = b;
+    while (true) {
+      int lev = box_level(q, d);
+      int sh = d * (D + 1 - lev);
+      int64_t s = std::lower_bound(mc.begin(), mc.end(), q << sh) - mc.begin();
+      int64_t e = std::lower_bound(mc.begin(), mc.end(), (q + 1) << sh) - mc.begin();
+      if (e > s) {
+        double sum = 0;
+        for (int64_t i = s; i < e; ++i) sum += h.kappa[order[i]];
+        h.leaf_kappa[b] = sum / (double)(e - s);
+        break;
+      }
+      q >>= d;
+    }
+  }
+  compute_kuhn_means(h);
+  for (int l = h.J; l >= h.lc; --l) assemble_level(h, l, h.Al[l], false);
+}
+
+// ---------------------------------------------------------------------------
+// Scott-Zhang transfer (Section 4.1)
+// ---------------------------------------------------------------------------
+
+static void collect_leaves(const Hierarchy &h, BoxCode b, const double *lo, const double *hi,
+                           std::vector<BoxCode> &out) {
+  const int d = h.d;
+  int64_t idx[3];
+  box_index(b, d, idx);
+  const int lev = box_level(b, d);
+  const double side = std::ldexp(h.L, -(lev - 1));
+  for (int q = 0; q < d; ++q) {
+    double b0 = h.a[q] + (double)idx[q] * side, b1 = h.a[q] + (double)(idx[q] + 1) * side;
+    if (b0 > hi[q] || b1 < lo[q]) return;
+  }
+  if (!h.R.count(b)) {
+    out.push_back(b);
+    return;
+  }
+  for (int ci = 0; ci < (1 << d); ++ci) collect_leaves(h, (b << d) | (BoxCode)ci, lo, hi, out);
+}
+
+static inline double det3(const double *u, const double *v, const double *w) {
+  return u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) + u[2] * (v[0] * w[1] - v[1] * w[0]);
+}
+
+void build_transfer(Hierarchy &h) {
+  const int d = h.d, k = d + 1;
+  const LevelMesh &lm = level_mesh(h, h.J);
+  const double unit = std::ldexp(h.L, -h.J);
+  const int64_t n = h.n();
+  // sigma_i: 2-D the edge to the smallest-id neighbour, 3-D the lexicographically smallest face
+  std::vector<int64_t> sj(h.nv, INT64_MAX), sk(h.nv, INT64_MAX);
+  for (int64_t e = 0; e < h.ne; ++e) {
+    const int32_t *ev = &h.elems[e * k];
+    for (int a = 0; a < k; ++a) {
+      int64_t v = ev[a];
+      if (d == 2) {
+        for (int b = 0; b < k; ++b)
+          if (b != a) sj[v] = std::min<int64_t>(sj[v], ev[b]);
+      } else {
+        int o[3], c = 0;
+        for (int b = 0; b < 4; ++b)
+          if (b != a) o[c++] = ev[b];
+        for (int x = 0; x < 3; ++x)
+          for (int y = x + 1; y < 3; ++y) {
+            int64_t j = std::min(o[x], o[y]), kk = std::max(o[x], o[y]);
+            if (j < sj[v] || (j == sj[v] && kk < sk[v])) {
+              sj[v] = j;
+              sk[v] = kk;
+            }
+          }
+      }
+    }
+  }
+  Csr &Pi = h.Pi;
+  Pi.nrows = n;
+  Pi.ncols = lm.n();
+  Pi.rp.assign(n + 1, 0);
+  Pi.ci.clear();
+  Pi.v.clear();
+  std::vector<BoxCode> lv;
+  std::vector<std::pair<int32_t, double>> acc;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t vi = h.dofs[i];
+    double P[3][3];
+    int64_t sv[3] = {vi, sj[vi], sk[vi]};
+    for (int m = 0; m < d; ++m)
+      for (int q = 0; q < d; ++q) P[m][q] = h.coords[sv[m] * d + q];
+    double lo[3], hi[3];
+    for (int q = 0; q < d; ++q) {
+      lo[q] = hi[q] = P[0][q];
+      for (int m = 1; m < d; ++m) {
+        lo[q] = std::min(lo[q], P[m][q]);
+        hi[q] = std::max(hi[q], P[m][q]);
+      }
+    }
+    lv.clear();
+    collect_leaves(h, (BoxCode)1, lo, hi, lv);
+    acc.clear();
+    for (BoxCode b : lv) {
+      auto it = lm.box_index.find(b);
+      if (it == lm.box_index.end()) continue;
+      const int32_t bi = it->second;
+      for (int64_t s = lm.box_simp[bi]; s < lm.box_simp[bi + 1]; ++s) {
+        double T[4][3];
+        int64_t cols[4];
+        for (int m = 0; m < k; ++m) {
+          int64_t vv = lm.simp[s * k + m];
+          cols[m] = lm.dof_of_vert[vv];
+          for (int q = 0; q < d; ++q) T[m][q] = h.a[q] + (double)lm.verts[vv * d + q] * unit;
+        }
+        if (d == 2) {
+          // barycentric coordinates of the segment ends; lambda_m(t) affine in t
+          auto cross = [](double ux, double uy, double vx, double vy) { return ux * vy - uy * vx; };
+          const double a2 = cross(T[1][0] - T[0][0], T[1][1] - T[0][1], T[2][0] - T[0][0], T[2][1] - T[0][1]);
+          double l0[3], l1[3];
+          for (int e = 0; e < 2; ++e) {
+            const double x = P[e][0], y = P[e][1];
+            double *l = e == 0 ? l0 : l1;
+            l[0] = cross(T[1][0] - x, T[1][1] - y, T[2][0] - x, T[2][1] - y) / a2;
+            l[1] = cross(T[2][0] - x, T[2][1] - y, T[0][0] - x, T[0][1] - y) / a2;
+            l[2] = cross(T[0][0] - x, T[0][1] - y, T[1][0] - x, T[1][1] - y) / a2;
+          }
+          double t0 = 0.0, t1 = 1.0;
+          bool empty = false, on_facet = false;
+          for (int m = 0; m < 3; ++m) {
+            const double sl = l1[m] - l0[m];
+            if (l0[m] == 0.0 && l1[m] == 0.0) on_facet = true;
+            if (sl == 0.0) {
+              if (l0[m] < 0.0) empty = true;
+              continue;
+            }
+            const double tc = -l0[m] / sl;
+            if (sl > 0)
+              t0 = std::max(t0, tc);
+            else
+              t1 = std::min(t1, tc);
+          }
+          if (empty || !(t1 > t0)) continue;
+          const double wgt = on_facet ? 0.5 : 1.0, tm = 0.5 * (t0 + t1);
+          for (int m = 0; m < 3; ++m) {
+            if (cols[m] < 0) continue;
+            auto f = [&](double t) { return (4.0 - 6.0 * t) * (l0[m] + t * (l1[m] - l0[m])); };
+            const double val = (t1 - t0) / 6.0 * (f(t0) + 4.0 * f(tm) + f(t1)) * wgt;
+            if (val != 0.0) acc.push_back({(int32_t)cols[m], val});
+          }
+        } else {
+          // barycentric coordinates of the face corners; clip the reference triangle in (s, t)
+          double c[4][3];
+          double e1[3], e2[3], e3[3];
+          for (int q = 0; q < 3; ++q) {
+            e1[q] = T[1][q] - T[0][q];
+            e2[q] = T[2][q] - T[0][q];
+            e3[q] = T[3][q] - T[0][q];
+          }
+          const double vol = det3(e1, e2, e3);
+          for (int corner = 0; corner < 3; ++corner) {
+            const double *x = P[corner];
+            for (int m = 0; m < 4; ++m) {
+              double Q[4][3];
+              for (int r = 0; r < 4; ++r)
+                for (int q = 0; q < 3; ++q) Q[r][q] = r == m ? x[q] : T[r][q];
+              double f1[3], f2[3], f3[3];
+              for (int q = 0; q < 3; ++q) {
+                f1[q] = Q[1][q] - Q[0][q];
+                f2[q] = Q[2][q] - Q[0][q];
+                f3[q] = Q[3][q] - Q[0][q];
+              }
+              c[m][corner] = det3(f1, f2, f3) / vol;
+            }
+          }
+          std::vector<std::array<double, 2>> poly{{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}}, out;
+          bool on_facet = false;
+          for (int m = 0; m < 4 && poly.size() >= 3; ++m) {
+            const double c0 = c[m][0], c1 = c[m][1], c2 = c[m][2];
+            if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) on_facet = true;
+            auto f = [&](const std::array<double, 2> &p) { return c0 + p[0] * (c1 - c0) + p[1] * (c2 - c0); };
+            out.clear();
+            const size_t np = poly.size();
+            for (size_t q = 0; q < np; ++q) {
+              const auto &A_ = poly[q];
+              const auto &B_ = poly[(q + 1) % np];
+              const double fa = f(A_), fb = f(B_);
+              if (fa >= 0) out.push_back(A_);
+              if ((fa > 0 && fb < 0) || (fa < 0 && fb > 0)) {
+                const double t = fa / (fa - fb);
+                out.push_back({A_[0] + t * (B_[0] - A_[0]), A_[1] + t * (B_[1] - A_[1])});
+              }
+            }
+            poly.swap(out);
+          }
+          if (poly.size() < 3) continue;
+          const double wgt = on_facet ? 0.5 : 1.0;
+          for (int m = 0; m < 4; ++m) {
+            if (cols[m] < 0) continue;
+            const double c0 = c[m][0], c1 = c[m][1], c2 = c[m][2];
+            auto f = [&](double s_, double t_) {
+              return (18.0 - 24.0 * (s_ + t_)) * (c0 + s_ * (c1 - c0) + t_ * (c2 - c0));
+            };
+            double val = 0.0;
+            for (size_t q = 1; q + 1 < poly.size(); ++q) {
+              const auto &A_ = poly[0], &B_ = poly[q], &C_ = poly[q + 1];
+              const double area =
+                  0.5 * std::fabs((B_[0] - A_[0]) * (C_[1] - A_[1]) - (B_[1] - A_[1]) * (C_[0] - A_[0]));
+              if (area == 0.0) continue;
+              val += area *
+                     (f(0.5 * (A_[0] + B_[0]), 0.5 * (A_[1] + B_[1])) + f(0.5 * (B_[0] + C_[0]), 0.5 * (B_[1] + C_[1])) +
+                      f(0.5 * (C_[0] + A_[0]), 0.5 * (C_[1] + A_[1]))) /
+                     3.0;
+            }
+            val *= wgt;
+            if (val != 0.0) acc.push_back({(int32_t)cols[m], val});
+          }
+        }
+      }
+    }
+    std::sort(acc.begin(), acc.end(), [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+      return x.first < y.first;
+    });
+    for (size_t q = 0; q < acc.size(); ++q) {
+      if (q > 0 && acc[q].first == acc[q - 1].first)
+        Pi.v.back() += acc[q].second;
+      else {
+        Pi.ci.push_back(acc[q].first);
+        Pi.v.push_back(acc[q].second);
+      }
+    }
+    Pi.rp[i + 1] = (int64_t)Pi.ci.size();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multicolour ordering
+// ---------------------------------------------------------------------------
+
+static inline uint32_t fmix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed) {
+  const int64_t n = A.nrows;
+  std::vector<int64_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<uint32_t> w(n);
+  for (int64_t i = 0; i < n; ++i) w[i] = fmix32((uint32_t)i ^ seed);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return w[x] > w[y] || (w[x] == w[y] && x > y);
+  });
+  std::vector<int32_t> col(n, -1);
+  std::vector<int64_t> mark(64, -1);
+  for (int64_t i : order) {
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      int32_t c = col[A.ci[p]];
+      if (c >= 0) {
+        if (c >= (int32_t)mark.size()) mark.resize(c + 1, -1);
+        mark[c] = i;
+      }
+    }
+    int32_t c = 0;
+    while (c < (int32_t)mark.size() && mark[c] == i) ++c;
+    col[i] = c;
+  }
+  return col;
+}
+
+void build_colourings(Hierarchy &h) {
+  h.colour_fine = greedy_colouring(h.A, h.opt.colour_seed);
+  h.colour_aux.clear();
+  for (int l = h.lc + 1; l <= h.J; ++l) h.colour_aux[l] = greedy_colouring(h.Al.at(l), h.opt.colour_seed);
+}
+
+// ---------------------------------------------------------------------------
+// bottom of the V-cycle: Cholesky factor A_lc = L L^T and the explicit inverse
+// ---------------------------------------------------------------------------
+
+void build_coarse(Hierarchy &h) {
+  const Csr &A = h.Al.at(h.lc);
+  const int64_t n = A.nrows;
+  h.nc = n;
+  h.coarse_inv.assign(n * n, 0.0);
+  if (n == 0) return;
+  std::vector<double> Lm(n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) Lm[i * n + A.ci[p]] = A.v[p];
+  for (int64_t j = 0; j < n; ++j) {
+    double s = Lm[j * n + j];
+    for (int64_t k = 0; k < j; ++k) s -= Lm[j * n + k] * Lm[j * n + k];
+    if (!(s > 0)) fail(ASMG_ENOTSPD, "coarse matrix is not positive definite");
+    const double djj = std::sqrt(s);
+    Lm[j * n + j] = djj;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double t = Lm[i * n + j];
+      for (int64_t k = 0; k < j; ++k) t -= Lm[i * n + k] * Lm[j * n + k];
+      Lm[i * n + j] = t / djj;
+    }
+    for (int64_t i = 0; i < j; ++i) Lm[i * n + j] = 0.0;
+  }
+  // inverse column by column: solve L y = e_c, L^T x = y
+  std::vector<double> y(n);
+  for (int64_t c = 0; c < n; ++c) {
+    for (int64_t i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int64_t k = 0; k < i; ++k) s -= Lm[i * n + k] * y[k];
+      y[i] = s / Lm[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int64_t k = i + 1; k < n; ++k) s -= Lm[k * n + i] * h.coarse_inv[k * n + c];
+      h.coarse_inv[i * n + c] = s / Lm[i * n + i];
+    }
+  }
+}
+
+}  // namespace asmg

@@ -1,0 +1,107 @@
+// Host-side setup of the ASMG hierarchy: data structures shared by the setup,
+// the device upload and the C ABI. Everything here is plain C++17.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/asmg.h"
+
+namespace asmg {
+
+struct AsmgError {
+  int code;
+  std::string msg;
+};
+
+// Compressed sparse rows with int64 row pointers, int32 columns, FP64 values.
+struct Csr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Box of the regular box tree, encoded as a locational code:
+// (1 << d*(level-1)) | Morton(index), axis 0 most significant in each bit group.
+using BoxCode = uint64_t;
+
+// One auxiliary triangulation sigma^(level) (Section 3.3).
+struct LevelMesh {
+  int level = 0;
+  std::vector<int64_t> verts;       // nv * d integer coordinates (units of L 2^-J), Morton order
+  std::vector<int64_t> simp;        // ns * (d+1) vertex indices
+  std::vector<int32_t> simp_box;    // box index of each simplex
+  std::vector<int8_t> simp_tmpl;    // template position (Kuhn permutation for non-fan boxes)
+  std::vector<BoxCode> boxes;       // active boxes, Morton order of lower corners
+  std::vector<uint8_t> fan;         // fan flag per box
+  std::vector<int64_t> box_simp;    // simplex range per box (nb + 1)
+  std::unordered_map<BoxCode, int32_t> box_index;
+  std::vector<int64_t> dof_vert;    // vertex index of each unknown
+  std::vector<int64_t> dof_of_vert; // unknown index of each vertex (-1 on the boundary)
+  int64_t nverts() const { return (int64_t)dof_of_vert.size(); }
+  int64_t n() const { return (int64_t)dof_vert.size(); }
+};
+
+struct Hierarchy {
+  // input
+  int d = 2;
+  int64_t nv = 0, ne = 0;
+  std::vector<double> coords;
+  std::vector<int32_t> elems;
+  std::vector<double> kappa;
+  std::vector<uint8_t> dirichlet;
+  asmg_options opt{};
+
+  // fine problem (Section 2)
+  std::vector<int64_t> dofs;          // vertex id per unknown
+  std::vector<int64_t> dof_of_vertex; // -1 for Dirichlet vertices
+  Csr A;                              // unknown order, diagonal included
+  std::vector<double> K1;             // per-element stiffness at kappa = 1, ne * (d+1)^2
+
+  // cluster tree (Sections 3.1-3.2)
+  double a[3] = {0, 0, 0};
+  double L = 1;
+  std::vector<int64_t> keys;          // ne * d
+  std::unordered_set<BoxCode> R0, R;  // refined boxes before / after closure
+  std::vector<BoxCode> leaves;        // sorted by (level, index)
+  std::unordered_map<BoxCode, double> leaf_kappa;
+  std::unordered_map<BoxCode, std::vector<double>> kuhn_w;  // mean coefficient per Kuhn simplex
+  int J = 1;
+
+  // auxiliary hierarchy (Sections 3.3-3.4, 4.1)
+  std::unordered_map<int, LevelMesh> meshes;
+  std::vector<int64_t> level_n;       // unknowns of levels 1..J (index level-1)
+  int lc = 1;
+  std::unordered_map<int, Csr> Al;    // lc..J
+  std::unordered_map<int, Csr> P;     // lc+1..J
+  Csr Pi;                             // fine unknowns x level-J unknowns
+  std::vector<int32_t> colour_fine;
+  std::unordered_map<int, std::vector<int32_t>> colour_aux;  // lc+1..J
+  int64_t nc = 0;
+  std::vector<double> coarse_inv;     // nc * nc, row-major, explicit inverse of A_lc
+
+  int64_t n() const { return (int64_t)dofs.size(); }
+};
+
+// setup steps (setup.cpp)
+void build_fine(Hierarchy &h);
+void assemble_fine_values(Hierarchy &h);
+void build_tree(Hierarchy &h);
+void build_levels(Hierarchy &h);
+void assemble_aux_values(Hierarchy &h);
+void build_transfer(Hierarchy &h);
+void build_colourings(Hierarchy &h);
+void build_coarse(Hierarchy &h);
+const LevelMesh &level_mesh(Hierarchy &h, int level);
+
+// helpers
+int box_level(BoxCode c, int d);
+void box_index(BoxCode c, int d, int64_t *idx);
+BoxCode box_code(int level, const int64_t *idx, int d);
+
+}  // namespace asmg

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every function include/asmg.h declares, and rejects bad input (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+A = pytest.importorskip("paper_1410_2153_amd")
+
+
+def _declared():
+    hdr = open(os.path.join(ROOT, "include", "asmg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**(asmg_\w+)\s*\(", hdr, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(A.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(A.EXPORTED)
+
+
+def test_rejects_invalid_input():
+    coords, elems, _ = W.square_mesh(6, 0.2)
+    k = np.ones(len(elems))
+    with pytest.raises(A.AsmgError) as e:
+        A.Solver(coords, elems, -k, device=-1)
+    assert e.value.code == A.EINVAL
+    bad = elems.copy()
+    bad[3, 1] = 10 ** 6
+    with pytest.raises(A.AsmgError):
+        A.Solver(coords, bad, k, device=-1)
+    deg = elems.copy()
+    deg[0] = [0, 0, 1]
+    with pytest.raises(A.AsmgError) as e:
+        A.Solver(coords, deg, k, device=-1)
+    assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError):
+        A.Solver(coords, elems, k, device=-1, nu_aux=0)
+
+
+def test_host_only_handle_refuses_device_calls():
+    coords, elems, _ = W.square_mesh(6, 0.2)
+    S = A.Solver(coords, elems, np.ones(len(elems)), device=-1)
+    with pytest.raises(A.AsmgError) as e:
+        S.solve(np.ones(S.n))
+    assert e.value.code == A.EDEVICE
+    with pytest.raises(A.AsmgError) as e:
+        S.export("nonsense")
+    assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError):
+        S.export("level_verts", level=99)
+
+
+def test_update_coefficient_host_only():
+    from oracle import fem
+    coords, elems, _ = W.square_mesh(10, 0.2)
+    S = A.Solver(coords, elems, np.ones(len(elems)), device=-1)
+    k2 = np.random.default_rng(0).uniform(0.5, 2.0, len(elems))
+    S.update_coefficient(k2)
+    ref, _ = fem.assemble(coords, elems, k2)
+    got = S.export_csr("A", shape=ref.shape)
+    assert abs(got - ref).max() <= 1e-13 * abs(ref).max()
+    with pytest.raises(A.AsmgError):
+        S.update_coefficient(np.zeros(len(elems)))

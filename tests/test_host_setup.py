@@ -1,0 +1,88 @@
+"""The C++ host setup (through the C ABI, host-only handle) against the oracle.
+
+Bit-exact: box keys, refined set, J, bottom level, level vertices/simplices/
+unknown numbering, sparsity patterns of A, A_l, P_l, colourings. Values: A,
+A_l, P_l, Pi to 1e-13 relative (P_l exactly).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.hierarchy import Hierarchy
+
+A = pytest.importorskip("paper_1410_2153_amd")
+
+
+def _graded_cube():
+    coords, elems, _ = W.kuhn_cube_mesh(8, 0.1, cfg=2, item=3)
+    return dict(coords=coords ** 2, elems=elems, kappa=np.random.default_rng(0).uniform(0.5, 2, len(elems))), 3
+
+
+CASES = {
+    "square64": lambda: (W.make_config(0), 0),
+    "graded": lambda: (W.make_config(1, scale=0.004), 0),
+    "cube8": lambda: (W.make_config(2, scale=1 / 16), 0),
+    "graded_cube": _graded_cube,
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    c, n_min = CASES[request.param]()
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min)
+    return c, S, H
+
+
+def test_tree(pair):
+    c, S, H = pair
+    d = c["coords"].shape[1]
+    info = S.info()
+    assert np.array_equal(S.export("keys").reshape(-1, d), H.tree.keys)
+    assert set(map(tuple, S.export("refined").reshape(-1, d + 1).tolist())) == H.tree.R
+    assert sorted(map(tuple, S.export("leaves").reshape(-1, d + 1).tolist())) == sorted(H.tree.leaves)
+    assert info["J"] == H.tree.J and info["lc"] == H.aux.lc
+
+
+def test_level_meshes(pair):
+    c, S, H = pair
+    d = c["coords"].shape[1]
+    for l in range(H.aux.lc, H.tree.J + 1):
+        lm = H.meshes.level(l)
+        assert np.array_equal(S.export("level_verts", l).reshape(-1, d), lm.verts)
+        assert np.array_equal(S.export("level_simp", l).reshape(-1, d + 1), lm.simp)
+        assert np.array_equal(S.export("level_dofs", l), lm.dof_vert)
+
+
+def _same_pattern(X, Y):
+    return np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+
+
+def test_operators(pair):
+    c, S, H = pair
+    Af = S.export_csr("A", shape=H.A.shape)
+    assert _same_pattern(Af, H.A)
+    assert abs(Af - H.A).max() <= 1e-13 * abs(H.A).max()
+    for l in range(H.aux.lc, H.tree.J + 1):
+        Al = S.export_csr("Al", l, shape=H.aux.A[l].shape)
+        assert _same_pattern(Al, H.aux.A[l])
+        assert abs(Al - H.aux.A[l]).max() <= 1e-13 * abs(H.aux.A[l]).max()
+    for l in range(H.aux.lc + 1, H.tree.J + 1):
+        P = S.export_csr("P", l, shape=H.aux.P[l].shape)
+        assert _same_pattern(P, H.aux.P[l])
+        assert abs(P - H.aux.P[l]).max() == 0.0
+    Pi = S.export_csr("Pi", shape=H.Pi.shape)
+    assert abs(Pi - H.Pi).max() <= 1e-13
+
+
+def test_colourings(pair):
+    c, S, H = pair
+    assert np.array_equal(S.export("colour_fine"), H.colour_fine)
+    for l, col in H.colour_aux.items():
+        assert np.array_equal(S.export("colour_aux", l), col)
+
+
+def test_level_sizes(pair):
+    c, S, H = pair
+    n = S.export("level_n")
+    assert list(n) == [H.meshes.level(l).n for l in range(1, H.tree.J + 1)]

@@ -173,14 +173,16 @@ def test_worked_example_kuhn_cube_uniform():
     assert tree.R == tree.R0
 
 
-def test_leaf_kappa_means():
-    c = W.make_config(1, scale=0.002)
+@pytest.mark.parametrize("cfg,scale", [(1, 0.002), (2, 1 / 16)])
+def test_leaf_kappa_means(cfg, scale):
+    c = W.make_config(cfg, scale=scale)
+    d = c["coords"].shape[1]
     tree = cluster.BoxTree(c["coords"], c["elems"])
     lk = tree.leaf_kappa(c["kappa"])
-    for lf, v in list(lk.items())[:200]:
+    for lf, v in list(lk.items())[:300]:
         q = lf
         while True:
-            bx = cluster.box_of(tree.keys, q[0], 2)
+            bx = cluster.box_of(tree.keys, q[0], d)
             m = np.all(bx == np.array(q[1:]), axis=1)
             if m.any():
                 assert v == pytest.approx(c["kappa"][m].mean(), rel=1e-14)
