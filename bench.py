@@ -1,0 +1,152 @@
+"""Benchmark: DOF-solves/s of the ASMG-preconditioned CG solve on one MI355X.
+
+Workload (default): the graded unstructured 2-D mesh: about 1.0 M vertices,
+2.0 M triangles, density proportional to 1/(r + 0.01) + 1 towards (0, 0),
+Delaunay, min angle > 20 degrees. Coefficient exp(g) with g ~ N(0, 0.5^2) per
+element, f ~ U[-1, 1] per unknown, homogeneous Dirichlet data. A step is one
+full solve, from f resident in HBM to u resident in HBM, stopping at
+||r|| <= 1e-8 ||f||. Both precisions run: the FP64 solve (`value`) and the
+FP32-preconditioner solve (`mixed`).
+
+Prints one JSON line. `roofline` is for the dominant kernel of the solve,
+timed with HIP events inside the library on torch's stream.
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same family
+on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def load_workload(scale: float):
+    import workloads as W
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"asmg_cfg1_{scale:g}.npz")
+    if os.path.exists(cache):
+        z = np.load(cache)
+        return {k: z[k] for k in z.files}
+    c = W.make_config(1, scale=scale)
+    out = dict(coords=c["coords"], elems=c["elems"], kappa=c["kappa"], f_vertex=c["f_vertex"])
+    try:
+        np.savez(cache, **out)
+    except OSError:
+        pass
+    return out
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """Oracle solve phase on a bounded sample (graded family, 20k vertices), one thread."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import workloads as W
+    from oracle.hierarchy import Hierarchy
+    c = W.make_config(1, scale=0.02)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
+    f = c["f_vertex"][H.dofs]
+    H.solve(f, 1e-8)  # warm-up (builds the per-colour slices)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        H.solve(f, 1e-8)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=H.n * reps / dt, unit="DOF-solves/s", cores=1, kind="oracle",
+                sample=f"graded mesh {len(c['coords'])} vertices ({H.n} unknowns), FP64 oracle PCG to 1e-8, "
+                       f"{reps} solves in {dt:.1f} s, 1 thread of {len(os.sched_getaffinity(0))}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1410_2153_amd as A
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    c = load_workload(args.scale)
+    log(f"workload: {len(c['coords'])} vertices, {len(c['elems'])} triangles ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64)
+    t_setup = time.perf_counter() - t0
+    info = S64.info()
+    log(f"setup {t_setup:.1f} s: {info}")
+    dofs = S64.dof_vertex()
+    f = torch.from_numpy(np.ascontiguousarray(c["f_vertex"][dofs])).to(dev)
+    n = S64.n
+
+    def run(S, steps, warmup):
+        u = torch.empty_like(f)
+        for _ in range(warmup):
+            S.solve_device(f, 1e-8, out=u)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for _ in range(steps):
+            _, it, tr = S.solve_device(f, 1e-8, out=u)
+            its.append(it)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        return dt, its, tr, u
+
+    dt64, its64, tr64, u64 = run(S64, args.steps, args.warmup)
+    log(f"fp64: {dt64 / args.steps * 1e3:.2f} ms/solve, iters {its64}, true rel res {tr64:.2e}")
+    S64.set_precision(A.PREC_MIXED)
+    dt32, its32, tr32, u32 = run(S64, args.steps, args.warmup)
+    S64.set_precision(A.PREC_FP64)
+    log(f"mixed: {dt32 / args.steps * 1e3:.2f} ms/solve, iters {its32}, true rel res {tr32:.2e}")
+    diff = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+
+    # dominant-kernel roofline and whole-preconditioner bandwidth (HIP events on torch's stream)
+    ms_spmv, by_spmv = S64.time_kernel(0, reps=50)
+    ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
+    ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
+    roof = {"bound": "hbm", "kernel": "k_matvec (fine SpMV, FP64)", "achieved": by_spmv / ms_spmv / 1e6,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by_spmv / ms_spmv / 1e6 / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": by_spmv, "ms_per_launch": ms_spmv}
+    vcyc = {"fp64": {"ms": ms_b64, "model_bytes": by_b64, "GBs": by_b64 / ms_b64 / 1e6},
+            "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6}}
+    out = {
+        "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",
+        "value": n * args.steps / dt64, "unit": "DOF-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"graded 2-D Delaunay mesh, {len(c['coords'])} vertices, {len(c['elems'])} "
+                               f"triangles, kappa=exp(N(0,0.5^2)), f~U[-1,1], PCG to 1e-8 from u0=0",
+                   "unknowns": n, "iterations_fp64": its64[-1], "setup_s": t_setup, "J": info["J"],
+                   "lc": info["lc"]},
+        "mixed": {"value": n * args.steps / dt32, "ms_per_step": dt32 / args.steps * 1e3,
+                  "iterations": its32[-1], "true_rel_residual": tr32, "rel_diff_vs_fp64": diff},
+        "vcycle": vcyc,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -88,6 +88,10 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
  * re-assembles A, A_l and the coarse inverse (Section 4.1), uploads values. */
 int asmg_update_coefficient(asmg_handle h, const double *kappa);
 
+/* Switch the precision of later solves (ASMG_PREC_FP64 or ASMG_PREC_MIXED); both
+ * value copies are resident after setup, so this only changes which kernels run. */
+int asmg_set_precision(asmg_handle h, int precision);
+
 /* Number of unknowns, and the vertex id of each unknown (n int32). */
 int asmg_num_dofs(asmg_handle h, int64_t *n);
 int asmg_dof_vertex(asmg_handle h, int32_t *map);

@@ -21,7 +21,7 @@ OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
 
 EXPORTED = [
-    "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_num_dofs", "asmg_dof_vertex",
+    "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_set_precision", "asmg_num_dofs", "asmg_dof_vertex",
     "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
 ]
@@ -49,6 +49,7 @@ def _load():
     lib.asmg_default_options.argtypes = [ctypes.POINTER(Options)]
     lib.asmg_setup.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
     lib.asmg_update_coefficient.argtypes = [P, P]
+    lib.asmg_set_precision.argtypes = [P, ctypes.c_int]
     lib.asmg_num_dofs.argtypes = [P, ctypes.POINTER(I64)]
     lib.asmg_dof_vertex.argtypes = [P, P]
     lib.asmg_solve.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
@@ -139,6 +140,10 @@ class Solver:
         _check(lib.asmg_solve(self.h, _ptr(f), tol, _ptr(u), ctypes.byref(it), ctypes.byref(tr)),
                (ENOCONV,) if allow_noconv else ())
         return u, it.value, tr.value
+
+    def set_precision(self, precision):
+        _check(lib.asmg_set_precision(self.h, precision))
+        self.precision = precision
 
     def update_coefficient(self, kappa):
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "../../include/asmg.h"
@@ -112,9 +113,9 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     if (elems[i] < 0 || elems[i] >= n_vertices) return set_err(ASMG_EINVAL, "element vertex id out of range");
   for (int64_t e = 0; e < n_elements; ++e)
     if (!(kappa[e] > 0) || !std::isfinite(kappa[e])) return set_err(ASMG_EINVAL, "kappa must be finite and > 0");
-  asmg_s *H = nullptr;
   ASMG_TRY({
-    H = new asmg_s();
+    std::unique_ptr<asmg_s> HP(new asmg_s());
+    asmg_s *H = HP.get();
     Hierarchy &h = H->h;
     h.d = dim;
     h.nv = n_vertices;
@@ -131,7 +132,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     build_colourings(h);
     build_coarse(h);
     if (o.device >= 0) H->dev = device_create(h, o.device);
-    *out = H;
+    *out = HP.release();
     return ASMG_OK;
   })
 }
@@ -149,6 +150,13 @@ int asmg_update_coefficient(asmg_handle H, const double *kappa) {
     if (H->dev) device_update_values(H->dev, h);
     return ASMG_OK;
   })
+}
+
+int asmg_set_precision(asmg_handle H, int precision) {
+  if (!H || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED)) return set_err(ASMG_EINVAL, "bad argument");
+  H->h.opt.precision = precision;
+  if (H->dev) device_set_precision(H->dev, precision);
+  return ASMG_OK;
 }
 
 int asmg_num_dofs(asmg_handle H, int64_t *n) {

@@ -774,6 +774,8 @@ void device_update_values(Device *dv, Hierarchy &h) {
   HIPCHECK(hipDeviceSynchronize());
 }
 
+void device_set_precision(Device *dv, int precision) { dv->precision = precision; }
+
 void device_destroy(Device *dv) {
   if (!dv) return;
   hipSetDevice(dv->ordinal);

@@ -14,6 +14,7 @@ Device *device_create(Hierarchy &h, int ordinal);
 // Re-upload matrix values after a coefficient update (patterns unchanged).
 void device_update_values(Device *dv, Hierarchy &h);
 void device_destroy(Device *dv);
+void device_set_precision(Device *dv, int precision);
 
 int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream);
 int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, void *stream);

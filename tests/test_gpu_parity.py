@@ -1,0 +1,136 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (stated per test): same PCG iteration count and ||u_gpu - u_oracle|| <=
+1e-10 ||u_oracle|| in FP64 (same algorithm, same ordering; only the summation
+order inside a row or a dot product differs); mixed precision within 1e-6 of
+the oracle solved to 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.hierarchy import Hierarchy
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+A = pytest.importorskip("paper_1410_2153_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _graded_cube():
+    coords, elems, _ = W.kuhn_cube_mesh(8, 0.1, cfg=2, item=3)
+    c = dict(coords=coords ** 2, elems=elems, kappa=np.random.default_rng(0).uniform(0.5, 2, len(elems)))
+    c["f_vertex"] = W.rhs_per_vertex(len(coords), 2, 3)
+    return c, 3
+
+
+CASES = {
+    "square64": lambda: (W.make_config(0), 0),
+    "graded20k": lambda: (W.make_config(1, scale=0.01), 0),
+    "cube16": lambda: (W.make_config(2, scale=1 / 8), 0),
+    "graded_cube": _graded_cube,
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    _say(f"[gpu parity] case {request.param}")
+    c, n_min = CASES[request.param]()
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min)
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min)
+    S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED)
+    f = c["f_vertex"][H.dofs]
+    return request.param, c, H, S64, S32, f
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_matvec(case):
+    name, c, H, S64, S32, f = case
+    x = np.random.default_rng(1).standard_normal(H.n)
+    y = S64.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, H.A @ x) <= 1e-14
+
+
+def test_preconditioner_fp64(case):
+    name, c, H, S64, S32, f = case
+    r = np.random.default_rng(2).standard_normal(H.n)
+    z = S64.apply_preconditioner(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = H.preconditioner()(r)
+    _say(name, "B_co fp64 rel diff", _rel(z, zo))
+    assert _rel(z, zo) <= 1e-12
+
+
+def test_preconditioner_mixed(case):
+    name, c, H, S64, S32, f = case
+    r = np.random.default_rng(3).standard_normal(H.n)
+    z = S32.apply_preconditioner(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = H.preconditioner()(r)
+    _say(name, "B_co fp32 vs fp64 oracle rel diff", _rel(z, zo))
+    assert _rel(z, zo) <= 1e-5
+
+
+def test_preconditioner_symmetric(case):
+    name, c, H, S64, S32, f = case
+    g = np.random.default_rng(4)
+    x, y = g.standard_normal(H.n), g.standard_normal(H.n)
+    Bx = S64.apply_preconditioner(torch.from_numpy(x).cuda()).cpu().numpy()
+    By = S64.apply_preconditioner(torch.from_numpy(y).cuda()).cpu().numpy()
+    assert abs(Bx @ y - x @ By) <= 1e-12 * abs(Bx @ y)
+    assert Bx @ x > 0
+
+
+def test_solve_fp64(case):
+    name, c, H, S64, S32, f = case
+    uo, ito, info = H.solve(f, 1e-8, record=True)
+    u, it, tr = S64.solve(f, 1e-8)
+    _say(name, "iters gpu", it, "oracle", ito, "rel diff", _rel(u, uo), "true res", tr)
+    hist = info["history"]
+    near = any(abs(h - 1e-8) < 1e-3 * 1e-8 for h in hist[-2:])
+    assert it == ito or near
+    assert tr <= 1e-8 * (1 + 1e-6)
+    assert _rel(u, uo) <= 1e-10
+
+
+def test_solve_device_matches_host_and_is_deterministic(case):
+    name, c, H, S64, S32, f = case
+    u1, it1, _ = S64.solve(f, 1e-8)
+    fd = torch.from_numpy(f).cuda()
+    u2, it2, _ = S64.solve_device(fd, 1e-8)
+    u3, it3, _ = S64.solve_device(fd, 1e-8)
+    assert it1 == it2 == it3
+    assert np.array_equal(u1, u2.cpu().numpy())
+    assert torch.equal(u2, u3)
+
+
+def test_solve_mixed(case):
+    name, c, H, S64, S32, f = case
+    ref, _, _ = H.solve(f, 1e-12)
+    u, it, tr = S32.solve(f, 1e-8)
+    u64, it64, _ = S64.solve(f, 1e-8)
+    err = _rel(u, ref)
+    _say(name, "mixed iters", it, "fp64 iters", it64, "err vs 1e-12 oracle", err, "fp64 err", _rel(u64, ref))
+    assert tr <= 1e-8
+    assert err <= 1e-6
+
+
+def test_zero_rhs_and_max_iter(case):
+    name, c, H, S64, S32, f = case
+    u, it, tr = S64.solve(np.zeros(H.n), 1e-8)
+    assert it == 0 and np.all(u == 0)
+    S1 = A.Solver(c["coords"], c["elems"], c["kappa"], max_iter=2,
+                  n_min=3 if name == "graded_cube" else 0)
+    with pytest.raises(A.AsmgError) as e:
+        S1.solve(f, 1e-14)
+    assert e.value.code == A.ENOCONV
+    u, it, tr = S1.solve(f, 1e-14, allow_noconv=True)
+    assert it == 2
