@@ -517,6 +517,13 @@ struct Device {
   double *coords = nullptr, *kappa = nullptr;
   int *elems = nullptr, *dof_of_vertex = nullptr;
   int64_t ne = 0, nv = 0;
+  // execution: an internal stream carries the PCG loop (joined to the caller's stream with
+  // events); one PCG iteration is captured per precision as a HIP graph
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int last_iters[2] = {0, 0};
+  bool use_graph = true;
   // byte model accumulation
   bool count_bytes = false;
   double bytes = 0.0;
@@ -744,6 +751,9 @@ Device *device_create(Hierarchy &h, int ordinal) {
     dv->ctl = dalloc<Ctl>(dv, 1);
     HIPCHECK(hipMemset(dv->ctl, 0, sizeof(Ctl)));
     HIPCHECK(hipHostMalloc((void **)&dv->ctl_host, sizeof(Ctl), hipHostMallocDefault));
+    HIPCHECK(hipStreamCreateWithFlags(&dv->stream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&dv->ev_in, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&dv->ev_out, hipEventDisableTiming));
     dv->zero_flag = dalloc<int>(dv, 1);
     HIPCHECK(hipMemset(dv->zero_flag, 0, sizeof(int)));
     dv->max_blocks = std::max(1, (int)(((int64_t)n * 16 + BS - 1) / BS));
@@ -778,9 +788,15 @@ void device_set_precision(Device *dv, int precision) { dv->precision = precision
 
 void device_destroy(Device *dv) {
   if (!dv) return;
-  hipSetDevice(dv->ordinal);
-  for (void *p : dv->allocs) hipFree(p);
-  if (dv->ctl_host) hipHostFree(dv->ctl_host);
+  (void)hipSetDevice(dv->ordinal);
+  if (dv->stream) (void)hipStreamSynchronize(dv->stream);
+  for (int k = 0; k < 2; ++k)
+    if (dv->graph[k]) (void)hipGraphExecDestroy(dv->graph[k]);
+  if (dv->ev_in) (void)hipEventDestroy(dv->ev_in);
+  if (dv->ev_out) (void)hipEventDestroy(dv->ev_out);
+  if (dv->stream) (void)hipStreamDestroy(dv->stream);
+  for (void *p : dv->allocs) (void)hipFree(p);
+  if (dv->ctl_host) (void)hipHostFree(dv->ctl_host);
   delete dv;
 }
 
@@ -1020,18 +1036,44 @@ static void read_ctl(Device *dv, hipStream_t s) {
 }
 
 template <class T>
+static void launch_iterations(Device *dv, int k, hipStream_t s) {
+  const int pi = sizeof(T) == 4 ? 1 : 0;
+  if (dv->use_graph && !dv->graph[pi]) {
+    hipGraph_t g;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pcg_iteration<T>(dv, s);
+    HIPCHECK(hipStreamEndCapture(s, &g));
+    HIPCHECK(hipGraphInstantiate(&dv->graph[pi], g, nullptr, nullptr, 0));
+    HIPCHECK(hipGraphDestroy(g));
+  }
+  for (int i = 0; i < k; ++i) {
+    if (dv->use_graph)
+      HIPCHECK(hipGraphLaunch(dv->graph[pi], s));
+    else
+      pcg_iteration<T>(dv, s);
+  }
+}
+
+template <class T>
 static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t s) {
   const int n = dv->fine.n;
+  const int pi = sizeof(T) == 4 ? 1 : 0;
   DLevel &F = dv->fine;
   hipLaunchKernelGGL(k_cg_init, dim3(nblk(n)), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, tol, dv->maxit, dv->ctl,
                      dv->partials);
   pcg_tail<T>(dv, s);
-  int K = dv->check_every > 0 ? dv->check_every : 4;
+  // host checks of the device flag: first after (previous count - 1) iterations, then every
+  // iteration; with no history, every `check_every` (default 4) iterations
+  int first = dv->last_iters[pi] > 1 ? dv->last_iters[pi] - 1 : 0;
+  const int K = dv->check_every > 0 ? dv->check_every : (dv->last_iters[pi] > 0 ? 1 : 4);
   int restarts = 0;
+  if (first > 0) {
+    launch_iterations<T>(dv, std::min(first, dv->maxit), s);
+  }
   while (true) {
     read_ctl(dv, s);
     if (!dv->ctl_host->done) {
-      for (int k = 0; k < K; ++k) pcg_iteration<T>(dv, s);
+      launch_iterations<T>(dv, K, s);
       continue;
     }
     // converged, broke down or hit max_iter: true residual in FP64
@@ -1045,8 +1087,8 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
     const double rel = c.fnorm2 > 0 ? std::sqrt(c.tr / c.fnorm2) : 0.0;
     if (c.status == ST_OK && sizeof(T) == 4 && rel > tol && restarts < 3 && c.iter < dv->maxit) {
       ++restarts;
-      with_lpr(F.A.lpr, [&](auto c) {
-        constexpr int LP = decltype(c)::value;
+      with_lpr(F.A.lpr, [&](auto cc) {
+        constexpr int LP = decltype(cc)::value;
         hipLaunchKernelGGL((k_cg_restart<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci,
                            F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->ctl);
       });
@@ -1055,6 +1097,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
     }
     if (iters) *iters = c.iter;
     if (true_rel) *true_rel = rel;
+    if (c.status == ST_OK) dv->last_iters[pi] = c.iter;
     switch (c.status) {
       case ST_OK: return ASMG_OK;
       case ST_NOTSPD: return ASMG_ENOTSPD;
@@ -1066,18 +1109,23 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
 
 int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream) {
   HIPCHECK(hipSetDevice(dv->ordinal));
-  hipStream_t s = (hipStream_t)stream;
+  hipStream_t cs = (hipStream_t)stream;
+  hipStream_t s = dv->stream;
   const int n = dv->fine.n;
   if (n == 0) {
     if (iters) *iters = 0;
     if (true_rel) *true_rel = 0;
     return ASMG_OK;
   }
+  HIPCHECK(hipEventRecord(dv->ev_in, cs));
+  HIPCHECK(hipStreamWaitEvent(s, dv->ev_in, 0));
   hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_f, dv->f);
   const int rc = dv->precision == ASMG_PREC_MIXED ? pcg<float>(dv, tol, iters, true_rel, s)
                                                    : pcg<double>(dv, tol, iters, true_rel, s);
   hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, dv->u, d_u);
   HIPCHECK(hipGetLastError());
+  HIPCHECK(hipEventRecord(dv->ev_out, s));
+  HIPCHECK(hipStreamWaitEvent(cs, dv->ev_out, 0));
   HIPCHECK(hipStreamSynchronize(s));
   return rc;
 }
