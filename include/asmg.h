@@ -164,6 +164,43 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  */
 int asmg_export(asmg_handle h, const char *name, int level, void *buf, int64_t *count);
 
+/*
+ * Batched setup: n_meshes independent meshes of one dimension, concatenated.
+ * Mesh m has vertices [vert_off[m], vert_off[m+1]) of `coords` (dim doubles each)
+ * and elements [elem_off[m], elem_off[m+1]) of `elems` ((dim+1) int32 each, vertex
+ * ids local to the mesh) and of `kappa`. Dirichlet vertices: the bounding-box
+ * boundary of each mesh. Every mesh gets its own hierarchy (Sections 3-4); the
+ * meshes are set up on parallel host threads. The device copy merges all meshes
+ * level by level (level k = k-th auxiliary level below each mesh's finest).
+ * Single-mesh entry points return ASMG_EINVAL on a batch handle; asmg_num_dofs
+ * returns the total number of unknowns. Exports: "batch_n", "batch_J",
+ * "batch_lc" (int64 per mesh).
+ */
+int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const double *coords,
+                     const int64_t *elem_off, const int32_t *elems, const double *kappa,
+                     const asmg_options *opt, asmg_handle *out);
+
+/*
+ * Batched PCG: every (mesh, right-hand side) system runs the same algorithm as
+ * asmg_solve_device, all systems advancing in one launch sequence per step.
+ * Each system has its own CG scalars and stops on its own ||r|| <= tol ||f||.
+ *   n_rhs        1, 2 or 4
+ *   d_F, d_U     device arrays laid out [mesh][rhs][unknown]: mesh m starts at
+ *                n_rhs * (n_0 + ... + n_{m-1}), right-hand side r of mesh m at
+ *                that offset + r * n_m
+ *   iterations   n_meshes * n_rhs ints (mesh-major), may be NULL
+ *   true_rel_residual  n_meshes * n_rhs doubles, may be NULL
+ * Returns the first failure status over the systems (ASMG_ENOTSPD, ASMG_ENAN,
+ * ASMG_ENOCONV) or 0.
+ */
+int asmg_solve_batch_device(asmg_handle h, int n_rhs, const double *d_F, double tol, double *d_U,
+                            int *iterations, double *true_rel_residual, void *stream);
+
+/* One batched B_co application timed with HIP events over `reps` launches on
+ * `stream` (mean ms) and its algorithmic bytes. */
+int asmg_time_batch(asmg_handle h, int n_rhs, int reps, int precision, void *stream, double *ms,
+                    double *bytes);
+
 /* Free the handle and all its device memory. NULL is ignored. */
 void asmg_destroy(asmg_handle h);
 

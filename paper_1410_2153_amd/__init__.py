@@ -24,6 +24,7 @@ EXPORTED = [
     "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_set_precision", "asmg_num_dofs", "asmg_dof_vertex",
     "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
+    "asmg_setup_batch", "asmg_solve_batch_device", "asmg_time_batch",
 ]
 
 
@@ -61,6 +62,11 @@ def _load():
     lib.asmg_time_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.asmg_export.argtypes = [P, ctypes.c_char_p, ctypes.c_int, P, ctypes.POINTER(I64)]
+    lib.asmg_setup_batch.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.POINTER(Options),
+                                     ctypes.POINTER(P)]
+    lib.asmg_solve_batch_device.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P, P, P, P]
+    lib.asmg_time_batch.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.asmg_destroy.argtypes = [P]
     lib.asmg_destroy.restype = None
     return lib
@@ -214,6 +220,71 @@ class Solver:
         if shape is None:
             shape = (n, int(ci.max()) + 1 if len(ci) else 0)
         return sp.csr_matrix((v, ci, rp), shape=shape)
+
+
+class BatchSolver:
+    """Many meshes, solved together (asmg_setup_batch / asmg_solve_batch_device).
+
+    ``meshes`` is a list of (coords, elems, kappa). Right-hand sides and solutions
+    are device tensors laid out [mesh][rhs][unknown] (see ``offsets``).
+    """
+
+    def __init__(self, meshes, *, device=0, precision=PREC_FP64, n_min=0, nu_aux=2, nu_fine=1,
+                 coarse_max_dofs=1024, max_iter=1000):
+        dim = np.asarray(meshes[0][0]).shape[1]
+        coords = np.ascontiguousarray(np.concatenate([np.asarray(m[0], dtype=np.float64) for m in meshes]))
+        elems = np.ascontiguousarray(np.concatenate([np.asarray(m[1], dtype=np.int32) for m in meshes]))
+        kappa = np.ascontiguousarray(np.concatenate([np.asarray(m[2], dtype=np.float64) for m in meshes]))
+        vo = np.zeros(len(meshes) + 1, dtype=np.int64)
+        eo = np.zeros(len(meshes) + 1, dtype=np.int64)
+        vo[1:] = np.cumsum([len(m[0]) for m in meshes])
+        eo[1:] = np.cumsum([len(m[1]) for m in meshes])
+        opt = Options()
+        lib.asmg_default_options(ctypes.byref(opt))
+        opt.n_min, opt.nu_aux, opt.nu_fine = n_min, nu_aux, nu_fine
+        opt.coarse_max_dofs, opt.max_iter, opt.precision, opt.device = coarse_max_dofs, max_iter, precision, device
+        h = ctypes.c_void_p()
+        _check(lib.asmg_setup_batch(len(meshes), dim, _ptr(vo), _ptr(coords), _ptr(eo), _ptr(elems), _ptr(kappa),
+                                    ctypes.byref(opt), ctypes.byref(h)))
+        self.h = h
+        self.n_meshes = len(meshes)
+        cnt = ctypes.c_int64(self.n_meshes)
+        self.n_per_mesh = np.empty(self.n_meshes, dtype=np.int64)
+        _check(lib.asmg_export(self.h, b"batch_n", 0, _ptr(self.n_per_mesh), ctypes.byref(cnt)))
+        self.n_total = int(self.n_per_mesh.sum())
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.asmg_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def offsets(self, n_rhs):
+        o = np.zeros(self.n_meshes + 1, dtype=np.int64)
+        o[1:] = np.cumsum(self.n_per_mesh * n_rhs)
+        return o
+
+    def set_precision(self, precision):
+        _check(lib.asmg_set_precision(self.h, precision))
+        self.precision = precision
+
+    def solve(self, F, n_rhs, tol=1e-8, out=None):
+        import torch
+        assert F.is_cuda and F.dtype == torch.float64 and F.is_contiguous() and F.numel() == self.n_total * n_rhs
+        U = torch.empty_like(F) if out is None else out
+        it = np.zeros(self.n_meshes * n_rhs, dtype=np.int32)
+        tr = np.zeros(self.n_meshes * n_rhs)
+        _check(lib.asmg_solve_batch_device(self.h, n_rhs, _tptr(F), tol, _tptr(U), _ptr(it), _ptr(tr), _stream()))
+        return U, it.reshape(self.n_meshes, n_rhs), tr.reshape(self.n_meshes, n_rhs)
+
+    def time_preconditioner(self, n_rhs, reps=10, precision=None):
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        prec = self.precision if precision is None else precision
+        _check(lib.asmg_time_batch(self.h, n_rhs, reps, prec, _stream(), ctypes.byref(ms), ctypes.byref(by)))
+        return ms.value, by.value
 
 
 class LogCoefficientSolve:

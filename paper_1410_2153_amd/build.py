@@ -34,11 +34,12 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    obj = os.path.join(OUT_DIR, "device.o")
-    _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", os.path.join(CSRC, "device.hip"), "-o", obj])
-    objs.append(obj)
+    for src in ("device.hip", "batch.hip"):
+        obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
+        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

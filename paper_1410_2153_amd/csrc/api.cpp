@@ -4,16 +4,23 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
+#include <atomic>
+#include <mutex>
 
 #include "../../include/asmg.h"
+#include "batch.hpp"
 #include "device.hpp"
 #include "setup.hpp"
 
 using namespace asmg;
 
 struct asmg_s {
-  Hierarchy h;
+  Hierarchy h;                                     // single-mesh handle
   Device *dev = nullptr;
+  std::vector<std::unique_ptr<Hierarchy>> batch;   // batch handle: one hierarchy per mesh
+  BatchDevice *bdev = nullptr;
+  bool is_batch() const { return !batch.empty(); }
 };
 
 static thread_local std::string g_err;
@@ -156,11 +163,18 @@ int asmg_set_precision(asmg_handle H, int precision) {
   if (!H || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED)) return set_err(ASMG_EINVAL, "bad argument");
   H->h.opt.precision = precision;
   if (H->dev) device_set_precision(H->dev, precision);
+  if (H->bdev) batch_device_set_precision(H->bdev, precision);
   return ASMG_OK;
 }
 
 int asmg_num_dofs(asmg_handle H, int64_t *n) {
   if (!H || !n) return set_err(ASMG_EINVAL, "null argument");
+  if (H->is_batch()) {
+    int64_t t = 0;
+    for (auto &hp : H->batch) t += hp->n();
+    *n = t;
+    return ASMG_OK;
+  }
   *n = H->h.n();
   return ASMG_OK;
 }
@@ -173,6 +187,7 @@ int asmg_dof_vertex(asmg_handle H, int32_t *map) {
 
 static int need_dev(asmg_handle H) {
   if (!H) return set_err(ASMG_EINVAL, "null handle");
+  if (H->is_batch()) return set_err(ASMG_EINVAL, "batch handle: use the batch entry points");
   if (!H->dev) return set_err(ASMG_EDEVICE, "host-only handle (options.device = -1)");
   return ASMG_OK;
 }
@@ -225,9 +240,105 @@ int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *st
   ASMG_TRY({ return device_time_kernel(H->dev, which, reps, precision, stream, ms, bytes); })
 }
 
+
+static int check_options(const asmg_options &o) {
+  if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
+      (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0)
+    return set_err(ASMG_EINVAL, "invalid options");
+  return ASMG_OK;
+}
+
+int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const double *coords, const int64_t *elem_off,
+                     const int32_t *elems, const double *kappa, const asmg_options *opt, asmg_handle *out) {
+  if (!out) return set_err(ASMG_EINVAL, "null output handle");
+  *out = nullptr;
+  if (n_meshes < 1 || (dim != 2 && dim != 3) || !vert_off || !coords || !elem_off || !elems || !kappa)
+    return set_err(ASMG_EINVAL, "bad batch arguments");
+  asmg_options o;
+  asmg_default_options(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(o)) return rc;
+  for (int m = 0; m < n_meshes; ++m) {
+    const int64_t nv = vert_off[m + 1] - vert_off[m], ne = elem_off[m + 1] - elem_off[m];
+    if (nv <= 0 || ne <= 0) return set_err(ASMG_EINVAL, "empty mesh in batch");
+    for (int64_t i = vert_off[m] * dim; i < vert_off[m + 1] * dim; ++i)
+      if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
+    for (int64_t i = elem_off[m] * (dim + 1); i < elem_off[m + 1] * (dim + 1); ++i)
+      if (elems[i] < 0 || elems[i] >= nv) return set_err(ASMG_EINVAL, "element vertex id out of range");
+    for (int64_t e = elem_off[m]; e < elem_off[m + 1]; ++e)
+      if (!(kappa[e] > 0) || !std::isfinite(kappa[e])) return set_err(ASMG_EINVAL, "kappa must be finite and > 0");
+  }
+  ASMG_TRY({
+    std::unique_ptr<asmg_s> HP(new asmg_s());
+    HP->batch.resize(n_meshes);
+    std::atomic<int> next{0};
+    std::vector<AsmgError> errs;
+    std::mutex mu;
+    auto work = [&]() {
+      while (true) {
+        const int m = next.fetch_add(1);
+        if (m >= n_meshes) return;
+        try {
+          auto h = std::make_unique<Hierarchy>();
+          h->d = dim;
+          h->nv = vert_off[m + 1] - vert_off[m];
+          h->ne = elem_off[m + 1] - elem_off[m];
+          h->opt = o;
+          h->coords.assign(coords + vert_off[m] * dim, coords + vert_off[m + 1] * dim);
+          h->elems.assign(elems + elem_off[m] * (dim + 1), elems + elem_off[m + 1] * (dim + 1));
+          h->kappa.assign(kappa + elem_off[m], kappa + elem_off[m + 1]);
+          build_fine(*h);
+          build_tree(*h);
+          build_levels(*h);
+          build_transfer(*h);
+          build_colourings(*h);
+          build_coarse(*h);
+          HP->batch[m] = std::move(h);
+        } catch (const AsmgError &e) {
+          std::lock_guard<std::mutex> g(mu);
+          errs.push_back(AsmgError{e.code, "mesh " + std::to_string(m) + ": " + e.msg});
+        } catch (const std::bad_alloc &) {
+          std::lock_guard<std::mutex> g(mu);
+          errs.push_back(AsmgError{ASMG_ENOMEM, "host allocation failed"});
+        }
+      }
+    };
+    const int nt = std::max(1, std::min<int>(n_meshes, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(work);
+    for (auto &t : th) t.join();
+    if (!errs.empty()) throw errs.front();
+    HP->h.d = dim;
+    HP->h.opt = o;
+    if (o.device >= 0) HP->bdev = batch_device_create(HP->batch, o.device);
+    *out = HP.release();
+    return ASMG_OK;
+  })
+}
+
+int asmg_solve_batch_device(asmg_handle H, int n_rhs, const double *d_F, double tol, double *d_U, int *iterations,
+                            double *true_rel, void *stream) {
+  if (!H || !H->is_batch()) return set_err(ASMG_EINVAL, "not a batch handle");
+  if (!H->bdev) return set_err(ASMG_EDEVICE, "host-only handle (options.device = -1)");
+  if (!d_F || !d_U || (n_rhs != 1 && n_rhs != 2 && n_rhs != 4)) return set_err(ASMG_EINVAL, "bad argument");
+  if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
+  ASMG_TRY({
+    int rc = batch_device_solve(H->bdev, n_rhs, d_F, tol, d_U, iterations, true_rel, stream);
+    if (rc) set_err(rc, "a system did not converge or broke down");
+    return rc;
+  })
+}
+
+int asmg_time_batch(asmg_handle H, int n_rhs, int reps, int precision, void *stream, double *ms, double *bytes) {
+  if (!H || !H->is_batch() || !H->bdev) return set_err(ASMG_EINVAL, "not a device batch handle");
+  if ((n_rhs != 1 && n_rhs != 2 && n_rhs != 4) || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
+  ASMG_TRY({ return batch_device_time(H->bdev, n_rhs, reps, precision, stream, ms, bytes); })
+}
+
 void asmg_destroy(asmg_handle H) {
   if (!H) return;
   if (H->dev) device_destroy(H->dev);
+  if (H->bdev) batch_device_destroy(H->bdev);
   delete H;
 }
 
@@ -236,6 +347,14 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
   Hierarchy &h = H->h;
   const std::string name(name_c);
   ASMG_TRY({
+    if (H->is_batch()) {
+      if (name == "batch_n" || name == "batch_J" || name == "batch_lc") {
+        std::vector<int64_t> v;
+        for (auto &hp : H->batch) v.push_back(name == "batch_n" ? hp->n() : name == "batch_J" ? hp->J : hp->lc);
+        return put(v, buf, count);
+      }
+      return set_err(ASMG_EINVAL, "batch handle exports: batch_n, batch_J, batch_lc");
+    }
     if (name == "info") {
       std::vector<int64_t> v(16, 0);
       v[0] = h.d;

@@ -1,0 +1,22 @@
+// Batched engine (batch.hip): many meshes x up to 4 right-hand sides per launch sequence.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "setup.hpp"
+
+namespace asmg {
+
+struct BatchDevice;
+
+BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int ordinal);
+void batch_device_destroy(BatchDevice *dv);
+void batch_device_set_precision(BatchDevice *dv, int precision);
+int batch_device_solve(BatchDevice *dv, int n_rhs, const double *d_F, double tol, double *d_U, int *iters,
+                       double *true_rel, void *stream);
+int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void *stream, double *ms, double *bytes);
+int64_t batch_n_total(BatchDevice *dv);
+
+}  // namespace asmg

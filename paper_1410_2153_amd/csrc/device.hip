@@ -27,17 +27,10 @@
 #include <type_traits>
 #include <vector>
 
+#include "common.hpp"
 #include "device.hpp"
 
 namespace asmg {
-
-#define HIPCHECK(x)                                                                                    \
-  do {                                                                                                 \
-    hipError_t e_ = (x);                                                                               \
-    if (e_ != hipSuccess) throw AsmgError{ASMG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
-  } while (0)
-
-static constexpr int BS = 256;
 
 // ---------------------------------------------------------------------------
 // device control block for PCG
@@ -50,70 +43,6 @@ struct Ctl {
 };
 
 enum { ST_OK = 0, ST_NOTSPD = 1, ST_NAN = 2, ST_NOCONV = 3 };
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-
-template <int W, class T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
-}
-
-// sum over a 256-thread block; result valid in thread 0
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sm[BS / 64];
-  v = group_sum<64>(v);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sm[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < BS / 64; ++i) r += sm[i];
-  }
-  return r;
-}
-
-// Store this block's partial; return true in every thread of the last block to
-// finish. The last block then reads all partials (agent-scope acquire).
-__device__ __forceinline__ bool publish_partial(double v, double *partials, unsigned *ticket) {
-  __shared__ bool last;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  return last;
-}
-
-// deterministic sum of nb partials by one block; valid in thread 0
-__device__ __forceinline__ double reduce_partials(const double *partials, int nb) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += BS)
-    s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return block_sum(s);
-}
-
-// ---------------------------------------------------------------------------
-// sparse kernels
-// ---------------------------------------------------------------------------
-
-template <int LPR, class T>
-__device__ __forceinline__ T row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
-                                     const T *__restrict__ av, const T *__restrict__ x, int row, bool act,
-                                     int lane) {
-  T s = 0;
-  if (act) {
-    const int b = rp[row], e = rp[row + 1];
-    for (int k = b + lane; k < e; k += LPR) s += av[k] * x[ci[k]];
-  }
-  return group_sum<LPR>(s);
-}
 
 // one Gauss-Seidel colour pass: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii for rows [r0, r1)
 template <int LPR, class T>
@@ -546,14 +475,6 @@ static T *dupload(Device *dv, const std::vector<T> &v) {
   return p;
 }
 
-static int pick_lpr(int64_t nnz, int64_t rows) {
-  if (rows <= 0) return 4;
-  const double avg = (double)nnz / (double)rows;
-  if (avg <= 2.0) return 2;
-  if (avg <= 4.0) return 4;
-  if (avg <= 8.0) return 8;
-  return 16;
-}
 
 // host CSR triple in an internal numbering
 struct HCsr {
@@ -804,7 +725,6 @@ void device_destroy(Device *dv) {
 // launch helpers
 // ---------------------------------------------------------------------------
 
-static inline int nblk(int64_t threads) { return (int)std::max<int64_t>(1, (threads + BS - 1) / BS); }
 
 static inline double csr_bytes(const DCsr &A, int vbytes) {
   return (double)A.nnz * (vbytes + 4) + 4.0 * (A.nrows + 1);
@@ -842,15 +762,6 @@ struct LV<float> {
   static const float *id(DLevel &L) { return L.id32; }
 };
 
-template <class F>
-static void with_lpr(int lpr, F &&f) {
-  switch (lpr) {
-    case 2: f(std::integral_constant<int, 2>()); break;
-    case 4: f(std::integral_constant<int, 4>()); break;
-    case 8: f(std::integral_constant<int, 8>()); break;
-    default: f(std::integral_constant<int, 16>()); break;
-  }
-}
 
 template <int LPR, class T>
 static void launch_gs(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
