@@ -58,9 +58,11 @@ typedef struct {
   int coarse_max_dofs; /* the V-cycle bottom is the finest level with at most this many unknowns (1024) */
   int max_iter;        /* PCG iteration cap (1000) */
   int precision;       /* ASMG_PREC_FP64 or ASMG_PREC_MIXED */
-  uint32_t colour_seed;/* seed of the multicolour ordering (0) */
+  uint32_t colour_seed;/* seed of the hash colour order (colouring = 1) */
   int device;          /* HIP device ordinal; -1 = host-only handle (setup and exports, no solve) */
   int check_every;     /* PCG iterations between host reads of the device convergence flag (0 = auto) */
+  int colouring;       /* Gauss-Seidel colour order: 0 = greedy in unknown order (default),
+                          1 = greedy in descending (fmix32(i ^ colour_seed), i) (Jones-Plassmann order) */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */

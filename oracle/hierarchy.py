@@ -14,7 +14,7 @@ from . import asmg, auxgrid, auxops, cluster, colour, fem, pcg, transfer
 
 class Hierarchy:
     def __init__(self, coords, elems, kappa, dirichlet=None, n_min=None, coarse_max_dofs=1024,
-                 colour_seed=0, check_literal=False):
+                 colour_seed=0, check_literal=False, colouring="natural"):
         coords = np.asarray(coords, dtype=np.float64)
         elems = np.asarray(elems, dtype=np.int64)
         self.coords = coords
@@ -26,8 +26,8 @@ class Hierarchy:
         self.meshes = auxgrid.AuxMeshes(self.tree)
         self.aux = auxops.AuxOperators(self.tree, self.meshes, self.kappa, coarse_max_dofs)
         self.Pi = transfer.transfer(self.tree, self.meshes, coords, elems, self.dofs)
-        self.colour_fine = colour.greedy_colouring(self.A, colour_seed)
-        self.colour_aux = {l: colour.greedy_colouring(self.aux.A[l], colour_seed)
+        self.colour_fine = colour.greedy_colouring(self.A, colour_seed, colouring)
+        self.colour_aux = {l: colour.greedy_colouring(self.aux.A[l], colour_seed, colouring)
                            for l in range(self.aux.lc + 1, self.aux.J + 1)}
         self._B = {}
 

@@ -37,7 +37,8 @@ class AsmgError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("n_min", ctypes.c_int), ("nu_aux", ctypes.c_int), ("nu_fine", ctypes.c_int),
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
-                ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("colouring", ctypes.c_int)]
 
 
 def _load():
@@ -98,7 +99,8 @@ class Solver:
     """One mesh: ``asmg_setup`` on construction, ``asmg_destroy`` on close/garbage collection."""
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
-                 nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0):
+                 nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
+                 colouring=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -110,6 +112,7 @@ class Solver:
         opt.n_min, opt.nu_aux, opt.nu_fine = n_min, nu_aux, nu_fine
         opt.coarse_max_dofs, opt.max_iter, opt.precision = coarse_max_dofs, max_iter, precision
         opt.colour_seed, opt.device, opt.check_every = colour_seed, device, check_every
+        opt.colouring = colouring
         self.precision = precision
         self.device = device
         dptr = None

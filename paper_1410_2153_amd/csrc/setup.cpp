@@ -1096,15 +1096,18 @@ static inline uint32_t fmix32(uint32_t x) {
   return x;
 }
 
-static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed) {
+// greedy colouring: ascending index (mode 0) or descending (fmix32(i ^ seed), i) (mode 1)
+static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed, int mode) {
   const int64_t n = A.nrows;
   std::vector<int64_t> order(n);
   std::iota(order.begin(), order.end(), 0);
-  std::vector<uint32_t> w(n);
-  for (int64_t i = 0; i < n; ++i) w[i] = fmix32((uint32_t)i ^ seed);
-  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-    return w[x] > w[y] || (w[x] == w[y] && x > y);
-  });
+  if (mode == 1) {
+    std::vector<uint32_t> w(n);
+    for (int64_t i = 0; i < n; ++i) w[i] = fmix32((uint32_t)i ^ seed);
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+      return w[x] > w[y] || (w[x] == w[y] && x > y);
+    });
+  }
   std::vector<int32_t> col(n, -1);
   std::vector<int64_t> mark(64, -1);
   for (int64_t i : order) {
@@ -1123,9 +1126,10 @@ static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed) {
 }
 
 void build_colourings(Hierarchy &h) {
-  h.colour_fine = greedy_colouring(h.A, h.opt.colour_seed);
+  h.colour_fine = greedy_colouring(h.A, h.opt.colour_seed, h.opt.colouring);
   h.colour_aux.clear();
-  for (int l = h.lc + 1; l <= h.J; ++l) h.colour_aux[l] = greedy_colouring(h.Al.at(l), h.opt.colour_seed);
+  for (int l = h.lc + 1; l <= h.J; ++l)
+    h.colour_aux[l] = greedy_colouring(h.Al.at(l), h.opt.colour_seed, h.opt.colouring);
 }
 
 // ---------------------------------------------------------------------------

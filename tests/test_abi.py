@@ -69,3 +69,17 @@ def test_update_coefficient_host_only():
     assert abs(got - ref).max() <= 1e-13 * abs(ref).max()
     with pytest.raises(A.AsmgError):
         S.update_coefficient(np.zeros(len(elems)))
+
+
+def test_batch_setup_host_only():
+    meshes = W.batched_config(n_meshes=5, side_lo=4, side_hi=20, n_rhs=1, item=3)
+    B = A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes], device=-1)
+    for m, nm in zip(meshes, B.n_per_mesh):
+        S = A.Solver(m["coords"], m["elems"], m["kappa"], device=-1)
+        assert S.n == nm
+    with pytest.raises(A.AsmgError) as e:
+        A.lib.asmg_solve(B.h, None, 1e-8, None, None, None)
+        A._check(A.lib.asmg_solve(B.h, None, 1e-8, None, None, None))
+    bad = [(m["coords"], m["elems"], -m["kappa"]) for m in meshes]
+    with pytest.raises(A.AsmgError):
+        A.BatchSolver(bad, device=-1)

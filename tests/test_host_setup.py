@@ -86,3 +86,12 @@ def test_level_sizes(pair):
     c, S, H = pair
     n = S.export("level_n")
     assert list(n) == [H.meshes.level(l).n for l in range(1, H.tree.J + 1)]
+
+
+def test_hash_colouring_mode_matches():
+    c = W.make_config(1, scale=0.003)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, colouring=1, colour_seed=12345)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], colour_seed=12345, colouring="hash")
+    assert np.array_equal(S.export("colour_fine"), H.colour_fine)
+    for l, col in H.colour_aux.items():
+        assert np.array_equal(S.export("colour_aux", l), col)

@@ -26,6 +26,8 @@ def test_colouring_proper_and_deterministic(cfg0_hier):
         off = A.row != A.col
         assert np.all(col[A.row[off]] != col[A.col[off]])
         assert np.array_equal(col, colour.greedy_colouring(A, 0))
+        hc = colour.greedy_colouring(A, 7, "hash")
+        assert np.all(hc[A.row[off]] != hc[A.col[off]])
 
 
 def _perm_parts(A, col):
@@ -34,6 +36,16 @@ def _perm_parts(A, col):
     D = sp.diags(Ap.diagonal())
     Lo = -sp.tril(Ap, -1)
     return order, Ap, D, Lo
+
+
+def test_natural_order_checkerboard_on_five_point():
+    import scipy.sparse as sp
+    n = 9
+    T = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(n, n))
+    A = sp.kron(T, sp.eye(n)) + sp.kron(sp.eye(n), T)
+    col = colour.greedy_colouring(A)
+    i, j = np.divmod(np.arange(n * n), n)
+    assert np.array_equal(col, (i + j) % 2)
 
 
 def test_multicolour_sweep_is_gauss_seidel_in_colour_order(cfg0_hier):
