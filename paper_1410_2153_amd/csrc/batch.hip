@@ -1166,7 +1166,8 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
   const int nm = dv->nm, ns = nm * NR;
   const SegTable &E = dv->fine_ew, &Sp = dv->fine_sp;
   BLevel &F = dv->fine;
-  HIPCHECK(hipMemsetAsync(dv->ctl_ints, 0, ((size_t)ns * 4 + nm + 2) * sizeof(int), s));
+  // per-system ints (4 arrays sized for 4 right-hand sides), mesh tickets, active count, done flag
+  HIPCHECK(hipMemsetAsync(dv->ctl_ints, 0, ((size_t)nm * 4 * 4 + nm + 2) * sizeof(int), s));
   hipLaunchKernelGGL((kb_cg_init<NR>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->f, dv->r, dv->u,
                      dv->p, tol, dv->ctl, dv->partials);
   int hst[2];
