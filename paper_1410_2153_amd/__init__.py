@@ -14,6 +14,11 @@ import os
 
 import numpy as np
 
+# torch first: its bundled HIP runtime then provides the `libamdhip64.so.7` this library
+# needs, so the process holds one HIP runtime (loading the library first would bring in a
+# second runtime from /opt/rocm, and torch would then see no device)
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libasmg.so")
 
