@@ -70,6 +70,65 @@ def cpu_baseline(budget_s: float = 20.0):
                        f"{reps} solves in {dt:.1f} s, 1 thread of {len(os.sched_getaffinity(0))}")
 
 
+def batched(n_meshes: int, steps: int):
+    """Batched workload: n_meshes jittered squares, sides ~ U{32..512}, 4 right-hand sides each."""
+    import torch
+
+    import paper_1410_2153_amd as A
+    import workloads as W
+    t0 = time.perf_counter()
+    ms = W.batched_config(n_meshes=n_meshes)
+    log(f"batched: generated {n_meshes} meshes in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    B = A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in ms], precision=A.PREC_FP64)
+    t_setup = time.perf_counter() - t0
+    log(f"batched: setup {t_setup:.1f} s, {B.n_total} unknowns")
+    # right-hand sides per unknown, [mesh][rhs][unknown]
+    F = []
+    for m, mesh in enumerate(ms):
+        bnd = W.boundary_vertices(mesh["coords"])
+        F.append(mesh["f_vertex"][:, ~bnd].ravel())
+    F = torch.from_numpy(np.concatenate(F)).cuda()
+    res = {"workload": f"{n_meshes} jittered square meshes, side ~ U{{32..512}}, 4 right-hand sides, "
+                       f"{B.n_total} unknowns", "unknowns": B.n_total, "setup_s": t_setup}
+    for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
+        B.set_precision(prec)
+        U, its, tr = B.solve(F, 4, 1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            U, its, tr = B.solve(F, 4, 1e-8, out=U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        res[name] = {"value": B.n_total * 4 / dt, "ms_per_step": dt * 1e3, "max_iterations": int(its.max()),
+                     "max_true_rel_residual": float(tr.max())}
+        log(f"batched {name}: {dt * 1e3:.1f} ms per batch ({B.n_total * 4 / dt:.3e} DOF-solves/s), "
+            f"iterations <= {its.max()}")
+    ms_b, by_b = B.time_preconditioner(4, reps=5, precision=A.PREC_FP64)
+    res["preconditioner_fp64_4rhs"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6}
+    del B
+    # same systems solved one at a time with the single-mesh engine, on a sample of meshes
+    sample = list(range(0, n_meshes, max(1, n_meshes // 16)))
+    tot_dofs, tot_t = 0, 0.0
+    for m in sample:
+        mesh = ms[m]
+        S = A.Solver(mesh["coords"], mesh["elems"], mesh["kappa"])
+        dofs = S.dof_vertex()
+        for r in range(4):
+            f = torch.from_numpy(np.ascontiguousarray(mesh["f_vertex"][r, dofs])).cuda()
+            S.solve_device(f, 1e-8)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.solve_device(f, 1e-8)
+            torch.cuda.synchronize()
+            tot_t += time.perf_counter() - t
+            tot_dofs += S.n
+        del S
+    res["single_solves_fp64_sample"] = {"value": tot_dofs / tot_t, "meshes": len(sample), "rhs": 4}
+    log(f"single-mesh solves (sample of {len(sample)} meshes x 4 rhs): {tot_dofs / tot_t:.3e} DOF-solves/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +136,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -119,15 +179,19 @@ def main():
     log(f"mixed: {dt32 / args.steps * 1e3:.2f} ms/solve, iters {its32}, true rel res {tr32:.2e}")
     diff = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
 
-    # dominant-kernel roofline and whole-preconditioner bandwidth (HIP events on torch's stream)
+    # dominant kernel: the Gauss-Seidel colour pass (8 lanes per row, FP64), every launch inside
+    # full B_co applications bracketed by HIP events on torch's stream
+    ms_gs, by_gs = S64.time_kernel(4, reps=10, precision=A.PREC_FP64)
     ms_spmv, by_spmv = S64.time_kernel(0, reps=50)
     ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
     ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
-    roof = {"bound": "hbm", "kernel": "k_matvec (fine SpMV, FP64)", "achieved": by_spmv / ms_spmv / 1e6,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by_spmv / ms_spmv / 1e6 / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_launch": by_spmv, "ms_per_launch": ms_spmv}
+    roof = {"bound": "hbm", "kernel": "asmg::k_gs<8, double> (Gauss-Seidel colour pass)",
+            "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": by_gs, "ms_per_launch": ms_gs}
     vcyc = {"fp64": {"ms": ms_b64, "model_bytes": by_b64, "GBs": by_b64 / ms_b64 / 1e6},
-            "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6}}
+            "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6},
+            "fine_spmv_fp64": {"ms": ms_spmv, "model_bytes": by_spmv, "GBs": by_spmv / ms_spmv / 1e6}}
     out = {
         "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",
         "value": n * args.steps / dt64, "unit": "DOF-solves/s", "n_gpus": 1, "steps": args.steps,
@@ -142,6 +206,10 @@ def main():
         "vcycle": vcyc,
         "roofline": roof,
     }
+    del S64
+    torch.cuda.synchronize()
+    if args.batch_meshes > 0:
+        out["batched"] = batched(args.batch_meshes, args.steps)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -137,7 +137,13 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
  * on `stream` between two HIP events and returns the mean duration in ms and
  * the algorithmic bytes one launch moves.
  *   which: 0 = fine SpMV q = A p (FP64), 1 = fine Gauss-Seidel sweep (all colours),
- *          2 = one full B_co application, 3 = same as 2 in the precision set at setup
+ *          2 = one full B_co application, 3 = same as 2 in the precision set at setup,
+ *          4 / 5 = the Gauss-Seidel colour-pass kernel with 8 / 4 lanes per row: every
+ *          launch of it inside `reps` full B_co applications is bracketed by its own
+ *          pair of HIP events; *ms and *bytes are the mean per launch
+ * Algorithmic bytes count each matrix entry, row pointer and vector entry the
+ * operation needs once (a colour pass: its rows, b, 1/diag, the x write, and each
+ * distinct gathered x entry).
  */
 int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *stream, double *ms,
                      double *bytes);

@@ -238,7 +238,7 @@ int asmg_element_gradient_device(asmg_handle H, const double *d_u, const double 
 
 int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
   if (int r = need_dev(H)) return r;
-  if (which < 0 || which > 3 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
+  if (which < 0 || which > 5 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
   ASMG_TRY({ return device_time_kernel(H->dev, which, reps, precision, stream, ms, bytes); })
 }
 

@@ -210,21 +210,17 @@ struct BCtl {  // device pointers of the per-system scalars (arrays of n_meshes 
   int maxit;
 };
 
-// per-mesh reduction: publish NR partials of this block; the last block of the mesh gets true
+// Reductions: every block of a CG kernel belongs to one mesh and writes NR partials; a finalize
+// kernel with one block per mesh reduces that mesh's partials in a fixed order. No atomics
+// except the count of active systems.
+
 template <int NR>
-__device__ __forceinline__ bool bpublish(const double v[NR], double *partials, unsigned *ticket, int nblocks_mesh) {
-  __shared__ bool last;
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void bwrite(double v[NR], double *partials) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      __hip_atomic_store(&partials[(size_t)blockIdx.x * NR + r], v[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)nblocks_mesh - 1);
-  }
-  __syncthreads();
-  if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  return last;
+  for (int r = 0; r < NR; ++r) v[r] = block_sum(v[r]);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) partials[(size_t)blockIdx.x * NR + r] = v[r];
 }
 
 template <int NR>
@@ -234,8 +230,7 @@ __device__ __forceinline__ void breduce(const double *partials, int b0, int b1, 
   for (int r = 0; r < NR; ++r) s[r] = 0;
   for (int b = b0 + (int)threadIdx.x; b < b1; b += BS)
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      s[r] += __hip_atomic_load(&partials[(size_t)b * NR + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int r = 0; r < NR; ++r) s[r] += partials[(size_t)b * NR + r];
 #pragma unroll
   for (int r = 0; r < NR; ++r) out[r] = block_sum(s[r]);
 }
@@ -251,7 +246,7 @@ template <int NR>
 __global__ __launch_bounds__(BS) void kb_cg_init(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
                                                  const int *__restrict__ m_b0, int nm, const double *__restrict__ f,
                                                  double *__restrict__ r, double *__restrict__ u,
-                                                 double *__restrict__ p, double tol, BCtl c, double *partials) {
+                                                 double *__restrict__ p, double *partials) {
   const int m = find_seg(m_b0, nm, blockIdx.x);
   const int row = m_r0[m] + (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
   double v[NR];
@@ -268,24 +263,28 @@ __global__ __launch_bounds__(BS) void kb_cg_init(const int *__restrict__ m_r0, c
       v[q] = fi * fi;
     }
   }
-#pragma unroll
-  for (int q = 0; q < NR; ++q) v[q] = block_sum(v[q]);
-  if (bpublish<NR>(v, partials, &c.ticket[m], m_b0[m + 1] - m_b0[m])) {
-    double t[NR];
-    breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
-    if (threadIdx.x == 0) {
-      for (int q = 0; q < NR; ++q) {
-        const int sys = m * NR + q;
-        c.fn2[sys] = t[q];
-        c.tol2[sys] = tol * tol * t[q];
-        c.iter[sys] = 0;
-        c.status[sys] = BST_OK;
-        c.first[sys] = 1;
-        c.dn[sys] = (t[q] == 0.0) ? 1 : 0;
-        if (t[q] != 0.0) atomicAdd(c.active, 1);
-      }
-      c.ticket[m] = 0;
+  bwrite<NR>(v, partials);
+}
+
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_fin_init(const int *__restrict__ m_b0, const double *partials, double tol,
+                                                  BCtl c) {
+  const int m = blockIdx.x;
+  double t[NR];
+  breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
+  if (threadIdx.x == 0) {
+    int act = 0;
+    for (int q = 0; q < NR; ++q) {
+      const int sys = m * NR + q;
+      c.fn2[sys] = t[q];
+      c.tol2[sys] = tol * tol * t[q];
+      c.iter[sys] = 0;
+      c.status[sys] = BST_OK;
+      c.first[sys] = 1;
+      c.dn[sys] = (t[q] == 0.0) ? 1 : 0;
+      act += (t[q] != 0.0);
     }
+    if (act) atomicAdd(c.active, act);
   }
 }
 
@@ -314,23 +313,25 @@ __global__ __launch_bounds__(BS) void kb_cg_spmv(const int *__restrict__ m_r0, c
       v[k] = p[i] * qi;
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) v[k] = block_sum(v[k]);
-  if (bpublish<NR>(v, partials, &c.ticket[m], m_b0[m + 1] - m_b0[m])) {
-    double t2[NR];
-    breduce<NR>(partials, m_b0[m], m_b0[m + 1], t2);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NR; ++k) {
-        const int sys = m * NR + k;
-        if (c.dn[sys]) continue;
-        c.pq[sys] = t2[k];
-        c.iter[sys] += 1;
-        if (!(t2[k] > 0.0) || !isfinite(t2[k]))
-          bretire(c, sys, isfinite(t2[k]) ? BST_NOTSPD : BST_NAN);
-        else
-          c.alpha[sys] = c.rho[sys] / t2[k];
-      }
-      c.ticket[m] = 0;
+  bwrite<NR>(v, partials);
+}
+
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_fin_spmv(const int *__restrict__ m_b0, const double *partials, BCtl c) {
+  if (*c.gdone) return;
+  const int m = blockIdx.x;
+  double t[NR];
+  breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      const int sys = m * NR + k;
+      if (c.dn[sys]) continue;
+      c.pq[sys] = t[k];
+      c.iter[sys] += 1;
+      if (!(t[k] > 0.0) || !isfinite(t[k]))
+        bretire(c, sys, isfinite(t[k]) ? BST_NOTSPD : BST_NAN);
+      else
+        c.alpha[sys] = c.rho[sys] / t[k];
     }
   }
 }
@@ -357,24 +358,26 @@ __global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ m_r0, c
       v[k] = ri * ri;
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) v[k] = block_sum(v[k]);
-  if (bpublish<NR>(v, partials, &c.ticket[m], m_b0[m + 1] - m_b0[m])) {
-    double t2[NR];
-    breduce<NR>(partials, m_b0[m], m_b0[m + 1], t2);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NR; ++k) {
-        const int sys = m * NR + k;
-        if (c.dn[sys]) continue;
-        c.rr[sys] = t2[k];
-        if (!isfinite(t2[k]))
-          bretire(c, sys, BST_NAN);
-        else if (t2[k] <= c.tol2[sys])
-          bretire(c, sys, BST_OK);
-        else if (c.iter[sys] >= c.maxit)
-          bretire(c, sys, BST_NOCONV);
-      }
-      c.ticket[m] = 0;
+  bwrite<NR>(v, partials);
+}
+
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_fin_axpy(const int *__restrict__ m_b0, const double *partials, BCtl c) {
+  if (*c.gdone) return;
+  const int m = blockIdx.x;
+  double t[NR];
+  breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      const int sys = m * NR + k;
+      if (c.dn[sys]) continue;
+      c.rr[sys] = t[k];
+      if (!isfinite(t[k]))
+        bretire(c, sys, BST_NAN);
+      else if (t[k] <= c.tol2[sys])
+        bretire(c, sys, BST_OK);
+      else if (c.iter[sys] >= c.maxit)
+        bretire(c, sys, BST_NOCONV);
     }
   }
 }
@@ -392,28 +395,30 @@ __global__ __launch_bounds__(BS) void kb_cg_rz(const int *__restrict__ m_r0, con
     const size_t i = (size_t)row * NR + k;
     v[k] = row < m_r1[m] ? r[i] * (double)z[i] : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) v[k] = block_sum(v[k]);
-  if (bpublish<NR>(v, partials, &c.ticket[m], m_b0[m + 1] - m_b0[m])) {
-    double t2[NR];
-    breduce<NR>(partials, m_b0[m], m_b0[m + 1], t2);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NR; ++k) {
-        const int sys = m * NR + k;
-        if (c.dn[sys]) continue;
-        c.rz[sys] = t2[k];
-        if (!(t2[k] > 0.0) || !isfinite(t2[k])) {
-          bretire(c, sys, isfinite(t2[k]) ? BST_NOTSPD : BST_NAN);
-        } else if (c.first[sys]) {
-          c.beta[sys] = 0.0;
-          c.rho[sys] = t2[k];
-          c.first[sys] = 0;
-        } else {
-          c.beta[sys] = t2[k] / c.rho[sys];
-          c.rho[sys] = t2[k];
-        }
+  bwrite<NR>(v, partials);
+}
+
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_fin_rz(const int *__restrict__ m_b0, const double *partials, BCtl c) {
+  if (*c.gdone) return;
+  const int m = blockIdx.x;
+  double t[NR];
+  breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      const int sys = m * NR + k;
+      if (c.dn[sys]) continue;
+      c.rz[sys] = t[k];
+      if (!(t[k] > 0.0) || !isfinite(t[k])) {
+        bretire(c, sys, isfinite(t[k]) ? BST_NOTSPD : BST_NAN);
+      } else if (c.first[sys]) {
+        c.beta[sys] = 0.0;
+        c.rho[sys] = t[k];
+        c.first[sys] = 0;
+      } else {
+        c.beta[sys] = t[k] / c.rho[sys];
+        c.rho[sys] = t[k];
       }
-      c.ticket[m] = 0;
     }
   }
 }
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(BS) void kb_true_res(const int *__restrict__ m_r0, 
                                                   const int *__restrict__ m_b0, int nm, const int *__restrict__ rp,
                                                   const int *__restrict__ ci, const double *__restrict__ av,
                                                   const double *__restrict__ dg, const double *__restrict__ f,
-                                                  const double *__restrict__ u, BCtl c, double *partials) {
+                                                  const double *__restrict__ u, double *partials) {
   const int m = find_seg(m_b0, nm, blockIdx.x);
   const int t = (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
   const int row = m_r0[m] + t / LPR, lane = t % LPR;
@@ -458,16 +463,16 @@ __global__ __launch_bounds__(BS) void kb_true_res(const int *__restrict__ m_r0, 
       v[k] = e * e;
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) v[k] = block_sum(v[k]);
-  if (bpublish<NR>(v, partials, &c.ticket[m], m_b0[m + 1] - m_b0[m])) {
-    double t2[NR];
-    breduce<NR>(partials, m_b0[m], m_b0[m + 1], t2);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NR; ++k) c.tr[m * NR + k] = t2[k];
-      c.ticket[m] = 0;
-    }
-  }
+  bwrite<NR>(v, partials);
+}
+
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_fin_tr(const int *__restrict__ m_b0, const double *partials, BCtl c) {
+  const int m = blockIdx.x;
+  double t[NR];
+  breduce<NR>(partials, m_b0[m], m_b0[m + 1], t);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NR; ++k) c.tr[m * NR + k] = t[k];
 }
 
 // restart systems whose true residual is above tol (mixed precision): r = f - A u, p = 0
@@ -1124,6 +1129,7 @@ static void b_tail(BatchDevice *dv, hipStream_t s) {
   const T *z = BV<T>::x(dv->fine);
   hipLaunchKernelGGL((kb_cg_rz<NR, T>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->r, z, dv->ctl,
                      dv->partials);
+  hipLaunchKernelGGL((kb_fin_rz<NR>), dim3(dv->nm), dim3(BS), 0, s, E.b0, dv->partials, dv->ctl);
   hipLaunchKernelGGL((kb_cg_p<NR, T>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, z, dv->p, dv->ctl);
 }
 
@@ -1136,8 +1142,10 @@ static void b_iteration(BatchDevice *dv, hipStream_t s) {
     hipLaunchKernelGGL((kb_cg_spmv<LP, NR>), dim3(Sp.nblocks), dim3(BS), 0, s, Sp.r0, Sp.r1, Sp.b0, Sp.nseg, F.A.rp,
                        F.A.ci, F.A.v64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
   });
+  hipLaunchKernelGGL((kb_fin_spmv<NR>), dim3(dv->nm), dim3(BS), 0, s, Sp.b0, dv->partials, dv->ctl);
   hipLaunchKernelGGL((kb_cg_axpy<NR>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->u, dv->r, dv->p,
                      dv->q, dv->ctl, dv->partials);
+  hipLaunchKernelGGL((kb_fin_axpy<NR>), dim3(dv->nm), dim3(BS), 0, s, E.b0, dv->partials, dv->ctl);
   b_tail<NR, T>(dv, s);
 }
 
@@ -1169,7 +1177,8 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
   // per-system ints (4 arrays sized for 4 right-hand sides), mesh tickets, active count, done flag
   HIPCHECK(hipMemsetAsync(dv->ctl_ints, 0, ((size_t)nm * 4 * 4 + nm + 2) * sizeof(int), s));
   hipLaunchKernelGGL((kb_cg_init<NR>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->f, dv->r, dv->u,
-                     dv->p, tol, dv->ctl, dv->partials);
+                     dv->p, dv->partials);
+  hipLaunchKernelGGL((kb_fin_init<NR>), dim3(nm), dim3(BS), 0, s, E.b0, dv->partials, tol, dv->ctl);
   int hst[2];
   HIPCHECK(hipMemcpyAsync(hst, dv->ctl.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -1193,8 +1202,9 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
     with_lpr(F.A.lpr, [&](auto cc) {
       constexpr int LP = decltype(cc)::value;
       hipLaunchKernelGGL((kb_true_res<LP, NR>), dim3(Sp.nblocks), dim3(BS), 0, s, Sp.r0, Sp.r1, Sp.b0, Sp.nseg,
-                         F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f, dv->u, dv->ctl, dv->partials);
+                         F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f, dv->u, dv->partials);
     });
+    hipLaunchKernelGGL((kb_fin_tr<NR>), dim3(nm), dim3(BS), 0, s, Sp.b0, dv->partials, dv->ctl);
     HIPCHECK(hipMemcpyAsync(tr.data(), dv->ctl.tr, ns * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(fn2.data(), dv->ctl.fn2, ns * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(st.data(), dv->ctl.status, ns * sizeof(int), hipMemcpyDeviceToHost, s));

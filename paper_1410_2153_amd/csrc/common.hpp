@@ -44,29 +44,6 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
-// Store this block's partial; return true in every thread of the last block to
-// finish. The last block then reads all partials (agent-scope acquire).
-__device__ __forceinline__ bool publish_partial(double v, double *partials, unsigned *ticket) {
-  __shared__ bool last;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  return last;
-}
-
-// deterministic sum of nb partials by one block; valid in thread 0
-__device__ __forceinline__ double reduce_partials(const double *partials, int nb) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += BS)
-    s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return block_sum(s);
-}
-
 // ---------------------------------------------------------------------------
 // sparse kernels
 // ---------------------------------------------------------------------------

@@ -145,32 +145,44 @@ __global__ __launch_bounds__(BS) void k_scatter_cvt(int n, const int *__restrict
   if (i < n) dst[perm[i]] = (double)src[i];
 }
 
-// r = f, u = 0, p = 0, ||f||^2 -> ctl
+// Reductions: a producer kernel runs a bounded grid-stride grid (at most RED_BLOCKS blocks)
+// and writes one partial per block; a one-block finalize kernel reduces the partials in a
+// fixed order and updates the PCG scalars. No atomics, reproducible results.
+static constexpr int RED_BLOCKS = 1024;
+
+// r = f, u = 0, p = 0; partials of ||f||^2
 __global__ __launch_bounds__(BS) void k_cg_init(int n, const double *__restrict__ f, double *__restrict__ r,
-                                                double *__restrict__ u, double *__restrict__ p, double tol,
-                                                int maxit, Ctl *ctl, double *partials) {
-  const int i = blockIdx.x * BS + threadIdx.x;
+                                                double *__restrict__ u, double *__restrict__ p,
+                                                double *__restrict__ partials) {
   double v = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
     const double fi = f[i];
     r[i] = fi;
     u[i] = 0.0;
     p[i] = 0.0;
-    v = fi * fi;
+    v += fi * fi;
   }
-  const double s = block_sum(v);
-  if (publish_partial(s, partials, &ctl->ticket)) {
-    const double t = reduce_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) {
-      ctl->fnorm2 = t;
-      ctl->tol2 = tol * tol * t;
-      ctl->iter = 0;
-      ctl->status = ST_OK;
-      ctl->done = (t == 0.0) ? 1 : 0;
-      ctl->first = 1;
-      ctl->maxit = maxit;
-      ctl->ticket = 0;
-    }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+__device__ __forceinline__ double sum_partials(const double *__restrict__ partials, int nb) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS) s += partials[i];
+  return block_sum(s);
+}
+
+__global__ __launch_bounds__(BS) void k_fin_init(const double *__restrict__ partials, int nb, double tol, int maxit,
+                                                 Ctl *ctl) {
+  const double t = sum_partials(partials, nb);
+  if (threadIdx.x == 0) {
+    ctl->fnorm2 = t;
+    ctl->tol2 = tol * tol * t;
+    ctl->iter = 0;
+    ctl->status = ST_OK;
+    ctl->done = (t == 0.0) ? 1 : 0;
+    ctl->first = 1;
+    ctl->maxit = maxit;
   }
 }
 
@@ -194,123 +206,136 @@ __global__ __launch_bounds__(BS) void k_cg_restart(int n, const int *__restrict_
   }
 }
 
-// ||f - A u||^2 -> ctl->tr
+// partials of ||f - A u||^2 (grid-stride over row groups)
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_true_res(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                  const double *__restrict__ av, const double *__restrict__ dg,
                                                  const double *__restrict__ f, const double *__restrict__ u,
-                                                 Ctl *ctl, double *partials) {
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  const double s = row_dot<LPR>(rp, ci, av, u, row, act, lane);
+                                                 double *__restrict__ partials) {
+  constexpr int RPB = BS / LPR;
+  const int lane = threadIdx.x % LPR;
   double v = 0.0;
-  if (act && lane == 0) {
-    const double e = f[row] - dg[row] * u[row] - s;
-    v = e * e;
-  }
-  const double bsum = block_sum(v);
-  if (publish_partial(bsum, partials, &ctl->ticket)) {
-    const double tt = reduce_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) {
-      ctl->tr = tt;
-      ctl->ticket = 0;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / LPR;
+    const bool act = row < n;
+    const double s = row_dot<LPR>(rp, ci, av, u, row, act, lane);
+    if (act && lane == 0) {
+      const double e = f[row] - dg[row] * u[row] - s;
+      v += e * e;
     }
   }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
-// q = A p, p.q -> alpha = rho / p.q, iteration count
+__global__ __launch_bounds__(BS) void k_fin_tr(const double *__restrict__ partials, int nb, Ctl *ctl) {
+  const double t = sum_partials(partials, nb);
+  if (threadIdx.x == 0) ctl->tr = t;
+}
+
+// q = A p; partials of p.q
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_cg_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                 const double *__restrict__ av, const double *__restrict__ dg,
-                                                const double *__restrict__ p, double *__restrict__ q, Ctl *ctl,
-                                                double *partials) {
+                                                const double *__restrict__ p, double *__restrict__ q,
+                                                const Ctl *ctl, double *__restrict__ partials) {
   if (ctl->done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  const double s = row_dot<LPR>(rp, ci, av, p, row, act, lane);
+  constexpr int RPB = BS / LPR;
+  const int lane = threadIdx.x % LPR;
   double v = 0.0;
-  if (act && lane == 0) {
-    const double pi = p[row];
-    const double qi = dg[row] * pi + s;
-    q[row] = qi;
-    v = pi * qi;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / LPR;
+    const bool act = row < n;
+    const double s = row_dot<LPR>(rp, ci, av, p, row, act, lane);
+    if (act && lane == 0) {
+      const double pi = p[row];
+      const double qi = dg[row] * pi + s;
+      q[row] = qi;
+      v += pi * qi;
+    }
   }
-  const double bsum = block_sum(v);
-  if (publish_partial(bsum, partials, &ctl->ticket)) {
-    const double pq = reduce_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) {
-      ctl->pq = pq;
-      ctl->iter += 1;
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        ctl->status = isfinite(pq) ? ST_NOTSPD : ST_NAN;
-        ctl->done = 1;
-      } else {
-        ctl->alpha = ctl->rho / pq;
-      }
-      ctl->ticket = 0;
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// alpha = rho / p.q, iteration count
+__global__ __launch_bounds__(BS) void k_fin_spmv(const double *__restrict__ partials, int nb, Ctl *ctl) {
+  if (ctl->done) return;
+  const double pq = sum_partials(partials, nb);
+  if (threadIdx.x == 0) {
+    ctl->pq = pq;
+    ctl->iter += 1;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      ctl->status = isfinite(pq) ? ST_NOTSPD : ST_NAN;
+      ctl->done = 1;
+    } else {
+      ctl->alpha = ctl->rho / pq;
     }
   }
 }
 
-// u += alpha p, r -= alpha q, ||r||^2 -> convergence flag
+// u += alpha p, r -= alpha q; partials of ||r||^2
 __global__ __launch_bounds__(BS) void k_cg_axpy(int n, double *__restrict__ u, double *__restrict__ r,
-                                                const double *__restrict__ p, const double *__restrict__ q, Ctl *ctl,
-                                                double *partials) {
+                                                const double *__restrict__ p, const double *__restrict__ q,
+                                                const Ctl *ctl, double *__restrict__ partials) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
-  const int i = blockIdx.x * BS + threadIdx.x;
   double v = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
     u[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
-    v = ri * ri;
+    v += ri * ri;
   }
-  const double bsum = block_sum(v);
-  if (publish_partial(bsum, partials, &ctl->ticket)) {
-    const double rr = reduce_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) {
-      ctl->rr = rr;
-      if (!isfinite(rr)) {
-        ctl->status = ST_NAN;
-        ctl->done = 1;
-      } else if (rr <= ctl->tol2) {
-        ctl->done = 1;
-      } else if (ctl->iter >= ctl->maxit) {
-        ctl->status = ST_NOCONV;
-        ctl->done = 1;
-      }
-      ctl->ticket = 0;
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// convergence test on ||r||^2
+__global__ __launch_bounds__(BS) void k_fin_axpy(const double *__restrict__ partials, int nb, Ctl *ctl) {
+  if (ctl->done) return;
+  const double rr = sum_partials(partials, nb);
+  if (threadIdx.x == 0) {
+    ctl->rr = rr;
+    if (!isfinite(rr)) {
+      ctl->status = ST_NAN;
+      ctl->done = 1;
+    } else if (rr <= ctl->tol2) {
+      ctl->done = 1;
+    } else if (ctl->iter >= ctl->maxit) {
+      ctl->status = ST_NOCONV;
+      ctl->done = 1;
     }
   }
 }
 
-// rho' = r.z (z = B_co r in precision T) -> beta
+// partials of r.z (z = B_co r in precision T)
 template <class T>
-__global__ __launch_bounds__(BS) void k_cg_rz(int n, const double *__restrict__ r, const T *__restrict__ z, Ctl *ctl,
-                                              double *partials) {
+__global__ __launch_bounds__(BS) void k_cg_rz(int n, const double *__restrict__ r, const T *__restrict__ z,
+                                              const Ctl *ctl, double *__restrict__ partials) {
   if (ctl->done) return;
-  const int i = blockIdx.x * BS + threadIdx.x;
-  const double v = i < n ? r[i] * (double)z[i] : 0.0;
-  const double bsum = block_sum(v);
-  if (publish_partial(bsum, partials, &ctl->ticket)) {
-    const double rz = reduce_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) {
-      ctl->rz = rz;
-      if (!(rz > 0.0) || !isfinite(rz)) {
-        ctl->status = isfinite(rz) ? ST_NOTSPD : ST_NAN;
-        ctl->done = 1;
-      } else if (ctl->first) {
-        ctl->beta = 0.0;
-        ctl->rho = rz;
-        ctl->first = 0;
-      } else {
-        ctl->beta = rz / ctl->rho;
-        ctl->rho = rz;
-      }
-      ctl->ticket = 0;
+  double v = 0.0;
+  for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) v += r[i] * (double)z[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// rho' = r.z -> beta
+__global__ __launch_bounds__(BS) void k_fin_rz(const double *__restrict__ partials, int nb, Ctl *ctl) {
+  if (ctl->done) return;
+  const double rz = sum_partials(partials, nb);
+  if (threadIdx.x == 0) {
+    ctl->rz = rz;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      ctl->status = isfinite(rz) ? ST_NOTSPD : ST_NAN;
+      ctl->done = 1;
+    } else if (ctl->first) {
+      ctl->beta = 0.0;
+      ctl->rho = rz;
+      ctl->first = 0;
+    } else {
+      ctl->beta = rz / ctl->rho;
+      ctl->rho = rz;
     }
   }
 }
@@ -411,6 +436,8 @@ struct DCsr {
 struct DLevel {
   int n = 0;
   std::vector<int> coff;      // colour offsets, C + 1
+  std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each colour's rows
+  std::vector<int64_t> ucols; // distinct columns referenced by each colour's rows
   std::vector<int> perm;      // internal -> unknown
   std::vector<int> iperm;     // unknown -> internal
   DCsr A;                     // off-diagonal part
@@ -453,9 +480,13 @@ struct Device {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int last_iters[2] = {0, 0};
   bool use_graph = true;
-  // byte model accumulation
+  // byte model accumulation, and per-launch HIP event timing of one GS kernel instance
   bool count_bytes = false;
   double bytes = 0.0;
+  int probe_lpr = 0, probe_prec = -1;          // GS launches to bracket with events (0 = none)
+  std::vector<hipEvent_t> probe_ev;            // pairs (start, stop)
+  std::vector<double> probe_bytes;
+  size_t probe_used = 0;
   std::string last_kernel;
 };
 
@@ -583,6 +614,19 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
   std::vector<float> d32(diag.begin(), diag.end()), i32(diag.size());
   for (size_t i = 0; i < diag.size(); ++i) i32[i] = 1.0f / (float)diag[i];
   if (first_time) {
+    const int C = (int)L.coff.size() - 1;
+    L.cnnz.assign(C, 0);
+    L.ucols.assign(C, 0);
+    std::vector<int> seen(L.n, -1);
+    for (int c = 0; c < C; ++c)
+      for (int i = L.coff[c]; i < L.coff[c + 1]; ++i)
+        for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+          ++L.cnnz[c];
+          if (seen[H.ci[p]] != c) {
+            seen[H.ci[p]] = c;
+            ++L.ucols[c];
+          }
+        }
     upload_csr(dv, H, L.A);
     L.dg64 = dupload(dv, diag);
     L.id64 = dupload(dv, inv);
@@ -677,7 +721,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
     HIPCHECK(hipEventCreateWithFlags(&dv->ev_out, hipEventDisableTiming));
     dv->zero_flag = dalloc<int>(dv, 1);
     HIPCHECK(hipMemset(dv->zero_flag, 0, sizeof(int)));
-    dv->max_blocks = std::max(1, (int)(((int64_t)n * 16 + BS - 1) / BS));
+    dv->max_blocks = RED_BLOCKS;
     dv->partials = dalloc<double>(dv, dv->max_blocks);
     // element data for the gradient kernel
     dv->ne = h.ne;
@@ -713,6 +757,7 @@ void device_destroy(Device *dv) {
   if (dv->stream) (void)hipStreamSynchronize(dv->stream);
   for (int k = 0; k < 2; ++k)
     if (dv->graph[k]) (void)hipGraphExecDestroy(dv->graph[k]);
+  for (hipEvent_t e : dv->probe_ev) (void)hipEventDestroy(e);
   if (dv->ev_in) (void)hipEventDestroy(dv->ev_in);
   if (dv->ev_out) (void)hipEventDestroy(dv->ev_out);
   if (dv->stream) (void)hipStreamDestroy(dv->stream);
@@ -725,6 +770,9 @@ void device_destroy(Device *dv) {
 // launch helpers
 // ---------------------------------------------------------------------------
 
+
+// grid of a reducing kernel: enough blocks for one pass, capped at RED_BLOCKS
+static inline int red_grid(int64_t rows, int lpr) { return std::min<int>(RED_BLOCKS, nblk(rows * lpr)); }
 
 static inline double csr_bytes(const DCsr &A, int vbytes) {
   return (double)A.nnz * (vbytes + 4) + 4.0 * (A.nrows + 1);
@@ -771,21 +819,41 @@ static void launch_gs(Device *dv, DLevel &L, int c, T *x, const T *b, const int 
                      vals<T>(L.A), LV<T>::id(L), b, x, done);
 }
 
+// algorithmic bytes of one colour pass: the colour's matrix rows (values, columns, row pointers),
+// b, 1/diag and the x write of its rows, and each distinct x entry it gathers once
+template <class T>
+static double gs_bytes(const DLevel &L, int c) {
+  const double rows = L.coff[c + 1] - L.coff[c];
+  return (double)L.cnnz[c] * (sizeof(T) + 4) + 4.0 * (rows + 1) + 3.0 * sizeof(T) * rows +
+         (double)sizeof(T) * L.ucols[c];
+}
+
 template <class T>
 static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
+  const bool probe = dv->probe_lpr == L.A.lpr && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0) &&
+                     L.coff[c + 1] > L.coff[c];
+  if (probe) {
+    if (dv->probe_used + 2 > dv->probe_ev.size()) {
+      hipEvent_t e0, e1;
+      HIPCHECK(hipEventCreate(&e0));
+      HIPCHECK(hipEventCreate(&e1));
+      dv->probe_ev.push_back(e0);
+      dv->probe_ev.push_back(e1);
+    }
+    HIPCHECK(hipEventRecord(dv->probe_ev[dv->probe_used], s));
+  }
   switch (L.A.lpr) {
     case 2: launch_gs<2, T>(dv, L, c, x, b, done, s); break;
     case 4: launch_gs<4, T>(dv, L, c, x, b, done, s); break;
     case 8: launch_gs<8, T>(dv, L, c, x, b, done, s); break;
     default: launch_gs<16, T>(dv, L, c, x, b, done, s); break;
   }
-  if (dv->count_bytes) {
-    const int rows = L.coff[c + 1] - L.coff[c];
-    // rows of this colour: matrix rows + b, 1/diag, x write; gathers of x counted once per sweep
-    double nnz = 0;  // approximated by the colour's share of the nonzeros
-    nnz = (double)L.A.nnz * rows / std::max(1, L.n);
-    dv->bytes += nnz * (sizeof(T) + 4) + 4.0 * rows + rows * 3.0 * sizeof(T);
+  if (probe) {
+    HIPCHECK(hipEventRecord(dv->probe_ev[dv->probe_used + 1], s));
+    dv->probe_used += 2;
+    dv->probe_bytes.push_back(gs_bytes<T>(L, c));
   }
+  if (dv->count_bytes) dv->bytes += gs_bytes<T>(L, c);
 }
 
 template <class T>
@@ -803,7 +871,6 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
   } else {
     for (int c = C - 1; c >= 0; --c) gs_pass<T>(dv, L, c, x, b, done, s);
   }
-  if (dv->count_bytes) dv->bytes += (double)L.n * sizeof(T);  // one read of x per sweep for the gathers
 }
 
 template <class T>
@@ -904,7 +971,6 @@ static void apply_Bco(Device *dv, const double *r, const int *done, hipStream_t 
     b = F.b32;
     const int C = (int)F.coff.size() - 1;
     for (int c = 1; c < C; ++c) gs_pass<T>(dv, F, c, x, b, done, s);
-    if (dv->count_bytes) dv->bytes += (double)F.n * sizeof(T);
     for (int k = 1; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, true, done, s);
   }
   residual<T>(dv, F, b, x, LV<T>::r(F), done, s);
@@ -923,8 +989,10 @@ static void pcg_tail(Device *dv, hipStream_t s) {
   // z = B_co r, rho/beta, p = z + beta p
   const int n = dv->fine.n;
   apply_Bco<T>(dv, dv->r, &dv->ctl->done, s);
-  hipLaunchKernelGGL((k_cg_rz<T>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->r, (const T *)LV<T>::x(dv->fine), dv->ctl,
+  const int g = red_grid(n, 1);
+  hipLaunchKernelGGL((k_cg_rz<T>), dim3(g), dim3(BS), 0, s, n, dv->r, (const T *)LV<T>::x(dv->fine), dv->ctl,
                      dv->partials);
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   hipLaunchKernelGGL((k_cg_p<T>), dim3(nblk(n)), dim3(BS), 0, s, n, (const T *)LV<T>::x(dv->fine), dv->p, dv->ctl);
 }
 
@@ -932,12 +1000,16 @@ template <class T>
 static void pcg_iteration(Device *dv, hipStream_t s) {
   const int n = dv->fine.n;
   DLevel &F = dv->fine;
+  int g = red_grid(n, F.A.lpr);
   with_lpr(F.A.lpr, [&](auto c) {
     constexpr int LP = decltype(c)::value;
-    hipLaunchKernelGGL((k_cg_spmv<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
-                       F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
+    hipLaunchKernelGGL((k_cg_spmv<LP>), dim3(g), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->p, dv->q,
+                       dv->ctl, dv->partials);
   });
-  hipLaunchKernelGGL(k_cg_axpy, dim3(nblk(n)), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials);
+  hipLaunchKernelGGL(k_fin_spmv, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
+  g = red_grid(n, 1);
+  hipLaunchKernelGGL(k_cg_axpy, dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials);
+  hipLaunchKernelGGL(k_fin_axpy, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   pcg_tail<T>(dv, s);
 }
 
@@ -970,8 +1042,9 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
   const int n = dv->fine.n;
   const int pi = sizeof(T) == 4 ? 1 : 0;
   DLevel &F = dv->fine;
-  hipLaunchKernelGGL(k_cg_init, dim3(nblk(n)), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, tol, dv->maxit, dv->ctl,
-                     dv->partials);
+  const int gi = red_grid(n, 1);
+  hipLaunchKernelGGL(k_cg_init, dim3(gi), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, dv->partials);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, s, dv->partials, gi, tol, dv->maxit, dv->ctl);
   pcg_tail<T>(dv, s);
   // host checks of the device flag: first after (previous count - 1) iterations, then every
   // iteration; with no history, every `check_every` (default 4) iterations
@@ -988,11 +1061,13 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
       continue;
     }
     // converged, broke down or hit max_iter: true residual in FP64
+    const int gt = red_grid(n, F.A.lpr);
     with_lpr(F.A.lpr, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      hipLaunchKernelGGL((k_true_res<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
-                         F.dg64, dv->f, dv->u, dv->ctl, dv->partials);
+      hipLaunchKernelGGL((k_true_res<LP>), dim3(gt), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f,
+                         dv->u, dv->partials);
     });
+    hipLaunchKernelGGL(k_fin_tr, dim3(1), dim3(BS), 0, s, dv->partials, gt, dv->ctl);
     read_ctl(dv, s);
     const Ctl &c = *dv->ctl_host;
     const double rel = c.fnorm2 > 0 ? std::sqrt(c.tr / c.fnorm2) : 0.0;
@@ -1107,10 +1182,13 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   hipStream_t s = (hipStream_t)stream;
   DLevel &F = dv->fine;
   const int n = F.n;
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
   const bool mixed = which == 3 ? dv->precision == ASMG_PREC_MIXED : precision == ASMG_PREC_MIXED;
+  auto bco = [&]() {
+    if (mixed)
+      apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
+    else
+      apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+  };
   auto one = [&]() {
     if (which == 0) {
       with_lpr(F.A.lpr, [&](auto c) {
@@ -1124,25 +1202,49 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
       else
         sweep<double>(dv, F, F.x64, F.b64, false, true, dv->zero_flag, s);
     } else {
-      if (mixed)
-        apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
-      else
-        apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+      bco();
     }
   };
-  // byte model of one launch
-  dv->count_bytes = true;
-  dv->bytes = 0;
-  if (which == 0)
-    dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 3;
-  else
-    one();
-  dv->count_bytes = false;
-  *bytes = dv->bytes;
   HIPCHECK(hipMemsetAsync(dv->p, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(F.b64, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(F.b32, 0, (size_t)n * 4, s));
+  if (which == 4 || which == 5) {
+    // every launch of the Gauss-Seidel colour-pass kernel with LPR 8 (which = 4) or 4 (which = 5)
+    // inside `reps` full B_co applications, each bracketed by HIP events on `s`
+    bco();  // warm-up
+    dv->probe_lpr = which == 4 ? 8 : 4;
+    dv->probe_prec = mixed ? 1 : 0;
+    dv->probe_used = 0;
+    dv->probe_bytes.clear();
+    for (int k = 0; k < reps; ++k) bco();
+    dv->probe_lpr = 0;
+    HIPCHECK(hipStreamSynchronize(s));
+    double tot = 0;
+    const size_t nl = dv->probe_used / 2;
+    for (size_t i = 0; i < nl; ++i) {
+      float t = 0;
+      HIPCHECK(hipEventElapsedTime(&t, dv->probe_ev[2 * i], dv->probe_ev[2 * i + 1]));
+      tot += t;
+    }
+    double by = 0;
+    for (double b : dv->probe_bytes) by += b;
+    *ms = nl ? tot / nl : 0.0;
+    *bytes = nl ? by / nl : 0.0;
+    return ASMG_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  // byte model of one launch
+  dv->count_bytes = true;
+  dv->bytes = 0;
+  if (which == 0)
+    dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 4;
+  else
+    one();
+  dv->count_bytes = false;
+  *bytes = dv->bytes;
   one();  // warm-up
   HIPCHECK(hipEventRecord(e0, s));
   for (int k = 0; k < reps; ++k) one();
