@@ -179,13 +179,13 @@ def main():
     log(f"mixed: {dt32 / args.steps * 1e3:.2f} ms/solve, iters {its32}, true rel res {tr32:.2e}")
     diff = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
 
-    # dominant kernel: the Gauss-Seidel colour pass (8 lanes per row, FP64), every launch inside
-    # full B_co applications bracketed by HIP events on torch's stream
+    # dominant kernel: the Gauss-Seidel colour pass (sliced ELL, FP64); every pass inside full B_co
+    # applications is timed between HIP events on torch's stream
     ms_gs, by_gs = S64.time_kernel(4, reps=10, precision=A.PREC_FP64)
     ms_spmv, by_spmv = S64.time_kernel(0, reps=50)
     ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
     ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
-    roof = {"bound": "hbm", "kernel": "asmg::k_gs<8, double> (Gauss-Seidel colour pass)",
+    roof = {"bound": "hbm", "kernel": "asmg::k_sell<0, double> (Gauss-Seidel colour pass, sliced ELL)",
             "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": by_gs, "ms_per_launch": ms_gs}

@@ -138,9 +138,10 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
  * the algorithmic bytes one launch moves.
  *   which: 0 = fine SpMV q = A p (FP64), 1 = fine Gauss-Seidel sweep (all colours),
  *          2 = one full B_co application, 3 = same as 2 in the precision set at setup,
- *          4 / 5 = the Gauss-Seidel colour-pass kernel with 8 / 4 lanes per row: every
- *          launch of it inside `reps` full B_co applications is bracketed by its own
- *          pair of HIP events; *ms and *bytes are the mean per launch
+ *          4 (or 5) = the Gauss-Seidel colour-pass kernel (sliced ELL): inside `reps`
+ *          full B_co applications every colour pass is launched 10 times back to back
+ *          between its own pair of HIP events (a pass is idempotent); *ms and *bytes
+ *          are the mean per launch
  * Algorithmic bytes count each matrix entry, row pointer and vector entry the
  * operation needs once (a colour pass: its rows, b, 1/diag, the x write, and each
  * distinct gathered x entry).

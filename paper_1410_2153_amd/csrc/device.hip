@@ -79,6 +79,43 @@ __global__ __launch_bounds__(BS) void k_gs_first_cvt(int n, int c0, const double
   }
 }
 
+// Sliced ELL (64 rows per slice = one wave, one row per lane), per colour, rows sorted by
+// length inside windows of 256 rows. Entry k of slice s, lane j sits at soff[s] + 64 k + j;
+// padding entries point at the lane's own row with value 0; srow = -1 marks empty lanes.
+// MODE 0: Gauss-Seidel pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii
+// MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j
+template <int MODE, class T>
+__global__ __launch_bounds__(BS) void k_sell(int s0, int s1, const int *__restrict__ srow,
+                                             const int *__restrict__ soff, const int *__restrict__ scol,
+                                             const T *__restrict__ sv, const T *__restrict__ dv_,
+                                             const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
+                                             const int *__restrict__ done) {
+  if (*done) return;
+  const int s = s0 + blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  if (s >= s1) return;
+  const int lane = threadIdx.x & 63;
+  const int row = srow[(size_t)s * 64 + lane];
+  if (row < 0) return;
+  const int o0 = soff[s];
+  const int w = (soff[s + 1] - o0) >> 6;
+  const int *cp = scol + o0 + lane;
+  const T *vp = sv + o0 + lane;
+  T acc0 = 0, acc1 = 0;
+  int k = 0;
+  for (; k + 1 < w; k += 2) {
+    const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
+    const T v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
+    acc0 += v0 * x[c0];
+    acc1 += v1 * x[c1];
+  }
+  if (k < w) acc0 += vp[k * 64] * x[cp[k * 64]];
+  const T acc = acc0 + acc1;
+  if (MODE == 0)
+    x[row] = (b[row] - acc) * dv_[row];
+  else
+    r[row] = b[row] - dv_[row] * x[row] - acc;
+}
+
 // residual r = b - D x - A_off x
 template <int LPR, class T>
 __global__ __launch_bounds__(BS) void k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -433,8 +470,18 @@ struct DCsr {
   int lpr = 4;
 };
 
+struct DSell {
+  int nslices = 0;
+  std::vector<int> cslice;    // slice range of each colour, C + 1 (host)
+  int *srow = nullptr, *soff = nullptr, *scol = nullptr;
+  double *sv64 = nullptr;
+  float *sv32 = nullptr;
+  int64_t entries = 0;        // stored entries including padding
+};
+
 struct DLevel {
   int n = 0;
+  DSell sell;                 // same off-diagonal part as A, sliced by colour
   std::vector<int> coff;      // colour offsets, C + 1
   std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each colour's rows
   std::vector<int64_t> ucols; // distinct columns referenced by each colour's rows
@@ -606,6 +653,65 @@ static void alloc_vectors(Device *dv, DLevel &L) {
   L.r32 = dalloc<float>(dv, L.n);
 }
 
+// sliced ELL of the internal off-diagonal CSR H, one slice set per colour
+static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
+  const int C = (int)L.coff.size() - 1;
+  std::vector<int> srow, soff{0}, scol;
+  std::vector<double> sv;
+  std::vector<int> cs{0};
+  std::vector<int> idx;
+  for (int c = 0; c < C; ++c) {
+    for (int w0 = L.coff[c]; w0 < L.coff[c + 1]; w0 += 256) {
+      const int w1 = std::min(w0 + 256, L.coff[c + 1]);
+      idx.resize(w1 - w0);
+      std::iota(idx.begin(), idx.end(), w0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        return (H.rp[a + 1] - H.rp[a]) > (H.rp[b + 1] - H.rp[b]);
+      });
+      for (size_t s0 = 0; s0 < idx.size(); s0 += 64) {
+        const size_t s1 = std::min(s0 + 64, idx.size());
+        int wmax = 0;
+        for (size_t i = s0; i < s1; ++i) wmax = std::max(wmax, H.rp[idx[i] + 1] - H.rp[idx[i]]);
+        const int base = soff.back();
+        scol.resize(base + 64 * wmax);
+        sv.resize(base + 64 * wmax);
+        for (int lane = 0; lane < 64; ++lane) {
+          const size_t i = s0 + lane;
+          const int row = i < s1 ? idx[i] : -1;
+          srow.push_back(row);
+          for (int k = 0; k < wmax; ++k) {
+            int cc = row < 0 ? 0 : row;
+            double v = 0.0;
+            if (row >= 0 && k < H.rp[row + 1] - H.rp[row]) {
+              cc = H.ci[H.rp[row] + k];
+              v = H.v[H.rp[row] + k];
+            }
+            scol[base + 64 * k + lane] = cc;
+            sv[base + 64 * k + lane] = v;
+          }
+        }
+        soff.push_back(base + 64 * wmax);
+      }
+    }
+    cs.push_back((int)srow.size() / 64);
+  }
+  std::vector<float> sv32(sv.begin(), sv.end());
+  DSell &S = L.sell;
+  if (first_time) {
+    S.nslices = (int)srow.size() / 64;
+    S.cslice = cs;
+    S.entries = (int64_t)sv.size();
+    S.srow = dupload(dv, srow);
+    S.soff = dupload(dv, soff);
+    S.scol = dupload(dv, scol);
+    S.sv64 = dupload(dv, sv);
+    S.sv32 = dupload(dv, sv32);
+  } else if (!sv.empty()) {
+    HIPCHECK(hipMemcpy(S.sv64, sv.data(), sv.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(S.sv32, sv32.data(), sv32.size() * 4, hipMemcpyHostToDevice));
+  }
+}
+
 static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time) {
   std::vector<double> diag;
   HCsr H = permute(A, L.perm, &L.iperm, true, &diag);
@@ -628,12 +734,14 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
           }
         }
     upload_csr(dv, H, L.A);
+    build_sell(dv, L, H, true);
     L.dg64 = dupload(dv, diag);
     L.id64 = dupload(dv, inv);
     L.dg32 = dupload(dv, d32);
     L.id32 = dupload(dv, i32);
   } else {
     upload_values(L.A, H);
+    build_sell(dv, L, H, false);
     HIPCHECK(hipMemcpy(L.dg64, diag.data(), diag.size() * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(L.id64, inv.data(), inv.size() * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(L.dg32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
@@ -786,6 +894,13 @@ template <>
 const float *vals<float>(const DCsr &A) { return A.v32; }
 
 template <class T>
+static const T *sell_vals(const DSell &S);
+template <>
+const double *sell_vals<double>(const DSell &S) { return S.sv64; }
+template <>
+const float *sell_vals<float>(const DSell &S) { return S.sv32; }
+
+template <class T>
 struct LV {
   static T *x(DLevel &L);
   static T *b(DLevel &L);
@@ -819,6 +934,8 @@ static void launch_gs(Device *dv, DLevel &L, int c, T *x, const T *b, const int 
                      vals<T>(L.A), LV<T>::id(L), b, x, done);
 }
 
+static constexpr int PROBE_REPS = 10;
+
 // algorithmic bytes of one colour pass: the colour's matrix rows (values, columns, row pointers),
 // b, 1/diag and the x write of its rows, and each distinct x entry it gathers once
 template <class T>
@@ -830,7 +947,7 @@ static double gs_bytes(const DLevel &L, int c) {
 
 template <class T>
 static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
-  const bool probe = dv->probe_lpr == L.A.lpr && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0) &&
+  const bool probe = dv->probe_lpr != 0 && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0) &&
                      L.coff[c + 1] > L.coff[c];
   if (probe) {
     if (dv->probe_used + 2 > dv->probe_ev.size()) {
@@ -842,11 +959,13 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *d
     }
     HIPCHECK(hipEventRecord(dv->probe_ev[dv->probe_used], s));
   }
-  switch (L.A.lpr) {
-    case 2: launch_gs<2, T>(dv, L, c, x, b, done, s); break;
-    case 4: launch_gs<4, T>(dv, L, c, x, b, done, s); break;
-    case 8: launch_gs<8, T>(dv, L, c, x, b, done, s); break;
-    default: launch_gs<16, T>(dv, L, c, x, b, done, s); break;
+  // a colour pass is idempotent (its rows depend only on rows of other colours), so the probe
+  // replays it PROBE_REPS times between its events
+  for (int rep = 0; rep < (probe ? PROBE_REPS : 1); ++rep) {
+    const DSell &S = L.sell;
+    const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
+    hipLaunchKernelGGL((k_sell<0, T>), dim3(nblk((int64_t)(s1 - s0) * 64)), dim3(BS), 0, s, s0, s1, S.srow, S.soff,
+                       S.scol, sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr, done);
   }
   if (probe) {
     HIPCHECK(hipEventRecord(dv->probe_ev[dv->probe_used + 1], s));
@@ -876,11 +995,9 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
 template <class T>
 static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, const int *done, hipStream_t s) {
   const int n = L.n;
-  with_lpr(L.A.lpr, [&](auto c) {
-    constexpr int LP = decltype(c)::value;
-    hipLaunchKernelGGL((k_residual<LP, T>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, L.A.rp, L.A.ci,
-                       vals<T>(L.A), LV<T>::dg(L), b, x, r, done);
-  });
+  const DSell &S = L.sell;
+  hipLaunchKernelGGL((k_sell<1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, 0, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, done);
   if (dv->count_bytes) dv->bytes += csr_bytes(L.A, sizeof(T)) + 4.0 * n * sizeof(T);
 }
 
@@ -1210,10 +1327,10 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   HIPCHECK(hipMemsetAsync(F.b64, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(F.b32, 0, (size_t)n * 4, s));
   if (which == 4 || which == 5) {
-    // every launch of the Gauss-Seidel colour-pass kernel with LPR 8 (which = 4) or 4 (which = 5)
-    // inside `reps` full B_co applications, each bracketed by HIP events on `s`
+    // every Gauss-Seidel colour pass (k_sell<0, T>) inside `reps` full B_co applications,
+    // each bracketed by HIP events on `s`
     bco();  // warm-up
-    dv->probe_lpr = which == 4 ? 8 : 4;
+    dv->probe_lpr = 1;
     dv->probe_prec = mixed ? 1 : 0;
     dv->probe_used = 0;
     dv->probe_bytes.clear();
@@ -1225,7 +1342,7 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
     for (size_t i = 0; i < nl; ++i) {
       float t = 0;
       HIPCHECK(hipEventElapsedTime(&t, dv->probe_ev[2 * i], dv->probe_ev[2 * i + 1]));
-      tot += t;
+      tot += t / PROBE_REPS;
     }
     double by = 0;
     for (double b : dv->probe_bytes) by += b;
