@@ -48,6 +48,20 @@ def load_workload(scale: float):
     return out
 
 
+def counter_traffic():
+    """HBM traffic per colour-pass launch from the committed counter summary, if the kernel source
+    has not changed since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_sell_gs.json")
+    src = os.path.join(ROOT, "paper_1410_2153_amd", "csrc", "device.hip")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec.get("traffic_bytes_per_launch") if rec.get("device_hip_sha256") == h else None
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """Oracle solve phase on a bounded sample (graded family, 20k vertices), one thread."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -137,6 +151,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -187,7 +203,7 @@ def main():
     ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
     roof = {"bound": "hbm", "kernel": "asmg::k_sell<0, double> (Gauss-Seidel colour pass, sliced ELL)",
             "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": None,
+            "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": counter_traffic(),
             "bytes_per_launch": by_gs, "ms_per_launch": ms_gs}
     vcyc = {"fp64": {"ms": ms_b64, "model_bytes": by_b64, "GBs": by_b64 / ms_b64 / 1e6},
             "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6},
@@ -208,6 +224,13 @@ def main():
     }
     del S64
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        x = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     if args.batch_meshes > 0:
         out["batched"] = batched(args.batch_meshes, args.steps)
     if not args.no_cpu:

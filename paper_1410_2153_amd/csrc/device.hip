@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <memory>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -116,6 +117,35 @@ __global__ __launch_bounds__(BS) void k_sell(int s0, int s1, const int *__restri
     r[row] = b[row] - dv_[row] * x[row] - acc;
 }
 
+// transfer products on a sliced ELL (one colour class = all rows): y = A x (ADD = 0) or y += A x
+template <int ADD, class T>
+__global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
+                                                  const int *__restrict__ scol, const T *__restrict__ sv,
+                                                  const T *__restrict__ x, T *__restrict__ y,
+                                                  const int *__restrict__ done) {
+  if (*done) return;
+  const int s = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  if (s >= ns) return;
+  const int lane = threadIdx.x & 63;
+  const int row = srow[(size_t)s * 64 + lane];
+  if (row < 0) return;
+  const int o0 = soff[s];
+  const int w = (soff[s + 1] - o0) >> 6;
+  const int *cp = scol + o0 + lane;
+  const T *vp = sv + o0 + lane;
+  T acc0 = 0, acc1 = 0;
+  int k = 0;
+  for (; k + 1 < w; k += 2) {
+    const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
+    const T v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
+    acc0 += v0 * x[c0];
+    acc1 += v1 * x[c1];
+  }
+  if (k < w) acc0 += vp[k * 64] * x[cp[k * 64]];
+  const T acc = acc0 + acc1;
+  y[row] = ADD ? y[row] + acc : acc;
+}
+
 // residual r = b - D x - A_off x
 template <int LPR, class T>
 __global__ __launch_bounds__(BS) void k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -185,7 +215,7 @@ __global__ __launch_bounds__(BS) void k_scatter_cvt(int n, const int *__restrict
 // Reductions: a producer kernel runs a bounded grid-stride grid (at most RED_BLOCKS blocks)
 // and writes one partial per block; a one-block finalize kernel reduces the partials in a
 // fixed order and updates the PCG scalars. No atomics, reproducible results.
-static constexpr int RED_BLOCKS = 1024;
+static constexpr int RED_BLOCKS = 2048;
 
 // r = f, u = 0, p = 0; partials of ||f||^2
 __global__ __launch_bounds__(BS) void k_cg_init(int n, const double *__restrict__ f, double *__restrict__ r,
@@ -270,26 +300,35 @@ __global__ __launch_bounds__(BS) void k_fin_tr(const double *__restrict__ partia
   if (threadIdx.x == 0) ctl->tr = t;
 }
 
-// q = A p; partials of p.q
-template <int LPR>
-__global__ __launch_bounds__(BS) void k_cg_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                const double *__restrict__ av, const double *__restrict__ dg,
-                                                const double *__restrict__ p, double *__restrict__ q,
-                                                const Ctl *ctl, double *__restrict__ partials) {
+// q = A p on the sliced ELL of the original grid (all colours); partials of p.q
+__global__ __launch_bounds__(BS) void k_cg_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
+                                                const int *__restrict__ scol, const double *__restrict__ sv,
+                                                const double *__restrict__ dg, const double *__restrict__ p,
+                                                double *__restrict__ q, const Ctl *ctl,
+                                                double *__restrict__ partials) {
   if (ctl->done) return;
-  constexpr int RPB = BS / LPR;
-  const int lane = threadIdx.x % LPR;
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / LPR;
-    const bool act = row < n;
-    const double s = row_dot<LPR>(rp, ci, av, p, row, act, lane);
-    if (act && lane == 0) {
-      const double pi = p[row];
-      const double qi = dg[row] * pi + s;
-      q[row] = qi;
-      v += pi * qi;
+  for (int s = blockIdx.x * (BS / 64) + (threadIdx.x >> 6); s < ns; s += gridDim.x * (BS / 64)) {
+    const int row = srow[(size_t)s * 64 + lane];
+    if (row < 0) continue;
+    const int o0 = soff[s];
+    const int w = (soff[s + 1] - o0) >> 6;
+    const int *cp = scol + o0 + lane;
+    const double *vp = sv + o0 + lane;
+    double acc0 = 0, acc1 = 0;
+    int k = 0;
+    for (; k + 1 < w; k += 2) {
+      const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
+      const double v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
+      acc0 += v0 * p[c0];
+      acc1 += v1 * p[c1];
     }
+    if (k < w) acc0 += vp[k * 64] * p[cp[k * 64]];
+    const double pi = p[row];
+    const double qi = dg[row] * pi + (acc0 + acc1);
+    q[row] = qi;
+    v += pi * qi;
   }
   v = block_sum(v);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -461,6 +500,7 @@ __global__ __launch_bounds__(BS) void k_elem_grad(int ne, const double *__restri
 // device data
 // ---------------------------------------------------------------------------
 
+struct DSell;
 struct DCsr {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
@@ -468,6 +508,7 @@ struct DCsr {
   double *v64 = nullptr;
   float *v32 = nullptr;
   int lpr = 4;
+  DSell *sell = nullptr;       // sliced ELL copy used by the transfer products
 };
 
 struct DSell {
@@ -496,6 +537,7 @@ struct DLevel {
 };
 
 struct Device {
+  std::vector<std::unique_ptr<DSell>> sells;  // sliced ELL copies of the transfers
   int ordinal = 0;
   int d = 2;
   int J = 1, lc = 1;
@@ -610,6 +652,8 @@ static HCsr transpose(const HCsr &A) {
   return T;
 }
 
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time);
+
 static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
   D.nrows = H.nrows;
   D.ncols = H.ncols;
@@ -627,6 +671,13 @@ static void upload_values(DCsr &D, const HCsr &H) {
   HIPCHECK(hipMemcpy(D.v64, H.v.data(), H.v.size() * sizeof(double), hipMemcpyHostToDevice));
   std::vector<float> f(H.v.begin(), H.v.end());
   HIPCHECK(hipMemcpy(D.v32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+static void upload_transfer(Device *dv, const HCsr &H, DCsr &D) {
+  upload_csr(dv, H, D);
+  dv->sells.emplace_back(new DSell());
+  D.sell = dv->sells.back().get();
+  build_sell_ranges(dv, *D.sell, H, std::vector<int>{0, H.nrows}, true);
 }
 
 static void colour_order(const std::vector<int32_t> &col, DLevel &L) {
@@ -653,16 +704,17 @@ static void alloc_vectors(Device *dv, DLevel &L) {
   L.r32 = dalloc<float>(dv, L.n);
 }
 
-// sliced ELL of the internal off-diagonal CSR H, one slice set per colour
-static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
-  const int C = (int)L.coff.size() - 1;
+// sliced ELL of a host CSR: one slice set per row range [coff[c], coff[c+1]) (a colour class),
+// rows sorted by length inside windows of 256 rows, 64 rows per slice
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time) {
+  const int C = (int)coff.size() - 1;
   std::vector<int> srow, soff{0}, scol;
   std::vector<double> sv;
   std::vector<int> cs{0};
   std::vector<int> idx;
   for (int c = 0; c < C; ++c) {
-    for (int w0 = L.coff[c]; w0 < L.coff[c + 1]; w0 += 256) {
-      const int w1 = std::min(w0 + 256, L.coff[c + 1]);
+    for (int w0 = coff[c]; w0 < coff[c + 1]; w0 += 256) {
+      const int w1 = std::min(w0 + 256, coff[c + 1]);
       idx.resize(w1 - w0);
       std::iota(idx.begin(), idx.end(), w0);
       std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
@@ -680,11 +732,13 @@ static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
           const int row = i < s1 ? idx[i] : -1;
           srow.push_back(row);
           for (int k = 0; k < wmax; ++k) {
-            int cc = row < 0 ? 0 : row;
+            int cc = 0;  // padding: column 0 with value 0 (a valid index of x)
             double v = 0.0;
             if (row >= 0 && k < H.rp[row + 1] - H.rp[row]) {
               cc = H.ci[H.rp[row] + k];
               v = H.v[H.rp[row] + k];
+            } else if (row >= 0 && H.rp[row + 1] > H.rp[row]) {
+              cc = H.ci[H.rp[row]];  // repeat the row's first column: no extra cache line
             }
             scol[base + 64 * k + lane] = cc;
             sv[base + 64 * k + lane] = v;
@@ -696,7 +750,6 @@ static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
     cs.push_back((int)srow.size() / 64);
   }
   std::vector<float> sv32(sv.begin(), sv.end());
-  DSell &S = L.sell;
   if (first_time) {
     S.nslices = (int)srow.size() / 64;
     S.cslice = cs;
@@ -710,6 +763,10 @@ static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
     HIPCHECK(hipMemcpy(S.sv64, sv.data(), sv.size() * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(S.sv32, sv32.data(), sv32.size() * 4, hipMemcpyHostToDevice));
   }
+}
+
+static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
+  build_sell_ranges(dv, L.sell, H, L.coff, first_time);
 }
 
 static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time) {
@@ -802,15 +859,15 @@ Device *device_create(Hierarchy &h, int ordinal) {
       const std::vector<int> *cmap = nullptr;
       if (l - 1 > h.lc) cmap = &dv->aux[l - 1].iperm;
       HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
-      upload_csr(dv, P, L.P);
-      upload_csr(dv, transpose(P), L.PT);
+      upload_transfer(dv, P, L.P);
+      upload_transfer(dv, transpose(P), L.PT);
     }
     // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom)
     {
       const std::vector<int> *cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
       HCsr Pi = permute(h.Pi, dv->fine.perm, cmap, false, nullptr);
-      upload_csr(dv, Pi, dv->Pi);
-      upload_csr(dv, transpose(Pi), dv->PiT);
+      upload_transfer(dv, Pi, dv->Pi);
+      upload_transfer(dv, transpose(Pi), dv->PiT);
     }
     upload_coarse(dv, h, true);
     const int n = dv->fine.n;
@@ -1004,25 +1061,11 @@ static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, const 
 template <class T, int ADD>
 static void spmv(Device *dv, const DCsr &A, const T *x, T *y, const int *done, hipStream_t s) {
   if (A.nrows == 0) return;
-  switch (A.lpr) {
-    case 2:
-      hipLaunchKernelGGL((k_spmv<2, ADD, T>), dim3(nblk((int64_t)A.nrows * 2)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
-                         vals<T>(A), x, y, done);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_spmv<4, ADD, T>), dim3(nblk((int64_t)A.nrows * 4)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
-                         vals<T>(A), x, y, done);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_spmv<8, ADD, T>), dim3(nblk((int64_t)A.nrows * 8)), dim3(BS), 0, s, A.nrows, A.rp, A.ci,
-                         vals<T>(A), x, y, done);
-      break;
-    default:
-      hipLaunchKernelGGL((k_spmv<16, ADD, T>), dim3(nblk((int64_t)A.nrows * 16)), dim3(BS), 0, s, A.nrows, A.rp,
-                         A.ci, vals<T>(A), x, y, done);
-      break;
-  }
-  if (dv->count_bytes) dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
+  const DSell &S = *A.sell;
+  hipLaunchKernelGGL((k_sell_spmv<ADD, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, y, done);
+  if (dv->count_bytes)
+    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
 }
 
 template <class T>
@@ -1117,12 +1160,9 @@ template <class T>
 static void pcg_iteration(Device *dv, hipStream_t s) {
   const int n = dv->fine.n;
   DLevel &F = dv->fine;
-  int g = red_grid(n, F.A.lpr);
-  with_lpr(F.A.lpr, [&](auto c) {
-    constexpr int LP = decltype(c)::value;
-    hipLaunchKernelGGL((k_cg_spmv<LP>), dim3(g), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->p, dv->q,
-                       dv->ctl, dv->partials);
-  });
+  int g = std::min<int>(RED_BLOCKS, nblk((int64_t)F.sell.nslices * 64));
+  hipLaunchKernelGGL(k_cg_spmv, dim3(g), dim3(BS), 0, s, F.sell.nslices, F.sell.srow, F.sell.soff, F.sell.scol,
+                     F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
   hipLaunchKernelGGL(k_fin_spmv, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   g = red_grid(n, 1);
   hipLaunchKernelGGL(k_cg_axpy, dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials);
