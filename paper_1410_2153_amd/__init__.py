@@ -133,7 +133,7 @@ class Solver:
         self.n = n.value
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.asmg_destroy(self.h)
             self.h = None
 
@@ -263,7 +263,7 @@ class BatchSolver:
         self.precision = precision
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.asmg_destroy(self.h)
             self.h = None
 

@@ -1,5 +1,8 @@
 // C ABI (include/asmg.h): argument checks, error codes, exports of setup objects.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -134,13 +137,28 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     h.elems.assign(elems, elems + n_elements * (dim + 1));
     h.kappa.assign(kappa, kappa + n_elements);
     if (dirichlet) h.dirichlet.assign(dirichlet, dirichlet + n_vertices);
+    const bool tm = std::getenv("ASMG_SETUP_TIMING") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&](const char *what) {
+      if (!tm) return;
+      auto t1 = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[asmg setup] %-12s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+      t0 = t1;
+    };
     build_fine(h);
+    lap("fine");
     build_tree(h);
+    lap("tree");
     build_levels(h);
+    lap("levels");
     build_transfer(h);
+    lap("transfer");
     build_colourings(h);
+    lap("colourings");
     build_coarse(h);
+    lap("coarse");
     if (o.device >= 0) H->dev = device_create(h, o.device);
+    lap("upload");
     *out = HP.release();
     return ASMG_OK;
   })
@@ -287,6 +305,7 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
           h->nv = vert_off[m + 1] - vert_off[m];
           h->ne = elem_off[m + 1] - elem_off[m];
           h->opt = o;
+          h->threads = 1;  // the meshes themselves run on parallel threads
           h->coords.assign(coords + vert_off[m] * dim, coords + vert_off[m + 1] * dim);
           h->elems.assign(elems + elem_off[m] * (dim + 1), elems + elem_off[m + 1] * (dim + 1));
           h->kappa.assign(kappa + elem_off[m], kappa + elem_off[m + 1]);

@@ -19,11 +19,46 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <exception>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 namespace asmg {
 
 [[noreturn]] static void fail(int code, const std::string &m) { throw AsmgError{code, m}; }
+
+// run f(i) for i in [0, n) on up to h.threads host threads (0 = all cores); the first error is rethrown
+template <class F>
+static void parallel_for(const Hierarchy &h, int64_t n, F f) {
+  int nt = h.threads > 0 ? h.threads : (int)std::thread::hardware_concurrency();
+  nt = (int)std::max<int64_t>(1, std::min<int64_t>(nt, n));
+  if (nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::mutex mu;
+  std::exception_ptr err;
+  auto work = [&]() {
+    try {
+      while (true) {
+        const int64_t i = next.fetch_add(1);
+        if (i >= n) return;
+        f(i);
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> g(mu);
+      if (!err) err = std::current_exception();
+      next = n;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back(work);
+  for (auto &t : th) t.join();
+  if (err) std::rethrow_exception(err);
+}
 
 static constexpr int key_bits(int d) { return d == 2 ? 30 : 20; }
 
@@ -568,9 +603,7 @@ static bool is_fan(const Hierarchy &h, BoxCode b, int level) {
   return false;
 }
 
-const LevelMesh &level_mesh(Hierarchy &h, int level) {
-  auto it = h.meshes.find(level);
-  if (it != h.meshes.end()) return it->second;
+static LevelMesh make_level_mesh(const Hierarchy &h, int level) {
   const int d = h.d, J = h.J;
   LevelMesh lm;
   lm.level = level;
@@ -646,7 +679,13 @@ const LevelMesh &level_mesh(Hierarchy &h, int level) {
       lm.dof_vert.push_back(v);
     }
   }
-  return h.meshes.emplace(level, std::move(lm)).first->second;
+  return lm;
+}
+
+const LevelMesh &level_mesh(Hierarchy &h, int level) {
+  auto it = h.meshes.find(level);
+  if (it != h.meshes.end()) return it->second;
+  return h.meshes.emplace(level, make_level_mesh(h, level)).first->second;
 }
 
 // ---------------------------------------------------------------------------
@@ -823,19 +862,42 @@ void build_levels(Hierarchy &h) {
   const int J = h.J;
   const int Nc = h.opt.coarse_max_dofs > 0 ? h.opt.coarse_max_dofs : 1024;
   h.level_n.assign(J, -1);
+  // level sizes shrink going down; build meshes from J downwards in parallel batches until one
+  // has at most Nc unknowns
   h.lc = 1;
-  for (int l = J; l >= 1; --l) {
-    const LevelMesh &lm = level_mesh(h, l);
-    h.level_n[l - 1] = lm.n();
-    if (lm.n() <= Nc) {
-      h.lc = l;
-      break;
+  int l = J;
+  bool found = false;
+  while (!found && l >= 1) {
+    const int nb = std::min(l, std::max(1, h.threads > 0 ? h.threads : (int)std::thread::hardware_concurrency()));
+    std::vector<LevelMesh> got(nb);
+    parallel_for(h, nb, [&](int64_t i) {
+      if (!h.meshes.count(l - (int)i)) got[i] = make_level_mesh(h, l - (int)i);
+    });
+    for (int i = 0; i < nb; ++i) {
+      const int li = l - i;
+      if (!h.meshes.count(li)) h.meshes.emplace(li, std::move(got[i]));
+      h.level_n[li - 1] = h.meshes.at(li).n();
     }
+    for (int i = 0; i < nb; ++i) {
+      const int li = l - i;
+      if (h.level_n[li - 1] <= Nc) {
+        h.lc = li;
+        found = true;
+        break;
+      }
+    }
+    l -= nb;
   }
+  // meshes below the bottom are not needed
+  for (auto it = h.meshes.begin(); it != h.meshes.end();)
+    it = it->first < h.lc ? h.meshes.erase(it) : std::next(it);
+  for (int li = 1; li < h.lc; ++li) h.level_n[li - 1] = -1;
   h.Al.clear();
   h.P.clear();
-  for (int l = J; l >= h.lc; --l) assemble_level(h, l, h.Al[l], true);
-  for (int l = J; l > h.lc; --l) build_prolongation(h, l, h.P[l]);
+  for (int li = J; li >= h.lc; --li) h.Al[li];
+  for (int li = J; li > h.lc; --li) h.P[li];
+  parallel_for(h, J - h.lc + 1, [&](int64_t i) { assemble_level(h, J - (int)i, h.Al.at(J - (int)i), true); });
+  parallel_for(h, J - h.lc, [&](int64_t i) { build_prolongation(h, J - (int)i, h.P.at(J - (int)i)); });
 }
 
 void assemble_aux_values(Hierarchy &h) {
@@ -868,7 +930,7 @@ void assemble_aux_values(Hierarchy &h) {
     }
   }
   compute_kuhn_means(h);
-  for (int l = h.J; l >= h.lc; --l) assemble_level(h, l, h.Al[l], false);
+  parallel_for(h, h.J - h.lc + 1, [&](int64_t i) { assemble_level(h, h.J - (int)i, h.Al.at(h.J - (int)i), false); });
 }
 
 // ---------------------------------------------------------------------------
@@ -929,12 +991,19 @@ void build_transfer(Hierarchy &h) {
   Csr &Pi = h.Pi;
   Pi.nrows = n;
   Pi.ncols = lm.n();
-  Pi.rp.assign(n + 1, 0);
-  Pi.ci.clear();
-  Pi.v.clear();
+  // rows in chunks on parallel threads, concatenated in order
+  const int64_t CH = 4096;
+  const int64_t nch = (n + CH - 1) / CH;
+  std::vector<std::vector<int32_t>> cci(nch);
+  std::vector<std::vector<double>> cv(nch);
+  std::vector<std::vector<int64_t>> crl(nch);
+  parallel_for(h, nch, [&](int64_t ch) {
   std::vector<BoxCode> lv;
   std::vector<std::pair<int32_t, double>> acc;
-  for (int64_t i = 0; i < n; ++i) {
+  std::vector<int32_t> &oci = cci[ch];
+  std::vector<double> &ov = cv[ch];
+  std::vector<int64_t> &orl = crl[ch];
+  for (int64_t i = ch * CH; i < std::min(n, (ch + 1) * CH); ++i) {
     const int64_t vi = h.dofs[i];
     double P[3][3];
     int64_t sv[3] = {vi, sj[vi], sk[vi]};
@@ -1071,15 +1140,29 @@ void build_transfer(Hierarchy &h) {
     std::sort(acc.begin(), acc.end(), [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
       return x.first < y.first;
     });
+    const size_t before = oci.size();
     for (size_t q = 0; q < acc.size(); ++q) {
       if (q > 0 && acc[q].first == acc[q - 1].first)
-        Pi.v.back() += acc[q].second;
+        ov.back() += acc[q].second;
       else {
-        Pi.ci.push_back(acc[q].first);
-        Pi.v.push_back(acc[q].second);
+        oci.push_back(acc[q].first);
+        ov.push_back(acc[q].second);
       }
     }
-    Pi.rp[i + 1] = (int64_t)Pi.ci.size();
+    orl.push_back((int64_t)(oci.size() - before));
+  }
+  });
+  Pi.rp.assign(n + 1, 0);
+  Pi.ci.clear();
+  Pi.v.clear();
+  int64_t row = 0;
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    Pi.ci.insert(Pi.ci.end(), cci[ch].begin(), cci[ch].end());
+    Pi.v.insert(Pi.v.end(), cv[ch].begin(), cv[ch].end());
+    for (int64_t len : crl[ch]) {
+      Pi.rp[row + 1] = Pi.rp[row] + len;
+      ++row;
+    }
   }
 }
 
@@ -1158,9 +1241,9 @@ void build_coarse(Hierarchy &h) {
     }
     for (int64_t i = 0; i < j; ++i) Lm[i * n + j] = 0.0;
   }
-  // inverse column by column: solve L y = e_c, L^T x = y
-  std::vector<double> y(n);
-  for (int64_t c = 0; c < n; ++c) {
+  // inverse column by column (independent columns on parallel threads): solve L y = e_c, L^T x = y
+  parallel_for(h, n, [&](int64_t c) {
+    std::vector<double> y(n);
     for (int64_t i = 0; i < n; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
       for (int64_t k = 0; k < i; ++k) s -= Lm[i * n + k] * y[k];
@@ -1171,7 +1254,7 @@ void build_coarse(Hierarchy &h) {
       for (int64_t k = i + 1; k < n; ++k) s -= Lm[k * n + i] * h.coarse_inv[k * n + c];
       h.coarse_inv[i * n + c] = s / Lm[i * n + i];
     }
-  }
+  });
 }
 
 }  // namespace asmg

@@ -56,6 +56,7 @@ struct Hierarchy {
   std::vector<double> kappa;
   std::vector<uint8_t> dirichlet;
   asmg_options opt{};
+  int threads = 0;  // host threads for the setup (0 = all cores)
 
   // fine problem (Section 2)
   std::vector<int64_t> dofs;          // vertex id per unknown
