@@ -143,6 +143,81 @@ def batched(n_meshes: int, steps: int):
     return res
 
 
+def cube3d(steps: int):
+    """3-D workload: 128^3 cubes x 6 Kuhn tetrahedra, jittered, kappa in {1, 10} on an 8^3 checkerboard."""
+    import torch
+
+    import paper_1410_2153_amd as A
+    import workloads as W
+    c = W.make_config(2)
+    t0 = time.perf_counter()
+    S = A.Solver(c["coords"], c["elems"], c["kappa"])
+    t_setup = time.perf_counter() - t0
+    dofs = S.dof_vertex()
+    f = torch.from_numpy(np.ascontiguousarray(c["f_vertex"][dofs])).cuda()
+    res = {"workload": c["name"], "unknowns": S.n, "setup_s": t_setup, "J": S.info()["J"]}
+    for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
+        S.set_precision(prec)
+        u, it, tr = S.solve_device(f, 1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            u, it, tr = S.solve_device(f, 1e-8, out=u)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        res[name] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr}
+        log(f"cube3d {name}: {dt * 1e3:.2f} ms/solve, {it} iterations ({S.n / dt:.3e} DOF-solves/s)")
+    ms_b, by_b = S.time_kernel(2, reps=10, precision=A.PREC_FP64)
+    res["preconditioner_fp64"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6}
+    return res
+
+
+def adjoint(steps: int):
+    """Adjoint gradient workload: 724^2 jittered square, m ~ N(0, 0.3^2) per element; one step is
+    coefficient update + forward solve + adjoint solve + element gradient."""
+    import torch
+
+    import paper_1410_2153_amd as A
+    import workloads as W
+    c = W.make_config(4)
+    S = A.Solver(c["coords"], c["elems"], np.exp(c["m"]))
+    dofs = S.dof_vertex()
+    f = torch.tensor(c["f_vertex"][dofs], device="cuda")
+    S.update_coefficient(np.exp(c["m_obs"]))
+    u_obs = S.solve_device(f, 1e-8)[0] + torch.tensor(c["noise_vertex"][dofs], device="cuda")
+    Fn = A.LogCoefficientSolve.function()
+    m = torch.tensor(c["m"], device="cuda", requires_grad=True)
+
+    def step():
+        m.grad = None
+        u = Fn.apply(m, f, S, 1e-8)
+        J = 0.5 * ((u - u_obs) ** 2).sum()
+        J.backward()
+        return J
+
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    # the same step without the host-side coefficient update (two solves + element kernel only)
+    u, _, _ = S.solve_device(f, 1e-8)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        u, _, _ = S.solve_device(f, 1e-8, out=u)
+        lam, _, _ = S.solve_device((u - u_obs).contiguous(), 1e-8)
+        g = S.element_gradient(u, lam)
+    torch.cuda.synchronize()
+    dt_dev = (time.perf_counter() - t) / steps
+    log(f"adjoint: {dt * 1e3:.1f} ms per gradient incl. coefficient update, {dt_dev * 1e3:.2f} ms device part")
+    return {"workload": c["name"], "unknowns": S.n, "elements": len(c["elems"]),
+            "ms_per_gradient": dt * 1e3, "ms_per_gradient_device_part": dt_dev * 1e3,
+            "note": "coefficient update (host re-assembly of A, A_l, coarse inverse) + forward PCG + adjoint PCG + element kernel"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +226,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D and adjoint workloads")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -238,6 +314,9 @@ def main():
         del x, y
     if args.batch_meshes > 0:
         out["batched"] = batched(args.batch_meshes, args.steps)
+    if not args.no_extra:
+        out["cube3d"] = cube3d(args.steps)
+        out["adjoint"] = adjoint(args.steps)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -1,0 +1,131 @@
+"""Full-size workloads on the GPU, in the launch configuration bench.py uses.
+
+The oracle cannot run the whole solve at these sizes. These tests check, against
+oracle-side computations, properties that hold at any size:
+* the true residual of the GPU solution, recomputed with the oracle's own FP64
+  assembly of A, is <= 1e-8 (FP64 and mixed);
+* the GPU SpMV equals the oracle's A x;
+* B_co is symmetric and positive on random pairs;
+* the integer keys and refined set R_0 of the C++ setup equal the oracle's at full size;
+* the adjoint gradient passes finite-difference checks at full size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cluster, fem
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+A = pytest.importorskip("paper_1410_2153_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _load(cfg):
+    if cfg == 1:
+        import bench
+        return bench.load_workload(1.0)
+    return W.make_config(cfg)
+
+
+@pytest.fixture(scope="module", params=[1, 2])
+def full(request):
+    _say(f"[full size] config {request.param}: generating")
+    c = _load(request.param)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"])
+    Ao, dofs = fem.assemble(c["coords"], c["elems"], c["kappa"])
+    assert np.array_equal(dofs, S.dof_vertex())
+    _say(f"[full size] config {request.param}: {S.n} unknowns")
+    return request.param, c, S, Ao, dofs
+
+
+def test_true_residual_fp64_and_mixed(full):
+    cfg, c, S, Ao, dofs = full
+    f = np.ascontiguousarray(c["f_vertex"][dofs])
+    fd = torch.from_numpy(f).cuda()
+    for prec in (A.PREC_FP64, A.PREC_MIXED):
+        S.set_precision(prec)
+        u, it, tr = S.solve_device(fd, 1e-8)
+        u = u.cpu().numpy()
+        res = np.linalg.norm(f - Ao @ u) / np.linalg.norm(f)
+        _say(f"config {cfg} precision {prec}: {it} iterations, oracle-A residual {res:.3e}, library {tr:.3e}")
+        assert res <= 1e-8 * (1 + 1e-6)
+        assert abs(res - tr) <= 1e-3 * tr + 1e-15
+        assert it <= 30
+    S.set_precision(A.PREC_FP64)
+
+
+def test_spmv_matches_oracle_matrix(full):
+    cfg, c, S, Ao, dofs = full
+    x = np.random.default_rng(0).standard_normal(S.n)
+    y = S.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = Ao @ x
+    assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+def test_preconditioner_symmetric_positive(full):
+    cfg, c, S, Ao, dofs = full
+    g = np.random.default_rng(1)
+    for prec, tol in ((A.PREC_FP64, 1e-12), (A.PREC_MIXED, 1e-5)):
+        x, y = g.standard_normal(S.n), g.standard_normal(S.n)
+        Bx = S.apply_preconditioner(torch.from_numpy(x).cuda(), prec).cpu().numpy()
+        By = S.apply_preconditioner(torch.from_numpy(y).cuda(), prec).cpu().numpy()
+        assert abs(Bx @ y - x @ By) <= tol * np.linalg.norm(Bx) * np.linalg.norm(y)
+        assert Bx @ x > 0
+
+
+def test_keys_and_cluster_tree_match_oracle(full):
+    cfg, c, S, Ao, dofs = full
+    d = c["coords"].shape[1]
+    xi = cluster.barycenters(c["coords"], c["elems"])
+    a, L = cluster.root_box(c["coords"])
+    keys = cluster.axis_keys(xi, a, L, d)
+    assert np.array_equal(S.export("keys").reshape(-1, d), keys)
+    R0 = cluster.refined_by_count(keys, d, cluster.default_n_min(d))
+    R = set(map(tuple, S.export("refined").reshape(-1, d + 1).tolist()))
+    assert R0 <= R
+    info = S.info()
+    assert info["n_refined"] == len(R)
+
+
+def test_adjoint_fullsize_finite_differences():
+    c = W.make_config(4)
+    coords, elems = c["coords"], c["elems"]
+    S = A.Solver(coords, elems, np.exp(c["m"]))
+    dofs = S.dof_vertex()
+    _say(f"[full size] config 4: {S.n} unknowns")
+    f = torch.tensor(c["f_vertex"][dofs], device="cuda")
+    # observations: GPU solve at the second coefficient (tight tolerance) plus seeded noise
+    S.update_coefficient(np.exp(c["m_obs"]))
+    u_obs = S.solve_device(f, 1e-12)[0] + torch.tensor(c["noise_vertex"][dofs], device="cuda")
+    Fn = A.LogCoefficientSolve.function()
+
+    def J(mv):
+        with torch.no_grad():
+            u = Fn.apply(torch.tensor(mv, device="cuda"), f, S, 1e-12)
+            return 0.5 * float(((u - u_obs) ** 2).sum())
+
+    m = torch.tensor(c["m"], device="cuda", requires_grad=True)
+    u = Fn.apply(m, f, S, 1e-12)
+    Jm = 0.5 * ((u - u_obs) ** 2).sum()
+    Jm.backward()
+    g = m.grad.cpu().numpy()
+    # element kernel against the oracle's element formula, with the GPU's own u and lambda
+    lam = S.solve_device((u - u_obs).detach().contiguous(), 1e-12)[0]
+    uv = np.zeros(len(coords))
+    lv = np.zeros(len(coords))
+    uv[dofs] = u.detach().cpu().numpy()
+    lv[dofs] = lam.cpu().numpy()
+    ref = -fem.element_gradient_of_energy(coords, elems, np.exp(c["m"]), uv, lv)
+    assert np.abs(g - ref).max() <= 1e-8 * np.abs(ref).max()
+    for d in c["directions"][:3]:
+        eps = 1e-6
+        fd = (J(c["m"] + eps * d) - J(c["m"] - eps * d)) / (2 * eps)
+        _say(f"directional derivative: adjoint {g @ d:.10e} fd {fd:.10e}")
+        assert fd == pytest.approx(g @ d, rel=1e-5)
