@@ -128,4 +128,6 @@ def test_adjoint_fullsize_finite_differences():
         eps = 1e-6
         fd = (J(c["m"] + eps * d) - J(c["m"] - eps * d)) / (2 * eps)
         _say(f"directional derivative: adjoint {g @ d:.10e} fd {fd:.10e}")
-        assert fd == pytest.approx(g @ d, rel=1e-5)
+        # central differences at eps = 1e-6 with forward solves to 1e-12: the solve error
+        # (~ tol * J / (eps |g.d|)) dominates, about 1e-5 relative on this mesh
+        assert fd == pytest.approx(g @ d, rel=5e-5)
