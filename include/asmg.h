@@ -90,6 +90,19 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
  * re-assembles A, A_l and the coarse inverse (Section 4.1), uploads values. */
 int asmg_update_coefficient(asmg_handle h, const double *kappa);
 
+/*
+ * Replace the coefficient of the operator A on the original grid from a device
+ * array d_kappa (n_elements doubles, finite and > 0, not checked) without any
+ * host work. A is linear in kappa (Section 2, eq. (2)): every stored entry is
+ * re-summed from fixed per-element contributions on the device, in element
+ * order. The auxiliary hierarchy (A_l, bottom inverse) keeps the coefficient of
+ * the last asmg_setup / asmg_update_coefficient. The preconditioner stays SPD
+ * (its Gauss-Seidel part uses the new A). Later solves are exact for the new A
+ * to the requested tolerance; only the iteration count may change. Host-side
+ * exports of A are not updated. Stream-ordered on `stream`.
+ */
+int asmg_set_coefficient_device(asmg_handle h, const double *d_kappa, void *stream);
+
 /* Switch the precision of later solves (ASMG_PREC_FP64 or ASMG_PREC_MIXED); both
  * value copies are resident after setup, so this only changes which kernels run. */
 int asmg_set_precision(asmg_handle h, int precision);

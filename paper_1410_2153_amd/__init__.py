@@ -26,7 +26,8 @@ OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
 
 EXPORTED = [
-    "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_set_precision", "asmg_num_dofs", "asmg_dof_vertex",
+    "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_set_precision",
+    "asmg_set_coefficient_device", "asmg_num_dofs", "asmg_dof_vertex",
     "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
     "asmg_setup_batch", "asmg_solve_batch_device", "asmg_time_batch",
@@ -57,6 +58,7 @@ def _load():
     lib.asmg_setup.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
     lib.asmg_update_coefficient.argtypes = [P, P]
     lib.asmg_set_precision.argtypes = [P, ctypes.c_int]
+    lib.asmg_set_coefficient_device.argtypes = [P, P, P]
     lib.asmg_num_dofs.argtypes = [P, ctypes.POINTER(I64)]
     lib.asmg_dof_vertex.argtypes = [P, P]
     lib.asmg_solve.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
@@ -158,6 +160,13 @@ class Solver:
     def set_precision(self, precision):
         _check(lib.asmg_set_precision(self.h, precision))
         self.precision = precision
+
+    def set_coefficient_device(self, kappa):
+        """Operator A from a device coefficient tensor; the auxiliary hierarchy is kept."""
+        import torch
+        assert kappa.is_cuda and kappa.dtype == torch.float64 and kappa.is_contiguous()
+        assert kappa.numel() == self.n_elements
+        _check(lib.asmg_set_coefficient_device(self.h, _tptr(kappa), _stream()))
 
     def update_coefficient(self, kappa):
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -298,8 +307,9 @@ class BatchSolver:
 class LogCoefficientSolve:
     """u(m) = A(exp(m))^{-1} f as a torch.autograd.Function over per-element log-coefficients m.
 
-    Forward: coefficient update + PCG solve. Backward: one more PCG solve with the
-    same (symmetric) matrix, A lam = dJ/du, then the element kernel
+    Forward: device-side refresh of A from kappa = exp(m) (the auxiliary hierarchy of
+    the last setup is kept as the preconditioner) + PCG solve. Backward: one more PCG
+    solve with the same symmetric matrix, A lam = dJ/du, then the element kernel
     dJ/dm_e = -kappa_e lam_e^T K1_e u_e.
     """
 
@@ -310,7 +320,7 @@ class LogCoefficientSolve:
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, m, f, solver, tol):
-                solver.update_coefficient(torch.exp(m).detach().cpu().numpy())
+                solver.set_coefficient_device(torch.exp(m.detach()).contiguous())
                 u, _, _ = solver.solve_device(f.contiguous(), tol)
                 ctx.solver = solver
                 ctx.tol = tol

@@ -425,6 +425,44 @@ __global__ __launch_bounds__(BS) void k_cg_p(int n, const T *__restrict__ z, dou
   if (i < n) p[i] = (double)z[i] + beta * p[i];
 }
 
+// Operator refresh from a new per-element coefficient: every matrix entry is a fixed list of
+// (element, kappa-free element-matrix value) contributions, summed in element order.
+__global__ __launch_bounds__(BS) void k_refresh_off(int nnz, const int *__restrict__ ptr, const int *__restrict__ el,
+                                                    const double *__restrict__ w, const double *__restrict__ kappa,
+                                                    double *__restrict__ v64, float *__restrict__ v32) {
+  const int p = blockIdx.x * BS + threadIdx.x;
+  if (p >= nnz) return;
+  double s = 0.0;
+  for (int q = ptr[p]; q < ptr[p + 1]; ++q) s += w[q] * kappa[el[q]];
+  v64[p] = s;
+  v32[p] = (float)s;
+}
+
+__global__ __launch_bounds__(BS) void k_refresh_diag(int n, const int *__restrict__ ptr, const int *__restrict__ el,
+                                                     const double *__restrict__ w, const double *__restrict__ kappa,
+                                                     double *__restrict__ dg64, double *__restrict__ id64,
+                                                     float *__restrict__ dg32, float *__restrict__ id32) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = ptr[i]; q < ptr[i + 1]; ++q) s += w[q] * kappa[el[q]];
+  dg64[i] = s;
+  id64[i] = 1.0 / s;
+  dg32[i] = (float)s;
+  id32[i] = 1.0f / (float)s;
+}
+
+__global__ __launch_bounds__(BS) void k_refresh_sell(int nslots, const int *__restrict__ map,
+                                                     const double *__restrict__ v64, double *__restrict__ s64,
+                                                     float *__restrict__ s32) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t >= nslots) return;
+  const int p = map[t];
+  const double v = p >= 0 ? v64[p] : 0.0;
+  s64[t] = v;
+  s32[t] = (float)v;
+}
+
 // plain y = A x (diag + off), for the matvec entry point
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_matvec(int n, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -558,6 +596,10 @@ struct Device {
   int *zero_flag = nullptr;   // always 0 (for kernels run outside a PCG)
   double *partials = nullptr;
   int max_blocks = 1;
+  // operator refresh from a device coefficient (original grid)
+  int *rf_off_ptr = nullptr, *rf_off_el = nullptr, *rf_dg_ptr = nullptr, *rf_dg_el = nullptr, *rf_sell_map = nullptr;
+  double *rf_off_w = nullptr, *rf_dg_w = nullptr;
+  int rf_nslots = 0;
   // element data for the gradient
   double *coords = nullptr, *kappa = nullptr;
   int *elems = nullptr, *dof_of_vertex = nullptr;
@@ -652,7 +694,8 @@ static HCsr transpose(const HCsr &A) {
   return T;
 }
 
-static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time);
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
+                              std::vector<int> *slot_map = nullptr);
 
 static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
   D.nrows = H.nrows;
@@ -706,7 +749,9 @@ static void alloc_vectors(Device *dv, DLevel &L) {
 
 // sliced ELL of a host CSR: one slice set per row range [coff[c], coff[c+1]) (a colour class),
 // rows sorted by length inside windows of 256 rows, 64 rows per slice
-static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time) {
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
+                              std::vector<int> *slot_map) {
+  if (slot_map) slot_map->clear();
   const int C = (int)coff.size() - 1;
   std::vector<int> srow, soff{0}, scol;
   std::vector<double> sv;
@@ -742,6 +787,11 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
             }
             scol[base + 64 * k + lane] = cc;
             sv[base + 64 * k + lane] = v;
+            if (slot_map) {
+              if ((int)slot_map->size() < base + 64 * wmax) slot_map->resize(base + 64 * wmax, -1);
+              (*slot_map)[base + 64 * k + lane] =
+                  (row >= 0 && k < H.rp[row + 1] - H.rp[row]) ? H.rp[row] + k : -1;
+            }
           }
         }
         soff.push_back(base + 64 * wmax);
@@ -765,11 +815,12 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
   }
 }
 
-static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time) {
-  build_sell_ranges(dv, L.sell, H, L.coff, first_time);
+static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time, std::vector<int> *slot_map = nullptr) {
+  build_sell_ranges(dv, L.sell, H, L.coff, first_time, slot_map);
 }
 
-static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time) {
+static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time, HCsr *keep = nullptr,
+                                std::vector<int> *slot_map = nullptr) {
   std::vector<double> diag;
   HCsr H = permute(A, L.perm, &L.iperm, true, &diag);
   std::vector<double> inv(diag.size());
@@ -791,7 +842,7 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
           }
         }
     upload_csr(dv, H, L.A);
-    build_sell(dv, L, H, true);
+    build_sell(dv, L, H, true, slot_map);
     L.dg64 = dupload(dv, diag);
     L.id64 = dupload(dv, inv);
     L.dg32 = dupload(dv, d32);
@@ -804,6 +855,78 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
     HIPCHECK(hipMemcpy(L.dg32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(L.id32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice));
   }
+  if (keep) *keep = std::move(H);
+}
+
+// contribution lists of the original-grid operator (internal numbering): entry value =
+// sum over elements e of kappa_e * K1_e[a][b], elements in ascending order
+static void build_refresh(Device *dv, Hierarchy &h, const HCsr &H, const std::vector<int> &slot_map) {
+  const int d = h.d, k = d + 1, n = dv->fine.n;
+  const std::vector<int> &ip = dv->fine.iperm;
+  const int64_t nnz = (int64_t)H.ci.size();
+  std::vector<int> cnt_off(nnz + 1, 0), cnt_dg(n + 1, 0);
+  auto pos_of = [&](int i, int j) {
+    const int *b = H.ci.data() + H.rp[i], *e = H.ci.data() + H.rp[i + 1];
+    return (int)(std::lower_bound(b, e, j) - H.ci.data());
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int> eo, ed;
+    std::vector<double> wo, wd;
+    std::vector<int> fo, fd;
+    if (pass == 1) {
+      for (int64_t p = 0; p < nnz; ++p) cnt_off[p + 1] += cnt_off[p];
+      for (int i = 0; i < n; ++i) cnt_dg[i + 1] += cnt_dg[i];
+      eo.resize(cnt_off[nnz]);
+      wo.resize(cnt_off[nnz]);
+      ed.resize(cnt_dg[n]);
+      wd.resize(cnt_dg[n]);
+      fo.assign(cnt_off.begin(), cnt_off.end() - 1);
+      fd.assign(cnt_dg.begin(), cnt_dg.end() - 1);
+    }
+    double K[4][4];
+    for (int64_t e = 0; e < h.ne; ++e) {
+      int in[4];
+      for (int a = 0; a < k; ++a) {
+        const int64_t u = h.dof_of_vertex[h.elems[e * k + a]];
+        in[a] = u >= 0 ? ip[u] : -1;
+      }
+      if (pass == 1) element_unit_stiffness(h, e, K);
+      for (int a = 0; a < k; ++a) {
+        if (in[a] < 0) continue;
+        for (int b = 0; b < k; ++b) {
+          if (in[b] < 0) continue;
+          if (a == b) {
+            if (pass == 0) {
+              cnt_dg[in[a] + 1]++;
+            } else {
+              const int q = fd[in[a]]++;
+              ed[q] = (int)e;
+              wd[q] = K[a][b];
+            }
+          } else {
+            const int p = pos_of(in[a], in[b]);
+            if (pass == 0) {
+              cnt_off[p + 1]++;
+            } else {
+              const int q = fo[p]++;
+              eo[q] = (int)e;
+              wo[q] = K[a][b];
+            }
+          }
+        }
+      }
+    }
+    if (pass == 1) {
+      dv->rf_off_ptr = dupload(dv, cnt_off);
+      dv->rf_off_el = dupload(dv, eo);
+      dv->rf_off_w = dupload(dv, wo);
+      dv->rf_dg_ptr = dupload(dv, cnt_dg);
+      dv->rf_dg_el = dupload(dv, ed);
+      dv->rf_dg_w = dupload(dv, wd);
+    }
+  }
+  dv->rf_sell_map = dupload(dv, slot_map);
+  dv->rf_nslots = (int)slot_map.size();
 }
 
 static void upload_coarse(Device *dv, Hierarchy &h, bool first_time) {
@@ -841,7 +964,10 @@ Device *device_create(Hierarchy &h, int ordinal) {
     dv->check_every = h.opt.check_every;
     // fine level
     colour_order(h.colour_fine, dv->fine);
-    upload_level_matrix(dv, dv->fine, h.A, true);
+    HCsr Hfine;
+    std::vector<int> fine_slots;
+    upload_level_matrix(dv, dv->fine, h.A, true, &Hfine, &fine_slots);
+    build_refresh(dv, h, Hfine, fine_slots);
     alloc_vectors(dv, dv->fine);
     dv->perm_d = dupload(dv, dv->fine.perm);
     // auxiliary levels
@@ -1271,6 +1397,22 @@ int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *it
   HIPCHECK(hipStreamWaitEvent(cs, dv->ev_out, 0));
   HIPCHECK(hipStreamSynchronize(s));
   return rc;
+}
+
+int device_set_coefficient(Device *dv, const double *d_kappa, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  DLevel &F = dv->fine;
+  HIPCHECK(hipMemcpyAsync(dv->kappa, d_kappa, (size_t)dv->ne * 8, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_refresh_off, dim3(nblk(F.A.nnz)), dim3(BS), 0, s, (int)F.A.nnz, dv->rf_off_ptr, dv->rf_off_el,
+                     dv->rf_off_w, dv->kappa, F.A.v64, F.A.v32);
+  hipLaunchKernelGGL(k_refresh_diag, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, dv->rf_dg_ptr, dv->rf_dg_el, dv->rf_dg_w,
+                     dv->kappa, F.dg64, F.id64, F.dg32, F.id32);
+  hipLaunchKernelGGL(k_refresh_sell, dim3(nblk(dv->rf_nslots)), dim3(BS), 0, s, dv->rf_nslots, dv->rf_sell_map,
+                     F.A.v64, F.sell.sv64, F.sell.sv32);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  return ASMG_OK;
 }
 
 int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel) {

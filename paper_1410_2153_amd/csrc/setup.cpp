@@ -201,6 +201,18 @@ static inline int64_t find_col(const Csr &A, int64_t row, int32_t col) {
   return (int64_t)(p - A.ci.data());
 }
 
+void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]) {
+  const int d = h.d;
+  double G[4][3];
+  const double vol = element_grads(h, e, G) / (d == 2 ? 2.0 : 6.0);
+  for (int i = 0; i <= d; ++i)
+    for (int j = 0; j <= d; ++j) {
+      double g = 0;
+      for (int r = 0; r < d; ++r) g += G[i][r] * G[j][r];
+      K[i][j] = vol * g;
+    }
+}
+
 void build_fine(Hierarchy &h) {
   const int d = h.d;
   if (h.dirichlet.empty()) {

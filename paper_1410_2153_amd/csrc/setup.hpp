@@ -99,6 +99,8 @@ void build_transfer(Hierarchy &h);
 void build_colourings(Hierarchy &h);
 void build_coarse(Hierarchy &h);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
+// element stiffness at kappa = 1 (|tau| grad(lambda_i).grad(lambda_j))
+void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]);
 
 // helpers
 int box_level(BoxCode c, int d);

@@ -52,3 +52,30 @@ def test_autograd_gradient_vs_oracle_and_fd():
         Jp = adjoint.loss_and_gradient(coords, elems, c["m"] + eps * d, c["f_vertex"][dofs], u_obs)[0]
         Jm = adjoint.loss_and_gradient(coords, elems, c["m"] - eps * d, c["f_vertex"][dofs], u_obs)[0]
         assert (Jp - Jm) / (2 * eps) == pytest.approx(g @ d, rel=1e-5)
+
+
+def test_set_coefficient_device_refreshes_operator():
+    import scipy.sparse.linalg as sla
+    c = W.make_config(1, scale=0.01)
+    coords, elems = c["coords"], c["elems"]
+    S = A.Solver(coords, elems, c["kappa"])
+    k2 = np.exp(np.random.default_rng(9).normal(0, 0.7, len(elems)))
+    S.set_coefficient_device(torch.from_numpy(k2).cuda())
+    A2, dofs = fem.assemble(coords, elems, k2)
+    x = np.random.default_rng(1).standard_normal(S.n)
+    y = S.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.linalg.norm(y - A2 @ x) <= 1e-14 * np.linalg.norm(A2 @ x)
+    f = c["f_vertex"][dofs]
+    for prec in (A.PREC_FP64, A.PREC_MIXED):
+        S.set_precision(prec)
+        u, it, tr = S.solve(f, 1e-10)
+        assert np.linalg.norm(f - A2 @ u) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(f)
+        ref = sla.spsolve(A2.tocsc(), f)
+        assert np.linalg.norm(u - ref) <= 1e-7 * np.linalg.norm(ref)
+    lam = np.random.default_rng(2).standard_normal(S.n)
+    g = S.element_gradient(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    uv = np.zeros(len(coords))
+    lv = np.zeros(len(coords))
+    uv[dofs] = u
+    lv[dofs] = lam
+    assert np.abs(g - fem.element_gradient_of_energy(coords, elems, k2, uv, lv)).max() <= 1e-12 * np.abs(g).max()
