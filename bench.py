@@ -202,7 +202,7 @@ def adjoint(steps: int):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / steps
-    # the same step without the host-side coefficient update (two solves + element kernel only)
+    # the device part alone: two solves + element kernel
     u, _, _ = S.solve_device(f, 1e-8)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -215,7 +215,8 @@ def adjoint(steps: int):
     log(f"adjoint: {dt * 1e3:.1f} ms per gradient incl. coefficient update, {dt_dev * 1e3:.2f} ms device part")
     return {"workload": c["name"], "unknowns": S.n, "elements": len(c["elems"]),
             "ms_per_gradient": dt * 1e3, "ms_per_gradient_device_part": dt_dev * 1e3,
-            "note": "coefficient update (host re-assembly of A, A_l, coarse inverse) + forward PCG + adjoint PCG + element kernel"}
+            "note": "device refresh of A from kappa=exp(m) (auxiliary hierarchy kept) + forward PCG + adjoint PCG "
+                    "+ element kernel, through the torch.autograd.Function"}
 
 
 def main():
