@@ -45,24 +45,10 @@ struct Ctl {
 
 enum { ST_OK = 0, ST_NOTSPD = 1, ST_NAN = 2, ST_NOCONV = 3 };
 
-// one Gauss-Seidel colour pass: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii for rows [r0, r1)
-template <int LPR, class T>
-__global__ __launch_bounds__(BS) void k_gs(int r0, int r1, const int *__restrict__ rp, const int *__restrict__ ci,
-                                           const T *__restrict__ av, const T *__restrict__ invd,
-                                           const T *__restrict__ b, T *__restrict__ x, const int *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = r0 + t / LPR, lane = t % LPR;
-  const bool act = row < r1;
-  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
-  if (act && lane == 0) x[row] = (b[row] - s) * invd[row];
-}
-
 // first colour pass of a sweep that starts from x = 0: colour-0 rows get b_i / a_ii, all other rows 0
 template <class T>
 __global__ __launch_bounds__(BS) void k_gs_first(int n, int c0, const T *__restrict__ b, const T *__restrict__ invd,
-                                                 T *__restrict__ x, const int *__restrict__ done) {
-  if (*done) return;
+                                                 T *__restrict__ x) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i < n) x[i] = i < c0 ? b[i] * invd[i] : T(0);
 }
@@ -70,8 +56,7 @@ __global__ __launch_bounds__(BS) void k_gs_first(int n, int c0, const T *__restr
 // mixed precision: first pass of the fine sweep also rounds the FP64 right-hand side to FP32
 __global__ __launch_bounds__(BS) void k_gs_first_cvt(int n, int c0, const double *__restrict__ r64,
                                                      float *__restrict__ b32, const float *__restrict__ invd,
-                                                     float *__restrict__ x, const int *__restrict__ done) {
-  if (*done) return;
+                                                     float *__restrict__ x) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i < n) {
     const float bi = (float)r64[i];
@@ -82,102 +67,163 @@ __global__ __launch_bounds__(BS) void k_gs_first_cvt(int n, int c0, const double
 
 // Sliced ELL (64 rows per slice = one wave, one row per lane), per colour, rows sorted by
 // length inside windows of 256 rows. Entry k of slice s, lane j sits at soff[s] + 64 k + j;
-// padding entries point at the lane's own row with value 0; srow = -1 marks empty lanes.
+// padding entries repeat a column of the lane's row with value 0; srow = -1 marks empty lanes
+// (their entries are padding too, so every lane may load its w entries).
+//
+// An empty volatile asm that takes v as input and output: the value must be computed on every
+// active lane at this point, so the compiler cannot sink the loads feeding it under the
+// `row >= 0` store condition (which would wait for srow before issuing them).
+template <class T>
+__device__ __forceinline__ void pin(T &v) {
+  asm volatile("" : "+v"(v));
+}
+
+// A wave handles one slice. Its width w is uniform over the wave, so a row is processed by a
+// switch over w into straight-line code that issues every column and value load of the row,
+// then the row's own loads (`pre`: right-hand side, diagonal), then the gathers of x, and
+// finally calls `post` with the row product. With the row index (srow) loaded before the
+// matrix entries, a slice costs three dependent memory round trips:
+// {soff, srow} -> {columns, values, row data} -> gathers.
+template <int W, class T, class Pre, class Post>
+__device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
+                                           const T *__restrict__ x, Pre &pre, Post &post) {
+  int c[W];
+  T v[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) c[k] = cp[k * 64];
+#pragma unroll
+  for (int k = 0; k < W; ++k) v[k] = vp[k * 64];
+  pre();
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    if (k & 1)
+      a1 += v[k] * x[c[k]];
+    else
+      a0 += v[k] * x[c[k]];
+  }
+  T acc = a0 + a1;
+  pin(acc);
+  post(acc);
+}
+
+template <int W, class T>
+__device__ __forceinline__ T sell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
+                                        const T *__restrict__ x) {
+  T acc = 0;
+  auto pre = [] {};
+  auto post = [&](T a) { acc = a; };
+  sell_row_w<W>(cp, vp, x, pre, post);
+  return acc;
+}
+
+template <class T, class Pre, class Post>
+__device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
+                                         const T *__restrict__ x, Pre &pre, Post &post) {
+  switch (w) {
+    case 0: pre(); post(T(0)); break;
+    case 1: sell_row_w<1>(cp, vp, x, pre, post); break;
+    case 2: sell_row_w<2>(cp, vp, x, pre, post); break;
+    case 3: sell_row_w<3>(cp, vp, x, pre, post); break;
+    case 4: sell_row_w<4>(cp, vp, x, pre, post); break;
+    case 5: sell_row_w<5>(cp, vp, x, pre, post); break;
+    case 6: sell_row_w<6>(cp, vp, x, pre, post); break;
+    case 7: sell_row_w<7>(cp, vp, x, pre, post); break;
+    case 8: sell_row_w<8>(cp, vp, x, pre, post); break;
+    case 9: sell_row_w<9>(cp, vp, x, pre, post); break;
+    case 10: sell_row_w<10>(cp, vp, x, pre, post); break;
+    case 11: sell_row_w<11>(cp, vp, x, pre, post); break;
+    case 12: sell_row_w<12>(cp, vp, x, pre, post); break;
+    case 13: sell_row_w<13>(cp, vp, x, pre, post); break;
+    case 14: sell_row_w<14>(cp, vp, x, pre, post); break;
+    case 15: sell_row_w<15>(cp, vp, x, pre, post); break;
+    case 16: sell_row_w<16>(cp, vp, x, pre, post); break;
+    default: {
+      // long rows: chunks of 8 entries, each with its loads issued together
+      pre();
+      T acc = 0;
+      int k = 0;
+      for (; k + 8 <= w; k += 8) acc += sell_chunk<8>(cp + k * 64, vp + k * 64, x);
+      for (; k < w; ++k) acc += vp[k * 64] * x[cp[k * 64]];
+      post(acc);
+    }
+  }
+}
+
+// wave-uniform slice index of this wave (scalar registers, so the slice header is a scalar load)
+__device__ __forceinline__ int wave_slice(int first) {
+  return first + (int)blockIdx.x * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+}
+
 // MODE 0: Gauss-Seidel pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j
+// (dv_ holds 1/a_ii for MODE 0 and a_ii for MODE 1)
 template <int MODE, class T>
 __global__ __launch_bounds__(BS) void k_sell(int s0, int s1, const int *__restrict__ srow,
                                              const int *__restrict__ soff, const int *__restrict__ scol,
                                              const T *__restrict__ sv, const T *__restrict__ dv_,
-                                             const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
-                                             const int *__restrict__ done) {
-  if (*done) return;
-  const int s = s0 + blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+                                             const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r) {
+  const int s = wave_slice(s0);
   if (s >= s1) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
-  if (row < 0) return;
   const int o0 = soff[s];
   const int w = (soff[s + 1] - o0) >> 6;
-  const int *cp = scol + o0 + lane;
-  const T *vp = sv + o0 + lane;
-  T acc0 = 0, acc1 = 0;
-  int k = 0;
-  for (; k + 1 < w; k += 2) {
-    const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
-    const T v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
-    acc0 += v0 * x[c0];
-    acc1 += v1 * x[c1];
-  }
-  if (k < w) acc0 += vp[k * 64] * x[cp[k * 64]];
-  const T acc = acc0 + acc1;
-  if (MODE == 0)
-    x[row] = (b[row] - acc) * dv_[row];
-  else
-    r[row] = b[row] - dv_[row] * x[row] - acc;
+  T bi = 0, di = 0, xi = 0;
+  auto pre = [&] {
+    const int rr = row < 0 ? 0 : row;
+    bi = b[rr];
+    di = dv_[rr];
+    if (MODE == 1) xi = x[rr];
+  };
+  auto post = [&](T acc) {
+    pin(bi);
+    pin(di);
+    if (MODE == 1) pin(xi);
+    if (row < 0) return;
+    if (MODE == 0)
+      x[row] = (bi - acc) * di;
+    else
+      r[row] = bi - di * xi - acc;
+  };
+  sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
 
-// transfer products on a sliced ELL (one colour class = all rows): y = A x (ADD = 0) or y += A x
-template <int ADD, class T>
+// transfer products on a sliced ELL (one colour class = all rows): y = A x (ADD = 0) or y += A x.
+// FIRST (with ADD = 0): y is the right-hand side of a level whose smoothing starts from zero, and
+// the kernel also runs that first colour pass: xs_i = y_i / a_ii for rows i < c0 (colour 0),
+// xs_i = 0 for the other rows.
+template <int ADD, int FIRST, class T>
 __global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
                                                   const int *__restrict__ scol, const T *__restrict__ sv,
-                                                  const T *__restrict__ x, T *__restrict__ y,
-                                                  const int *__restrict__ done) {
-  if (*done) return;
-  const int s = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+                                                  const T *__restrict__ x, T *__restrict__ y, int c0,
+                                                  const T *__restrict__ invd, T *__restrict__ xs) {
+  const int s = wave_slice(0);
   if (s >= ns) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
-  if (row < 0) return;
   const int o0 = soff[s];
   const int w = (soff[s + 1] - o0) >> 6;
-  const int *cp = scol + o0 + lane;
-  const T *vp = sv + o0 + lane;
-  T acc0 = 0, acc1 = 0;
-  int k = 0;
-  for (; k + 1 < w; k += 2) {
-    const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
-    const T v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
-    acc0 += v0 * x[c0];
-    acc1 += v1 * x[c1];
-  }
-  if (k < w) acc0 += vp[k * 64] * x[cp[k * 64]];
-  const T acc = acc0 + acc1;
-  y[row] = ADD ? y[row] + acc : acc;
-}
-
-// residual r = b - D x - A_off x
-template <int LPR, class T>
-__global__ __launch_bounds__(BS) void k_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                 const T *__restrict__ av, const T *__restrict__ dg,
-                                                 const T *__restrict__ b, const T *__restrict__ x,
-                                                 T *__restrict__ r, const int *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
-  if (act && lane == 0) r[row] = b[row] - dg[row] * x[row] - s;
-}
-
-// y = A x (ADD = 0) or y += A x (ADD = 1), A a transfer matrix (no diagonal part)
-template <int LPR, int ADD, class T>
-__global__ __launch_bounds__(BS) void k_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                             const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y,
-                                             const int *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  const T s = row_dot<LPR>(rp, ci, av, x, row, act, lane);
-  if (act && lane == 0) y[row] = ADD ? y[row] + s : s;
+  T yi = 0, di = 0;
+  auto pre = [&] {
+    const int rr = row < 0 ? 0 : row;
+    if (ADD) yi = y[rr];
+    if (FIRST && rr < c0) di = invd[rr];
+  };
+  auto post = [&](T acc) {
+    if (ADD) pin(yi);
+    if (FIRST) pin(di);
+    if (row < 0) return;
+    y[row] = ADD ? yi + acc : acc;
+    if (FIRST) xs[row] = row < c0 ? acc * di : T(0);
+  };
+  sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
 
 // dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
 template <class T>
 __global__ __launch_bounds__(BS) void k_gemv(int n, const T *__restrict__ M, const T *__restrict__ g,
-                                             T *__restrict__ y, const int *__restrict__ done) {
-  if (*done) return;
+                                             T *__restrict__ y) {
   const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   T s = 0;
@@ -309,26 +355,25 @@ __global__ __launch_bounds__(BS) void k_cg_spmv(int ns, const int *__restrict__ 
   if (ctl->done) return;
   const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int s = blockIdx.x * (BS / 64) + (threadIdx.x >> 6); s < ns; s += gridDim.x * (BS / 64)) {
+  for (int s = wave_slice(0); s < ns; s += gridDim.x * (BS / 64)) {
     const int row = srow[(size_t)s * 64 + lane];
-    if (row < 0) continue;
     const int o0 = soff[s];
     const int w = (soff[s + 1] - o0) >> 6;
-    const int *cp = scol + o0 + lane;
-    const double *vp = sv + o0 + lane;
-    double acc0 = 0, acc1 = 0;
-    int k = 0;
-    for (; k + 1 < w; k += 2) {
-      const int c0 = cp[k * 64], c1 = cp[(k + 1) * 64];
-      const double v0 = vp[k * 64], v1 = vp[(k + 1) * 64];
-      acc0 += v0 * p[c0];
-      acc1 += v1 * p[c1];
-    }
-    if (k < w) acc0 += vp[k * 64] * p[cp[k * 64]];
-    const double pi = p[row];
-    const double qi = dg[row] * pi + (acc0 + acc1);
-    q[row] = qi;
-    v += pi * qi;
+    double pi = 0, di = 0;
+    auto pre = [&] {
+      const int rr = row < 0 ? 0 : row;
+      pi = p[rr];
+      di = dg[rr];
+    };
+    auto post = [&](double acc) {
+      pin(pi);
+      pin(di);
+      if (row < 0) return;
+      const double qi = di * pi + acc;
+      q[row] = qi;
+      v += pi * qi;
+    };
+    sell_row<double>(w, scol + o0 + lane, sv + o0 + lane, p, pre, post);
   }
   v = block_sum(v);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -350,10 +395,14 @@ __global__ __launch_bounds__(BS) void k_fin_spmv(const double *__restrict__ part
   }
 }
 
-// u += alpha p, r -= alpha q; partials of ||r||^2
+// u += alpha p, r -= alpha q; partials of ||r||^2. The same pass runs the colour-0 Gauss-Seidel
+// pass of the next B_co application (sweep from zero) on the new r, in the precision T of B_co:
+// xf_i = r_i / a_ii on colour-0 rows (i < c0), 0 elsewhere; in FP32 r is also rounded into bf.
+template <class T>
 __global__ __launch_bounds__(BS) void k_cg_axpy(int n, double *__restrict__ u, double *__restrict__ r,
                                                 const double *__restrict__ p, const double *__restrict__ q,
-                                                const Ctl *ctl, double *__restrict__ partials) {
+                                                const Ctl *ctl, double *__restrict__ partials, int c0,
+                                                const T *__restrict__ invd, T *__restrict__ bf, T *__restrict__ xf) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
   double v = 0.0;
@@ -362,6 +411,13 @@ __global__ __launch_bounds__(BS) void k_cg_axpy(int n, double *__restrict__ u, d
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     v += ri * ri;
+    if constexpr (sizeof(T) == 4) {
+      const float bi = (float)ri;
+      bf[i] = bi;
+      xf[i] = i < c0 ? bi * invd[i] : 0.0f;
+    } else {
+      xf[i] = i < c0 ? ri * invd[i] : 0.0;
+    }
   }
   v = block_sum(v);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -593,7 +649,6 @@ struct Device {
   double *io_in = nullptr, *io_out = nullptr;   // staging for host-pointer calls
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;    // pinned
-  int *zero_flag = nullptr;   // always 0 (for kernels run outside a PCG)
   double *partials = nullptr;
   int max_blocks = 1;
   // operator refresh from a device coefficient (original grid)
@@ -1010,8 +1065,6 @@ Device *device_create(Hierarchy &h, int ordinal) {
     HIPCHECK(hipStreamCreateWithFlags(&dv->stream, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&dv->ev_in, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&dv->ev_out, hipEventDisableTiming));
-    dv->zero_flag = dalloc<int>(dv, 1);
-    HIPCHECK(hipMemset(dv->zero_flag, 0, sizeof(int)));
     dv->max_blocks = RED_BLOCKS;
     dv->partials = dalloc<double>(dv, dv->max_blocks);
     // element data for the gradient kernel
@@ -1109,14 +1162,6 @@ struct LV<float> {
 };
 
 
-template <int LPR, class T>
-static void launch_gs(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
-  const int r0 = L.coff[c], r1 = L.coff[c + 1];
-  if (r1 <= r0) return;
-  hipLaunchKernelGGL((k_gs<LPR, T>), dim3(nblk((int64_t)(r1 - r0) * LPR)), dim3(BS), 0, s, r0, r1, L.A.rp, L.A.ci,
-                     vals<T>(L.A), LV<T>::id(L), b, x, done);
-}
-
 static constexpr int PROBE_REPS = 10;
 
 // algorithmic bytes of one colour pass: the colour's matrix rows (values, columns, row pointers),
@@ -1129,7 +1174,7 @@ static double gs_bytes(const DLevel &L, int c) {
 }
 
 template <class T>
-static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *done, hipStream_t s) {
+static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t s) {
   const bool probe = dv->probe_lpr != 0 && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0) &&
                      L.coff[c + 1] > L.coff[c];
   if (probe) {
@@ -1147,8 +1192,9 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *d
   for (int rep = 0; rep < (probe ? PROBE_REPS : 1); ++rep) {
     const DSell &S = L.sell;
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
-    hipLaunchKernelGGL((k_sell<0, T>), dim3(nblk((int64_t)(s1 - s0) * 64)), dim3(BS), 0, s, s0, s1, S.srow, S.soff,
-                       S.scol, sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr, done);
+    if (s1 > s0)
+      hipLaunchKernelGGL((k_sell<0, T>), dim3(nblk((int64_t)(s1 - s0) * 64)), dim3(BS), 0, s, s0, s1, S.srow,
+                         S.soff, S.scol, sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr);
   }
   if (probe) {
     HIPCHECK(hipEventRecord(dv->probe_ev[dv->probe_used + 1], s));
@@ -1158,40 +1204,65 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, const int *d
   if (dv->count_bytes) dv->bytes += gs_bytes<T>(L, c);
 }
 
+// bytes of the first colour pass of a sweep from zero when it runs on its own:
+// x written on every row, b and 1/diag read on colour 0
 template <class T>
-static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool forward, const int *done,
+static double first_pass_bytes(const DLevel &L) {
+  return (double)L.n * sizeof(T) + (double)L.coff[1] * 2 * sizeof(T);
+}
+
+// Gauss-Seidel sweep over colours. `first_done`: the sweep starts from zero and its colour-0
+// pass has already been run by the kernel that produced b.
+template <class T>
+static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool first_done, bool forward,
                   hipStream_t s) {
   const int C = (int)L.coff.size() - 1;
   if (forward) {
     int c = 0;
     if (from_zero) {
-      hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.coff[1], b, LV<T>::id(L), x, done);
-      if (dv->count_bytes) dv->bytes += (double)L.n * sizeof(T) + (double)L.coff[1] * 2 * sizeof(T);
+      if (!first_done) {
+        hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.coff[1], b, LV<T>::id(L), x);
+        if (dv->count_bytes) dv->bytes += first_pass_bytes<T>(L);
+      }
       c = 1;
     }
-    for (; c < C; ++c) gs_pass<T>(dv, L, c, x, b, done, s);
+    for (; c < C; ++c) gs_pass<T>(dv, L, c, x, b, s);
   } else {
-    for (int c = C - 1; c >= 0; --c) gs_pass<T>(dv, L, c, x, b, done, s);
+    for (int c = C - 1; c >= 0; --c) gs_pass<T>(dv, L, c, x, b, s);
   }
 }
 
 template <class T>
-static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, const int *done, hipStream_t s) {
+static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s) {
   const int n = L.n;
   const DSell &S = L.sell;
   hipLaunchKernelGGL((k_sell<1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, 0, S.nslices, S.srow,
-                     S.soff, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, done);
+                     S.soff, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r);
   if (dv->count_bytes) dv->bytes += csr_bytes(L.A, sizeof(T)) + 4.0 * n * sizeof(T);
 }
 
+// y = A x (ADD 0) or y += A x (ADD 1) for a transfer matrix A
 template <class T, int ADD>
-static void spmv(Device *dv, const DCsr &A, const T *x, T *y, const int *done, hipStream_t s) {
+static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s) {
   if (A.nrows == 0) return;
   const DSell &S = *A.sell;
-  hipLaunchKernelGGL((k_sell_spmv<ADD, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices, S.srow,
-                     S.soff, S.scol, sell_vals<T>(S), x, y, done);
+  hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
+                     S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
   if (dv->count_bytes)
     dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
+}
+
+// restriction y = A x into the right-hand side of level L, fused with the colour-0 pass of the
+// first (from zero) forward sweep on L
+template <class T>
+static void spmv_first(Device *dv, const DCsr &A, const T *x, DLevel &L, hipStream_t s) {
+  if (A.nrows == 0) return;
+  const DSell &S = *A.sell;
+  hipLaunchKernelGGL((k_sell_spmv<0, 1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
+  if (dv->count_bytes)
+    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + 2.0 * A.nrows * sizeof(T) +
+                 (double)L.coff[1] * sizeof(T);
 }
 
 template <class T>
@@ -1219,13 +1290,23 @@ static T *lvl_b(Device *dv, int l) { return l == dv->lc ? cvec_b<T>(dv) : LV<T>:
 template <class T>
 static T *lvl_x(Device *dv, int l) { return l == dv->lc ? cvec_x<T>(dv) : LV<T>::x(dv->aux[l]); }
 
-// Algorithm 2: B_l applied to the level's b, result in the level's x
+// restriction into level l's right-hand side (with its first colour pass above the bottom)
 template <class T>
-static void vcycle(Device *dv, int l, const int *done, hipStream_t s) {
+static void restrict_to(Device *dv, const DCsr &A, const T *x, int l, hipStream_t s) {
+  if (l == dv->lc)
+    spmv<T, 0>(dv, A, x, cvec_b<T>(dv), s);
+  else
+    spmv_first<T>(dv, A, x, dv->aux[l], s);
+}
+
+// Algorithm 2: B_l applied to the level's b, result in the level's x. Above the bottom, the
+// colour-0 pass of the first forward sweep has been run by the restriction that wrote b.
+template <class T>
+static void vcycle(Device *dv, int l, hipStream_t s) {
   if (l == dv->lc) {
     if (dv->nc > 0) {
       hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)dv->nc * 64)), dim3(BS), 0, s, dv->nc, cinv<T>(dv),
-                         cvec_b<T>(dv), cvec_x<T>(dv), done);
+                         cvec_b<T>(dv), cvec_x<T>(dv));
       if (dv->count_bytes) dv->bytes += (double)dv->nc * dv->nc * sizeof(T) + 2.0 * dv->nc * sizeof(T);
     }
     return;
@@ -1233,48 +1314,51 @@ static void vcycle(Device *dv, int l, const int *done, hipStream_t s) {
   DLevel &L = dv->aux[l];
   T *x = LV<T>::x(L);
   T *b = LV<T>::b(L);
-  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, k == 0, true, done, s);
-  residual<T>(dv, L, b, x, LV<T>::r(L), done, s);
-  spmv<T, 0>(dv, L.PT, LV<T>::r(L), lvl_b<T>(dv, l - 1), done, s);
-  vcycle<T>(dv, l - 1, done, s);
-  spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, done, s);
-  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, false, false, done, s);
+  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, k == 0, true, true, s);
+  residual<T>(dv, L, b, x, LV<T>::r(L), s);
+  restrict_to<T>(dv, L.PT, LV<T>::r(L), l - 1, s);
+  vcycle<T>(dv, l - 1, s);
+  spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, s);
+  for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, false, false, false, s);
 }
 
-// Algorithm 1 (u_0 = 0): x_fine = B_co r; r in FP64 (internal order), result in fine.x{64,32}
+// Algorithm 1 (u_0 = 0): x_fine = B_co r; r in FP64 (internal order), result in fine.x{64,32}.
+// `first_done`: the colour-0 pass of the fine forward sweep (and, in FP32, the rounding of r
+// into fine.b32) has already been run by the CG update that produced r.
 template <class T>
-static void apply_Bco(Device *dv, const double *r, const int *done, hipStream_t s) {
+static void apply_Bco(Device *dv, const double *r, bool first_done, hipStream_t s) {
   DLevel &F = dv->fine;
   T *x = LV<T>::x(F);
   const T *b;
   if constexpr (sizeof(T) == 8) {
     b = r;
-    for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, k == 0, true, done, s);
   } else {
-    hipLaunchKernelGGL(k_gs_first_cvt, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, F.coff.size() > 1 ? F.coff[1] : 0, r,
-                       F.b32, F.id32, F.x32, done);
-    if (dv->count_bytes) dv->bytes += (double)F.n * (8 + 4 + 4) + (double)F.coff[1] * 4;
+    if (!first_done) {
+      hipLaunchKernelGGL(k_gs_first_cvt, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, F.coff.size() > 1 ? F.coff[1] : 0,
+                         r, F.b32, F.id32, F.x32);
+      if (dv->count_bytes) dv->bytes += (double)F.n * (8 + 4 + 4) + (double)F.coff[1] * 4;
+      first_done = true;
+    }
     b = F.b32;
-    const int C = (int)F.coff.size() - 1;
-    for (int c = 1; c < C; ++c) gs_pass<T>(dv, F, c, x, b, done, s);
-    for (int k = 1; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, true, done, s);
   }
-  residual<T>(dv, F, b, x, LV<T>::r(F), done, s);
-  spmv<T, 0>(dv, dv->PiT, LV<T>::r(F), lvl_b<T>(dv, dv->J), done, s);
-  vcycle<T>(dv, dv->J, done, s);
-  spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, done, s);
-  for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, false, done, s);
+  for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, k == 0, first_done, true, s);
+  residual<T>(dv, F, b, x, LV<T>::r(F), s);
+  restrict_to<T>(dv, dv->PiT, LV<T>::r(F), dv->J, s);
+  vcycle<T>(dv, dv->J, s);
+  spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, s);
+  for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, false, false, s);
 }
 
 // ---------------------------------------------------------------------------
 // PCG driver
 // ---------------------------------------------------------------------------
 
+// z = B_co r, rho/beta, p = z + beta p (`first_done`: the CG update already ran the first
+// colour pass of B_co on r)
 template <class T>
-static void pcg_tail(Device *dv, hipStream_t s) {
-  // z = B_co r, rho/beta, p = z + beta p
+static void pcg_tail(Device *dv, hipStream_t s, bool first_done) {
   const int n = dv->fine.n;
-  apply_Bco<T>(dv, dv->r, &dv->ctl->done, s);
+  apply_Bco<T>(dv, dv->r, first_done, s);
   const int g = red_grid(n, 1);
   hipLaunchKernelGGL((k_cg_rz<T>), dim3(g), dim3(BS), 0, s, n, dv->r, (const T *)LV<T>::x(dv->fine), dv->ctl,
                      dv->partials);
@@ -1291,9 +1375,10 @@ static void pcg_iteration(Device *dv, hipStream_t s) {
                      F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
   hipLaunchKernelGGL(k_fin_spmv, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   g = red_grid(n, 1);
-  hipLaunchKernelGGL(k_cg_axpy, dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials);
+  hipLaunchKernelGGL((k_cg_axpy<T>), dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials,
+                     F.coff.size() > 1 ? F.coff[1] : 0, LV<T>::id(F), LV<T>::b(F), LV<T>::x(F));
   hipLaunchKernelGGL(k_fin_axpy, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
-  pcg_tail<T>(dv, s);
+  pcg_tail<T>(dv, s, true);
 }
 
 static void read_ctl(Device *dv, hipStream_t s) {
@@ -1328,7 +1413,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
   const int gi = red_grid(n, 1);
   hipLaunchKernelGGL(k_cg_init, dim3(gi), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, dv->partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, s, dv->partials, gi, tol, dv->maxit, dv->ctl);
-  pcg_tail<T>(dv, s);
+  pcg_tail<T>(dv, s, false);
   // host checks of the device flag: first after (previous count - 1) iterations, then every
   // iteration; with no history, every `check_every` (default 4) iterations
   int first = dv->last_iters[pi] > 1 ? dv->last_iters[pi] - 1 : 0;
@@ -1361,7 +1446,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
         hipLaunchKernelGGL((k_cg_restart<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci,
                            F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->ctl);
       });
-      pcg_tail<T>(dv, s);
+      pcg_tail<T>(dv, s, false);
       continue;
     }
     if (iters) *iters = c.iter;
@@ -1431,11 +1516,11 @@ int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, vo
   if (n == 0) return ASMG_OK;
   hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_r, dv->f);
   if (precision == ASMG_PREC_MIXED) {
-    apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
+    apply_Bco<float>(dv, dv->f, false, s);
     hipLaunchKernelGGL((k_scatter_cvt<float>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d,
                        (const float *)dv->fine.x32, d_z);
   } else {
-    apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+    apply_Bco<double>(dv, dv->f, false, s);
     hipLaunchKernelGGL((k_scatter_cvt<double>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d,
                        (const double *)dv->fine.x64, d_z);
   }
@@ -1484,9 +1569,9 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   const bool mixed = which == 3 ? dv->precision == ASMG_PREC_MIXED : precision == ASMG_PREC_MIXED;
   auto bco = [&]() {
     if (mixed)
-      apply_Bco<float>(dv, dv->f, dv->zero_flag, s);
+      apply_Bco<float>(dv, dv->f, false, s);
     else
-      apply_Bco<double>(dv, dv->f, dv->zero_flag, s);
+      apply_Bco<double>(dv, dv->f, false, s);
   };
   auto one = [&]() {
     if (which == 0) {
@@ -1497,9 +1582,9 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
       });
     } else if (which == 1) {
       if (mixed)
-        sweep<float>(dv, F, F.x32, F.b32, false, true, dv->zero_flag, s);
+        sweep<float>(dv, F, F.x32, F.b32, false, false, true, s);
       else
-        sweep<double>(dv, F, F.x64, F.b64, false, true, dv->zero_flag, s);
+        sweep<double>(dv, F, F.x64, F.b64, false, false, true, s);
     } else {
       bco();
     }
