@@ -143,7 +143,7 @@ def batched(n_meshes: int, steps: int):
     return res
 
 
-def cube3d(steps: int):
+def cube3d(steps: int, colouring: int = 2):
     """3-D workload: 128^3 cubes x 6 Kuhn tetrahedra, jittered, kappa in {1, 10} on an 8^3 checkerboard."""
     import torch
 
@@ -151,7 +151,7 @@ def cube3d(steps: int):
     import workloads as W
     c = W.make_config(2)
     t0 = time.perf_counter()
-    S = A.Solver(c["coords"], c["elems"], c["kappa"])
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], colouring=colouring)
     t_setup = time.perf_counter() - t0
     dofs = S.dof_vertex()
     f = torch.from_numpy(np.ascontiguousarray(c["f_vertex"][dofs])).cuda()
@@ -172,7 +172,7 @@ def cube3d(steps: int):
     return res
 
 
-def adjoint(steps: int):
+def adjoint(steps: int, colouring: int = 2):
     """Adjoint gradient workload: 724^2 jittered square, m ~ N(0, 0.3^2) per element; one step is
     coefficient update + forward solve + adjoint solve + element gradient."""
     import torch
@@ -180,7 +180,7 @@ def adjoint(steps: int):
     import paper_1410_2153_amd as A
     import workloads as W
     c = W.make_config(4)
-    S = A.Solver(c["coords"], c["elems"], np.exp(c["m"]))
+    S = A.Solver(c["coords"], c["elems"], np.exp(c["m"]), colouring=colouring)
     dofs = S.dof_vertex()
     f = torch.tensor(c["f_vertex"][dofs], device="cuda")
     S.update_coefficient(np.exp(c["m_obs"]))
@@ -230,6 +230,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 3-D and adjoint workloads")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
+    ap.add_argument("--colouring", type=int, default=2,
+                    help="Gauss-Seidel colour order of the single-mesh solves: 0 natural, 1 hash, 2 smallest-last")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -244,7 +246,7 @@ def main():
     c = load_workload(args.scale)
     log(f"workload: {len(c['coords'])} vertices, {len(c['elems'])} triangles ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64)
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64, colouring=args.colouring)
     t_setup = time.perf_counter() - t0
     info = S64.info()
     log(f"setup {t_setup:.1f} s: {info}")
@@ -298,7 +300,8 @@ def main():
         "config": {"workload": f"graded 2-D Delaunay mesh, {len(c['coords'])} vertices, {len(c['elems'])} "
                                f"triangles, kappa=exp(N(0,0.5^2)), f~U[-1,1], PCG to 1e-8 from u0=0",
                    "unknowns": n, "iterations_fp64": its64[-1], "setup_s": t_setup, "J": info["J"],
-                   "lc": info["lc"]},
+                   "lc": info["lc"], "colouring": ["natural", "hash", "smallest-last"][args.colouring],
+                   "colours_fine": info["n_colours_fine"]},
         "mixed": {"value": n * args.steps / dt32, "ms_per_step": dt32 / args.steps * 1e3,
                   "iterations": its32[-1], "true_rel_residual": tr32, "rel_diff_vs_fp64": diff},
         "vcycle": vcyc,
@@ -316,8 +319,8 @@ def main():
     if args.batch_meshes > 0:
         out["batched"] = batched(args.batch_meshes, args.steps)
     if not args.no_extra:
-        out["cube3d"] = cube3d(args.steps)
-        out["adjoint"] = adjoint(args.steps)
+        out["cube3d"] = cube3d(args.steps, args.colouring)
+        out["adjoint"] = adjoint(args.steps, args.colouring)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()

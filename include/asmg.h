@@ -61,8 +61,11 @@ typedef struct {
   uint32_t colour_seed;/* seed of the hash colour order (colouring = 1) */
   int device;          /* HIP device ordinal; -1 = host-only handle (setup and exports, no solve) */
   int check_every;     /* PCG iterations between host reads of the device convergence flag (0 = auto) */
-  int colouring;       /* Gauss-Seidel colour order: 0 = greedy in unknown order (default),
-                          1 = greedy in descending (fmix32(i ^ colour_seed), i) (Jones-Plassmann order) */
+  int colouring;       /* Gauss-Seidel colour order (greedy colouring of each matrix's pattern):
+                          0 = greedy in unknown order,
+                          1 = greedy in descending (fmix32(i ^ colour_seed), i) (Jones-Plassmann order),
+                          2 = greedy in smallest-last order (Matula-Beck; at most degeneracy + 1
+                              colours; default) */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -14,7 +14,7 @@ from . import asmg, auxgrid, auxops, cluster, colour, fem, pcg, transfer
 
 class Hierarchy:
     def __init__(self, coords, elems, kappa, dirichlet=None, n_min=None, coarse_max_dofs=1024,
-                 colour_seed=0, check_literal=False, colouring="natural"):
+                 colour_seed=0, check_literal=False, colouring="smallest_last"):
         coords = np.asarray(coords, dtype=np.float64)
         elems = np.asarray(elems, dtype=np.int64)
         self.coords = coords

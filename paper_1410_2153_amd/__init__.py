@@ -107,7 +107,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=0):
+                 colouring=2):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)

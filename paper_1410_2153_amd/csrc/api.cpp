@@ -100,7 +100,7 @@ int asmg_default_options(asmg_options *o) {
   o->colour_seed = 0;
   o->device = 0;
   o->check_every = 0;
-  o->colouring = 0;
+  o->colouring = 2;
   return ASMG_OK;
 }
 
@@ -117,7 +117,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (opt) o = *opt;
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 1)
+      o.colouring > 2)
     return set_err(ASMG_EINVAL, "invalid options");
   for (int64_t i = 0; i < n_vertices * dim; ++i)
     if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
@@ -270,7 +270,7 @@ int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *st
 static int check_options(const asmg_options &o) {
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 1)
+      o.colouring > 2)
     return set_err(ASMG_EINVAL, "invalid options");
   return ASMG_OK;
 }

@@ -23,6 +23,7 @@
 #include <exception>
 #include <mutex>
 #include <numeric>
+#include <queue>
 #include <thread>
 
 namespace asmg {
@@ -1191,11 +1192,45 @@ static inline uint32_t fmix32(uint32_t x) {
   return x;
 }
 
-// greedy colouring: ascending index (mode 0) or descending (fmix32(i ^ seed), i) (mode 1)
+// Smallest-last order (Matula and Beck): repeatedly remove the remaining row of smallest
+// (degree among the remaining rows, row index); colour in the reverse removal order. The
+// lazy-deletion heap pops exactly that minimum, so the order is unique.
+static std::vector<int64_t> smallest_last_order(const Csr &A) {
+  const int64_t n = A.nrows;
+  std::vector<int32_t> deg(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) deg[i] += A.ci[p] != i;
+  using Item = std::pair<int32_t, int64_t>;
+  std::vector<Item> init(n);
+  for (int64_t i = 0; i < n; ++i) init[i] = {deg[i], i};
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap(std::greater<Item>(), std::move(init));
+  std::vector<uint8_t> removed(n, 0);
+  std::vector<int64_t> order;
+  order.reserve(n);
+  while (!heap.empty()) {
+    const Item it = heap.top();
+    heap.pop();
+    const int64_t i = it.second;
+    if (removed[i] || it.first != deg[i]) continue;
+    removed[i] = 1;
+    order.push_back(i);
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      const int64_t j = A.ci[p];
+      if (j == i || removed[j]) continue;
+      heap.push({--deg[j], j});
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// greedy colouring (each row takes the smallest colour unused by its coloured neighbours) in
+// ascending index (mode 0), descending (fmix32(i ^ seed), i) (mode 1) or smallest-last order (mode 2)
 static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed, int mode) {
   const int64_t n = A.nrows;
   std::vector<int64_t> order(n);
   std::iota(order.begin(), order.end(), 0);
+  if (mode == 2) order = smallest_last_order(A);
   if (mode == 1) {
     std::vector<uint32_t> w(n);
     for (int64_t i = 0; i < n; ++i) w[i] = fmix32((uint32_t)i ^ seed);
@@ -1221,10 +1256,17 @@ static std::vector<int32_t> greedy_colouring(const Csr &A, uint32_t seed, int mo
 }
 
 void build_colourings(Hierarchy &h) {
-  h.colour_fine = greedy_colouring(h.A, h.opt.colour_seed, h.opt.colouring);
+  // one matrix per task: the original grid and the smoothed auxiliary levels
+  std::vector<int> lv{0};
+  for (int l = h.lc + 1; l <= h.J; ++l) lv.push_back(l);
+  std::vector<std::vector<int32_t>> out(lv.size());
+  parallel_for(h, (int64_t)lv.size(), [&](int64_t t) {
+    const Csr &A = lv[t] == 0 ? h.A : h.Al.at(lv[t]);
+    out[t] = greedy_colouring(A, h.opt.colour_seed, h.opt.colouring);
+  });
+  h.colour_fine = std::move(out[0]);
   h.colour_aux.clear();
-  for (int l = h.lc + 1; l <= h.J; ++l)
-    h.colour_aux[l] = greedy_colouring(h.Al.at(l), h.opt.colour_seed, h.opt.colouring);
+  for (size_t t = 1; t < lv.size(); ++t) h.colour_aux[lv[t]] = std::move(out[t]);
 }
 
 // ---------------------------------------------------------------------------

@@ -95,3 +95,13 @@ def test_hash_colouring_mode_matches():
     assert np.array_equal(S.export("colour_fine"), H.colour_fine)
     for l, col in H.colour_aux.items():
         assert np.array_equal(S.export("colour_aux", l), col)
+
+
+@pytest.mark.parametrize("cfg,scale,mode", [(1, 0.003, 2), (2, 0.0625, 2), (1, 0.003, 0), (2, 0.0625, 0)])
+def test_colouring_modes_match(cfg, scale, mode):
+    c = W.make_config(cfg, scale=scale)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, colouring=mode)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], colouring={0: "natural", 2: "smallest_last"}[mode])
+    assert np.array_equal(S.export("colour_fine"), H.colour_fine)
+    for l, col in H.colour_aux.items():
+        assert np.array_equal(S.export("colour_aux", l), col)
