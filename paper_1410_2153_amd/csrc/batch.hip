@@ -66,111 +66,224 @@ __device__ __forceinline__ void row_dot_nr(const int *__restrict__ rp, const int
   for (int r = 0; r < NR; ++r) acc[r] = group_sum<LPR>(acc[r]);
 }
 
-// Gauss-Seidel colour pass over a segment table
-template <int LPR, int NR, class T>
-__global__ __launch_bounds__(BS) void kb_gs(const int *__restrict__ s_r0, const int *__restrict__ s_r1,
-                                            const int *__restrict__ s_b0, int nseg, const int *__restrict__ rp,
-                                            const int *__restrict__ ci, const T *__restrict__ av,
-                                            const T *__restrict__ invd, const T *__restrict__ b, T *__restrict__ x,
-                                            const int *__restrict__ done) {
-  if (*done) return;
-  const int s = find_seg(s_b0, nseg, blockIdx.x);
-  const int t = (blockIdx.x - s_b0[s]) * BS + threadIdx.x;
-  const int row = s_r0[s] + t / LPR, lane = t % LPR;
-  const bool act = row < s_r1[s];
-  T acc[NR];
-  row_dot_nr<LPR, NR>(rp, ci, av, x, row, act, lane, acc);
-  if (act && lane == 0) {
-    const T id = invd[row];
-    VecR<NR, T> o;
-    const VecR<NR, T> bv = reinterpret_cast<const VecR<NR, T> *>(b)[row];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) o.v[r] = (bv.v[r] - acc[r]) * id;
-    reinterpret_cast<VecR<NR, T> *>(x)[row] = o;
-  }
+// ----------------------------------------------------------------------------
+// sliced ELL over NR interleaved right-hand sides
+//
+// Layout as in the single-mesh engine: 64 rows per slice (one wave, one row per lane), entry k
+// of slice s and lane j at soff[s] + 64 k + j, padding entries repeat a column of the lane's
+// row with value 0, srow = -1 marks empty lanes. A wave's slice width w is uniform, so each
+// width has straight-line code that issues every column and value load of the row, then the
+// row's own loads (`pre`), then the NR-wide gathers of x, then calls `post` with the NR sums.
+// ----------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ void bpin(T &v) {
+  asm volatile("" : "+v"(v));
 }
 
-// first pass of a sweep from zero over the smoothing rows [0, n): rows of colour 0 of their
-// mesh (row < c0 of the mesh segment) get b / a_ii, others 0. Segments = meshes, 1 row per thread.
+template <int W, int NR, class T, class Pre, class Post>
+__device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
+                                            const T *__restrict__ x, Pre &pre, Post &post) {
+  const VecR<NR, T> *X = reinterpret_cast<const VecR<NR, T> *>(x);
+  int c[W];
+  T v[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) c[k] = cp[k * 64];
+#pragma unroll
+  for (int k = 0; k < W; ++k) v[k] = vp[k * 64];
+  pre();
+  T a0[NR], a1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) a0[r] = a1[r] = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const VecR<NR, T> xv = X[c[k]];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (k & 1)
+        a1[r] += v[k] * xv.v[r];
+      else
+        a0[r] += v[k] * xv.v[r];
+    }
+  }
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    acc[r] = a0[r] + a1[r];
+    bpin(acc[r]);
+  }
+  post(acc);
+}
+
 template <int NR, class T>
-__global__ __launch_bounds__(BS) void kb_gs_first(const int *__restrict__ m_r0, const int *__restrict__ m_c0,
-                                                  const int *__restrict__ m_r1, const int *__restrict__ m_b0,
-                                                  int nseg, const T *__restrict__ b, const T *__restrict__ invd,
-                                                  T *__restrict__ x, const int *__restrict__ done) {
-  if (*done) return;
-  const int s = find_seg(m_b0, nseg, blockIdx.x);
-  const int row = m_r0[s] + (blockIdx.x - m_b0[s]) * BS + threadIdx.x;
-  if (row >= m_r1[s]) return;
-  VecR<NR, T> o;
-  if (row < m_c0[s]) {
-    const T id = invd[row];
-    const VecR<NR, T> bv = reinterpret_cast<const VecR<NR, T> *>(b)[row];
+__device__ __forceinline__ void bsell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
+                                            const T *__restrict__ x, T acc[NR]) {
+  auto pre = [] {};
+  auto post = [&](T a[NR]) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) o.v[r] = bv.v[r] * id;
-  } else {
+    for (int r = 0; r < NR; ++r) acc[r] += a[r];
+  };
+  bsell_row_w<8, NR>(cp, vp, x, pre, post);
+}
+
+template <int NR, class T, class Pre, class Post>
+__device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
+                                          const T *__restrict__ x, Pre &pre, Post &post) {
+  switch (w) {
+    case 0: {
+      pre();
+      T z[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) o.v[r] = 0;
+      for (int r = 0; r < NR; ++r) z[r] = 0;
+      post(z);
+      break;
+    }
+    case 1: bsell_row_w<1, NR>(cp, vp, x, pre, post); break;
+    case 2: bsell_row_w<2, NR>(cp, vp, x, pre, post); break;
+    case 3: bsell_row_w<3, NR>(cp, vp, x, pre, post); break;
+    case 4: bsell_row_w<4, NR>(cp, vp, x, pre, post); break;
+    case 5: bsell_row_w<5, NR>(cp, vp, x, pre, post); break;
+    case 6: bsell_row_w<6, NR>(cp, vp, x, pre, post); break;
+    case 7: bsell_row_w<7, NR>(cp, vp, x, pre, post); break;
+    case 8: bsell_row_w<8, NR>(cp, vp, x, pre, post); break;
+    case 9: bsell_row_w<9, NR>(cp, vp, x, pre, post); break;
+    case 10: bsell_row_w<10, NR>(cp, vp, x, pre, post); break;
+    case 11: bsell_row_w<11, NR>(cp, vp, x, pre, post); break;
+    case 12: bsell_row_w<12, NR>(cp, vp, x, pre, post); break;
+    default: {
+      // long rows: chunks of 8 entries, each with its loads issued together
+      pre();
+      const VecR<NR, T> *X = reinterpret_cast<const VecR<NR, T> *>(x);
+      T acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = 0;
+      int k = 0;
+      for (; k + 8 <= w; k += 8) bsell_chunk<NR>(cp + k * 64, vp + k * 64, x, acc);
+      for (; k < w; ++k) {
+        const T a = vp[k * 64];
+        const VecR<NR, T> xv = X[cp[k * 64]];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] += a * xv.v[r];
+      }
+      post(acc);
+    }
   }
-  reinterpret_cast<VecR<NR, T> *>(x)[row] = o;
 }
 
-// FP64 -> FP32 copy of the fine right-hand side (mixed precision)
-template <int NR>
-__global__ __launch_bounds__(BS) void kb_cvt(int n, const double *__restrict__ src, float *__restrict__ dst,
-                                             const int *__restrict__ done) {
-  if (*done) return;
-  const int i = blockIdx.x * BS + threadIdx.x;
-  if (i < n * NR) dst[i] = (float)src[i];
+__device__ __forceinline__ int bwave_slice(int first) {
+  return first + (int)blockIdx.x * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
-template <int LPR, int NR, class T>
-__global__ __launch_bounds__(BS) void kb_residual(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                  const T *__restrict__ av, const T *__restrict__ dg,
-                                                  const T *__restrict__ b, const T *__restrict__ x,
-                                                  T *__restrict__ r, const int *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  T acc[NR];
-  row_dot_nr<LPR, NR>(rp, ci, av, x, row, act, lane, acc);
-  if (act && lane == 0) {
-    const T d = dg[row];
-    const VecR<NR, T> bv = reinterpret_cast<const VecR<NR, T> *>(b)[row];
-    const VecR<NR, T> xv = reinterpret_cast<const VecR<NR, T> *>(x)[row];
+// MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
+// MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j (dv_ = a_ii)
+// over slices [s0, s1), every right-hand side of a row at once
+template <int MODE, int NR, class T>
+__global__ __launch_bounds__(BS) void kb_sell(int s0, int s1, const int *__restrict__ srow,
+                                              const int *__restrict__ soff, const int *__restrict__ scol,
+                                              const T *__restrict__ sv, const T *__restrict__ dv_,
+                                              const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r) {
+  const int s = bwave_slice(s0);
+  if (s >= s1) return;
+  const int lane = threadIdx.x & 63;
+  const int row = srow[(size_t)s * 64 + lane];
+  const int o0 = soff[s];
+  const int w = (soff[s + 1] - o0) >> 6;
+  VecR<NR, T> bv, xv;
+  T di = 0;
+  auto pre = [&] {
+    const int rr = row < 0 ? 0 : row;
+    bv = reinterpret_cast<const VecR<NR, T> *>(b)[rr];
+    di = dv_[rr];
+    if (MODE == 1) xv = reinterpret_cast<const VecR<NR, T> *>(x)[rr];
+  };
+  auto post = [&](T acc[NR]) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) bpin(bv.v[q]);
+    bpin(di);
+    if (row < 0) return;
     VecR<NR, T> o;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) o.v[q] = bv.v[q] - d * xv.v[q] - acc[q];
-    reinterpret_cast<VecR<NR, T> *>(r)[row] = o;
-  }
+    for (int q = 0; q < NR; ++q) o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : bv.v[q] - di * xv.v[q] - acc[q];
+    reinterpret_cast<VecR<NR, T> *>(MODE == 0 ? x : r)[row] = o;
+  };
+  bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
 
-template <int LPR, int NR, int ADD, class T>
-__global__ __launch_bounds__(BS) void kb_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                              const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y,
-                                              const int *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * BS + threadIdx.x;
-  const int row = t / LPR, lane = t % LPR;
-  const bool act = row < n;
-  T acc[NR];
-  row_dot_nr<LPR, NR>(rp, ci, av, x, row, act, lane, acc);
-  if (act && lane == 0) {
-    VecR<NR, T> o;
-    if (ADD) o = reinterpret_cast<const VecR<NR, T> *>(y)[row];
+// transfer product y = A x (ADD 0) or y += A x (ADD 1). FIRST (ADD 0): y is the right-hand side
+// of a level whose smoothing starts from zero; the kernel also runs its first colour pass,
+// xs_i = y_i * id0_i with id0_i = 1/a_ii on colour-0 rows of their mesh and 0 elsewhere.
+template <int ADD, int FIRST, int NR, class T>
+__global__ __launch_bounds__(BS) void kb_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
+                                                   const int *__restrict__ scol, const T *__restrict__ sv,
+                                                   const T *__restrict__ x, T *__restrict__ y,
+                                                   const T *__restrict__ id0, T *__restrict__ xs) {
+  const int s = bwave_slice(0);
+  if (s >= ns) return;
+  const int lane = threadIdx.x & 63;
+  const int row = srow[(size_t)s * 64 + lane];
+  const int o0 = soff[s];
+  const int w = (soff[s + 1] - o0) >> 6;
+  VecR<NR, T> yv;
+  T di = 0;
+  auto pre = [&] {
+    const int rr = row < 0 ? 0 : row;
+    if (ADD) yv = reinterpret_cast<const VecR<NR, T> *>(y)[rr];
+    if (FIRST) di = id0[rr];
+  };
+  auto post = [&](T acc[NR]) {
+    if (ADD)
 #pragma unroll
-    for (int q = 0; q < NR; ++q) o.v[q] = ADD ? o.v[q] + acc[q] : acc[q];
+      for (int q = 0; q < NR; ++q) bpin(yv.v[q]);
+    if (FIRST) bpin(di);
+    if (row < 0) return;
+    VecR<NR, T> o, f;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      o.v[q] = ADD ? yv.v[q] + acc[q] : acc[q];
+      f.v[q] = di != T(0) ? acc[q] * di : T(0);
+    }
     reinterpret_cast<VecR<NR, T> *>(y)[row] = o;
+    if (FIRST) reinterpret_cast<VecR<NR, T> *>(xs)[row] = f;
+  };
+  bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+}
+
+// first colour pass of a sweep from zero on its own: x_i = b_i * id0_i (0 off colour 0)
+template <int NR, class T>
+__global__ __launch_bounds__(BS) void kb_first(int n, const T *__restrict__ b, const T *__restrict__ id0,
+                                               T *__restrict__ x) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const T d = id0[i];
+  const VecR<NR, T> bv = reinterpret_cast<const VecR<NR, T> *>(b)[i];
+  VecR<NR, T> o;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) o.v[q] = d != T(0) ? bv.v[q] * d : T(0);
+  reinterpret_cast<VecR<NR, T> *>(x)[i] = o;
+}
+
+// mixed precision: the same pass on the original grid, which also rounds the FP64 residual to FP32
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_first_cvt(int n, const double *__restrict__ r, const float *__restrict__ id0,
+                                                   float *__restrict__ b32, float *__restrict__ x) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const float d = id0[i];
+  VecR<NR, float> bo, o;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    bo.v[q] = (float)r[(size_t)i * NR + q];
+    o.v[q] = d != 0.0f ? bo.v[q] * d : 0.0f;
   }
+  reinterpret_cast<VecR<NR, float> *>(b32)[i] = bo;
+  reinterpret_cast<VecR<NR, float> *>(x)[i] = o;
 }
 
 // bottom solves of the meshes whose V-cycle ends on this level: y = M_m g, one wave per row
 template <int NR, class T>
 __global__ __launch_bounds__(BS) void kb_gemv(const int *__restrict__ rowpref, int nb, const int *__restrict__ nc,
                                               const int64_t *__restrict__ moff, const int *__restrict__ voff,
-                                              const T *__restrict__ M, const T *__restrict__ g, T *__restrict__ y,
-                                              const int *__restrict__ done) {
-  if (*done) return;
+                                              const T *__restrict__ M, const T *__restrict__ g, T *__restrict__ y) {
   const int w = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= rowpref[nb]) return;  // whole wave leaves together
@@ -242,17 +355,17 @@ __device__ __forceinline__ void bretire(BCtl c, int sys, int status) {
   if (prev == 1) *c.gdone = 1;
 }
 
+// Element-wise CG kernels run one block per (mesh, 256-row chunk): block b covers rows
+// [ew_r0[b], ew_r1[b]) of mesh ew_m[b], and the blocks of a mesh are contiguous.
 template <int NR>
-__global__ __launch_bounds__(BS) void kb_cg_init(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
-                                                 const int *__restrict__ m_b0, int nm, const double *__restrict__ f,
-                                                 double *__restrict__ r, double *__restrict__ u,
-                                                 double *__restrict__ p, double *partials) {
-  const int m = find_seg(m_b0, nm, blockIdx.x);
-  const int row = m_r0[m] + (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
+__global__ __launch_bounds__(BS) void kb_cg_init(const int *__restrict__ ew_r0, const int *__restrict__ ew_r1,
+                                                 const double *__restrict__ f, double *__restrict__ r,
+                                                 double *__restrict__ u, double *__restrict__ p, double *partials) {
+  const int row = ew_r0[blockIdx.x] + threadIdx.x;
   double v[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) v[q] = 0;
-  if (row < m_r1[m]) {
+  if (row < ew_r1[blockIdx.x]) {
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const size_t i = (size_t)row * NR + q;
@@ -288,31 +401,43 @@ __global__ __launch_bounds__(BS) void kb_fin_init(const int *__restrict__ m_b0, 
   }
 }
 
-template <int LPR, int NR>
-__global__ __launch_bounds__(BS) void kb_cg_spmv(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
-                                                 const int *__restrict__ m_b0, int nm, const int *__restrict__ rp,
-                                                 const int *__restrict__ ci, const double *__restrict__ av,
+// q = A p over the mesh-major sliced ELL of the original grids (each mesh padded to whole
+// blocks of 4 slices, so no block straddles two meshes); partials of p.q per block
+template <int NR>
+__global__ __launch_bounds__(BS) void kb_cg_spmv(const int *__restrict__ srow, const int *__restrict__ soff,
+                                                 const int *__restrict__ scol, const double *__restrict__ sv,
                                                  const double *__restrict__ dg, const double *__restrict__ p,
                                                  double *__restrict__ q, BCtl c, double *partials) {
   if (*c.gdone) return;
-  const int m = find_seg(m_b0, nm, blockIdx.x);
-  const int t = (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
-  const int row = m_r0[m] + t / LPR, lane = t % LPR;
-  const bool act = row < m_r1[m];
-  double acc[NR], v[NR];
-  row_dot_nr<LPR, NR>(rp, ci, av, p, row, act, lane, acc);
+  const int s = bwave_slice(0);
+  const int lane = threadIdx.x & 63;
+  const int row = srow[(size_t)s * 64 + lane];
+  const int o0 = soff[s];
+  const int w = (soff[s + 1] - o0) >> 6;
+  double v[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) v[k] = 0;
-  if (act && lane == 0) {
-    const double d = dg[row];
+  VecR<NR, double> pv;
+  double di = 0;
+  auto pre = [&] {
+    const int rr = row < 0 ? 0 : row;
+    pv = reinterpret_cast<const VecR<NR, double> *>(p)[rr];
+    di = dg[rr];
+  };
+  auto post = [&](double acc[NR]) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) bpin(pv.v[k]);
+    bpin(di);
+    if (row < 0) return;
+    VecR<NR, double> o;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const size_t i = (size_t)row * NR + k;
-      const double qi = d * p[i] + acc[k];
-      q[i] = qi;
-      v[k] = p[i] * qi;
+      o.v[k] = di * pv.v[k] + acc[k];
+      v[k] = pv.v[k] * o.v[k];
     }
-  }
+    reinterpret_cast<VecR<NR, double> *>(q)[row] = o;
+  };
+  bsell_row<NR, double>(w, scol + o0 + lane, sv + o0 + lane, p, pre, post);
   bwrite<NR>(v, partials);
 }
 
@@ -336,27 +461,42 @@ __global__ __launch_bounds__(BS) void kb_fin_spmv(const int *__restrict__ m_b0, 
   }
 }
 
-template <int NR>
-__global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
-                                                 const int *__restrict__ m_b0, int nm, double *__restrict__ u,
+// u += alpha p, r -= alpha q per system; partials of ||r||^2. The same pass runs the first
+// colour pass of the next B_co on the new r in precision T: xf = r * id0 (0 off colour 0),
+// and in FP32 also bf = (float) r.
+template <int NR, class T>
+__global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ ew_m, const int *__restrict__ ew_r0,
+                                                 const int *__restrict__ ew_r1, double *__restrict__ u,
                                                  double *__restrict__ r, const double *__restrict__ p,
-                                                 const double *__restrict__ q, BCtl c, double *partials) {
+                                                 const double *__restrict__ q, BCtl c, double *partials,
+                                                 const T *__restrict__ id0, T *__restrict__ bf, T *__restrict__ xf) {
   if (*c.gdone) return;
-  const int m = find_seg(m_b0, nm, blockIdx.x);
-  const int row = m_r0[m] + (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
+  const int m = ew_m[blockIdx.x];
+  const int row = ew_r0[blockIdx.x] + threadIdx.x;
+  const bool act = row < ew_r1[blockIdx.x];
+  const T d = act ? id0[row] : T(0);
   double v[NR];
+  VecR<NR, T> bo, xo;
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     v[k] = 0;
+    if (!act) continue;
     const int sys = m * NR + k;
-    if (row < m_r1[m] && !c.dn[sys]) {
-      const size_t i = (size_t)row * NR + k;
+    const size_t i = (size_t)row * NR + k;
+    double ri = r[i];
+    if (!c.dn[sys]) {
       const double a = c.alpha[sys];
       u[i] += a * p[i];
-      const double ri = r[i] - a * q[i];
+      ri = ri - a * q[i];
       r[i] = ri;
       v[k] = ri * ri;
     }
+    bo.v[k] = (T)ri;
+    xo.v[k] = d != T(0) ? bo.v[k] * d : T(0);
+  }
+  if (act) {
+    if constexpr (sizeof(T) == 4) reinterpret_cast<VecR<NR, T> *>(bf)[row] = bo;
+    reinterpret_cast<VecR<NR, T> *>(xf)[row] = xo;
   }
   bwrite<NR>(v, partials);
 }
@@ -383,17 +523,17 @@ __global__ __launch_bounds__(BS) void kb_fin_axpy(const int *__restrict__ m_b0, 
 }
 
 template <int NR, class T>
-__global__ __launch_bounds__(BS) void kb_cg_rz(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
-                                               const int *__restrict__ m_b0, int nm, const double *__restrict__ r,
-                                               const T *__restrict__ z, BCtl c, double *partials) {
+__global__ __launch_bounds__(BS) void kb_cg_rz(const int *__restrict__ ew_r0, const int *__restrict__ ew_r1,
+                                               const double *__restrict__ r, const T *__restrict__ z, BCtl c,
+                                               double *partials) {
   if (*c.gdone) return;
-  const int m = find_seg(m_b0, nm, blockIdx.x);
-  const int row = m_r0[m] + (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
+  const int row = ew_r0[blockIdx.x] + threadIdx.x;
+  const bool act = row < ew_r1[blockIdx.x];
   double v[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const size_t i = (size_t)row * NR + k;
-    v[k] = row < m_r1[m] ? r[i] * (double)z[i] : 0.0;
+    v[k] = act ? r[i] * (double)z[i] : 0.0;
   }
   bwrite<NR>(v, partials);
 }
@@ -424,13 +564,13 @@ __global__ __launch_bounds__(BS) void kb_fin_rz(const int *__restrict__ m_b0, co
 }
 
 template <int NR, class T>
-__global__ __launch_bounds__(BS) void kb_cg_p(const int *__restrict__ m_r0, const int *__restrict__ m_r1,
-                                              const int *__restrict__ m_b0, int nm, const T *__restrict__ z,
+__global__ __launch_bounds__(BS) void kb_cg_p(const int *__restrict__ ew_m, const int *__restrict__ ew_r0,
+                                              const int *__restrict__ ew_r1, const T *__restrict__ z,
                                               double *__restrict__ p, BCtl c) {
   if (*c.gdone) return;
-  const int m = find_seg(m_b0, nm, blockIdx.x);
-  const int row = m_r0[m] + (blockIdx.x - m_b0[m]) * BS + threadIdx.x;
-  if (row >= m_r1[m]) return;
+  const int m = ew_m[blockIdx.x];
+  const int row = ew_r0[blockIdx.x] + threadIdx.x;
+  if (row >= ew_r1[blockIdx.x]) return;
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const int sys = m * NR + k;
@@ -542,19 +682,27 @@ struct SegTable {  // rows [r0, r1) per segment; first block of each segment (pr
   int *r0 = nullptr, *r1 = nullptr, *b0 = nullptr, *c0 = nullptr;
 };
 
+// sliced ELL of a merged matrix; slice groups (colour classes, or meshes) in cslice
+struct BSell {
+  int nrows = 0, ncols = 0, nslices = 0;
+  int64_t nnz = 0, entries = 0;
+  std::vector<int> cslice{0};
+  int *srow = nullptr, *soff = nullptr, *scol = nullptr;
+  double *sv64 = nullptr;
+  float *sv32 = nullptr;
+};
+
 struct BLevel {
   int nrows = 0;         // all rows (smoothing meshes, then bottom meshes)
   int nsmooth = 0;       // rows of smoothing meshes (a prefix)
   std::vector<int> mesh; // meshes present; smoothing first
   std::vector<int> off;  // row offset of each present mesh
-  std::vector<SegTable> colour;  // colour passes over smoothing meshes (built for the matrix LPR)
-  SegTable first;        // mesh segments with colour-0 ends (1 row per thread)
-  BCsr A;                // off-diagonal, smoothing rows
-  double *dg64 = nullptr, *id64 = nullptr;
-  float *dg32 = nullptr, *id32 = nullptr;
+  BSell sell;            // off-diagonal part of the smoothing rows; group c = colour c of every mesh
+  double *dg64 = nullptr, *id64 = nullptr, *id0_64 = nullptr;  // a_ii, 1/a_ii, 1/a_ii on colour 0 else 0
+  float *dg32 = nullptr, *id32 = nullptr, *id0_32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
   float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
-  BCsr P, PT;            // P: rows = smoothing rows, cols = rows of level k+1
+  BSell P, PT;           // P: rows = smoothing rows, cols = rows of level k+1
   // bottom meshes
   int nbottom = 0;
   int *bt_rowpref = nullptr, *bt_nc = nullptr, *bt_voff = nullptr;
@@ -571,8 +719,13 @@ struct BatchDevice {
   std::vector<int64_t> dof_off;   // prefix of n_m (user vectors, per rhs block)
   // fine level
   BLevel fine;                    // nsmooth = nrows
-  SegTable fine_sp, fine_ew;      // per-mesh block tables for SpMV-type / element-wise CG kernels
-  BCsr Pi, PiT;
+  BCsr fineA;                     // CSR of the original grids (true residual, restart)
+  SegTable fine_sp;               // per-mesh row-group blocks for the CSR kernels
+  BSell cg_sell;                  // mesh-major sliced ELL (whole 4-slice blocks per mesh) for q = A p
+  int *cg_b0 = nullptr;           // first block of each mesh in cg_sell (nm + 1)
+  int ew_blocks = 0;              // element-wise blocks: (mesh, 256-row chunk)
+  int *ew_m = nullptr, *ew_r0 = nullptr, *ew_r1 = nullptr, *ew_b0 = nullptr;
+  BSell Pi, PiT;
   int *row_stride = nullptr;      // gather/scatter
   int64_t *row_src0[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per NR (index NR)
   std::vector<BLevel> aux;        // merged level k = 0..K
@@ -672,27 +825,83 @@ static void bupload_csr(BatchDevice *dv, const HMat &H, BCsr &D) {
   D.lpr = pick_lpr(D.nnz, D.nrows);
 }
 
-static SegTable make_segs(BatchDevice *dv, const std::vector<int> &r0, const std::vector<int> &r1,
-                          const std::vector<int> *c0, int rows_per_block) {
-  SegTable S;
-  std::vector<int> a, b, blk, cc;
-  int nb = 0;
-  for (size_t i = 0; i < r0.size(); ++i) {
-    if (r1[i] <= r0[i]) continue;
-    a.push_back(r0[i]);
-    b.push_back(r1[i]);
-    if (c0) cc.push_back((*c0)[i]);
-    blk.push_back(nb);
-    nb += (r1[i] - r0[i] + rows_per_block - 1) / rows_per_block;
+// Sliced ELL of H over row-range groups: inside a range, windows of 256 rows sorted by length
+// (longest first, stable), 64 rows per slice. pad_blocks: every group ends on a whole block of
+// 4 slices (at least one block), so blocks never straddle groups; block0 gets the first block
+// of each group.
+static void bsell_build(BatchDevice *dv, const HMat &H, const std::vector<std::vector<std::pair<int, int>>> &groups,
+                        bool pad_blocks, BSell &S, std::vector<int> *block0 = nullptr) {
+  std::vector<int> srow, soff{0}, scol, idx;
+  std::vector<double> sv;
+  S.cslice.assign(1, 0);
+  if (block0) block0->assign(1, 0);
+  auto len = [&](int r) { return H.rp[r + 1] - H.rp[r]; };
+  auto empty_slice = [&]() {
+    for (int j = 0; j < 64; ++j) srow.push_back(-1);
+    soff.push_back(soff.back());
+  };
+  for (const auto &g : groups) {
+    const size_t first = srow.size() / 64;
+    for (const auto &rg : g) {
+      for (int w0 = rg.first; w0 < rg.second; w0 += 256) {
+        const int w1 = std::min(w0 + 256, rg.second);
+        idx.resize(w1 - w0);
+        std::iota(idx.begin(), idx.end(), w0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return len(x) > len(y); });
+        for (size_t a = 0; a < idx.size(); a += 64) {
+          const size_t e = std::min(a + 64, idx.size());
+          int wmax = 0;
+          for (size_t i = a; i < e; ++i) wmax = std::max(wmax, len(idx[i]));
+          const int base = soff.back();
+          scol.resize(base + 64 * wmax);
+          sv.resize(base + 64 * wmax);
+          for (int lane = 0; lane < 64; ++lane) {
+            const int row = a + lane < e ? idx[a + lane] : -1;
+            srow.push_back(row);
+            for (int k = 0; k < wmax; ++k) {
+              int cc = 0;  // padding: a valid column with value 0
+              double v = 0.0;
+              if (row >= 0 && k < len(row)) {
+                cc = H.ci[H.rp[row] + k];
+                v = H.v[H.rp[row] + k];
+              } else if (row >= 0 && len(row) > 0) {
+                cc = H.ci[H.rp[row]];
+              } else if (a < e && len(idx[a]) > 0) {
+                cc = H.ci[H.rp[idx[a]]];  // empty lane: a column of the slice's first row
+              }
+              scol[base + 64 * k + lane] = cc;
+              sv[base + 64 * k + lane] = v;
+            }
+          }
+          soff.push_back(base + 64 * wmax);
+        }
+      }
+    }
+    if (pad_blocks) {
+      size_t ns = srow.size() / 64 - first;
+      if (ns == 0) {
+        empty_slice();
+        ns = 1;
+      }
+      while (ns % (BS / 64)) {
+        empty_slice();
+        ++ns;
+      }
+      block0->push_back((int)(srow.size() / 64 / (BS / 64)));
+    }
+    S.cslice.push_back((int)(srow.size() / 64));
   }
-  blk.push_back(nb);
-  S.nseg = (int)a.size();
-  S.nblocks = nb;
-  S.r0 = bupload(dv, a);
-  S.r1 = bupload(dv, b);
-  S.b0 = bupload(dv, blk);
-  if (c0) S.c0 = bupload(dv, cc);
-  return S;
+  S.nrows = H.nrows;
+  S.ncols = H.ncols;
+  S.nnz = (int64_t)H.ci.size();
+  S.nslices = (int)(srow.size() / 64);
+  S.entries = (int64_t)sv.size();
+  S.srow = bupload(dv, srow);
+  S.soff = bupload(dv, soff);
+  S.scol = bupload(dv, scol);
+  S.sv64 = bupload(dv, sv);
+  std::vector<float> sv32(sv.begin(), sv.end());
+  S.sv32 = bupload(dv, sv32);
 }
 
 // per-mesh block tables that keep every mesh's rows in blocks of its own (empty meshes keep
@@ -740,17 +949,29 @@ static void alloc_level_vectors(BatchDevice *dv, BLevel &L) {
   L.r32 = balloc<float>(dv, n);
 }
 
-static void upload_diag(BatchDevice *dv, BLevel &L, const std::vector<double> &diag) {
-  std::vector<double> inv(diag.size());
-  std::vector<float> d32(diag.begin(), diag.end()), i32(diag.size());
+// a_ii, 1/a_ii and the first-pass scale id0 (1/a_ii on colour-0 rows, 0 elsewhere and on the
+// rows of bottom meshes, which have no diagonal entry here) for all nrows rows
+static void upload_diag(BatchDevice *dv, BLevel &L, const std::vector<double> &diag,
+                        const std::vector<uint8_t> &colour0) {
+  const size_t n = std::max<size_t>(L.nrows, diag.size());
+  std::vector<double> d(n, 1.0), inv(n, 1.0), i0(n, 0.0);
   for (size_t i = 0; i < diag.size(); ++i) {
+    d[i] = diag[i];
     inv[i] = 1.0 / diag[i];
-    i32[i] = 1.0f / (float)diag[i];
+    if (colour0[i]) i0[i] = inv[i];
   }
-  L.dg64 = bupload(dv, diag);
+  std::vector<float> d32(n), i32(n), i032(n, 0.0f);
+  for (size_t i = 0; i < n; ++i) {
+    d32[i] = (float)d[i];
+    i32[i] = i < diag.size() ? 1.0f / (float)diag[i] : 1.0f;
+    if (i < diag.size() && colour0[i]) i032[i] = i32[i];
+  }
+  L.dg64 = bupload(dv, d);
   L.id64 = bupload(dv, inv);
+  L.id0_64 = bupload(dv, i0);
   L.dg32 = bupload(dv, d32);
   L.id32 = bupload(dv, i32);
+  L.id0_32 = bupload(dv, i032);
 }
 
 BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int ordinal) {
@@ -789,12 +1010,13 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       dv->dof_off[m + 1] = dv->dof_off[m] + h.n();
     }
     if (dv->dof_off[nm] * 4 > INT32_MAX) throw AsmgError{ASMG_EINVAL, "batch too large"};
-    // ---- fine level
+    // ---- fine level: mesh-major, colour-major inside a mesh
     {
       BLevel &F = dv->fine;
       HMat A;
       std::vector<double> diag;
-      std::vector<int> r0, r1, c0;
+      std::vector<uint8_t> c0flag;
+      std::vector<int> r0, r1;
       int off = 0;
       int C = 0;
       for (int m = 0; m < nm; ++m) {
@@ -804,30 +1026,49 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         C = std::max(C, (int)fine[m].coff.size() - 1);
         r0.push_back(off);
         r1.push_back(off + (int)H[m]->n());
-        c0.push_back(off + fine[m].coff[1]);
+        for (int64_t i = 0; i < H[m]->n(); ++i) c0flag.push_back(i < fine[m].coff[1]);
         off += (int)H[m]->n();
       }
       A.ncols = off;
       F.nrows = F.nsmooth = off;
-      bupload_csr(dv, A, F.A);
-      upload_diag(dv, F, diag);
+      bupload_csr(dv, A, dv->fineA);
+      upload_diag(dv, F, diag, c0flag);
       alloc_level_vectors(dv, F);
-      for (int c = 0; c < C; ++c) {
-        std::vector<int> a, b;
+      // Gauss-Seidel passes: group c = colour c of every mesh
+      std::vector<std::vector<std::pair<int, int>>> groups(C);
+      for (int c = 0; c < C; ++c)
         for (int m = 0; m < nm; ++m) {
           const auto &co = fine[m].coff;
-          if (c + 1 < (int)co.size()) {
-            a.push_back(F.off[m] + co[c]);
-            b.push_back(F.off[m] + co[c + 1]);
-          }
+          if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
         }
-        F.colour.push_back(make_segs(dv, a, b, nullptr, BS / F.A.lpr));
+      bsell_build(dv, A, groups, false, F.sell);
+      // CG products: group m = mesh m, whole blocks per mesh
+      std::vector<std::vector<std::pair<int, int>>> mg(nm);
+      for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
+      std::vector<int> b0;
+      bsell_build(dv, A, mg, true, dv->cg_sell, &b0);
+      dv->cg_b0 = bupload(dv, b0);
+      dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
+      // element-wise blocks: 256-row chunks of each mesh (one block for an empty mesh)
+      std::vector<int> em, e0, e1, eb{0};
+      for (int m = 0; m < nm; ++m) {
+        int r = r0[m];
+        do {
+          em.push_back(m);
+          e0.push_back(r);
+          e1.push_back(std::min(r + BS, r1[m]));
+          r += BS;
+        } while (r < r1[m]);
+        eb.push_back((int)em.size());
       }
-      F.first = make_segs(dv, r0, r1, &c0, BS);
-      dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / F.A.lpr);
-      dv->fine_ew = make_mesh_blocks(dv, r0, r1, BS);
+      dv->ew_blocks = (int)em.size();
+      dv->ew_m = bupload(dv, em);
+      dv->ew_r0 = bupload(dv, e0);
+      dv->ew_r1 = bupload(dv, e1);
+      dv->ew_b0 = bupload(dv, eb);
     }
-    // ---- auxiliary levels k = 0..K
+    // ---- auxiliary levels k = 0..K: smoothing meshes (mesh-major, colour-major inside a mesh), then
+    // the meshes whose bottom level this is
     dv->aux.resize(K + 1);
     for (int k = 0; k <= K; ++k) {
       BLevel &L = dv->aux[k];
@@ -840,7 +1081,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       int off = 0;
       HMat A;
       std::vector<double> diag;
-      std::vector<int> r0, r1, c0;
+      std::vector<uint8_t> c0flag;
       int C = 0;
       for (int m : sm) {
         L.mesh.push_back(m);
@@ -848,28 +1089,19 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         const int l = H[m]->J - k;
         append_rows(A, H[m]->Al.at(l), lev[m][k].perm, &lev[m][k].iperm, off, true, &diag);
         C = std::max(C, (int)lev[m][k].coff.size() - 1);
-        r0.push_back(off);
         const int nl = (int)H[m]->Al.at(l).nrows;
-        r1.push_back(off + nl);
-        c0.push_back(off + lev[m][k].coff[1]);
+        for (int i = 0; i < nl; ++i) c0flag.push_back(i < lev[m][k].coff[1]);
         off += nl;
       }
       L.nsmooth = off;
       A.ncols = off;
-      bupload_csr(dv, A, L.A);
-      upload_diag(dv, L, diag);
-      for (int c = 0; c < C; ++c) {
-        std::vector<int> a, b;
+      std::vector<std::vector<std::pair<int, int>>> groups(C);
+      for (int c = 0; c < C; ++c)
         for (size_t i = 0; i < sm.size(); ++i) {
           const auto &co = lev[sm[i]][k].coff;
-          if (c + 1 < (int)co.size()) {
-            a.push_back(L.off[i] + co[c]);
-            b.push_back(L.off[i] + co[c + 1]);
-          }
+          if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
         }
-        L.colour.push_back(make_segs(dv, a, b, nullptr, BS / L.A.lpr));
-      }
-      L.first = make_segs(dv, r0, r1, &c0, BS);
+      bsell_build(dv, A, groups, false, L.sell);
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
       std::vector<int64_t> moff;
@@ -886,6 +1118,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         off += nc;
       }
       L.nrows = off;
+      upload_diag(dv, L, diag, c0flag);
       L.nbottom = (int)bt.size();
       L.bottom_rows = pref.back();
       L.bt_rowpref = bupload(dv, pref);
@@ -911,8 +1144,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         append_rows(P, H[m]->P.at(l), lev[m][k].perm, cmap, Lc.off[j], false, nullptr);
       }
       P.ncols = Lc.nrows;
-      bupload_csr(dv, P, L.P);
-      bupload_csr(dv, htranspose(P), L.PT);
+      const HMat PT = htranspose(P);
+      bsell_build(dv, P, {{{0, P.nrows}}}, false, L.P);
+      bsell_build(dv, PT, {{{0, PT.nrows}}}, false, L.PT);
     }
     // ---- Pi (fine rows -> merged level 0 rows)
     {
@@ -925,8 +1159,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
       }
       Pi.ncols = L0.nrows;
-      bupload_csr(dv, Pi, dv->Pi);
-      bupload_csr(dv, htranspose(Pi), dv->PiT);
+      const HMat PiT = htranspose(Pi);
+      bsell_build(dv, Pi, {{{0, Pi.nrows}}}, false, dv->Pi);
+      bsell_build(dv, PiT, {{{0, PiT.nrows}}}, false, dv->PiT);
     }
     // ---- gather/scatter maps: internal fine row -> user offset of (mesh, rhs 0, dof), stride n_m
     {
@@ -952,7 +1187,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
     dv->p = balloc<double>(dv, nv);
     dv->q = balloc<double>(dv, nv);
     const int ns = nm * 4;
-    dv->partials = balloc<double>(dv, (int64_t)std::max(dv->fine_sp.nblocks, dv->fine_ew.nblocks) * 4);
+    const int64_t nblocks_max = std::max<int64_t>({(int64_t)dv->fine_sp.nblocks, (int64_t)dv->ew_blocks,
+                                                   (int64_t)dv->cg_sell.nslices / (BS / 64)});
+    dv->partials = balloc<double>(dv, nblocks_max * 4);
     double *sc = balloc<double>(dv, (int64_t)ns * 9);
     HIPCHECK(hipMemset(sc, 0, (size_t)ns * 9 * sizeof(double)));
     dv->ctl.rho = sc;
@@ -1031,122 +1268,136 @@ struct BV<float> {
   static const float *inv(BLevel &L) { return L.inv32; }
 };
 
-static inline double bcsr_bytes(const BCsr &A, int s) { return (double)A.nnz * (s + 4) + 4.0 * (A.nrows + 1); }
+static inline double bsell_bytes(const BSell &A, int s) { return (double)A.nnz * (s + 4) + 4.0 * (A.nrows + 1); }
 
+template <class T>
+static const T *bsv(const BSell &S);
+template <>
+const double *bsv<double>(const BSell &S) { return S.sv64; }
+template <>
+const float *bsv<float>(const BSell &S) { return S.sv32; }
+
+template <class T>
+static const T *bid0(const BLevel &L);
+template <>
+const double *bid0<double>(const BLevel &L) { return L.id0_64; }
+template <>
+const float *bid0<float>(const BLevel &L) { return L.id0_32; }
+
+// Gauss-Seidel sweep over the colour groups of L. `first_done`: the sweep starts from zero and
+// its colour-0 pass was run by the kernel that produced b.
 template <int NR, class T>
-static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool forward, const int *done,
+static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool first_done, bool forward,
                     hipStream_t s) {
   if (L.nsmooth == 0) return;
   T *x = BV<T>::x(L);
-  const int C = (int)L.colour.size();
+  const BSell &S = L.sell;
+  const int C = (int)S.cslice.size() - 1;
   auto pass = [&](int c) {
-    const SegTable &S = L.colour[c];
-    if (S.nblocks == 0) return;
-    with_lpr(L.A.lpr, [&](auto cc) {
-      constexpr int LP = decltype(cc)::value;
-      hipLaunchKernelGGL((kb_gs<LP, NR, T>), dim3(S.nblocks), dim3(BS), 0, s, S.r0, S.r1, S.b0, S.nseg, L.A.rp,
-                         L.A.ci, BV<T>::v(L.A), BV<T>::id(L), b, x, done);
-    });
+    const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
+    if (s1 <= s0) return;
+    hipLaunchKernelGGL((kb_sell<0, NR, T>), dim3(nblk((int64_t)(s1 - s0) * 64)), dim3(BS), 0, s, s0, s1, S.srow,
+                       S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr);
   };
   if (forward) {
     int c = 0;
     if (from_zero) {
-      hipLaunchKernelGGL((kb_gs_first<NR, T>), dim3(L.first.nblocks), dim3(BS), 0, s, L.first.r0, L.first.c0,
-                         L.first.r1, L.first.b0, L.first.nseg, b, BV<T>::id(L), x, done);
+      if (!first_done)
+        hipLaunchKernelGGL((kb_first<NR, T>), dim3(nblk(L.nsmooth)), dim3(BS), 0, s, L.nsmooth, b, bid0<T>(L), x);
       c = 1;
     }
     for (; c < C; ++c) pass(c);
   } else {
     for (int c = C - 1; c >= 0; --c) pass(c);
   }
-  if (dv->count_bytes) dv->bytes += bcsr_bytes(L.A, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
+  if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
 }
 
 template <int NR, class T>
-static void b_residual(BatchDevice *dv, BLevel &L, const T *b, const int *done, hipStream_t s) {
+static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   if (L.nsmooth == 0) return;
-  with_lpr(L.A.lpr, [&](auto cc) {
-    constexpr int LP = decltype(cc)::value;
-    hipLaunchKernelGGL((kb_residual<LP, NR, T>), dim3(nblk((int64_t)L.nsmooth * LP)), dim3(BS), 0, s, L.nsmooth,
-                       L.A.rp, L.A.ci, BV<T>::v(L.A), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), done);
-  });
-  if (dv->count_bytes) dv->bytes += bcsr_bytes(L.A, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
+  const BSell &S = L.sell;
+  hipLaunchKernelGGL((kb_sell<1, NR, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, 0, S.nslices, S.srow,
+                     S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L));
+  if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
 }
 
-template <int NR, int ADD, class T>
-static void b_spmv(BatchDevice *dv, const BCsr &A, const T *x, T *y, const int *done, hipStream_t s) {
+// y = A x (ADD 0) or y += A x (ADD 1); FIRST: y is level Lt's right-hand side and the first colour
+// pass on Lt runs in the same kernel
+template <int NR, int ADD, int FIRST, class T>
+static void b_spmv(BatchDevice *dv, const BSell &A, const T *x, T *y, BLevel *Lt, hipStream_t s) {
   if (A.nrows == 0) return;
-  with_lpr(A.lpr, [&](auto cc) {
-    constexpr int LP = decltype(cc)::value;
-    hipLaunchKernelGGL((kb_spmv<LP, NR, ADD, T>), dim3(nblk((int64_t)A.nrows * LP)), dim3(BS), 0, s, A.nrows, A.rp,
-                       A.ci, BV<T>::v(A), x, y, done);
-  });
+  hipLaunchKernelGGL((kb_sell_spmv<ADD, FIRST, NR, T>), dim3(nblk((int64_t)A.nslices * 64)), dim3(BS), 0, s,
+                     A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y, FIRST ? bid0<T>(*Lt) : (const T *)nullptr,
+                     FIRST ? BV<T>::x(*Lt) : (T *)nullptr);
   if (dv->count_bytes)
-    dv->bytes += bcsr_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD) * (double)A.nrows);
+    dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD + FIRST) * (double)A.nrows) +
+                 (FIRST ? (double)sizeof(T) * A.nrows : 0.0);
 }
 
 template <int NR, class T>
-static void b_vcycle(BatchDevice *dv, int k, const int *done, hipStream_t s) {
+static void b_vcycle(BatchDevice *dv, int k, hipStream_t s) {
   BLevel &L = dv->aux[k];
   const T *b = BV<T>::b(L);
   if (L.nbottom > 0 && L.bottom_rows > 0) {
     hipLaunchKernelGGL((kb_gemv<NR, T>), dim3(nblk((int64_t)L.bottom_rows * 64)), dim3(BS), 0, s, L.bt_rowpref,
-                       L.nbottom, L.bt_nc, L.bt_moff, L.bt_voff, BV<T>::inv(L), b, BV<T>::x(L), done);
+                       L.nbottom, L.bt_nc, L.bt_moff, L.bt_voff, BV<T>::inv(L), b, BV<T>::x(L));
   }
   if (L.nsmooth == 0) return;
-  for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, it == 0, true, done, s);
-  b_residual<NR, T>(dv, L, b, done, s);
+  for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, it == 0, true, true, s);
+  b_residual<NR, T>(dv, L, b, s);
   BLevel &Lc = dv->aux[k + 1];
-  b_spmv<NR, 0, T>(dv, L.PT, BV<T>::r(L), BV<T>::b(Lc), done, s);
-  b_vcycle<NR, T>(dv, k + 1, done, s);
-  b_spmv<NR, 1, T>(dv, L.P, BV<T>::x(Lc), BV<T>::x(L), done, s);
-  for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, false, false, done, s);
+  b_spmv<NR, 0, 1, T>(dv, L.PT, BV<T>::r(L), BV<T>::b(Lc), &Lc, s);
+  b_vcycle<NR, T>(dv, k + 1, s);
+  b_spmv<NR, 1, 0, T>(dv, L.P, BV<T>::x(Lc), BV<T>::x(L), nullptr, s);
+  for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, false, false, false, s);
 }
 
-// z = B_co r for every system; r (FP64, internal) -> fine.x (precision T)
+// z = B_co r for every system; r (FP64, internal) -> fine.x (precision T). `first_done`: the CG
+// update already ran the first colour pass on the original grids (and the FP32 rounding of r).
 template <int NR, class T>
-static void b_apply(BatchDevice *dv, const double *r, const int *done, hipStream_t s) {
+static void b_apply(BatchDevice *dv, const double *r, bool first_done, hipStream_t s) {
   BLevel &F = dv->fine;
   const T *b;
   if constexpr (sizeof(T) == 8) {
     b = r;
   } else {
-    hipLaunchKernelGGL((kb_cvt<NR>), dim3(nblk((int64_t)F.nrows * NR)), dim3(BS), 0, s, F.nrows, r, F.b32, done);
+    if (!first_done) {
+      hipLaunchKernelGGL((kb_first_cvt<NR>), dim3(nblk(F.nrows)), dim3(BS), 0, s, F.nrows, r, F.id0_32, F.b32, F.x32);
+      first_done = true;
+    }
     b = F.b32;
   }
-  for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, it == 0, true, done, s);
-  b_residual<NR, T>(dv, F, b, done, s);
-  b_spmv<NR, 0, T>(dv, dv->PiT, BV<T>::r(F), BV<T>::b(dv->aux[0]), done, s);
-  b_vcycle<NR, T>(dv, 0, done, s);
-  b_spmv<NR, 1, T>(dv, dv->Pi, BV<T>::x(dv->aux[0]), BV<T>::x(F), done, s);
-  for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, false, false, done, s);
+  for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, it == 0, first_done, true, s);
+  b_residual<NR, T>(dv, F, b, s);
+  b_spmv<NR, 0, 1, T>(dv, dv->PiT, BV<T>::r(F), BV<T>::b(dv->aux[0]), &dv->aux[0], s);
+  b_vcycle<NR, T>(dv, 0, s);
+  b_spmv<NR, 1, 0, T>(dv, dv->Pi, BV<T>::x(dv->aux[0]), BV<T>::x(F), nullptr, s);
+  for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, false, false, false, s);
 }
 
 template <int NR, class T>
-static void b_tail(BatchDevice *dv, hipStream_t s) {
-  const SegTable &E = dv->fine_ew;
-  b_apply<NR, T>(dv, dv->r, dv->ctl.gdone, s);
+static void b_tail(BatchDevice *dv, hipStream_t s, bool first_done) {
+  b_apply<NR, T>(dv, dv->r, first_done, s);
   const T *z = BV<T>::x(dv->fine);
-  hipLaunchKernelGGL((kb_cg_rz<NR, T>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->r, z, dv->ctl,
+  hipLaunchKernelGGL((kb_cg_rz<NR, T>), dim3(dv->ew_blocks), dim3(BS), 0, s, dv->ew_r0, dv->ew_r1, dv->r, z, dv->ctl,
                      dv->partials);
-  hipLaunchKernelGGL((kb_fin_rz<NR>), dim3(dv->nm), dim3(BS), 0, s, E.b0, dv->partials, dv->ctl);
-  hipLaunchKernelGGL((kb_cg_p<NR, T>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, z, dv->p, dv->ctl);
+  hipLaunchKernelGGL((kb_fin_rz<NR>), dim3(dv->nm), dim3(BS), 0, s, dv->ew_b0, dv->partials, dv->ctl);
+  hipLaunchKernelGGL((kb_cg_p<NR, T>), dim3(dv->ew_blocks), dim3(BS), 0, s, dv->ew_m, dv->ew_r0, dv->ew_r1, z, dv->p,
+                     dv->ctl);
 }
 
 template <int NR, class T>
 static void b_iteration(BatchDevice *dv, hipStream_t s) {
   BLevel &F = dv->fine;
-  const SegTable &Sp = dv->fine_sp, &E = dv->fine_ew;
-  with_lpr(F.A.lpr, [&](auto cc) {
-    constexpr int LP = decltype(cc)::value;
-    hipLaunchKernelGGL((kb_cg_spmv<LP, NR>), dim3(Sp.nblocks), dim3(BS), 0, s, Sp.r0, Sp.r1, Sp.b0, Sp.nseg, F.A.rp,
-                       F.A.ci, F.A.v64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
-  });
-  hipLaunchKernelGGL((kb_fin_spmv<NR>), dim3(dv->nm), dim3(BS), 0, s, Sp.b0, dv->partials, dv->ctl);
-  hipLaunchKernelGGL((kb_cg_axpy<NR>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->u, dv->r, dv->p,
-                     dv->q, dv->ctl, dv->partials);
-  hipLaunchKernelGGL((kb_fin_axpy<NR>), dim3(dv->nm), dim3(BS), 0, s, E.b0, dv->partials, dv->ctl);
-  b_tail<NR, T>(dv, s);
+  const BSell &Q = dv->cg_sell;
+  hipLaunchKernelGGL((kb_cg_spmv<NR>), dim3(Q.nslices / (BS / 64)), dim3(BS), 0, s, Q.srow, Q.soff, Q.scol, Q.sv64,
+                     F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
+  hipLaunchKernelGGL((kb_fin_spmv<NR>), dim3(dv->nm), dim3(BS), 0, s, dv->cg_b0, dv->partials, dv->ctl);
+  hipLaunchKernelGGL((kb_cg_axpy<NR, T>), dim3(dv->ew_blocks), dim3(BS), 0, s, dv->ew_m, dv->ew_r0, dv->ew_r1, dv->u,
+                     dv->r, dv->p, dv->q, dv->ctl, dv->partials, bid0<T>(F), BV<T>::b(F), BV<T>::x(F));
+  hipLaunchKernelGGL((kb_fin_axpy<NR>), dim3(dv->nm), dim3(BS), 0, s, dv->ew_b0, dv->partials, dv->ctl);
+  b_tail<NR, T>(dv, s, true);
 }
 
 template <int NR, class T>
@@ -1172,18 +1423,19 @@ template <int NR, class T>
 static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
   const int nm = dv->nm, ns = nm * NR;
-  const SegTable &E = dv->fine_ew, &Sp = dv->fine_sp;
+  const SegTable &Sp = dv->fine_sp;
+  const BCsr &FA = dv->fineA;
   BLevel &F = dv->fine;
   // per-system ints (4 arrays sized for 4 right-hand sides), mesh tickets, active count, done flag
   HIPCHECK(hipMemsetAsync(dv->ctl_ints, 0, ((size_t)nm * 4 * 4 + nm + 2) * sizeof(int), s));
-  hipLaunchKernelGGL((kb_cg_init<NR>), dim3(E.nblocks), dim3(BS), 0, s, E.r0, E.r1, E.b0, E.nseg, dv->f, dv->r, dv->u,
+  hipLaunchKernelGGL((kb_cg_init<NR>), dim3(dv->ew_blocks), dim3(BS), 0, s, dv->ew_r0, dv->ew_r1, dv->f, dv->r, dv->u,
                      dv->p, dv->partials);
-  hipLaunchKernelGGL((kb_fin_init<NR>), dim3(nm), dim3(BS), 0, s, E.b0, dv->partials, tol, dv->ctl);
+  hipLaunchKernelGGL((kb_fin_init<NR>), dim3(nm), dim3(BS), 0, s, dv->ew_b0, dv->partials, tol, dv->ctl);
   int hst[2];
   HIPCHECK(hipMemcpyAsync(hst, dv->ctl.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   if (hst[0] == 0) HIPCHECK(hipMemcpyAsync(dv->ctl.gdone, &(hst[1] = 1), sizeof(int), hipMemcpyHostToDevice, s));
-  b_tail<NR, T>(dv, s);
+  b_tail<NR, T>(dv, s, false);
   const int first = dv->last_iters[pi][NR] > 1 ? dv->last_iters[pi][NR] - 1 : 0;
   if (first > 0) b_launch_iterations<NR, T>(dv, std::min(first, dv->maxit), s);
   const int Kc = dv->last_iters[pi][NR] > 0 ? 1 : 4;
@@ -1199,10 +1451,10 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
       b_launch_iterations<NR, T>(dv, Kc, s);
       continue;
     }
-    with_lpr(F.A.lpr, [&](auto cc) {
+    with_lpr(FA.lpr, [&](auto cc) {
       constexpr int LP = decltype(cc)::value;
       hipLaunchKernelGGL((kb_true_res<LP, NR>), dim3(Sp.nblocks), dim3(BS), 0, s, Sp.r0, Sp.r1, Sp.b0, Sp.nseg,
-                         F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f, dv->u, dv->partials);
+                         FA.rp, FA.ci, FA.v64, F.dg64, dv->f, dv->u, dv->partials);
     });
     hipLaunchKernelGGL((kb_fin_tr<NR>), dim3(nm), dim3(BS), 0, s, Sp.b0, dv->partials, dv->ctl);
     HIPCHECK(hipMemcpyAsync(tr.data(), dv->ctl.tr, ns * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1219,10 +1471,10 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
     if (nre > 0 && restarts < 3) {
       ++restarts;
       HIPCHECK(hipMemcpyAsync(dv->mask, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, s));
-      with_lpr(F.A.lpr, [&](auto cc) {
+      with_lpr(FA.lpr, [&](auto cc) {
         constexpr int LP = decltype(cc)::value;
         hipLaunchKernelGGL((kb_restart<LP, NR>), dim3(Sp.nblocks), dim3(BS), 0, s, Sp.r0, Sp.r1, Sp.b0, Sp.nseg,
-                           F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->mask);
+                           FA.rp, FA.ci, FA.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->mask);
       });
       // reopen the restarted systems: done = 0, first = 1, active = count, gdone = 0
       std::vector<int> dn(ns), fi(ns);
@@ -1239,7 +1491,7 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
       HIPCHECK(hipMemcpyAsync(dv->ctl.first, fi.data(), ns * sizeof(int), hipMemcpyHostToDevice, s));
       HIPCHECK(hipMemcpyAsync(dv->ctl.active, two, 2 * sizeof(int), hipMemcpyHostToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
-      b_tail<NR, T>(dv, s);
+      b_tail<NR, T>(dv, s, false);
       continue;
     }
     int rc = ASMG_OK, maxit = 0;
@@ -1292,9 +1544,9 @@ int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void 
   auto one = [&]() {
     const bool mixed = precision == ASMG_PREC_MIXED;
     switch (n_rhs) {
-      case 1: mixed ? b_apply<1, float>(dv, dv->f, dv->ctl.gdone + 1, s) : b_apply<1, double>(dv, dv->f, dv->ctl.gdone + 1, s); break;
-      case 2: mixed ? b_apply<2, float>(dv, dv->f, dv->ctl.gdone + 1, s) : b_apply<2, double>(dv, dv->f, dv->ctl.gdone + 1, s); break;
-      default: mixed ? b_apply<4, float>(dv, dv->f, dv->ctl.gdone + 1, s) : b_apply<4, double>(dv, dv->f, dv->ctl.gdone + 1, s); break;
+      case 1: mixed ? b_apply<1, float>(dv, dv->f, false, s) : b_apply<1, double>(dv, dv->f, false, s); break;
+      case 2: mixed ? b_apply<2, float>(dv, dv->f, false, s) : b_apply<2, double>(dv, dv->f, false, s); break;
+      default: mixed ? b_apply<4, float>(dv, dv->f, false, s) : b_apply<4, double>(dv, dv->f, false, s); break;
     }
   };
   HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)dv->fine.nrows * 4 * sizeof(double), s));
