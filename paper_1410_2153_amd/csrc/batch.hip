@@ -361,20 +361,22 @@ template <int NR>
 __global__ __launch_bounds__(BS) void kb_cg_init(const int *__restrict__ ew_r0, const int *__restrict__ ew_r1,
                                                  const double *__restrict__ f, double *__restrict__ r,
                                                  double *__restrict__ u, double *__restrict__ p, double *partials) {
+  using V = VecR<NR, double>;
   const int row = ew_r0[blockIdx.x] + threadIdx.x;
   double v[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) v[q] = 0;
   if (row < ew_r1[blockIdx.x]) {
+    const V fv = reinterpret_cast<const V *>(f)[row];
+    V z;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const size_t i = (size_t)row * NR + q;
-      const double fi = f[i];
-      r[i] = fi;
-      u[i] = 0.0;
-      p[i] = 0.0;
-      v[q] = fi * fi;
+      z.v[q] = 0.0;
+      v[q] = fv.v[q] * fv.v[q];
     }
+    reinterpret_cast<V *>(r)[row] = fv;
+    reinterpret_cast<V *>(u)[row] = z;
+    reinterpret_cast<V *>(p)[row] = z;
   }
   bwrite<NR>(v, partials);
 }
@@ -471,30 +473,34 @@ __global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ ew_m, c
                                                  const double *__restrict__ q, BCtl c, double *partials,
                                                  const T *__restrict__ id0, T *__restrict__ bf, T *__restrict__ xf) {
   if (*c.gdone) return;
+  using V = VecR<NR, double>;
   const int m = ew_m[blockIdx.x];
   const int row = ew_r0[blockIdx.x] + threadIdx.x;
   const bool act = row < ew_r1[blockIdx.x];
-  const T d = act ? id0[row] : T(0);
   double v[NR];
-  VecR<NR, T> bo, xo;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    v[k] = 0;
-    if (!act) continue;
-    const int sys = m * NR + k;
-    const size_t i = (size_t)row * NR + k;
-    double ri = r[i];
-    if (!c.dn[sys]) {
-      const double a = c.alpha[sys];
-      u[i] += a * p[i];
-      ri = ri - a * q[i];
-      r[i] = ri;
-      v[k] = ri * ri;
-    }
-    bo.v[k] = (T)ri;
-    xo.v[k] = d != T(0) ? bo.v[k] * d : T(0);
-  }
+  for (int k = 0; k < NR; ++k) v[k] = 0;
   if (act) {
+    const V al = reinterpret_cast<const V *>(c.alpha)[m];
+    const VecR<NR, int> dn = reinterpret_cast<const VecR<NR, int> *>(c.dn)[m];
+    const T d = id0[row];
+    V uv = reinterpret_cast<const V *>(u)[row];
+    V rv = reinterpret_cast<const V *>(r)[row];
+    const V pv = reinterpret_cast<const V *>(p)[row];
+    const V qv = reinterpret_cast<const V *>(q)[row];
+    VecR<NR, T> bo, xo;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (!dn.v[k]) {
+        uv.v[k] += al.v[k] * pv.v[k];
+        rv.v[k] = rv.v[k] - al.v[k] * qv.v[k];
+        v[k] = rv.v[k] * rv.v[k];
+      }
+      bo.v[k] = (T)rv.v[k];
+      xo.v[k] = d != T(0) ? bo.v[k] * d : T(0);
+    }
+    reinterpret_cast<V *>(u)[row] = uv;
+    reinterpret_cast<V *>(r)[row] = rv;
     if constexpr (sizeof(T) == 4) reinterpret_cast<VecR<NR, T> *>(bf)[row] = bo;
     reinterpret_cast<VecR<NR, T> *>(xf)[row] = xo;
   }
@@ -528,12 +534,14 @@ __global__ __launch_bounds__(BS) void kb_cg_rz(const int *__restrict__ ew_r0, co
                                                double *partials) {
   if (*c.gdone) return;
   const int row = ew_r0[blockIdx.x] + threadIdx.x;
-  const bool act = row < ew_r1[blockIdx.x];
   double v[NR];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const size_t i = (size_t)row * NR + k;
-    v[k] = act ? r[i] * (double)z[i] : 0.0;
+  for (int k = 0; k < NR; ++k) v[k] = 0;
+  if (row < ew_r1[blockIdx.x]) {
+    const VecR<NR, double> rv = reinterpret_cast<const VecR<NR, double> *>(r)[row];
+    const VecR<NR, T> zv = reinterpret_cast<const VecR<NR, T> *>(z)[row];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = rv.v[k] * (double)zv.v[k];
   }
   bwrite<NR>(v, partials);
 }
@@ -568,16 +576,18 @@ __global__ __launch_bounds__(BS) void kb_cg_p(const int *__restrict__ ew_m, cons
                                               const int *__restrict__ ew_r1, const T *__restrict__ z,
                                               double *__restrict__ p, BCtl c) {
   if (*c.gdone) return;
+  using V = VecR<NR, double>;
   const int m = ew_m[blockIdx.x];
   const int row = ew_r0[blockIdx.x] + threadIdx.x;
   if (row >= ew_r1[blockIdx.x]) return;
+  const V be = reinterpret_cast<const V *>(c.beta)[m];
+  const VecR<NR, int> dn = reinterpret_cast<const VecR<NR, int> *>(c.dn)[m];
+  const VecR<NR, T> zv = reinterpret_cast<const VecR<NR, T> *>(z)[row];
+  V pv = reinterpret_cast<const V *>(p)[row];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const int sys = m * NR + k;
-    if (c.dn[sys]) continue;
-    const size_t i = (size_t)row * NR + k;
-    p[i] = (double)z[i] + c.beta[sys] * p[i];
-  }
+  for (int k = 0; k < NR; ++k)
+    if (!dn.v[k]) pv.v[k] = (double)zv.v[k] + be.v[k] * pv.v[k];
+  reinterpret_cast<V *>(p)[row] = pv;
 }
 
 template <int LPR, int NR>
