@@ -171,7 +171,7 @@ __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, con
 }
 
 __device__ __forceinline__ int bwave_slice(int first) {
-  return first + (int)blockIdx.x * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  return first + xcd_block() * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
 // MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
@@ -327,13 +327,19 @@ struct BCtl {  // device pointers of the per-system scalars (arrays of n_meshes 
 // kernel with one block per mesh reduces that mesh's partials in a fixed order. No atomics
 // except the count of active systems.
 
+// block sums of the NR values into partials[blk] (blk = the block's logical index)
 template <int NR>
-__device__ __forceinline__ void bwrite(double v[NR], double *partials) {
+__device__ __forceinline__ void bwrite(double v[NR], double *partials, int blk) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) v[r] = block_sum(v[r]);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) partials[(size_t)blockIdx.x * NR + r] = v[r];
+    for (int r = 0; r < NR; ++r) partials[(size_t)blk * NR + r] = v[r];
+}
+
+template <int NR>
+__device__ __forceinline__ void bwrite(double v[NR], double *partials) {
+  bwrite<NR>(v, partials, (int)blockIdx.x);
 }
 
 template <int NR>
@@ -440,7 +446,7 @@ __global__ __launch_bounds__(BS) void kb_cg_spmv(const int *__restrict__ srow, c
     reinterpret_cast<VecR<NR, double> *>(q)[row] = o;
   };
   bsell_row<NR, double>(w, scol + o0 + lane, sv + o0 + lane, p, pre, post);
-  bwrite<NR>(v, partials);
+  bwrite<NR>(v, partials, xcd_block());  // the logical block of this block's slices
 }
 
 template <int NR>

@@ -44,6 +44,16 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
+// XCD-aware block index. Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b % 8),
+// and each XCD has its own L2. This bijection of [0, gridDim.x) gives XCD x a contiguous run of
+// logical blocks, so rows that are neighbours in the numbering (and gather the same entries of
+// x) are served by one L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int x = b & 7, i = b >> 3, per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // ---------------------------------------------------------------------------
 // sparse kernels
 // ---------------------------------------------------------------------------

@@ -152,7 +152,7 @@ __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, cons
 
 // wave-uniform slice index of this wave (scalar registers, so the slice header is a scalar load)
 __device__ __forceinline__ int wave_slice(int first) {
-  return first + (int)blockIdx.x * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  return first + xcd_block() * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
 // MODE 0: Gauss-Seidel pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii
