@@ -49,17 +49,15 @@ def load_workload(scale: float):
 
 
 def counter_traffic():
-    """HBM traffic per colour-pass launch from the committed counter summary, if the kernel source
+    """HBM traffic per colour-pass launch from the committed counter summary, if the kernel code
     has not changed since the counters were taken (else None)."""
-    import hashlib
+    from paper_1410_2153_amd.counters import source_key
     path = os.path.join(ROOT, "profiles", "traffic_k_sell_gs.json")
-    src = os.path.join(ROOT, "paper_1410_2153_amd", "csrc", "device.hip")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    return rec.get("traffic_bytes_per_launch") if rec.get("device_hip_sha256") == h else None
+    return rec.get("traffic_bytes_per_launch") if rec.get("device_hip_code_key") == source_key() else None
 
 
 def cpu_baseline(budget_s: float = 20.0):

@@ -8,8 +8,8 @@ Usage (after the two `rocprofv3 --pmc` runs of bench.py named in the output reco
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch. Each is scaled by the ratio of the
 bytes a plain device copy moves to what the same counter reads for that copy: the bench's
 `--copy-calibration` runs a 512 MiB copy, whose dispatch is the largest `__amd_rocclr_copyBuffer`
-in the run. The record is keyed by the SHA-256 of device.hip, so bench.py reports it only for
-the kernel source it was measured on.
+in the run. The record is keyed by the SHA-256 of device.hip with comments and whitespace
+removed (`source_key`), so bench.py reports it only for the kernel code it was measured on.
 """
 from __future__ import annotations
 
@@ -20,6 +20,18 @@ import os
 import sys
 
 KERNEL = "asmg::k_sell<0, double>"
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DEVICE_SRC = os.path.join(ROOT, "paper_1410_2153_amd", "csrc", "device.hip")
+
+
+def source_key(path=DEVICE_SRC):
+    """SHA-256 of a C++/HIP source with comments and whitespace removed (code changes only)."""
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = re.sub(r"\s+", "", text)
+    return hashlib.sha256(text.encode()).hexdigest()
 COPY_BYTES = 64 * 2 ** 20 * 8
 
 
@@ -41,8 +53,6 @@ def _per_dispatch(path, counter):
 
 
 def record(fetch_csv, write_csv):
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    src = os.path.join(root, "paper_1410_2153_amd", "csrc", "device.hip")
     f_kib, n, f_copy = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w_kib, n2, w_copy = _per_dispatch(write_csv, "WRITE_SIZE")
     f_scale = COPY_BYTES / (f_copy * 1024.0)
@@ -54,7 +64,7 @@ def record(fetch_csv, write_csv):
     return {
         "kernel": KERNEL,
         "workload": "graded 2-D Delaunay mesh, 1002722 vertices, FP64 solve",
-        "device_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "device_hip_code_key": source_key(),
         "dispatches": n,
         "fetch_kib_per_dispatch_raw": f_kib,
         "write_kib_per_dispatch_raw": w_kib,

@@ -3,20 +3,23 @@
 // Layout: every level (the original grid and the auxiliary levels above the
 // bottom) is renumbered colour-major (rows of colour 0 first, ascending unknown
 // id inside a colour), so one Gauss-Seidel colour pass is a contiguous row range.
-// Matrices are CSR with int32 row pointers and columns, the diagonal held apart
-// (diag and 1/diag), values in FP64 and FP32 copies. Transfers (Pi, Pi^T, P_l,
-// P_l^T) are stored explicitly in the internal numbering. The bottom level keeps
-// the unknown order and holds the explicit inverse of its matrix (from the
-// Cholesky factor built on the host).
+// Off-diagonal parts of the level matrices and the transfers (Pi, Pi^T, P_l,
+// P_l^T, stored explicitly in the internal numbering) are sliced ELL with 64-row
+// slices, one row per wave lane; the diagonal is held apart (diag and 1/diag);
+// values in FP64 and FP32 copies. The bottom level keeps the unknown order and
+// holds the explicit inverse of its matrix (from the Cholesky factor built on the
+// host), applied as a wave-per-row GEMV.
 //
-// Kernels: row-group CSR (LPR lanes per row, LPR in {2,4,8,16}, 256-thread
-// blocks) for the Gauss-Seidel colour pass, the residual and the transfer
-// products; wave-per-row dense GEMV at the bottom; fused CG vector kernels
-// whose block partial sums are reduced by the last block to finish (fixed
-// summation order, so results are reproducible run to run). Every kernel of an
-// iteration reads a device-side `done` flag first and returns if it is set, so
-// the host may enqueue several iterations ahead and the iteration count stays
-// exact.
+// A slice kernel is latency-bound on short colour passes, so its row product
+// issues all loads of a row before the first gather (three dependent round trips
+// per slice), and its blocks are remapped so that each XCD (own L2) takes a
+// contiguous run of slices. The first colour pass of a sweep from zero runs inside
+// the kernel that writes the level's right-hand side.
+//
+// PCG: reductions write one partial per block and a one-block finalize kernel sums
+// them in a fixed order (reproducible, no atomics); the CG kernels read a device
+// `done` flag and return when it is set, so the host may enqueue (replay a graph of)
+// several iterations ahead and the iteration count stays exact.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
