@@ -226,8 +226,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 3-D and adjoint workloads")
-    ap.add_argument("--batch-only", action="store_true",
-                    help="run only the batched workload and print its record (for profiling it alone)")
+    ap.add_argument("--only", choices=["batched", "cube3d", "adjoint"], default=None,
+                    help="run only this secondary workload and print its record (for profiling it alone)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
     ap.add_argument("--colouring", type=int, default=2,
@@ -242,8 +242,14 @@ def main():
 
     import paper_1410_2153_amd as A
     dev = torch.device("cuda:0")
-    if args.batch_only:
+    if args.only == "batched":
         print(json.dumps({"batched": batched(args.batch_meshes or 256, args.steps)}))
+        return
+    if args.only == "cube3d":
+        print(json.dumps({"cube3d": cube3d(args.steps, args.colouring)}))
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint(args.steps, args.colouring)}))
         return
     t0 = time.perf_counter()
     c = load_workload(args.scale)

@@ -120,37 +120,59 @@ __device__ __forceinline__ T sell_chunk(const int *__restrict__ cp, const T *__r
   return acc;
 }
 
-template <class T, class Pre, class Post>
+// Straight-line cases up to WMAX entries (16, or 32 for matrices with longer rows such as the
+// 3-D transfers); longer rows go in chunks of 8.
+template <class T, int WMAX = 16, class Pre, class Post>
 __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
                                          const T *__restrict__ x, Pre &pre, Post &post) {
   switch (w) {
-    case 0: pre(); post(T(0)); break;
-    case 1: sell_row_w<1>(cp, vp, x, pre, post); break;
-    case 2: sell_row_w<2>(cp, vp, x, pre, post); break;
-    case 3: sell_row_w<3>(cp, vp, x, pre, post); break;
-    case 4: sell_row_w<4>(cp, vp, x, pre, post); break;
-    case 5: sell_row_w<5>(cp, vp, x, pre, post); break;
-    case 6: sell_row_w<6>(cp, vp, x, pre, post); break;
-    case 7: sell_row_w<7>(cp, vp, x, pre, post); break;
-    case 8: sell_row_w<8>(cp, vp, x, pre, post); break;
-    case 9: sell_row_w<9>(cp, vp, x, pre, post); break;
-    case 10: sell_row_w<10>(cp, vp, x, pre, post); break;
-    case 11: sell_row_w<11>(cp, vp, x, pre, post); break;
-    case 12: sell_row_w<12>(cp, vp, x, pre, post); break;
-    case 13: sell_row_w<13>(cp, vp, x, pre, post); break;
-    case 14: sell_row_w<14>(cp, vp, x, pre, post); break;
-    case 15: sell_row_w<15>(cp, vp, x, pre, post); break;
-    case 16: sell_row_w<16>(cp, vp, x, pre, post); break;
-    default: {
-      // long rows: chunks of 8 entries, each with its loads issued together
-      pre();
-      T acc = 0;
-      int k = 0;
-      for (; k + 8 <= w; k += 8) acc += sell_chunk<8>(cp + k * 64, vp + k * 64, x);
-      for (; k < w; ++k) acc += vp[k * 64] * x[cp[k * 64]];
-      post(acc);
+    case 0: pre(); post(T(0)); return;
+    case 1: sell_row_w<1>(cp, vp, x, pre, post); return;
+    case 2: sell_row_w<2>(cp, vp, x, pre, post); return;
+    case 3: sell_row_w<3>(cp, vp, x, pre, post); return;
+    case 4: sell_row_w<4>(cp, vp, x, pre, post); return;
+    case 5: sell_row_w<5>(cp, vp, x, pre, post); return;
+    case 6: sell_row_w<6>(cp, vp, x, pre, post); return;
+    case 7: sell_row_w<7>(cp, vp, x, pre, post); return;
+    case 8: sell_row_w<8>(cp, vp, x, pre, post); return;
+    case 9: sell_row_w<9>(cp, vp, x, pre, post); return;
+    case 10: sell_row_w<10>(cp, vp, x, pre, post); return;
+    case 11: sell_row_w<11>(cp, vp, x, pre, post); return;
+    case 12: sell_row_w<12>(cp, vp, x, pre, post); return;
+    case 13: sell_row_w<13>(cp, vp, x, pre, post); return;
+    case 14: sell_row_w<14>(cp, vp, x, pre, post); return;
+    case 15: sell_row_w<15>(cp, vp, x, pre, post); return;
+    case 16: sell_row_w<16>(cp, vp, x, pre, post); return;
+    default: break;
+  }
+  if constexpr (WMAX > 16) {
+    switch (w) {
+      case 17: sell_row_w<17>(cp, vp, x, pre, post); return;
+      case 18: sell_row_w<18>(cp, vp, x, pre, post); return;
+      case 19: sell_row_w<19>(cp, vp, x, pre, post); return;
+      case 20: sell_row_w<20>(cp, vp, x, pre, post); return;
+      case 21: sell_row_w<21>(cp, vp, x, pre, post); return;
+      case 22: sell_row_w<22>(cp, vp, x, pre, post); return;
+      case 23: sell_row_w<23>(cp, vp, x, pre, post); return;
+      case 24: sell_row_w<24>(cp, vp, x, pre, post); return;
+      case 25: sell_row_w<25>(cp, vp, x, pre, post); return;
+      case 26: sell_row_w<26>(cp, vp, x, pre, post); return;
+      case 27: sell_row_w<27>(cp, vp, x, pre, post); return;
+      case 28: sell_row_w<28>(cp, vp, x, pre, post); return;
+      case 29: sell_row_w<29>(cp, vp, x, pre, post); return;
+      case 30: sell_row_w<30>(cp, vp, x, pre, post); return;
+      case 31: sell_row_w<31>(cp, vp, x, pre, post); return;
+      case 32: sell_row_w<32>(cp, vp, x, pre, post); return;
+      default: break;
     }
   }
+  // long rows: chunks of 8 entries, each with its loads issued together
+  pre();
+  T acc = 0;
+  int k = 0;
+  for (; k + 8 <= w; k += 8) acc += sell_chunk<8>(cp + k * 64, vp + k * 64, x);
+  for (; k < w; ++k) acc += vp[k * 64] * x[cp[k * 64]];
+  post(acc);
 }
 
 // wave-uniform slice index of this wave (scalar registers, so the slice header is a scalar load)
@@ -196,7 +218,7 @@ __global__ __launch_bounds__(BS) void k_sell(int s0, int s1, const int *__restri
 // FIRST (with ADD = 0): y is the right-hand side of a level whose smoothing starts from zero, and
 // the kernel also runs that first colour pass: xs_i = y_i / a_ii for rows i < c0 (colour 0),
 // xs_i = 0 for the other rows.
-template <int ADD, int FIRST, class T>
+template <int ADD, int FIRST, class T, int WMAX = 16>
 __global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
                                                   const int *__restrict__ scol, const T *__restrict__ sv,
                                                   const T *__restrict__ x, T *__restrict__ y, int c0,
@@ -220,7 +242,7 @@ __global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict_
     y[row] = ADD ? yi + acc : acc;
     if (FIRST) xs[row] = row < c0 ? acc * di : T(0);
   };
-  sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  sell_row<T, WMAX>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
 
 // dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
@@ -610,6 +632,7 @@ struct DCsr {
 
 struct DSell {
   int nslices = 0;
+  int wmax = 0;               // widest slice (entries per row)
   std::vector<int> cslice;    // slice range of each colour, C + 1 (host)
   int *srow = nullptr, *soff = nullptr, *scol = nullptr;
   double *sv64 = nullptr;
@@ -753,7 +776,8 @@ static HCsr transpose(const HCsr &A) {
 }
 
 static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
-                              std::vector<int> *slot_map = nullptr);
+                              std::vector<int> *slot_map = nullptr, int wround = 1,
+                              const std::vector<int> *order = nullptr);
 
 static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
   D.nrows = H.nrows;
@@ -774,14 +798,20 @@ static void upload_values(DCsr &D, const HCsr &H) {
   HIPCHECK(hipMemcpy(D.v32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
 }
 
-static void upload_transfer(Device *dv, const HCsr &H, DCsr &D) {
+// A transfer product may visit its rows in any order (each row is written once), so its slices
+// follow `order` (rows in a spatially coherent order: the level's Morton numbering, or Morton
+// order of the vertices on the original grid): neighbouring rows then gather neighbouring
+// entries of x, whereas the colour-major numbering would interleave four distant ranges.
+static void upload_transfer(Device *dv, const HCsr &H, DCsr &D, const std::vector<int> *order) {
   upload_csr(dv, H, D);
   dv->sells.emplace_back(new DSell());
   D.sell = dv->sells.back().get();
-  build_sell_ranges(dv, *D.sell, H, std::vector<int>{0, H.nrows}, true);
+  build_sell_ranges(dv, *D.sell, H, std::vector<int>{0, H.nrows}, true, nullptr, 4, order);
 }
 
-static void colour_order(const std::vector<int32_t> &col, DLevel &L) {
+// colour-major numbering: colour classes in order, inside a class ascending `rank` (the unknown
+// id when rank is null)
+static void colour_order(const std::vector<int32_t> &col, DLevel &L, const std::vector<int> *rank = nullptr) {
   const int n = (int)col.size();
   L.n = n;
   int C = 0;
@@ -791,7 +821,13 @@ static void colour_order(const std::vector<int32_t> &col, DLevel &L) {
   for (int c = 0; c < C; ++c) L.coff[c + 1] += L.coff[c];
   L.perm.resize(n);
   std::vector<int> pos(L.coff.begin(), L.coff.end() - 1);
-  for (int i = 0; i < n; ++i) L.perm[pos[col[i]]++] = i;  // ascending id inside a colour
+  if (rank) {
+    std::vector<int> byrank(n);
+    for (int i = 0; i < n; ++i) byrank[(*rank)[i]] = i;
+    for (int i : byrank) L.perm[pos[col[i]]++] = i;
+  } else {
+    for (int i = 0; i < n; ++i) L.perm[pos[col[i]]++] = i;
+  }
   L.iperm.resize(n);
   for (int i = 0; i < n; ++i) L.iperm[L.perm[i]] = i;
 }
@@ -806,20 +842,26 @@ static void alloc_vectors(Device *dv, DLevel &L) {
 }
 
 // sliced ELL of a host CSR: one slice set per row range [coff[c], coff[c+1]) (a colour class),
-// rows sorted by length inside windows of 256 rows, 64 rows per slice
+// rows sorted by length inside windows of 256 rows, 64 rows per slice. Slice widths above 16 are
+// rounded up to a multiple of `wround` (extra zero entries), so that matrices with long, uneven
+// rows use a few of the kernel's straight-line widths rather than many. With `order` (one range
+// only), position i of the range is row order[i].
 static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
-                              std::vector<int> *slot_map) {
+                              std::vector<int> *slot_map, int wround, const std::vector<int> *order) {
   if (slot_map) slot_map->clear();
   const int C = (int)coff.size() - 1;
   std::vector<int> srow, soff{0}, scol;
   std::vector<double> sv;
   std::vector<int> cs{0};
   std::vector<int> idx;
+  int widest = 0;
   for (int c = 0; c < C; ++c) {
     for (int w0 = coff[c]; w0 < coff[c + 1]; w0 += 256) {
       const int w1 = std::min(w0 + 256, coff[c + 1]);
       idx.resize(w1 - w0);
       std::iota(idx.begin(), idx.end(), w0);
+      if (order)
+        for (int &i : idx) i = (*order)[i];
       std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
         return (H.rp[a + 1] - H.rp[a]) > (H.rp[b + 1] - H.rp[b]);
       });
@@ -827,6 +869,7 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
         const size_t s1 = std::min(s0 + 64, idx.size());
         int wmax = 0;
         for (size_t i = s0; i < s1; ++i) wmax = std::max(wmax, H.rp[idx[i] + 1] - H.rp[idx[i]]);
+        if (wmax > 16) wmax = (wmax + wround - 1) / wround * wround;
         const int base = soff.back();
         scol.resize(base + 64 * wmax);
         sv.resize(base + 64 * wmax);
@@ -853,6 +896,7 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
           }
         }
         soff.push_back(base + 64 * wmax);
+        widest = std::max(widest, wmax);
       }
     }
     cs.push_back((int)srow.size() / 64);
@@ -860,6 +904,7 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
   std::vector<float> sv32(sv.begin(), sv.end());
   if (first_time) {
     S.nslices = (int)srow.size() / 64;
+    S.wmax = widest;
     S.cslice = cs;
     S.entries = (int64_t)sv.size();
     S.srow = dupload(dv, srow);
@@ -1004,6 +1049,33 @@ static void upload_coarse(Device *dv, Hierarchy &h, bool first_time) {
   }
 }
 
+// Morton rank of every unknown of the original grid: its position when the unknowns are sorted
+// by the Morton code of their vertex (quantised in the root box of the cluster tree, ties by id)
+static std::vector<int> morton_rank(const Hierarchy &h) {
+  const int64_t n = h.n();
+  const int d = h.d;
+  const int bits = d == 2 ? 31 : 21;
+  const double scale = std::ldexp(1.0, bits);
+  std::vector<std::pair<uint64_t, int64_t>> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double *x = &h.coords[h.dofs[i] * d];
+    uint64_t q[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) {
+      double t = (x[k] - h.a[k]) / h.L * scale;
+      t = std::min(std::max(t, 0.0), scale - 1.0);
+      q[k] = (uint64_t)t;
+    }
+    uint64_t m = 0;
+    for (int b = bits - 1; b >= 0; --b)
+      for (int k = 0; k < d; ++k) m = (m << 1) | ((q[k] >> b) & 1u);
+    key[i] = {m, i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> rank(n);
+  for (int64_t k = 0; k < n; ++k) rank[key[k].second] = (int)k;
+  return rank;
+}
+
 Device *device_create(Hierarchy &h, int ordinal) {
   int count = 0;
   HIPCHECK(hipGetDeviceCount(&count));
@@ -1020,8 +1092,10 @@ Device *device_create(Hierarchy &h, int ordinal) {
     dv->maxit = h.opt.max_iter;
     dv->precision = h.opt.precision;
     dv->check_every = h.opt.check_every;
-    // fine level
-    colour_order(h.colour_fine, dv->fine);
+    // fine level: colour-major, Morton order of the vertices inside a colour (rows that are
+    // neighbours in the numbering are neighbours in space, whatever the mesh's own numbering)
+    const std::vector<int> mrank = morton_rank(h);
+    colour_order(h.colour_fine, dv->fine, &mrank);
     HCsr Hfine;
     std::vector<int> fine_slots;
     upload_level_matrix(dv, dv->fine, h.A, true, &Hfine, &fine_slots);
@@ -1036,22 +1110,25 @@ Device *device_create(Hierarchy &h, int ordinal) {
       upload_level_matrix(dv, L, h.Al.at(l), true);
       alloc_vectors(dv, L);
     }
-    // prolongations in internal numbering
+    // prolongations in internal numbering; slices visit the rows in each level's own (Morton)
+    // numbering: position k holds internal row iperm[k] (the bottom level keeps its numbering)
     for (int l = h.J; l > h.lc; --l) {
       DLevel &L = dv->aux[l];
-      std::vector<int> ident;
       const std::vector<int> *cmap = nullptr;
       if (l - 1 > h.lc) cmap = &dv->aux[l - 1].iperm;
       HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
-      upload_transfer(dv, P, L.P);
-      upload_transfer(dv, transpose(P), L.PT);
+      upload_transfer(dv, P, L.P, &L.iperm);
+      upload_transfer(dv, transpose(P), L.PT, cmap);
     }
-    // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom)
+    // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom);
+    // Pi's slices visit the original-grid unknowns in Morton order of their vertices
     {
       const std::vector<int> *cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
       HCsr Pi = permute(h.Pi, dv->fine.perm, cmap, false, nullptr);
-      upload_transfer(dv, Pi, dv->Pi);
-      upload_transfer(dv, transpose(Pi), dv->PiT);
+      std::vector<int> forder(mrank.size());
+      for (size_t i = 0; i < mrank.size(); ++i) forder[mrank[i]] = dv->fine.iperm[i];
+      upload_transfer(dv, Pi, dv->Pi, &forder);
+      upload_transfer(dv, transpose(Pi), dv->PiT, cmap);
     }
     upload_coarse(dv, h, true);
     const int n = dv->fine.n;
@@ -1249,8 +1326,12 @@ template <class T, int ADD>
 static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s) {
   if (A.nrows == 0) return;
   const DSell &S = *A.sell;
-  hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
-                     S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
+  if (S.wmax > 16)
+    hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T, 32>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
+  else
+    hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
   if (dv->count_bytes)
     dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
 }
@@ -1261,8 +1342,12 @@ template <class T>
 static void spmv_first(Device *dv, const DCsr &A, const T *x, DLevel &L, hipStream_t s) {
   if (A.nrows == 0) return;
   const DSell &S = *A.sell;
-  hipLaunchKernelGGL((k_sell_spmv<0, 1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices, S.srow,
-                     S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
+  if (S.wmax > 16)
+    hipLaunchKernelGGL((k_sell_spmv<0, 1, T, 32>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
+  else
+    hipLaunchKernelGGL((k_sell_spmv<0, 1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
   if (dv->count_bytes)
     dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + 2.0 * A.nrows * sizeof(T) +
                  (double)L.coff[1] * sizeof(T);
