@@ -842,11 +842,13 @@ static void bupload_csr(BatchDevice *dv, const HMat &H, BCsr &D) {
 }
 
 // Sliced ELL of H over row-range groups: inside a range, windows of 256 rows sorted by length
-// (longest first, stable), 64 rows per slice. pad_blocks: every group ends on a whole block of
+// (longest first, stable), 64 rows per slice. With `order`, range positions map to rows
+// through it (transfer products visit their rows in a spatially coherent order). pad_blocks: every group ends on a whole block of
 // 4 slices (at least one block), so blocks never straddle groups; block0 gets the first block
 // of each group.
 static void bsell_build(BatchDevice *dv, const HMat &H, const std::vector<std::vector<std::pair<int, int>>> &groups,
-                        bool pad_blocks, BSell &S, std::vector<int> *block0 = nullptr) {
+                        bool pad_blocks, BSell &S, std::vector<int> *block0 = nullptr,
+                        const std::vector<int> *order = nullptr) {
   std::vector<int> srow, soff{0}, scol, idx;
   std::vector<double> sv;
   S.cslice.assign(1, 0);
@@ -863,6 +865,8 @@ static void bsell_build(BatchDevice *dv, const HMat &H, const std::vector<std::v
         const int w1 = std::min(w0 + 256, rg.second);
         idx.resize(w1 - w0);
         std::iota(idx.begin(), idx.end(), w0);
+        if (order)
+          for (int &i : idx) i = (*order)[i];  // position i of the range holds row order[i]
         std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return len(x) > len(y); });
         for (size_t a = 0; a < idx.size(); a += 64) {
           const size_t e = std::min(a + 64, idx.size());
@@ -940,8 +944,9 @@ static SegTable make_mesh_blocks(BatchDevice *dv, const std::vector<int> &r0, co
   return S;
 }
 
+// colour-major numbering; inside a colour ascending `rank` (the unknown id when rank is null)
 static void colour_perm(const std::vector<int32_t> &col, std::vector<int> &perm, std::vector<int> &iperm,
-                        std::vector<int> &coff) {
+                        std::vector<int> &coff, const std::vector<int> *rank = nullptr) {
   const int n = (int)col.size();
   int C = 0;
   for (int c : col) C = std::max(C, c + 1);
@@ -950,7 +955,13 @@ static void colour_perm(const std::vector<int32_t> &col, std::vector<int> &perm,
   for (int c = 0; c < C; ++c) coff[c + 1] += coff[c];
   perm.resize(n);
   std::vector<int> pos(coff.begin(), coff.end() - 1);
-  for (int i = 0; i < n; ++i) perm[pos[col[i]]++] = i;
+  if (rank) {
+    std::vector<int> byrank(n);
+    for (int i = 0; i < n; ++i) byrank[(*rank)[i]] = i;
+    for (int i : byrank) perm[pos[col[i]]++] = i;
+  } else {
+    for (int i = 0; i < n; ++i) perm[pos[col[i]]++] = i;
+  }
   iperm.resize(n);
   for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
 }
@@ -1008,6 +1019,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
     // per-mesh colour-major orderings of every smoothing level
     struct MeshOrd {
       std::vector<int> perm, iperm, coff;
+      std::vector<int> morton;  // original grid: internal rows in Morton order of their vertices
     };
     std::vector<MeshOrd> fine(nm);
     std::vector<std::vector<MeshOrd>> lev(nm);  // index k (aux level J - k), smoothing levels only
@@ -1016,7 +1028,10 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
     dv->dof_off.assign(nm + 1, 0);
     for (int m = 0; m < nm; ++m) {
       Hierarchy &h = *H[m];
-      colour_perm(h.colour_fine, fine[m].perm, fine[m].iperm, fine[m].coff);
+      const std::vector<int> mrank = morton_rank(h);
+      colour_perm(h.colour_fine, fine[m].perm, fine[m].iperm, fine[m].coff, &mrank);
+      fine[m].morton.resize(mrank.size());
+      for (size_t i = 0; i < mrank.size(); ++i) fine[m].morton[mrank[i]] = fine[m].iperm[i];
       const int D = h.J - h.lc;
       K = std::max(K, D);
       lev[m].resize(D);
@@ -1146,6 +1161,21 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       L.inv32 = bupload(dv, inv32);
       alloc_level_vectors(dv, L);
     }
+    // rows of merged level k in each mesh's own (Morton) numbering: smoothing meshes through their
+    // colour permutation, bottom meshes as they are
+    auto natural_rows = [&](const BLevel &L, int k) {
+      std::vector<int> o;
+      o.reserve(L.nrows);
+      for (size_t i = 0; i < L.mesh.size(); ++i) {
+        const int m = L.mesh[i];
+        const int end = i + 1 < L.mesh.size() ? L.off[i + 1] : L.nrows;
+        if (H[m]->J - H[m]->lc > k)
+          for (int r : lev[m][k].iperm) o.push_back(L.off[i] + r);
+        else
+          for (int r = L.off[i]; r < end; ++r) o.push_back(r);
+      }
+      return o;
+    };
     // ---- prolongations P (level k+1 -> k) for the smoothing meshes of level k
     for (int k = 0; k < K; ++k) {
       BLevel &L = dv->aux[k], &Lc = dv->aux[k + 1];
@@ -1161,8 +1191,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       }
       P.ncols = Lc.nrows;
       const HMat PT = htranspose(P);
-      bsell_build(dv, P, {{{0, P.nrows}}}, false, L.P);
-      bsell_build(dv, PT, {{{0, PT.nrows}}}, false, L.PT);
+      const std::vector<int> oP = natural_rows(L, k), oPT = natural_rows(Lc, k + 1);
+      bsell_build(dv, P, {{{0, P.nrows}}}, false, L.P, nullptr, &oP);
+      bsell_build(dv, PT, {{{0, PT.nrows}}}, false, L.PT, nullptr, &oPT);
     }
     // ---- Pi (fine rows -> merged level 0 rows)
     {
@@ -1176,8 +1207,12 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       }
       Pi.ncols = L0.nrows;
       const HMat PiT = htranspose(Pi);
-      bsell_build(dv, Pi, {{{0, Pi.nrows}}}, false, dv->Pi);
-      bsell_build(dv, PiT, {{{0, PiT.nrows}}}, false, dv->PiT);
+      std::vector<int> oPi;
+      for (int m = 0; m < nm; ++m)
+        for (int r : fine[m].morton) oPi.push_back(dv->fine.off[m] + r);
+      const std::vector<int> oPiT = natural_rows(L0, 0);
+      bsell_build(dv, Pi, {{{0, Pi.nrows}}}, false, dv->Pi, nullptr, &oPi);
+      bsell_build(dv, PiT, {{{0, PiT.nrows}}}, false, dv->PiT, nullptr, &oPiT);
     }
     // ---- gather/scatter maps: internal fine row -> user offset of (mesh, rhs 0, dof), stride n_m
     {

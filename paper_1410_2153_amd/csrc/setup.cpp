@@ -1311,4 +1311,32 @@ void build_coarse(Hierarchy &h) {
   });
 }
 
+// ---------------------------------------------------------------------------
+// Morton rank of every unknown of the original grid: its position when the unknowns are sorted
+// by the Morton code of their vertex (quantised in the root box of the cluster tree, ties by id)
+std::vector<int> morton_rank(const Hierarchy &h) {
+  const int64_t n = h.n();
+  const int d = h.d;
+  const int bits = d == 2 ? 31 : 21;
+  const double scale = std::ldexp(1.0, bits);
+  std::vector<std::pair<uint64_t, int64_t>> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double *x = &h.coords[h.dofs[i] * d];
+    uint64_t q[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) {
+      double t = (x[k] - h.a[k]) / h.L * scale;
+      t = std::min(std::max(t, 0.0), scale - 1.0);
+      q[k] = (uint64_t)t;
+    }
+    uint64_t m = 0;
+    for (int b = bits - 1; b >= 0; --b)
+      for (int k = 0; k < d; ++k) m = (m << 1) | ((q[k] >> b) & 1u);
+    key[i] = {m, i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> rank(n);
+  for (int64_t k = 0; k < n; ++k) rank[key[k].second] = (int)k;
+  return rank;
+}
+
 }  // namespace asmg

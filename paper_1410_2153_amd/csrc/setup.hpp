@@ -99,6 +99,8 @@ void build_transfer(Hierarchy &h);
 void build_colourings(Hierarchy &h);
 void build_coarse(Hierarchy &h);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
+// position of every unknown of the original grid in Morton order of its vertex (device layout)
+std::vector<int> morton_rank(const Hierarchy &h);
 // element stiffness at kappa = 1 (|tau| grad(lambda_i).grad(lambda_j))
 void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]);
 
