@@ -19,9 +19,18 @@
   S^(-1) + S^(-T) - A = D, B_co = S^T D S + (I - S^T A) Pi B~ Pi^T (I - A S)
   is symmetric positive definite whenever B~ is.
 
+* Local smoothing (option ``smoothing="local"``): the V-cycle smooths level l
+  only on the unknowns of N~_l (``auxops.local_set``), the index set of the
+  decomposition V_J = sum_l sum_{k in N~_l} V_{l,k} under which Section 4.3
+  proves the multigrid bound. The sweeps visit the same colours in the same
+  order, restricted to those rows; residuals and transfers stay whole.
+
 Pins: on small meshes B_co, formed densely, is symmetric (1e-13) and positive
 definite, and matches the closed form above; a V-cycle on the uniform hierarchy
-of the square is the textbook geometric multigrid of Section 5.1.
+of the square is the textbook geometric multigrid of Section 5.1; with local
+smoothing, B_co stays symmetric positive definite, N~_l agrees with a geometric
+count of bisected edges, and on the uniform hierarchy (N~_l = N_l) it is the
+full-smoothing B_co.
 """
 from __future__ import annotations
 
@@ -29,15 +38,17 @@ import numpy as np
 
 
 class Smoother:
-    """Multicolour Gauss-Seidel for one matrix (rows of each colour pre-sliced)."""
+    """Multicolour Gauss-Seidel for one matrix (rows of each colour pre-sliced). With ``mask``,
+    only the rows where it is true are smoothed (the other unknowns keep their values)."""
 
-    def __init__(self, A, colour, dtype=np.float64):
+    def __init__(self, A, colour, dtype=np.float64, mask=None):
         A = A.tocsr().astype(dtype)
         self.A = A
         self.dtype = dtype
         self.diag = A.diagonal().astype(dtype)
         C = int(colour.max()) + 1 if len(colour) else 0
-        self.rows = [np.nonzero(colour == c)[0] for c in range(C)]
+        sel = np.ones(len(colour), dtype=bool) if mask is None else np.asarray(mask, dtype=bool)
+        self.rows = [np.nonzero((colour == c) & sel)[0] for c in range(C)]
         self.blocks = [A[r] for r in self.rows]
         self.dblk = [self.diag[r] for r in self.rows]
 
@@ -57,7 +68,8 @@ class Smoother:
 class ASMGPreconditioner:
     """B_co of Algorithm 1 with the V-cycle of Algorithm 2 on the auxiliary levels."""
 
-    def __init__(self, hier, dtype=np.float64, nu_aux=2, nu_fine=1):
+    def __init__(self, hier, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full"):
+        from .auxops import local_set
         self.h = hier
         self.dtype = dtype
         self.nu_aux = nu_aux
@@ -66,7 +78,12 @@ class ASMGPreconditioner:
         self.lc = ops.lc
         self.J = ops.J
         self.fine = Smoother(hier.A, hier.colour_fine, dtype)
-        self.aux = {l: Smoother(ops.A[l], hier.colour_aux[l], dtype) for l in range(self.lc + 1, self.J + 1)}
+        if smoothing not in ("full", "local"):
+            raise ValueError(smoothing)
+        self.masks = {l: (local_set(ops.P[l]) if smoothing == "local" else None)
+                      for l in range(self.lc + 1, self.J + 1)}
+        self.aux = {l: Smoother(ops.A[l], hier.colour_aux[l], dtype, self.masks[l])
+                    for l in range(self.lc + 1, self.J + 1)}
         self.Aaux = {l: ops.A[l].astype(dtype) for l in ops.A}
         self.P = {l: ops.P[l].astype(dtype) for l in ops.P}
         self.PT = {l: ops.P[l].T.tocsr().astype(dtype) for l in ops.P}

@@ -187,6 +187,32 @@ def prolongation(meshes, lm_fine, lm_coarse):
     return P
 
 
+def local_set(P):
+    """Index set of the local decomposition of V_J (Section 4.3, the decomposition into
+    V_{l,k}, k in N~_l), as a boolean mask over the unknowns of level l.
+
+    k is in N~_l if it is new on level l (not an unknown of level l-1) or its nodal basis
+    function changed, phi_{k,l} != phi_{k,l-1}. In the level-l basis,
+    phi_{k,l-1} = sum_i P[i, k] phi_{i,l}, so the function is unchanged exactly when column k
+    of P_l holds nothing but the entry 1 on the row of k itself. The row of an unknown that
+    already existed on level l-1 is that single entry 1 (nodal interpolation reproduces its
+    value); a new unknown's row holds its edge's two parents with weight 1/2 (or one, next to
+    the boundary).
+    """
+    P = P.tocsr()
+    n = P.shape[0]
+    rl = np.diff(P.indptr)
+    one = np.zeros(n, dtype=bool)
+    has = rl == 1
+    one[has] = P.data[P.indptr[:-1][has]] == 1.0
+    old = has & one
+    colcount = np.diff(P.tocsc().indptr)
+    out = ~old
+    parent = P.indices[P.indptr[:-1][old]]
+    out[np.nonzero(old)[0]] = colcount[parent] > 1
+    return out
+
+
 class AuxOperators:
     """A_l (l = lc..J), P_l (l = lc+1..J) and the coarse Cholesky factor."""
 

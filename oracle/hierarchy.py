@@ -35,14 +35,15 @@ class Hierarchy:
     def n(self):
         return len(self.dofs)
 
-    def preconditioner(self, dtype=np.float64, nu_aux=2, nu_fine=1):
-        key = (np.dtype(dtype).name, nu_aux, nu_fine)
+    def preconditioner(self, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full"):
+        key = (np.dtype(dtype).name, nu_aux, nu_fine, smoothing)
         if key not in self._B:
-            self._B[key] = asmg.ASMGPreconditioner(self, dtype, nu_aux, nu_fine)
+            self._B[key] = asmg.ASMGPreconditioner(self, dtype, nu_aux, nu_fine, smoothing)
         return self._B[key]
 
-    def solve(self, f, tol=1e-8, max_iter=1000, mixed=False, record=False, nu_aux=2, nu_fine=1):
-        B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine)
+    def solve(self, f, tol=1e-8, max_iter=1000, mixed=False, record=False, nu_aux=2, nu_fine=1,
+              smoothing="full"):
+        B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine, smoothing)
         if mixed:
             def Bm(r):
                 return B(r.astype(np.float32)).astype(np.float64)
