@@ -318,6 +318,26 @@ def main():
     }
     del S64
     torch.cuda.synchronize()
+    if not args.no_extra:
+        # the same workload with local smoothing on N~_l (the decomposition of Section 4.3)
+        t0 = time.perf_counter()
+        SL = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64,
+                      colouring=args.colouring, smoothing=1)
+        t_setup_l = time.perf_counter() - t0
+        loc = {"setup_s": t_setup_l}
+        for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
+            SL.set_precision(prec)
+            dtl, itl, trl, ul = run(SL, args.steps, args.warmup)
+            loc[name] = {"value": n * args.steps / dtl, "ms_per_step": dtl / args.steps * 1e3, "iterations": itl[-1],
+                         "true_rel_residual": trl}
+            log(f"local smoothing {name}: {dtl / args.steps * 1e3:.2f} ms/solve, iters {itl}, true rel res {trl:.2e}")
+        loc["rel_diff_vs_full_fp64"] = float(torch.linalg.norm(ul - u64) / torch.linalg.norm(u64))
+        SL.set_precision(A.PREC_FP64)
+        ms_bl, by_bl = SL.time_kernel(2, reps=20, precision=A.PREC_FP64)
+        loc["vcycle_fp64"] = {"ms": ms_bl, "model_bytes": by_bl, "GBs": by_bl / ms_bl / 1e6}
+        out["local_smoothing"] = loc
+        del SL
+        torch.cuda.synchronize()
     if args.copy_calibration:
         x = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
         y = torch.empty_like(x)

@@ -66,6 +66,10 @@ typedef struct {
                           1 = greedy in descending (fmix32(i ^ colour_seed), i) (Jones-Plassmann order),
                           2 = greedy in smallest-last order (Matula-Beck; at most degeneracy + 1
                               colours; default) */
+  int smoothing;       /* auxiliary-level smoothing: 0 = every unknown of the level (Algorithm 2,
+                          default); 1 = local, only the unknowns of N~_l, the index set of the
+                          decomposition of Section 4.3 (new on level l, or with a basis function
+                          that changed from level l-1). Single-mesh handles only. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */

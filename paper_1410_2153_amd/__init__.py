@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("n_min", ctypes.c_int), ("nu_aux", ctypes.c_int), ("nu_fine", ctypes.c_int),
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("colouring", ctypes.c_int)]
+                ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int)]
 
 
 def _load():
@@ -107,7 +107,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2):
+                 colouring=2, smoothing=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -120,6 +120,7 @@ class Solver:
         opt.coarse_max_dofs, opt.max_iter, opt.precision = coarse_max_dofs, max_iter, precision
         opt.colour_seed, opt.device, opt.check_every = colour_seed, device, check_every
         opt.colouring = colouring
+        opt.smoothing = smoothing
         self.precision = precision
         self.device = device
         dptr = None
@@ -247,7 +248,7 @@ class BatchSolver:
     """
 
     def __init__(self, meshes, *, device=0, precision=PREC_FP64, n_min=0, nu_aux=2, nu_fine=1,
-                 coarse_max_dofs=1024, max_iter=1000):
+                 coarse_max_dofs=1024, max_iter=1000, smoothing=0):
         dim = np.asarray(meshes[0][0]).shape[1]
         coords = np.ascontiguousarray(np.concatenate([np.asarray(m[0], dtype=np.float64) for m in meshes]))
         elems = np.ascontiguousarray(np.concatenate([np.asarray(m[1], dtype=np.int32) for m in meshes]))
@@ -260,6 +261,7 @@ class BatchSolver:
         lib.asmg_default_options(ctypes.byref(opt))
         opt.n_min, opt.nu_aux, opt.nu_fine = n_min, nu_aux, nu_fine
         opt.coarse_max_dofs, opt.max_iter, opt.precision, opt.device = coarse_max_dofs, max_iter, precision, device
+        opt.smoothing = smoothing
         h = ctypes.c_void_p()
         _check(lib.asmg_setup_batch(len(meshes), dim, _ptr(vo), _ptr(coords), _ptr(eo), _ptr(elems), _ptr(kappa),
                                     ctypes.byref(opt), ctypes.byref(h)))

@@ -101,6 +101,7 @@ int asmg_default_options(asmg_options *o) {
   o->device = 0;
   o->check_every = 0;
   o->colouring = 2;
+  o->smoothing = 0;
   return ASMG_OK;
 }
 
@@ -117,7 +118,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (opt) o = *opt;
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 2)
+      o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1)
     return set_err(ASMG_EINVAL, "invalid options");
   for (int64_t i = 0; i < n_vertices * dim; ++i)
     if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
@@ -154,6 +155,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     build_transfer(h);
     lap("transfer");
     build_colourings(h);
+    build_local_sets(h);
     lap("colourings");
     build_coarse(h);
     lap("coarse");
@@ -272,6 +274,7 @@ static int check_options(const asmg_options &o) {
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
       o.colouring > 2)
     return set_err(ASMG_EINVAL, "invalid options");
+  if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
   return ASMG_OK;
 }
 
@@ -411,13 +414,19 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
       std::vector<int64_t> c(h.colour_fine.begin(), h.colour_fine.end());
       return put(c, buf, count);
     }
-    if (name.rfind("level_", 0) == 0 || name == "colour_aux" || name.rfind("Al_", 0) == 0 ||
+    if (name.rfind("level_", 0) == 0 || name == "colour_aux" || name == "local_set" || name.rfind("Al_", 0) == 0 ||
         name.rfind("P_", 0) == 0) {
       if (level < 1 || level > h.J) return set_err(ASMG_EINVAL, "level out of range");
     }
     if (name == "level_verts") return put(level_mesh(h, level).verts, buf, count);
     if (name == "level_simp") return put(level_mesh(h, level).simp, buf, count);
     if (name == "level_dofs") return put(level_mesh(h, level).dof_vert, buf, count);
+    if (name == "local_set") {
+      auto it = h.local_set.find(level);
+      if (it == h.local_set.end()) return set_err(ASMG_EINVAL, "no smoothed level there");
+      std::vector<int64_t> c(it->second.begin(), it->second.end());
+      return put(c, buf, count);
+    }
     if (name == "colour_aux") {
       auto it = h.colour_aux.find(level);
       if (it == h.colour_aux.end()) return set_err(ASMG_EINVAL, "no colouring on that level");

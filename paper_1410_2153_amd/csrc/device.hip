@@ -217,12 +217,13 @@ __global__ __launch_bounds__(BS) void k_sell(int s0, int s1, const int *__restri
 // transfer products on a sliced ELL (one colour class = all rows): y = A x (ADD = 0) or y += A x.
 // FIRST (with ADD = 0): y is the right-hand side of a level whose smoothing starts from zero, and
 // the kernel also runs that first colour pass: xs_i = y_i / a_ii for rows i < c0 (colour 0),
-// xs_i = 0 for the other rows.
+// xs_i = 0 for the other rows; with rc it also copies y into rc.
 template <int ADD, int FIRST, class T, int WMAX = 16>
 __global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
                                                   const int *__restrict__ scol, const T *__restrict__ sv,
                                                   const T *__restrict__ x, T *__restrict__ y, int c0,
-                                                  const T *__restrict__ invd, T *__restrict__ xs) {
+                                                  const T *__restrict__ invd, T *__restrict__ xs,
+                                                  T *__restrict__ rc) {
   const int s = wave_slice(0);
   if (s >= ns) return;
   const int lane = threadIdx.x & 63;
@@ -240,7 +241,10 @@ __global__ __launch_bounds__(BS) void k_sell_spmv(int ns, const int *__restrict_
     if (FIRST) pin(di);
     if (row < 0) return;
     y[row] = ADD ? yi + acc : acc;
-    if (FIRST) xs[row] = row < c0 ? acc * di : T(0);
+    if (FIRST) {
+      xs[row] = row < c0 ? acc * di : T(0);
+      if (rc) rc[row] = acc;
+    }
   };
   sell_row<T, WMAX>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
@@ -620,6 +624,7 @@ __global__ __launch_bounds__(BS) void k_elem_grad(int ne, const double *__restri
 // ---------------------------------------------------------------------------
 
 struct DSell;
+using Ranges = std::vector<std::pair<int, int>>;  // row ranges [first, second)
 struct DCsr {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
@@ -642,10 +647,17 @@ struct DSell {
 
 struct DLevel {
   int n = 0;
-  DSell sell;                 // same off-diagonal part as A, sliced by colour
+  DSell sell;                 // off-diagonal part of the smoothed rows, one slice group per range below
   std::vector<int> coff;      // colour offsets, C + 1
-  std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each colour's rows
-  std::vector<int64_t> ucols; // distinct columns referenced by each colour's rows
+  int C = 0;                  // colours; Gauss-Seidel pass c runs slice group c
+  // slice groups: colour c (full smoothing), or with local smoothing (auxiliary levels) first the
+  // rows of N~ in colour c (groups 0..C-1, the smoothed rows), then the other rows of N~+ (rows
+  // coupled to N~) in colour c (groups C..2C-1): the residual runs over all groups
+  Ranges groups;
+  int first_rows = 0;         // rows [0, first_rows): colour-0 rows of the first pass from zero
+  bool local = false;         // local smoothing: r is written only on N~+, elsewhere r = b
+  std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each group's rows
+  std::vector<int64_t> ucols; // distinct columns referenced by each group's rows
   std::vector<int> perm;      // internal -> unknown
   std::vector<int> iperm;     // unknown -> internal
   DCsr A;                     // off-diagonal part
@@ -775,7 +787,7 @@ static HCsr transpose(const HCsr &A) {
   return T;
 }
 
-static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges &groups, bool first_time,
                               std::vector<int> *slot_map = nullptr, int wround = 1,
                               const std::vector<int> *order = nullptr);
 
@@ -806,30 +818,62 @@ static void upload_transfer(Device *dv, const HCsr &H, DCsr &D, const std::vecto
   upload_csr(dv, H, D);
   dv->sells.emplace_back(new DSell());
   D.sell = dv->sells.back().get();
-  build_sell_ranges(dv, *D.sell, H, std::vector<int>{0, H.nrows}, true, nullptr, 4, order);
+  build_sell_ranges(dv, *D.sell, H, Ranges{{0, H.nrows}}, true, nullptr, 4, order);
 }
 
-// colour-major numbering: colour classes in order, inside a class ascending `rank` (the unknown
-// id when rank is null)
-static void colour_order(const std::vector<int32_t> &col, DLevel &L, const std::vector<int> *rank = nullptr) {
+// colour-major numbering: colour classes in order, inside a class ascending (part, rank), with
+// rank the unknown id when null and part 0 when null. Sets coff, C, the full-smoothing slice
+// groups (one per colour) and the colour-0 prefix of the first pass.
+static void colour_order(const std::vector<int32_t> &col, DLevel &L, const std::vector<int> *rank = nullptr,
+                         const std::vector<uint8_t> *part = nullptr) {
   const int n = (int)col.size();
   L.n = n;
   int C = 0;
   for (int c : col) C = std::max(C, c + 1);
+  L.C = C;
   L.coff.assign(C + 1, 0);
   for (int c : col) L.coff[c + 1]++;
   for (int c = 0; c < C; ++c) L.coff[c + 1] += L.coff[c];
+  std::vector<int> seq(n);
+  if (rank)
+    for (int i = 0; i < n; ++i) seq[(*rank)[i]] = i;
+  else
+    std::iota(seq.begin(), seq.end(), 0);
+  if (part) std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) { return (*part)[a] < (*part)[b]; });
   L.perm.resize(n);
   std::vector<int> pos(L.coff.begin(), L.coff.end() - 1);
-  if (rank) {
-    std::vector<int> byrank(n);
-    for (int i = 0; i < n; ++i) byrank[(*rank)[i]] = i;
-    for (int i : byrank) L.perm[pos[col[i]]++] = i;
-  } else {
-    for (int i = 0; i < n; ++i) L.perm[pos[col[i]]++] = i;
-  }
+  for (int i : seq) L.perm[pos[col[i]]++] = i;
   L.iperm.resize(n);
   for (int i = 0; i < n; ++i) L.iperm[L.perm[i]] = i;
+  L.groups.clear();
+  for (int c = 0; c < C; ++c) L.groups.push_back({L.coff[c], L.coff[c + 1]});
+  L.first_rows = C > 0 ? L.coff[1] : 0;
+  L.local = false;
+}
+
+// Local smoothing on an auxiliary level: rows of N~ first, then the rest of N~+ (N~ and the rows
+// coupled to it in A_l), inside every colour; the slice groups cover N~ (smoothing) and then
+// the rest of N~+ (residual only).
+static void local_order(const std::vector<int32_t> &col, const std::vector<uint8_t> &nt, const Csr &A, DLevel &L) {
+  const int n = (int)col.size();
+  std::vector<uint8_t> part(n, 2);
+  for (int i = 0; i < n; ++i)
+    if (nt[i]) {
+      part[i] = 0;
+      for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+        if (!nt[A.ci[p]]) part[A.ci[p]] = 1;
+    }
+  colour_order(col, L, nullptr, &part);
+  std::vector<int> cnt0(L.C, 0), cnt1(L.C, 0);
+  for (int i = 0; i < n; ++i) {
+    if (part[i] == 0) ++cnt0[col[i]];
+    if (part[i] == 1) ++cnt1[col[i]];
+  }
+  L.groups.clear();
+  for (int c = 0; c < L.C; ++c) L.groups.push_back({L.coff[c], L.coff[c] + cnt0[c]});
+  for (int c = 0; c < L.C; ++c) L.groups.push_back({L.coff[c] + cnt0[c], L.coff[c] + cnt0[c] + cnt1[c]});
+  L.first_rows = L.C > 0 ? cnt0[0] : 0;
+  L.local = true;
 }
 
 static void alloc_vectors(Device *dv, DLevel &L) {
@@ -841,23 +885,23 @@ static void alloc_vectors(Device *dv, DLevel &L) {
   L.r32 = dalloc<float>(dv, L.n);
 }
 
-// sliced ELL of a host CSR: one slice set per row range [coff[c], coff[c+1]) (a colour class),
+// sliced ELL of a host CSR: one slice group per row range (a colour class, or part of one),
 // rows sorted by length inside windows of 256 rows, 64 rows per slice. Slice widths above 16 are
 // rounded up to a multiple of `wround` (extra zero entries), so that matrices with long, uneven
 // rows use a few of the kernel's straight-line widths rather than many. With `order` (one range
 // only), position i of the range is row order[i].
-static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::vector<int> &coff, bool first_time,
+static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges &groups, bool first_time,
                               std::vector<int> *slot_map, int wround, const std::vector<int> *order) {
   if (slot_map) slot_map->clear();
-  const int C = (int)coff.size() - 1;
+  const int C = (int)groups.size();
   std::vector<int> srow, soff{0}, scol;
   std::vector<double> sv;
   std::vector<int> cs{0};
   std::vector<int> idx;
   int widest = 0;
   for (int c = 0; c < C; ++c) {
-    for (int w0 = coff[c]; w0 < coff[c + 1]; w0 += 256) {
-      const int w1 = std::min(w0 + 256, coff[c + 1]);
+    for (int w0 = groups[c].first; w0 < groups[c].second; w0 += 256) {
+      const int w1 = std::min(w0 + 256, groups[c].second);
       idx.resize(w1 - w0);
       std::iota(idx.begin(), idx.end(), w0);
       if (order)
@@ -919,7 +963,7 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const std::ve
 }
 
 static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time, std::vector<int> *slot_map = nullptr) {
-  build_sell_ranges(dv, L.sell, H, L.coff, first_time, slot_map);
+  build_sell_ranges(dv, L.sell, H, L.groups, first_time, slot_map);
 }
 
 static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time, HCsr *keep = nullptr,
@@ -931,12 +975,12 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
   std::vector<float> d32(diag.begin(), diag.end()), i32(diag.size());
   for (size_t i = 0; i < diag.size(); ++i) i32[i] = 1.0f / (float)diag[i];
   if (first_time) {
-    const int C = (int)L.coff.size() - 1;
-    L.cnnz.assign(C, 0);
-    L.ucols.assign(C, 0);
+    const int G = (int)L.groups.size();
+    L.cnnz.assign(G, 0);
+    L.ucols.assign(G, 0);
     std::vector<int> seen(L.n, -1);
-    for (int c = 0; c < C; ++c)
-      for (int i = L.coff[c]; i < L.coff[c + 1]; ++i)
+    for (int c = 0; c < G; ++c)
+      for (int i = L.groups[c].first; i < L.groups[c].second; ++i)
         for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
           ++L.cnnz[c];
           if (seen[H.ci[p]] != c) {
@@ -1079,7 +1123,10 @@ Device *device_create(Hierarchy &h, int ordinal) {
     dv->aux.resize(h.J + 1);
     for (int l = h.J; l > h.lc; --l) {
       DLevel &L = dv->aux[l];
-      colour_order(h.colour_aux.at(l), L);
+      if (h.opt.smoothing == 1)
+        local_order(h.colour_aux.at(l), h.local_set.at(l), h.Al.at(l), L);
+      else
+        colour_order(h.colour_aux.at(l), L);
       upload_level_matrix(dv, L, h.Al.at(l), true);
       alloc_vectors(dv, L);
     }
@@ -1221,7 +1268,7 @@ static constexpr int PROBE_REPS = 10;
 // b, 1/diag and the x write of its rows, and each distinct x entry it gathers once
 template <class T>
 static double gs_bytes(const DLevel &L, int c) {
-  const double rows = L.coff[c + 1] - L.coff[c];
+  const double rows = L.groups[c].second - L.groups[c].first;
   return (double)L.cnnz[c] * (sizeof(T) + 4) + 4.0 * (rows + 1) + 3.0 * sizeof(T) * rows +
          (double)sizeof(T) * L.ucols[c];
 }
@@ -1229,7 +1276,7 @@ static double gs_bytes(const DLevel &L, int c) {
 template <class T>
 static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t s) {
   const bool probe = dv->probe_lpr != 0 && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0) &&
-                     L.coff[c + 1] > L.coff[c];
+                     L.groups[c].second > L.groups[c].first;
   if (probe) {
     if (dv->probe_used + 2 > dv->probe_ev.size()) {
       hipEvent_t e0, e1;
@@ -1261,7 +1308,7 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t 
 // x written on every row, b and 1/diag read on colour 0
 template <class T>
 static double first_pass_bytes(const DLevel &L) {
-  return (double)L.n * sizeof(T) + (double)L.coff[1] * 2 * sizeof(T);
+  return (double)L.n * sizeof(T) + (double)L.first_rows * 2 * sizeof(T);
 }
 
 // Gauss-Seidel sweep over colours. `first_done`: the sweep starts from zero and its colour-0
@@ -1269,12 +1316,12 @@ static double first_pass_bytes(const DLevel &L) {
 template <class T>
 static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool first_done, bool forward,
                   hipStream_t s) {
-  const int C = (int)L.coff.size() - 1;
+  const int C = L.C;
   if (forward) {
     int c = 0;
     if (from_zero) {
       if (!first_done) {
-        hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.coff[1], b, LV<T>::id(L), x);
+        hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.first_rows, b, LV<T>::id(L), x);
         if (dv->count_bytes) dv->bytes += first_pass_bytes<T>(L);
       }
       c = 1;
@@ -1285,13 +1332,19 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
   }
 }
 
+// r = b - A x on the rows of every slice group (all rows; with local smoothing the rows of N~+,
+// r = b elsewhere having been written with b)
 template <class T>
 static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s) {
-  const int n = L.n;
   const DSell &S = L.sell;
+  if (S.nslices == 0) return;
   hipLaunchKernelGGL((k_sell<1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, 0, S.nslices, S.srow,
                      S.soff, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r);
-  if (dv->count_bytes) dv->bytes += csr_bytes(L.A, sizeof(T)) + 4.0 * n * sizeof(T);
+  if (dv->count_bytes)
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+      const double rows = L.groups[g].second - L.groups[g].first;
+      dv->bytes += (double)L.cnnz[g] * (sizeof(T) + 4) + 4.0 * rows + 4.0 * sizeof(T) * rows;
+    }
 }
 
 // y = A x (ADD 0) or y += A x (ADD 1) for a transfer matrix A
@@ -1301,29 +1354,37 @@ static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s) {
   const DSell &S = *A.sell;
   if (S.wmax > 16)
     hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T, 32>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
-                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr,
+                       (T *)nullptr);
   else
     hipLaunchKernelGGL((k_sell_spmv<ADD, 0, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
-                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr);
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr,
+                       (T *)nullptr);
   if (dv->count_bytes)
     dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
 }
 
 // restriction y = A x into the right-hand side of level L, fused with the colour-0 pass of the
 // first (from zero) forward sweep on L
+// restriction y = A x into the right-hand side of level L, fused with the colour-0 pass of the
+// first (from zero) forward sweep on L; with local smoothing also r = y (the residual kernel
+// then overwrites r on N~+ only)
 template <class T>
 static void spmv_first(Device *dv, const DCsr &A, const T *x, DLevel &L, hipStream_t s) {
   if (A.nrows == 0) return;
   const DSell &S = *A.sell;
+  T *rc = L.local ? LV<T>::r(L) : (T *)nullptr;
   if (S.wmax > 16)
     hipLaunchKernelGGL((k_sell_spmv<0, 1, T, 32>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
-                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L),
+                       LV<T>::x(L), rc);
   else
     hipLaunchKernelGGL((k_sell_spmv<0, 1, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, S.nslices,
-                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.coff[1], LV<T>::id(L), LV<T>::x(L));
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L),
+                       LV<T>::x(L), rc);
   if (dv->count_bytes)
-    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + 2.0 * A.nrows * sizeof(T) +
-                 (double)L.coff[1] * sizeof(T);
+    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (2.0 + (rc ? 1 : 0)) * A.nrows * sizeof(T) +
+                 (double)L.first_rows * sizeof(T);
 }
 
 template <class T>
@@ -1395,9 +1456,9 @@ static void apply_Bco(Device *dv, const double *r, bool first_done, hipStream_t 
     b = r;
   } else {
     if (!first_done) {
-      hipLaunchKernelGGL(k_gs_first_cvt, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, F.coff.size() > 1 ? F.coff[1] : 0,
+      hipLaunchKernelGGL(k_gs_first_cvt, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, F.first_rows,
                          r, F.b32, F.id32, F.x32);
-      if (dv->count_bytes) dv->bytes += (double)F.n * (8 + 4 + 4) + (double)F.coff[1] * 4;
+      if (dv->count_bytes) dv->bytes += (double)F.n * (8 + 4 + 4) + (double)F.first_rows * 4;
       first_done = true;
     }
     b = F.b32;
@@ -1437,7 +1498,7 @@ static void pcg_iteration(Device *dv, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_spmv, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   g = red_grid(n, 1);
   hipLaunchKernelGGL((k_cg_axpy<T>), dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials,
-                     F.coff.size() > 1 ? F.coff[1] : 0, LV<T>::id(F), LV<T>::b(F), LV<T>::x(F));
+                     F.first_rows, LV<T>::id(F), LV<T>::b(F), LV<T>::x(F));
   hipLaunchKernelGGL(k_fin_axpy, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
   pcg_tail<T>(dv, s, true);
 }

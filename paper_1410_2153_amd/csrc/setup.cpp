@@ -1269,6 +1269,25 @@ void build_colourings(Hierarchy &h) {
   for (size_t t = 1; t < lv.size(); ++t) h.colour_aux[lv[t]] = std::move(out[t]);
 }
 
+// N~_l (Section 4.3): unknowns of level l that are new, or whose nodal basis function changed
+// from level l-1. In the level-l basis phi_{k,l-1} = sum_i P[i,k] phi_{i,l}; an unknown that
+// already existed has the single entry 1 in its row of P_l, and its function is unchanged
+// exactly when that entry is alone in its column.
+void build_local_sets(Hierarchy &h) {
+  h.local_set.clear();
+  for (int l = h.lc + 1; l <= h.J; ++l) {
+    const Csr &P = h.P.at(l);
+    std::vector<int32_t> colcount(P.ncols, 0);
+    for (int32_t c : P.ci) ++colcount[c];
+    std::vector<uint8_t> m(P.nrows, 1);
+    for (int64_t i = 0; i < P.nrows; ++i) {
+      const bool old = P.rp[i + 1] - P.rp[i] == 1 && P.v[P.rp[i]] == 1.0;
+      if (old) m[i] = colcount[P.ci[P.rp[i]]] > 1;
+    }
+    h.local_set[l] = std::move(m);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // bottom of the V-cycle: Cholesky factor A_lc = L L^T and the explicit inverse
 // ---------------------------------------------------------------------------

@@ -83,6 +83,7 @@ struct Hierarchy {
   Csr Pi;                             // fine unknowns x level-J unknowns
   std::vector<int32_t> colour_fine;
   std::unordered_map<int, std::vector<int32_t>> colour_aux;  // lc+1..J
+  std::unordered_map<int, std::vector<uint8_t>> local_set;   // N~_l, lc+1..J (1 = smoothed locally)
   int64_t nc = 0;
   std::vector<double> coarse_inv;     // nc * nc, row-major, explicit inverse of A_lc
 
@@ -97,6 +98,7 @@ void build_levels(Hierarchy &h);
 void assemble_aux_values(Hierarchy &h);
 void build_transfer(Hierarchy &h);
 void build_colourings(Hierarchy &h);
+void build_local_sets(Hierarchy &h);
 void build_coarse(Hierarchy &h);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
 // position of every unknown of the original grid in Morton order of its vertex (device layout)

@@ -43,6 +43,9 @@ def test_rejects_invalid_input():
     assert e.value.code == A.EINVAL
     with pytest.raises(A.AsmgError):
         A.Solver(coords, elems, k, device=-1, nu_aux=0)
+    with pytest.raises(A.AsmgError) as e:
+        A.Solver(coords, elems, k, device=-1, smoothing=2)
+    assert e.value.code == A.EINVAL
 
 
 def test_host_only_handle_refuses_device_calls():
@@ -83,3 +86,7 @@ def test_batch_setup_host_only():
     bad = [(m["coords"], m["elems"], -m["kappa"]) for m in meshes]
     with pytest.raises(A.AsmgError):
         A.BatchSolver(bad, device=-1)
+    # local smoothing is a single-mesh option
+    with pytest.raises(A.AsmgError) as e:
+        A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes], device=-1, smoothing=1)
+    assert e.value.code == A.EINVAL

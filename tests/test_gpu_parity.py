@@ -28,28 +28,52 @@ def _graded_cube():
     coords, elems, _ = W.kuhn_cube_mesh(8, 0.1, cfg=2, item=3)
     c = dict(coords=coords ** 2, elems=elems, kappa=np.random.default_rng(0).uniform(0.5, 2, len(elems)))
     c["f_vertex"] = W.rhs_per_vertex(len(coords), 2, 3)
-    return c, 3, 0
+    return c, 3, 0, 0
 
 
-# name -> (workload, n_min (0 = default), colouring: 0 natural order, 2 smallest-last)
+# name -> (workload, n_min (0 = default), colouring: 0 natural order, 2 smallest-last,
+#          smoothing: 0 whole auxiliary levels, 1 local on N~_l)
 CASES = {
-    "square64": lambda: (W.make_config(0), 0, 0),
-    "graded20k": lambda: (W.make_config(1, scale=0.01), 0, 0),
-    "cube16": lambda: (W.make_config(2, scale=1 / 8), 0, 0),
+    "square64": lambda: (W.make_config(0), 0, 0, 0),
+    "graded20k": lambda: (W.make_config(1, scale=0.01), 0, 0, 0),
+    "cube16": lambda: (W.make_config(2, scale=1 / 8), 0, 0, 0),
     "graded_cube": _graded_cube,
-    "graded20k_smallest_last": lambda: (W.make_config(1, scale=0.01), 0, 2),
-    "cube16_smallest_last": lambda: (W.make_config(2, scale=1 / 8), 0, 2),
+    "graded20k_smallest_last": lambda: (W.make_config(1, scale=0.01), 0, 2, 0),
+    "cube16_smallest_last": lambda: (W.make_config(2, scale=1 / 8), 0, 2, 0),
+    "graded20k_local": lambda: (W.make_config(1, scale=0.01), 0, 2, 1),
+    "graded_cube_local": lambda: _graded_cube()[:2] + (2, 1),
 }
 ORACLE_COLOURING = {0: "natural", 2: "smallest_last"}
+ORACLE_SMOOTHING = {0: "full", 1: "local"}
+
+
+class _Oracle:
+    """The oracle hierarchy with the case's smoothing as the default of preconditioner() and solve()."""
+
+    def __init__(self, H, smoothing):
+        self._H, self._sm = H, smoothing
+
+    def __getattr__(self, k):
+        return getattr(self._H, k)
+
+    def preconditioner(self, *a, **kw):
+        kw.setdefault("smoothing", self._sm)
+        return self._H.preconditioner(*a, **kw)
+
+    def solve(self, *a, **kw):
+        kw.setdefault("smoothing", self._sm)
+        return self._H.solve(*a, **kw)
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     _say(f"[gpu parity] case {request.param}")
-    c, n_min, col = CASES[request.param]()
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col])
-    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col)
-    S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED, colouring=col)
+    c, n_min, col, sm = CASES[request.param]()
+    H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col]),
+                ORACLE_SMOOTHING[sm])
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col, smoothing=sm)
+    S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED, colouring=col,
+                   smoothing=sm)
     f = c["f_vertex"][H.dofs]
     return request.param, c, H, S64, S32, f
 

@@ -105,3 +105,13 @@ def test_colouring_modes_match(cfg, scale, mode):
     assert np.array_equal(S.export("colour_fine"), H.colour_fine)
     for l, col in H.colour_aux.items():
         assert np.array_equal(S.export("colour_aux", l), col)
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 0.003), (2, 0.0625)])
+def test_local_sets_match(cfg, scale):
+    from oracle import auxops
+    c = W.make_config(cfg, scale=scale)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, smoothing=1)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
+    for l in range(H.aux.lc + 1, H.aux.J + 1):
+        assert np.array_equal(S.export("local_set", l).astype(bool), auxops.local_set(H.aux.P[l])), l
