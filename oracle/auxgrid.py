@@ -76,7 +76,7 @@ def morton_order(X: np.ndarray) -> np.ndarray:
 class LevelMesh:
     """sigma^(l): integer vertices, simplices and unknown numbering of one level."""
 
-    def __init__(self, verts, simp, simp_box, simp_tmpl, boxes, box_fan, J, d):
+    def __init__(self, verts, simp, simp_box, simp_tmpl, boxes, box_fan, J, d, kept=None):
         self.verts = verts            # (nv, d) int64, Morton order
         self.simp = simp              # (ns, d+1) int64 into verts
         self.simp_box = simp_box      # (ns,) index into boxes
@@ -87,6 +87,13 @@ class LevelMesh:
         self.d = d
         top = 1 << J
         self.interior = np.all((verts > 0) & (verts < top), axis=1)
+        # general domain (Section 3.4): only the kept simplices form the grid, and an unknown
+        # needs its whole star kept
+        self.kept = np.ones(len(simp), dtype=bool) if kept is None else np.asarray(kept, dtype=bool)
+        if kept is not None:
+            bad = np.zeros(len(verts), dtype=bool)
+            bad[simp[~self.kept].ravel()] = True
+            self.interior &= ~bad
         self.dof_of_vert = np.full(len(verts), -1, dtype=np.int64)
         self.dof_vert = np.nonzero(self.interior)[0]
         self.dof_of_vert[self.dof_vert] = np.arange(len(self.dof_vert))
@@ -96,12 +103,13 @@ class LevelMesh:
 class AuxMeshes:
     """All level meshes sigma^(1..J) of a closed box tree."""
 
-    def __init__(self, tree):
+    def __init__(self, tree, domain=None):
         self.tree = tree
         self.d = tree.d
         self.J = tree.J
         self.R = tree.R
         self.offs = touch_offsets(self.d)
+        self.domain = domain          # oracle.domain.Domain, or None for the root box
         self._cache = {}
 
     # -- geometry ------------------------------------------------------------
@@ -265,7 +273,10 @@ class AuxMeshes:
         rank[order] = np.arange(len(order))
         verts = uniq[order]
         simp = rank[inv.ravel()].reshape(len(simps), d + 1)
-        lm = LevelMesh(verts, simp, np.array(sbox), np.array(stmpl), boxes, np.array(fan), self.J, d)
+        kept = None
+        if self.domain is not None:
+            kept = np.array([self.domain.keeps(self.tree, verts[t]) for t in simp], dtype=bool)
+        lm = LevelMesh(verts, simp, np.array(sbox), np.array(stmpl), boxes, np.array(fan), self.J, d, kept)
         self._cache[level] = lm
         return lm
 

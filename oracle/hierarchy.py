@@ -1,5 +1,9 @@
 """Everything the solve needs for one mesh, assembled by the oracle modules.
 
+``domain="box"`` builds the Dirichlet auxiliary grids on the root box (every simplex of
+sigma^(l)); ``domain="mesh"`` keeps only the simplices inside the mesh's own domain
+(``domain``, 2-D).
+
 ``Hierarchy(coords, elems, kappa)`` builds the fine matrix (``fem``), the closed
 box tree (``cluster``), the level meshes (``auxgrid``), the auxiliary operators
 (``auxops``), the transfer Pi (``transfer``) and the colourings (``colour``).
@@ -14,7 +18,7 @@ from . import asmg, auxgrid, auxops, cluster, colour, fem, pcg, transfer
 
 class Hierarchy:
     def __init__(self, coords, elems, kappa, dirichlet=None, n_min=None, coarse_max_dofs=1024,
-                 colour_seed=0, check_literal=False, colouring="smallest_last"):
+                 colour_seed=0, check_literal=False, colouring="smallest_last", domain="box"):
         coords = np.asarray(coords, dtype=np.float64)
         elems = np.asarray(elems, dtype=np.int64)
         self.coords = coords
@@ -23,7 +27,13 @@ class Hierarchy:
         self.d = coords.shape[1]
         self.A, self.dofs = fem.assemble(coords, elems, self.kappa, dirichlet)
         self.tree = cluster.BoxTree(coords, elems, n_min, check_literal=check_literal)
-        self.meshes = auxgrid.AuxMeshes(self.tree)
+        if domain not in ("box", "mesh"):
+            raise ValueError(domain)
+        dom = None
+        if domain == "mesh":       # Section 3.4 on the mesh's own (2-D polygonal) domain
+            from .domain import Domain
+            dom = Domain(coords, elems)
+        self.meshes = auxgrid.AuxMeshes(self.tree, dom)
         self.aux = auxops.AuxOperators(self.tree, self.meshes, self.kappa, coarse_max_dofs)
         self.Pi = transfer.transfer(self.tree, self.meshes, coords, elems, self.dofs)
         self.colour_fine = colour.greedy_colouring(self.A, colour_seed, colouring)

@@ -147,6 +147,91 @@ def square_mesh(n: int, jitter: float = 0.3, cfg: int = 0, item: int = 0,
 
 
 # ----------------------------------------------------------------------------
+# 2-D meshes of non-box domains (the general-domain Dirichlet grids of Section 3.4)
+# ----------------------------------------------------------------------------
+
+
+def mesh_boundary(elems: np.ndarray, n_vertices: int) -> np.ndarray:
+    """Vertices on an edge that belongs to a single triangle."""
+    e = np.sort(np.concatenate([elems[:, [0, 1]], elems[:, [1, 2]], elems[:, [2, 0]]]), axis=1)
+    u, c = np.unique(e, axis=0, return_counts=True)
+    m = np.zeros(n_vertices, dtype=bool)
+    m[u[c == 1].ravel()] = True
+    return m
+
+
+def _compact(coords, elems):
+    used = np.unique(elems.ravel())
+    new = np.full(len(coords), -1, dtype=np.int64)
+    new[used] = np.arange(len(used))
+    return coords[used], new[elems].astype(np.int32)
+
+
+def _jitter_interior(coords, elems, h, jitter, cfg, item, min_angle=5.0):
+    bnd = mesh_boundary(elems, len(coords))
+    idx = np.nonzero(~bnd)[0]
+    base = coords.copy()
+    coords = coords.copy()
+    coords[idx] += rng(cfg, S_JITTER, item).uniform(-jitter * h, jitter * h, (len(idx), 2))
+    rep = rng(cfg, S_REPAIR, item)
+    for _ in range(100):
+        bad = triangle_min_angles(coords, elems) < min_angle
+        if not bad.any():
+            return coords
+        nodes = np.unique(elems[bad].ravel())
+        nodes = nodes[~bnd[nodes]]
+        coords[nodes] = base[nodes] + rep.uniform(-jitter * h, jitter * h, (len(nodes), 2))
+    raise RuntimeError("repair did not converge")
+
+
+def lshape_mesh(n: int, jitter: float = 0.3, cfg: int = 5, item: int = 0):
+    """L-shaped domain [0,1]^2 minus (1/2,1)^2: the square mesh of side n (n even) without the
+    cells of the removed quadrant; interior vertices jittered as in ``square_mesh``.
+    Returns (coords, elems, dirichlet) with Dirichlet data on the whole boundary."""
+    if n % 2:
+        raise ValueError("n must be even")
+    coords, elems, _ = square_mesh(n, 0.0, cfg=cfg, item=item)
+    cen = coords[elems].mean(axis=1)
+    keep = ~((cen[:, 0] > 0.5) & (cen[:, 1] > 0.5))
+    coords, elems = _compact(coords, elems[keep])
+    if jitter > 0:
+        coords = _jitter_interior(coords, elems, 1.0 / n, jitter, cfg, item)
+    return coords, elems, mesh_boundary(elems, len(coords))
+
+
+def annulus_mesh(n: int, r_in: float = 0.2, r_out: float = 0.5, cfg: int = 6, item: int = 0):
+    """Annulus centred at (1/2, 1/2): n points on the outer circle, proportionally fewer on the
+    inner one, jittered interior points at spacing ~ 2 pi r_out / n, Delaunay, triangles with
+    centroid in the hole dropped. Its polygonal boundary lies on no dyadic line.
+    Returns (coords, elems, dirichlet) with Dirichlet data on both boundary circles."""
+    from scipy.spatial import Delaunay
+    h = 2 * np.pi * r_out / n
+    c = np.array([0.5, 0.5])
+    t_out = 2 * np.pi * np.arange(n) / n
+    n_in = max(8, int(round(n * r_in / r_out)))
+    t_in = 2 * np.pi * (np.arange(n_in) + 0.5) / n_in
+    outer = c + r_out * np.stack([np.cos(t_out), np.sin(t_out)], 1)
+    inner = c + r_in * np.stack([np.cos(t_in), np.sin(t_in)], 1)
+    g = np.arange(-r_out, r_out + h, h)
+    X, Y = np.meshgrid(g, g)
+    P = np.stack([X.ravel(), Y.ravel()], 1)
+    P += rng(cfg, S_JITTER, item).uniform(-0.25 * h, 0.25 * h, P.shape)
+    r = np.hypot(P[:, 0], P[:, 1])
+    P = c + P[(r < r_out - 0.5 * h) & (r > r_in + 0.5 * h)]
+    coords = np.concatenate([outer, inner, P])
+    tri = Delaunay(coords).simplices
+    cen = coords[tri].mean(axis=1)
+    rc = np.hypot(cen[:, 0] - 0.5, cen[:, 1] - 0.5)
+    elems = tri[rc > r_in * np.cos(np.pi / n_in)].astype(np.int32)
+    coords, elems = _compact(coords, elems)
+    # counter-clockwise orientation
+    a = coords[elems]
+    det = (a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1]) - (a[:, 1, 1] - a[:, 0, 1]) * (a[:, 2, 0] - a[:, 0, 0])
+    elems[det < 0] = elems[det < 0][:, [0, 2, 1]]
+    return coords, elems, mesh_boundary(elems, len(coords))
+
+
+# ----------------------------------------------------------------------------
 # 2-D graded Delaunay mesh
 # ----------------------------------------------------------------------------
 
