@@ -70,6 +70,11 @@ typedef struct {
                           default); 1 = local, only the unknowns of N~_l, the index set of the
                           decomposition of Section 4.3 (new on level l, or with a basis function
                           that changed from level l-1). Single-mesh handles only. */
+  int domain;          /* Dirichlet auxiliary grids (Section 3.4): 0 = every simplex of the root box
+                          (default; the domain is the mesh's bounding box); 1 = only the simplices
+                          inside the mesh's own domain, the closed union of its triangles (2-D,
+                          any polygon, holes allowed); with a null `dirichlet` the Dirichlet
+                          vertices are then the mesh's boundary vertices. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */

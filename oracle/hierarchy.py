@@ -25,6 +25,9 @@ class Hierarchy:
         self.elems = elems
         self.kappa = np.asarray(kappa, dtype=np.float64)
         self.d = coords.shape[1]
+        if domain == "mesh" and dirichlet is None:
+            from .domain import boundary_vertices
+            dirichlet = boundary_vertices(elems, len(coords))
         self.A, self.dofs = fem.assemble(coords, elems, self.kappa, dirichlet)
         self.tree = cluster.BoxTree(coords, elems, n_min, check_literal=check_literal)
         if domain not in ("box", "mesh"):

@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("n_min", ctypes.c_int), ("nu_aux", ctypes.c_int), ("nu_fine", ctypes.c_int),
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int)]
+                ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int)]
 
 
 def _load():
@@ -107,7 +107,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0):
+                 colouring=2, smoothing=0, domain=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         kappa = np.ascontiguousarray(kappa, dtype=np.float64)
@@ -121,6 +121,7 @@ class Solver:
         opt.colour_seed, opt.device, opt.check_every = colour_seed, device, check_every
         opt.colouring = colouring
         opt.smoothing = smoothing
+        opt.domain = domain
         self.precision = precision
         self.device = device
         dptr = None

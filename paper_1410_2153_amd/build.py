@@ -1,8 +1,9 @@
 """Build the HIP/C++ shared library libasmg.so for gfx950 (in-tree, under _lib/).
 
-Sources: csrc/setup.cpp (host setup), csrc/api.cpp (C ABI), csrc/device.hip
-(kernels and PCG driver). The host setup is compiled without floating-point
-contraction, so barycenters and box keys are plain IEEE operations.
+Sources: csrc/setup.cpp (host setup), csrc/domain.cpp (general-domain predicates),
+csrc/api.cpp (C ABI), csrc/device.hip and csrc/batch.hip (kernels and PCG drivers).
+The host setup is compiled without floating-point contraction, so barycenters, box
+keys and the exact orientation predicates are plain IEEE operations.
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     objs = []
-    for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("api.cpp", [])):
+    for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("domain.cpp", ["-ffp-contract=off"]), ("api.cpp", [])):
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -102,6 +102,7 @@ int asmg_default_options(asmg_options *o) {
   o->check_every = 0;
   o->colouring = 2;
   o->smoothing = 0;
+  o->domain = 0;
   return ASMG_OK;
 }
 
@@ -118,7 +119,8 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (opt) o = *opt;
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1)
+      o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 1 ||
+      (o.domain == 1 && dim != 2))
     return set_err(ASMG_EINVAL, "invalid options");
   for (int64_t i = 0; i < n_vertices * dim; ++i)
     if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
@@ -149,6 +151,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     build_fine(h);
     lap("fine");
     build_tree(h);
+    if (o.domain == 1) build_domain(h);
     lap("tree");
     build_levels(h);
     lap("levels");
@@ -272,7 +275,7 @@ int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *st
 static int check_options(const asmg_options &o) {
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 2)
+      o.colouring > 2 || o.domain < 0 || o.domain > 1)
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
   return ASMG_OK;
@@ -284,6 +287,7 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
   *out = nullptr;
   if (n_meshes < 1 || (dim != 2 && dim != 3) || !vert_off || !coords || !elem_off || !elems || !kappa)
     return set_err(ASMG_EINVAL, "bad batch arguments");
+  if (opt && opt->domain == 1 && dim != 2) return set_err(ASMG_EINVAL, "general domains are 2-D");
   asmg_options o;
   asmg_default_options(&o);
   if (opt) o = *opt;
@@ -320,6 +324,7 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
           h->kappa.assign(kappa + elem_off[m], kappa + elem_off[m + 1]);
           build_fine(*h);
           build_tree(*h);
+          if (o.domain == 1) build_domain(*h);
           build_levels(*h);
           build_transfer(*h);
           build_colourings(*h);
@@ -421,6 +426,13 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
     if (name == "level_verts") return put(level_mesh(h, level).verts, buf, count);
     if (name == "level_simp") return put(level_mesh(h, level).simp, buf, count);
     if (name == "level_dofs") return put(level_mesh(h, level).dof_vert, buf, count);
+    if (name == "level_kept") {
+      const LevelMesh &lm = level_mesh(h, level);
+      std::vector<int64_t> k(lm.simp_box.size(), 1);
+      if (!lm.kept.empty())
+        for (size_t i = 0; i < k.size(); ++i) k[i] = lm.kept[i];
+      return put(k, buf, count);
+    }
     if (name == "local_set") {
       auto it = h.local_set.find(level);
       if (it == h.local_set.end()) return set_err(ASMG_EINVAL, "no smoothed level there");

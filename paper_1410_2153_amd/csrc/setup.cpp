@@ -216,6 +216,24 @@ void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]) {
 
 void build_fine(Hierarchy &h) {
   const int d = h.d;
+  if (h.dirichlet.empty() && h.opt.domain == 1) {
+    // the mesh's own domain: Dirichlet data on its boundary vertices (edges of one triangle)
+    std::vector<std::pair<int64_t, int64_t>> e;
+    for (int64_t t = 0; t < h.ne; ++t)
+      for (int i = 0; i <= d; ++i)
+        for (int j = i + 1; j <= d; ++j) {
+          int64_t a = h.elems[t * (d + 1) + i], b = h.elems[t * (d + 1) + j];
+          e.push_back({std::min(a, b), std::max(a, b)});
+        }
+    std::sort(e.begin(), e.end());
+    h.dirichlet.assign(h.nv, 0);
+    for (size_t i = 0; i < e.size();) {
+      size_t j = i;
+      while (j < e.size() && e[j] == e[i]) ++j;
+      if (j - i == 1) h.dirichlet[e[i].first] = h.dirichlet[e[i].second] = 1;
+      i = j;
+    }
+  }
   if (h.dirichlet.empty()) {
     double lo[3], hi[3];
     for (int k = 0; k < d; ++k) lo[k] = hi[k] = h.coords[k];
@@ -680,9 +698,18 @@ static LevelMesh make_level_mesh(const Hierarchy &h, int level) {
   for (int64_t s = 0; s < ns; ++s) lm.box_simp[lm.simp_box[s] + 1]++;
   for (size_t i = 0; i < lm.boxes.size(); ++i) lm.box_simp[i + 1] += lm.box_simp[i];
   const int64_t top = (int64_t)1 << J;
+  // general domain (Section 3.4): keep the simplices inside the domain; an unknown needs its
+  // whole star kept
+  std::vector<uint8_t> outside(nv, 0);
+  if (h.domain) {
+    lm.kept = domain_keeps(h, lm);
+    for (int64_t s = 0; s < ns; ++s)
+      if (!lm.kept[s])
+        for (int i = 0; i <= d; ++i) outside[lm.simp[s * (d + 1) + i]] = 1;
+  }
   lm.dof_of_vert.assign(nv, -1);
   for (int64_t v = 0; v < nv; ++v) {
-    bool in = true;
+    bool in = !outside[v];
     for (int q = 0; q < d; ++q) {
       int64_t x = lm.verts[v * d + q];
       in = in && x > 0 && x < top;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -41,11 +42,14 @@ struct LevelMesh {
   std::vector<uint8_t> fan;         // fan flag per box
   std::vector<int64_t> box_simp;    // simplex range per box (nb + 1)
   std::unordered_map<BoxCode, int32_t> box_index;
+  std::vector<uint8_t> kept;        // general domain: simplex inside the domain (empty = all kept)
   std::vector<int64_t> dof_vert;    // vertex index of each unknown
   std::vector<int64_t> dof_of_vert; // unknown index of each vertex (-1 on the boundary)
   int64_t nverts() const { return (int64_t)dof_of_vert.size(); }
   int64_t n() const { return (int64_t)dof_vert.size(); }
 };
+
+struct DomainIndex;  // boundary edges and bucket grids of a general 2-D domain (domain.cpp)
 
 struct Hierarchy {
   // input
@@ -75,6 +79,7 @@ struct Hierarchy {
   int J = 1;
 
   // auxiliary hierarchy (Sections 3.3-3.4, 4.1)
+  std::shared_ptr<DomainIndex> domain;  // general domain (option domain = 1), else null
   std::unordered_map<int, LevelMesh> meshes;
   std::vector<int64_t> level_n;       // unknowns of levels 1..J (index level-1)
   int lc = 1;
@@ -99,6 +104,8 @@ void assemble_aux_values(Hierarchy &h);
 void build_transfer(Hierarchy &h);
 void build_colourings(Hierarchy &h);
 void build_local_sets(Hierarchy &h);
+void build_domain(Hierarchy &h);
+std::vector<uint8_t> domain_keeps(const Hierarchy &h, const LevelMesh &lm);
 void build_coarse(Hierarchy &h);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
 // position of every unknown of the original grid in Morton order of its vertex (device layout)

@@ -46,6 +46,13 @@ def test_rejects_invalid_input():
     with pytest.raises(A.AsmgError) as e:
         A.Solver(coords, elems, k, device=-1, smoothing=2)
     assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError) as e:
+        A.Solver(coords, elems, k, device=-1, domain=2)
+    assert e.value.code == A.EINVAL
+    c3, e3, _ = W.kuhn_cube_mesh(3, 0.0)
+    with pytest.raises(A.AsmgError) as e:   # general domains are 2-D
+        A.Solver(c3, e3, np.ones(len(e3)), device=-1, domain=1)
+    assert e.value.code == A.EINVAL
 
 
 def test_host_only_handle_refuses_device_calls():

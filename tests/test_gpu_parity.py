@@ -31,8 +31,15 @@ def _graded_cube():
     return c, 3, 0, 0
 
 
+def _general(gen):
+    coords, elems, _ = gen()
+    c = dict(coords=coords, elems=elems, kappa=np.exp(np.random.default_rng(2).normal(0, 0.5, len(elems))))
+    c["f_vertex"] = W.rhs_per_vertex(len(coords), 5, 1)
+    return c, 0, 2, 0, 1
+
+
 # name -> (workload, n_min (0 = default), colouring: 0 natural order, 2 smallest-last,
-#          smoothing: 0 whole auxiliary levels, 1 local on N~_l)
+#          smoothing: 0 whole auxiliary levels, 1 local on N~_l[, domain: 0 root box, 1 mesh domain])
 CASES = {
     "square64": lambda: (W.make_config(0), 0, 0, 0),
     "graded20k": lambda: (W.make_config(1, scale=0.01), 0, 0, 0),
@@ -42,6 +49,8 @@ CASES = {
     "cube16_smallest_last": lambda: (W.make_config(2, scale=1 / 8), 0, 2, 0),
     "graded20k_local": lambda: (W.make_config(1, scale=0.01), 0, 2, 1),
     "graded_cube_local": lambda: _graded_cube()[:2] + (2, 1),
+    "lshape_domain": lambda: _general(lambda: W.lshape_mesh(96, 0.3)),
+    "annulus_domain": lambda: _general(lambda: W.annulus_mesh(400)),
 }
 ORACLE_COLOURING = {0: "natural", 2: "smallest_last"}
 ORACLE_SMOOTHING = {0: "full", 1: "local"}
@@ -68,12 +77,13 @@ class _Oracle:
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     _say(f"[gpu parity] case {request.param}")
-    c, n_min, col, sm = CASES[request.param]()
-    H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col]),
-                ORACLE_SMOOTHING[sm])
-    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col, smoothing=sm)
+    c, n_min, col, sm, *rest = CASES[request.param]()
+    dom = rest[0] if rest else 0
+    H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col],
+                          domain=["box", "mesh"][dom]), ORACLE_SMOOTHING[sm])
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col, smoothing=sm, domain=dom)
     S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED, colouring=col,
-                   smoothing=sm)
+                   smoothing=sm, domain=dom)
     f = c["f_vertex"][H.dofs]
     return request.param, c, H, S64, S32, f
 

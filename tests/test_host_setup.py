@@ -18,19 +18,28 @@ def _graded_cube():
     return dict(coords=coords ** 2, elems=elems, kappa=np.random.default_rng(0).uniform(0.5, 2, len(elems))), 3
 
 
+def _general(gen):
+    coords, elems, _ = gen()
+    k = np.exp(np.random.default_rng(2).normal(0, 0.5, len(elems)))
+    return dict(coords=coords, elems=elems, kappa=k), 0, 1
+
+
 CASES = {
-    "square64": lambda: (W.make_config(0), 0),
-    "graded": lambda: (W.make_config(1, scale=0.004), 0),
-    "cube8": lambda: (W.make_config(2, scale=1 / 16), 0),
-    "graded_cube": _graded_cube,
+    "square64": lambda: (W.make_config(0), 0, 0),
+    "graded": lambda: (W.make_config(1, scale=0.004), 0, 0),
+    "cube8": lambda: (W.make_config(2, scale=1 / 16), 0, 0),
+    "graded_cube": lambda: _graded_cube() + (0,),
+    "square64_meshdomain": lambda: (W.make_config(0), 0, 1),
+    "lshape": lambda: _general(lambda: W.lshape_mesh(24, 0.3)),
+    "annulus": lambda: _general(lambda: W.annulus_mesh(64)),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
-    c, n_min = CASES[request.param]()
-    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min)
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min)
+    c, n_min, dom = CASES[request.param]()
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min, domain=dom)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, domain=["box", "mesh"][dom])
     return c, S, H
 
 
@@ -52,6 +61,7 @@ def test_level_meshes(pair):
         assert np.array_equal(S.export("level_verts", l).reshape(-1, d), lm.verts)
         assert np.array_equal(S.export("level_simp", l).reshape(-1, d + 1), lm.simp)
         assert np.array_equal(S.export("level_dofs", l), lm.dof_vert)
+        assert np.array_equal(S.export("level_kept", l).astype(bool), lm.kept)
 
 
 def _same_pattern(X, Y):
