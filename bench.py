@@ -170,6 +170,40 @@ def cube3d(steps: int, colouring: int = 2):
     return res
 
 
+def annulus(steps: int, colouring: int = 2):
+    """General-domain workload (Section 3.4 Dirichlet grids on the mesh's own domain): an annulus
+    (radii 0.2 and 0.5) of about 0.87 M vertices, kappa = exp(N(0, 0.5^2)), f ~ U[-1, 1]."""
+    import torch
+
+    import paper_1410_2153_amd as A
+    import workloads as W
+    t0 = time.perf_counter()
+    coords, elems, dirichlet = W.annulus_mesh(3600)
+    kappa = np.exp(W.rng(6, W.S_COEF, 0).normal(0.0, 0.5, len(elems)))
+    f_vertex = W.rhs_per_vertex(len(coords), 6, 0)
+    log(f"annulus: mesh {len(coords)} vertices in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    S = A.Solver(coords, elems, kappa, dirichlet, colouring=colouring, domain=1)
+    t_setup = time.perf_counter() - t0
+    dofs = S.dof_vertex()
+    f = torch.from_numpy(np.ascontiguousarray(f_vertex[dofs])).cuda()
+    res = {"workload": f"annulus r in [0.2, 0.5], {len(coords)} vertices, {len(elems)} triangles, "
+                       "kappa=exp(N(0,0.5^2)), Dirichlet grids on the mesh domain",
+           "unknowns": S.n, "setup_s": t_setup, "J": S.info()["J"]}
+    for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
+        S.set_precision(prec)
+        u, it, tr = S.solve_device(f, 1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            u, it, tr = S.solve_device(f, 1e-8, out=u)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        res[name] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr}
+        log(f"annulus {name}: {dt * 1e3:.2f} ms/solve, {it} iterations ({S.n / dt:.3e} DOF-solves/s)")
+    return res
+
+
 def adjoint(steps: int, colouring: int = 2):
     """Adjoint gradient workload: 724^2 jittered square, m ~ N(0, 0.3^2) per element; one step is
     coefficient update + forward solve + adjoint solve + element gradient."""
@@ -226,7 +260,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 3-D and adjoint workloads")
-    ap.add_argument("--only", choices=["batched", "cube3d", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["batched", "cube3d", "adjoint", "annulus"], default=None,
                     help="run only this secondary workload and print its record (for profiling it alone)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
@@ -250,6 +284,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps({"adjoint": adjoint(args.steps, args.colouring)}))
+        return
+    if args.only == "annulus":
+        print(json.dumps({"annulus": annulus(args.steps, args.colouring)}))
         return
     t0 = time.perf_counter()
     c = load_workload(args.scale)
@@ -350,6 +387,7 @@ def main():
     if not args.no_extra:
         out["cube3d"] = cube3d(args.steps, args.colouring)
         out["adjoint"] = adjoint(args.steps, args.colouring)
+        out["annulus"] = annulus(args.steps, args.colouring)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
