@@ -118,6 +118,9 @@ def batched(n_meshes: int, steps: int):
             f"iterations <= {its.max()}")
     ms_b, by_b = B.time_preconditioner(4, reps=5, precision=A.PREC_FP64)
     res["preconditioner_fp64_4rhs"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6}
+    shapes = B.tuned_shapes(4, A.PREC_FP64)
+    res["tuned_launch_shapes_fp64_4rhs"] = {f"{t}x{'xcd' if x else 'rr'}": int(((shapes[:, 0] == t) & (shapes[:, 1] == x)).sum())
+                                            for t, x in sorted(set(map(tuple, shapes.tolist())))}
     del B
     # same systems solved one at a time with the single-mesh engine, on a sample of meshes
     sample = list(range(0, n_meshes, max(1, n_meshes // 16)))

@@ -194,6 +194,12 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "Pi_rowptr","Pi_col" int64, "Pi_val" double   Pi (fine unknowns x aux unknowns of level J)
  *   "colour_fine"   int64 colour of every fine unknown
  *   "colour_aux"    int64 colour of every unknown of A_level (lc < level <= J)
+ *   "local_set"     int64 0/1 per unknown of level `level` (lc < level <= J): member of N~_l
+ *   "level_kept"    int64 0/1 per simplex of sigma^(level): kept in the Dirichlet grid
+ * Batch handles: "batch_n", "batch_J", "batch_lc" (int64 per mesh) and "batch_shapes"
+ * (level = n_rhs + 8 * precision): (threads per block, XCD order) pairs chosen by the
+ * launch-shape autotuner for every slice-kernel launch site of B_co, empty before the first
+ * solve with that n_rhs and precision.
  * Returns ASMG_EINVAL for an unknown name or level.
  */
 int asmg_export(asmg_handle h, const char *name, int level, void *buf, int64_t *count);

@@ -281,6 +281,16 @@ class BatchSolver:
 
     __del__ = close
 
+    def tuned_shapes(self, n_rhs, precision=PREC_FP64):
+        """(threads per block, XCD order) picked by the autotuner per slice-kernel launch site."""
+        cnt = ctypes.c_int64()
+        lvl = n_rhs + 8 * precision
+        _check(lib.asmg_export(self.h, b"batch_shapes", lvl, None, ctypes.byref(cnt)))
+        buf = np.empty(cnt.value, dtype=np.int64)
+        if cnt.value:
+            _check(lib.asmg_export(self.h, b"batch_shapes", lvl, _ptr(buf), ctypes.byref(cnt)))
+        return buf.reshape(-1, 2)
+
     def offsets(self, n_rhs):
         o = np.zeros(self.n_meshes + 1, dtype=np.int64)
         o[1:] = np.cumsum(self.n_per_mesh * n_rhs)

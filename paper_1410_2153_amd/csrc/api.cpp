@@ -384,12 +384,16 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
   const std::string name(name_c);
   ASMG_TRY({
     if (H->is_batch()) {
+      if (name == "batch_shapes") {  // level = NR + 8 * precision
+        if (!H->bdev) return set_err(ASMG_EINVAL, "host-only batch handle");
+        return put(batch_tuned_shapes(H->bdev, level % 8, level / 8), buf, count);
+      }
       if (name == "batch_n" || name == "batch_J" || name == "batch_lc") {
         std::vector<int64_t> v;
         for (auto &hp : H->batch) v.push_back(name == "batch_n" ? hp->n() : name == "batch_J" ? hp->J : hp->lc);
         return put(v, buf, count);
       }
-      return set_err(ASMG_EINVAL, "batch handle exports: batch_n, batch_J, batch_lc");
+      return set_err(ASMG_EINVAL, "batch handle exports: batch_n, batch_J, batch_lc, batch_shapes");
     }
     if (name == "info") {
       std::vector<int64_t> v(16, 0);

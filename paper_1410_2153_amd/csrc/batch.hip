@@ -174,15 +174,26 @@ __device__ __forceinline__ int bwave_slice(int first) {
   return first + xcd_block() * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
+// Tunable launch shape of the V-cycle slice kernels: blocks of blockDim.x / 64 waves (one slice
+// per wave), taken in XCD-contiguous order (xcd = 1) or in dispatch order (xcd = 0).
+static constexpr int BS_MAX = 512;
+
+__device__ __forceinline__ int tuned_slice(int first, int xcd) {
+  const int wpb = (int)blockDim.x >> 6;
+  const int blk = xcd ? xcd_block() : (int)blockIdx.x;
+  return first + blk * wpb + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+}
+
 // MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j (dv_ = a_ii)
 // over slices [s0, s1), every right-hand side of a row at once
 template <int MODE, int NR, class T>
-__global__ __launch_bounds__(BS) void kb_sell(int s0, int s1, const int *__restrict__ srow,
-                                              const int *__restrict__ soff, const int *__restrict__ scol,
-                                              const T *__restrict__ sv, const T *__restrict__ dv_,
-                                              const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r) {
-  const int s = bwave_slice(s0);
+__global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__restrict__ srow,
+                                                  const int *__restrict__ soff, const int *__restrict__ scol,
+                                                  const T *__restrict__ sv, const T *__restrict__ dv_,
+                                                  const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
+                                                  int xcd) {
+  const int s = tuned_slice(s0, xcd);
   if (s >= s1) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
@@ -213,11 +224,12 @@ __global__ __launch_bounds__(BS) void kb_sell(int s0, int s1, const int *__restr
 // of a level whose smoothing starts from zero; the kernel also runs its first colour pass,
 // xs_i = y_i * id0_i with id0_i = 1/a_ii on colour-0 rows of their mesh and 0 elsewhere.
 template <int ADD, int FIRST, int NR, class T>
-__global__ __launch_bounds__(BS) void kb_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
-                                                   const int *__restrict__ scol, const T *__restrict__ sv,
-                                                   const T *__restrict__ x, T *__restrict__ y,
-                                                   const T *__restrict__ id0, T *__restrict__ xs) {
-  const int s = bwave_slice(0);
+__global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__restrict__ srow,
+                                                       const int *__restrict__ soff, const int *__restrict__ scol,
+                                                       const T *__restrict__ sv, const T *__restrict__ x,
+                                                       T *__restrict__ y, const T *__restrict__ id0,
+                                                       T *__restrict__ xs, int xcd) {
+  const int s = tuned_slice(0, xcd);
   if (s >= ns) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
@@ -759,6 +771,13 @@ struct BatchDevice {
   // byte model
   bool count_bytes = false;
   double bytes = 0;
+  // launch shapes of the V-cycle slice kernels, per (precision, NR) and launch site (the k-th
+  // slice-kernel launch of one B_co application), chosen by `tune`
+  std::vector<std::pair<int, int>> shape[2][5];  // (threads per block, xcd order)
+  bool tuned[2][5] = {{false}};
+  bool tuning = false;
+  int site = 0;
+  int shape_pi = 0, shape_nr = 1;
 };
 
 template <class T>
@@ -1337,6 +1356,52 @@ const float *bid0<float>(const BLevel &L) { return L.id0_32; }
 
 // Gauss-Seidel sweep over the colour groups of L. `first_done`: the sweep starts from zero and
 // its colour-0 pass was run by the kernel that produced b.
+// Candidate launch shapes: 128, 256 or 512 threads per block, XCD-contiguous or dispatch order.
+static const std::pair<int, int> kShapes[] = {{256, 1}, {128, 1}, {512, 1}, {256, 0}, {128, 0}, {512, 0}};
+static constexpr int kTuneReps = 5;
+
+// One slice-kernel launch site of B_co. launch(threads, xcd) enqueues the kernel over `nslices`
+// slices. While tuning, every candidate shape is timed (kTuneReps launches between HIP events,
+// after one untimed launch) and the fastest is kept for this site; the kernels tuned here have
+// no reductions, so every shape computes the same result. Otherwise the site's stored shape
+// (or the default) is used.
+template <class F>
+static void slice_launch(BatchDevice *dv, int nslices, hipStream_t s, F &&launch) {
+  auto &tab = dv->shape[dv->shape_pi][dv->shape_nr];
+  const int site = dv->site++;
+  if (nslices <= 0) return;
+  if (!dv->tuning) {
+    const auto sh = site < (int)tab.size() ? tab[site] : kShapes[0];
+    launch(sh.first, sh.second);
+    return;
+  }
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  float best = INFINITY;
+  std::pair<int, int> pick = kShapes[0];
+  for (const auto &sh : kShapes) {
+    launch(sh.first, sh.second);
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < kTuneReps; ++r) launch(sh.first, sh.second);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+    if (t < best) {
+      best = t;
+      pick = sh;
+    }
+  }
+  HIPCHECK(hipEventDestroy(e0));
+  HIPCHECK(hipEventDestroy(e1));
+  if ((int)tab.size() <= site) tab.resize(site + 1, kShapes[0]);
+  tab[site] = pick;
+  launch(pick.first, pick.second);  // leave the site's result in place
+}
+
+static inline int slice_blocks(int nslices, int threads) { return std::max(1, (nslices * 64 + threads - 1) / threads); }
+
 template <int NR, class T>
 static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool first_done, bool forward,
                     hipStream_t s) {
@@ -1346,9 +1411,10 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   const int C = (int)S.cslice.size() - 1;
   auto pass = [&](int c) {
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
-    if (s1 <= s0) return;
-    hipLaunchKernelGGL((kb_sell<0, NR, T>), dim3(nblk((int64_t)(s1 - s0) * 64)), dim3(BS), 0, s, s0, s1, S.srow,
-                       S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr);
+    slice_launch(dv, s1 - s0, s, [&](int th, int xcd) {
+      hipLaunchKernelGGL((kb_sell<0, NR, T>), dim3(slice_blocks(s1 - s0, th)), dim3(th), 0, s, s0, s1, S.srow,
+                         S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, xcd);
+    });
   };
   if (forward) {
     int c = 0;
@@ -1368,8 +1434,10 @@ template <int NR, class T>
 static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   if (L.nsmooth == 0) return;
   const BSell &S = L.sell;
-  hipLaunchKernelGGL((kb_sell<1, NR, T>), dim3(nblk((int64_t)S.nslices * 64)), dim3(BS), 0, s, 0, S.nslices, S.srow,
-                     S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L));
+  slice_launch(dv, S.nslices, s, [&](int th, int xcd) {
+    hipLaunchKernelGGL((kb_sell<1, NR, T>), dim3(slice_blocks(S.nslices, th)), dim3(th), 0, s, 0, S.nslices, S.srow,
+                       S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), xcd);
+  });
   if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
 }
 
@@ -1378,9 +1446,11 @@ static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
 template <int NR, int ADD, int FIRST, class T>
 static void b_spmv(BatchDevice *dv, const BSell &A, const T *x, T *y, BLevel *Lt, hipStream_t s) {
   if (A.nrows == 0) return;
-  hipLaunchKernelGGL((kb_sell_spmv<ADD, FIRST, NR, T>), dim3(nblk((int64_t)A.nslices * 64)), dim3(BS), 0, s,
-                     A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y, FIRST ? bid0<T>(*Lt) : (const T *)nullptr,
-                     FIRST ? BV<T>::x(*Lt) : (T *)nullptr);
+  slice_launch(dv, A.nslices, s, [&](int th, int xcd) {
+    hipLaunchKernelGGL((kb_sell_spmv<ADD, FIRST, NR, T>), dim3(slice_blocks(A.nslices, th)), dim3(th), 0, s,
+                       A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y,
+                       FIRST ? bid0<T>(*Lt) : (const T *)nullptr, FIRST ? BV<T>::x(*Lt) : (T *)nullptr, xcd);
+  });
   if (dv->count_bytes)
     dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD + FIRST) * (double)A.nrows) +
                  (FIRST ? (double)sizeof(T) * A.nrows : 0.0);
@@ -1409,6 +1479,9 @@ static void b_vcycle(BatchDevice *dv, int k, hipStream_t s) {
 template <int NR, class T>
 static void b_apply(BatchDevice *dv, const double *r, bool first_done, hipStream_t s) {
   BLevel &F = dv->fine;
+  dv->site = 0;
+  dv->shape_pi = sizeof(T) == 4 ? 1 : 0;
+  dv->shape_nr = NR;
   const T *b;
   if constexpr (sizeof(T) == 8) {
     b = r;
@@ -1451,6 +1524,24 @@ static void b_iteration(BatchDevice *dv, hipStream_t s) {
   b_tail<NR, T>(dv, s, true);
 }
 
+// Autotuner: one eager B_co application on the current right-hand side in which every slice
+// launch site times the candidate shapes and keeps the fastest (the solve that follows starts
+// from scratch, so what tuning leaves in the work vectors is overwritten).
+template <int NR, class T>
+static void b_tune(BatchDevice *dv, hipStream_t s) {
+  const int pi = sizeof(T) == 4 ? 1 : 0;
+  if (dv->tuned[pi][NR]) return;
+  dv->tuning = true;
+  try {
+    b_apply<NR, T>(dv, dv->r, false, s);
+  } catch (...) {
+    dv->tuning = false;
+    throw;
+  }
+  dv->tuning = false;
+  dv->tuned[pi][NR] = true;
+}
+
 template <int NR, class T>
 static void b_launch_iterations(BatchDevice *dv, int count, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
@@ -1482,6 +1573,7 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
   hipLaunchKernelGGL((kb_cg_init<NR>), dim3(dv->ew_blocks), dim3(BS), 0, s, dv->ew_r0, dv->ew_r1, dv->f, dv->r, dv->u,
                      dv->p, dv->partials);
   hipLaunchKernelGGL((kb_fin_init<NR>), dim3(nm), dim3(BS), 0, s, dv->ew_b0, dv->partials, tol, dv->ctl);
+  b_tune<NR, T>(dv, s);  // first solve of this (precision, NR): pick the launch shapes (r = f now)
   int hst[2];
   HIPCHECK(hipMemcpyAsync(hst, dv->ctl.active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -1622,5 +1714,15 @@ int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void 
 }
 
 int64_t batch_n_total(BatchDevice *dv) { return dv->dof_off.back(); }
+
+std::vector<int64_t> batch_tuned_shapes(BatchDevice *dv, int nr, int precision) {
+  std::vector<int64_t> out;
+  if (nr < 1 || nr > 4 || precision < 0 || precision > 1) return out;
+  for (const auto &sh : dv->shape[precision][nr]) {
+    out.push_back(sh.first);
+    out.push_back(sh.second);
+  }
+  return out;
+}
 
 }  // namespace asmg

@@ -18,5 +18,8 @@ int batch_device_solve(BatchDevice *dv, int n_rhs, const double *d_F, double tol
                        double *true_rel, void *stream);
 int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void *stream, double *ms, double *bytes);
 int64_t batch_n_total(BatchDevice *dv);
+// launch shapes picked by the autotuner for (NR, precision): threads per block and XCD order of
+// every slice-kernel launch site, flattened pairs (empty before the first solve)
+std::vector<int64_t> batch_tuned_shapes(BatchDevice *dv, int nr, int precision);
 
 }  // namespace asmg

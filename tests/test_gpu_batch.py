@@ -45,6 +45,10 @@ def test_batched_fp64_matches_oracle(batch, nr):
             assert its[m, r] == ito or near, (m, r, its[m, r], ito)
             assert err <= 1e-10, (m, r, err)
             assert tr[m, r] <= 1e-8 * (1 + 1e-6)
+    # the launch-shape autotuner ran on the first solve and picked a shape for every site
+    shapes = B.tuned_shapes(nr, A.PREC_FP64)
+    assert len(shapes) > 10
+    assert set(shapes[:, 0].tolist()) <= {128, 256, 512} and set(shapes[:, 1].tolist()) <= {0, 1}
 
 
 def test_batched_mixed(batch):
