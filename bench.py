@@ -57,7 +57,7 @@ def counter_traffic():
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    return rec.get("traffic_bytes_per_launch") if rec.get("device_hip_code_key") == source_key() else None
+    return rec.get("traffic_bytes_per_launch") if rec.get("kernel_code_key") == source_key() else None
 
 
 def cpu_baseline(budget_s: float = 20.0):
@@ -267,6 +267,9 @@ def main():
                     help="run only this secondary workload and print its record (for profiling it alone)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="0: fixed default launch shapes (hardware-counter runs, which would otherwise "
+                         "also count the autotuner's trial launches)")
     ap.add_argument("--colouring", type=int, default=2,
                     help="Gauss-Seidel colour order of the single-mesh solves: 0 natural, 1 hash, 2 smallest-last")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -295,7 +298,8 @@ def main():
     c = load_workload(args.scale)
     log(f"workload: {len(c['coords'])} vertices, {len(c['elems'])} triangles ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64, colouring=args.colouring)
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64, colouring=args.colouring,
+                   autotune=args.autotune)
     t_setup = time.perf_counter() - t0
     info = S64.info()
     log(f"setup {t_setup:.1f} s: {info}")
@@ -326,7 +330,7 @@ def main():
     diff = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
 
     # dominant kernel: the Gauss-Seidel colour pass (sliced ELL, FP64); every pass inside full B_co
-    # applications is timed between HIP events on torch's stream
+    # applications is timed by HIP events stamped with that launch's start and end, on torch's stream
     if args.no_kernel_timing:
         ms_gs = by_gs = ms_spmv = by_spmv = ms_b64 = by_b64 = ms_b32 = by_b32 = float("nan")
     else:
@@ -362,7 +366,7 @@ def main():
         # the same workload with local smoothing on N~_l (the decomposition of Section 4.3)
         t0 = time.perf_counter()
         SL = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64,
-                      colouring=args.colouring, smoothing=1)
+                      colouring=args.colouring, smoothing=1, autotune=args.autotune)
         t_setup_l = time.perf_counter() - t0
         loc = {"setup_s": t_setup_l}
         for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):

@@ -75,6 +75,9 @@ typedef struct {
                           inside the mesh's own domain, the closed union of its triangles (2-D,
                           any polygon, holes allowed); with a null `dirichlet` the Dirichlet
                           vertices are then the mesh's boundary vertices. */
+  int autotune;        /* 1 = at the first solve in a precision, time the candidate launch shapes
+                          of every V-cycle slice kernel and keep the fastest (default); 0 = fixed
+                          256-thread blocks in XCD order. Results do not depend on it. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -164,9 +167,9 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
  *   which: 0 = fine SpMV q = A p (FP64), 1 = fine Gauss-Seidel sweep (all colours),
  *          2 = one full B_co application, 3 = same as 2 in the precision set at setup,
  *          4 (or 5) = the Gauss-Seidel colour-pass kernel (sliced ELL): inside `reps`
- *          full B_co applications every colour pass is launched 10 times back to back
- *          between its own pair of HIP events (a pass is idempotent); *ms and *bytes
- *          are the mean per launch
+ *          full B_co applications every colour pass is launched once with a pair of HIP
+ *          events stamped with that launch's own start and end (hipExtLaunchKernel), so
+ *          caches are as in a solve; *ms and *bytes are the mean per launch
  * Algorithmic bytes count each matrix entry, row pointer and vector entry the
  * operation needs once (a colour pass: its rows, b, 1/diag, the x write, and each
  * distinct gathered x entry).
@@ -196,6 +199,9 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "colour_aux"    int64 colour of every unknown of A_level (lc < level <= J)
  *   "local_set"     int64 0/1 per unknown of level `level` (lc < level <= J): member of N~_l
  *   "level_kept"    int64 0/1 per simplex of sigma^(level): kept in the Dirichlet grid
+ *   "tuned_shapes"  int64 (threads per block, XCD order) per slice-kernel launch site of B_co
+ *                   chosen by the launch-shape autotuner (level = precision; device handles,
+ *                   empty before the first solve in that precision)
  * Batch handles: "batch_n", "batch_J", "batch_lc" (int64 per mesh) and "batch_shapes"
  * (level = n_rhs + 8 * precision): (threads per block, XCD order) pairs chosen by the
  * launch-shape autotuner for every slice-kernel launch site of B_co, empty before the first

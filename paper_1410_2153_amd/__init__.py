@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
     _fields_ = [("n_min", ctypes.c_int), ("nu_aux", ctypes.c_int), ("nu_fine", ctypes.c_int),
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int)]
+                ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 def _load():
@@ -97,6 +98,21 @@ def _tptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need_host(a, n, what):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 1 or a.shape[0] != n:
+        raise ValueError(f"{what} must be a 1-D array of {n} values, got shape {a.shape}")
+    return a
+
+
+def _need_device(t, n, what):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"{what} must be a contiguous float64 device tensor of {n} values")
+    return t
+
+
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -107,10 +123,12 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0, domain=0):
+                 colouring=2, smoothing=0, domain=0, autotune=1):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
-        kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        if coords.ndim != 2 or elems.ndim != 2 or elems.shape[1] != coords.shape[1] + 1:
+            raise ValueError("coords must be (n_vertices, d) and elems (n_elements, d + 1)")
+        kappa = _need_host(kappa, elems.shape[0], "kappa")
         self.dim = coords.shape[1]
         self.n_vertices = coords.shape[0]
         self.n_elements = elems.shape[0]
@@ -122,11 +140,14 @@ class Solver:
         opt.colouring = colouring
         opt.smoothing = smoothing
         opt.domain = domain
+        opt.autotune = autotune
         self.precision = precision
         self.device = device
         dptr = None
         if dirichlet is not None:
             self._dir = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+            if self._dir.shape != (coords.shape[0],):
+                raise ValueError("dirichlet must hold one flag per vertex")
             dptr = _ptr(self._dir)
         h = ctypes.c_void_p()
         _check(lib.asmg_setup(self.dim, self.n_vertices, _ptr(coords), self.n_elements, _ptr(elems), _ptr(kappa),
@@ -151,7 +172,7 @@ class Solver:
 
     def solve(self, f, tol=1e-8, allow_noconv=False):
         """Host arrays: returns (u, iterations, true relative residual)."""
-        f = np.ascontiguousarray(f, dtype=np.float64)
+        f = _need_host(f, self.n, "f")
         u = np.empty(self.n)
         it = ctypes.c_int()
         tr = ctypes.c_double()
@@ -165,20 +186,18 @@ class Solver:
 
     def set_coefficient_device(self, kappa):
         """Operator A from a device coefficient tensor; the auxiliary hierarchy is kept."""
-        import torch
-        assert kappa.is_cuda and kappa.dtype == torch.float64 and kappa.is_contiguous()
-        assert kappa.numel() == self.n_elements
+        _need_device(kappa, self.n_elements, "kappa")
         _check(lib.asmg_set_coefficient_device(self.h, _tptr(kappa), _stream()))
 
     def update_coefficient(self, kappa):
-        kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        kappa = _need_host(kappa, self.n_elements, "kappa")
         _check(lib.asmg_update_coefficient(self.h, _ptr(kappa)))
 
     # -- device tensors (torch) ---------------------------------------------
     def solve_device(self, f, tol=1e-8, out=None, allow_noconv=False):
         import torch
-        assert f.is_cuda and f.dtype == torch.float64 and f.is_contiguous() and f.numel() == self.n
-        u = torch.empty_like(f) if out is None else out
+        _need_device(f, self.n, "f")
+        u = torch.empty_like(f) if out is None else _need_device(out, self.n, "out")
         it = ctypes.c_int()
         tr = ctypes.c_double()
         _check(lib.asmg_solve_device(self.h, _tptr(f), tol, _tptr(u), ctypes.byref(it), ctypes.byref(tr), _stream()),
@@ -187,7 +206,7 @@ class Solver:
 
     def apply_preconditioner(self, r, precision=None):
         import torch
-        assert r.is_cuda and r.dtype == torch.float64 and r.is_contiguous() and r.numel() == self.n
+        _need_device(r, self.n, "r")
         z = torch.empty_like(r)
         prec = self.precision if precision is None else precision
         _check(lib.asmg_apply_preconditioner_device(self.h, _tptr(r), _tptr(z), prec, _stream()))
@@ -195,13 +214,15 @@ class Solver:
 
     def matvec(self, x):
         import torch
-        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n
+        _need_device(x, self.n, "x")
         y = torch.empty_like(x)
         _check(lib.asmg_matvec_device(self.h, _tptr(x), _tptr(y), _stream()))
         return y
 
     def element_gradient(self, u, lam):
         import torch
+        _need_device(u, self.n, "u")
+        _need_device(lam, self.n, "lam")
         g = torch.empty(self.n_elements, dtype=torch.float64, device=u.device)
         _check(lib.asmg_element_gradient_device(self.h, _tptr(u), _tptr(lam), _tptr(g), _stream()))
         return g
@@ -223,6 +244,10 @@ class Solver:
         if cnt.value:
             _check(lib.asmg_export(self.h, name.encode(), level, _ptr(buf), ctypes.byref(cnt)))
         return buf
+
+    def tuned_shapes(self, precision=PREC_FP64):
+        """(threads per block, XCD order) picked by the autotuner per slice-kernel launch site."""
+        return self.export("tuned_shapes", precision).reshape(-1, 2)
 
     def info(self):
         v = self.export("info")
@@ -249,7 +274,7 @@ class BatchSolver:
     """
 
     def __init__(self, meshes, *, device=0, precision=PREC_FP64, n_min=0, nu_aux=2, nu_fine=1,
-                 coarse_max_dofs=1024, max_iter=1000, smoothing=0):
+                 coarse_max_dofs=1024, max_iter=1000, smoothing=0, autotune=1):
         dim = np.asarray(meshes[0][0]).shape[1]
         coords = np.ascontiguousarray(np.concatenate([np.asarray(m[0], dtype=np.float64) for m in meshes]))
         elems = np.ascontiguousarray(np.concatenate([np.asarray(m[1], dtype=np.int32) for m in meshes]))
@@ -263,6 +288,7 @@ class BatchSolver:
         opt.n_min, opt.nu_aux, opt.nu_fine = n_min, nu_aux, nu_fine
         opt.coarse_max_dofs, opt.max_iter, opt.precision, opt.device = coarse_max_dofs, max_iter, precision, device
         opt.smoothing = smoothing
+        opt.autotune = autotune
         h = ctypes.c_void_p()
         _check(lib.asmg_setup_batch(len(meshes), dim, _ptr(vo), _ptr(coords), _ptr(eo), _ptr(elems), _ptr(kappa),
                                     ctypes.byref(opt), ctypes.byref(h)))
@@ -302,8 +328,10 @@ class BatchSolver:
 
     def solve(self, F, n_rhs, tol=1e-8, out=None):
         import torch
-        assert F.is_cuda and F.dtype == torch.float64 and F.is_contiguous() and F.numel() == self.n_total * n_rhs
-        U = torch.empty_like(F) if out is None else out
+        if n_rhs not in (1, 2, 4):
+            raise ValueError("n_rhs must be 1, 2 or 4")
+        _need_device(F, self.n_total * n_rhs, "F")
+        U = torch.empty_like(F) if out is None else _need_device(out, self.n_total * n_rhs, "out")
         it = np.zeros(self.n_meshes * n_rhs, dtype=np.int32)
         tr = np.zeros(self.n_meshes * n_rhs)
         _check(lib.asmg_solve_batch_device(self.h, n_rhs, _tptr(F), tol, _tptr(U), _ptr(it), _ptr(tr), _stream()))

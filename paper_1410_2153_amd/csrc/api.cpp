@@ -103,6 +103,7 @@ int asmg_default_options(asmg_options *o) {
   o->colouring = 2;
   o->smoothing = 0;
   o->domain = 0;
+  o->autotune = 1;
   return ASMG_OK;
 }
 
@@ -436,6 +437,10 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
       if (!lm.kept.empty())
         for (size_t i = 0; i < k.size(); ++i) k[i] = lm.kept[i];
       return put(k, buf, count);
+    }
+    if (name == "tuned_shapes") {  // level = precision
+      if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");
+      return put(device_tuned_shapes(H->dev, level), buf, count);
     }
     if (name == "local_set") {
       auto it = h.local_set.find(level);

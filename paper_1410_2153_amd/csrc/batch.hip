@@ -174,16 +174,6 @@ __device__ __forceinline__ int bwave_slice(int first) {
   return first + xcd_block() * (BS / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
-// Tunable launch shape of the V-cycle slice kernels: blocks of blockDim.x / 64 waves (one slice
-// per wave), taken in XCD-contiguous order (xcd = 1) or in dispatch order (xcd = 0).
-static constexpr int BS_MAX = 512;
-
-__device__ __forceinline__ int tuned_slice(int first, int xcd) {
-  const int wpb = (int)blockDim.x >> 6;
-  const int blk = xcd ? xcd_block() : (int)blockIdx.x;
-  return first + blk * wpb + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-}
-
 // MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j (dv_ = a_ii)
 // over slices [s0, s1), every right-hand side of a row at once
@@ -192,8 +182,8 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__r
                                                   const int *__restrict__ soff, const int *__restrict__ scol,
                                                   const T *__restrict__ sv, const T *__restrict__ dv_,
                                                   const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
-                                                  int xcd) {
-  const int s = tuned_slice(s0, xcd);
+                                                  int shape) {
+  const int s = tuned_slice(s0, shape);
   if (s >= s1) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
@@ -228,8 +218,8 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__rest
                                                        const int *__restrict__ soff, const int *__restrict__ scol,
                                                        const T *__restrict__ sv, const T *__restrict__ x,
                                                        T *__restrict__ y, const T *__restrict__ id0,
-                                                       T *__restrict__ xs, int xcd) {
-  const int s = tuned_slice(0, xcd);
+                                                       T *__restrict__ xs, int shape) {
+  const int s = tuned_slice(0, shape);
   if (s >= ns) return;
   const int lane = threadIdx.x & 63;
   const int row = srow[(size_t)s * 64 + lane];
@@ -778,6 +768,10 @@ struct BatchDevice {
   bool tuning = false;
   int site = 0;
   int shape_pi = 0, shape_nr = 1;
+  int autotune = 1;
+  int tune_k = 0, tune_live = 0;       // autotuner: candidate under trial, sites seen
+  std::vector<hipEvent_t> tune_ev;     // two events per launch site
+  std::vector<uint8_t> tune_has;       // site launched something
 };
 
 template <class T>
@@ -1035,6 +1029,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
     dv->nu_fine = H[0]->opt.nu_fine;
     dv->maxit = H[0]->opt.max_iter;
     dv->precision = H[0]->opt.precision;
+    dv->autotune = H[0]->opt.autotune;
     // per-mesh colour-major orderings of every smoothing level
     struct MeshOrd {
       std::vector<int> perm, iperm, coff;
@@ -1302,6 +1297,7 @@ void batch_device_destroy(BatchDevice *dv) {
   for (auto &g : dv->graph)
     for (auto &x : g)
       if (x) (void)hipGraphExecDestroy(x);
+  for (hipEvent_t e : dv->tune_ev) (void)hipEventDestroy(e);
   if (dv->ev_in) (void)hipEventDestroy(dv->ev_in);
   if (dv->ev_out) (void)hipEventDestroy(dv->ev_out);
   if (dv->stream) (void)hipStreamDestroy(dv->stream);
@@ -1354,54 +1350,39 @@ const double *bid0<double>(const BLevel &L) { return L.id0_64; }
 template <>
 const float *bid0<float>(const BLevel &L) { return L.id0_32; }
 
-// Gauss-Seidel sweep over the colour groups of L. `first_done`: the sweep starts from zero and
-// its colour-0 pass was run by the kernel that produced b.
-// Candidate launch shapes: 128, 256 or 512 threads per block, XCD-contiguous or dispatch order.
-static const std::pair<int, int> kShapes[] = {{256, 1}, {128, 1}, {512, 1}, {256, 0}, {128, 0}, {512, 0}};
-static constexpr int kTuneReps = 5;
-
-// One slice-kernel launch site of B_co. launch(threads, xcd) enqueues the kernel over `nslices`
-// slices. While tuning, every candidate shape is timed (kTuneReps launches between HIP events,
-// after one untimed launch) and the fastest is kept for this site; the kernels tuned here have
-// no reductions, so every shape computes the same result. Otherwise the site's stored shape
-// (or the default) is used.
+// One slice-kernel launch site of B_co: launch(threads, xcd, e0, e1) enqueues the kernel over
+// `nslices` slices (launch_timed: with events, they are stamped with the kernel's own start and
+// end). While tuning, the site runs the candidate shape under trial with its pair of events, so
+// that its time is measured inside a whole B_co application (caches as in a solve); otherwise
+// it runs the shape stored for the site (or the default). The tuned kernels have no
+// reductions, so the shape does not change any result.
 template <class F>
 static void slice_launch(BatchDevice *dv, int nslices, hipStream_t s, F &&launch) {
   auto &tab = dv->shape[dv->shape_pi][dv->shape_nr];
   const int site = dv->site++;
   if (nslices <= 0) return;
-  if (!dv->tuning) {
-    const auto sh = site < (int)tab.size() ? tab[site] : kShapes[0];
-    launch(sh.first, sh.second);
-    return;
-  }
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
-  float best = INFINITY;
-  std::pair<int, int> pick = kShapes[0];
-  for (const auto &sh : kShapes) {
-    launch(sh.first, sh.second);
-    HIPCHECK(hipEventRecord(e0, s));
-    for (int r = 0; r < kTuneReps; ++r) launch(sh.first, sh.second);
-    HIPCHECK(hipEventRecord(e1, s));
-    HIPCHECK(hipEventSynchronize(e1));
-    float t = 0;
-    HIPCHECK(hipEventElapsedTime(&t, e0, e1));
-    if (t < best) {
-      best = t;
-      pick = sh;
+  auto sh = site < (int)tab.size() ? tab[site] : kShapes[0];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (dv->tuning) {
+    while ((int)dv->tune_ev.size() < 2 * (site + 1)) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      dv->tune_ev.push_back(e);
     }
+    sh = kShapes[dv->tune_k];
+    e0 = dv->tune_ev[2 * site];
+    e1 = dv->tune_ev[2 * site + 1];
+    dv->tune_live = std::max(dv->tune_live, site + 1);
+    dv->tune_has.resize(std::max<size_t>(dv->tune_has.size(), site + 1), 0);
+    dv->tune_has[site] = 1;
   }
-  HIPCHECK(hipEventDestroy(e0));
-  HIPCHECK(hipEventDestroy(e1));
-  if ((int)tab.size() <= site) tab.resize(site + 1, kShapes[0]);
-  tab[site] = pick;
-  launch(pick.first, pick.second);  // leave the site's result in place
+  launch(sh.first, sh.second, e0, e1);
 }
 
 static inline int slice_blocks(int nslices, int threads) { return std::max(1, (nslices * 64 + threads - 1) / threads); }
 
+// Gauss-Seidel sweep over the colour groups of L. `first_done`: the sweep starts from zero and
+// its colour-0 pass was run by the kernel that produced b.
 template <int NR, class T>
 static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool first_done, bool forward,
                     hipStream_t s) {
@@ -1411,9 +1392,9 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   const int C = (int)S.cslice.size() - 1;
   auto pass = [&](int c) {
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
-    slice_launch(dv, s1 - s0, s, [&](int th, int xcd) {
-      hipLaunchKernelGGL((kb_sell<0, NR, T>), dim3(slice_blocks(s1 - s0, th)), dim3(th), 0, s, s0, s1, S.srow,
-                         S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, xcd);
+    slice_launch(dv, s1 - s0, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+      launch_timed((kb_sell<0, NR, T>), slice_blocks(s1 - s0, th), th, s, e0, e1, s0, s1, S.srow,
+                         S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
     });
   };
   if (forward) {
@@ -1434,9 +1415,9 @@ template <int NR, class T>
 static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   if (L.nsmooth == 0) return;
   const BSell &S = L.sell;
-  slice_launch(dv, S.nslices, s, [&](int th, int xcd) {
-    hipLaunchKernelGGL((kb_sell<1, NR, T>), dim3(slice_blocks(S.nslices, th)), dim3(th), 0, s, 0, S.nslices, S.srow,
-                       S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), xcd);
+  slice_launch(dv, S.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed((kb_sell<1, NR, T>), slice_blocks(S.nslices, th), th, s, e0, e1, 0, S.nslices, S.srow,
+                       S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
   });
   if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
 }
@@ -1446,10 +1427,10 @@ static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
 template <int NR, int ADD, int FIRST, class T>
 static void b_spmv(BatchDevice *dv, const BSell &A, const T *x, T *y, BLevel *Lt, hipStream_t s) {
   if (A.nrows == 0) return;
-  slice_launch(dv, A.nslices, s, [&](int th, int xcd) {
-    hipLaunchKernelGGL((kb_sell_spmv<ADD, FIRST, NR, T>), dim3(slice_blocks(A.nslices, th)), dim3(th), 0, s,
+  slice_launch(dv, A.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed((kb_sell_spmv<ADD, FIRST, NR, T>), slice_blocks(A.nslices, th), th, s, e0, e1,
                        A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y,
-                       FIRST ? bid0<T>(*Lt) : (const T *)nullptr, FIRST ? BV<T>::x(*Lt) : (T *)nullptr, xcd);
+                       FIRST ? bid0<T>(*Lt) : (const T *)nullptr, FIRST ? BV<T>::x(*Lt) : (T *)nullptr, shape_arg(th, xcd));
   });
   if (dv->count_bytes)
     dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD + FIRST) * (double)A.nrows) +
@@ -1524,21 +1505,41 @@ static void b_iteration(BatchDevice *dv, hipStream_t s) {
   b_tail<NR, T>(dv, s, true);
 }
 
-// Autotuner: one eager B_co application on the current right-hand side in which every slice
-// launch site times the candidate shapes and keeps the fastest (the solve that follows starts
-// from scratch, so what tuning leaves in the work vectors is overwritten).
+// Autotuner: for every candidate shape (twice), one eager B_co application on the current r with
+// all slice sites in that shape and HIP events around each; every site then keeps the shape of
+// its shortest time if that beats the default clearly (pick_shape). The solve that follows starts
+// B_co from scratch.
 template <int NR, class T>
 static void b_tune(BatchDevice *dv, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
-  if (dv->tuned[pi][NR]) return;
+  if (dv->tuned[pi][NR] || !dv->autotune) return;
+  const int K = kNumShapes;
+  std::vector<std::vector<float>> t;
   dv->tuning = true;
   try {
-    b_apply<NR, T>(dv, dv->r, false, s);
+    for (int round = 0; round < kTuneRounds; ++round)
+      for (int k = 0; k < K; ++k) {
+        dv->tune_k = k;
+        dv->tune_live = 0;
+        b_apply<NR, T>(dv, dv->r, false, s);
+        HIPCHECK(hipStreamSynchronize(s));
+        if ((int)t.size() < dv->tune_live) t.resize(dv->tune_live, std::vector<float>(K, INFINITY));
+        for (int site = 0; site < dv->tune_live; ++site) {
+          if (!dv->tune_has[site]) continue;
+          float ms = 0;
+          HIPCHECK(hipEventElapsedTime(&ms, dv->tune_ev[2 * site], dv->tune_ev[2 * site + 1]));
+          t[site][k] = std::min(t[site][k], ms);
+        }
+      }
   } catch (...) {
     dv->tuning = false;
     throw;
   }
   dv->tuning = false;
+  auto &tab = dv->shape[pi][NR];
+  tab.assign(t.size(), kShapes[0]);
+  for (size_t site = 0; site < t.size(); ++site)
+    tab[site] = kShapes[pick_shape(t[site])];
   dv->tuned[pi][NR] = true;
 }
 

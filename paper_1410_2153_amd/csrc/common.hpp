@@ -1,11 +1,14 @@
 // Device helpers shared by the single-mesh engine (device.hip) and the batched engine (batch.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <string>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "setup.hpp"
 
@@ -52,6 +55,51 @@ __device__ __forceinline__ int xcd_block() {
   const int nb = (int)gridDim.x, b = (int)blockIdx.x;
   const int x = b & 7, i = b >> 3, per = nb >> 3, rem = nb & 7;
   return x * per + (x < rem ? x : rem) + i;
+}
+
+// Tunable launch shape of the V-cycle slice kernels: blocks of `threads` / 64 waves (one slice
+// per wave), taken in XCD-contiguous order (xcd = 1) or in dispatch order (xcd = 0), passed to
+// the kernel as one int shape = 2 * waves per block + xcd. (The block size comes in as an
+// argument because blockDim.x is a 16-bit field of the dispatch packet: reading it costs a
+// vector memory load at kernel start, on the critical path of these latency-bound kernels.)
+static constexpr int BS_MAX = 512;
+
+static inline int shape_arg(int threads, int xcd) { return 2 * (threads >> 6) + (xcd ? 1 : 0); }
+
+__device__ __forceinline__ int tuned_slice(int first, int shape) {
+  const int xb = xcd_block();  // both orders computed: no branch between the kernel-argument loads
+  const int blk = (shape & 1) ? xb : (int)blockIdx.x;
+  return first + blk * (shape >> 1) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+}
+
+// Candidate launch shapes (threads per block, XCD order) of the autotuner; the first is the
+// default. Each candidate is timed kTuneRounds times per launch site (best of), and a site leaves
+// the default only for a candidate faster by kTuneMargin of the default's time and by at least
+// kTuneFloorMs: timings of kernels of a few microseconds are noisy, and a pick on noise costs
+// more than it gains.
+static const std::pair<int, int> kShapes[] = {{256, 1}, {128, 1}, {512, 1}, {256, 0}, {128, 0}, {512, 0}};
+static constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+static constexpr int kTuneRounds = 3;
+static constexpr float kTuneMargin = 0.02f;
+static constexpr float kTuneFloorMs = 0.0005f;
+
+// Launch of a kernel over `grid` blocks of `threads`; with an event pair (timing runs only, never
+// under stream capture) the events are stamped with the kernel's own start and end
+// (hipExtLaunchKernel), so that their interval excludes the launch gaps around the kernel.
+template <class K, class... A>
+static void launch_timed(K kernel, int grid, int threads, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
+  if (e0) {
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, e0, e1, 0, args...);
+    HIPCHECK(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, args...);
+  }
+}
+
+// index into kShapes picked from one site's best times per candidate (INFINITY = not timed)
+static inline int pick_shape(const std::vector<float> &t) {
+  const int k = (int)(std::min_element(t.begin(), t.end()) - t.begin());
+  return t[0] - t[k] > std::max(kTuneMargin * t[0], kTuneFloorMs) ? k : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,8 @@
 // Device side of the solver: uploaded hierarchy, kernels and the PCG driver (device.hip).
 #pragma once
 
+#include <vector>
+
 #include <cstdint>
 
 #include "setup.hpp"
@@ -22,6 +24,9 @@ int device_set_coefficient(Device *dv, const double *d_kappa, void *stream);
 int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream);
 int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, void *stream);
 int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes);
+// launch shapes picked by the autotuner for a precision: (threads per block, XCD order) per
+// slice-kernel launch site, flattened (empty before the first solve in that precision)
+std::vector<int64_t> device_tuned_shapes(Device *dv, int precision);
 // host-pointer solve through device staging buffers
 int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel);
 

@@ -97,3 +97,16 @@ def test_batch_setup_host_only():
     with pytest.raises(A.AsmgError) as e:
         A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes], device=-1, smoothing=1)
     assert e.value.code == A.EINVAL
+
+
+def test_binding_rejects_wrong_sizes():
+    coords, elems, _ = W.square_mesh(6, 0.2)
+    S = A.Solver(coords, elems, np.ones(len(elems)), device=-1)
+    with pytest.raises(ValueError):
+        S.solve(np.ones(S.n + 3))
+    with pytest.raises(ValueError):
+        S.update_coefficient(np.ones(len(elems) - 1))
+    with pytest.raises(ValueError):
+        A.Solver(coords, elems, np.ones(len(elems) + 1), device=-1)
+    with pytest.raises(ValueError):
+        A.Solver(coords, elems, np.ones(len(elems)), np.zeros(3, dtype=bool), device=-1)

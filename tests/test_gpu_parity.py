@@ -82,6 +82,7 @@ def case(request):
     H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col],
                           domain=["box", "mesh"][dom]), ORACLE_SMOOTHING[sm])
     S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col, smoothing=sm, domain=dom)
+    S64.kwargs = dict(n_min=n_min, colouring=col, smoothing=sm, domain=dom)
     S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED, colouring=col,
                    smoothing=sm, domain=dom)
     f = c["f_vertex"][H.dofs]
@@ -165,10 +166,24 @@ def test_zero_rhs_and_max_iter(case):
     name, c, H, S64, S32, f = case
     u, it, tr = S64.solve(np.zeros(H.n), 1e-8)
     assert it == 0 and np.all(u == 0)
-    S1 = A.Solver(c["coords"], c["elems"], c["kappa"], max_iter=2,
-                  n_min=3 if name == "graded_cube" else 0)
+    S1 = A.Solver(c["coords"], c["elems"], c["kappa"], max_iter=2, **S64.kwargs)
     with pytest.raises(A.AsmgError) as e:
         S1.solve(f, 1e-14)
     assert e.value.code == A.ENOCONV
     u, it, tr = S1.solve(f, 1e-14, allow_noconv=True)
     assert it == 2
+
+
+def test_autotuned_shapes_do_not_change_b_co(case):
+    # B_co before any solve (default launch shapes) and after the first solve (autotuned shapes)
+    # is bitwise identical: the tuned kernels have no reductions
+    name, c, H, S64, S32, f = case
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], **S64.kwargs)
+    r = torch.from_numpy(np.random.default_rng(9).standard_normal(S.n)).cuda()
+    assert len(S.tuned_shapes()) == 0
+    z0 = S.apply_preconditioner(r).cpu().numpy()
+    S.solve_device(torch.from_numpy(f).cuda(), 1e-8)
+    shapes = S.tuned_shapes()
+    assert len(shapes) > 0 and set(shapes[:, 0].tolist()) <= {128, 256, 512}
+    z1 = S.apply_preconditioner(r).cpu().numpy()
+    assert np.array_equal(z0, z1)
