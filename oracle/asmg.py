@@ -25,6 +25,14 @@
   proves the multigrid bound. The sweeps visit the same colours in the same
   order, restricted to those rows; residuals and transfers stay whole.
 
+* Nested iteration (Section 5.2 starts CG from a nested iteration over the levels of the
+  hierarchy, coarsest to finest). Reading: the levels are the auxiliary levels l_c..J and
+  then the original grid. The load vector is carried down by the transposed transfers,
+  g_J = Pi^T f and g_(l-1) = P_l^T g_l (for nested P1 spaces P_l^T g_l is exactly level
+  l-1's load vector); e_(l_c) = A_(l_c)^(-1) g_(l_c); on each finer level
+  e_l = P_l e_(l-1) followed by ``cycles`` iterations e_l <- e_l + B_l (g_l - A_l e_l) with
+  the V-cycle B_l of Algorithm 2; the initial guess of CG is u_0 = Pi e_J.
+
 Pins: on small meshes B_co, formed densely, is symmetric (1e-13) and positive
 definite, and matches the closed form above; a V-cycle on the uniform hierarchy
 of the square is the textbook geometric multigrid of Section 5.1; with local
@@ -126,3 +134,20 @@ class ASMGPreconditioner:
         return u
 
     __call__ = apply
+
+    def nested_guess(self, f, cycles=1, levels=False):
+        """Initial guess u_0 = Pi e_J of the nested iteration over the auxiliary levels (in the
+        preconditioner's dtype). With ``levels``, also returns the dicts g and e per level."""
+        dt = self.dtype
+        f = np.asarray(f).astype(dt)
+        g = {self.J: self.PiT @ f}
+        for l in range(self.J, self.lc, -1):
+            g[l - 1] = self.PT[l] @ g[l]
+        e = {self.lc: np.asarray(self._coarse(g[self.lc])).astype(dt)}
+        for l in range(self.lc + 1, self.J + 1):
+            el = self.P[l] @ e[l - 1]
+            for _ in range(cycles):
+                el = el + self.vcycle(l, g[l] - self.Aaux[l] @ el)
+            e[l] = el
+        u0 = self.Pi @ e[self.J]
+        return (u0, g, e) if levels else u0

@@ -55,14 +55,19 @@ class Hierarchy:
         return self._B[key]
 
     def solve(self, f, tol=1e-8, max_iter=1000, mixed=False, record=False, nu_aux=2, nu_fine=1,
-              smoothing="full"):
+              smoothing="full", nested=0):
+        """PCG with B_co; ``nested`` > 0 starts from the nested iteration's guess with that many
+        V-cycles per auxiliary level (in the preconditioner's precision)."""
         B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine, smoothing)
         if mixed:
             def Bm(r):
                 return B(r.astype(np.float32)).astype(np.float64)
         else:
             Bm = B
-        return pcg.pcg(self.A, f, Bm, tol, max_iter, record)
+        u0 = None
+        if nested > 0 and np.any(np.asarray(f) != 0):
+            u0 = np.asarray(B.nested_guess(f, nested)).astype(np.float64)
+        return pcg.pcg(self.A, f, Bm, tol, max_iter, record, u0=u0)
 
     def level_sizes(self):
         return {l: self.meshes.level(l).n for l in range(1, self.tree.J + 1)}

@@ -1,6 +1,7 @@
 """Preconditioned conjugate gradients with the ASMG preconditioner (oracle).
 
-Section 5.2: CG preconditioned by ASMG. Readings: start from u_0 = 0; stop at the
+Section 5.2: CG preconditioned by ASMG. Readings: start from u_0 = 0 (or from the nested
+iteration's guess, ``ASMGPreconditioner.nested_guess``); stop at the
 first k with ||r_k||_2 <= tol ||f||_2 (the paper iterates to the discretisation
 error with nested iteration, which needs a family of meshes). The iteration
 count is the number of products A p. f = 0 gives u = 0 after 0 iterations. The
@@ -20,8 +21,9 @@ from __future__ import annotations
 import numpy as np
 
 
-def pcg(A, f, B, tol=1e-8, max_iter=1000, record=False):
-    """Returns (u, iterations, info) with info = dict(true_rel_residual, history, status)."""
+def pcg(A, f, B, tol=1e-8, max_iter=1000, record=False, u0=None):
+    """Returns (u, iterations, info) with info = dict(true_rel_residual, history, status).
+    ``u0``: initial guess (default 0); the stopping rule stays relative to ||f||."""
     f = np.asarray(f, dtype=np.float64)
     n = len(f)
     u = np.zeros(n)
@@ -31,7 +33,14 @@ def pcg(A, f, B, tol=1e-8, max_iter=1000, record=False):
         return u, 0, dict(true_rel_residual=0.0, history=hist, status="ok", restarts=0)
     total = 0
     restarts = 0
-    r = f.copy()
+    if u0 is None:
+        r = f.copy()
+    else:
+        u[:] = np.asarray(u0, dtype=np.float64)
+        r = f - A @ u
+        if float(np.linalg.norm(r)) <= tol * nf:   # the guess already meets the rule
+            return u, 0, dict(true_rel_residual=float(np.linalg.norm(r)) / nf, history=hist, status="ok",
+                              restarts=0)
     while True:
         z = np.asarray(B(r), dtype=np.float64)
         p = z.copy()
