@@ -382,6 +382,20 @@ def main():
         out["local_smoothing"] = loc
         del SL
         torch.cuda.synchronize()
+        # the same workload started from the nested iteration's guess (one V-cycle per level)
+        SN = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64,
+                      colouring=args.colouring, nested=1, autotune=args.autotune)
+        nst = {}
+        for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
+            SN.set_precision(prec)
+            dtn, itn, trn, un = run(SN, args.steps, args.warmup)
+            nst[name] = {"value": n * args.steps / dtn, "ms_per_step": dtn / args.steps * 1e3, "iterations": itn[-1],
+                         "true_rel_residual": trn}
+            log(f"nested start {name}: {dtn / args.steps * 1e3:.2f} ms/solve, iters {itn}, true rel res {trn:.2e}")
+        nst["rel_diff_vs_fp64"] = float(torch.linalg.norm(un - u64) / torch.linalg.norm(u64))
+        out["nested_start"] = nst
+        del SN
+        torch.cuda.synchronize()
     if args.copy_calibration:
         x = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
         y = torch.empty_like(x)

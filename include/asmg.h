@@ -78,6 +78,12 @@ typedef struct {
   int autotune;        /* 1 = at the first solve in a precision, time the candidate launch shapes
                           of every V-cycle slice kernel and keep the fastest (default); 0 = fixed
                           256-thread blocks in XCD order. Results do not depend on it. */
+  int nested;          /* initial guess of PCG: 0 = u_0 = 0 (default); k in 1..16 = nested iteration
+                          over the auxiliary levels (Section 5.2): g_J = Pi^T f, g_(l-1) = P_l^T g_l,
+                          e = A_(l_c)^-1 g_(l_c) at the bottom, then on each finer level
+                          e_l = P_l e_(l-1) and k V-cycles (Algorithm 2) on A_l e = g_l, in the
+                          V-cycle's precision; u_0 = Pi e_J. Single-mesh handles with whole-level
+                          smoothing (smoothing = 0) only. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -127,9 +133,10 @@ int asmg_num_dofs(asmg_handle h, int64_t *n);
 int asmg_dof_vertex(asmg_handle h, int32_t *map);
 
 /*
- * PCG solve from u_0 = 0 until ||f - A u||_2 <= tol ||f||_2 (recursively updated
- * residual; the true residual is recomputed in FP64 at exit and, in mixed
- * precision, CG restarts from it while it is above tol).
+ * PCG solve from u_0 = 0 (or the nested iteration's guess, asmg_options.nested) until
+ * ||f - A u||_2 <= tol ||f||_2 (recursively updated residual; the true residual is
+ * recomputed in FP64 at exit and, in mixed precision, CG restarts from it while it is
+ * above tol). A guess that already meets the rule returns it after 0 iterations.
  *   f, u                 n doubles (host pointers)
  *   iterations           number of products with A (may be NULL)
  *   true_rel_residual    ||f - A u|| / ||f|| recomputed at exit (may be NULL)

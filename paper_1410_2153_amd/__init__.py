@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("nested", ctypes.c_int)]
 
 
 def _load():
@@ -123,7 +123,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0, domain=0, autotune=1):
+                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         if coords.ndim != 2 or elems.ndim != 2 or elems.shape[1] != coords.shape[1] + 1:
@@ -141,6 +141,7 @@ class Solver:
         opt.smoothing = smoothing
         opt.domain = domain
         opt.autotune = autotune
+        opt.nested = nested
         self.precision = precision
         self.device = device
         dptr = None
@@ -274,7 +275,7 @@ class BatchSolver:
     """
 
     def __init__(self, meshes, *, device=0, precision=PREC_FP64, n_min=0, nu_aux=2, nu_fine=1,
-                 coarse_max_dofs=1024, max_iter=1000, smoothing=0, autotune=1):
+                 coarse_max_dofs=1024, max_iter=1000, smoothing=0, autotune=1, nested=0):
         dim = np.asarray(meshes[0][0]).shape[1]
         coords = np.ascontiguousarray(np.concatenate([np.asarray(m[0], dtype=np.float64) for m in meshes]))
         elems = np.ascontiguousarray(np.concatenate([np.asarray(m[1], dtype=np.int32) for m in meshes]))
@@ -289,6 +290,7 @@ class BatchSolver:
         opt.coarse_max_dofs, opt.max_iter, opt.precision, opt.device = coarse_max_dofs, max_iter, precision, device
         opt.smoothing = smoothing
         opt.autotune = autotune
+        opt.nested = nested
         h = ctypes.c_void_p()
         _check(lib.asmg_setup_batch(len(meshes), dim, _ptr(vo), _ptr(coords), _ptr(eo), _ptr(elems), _ptr(kappa),
                                     ctypes.byref(opt), ctypes.byref(h)))

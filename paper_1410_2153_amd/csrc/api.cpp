@@ -104,6 +104,7 @@ int asmg_default_options(asmg_options *o) {
   o->smoothing = 0;
   o->domain = 0;
   o->autotune = 1;
+  o->nested = 0;
   return ASMG_OK;
 }
 
@@ -121,8 +122,10 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
       o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 1 ||
-      (o.domain == 1 && dim != 2))
+      (o.domain == 1 && dim != 2) || o.nested < 0 || o.nested > 16)
     return set_err(ASMG_EINVAL, "invalid options");
+  if (o.nested > 0 && o.smoothing != 0)
+    return set_err(ASMG_EINVAL, "the nested iteration needs whole-level smoothing (smoothing = 0)");
   for (int64_t i = 0; i < n_vertices * dim; ++i)
     if (!std::isfinite(coords[i])) return set_err(ASMG_EINVAL, "non-finite coordinate");
   for (int64_t i = 0; i < n_elements * (dim + 1); ++i)
@@ -279,6 +282,7 @@ static int check_options(const asmg_options &o) {
       o.colouring > 2 || o.domain < 0 || o.domain > 1)
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
+  if (o.nested != 0) return set_err(ASMG_EINVAL, "the nested iteration is available on single-mesh handles only");
   return ASMG_OK;
 }
 

@@ -376,6 +376,51 @@ __global__ __launch_bounds__(BS) void k_fin_tr(const double *__restrict__ partia
   if (threadIdx.x == 0) ctl->tr = t;
 }
 
+// PCG start from a guess u: r = f - A u, p = 0, partials of ||r||^2 (grid-stride over row groups)
+template <int LPR>
+__global__ __launch_bounds__(BS) void k_cg_guess(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const double *__restrict__ av, const double *__restrict__ dg,
+                                                 const double *__restrict__ f, const double *__restrict__ u,
+                                                 double *__restrict__ r, double *__restrict__ p,
+                                                 double *__restrict__ partials) {
+  constexpr int RPB = BS / LPR;
+  const int lane = threadIdx.x % LPR;
+  double v = 0.0;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / LPR;
+    const bool act = row < n;
+    const double s = row_dot<LPR>(rp, ci, av, u, row, act, lane);
+    if (act && lane == 0) {
+      const double e = f[row] - dg[row] * u[row] - s;
+      r[row] = e;
+      p[row] = 0.0;
+      v += e * e;
+    }
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// a guess that already meets the stopping rule ends the solve before its first iteration
+__global__ __launch_bounds__(BS) void k_fin_guess(const double *__restrict__ partials, int nb, Ctl *ctl) {
+  const double t = sum_partials(partials, nb);
+  if (threadIdx.x == 0 && t <= ctl->tol2) ctl->done = 1;
+}
+
+// e += x
+template <class T>
+__global__ __launch_bounds__(BS) void k_add(int n, const T *__restrict__ x, T *__restrict__ e) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) e[i] += x[i];
+}
+
+// b = a, rounded to the destination type
+template <class S, class D>
+__global__ __launch_bounds__(BS) void k_convert(int n, const S *__restrict__ a, D *__restrict__ b) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) b[i] = (D)a[i];
+}
+
 // q = A p on the sliced ELL of the original grid (all colours); partials of p.q
 __global__ __launch_bounds__(BS) void k_cg_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
                                                 const int *__restrict__ scol, const double *__restrict__ sv,
@@ -666,6 +711,8 @@ struct DLevel {
   float *dg32 = nullptr, *id32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
   float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+  double *ng64 = nullptr, *ne64 = nullptr;  // nested iteration: load vector g_l and iterate e_l
+  float *ng32 = nullptr, *ne32 = nullptr;
   DCsr P, PT;                 // from the next coarser level (aux levels only)
 };
 
@@ -682,6 +729,9 @@ struct Device {
   int nc = 0;
   double *cinv64 = nullptr, *cb64 = nullptr, *cx64 = nullptr;
   float *cinv32 = nullptr, *cb32 = nullptr, *cx32 = nullptr;
+  double *cng64 = nullptr, *cne64 = nullptr;  // nested iteration at the bottom level
+  float *cng32 = nullptr, *cne32 = nullptr;
+  int nested = 0;             // V-cycles per level of the nested iteration (0 = u_0 = 0)
   int *perm_d = nullptr;      // fine internal -> unknown
   // PCG vectors (internal order, FP64)
   double *f = nullptr, *u = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
@@ -1163,6 +1213,20 @@ Device *device_create(Hierarchy &h, int ordinal) {
       upload_transfer(dv, transpose(Pi), dv->PiT, cmap);
     }
     upload_coarse(dv, h, true);
+    dv->nested = h.opt.nested;
+    if (dv->nested > 0) {
+      for (int l = dv->J; l > dv->lc; --l) {
+        DLevel &L = dv->aux[l];
+        L.ng64 = dalloc<double>(dv, L.n);
+        L.ne64 = dalloc<double>(dv, L.n);
+        L.ng32 = dalloc<float>(dv, L.n);
+        L.ne32 = dalloc<float>(dv, L.n);
+      }
+      dv->cng64 = dalloc<double>(dv, dv->nc);
+      dv->cne64 = dalloc<double>(dv, dv->nc);
+      dv->cng32 = dalloc<float>(dv, dv->nc);
+      dv->cne32 = dalloc<float>(dv, dv->nc);
+    }
     const int n = dv->fine.n;
     dv->f = dalloc<double>(dv, n);
     dv->u = dalloc<double>(dv, n);
@@ -1296,11 +1360,11 @@ static double gs_bytes(const DLevel &L, int c) {
 template <class F>
 static void slice_launch(Device *dv, int nslices, hipStream_t s, F &&launch, double probe_bytes = -1.0) {
   auto &tab = dv->shape[dv->shape_pi];
-  const int site = dv->site++;
+  const int site = dv->site >= 0 ? dv->site++ : -1;  // -1: outside B_co (default shape)
   if (nslices <= 0) return;
-  auto sh = site < (int)tab.size() ? tab[site] : kShapes[0];
+  auto sh = site >= 0 && site < (int)tab.size() ? tab[site] : kShapes[0];
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (dv->tuning) {
+  if (dv->tuning && site >= 0) {
     while ((int)dv->tune_ev.size() < 2 * (site + 1)) {
       hipEvent_t e;
       HIPCHECK(hipEventCreate(&e));
@@ -1518,6 +1582,74 @@ static void apply_Bco(Device *dv, const double *r, bool first_done, hipStream_t 
   for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, false, false, s);
 }
 
+// nested-iteration vectors of an auxiliary level / of the bottom level
+template <class T>
+struct NV;
+template <>
+struct NV<double> {
+  static double *g(Device *dv, int l) { return l == dv->lc ? dv->cng64 : dv->aux[l].ng64; }
+  static double *e(Device *dv, int l) { return l == dv->lc ? dv->cne64 : dv->aux[l].ne64; }
+};
+template <>
+struct NV<float> {
+  static float *g(Device *dv, int l) { return l == dv->lc ? dv->cng32 : dv->aux[l].ng32; }
+  static float *e(Device *dv, int l) { return l == dv->lc ? dv->cne32 : dv->aux[l].ne32; }
+};
+
+// Nested iteration over the auxiliary levels (Section 5.2), in the V-cycle's precision T:
+// g_J = Pi^T f, g_(l-1) = P_l^T g_l; e_(l_c) = A_(l_c)^-1 g_(l_c); on each finer level
+// e_l = P_l e_(l-1), then `nested` times e_l += B_l (g_l - A_l e_l) with the V-cycle of
+// Algorithm 2 (its right-hand side written by the residual kernel, its first colour pass from
+// zero run on its own); finally u = Pi e_J in FP64 (internal order). Whole-level smoothing.
+template <class T>
+static void nested_start(Device *dv, hipStream_t s) {
+  DLevel &F = dv->fine;
+  const int J = dv->J, lc = dv->lc;
+  dv->site = -1;  // these launches are not B_co's tuned sites
+  const T *fT;
+  if constexpr (sizeof(T) == 8) {
+    fT = dv->f;
+  } else {
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(F.n)), dim3(BS), 0, s, F.n, (const double *)dv->f,
+                       F.b32);
+    fT = F.b32;
+  }
+  spmv<T, 0>(dv, dv->PiT, fT, NV<T>::g(dv, J), s);
+  for (int l = J; l > lc; --l) spmv<T, 0>(dv, dv->aux[l].PT, NV<T>::g(dv, l), NV<T>::g(dv, l - 1), s);
+  if (dv->nc > 0)
+    hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)dv->nc * 64)), dim3(BS), 0, s, dv->nc, cinv<T>(dv),
+                       (const T *)NV<T>::g(dv, lc), NV<T>::e(dv, lc));
+  for (int l = lc + 1; l <= J; ++l) {
+    DLevel &L = dv->aux[l];
+    T *e = NV<T>::e(dv, l);
+    const T *g = NV<T>::g(dv, l);
+    spmv<T, 0>(dv, L.P, NV<T>::e(dv, l - 1), e, s);
+    for (int k = 0; k < dv->nested; ++k) {
+      residual<T>(dv, L, g, e, LV<T>::b(L), s);
+      hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.first_rows,
+                         (const T *)LV<T>::b(L), LV<T>::id(L), LV<T>::x(L));
+      vcycle<T>(dv, l, s);
+      hipLaunchKernelGGL((k_add<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, (const T *)LV<T>::x(L), e);
+    }
+  }
+  if constexpr (sizeof(T) == 8) {
+    spmv<T, 0>(dv, dv->Pi, NV<T>::e(dv, J), dv->u, s);
+  } else {
+    spmv<T, 0>(dv, dv->Pi, NV<T>::e(dv, J), F.x32, s);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(F.n)), dim3(BS), 0, s, F.n, (const float *)F.x32,
+                       dv->u);
+  }
+  dv->site = 0;
+  // r = f - A u, p = 0; done if the guess already meets the rule
+  const int gt = red_grid(F.n, F.A.lpr);
+  with_lpr(F.A.lpr, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    hipLaunchKernelGGL((k_cg_guess<LP>), dim3(gt), dim3(BS), 0, s, F.n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f,
+                       dv->u, dv->r, dv->p, dv->partials);
+  });
+  hipLaunchKernelGGL(k_fin_guess, dim3(1), dim3(BS), 0, s, dv->partials, gt, dv->ctl);
+}
+
 // ---------------------------------------------------------------------------
 // PCG driver
 // ---------------------------------------------------------------------------
@@ -1620,7 +1752,8 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
   const int gi = red_grid(n, 1);
   hipLaunchKernelGGL(k_cg_init, dim3(gi), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, dv->partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, s, dv->partials, gi, tol, dv->maxit, dv->ctl);
-  tune<T>(dv, s);  // first solve in this precision: pick the launch shapes (r = f now)
+  if (dv->nested > 0) nested_start<T>(dv, s);  // u = u_0, r = f - A u_0
+  tune<T>(dv, s);  // first solve in this precision: pick the launch shapes
   pcg_tail<T>(dv, s, false);
   // host checks of the device flag: first after (previous count - 1) iterations, then every
   // iteration; with no history, every `check_every` (default 4) iterations

@@ -49,6 +49,14 @@ def test_rejects_invalid_input():
     with pytest.raises(A.AsmgError) as e:
         A.Solver(coords, elems, k, device=-1, domain=2)
     assert e.value.code == A.EINVAL
+    for bad_nested in (-1, 17):
+        with pytest.raises(A.AsmgError) as e:
+            A.Solver(coords, elems, k, device=-1, nested=bad_nested)
+        assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError) as e:   # the nested iteration needs whole-level smoothing
+        A.Solver(coords, elems, k, device=-1, nested=1, smoothing=1)
+    assert e.value.code == A.EINVAL
+    A.Solver(coords, elems, k, device=-1, nested=2)
     c3, e3, _ = W.kuhn_cube_mesh(3, 0.0)
     with pytest.raises(A.AsmgError) as e:   # general domains are 2-D
         A.Solver(c3, e3, np.ones(len(e3)), device=-1, domain=1)
@@ -96,6 +104,9 @@ def test_batch_setup_host_only():
     # local smoothing is a single-mesh option
     with pytest.raises(A.AsmgError) as e:
         A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes], device=-1, smoothing=1)
+    assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError) as e:   # so is the nested iteration
+        A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes], device=-1, nested=1)
     assert e.value.code == A.EINVAL
 
 
