@@ -84,6 +84,10 @@ typedef struct {
                           e_l = P_l e_(l-1) and k V-cycles (Algorithm 2) on A_l e = g_l, in the
                           V-cycle's precision; u_0 = Pi e_J. Single-mesh handles with whole-level
                           smoothing (smoothing = 0) only. */
+  int setup_device;    /* 1 = build the cluster tree (Sections 3.1-3.2: root box, keys, Morton sort,
+                          refinement by cluster size, closure, leaves, kappa~) on the HIP device,
+                          with results identical to the host build; needs device >= 0; single-mesh
+                          handles. 0 = host (default). */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -194,6 +198,9 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "refined"       int64 (level, i_0..i_{d-1}) per refined box, sorted
  *   "leaves"        int64 (level, i_0..i_{d-1}) per leaf box, sorted
  *   "keys"          int64 per element and axis (n_elements*dim)
+ *   "leaf_kappa"    double kappa~ per leaf, in the order of "leaves"
+ *   "setup_seconds" double wall time of the setup phases: fine matrix, cluster tree, level
+ *                   meshes, transfers, colourings, bottom inverse, device upload
  *   "level_n"       int64 number of unknowns of every level 1..J
  *   "level_verts"   int64 integer coordinates (n_verts*dim) of sigma^(level)
  *   "level_simp"    int64 vertex indices (n_simp*(dim+1)) of sigma^(level)

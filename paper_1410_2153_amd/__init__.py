@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("coarse_max_dofs", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("nested", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("nested", ctypes.c_int),
+                ("setup_device", ctypes.c_int)]
 
 
 def _load():
@@ -123,7 +124,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0):
+                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0, setup_device=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         if coords.ndim != 2 or elems.ndim != 2 or elems.shape[1] != coords.shape[1] + 1:
@@ -142,6 +143,7 @@ class Solver:
         opt.domain = domain
         opt.autotune = autotune
         opt.nested = nested
+        opt.setup_device = setup_device
         self.precision = precision
         self.device = device
         dptr = None
@@ -240,7 +242,7 @@ class Solver:
         cnt = ctypes.c_int64()
         _check(lib.asmg_export(self.h, name.encode(), level, None, ctypes.byref(cnt)))
         if dtype is None:
-            dtype = np.float64 if name.endswith("_val") else np.int64
+            dtype = np.float64 if name.endswith("_val") or name in ("setup_seconds", "leaf_kappa") else np.int64
         buf = np.empty(cnt.value, dtype=dtype)
         if cnt.value:
             _check(lib.asmg_export(self.h, name.encode(), level, _ptr(buf), ctypes.byref(cnt)))
@@ -249,6 +251,11 @@ class Solver:
     def tuned_shapes(self, precision=PREC_FP64):
         """(threads per block, XCD order) picked by the autotuner per slice-kernel launch site."""
         return self.export("tuned_shapes", precision).reshape(-1, 2)
+
+    def setup_seconds(self):
+        """Wall time of the setup phases (s): fine, tree, levels, transfer, colourings, coarse, upload."""
+        keys = ["fine", "tree", "levels", "transfer", "colourings", "coarse", "upload"]
+        return dict(zip(keys, self.export("setup_seconds").tolist()))
 
     def info(self):
         v = self.export("info")

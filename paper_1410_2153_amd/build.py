@@ -1,7 +1,8 @@
 """Build the HIP/C++ shared library libasmg.so for gfx950 (in-tree, under _lib/).
 
 Sources: csrc/setup.cpp (host setup), csrc/domain.cpp (general-domain predicates),
-csrc/api.cpp (C ABI), csrc/device.hip and csrc/batch.hip (kernels and PCG drivers).
+csrc/api.cpp (C ABI), csrc/device.hip and csrc/batch.hip (kernels and PCG drivers),
+csrc/tree.hip (the cluster tree built on the device, option setup_device).
 The host setup is compiled without floating-point contraction, so barycenters, box
 keys and the exact orientation predicates are plain IEEE operations.
 """
@@ -35,7 +36,7 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("device.hip", "batch.hip"):
+    for src in ("device.hip", "batch.hip", "tree.hip"):
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -14,6 +14,7 @@
 #include "../../include/asmg.h"
 #include "batch.hpp"
 #include "device.hpp"
+#include "tree.hpp"
 #include "setup.hpp"
 
 using namespace asmg;
@@ -105,6 +106,7 @@ int asmg_default_options(asmg_options *o) {
   o->domain = 0;
   o->autotune = 1;
   o->nested = 0;
+  o->setup_device = 0;
   return ASMG_OK;
 }
 
@@ -122,7 +124,8 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
       o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 1 ||
-      (o.domain == 1 && dim != 2) || o.nested < 0 || o.nested > 16)
+      (o.domain == 1 && dim != 2) || o.nested < 0 || o.nested > 16 || o.setup_device < 0 || o.setup_device > 1 ||
+      (o.setup_device == 1 && o.device < 0))
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.nested > 0 && o.smoothing != 0)
     return set_err(ASMG_EINVAL, "the nested iteration needs whole-level smoothing (smoothing = 0)");
@@ -147,14 +150,18 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     const bool tm = std::getenv("ASMG_SETUP_TIMING") != nullptr;
     auto t0 = std::chrono::steady_clock::now();
     auto lap = [&](const char *what) {
-      if (!tm) return;
       auto t1 = std::chrono::steady_clock::now();
-      std::fprintf(stderr, "[asmg setup] %-12s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+      const double sec = std::chrono::duration<double>(t1 - t0).count();
+      h.setup_seconds.push_back(sec);
+      if (tm) std::fprintf(stderr, "[asmg setup] %-12s %8.3f s\n", what, sec);
       t0 = t1;
     };
     build_fine(h);
     lap("fine");
-    build_tree(h);
+    if (o.setup_device == 1)
+      build_tree_device(h, o.device);
+    else
+      build_tree(h);
     if (o.domain == 1) build_domain(h);
     lap("tree");
     build_levels(h);
@@ -283,6 +290,7 @@ static int check_options(const asmg_options &o) {
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
   if (o.nested != 0) return set_err(ASMG_EINVAL, "the nested iteration is available on single-mesh handles only");
+  if (o.setup_device != 0) return set_err(ASMG_EINVAL, "the device tree build is available on single-mesh handles only");
   return ASMG_OK;
 }
 
@@ -419,6 +427,12 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
     if (name == "refined") return put(boxes_tuples(h, std::vector<BoxCode>(h.R.begin(), h.R.end())), buf, count);
     if (name == "leaves") return put(boxes_tuples(h, h.leaves), buf, count);
     if (name == "keys") return put(h.keys, buf, count);
+    if (name == "leaf_kappa") {  // kappa~ per leaf, in the order of "leaves"
+      std::vector<double> v;
+      for (BoxCode b : h.leaves) v.push_back(h.leaf_kappa.at(b));
+      return put(v, buf, count);
+    }
+    if (name == "setup_seconds") return put(h.setup_seconds, buf, count);
     if (name == "level_n") {
       std::vector<int64_t> v(h.J);
       for (int l = 1; l <= h.J; ++l) v[l - 1] = level_mesh(h, l).n();

@@ -61,6 +61,8 @@ struct Hierarchy {
   std::vector<uint8_t> dirichlet;
   asmg_options opt{};
   int threads = 0;  // host threads for the setup (0 = all cores)
+  std::vector<double> setup_seconds;  // wall time of the setup phases: fine, tree, levels,
+                                      // transfer, colourings, coarse, upload
 
   // fine problem (Section 2)
   std::vector<int64_t> dofs;          // vertex id per unknown

@@ -57,6 +57,10 @@ def test_rejects_invalid_input():
         A.Solver(coords, elems, k, device=-1, nested=1, smoothing=1)
     assert e.value.code == A.EINVAL
     A.Solver(coords, elems, k, device=-1, nested=2)
+    for bad in (dict(setup_device=1), dict(setup_device=2, device=0)):   # the device tree needs a device
+        with pytest.raises(A.AsmgError) as e:
+            A.Solver(coords, elems, k, **{"device": -1, **bad})
+        assert e.value.code == A.EINVAL
     c3, e3, _ = W.kuhn_cube_mesh(3, 0.0)
     with pytest.raises(A.AsmgError) as e:   # general domains are 2-D
         A.Solver(c3, e3, np.ones(len(e3)), device=-1, domain=1)

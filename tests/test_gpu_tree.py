@@ -1,0 +1,78 @@
+"""The cluster tree built on the device (option setup_device) against the host build and the
+oracle's tree (Sections 3.1-3.2).
+
+Bar: bit-exact. Element keys, the refined set, the leaves (with their order), J and kappa~ per
+leaf equal the host build's; the refined set and the leaves equal the oracle's; and the solve
+that follows is the same (identical iteration count and bit-identical u).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cluster
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+A = pytest.importorskip("paper_1410_2153_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _kuhn_graded():
+    coords, elems, _ = W.kuhn_cube_mesh(8, 0.1, cfg=2, item=3)
+    return dict(coords=coords ** 2, elems=elems, kappa=np.random.default_rng(0).uniform(0.5, 2, len(elems)))
+
+
+def _lshape():
+    coords, elems, _ = W.lshape_mesh(96, 0.3)
+    return dict(coords=coords, elems=elems, kappa=np.exp(np.random.default_rng(2).normal(0, 0.5, len(elems))))
+
+
+def _tiny():
+    # 2 triangles: nothing is refined, the root is the only leaf
+    coords = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    elems = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    return dict(coords=coords, elems=elems, kappa=np.array([1.0, 3.0]))
+
+
+CASES = {
+    "square64": lambda: W.make_config(0),
+    "graded20k": lambda: W.make_config(1, scale=0.01),
+    "graded200k": lambda: W.make_config(1, scale=0.1),
+    "cube16": lambda: W.make_config(2, scale=1 / 8),
+    "graded_cube": _kuhn_graded,
+    "lshape": _lshape,
+    "two_triangles": _tiny,
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_device_tree_matches_host_and_oracle(name):
+    _say(f"[gpu tree] case {name}")
+    c = CASES[name]()
+    kw = dict(device=0)
+    Sh = A.Solver(c["coords"], c["elems"], c["kappa"], **kw)
+    Sd = A.Solver(c["coords"], c["elems"], c["kappa"], setup_device=1, **kw)
+    for ex in ("keys", "refined", "leaves", "leaf_kappa"):
+        a, b = Sh.export(ex), Sd.export(ex)
+        assert a.dtype == b.dtype and np.array_equal(a, b), ex
+    assert Sh.info() == Sd.info()
+    d = c["coords"].shape[1]
+    T = cluster.BoxTree(c["coords"], c["elems"])
+    ref = Sd.export("refined").reshape(-1, d + 1)
+    assert set(map(tuple, ref.tolist())) == set(T.R)
+    lv = Sd.export("leaves").reshape(-1, d + 1)
+    assert set(map(tuple, lv.tolist())) == set(cluster.leaves(T.R, d))
+    if len(c["elems"]) > 2:
+        f = np.random.default_rng(5).uniform(-1, 1, Sh.n)
+        uh, ih, _ = Sh.solve(f, 1e-8)
+        ud, idv, _ = Sd.solve(f, 1e-8)
+        assert ih == idv and np.array_equal(uh, ud)
+    _say(name, "tree s: host", round(Sh.setup_seconds()["tree"], 4), "device", round(Sd.setup_seconds()["tree"], 4))
+
