@@ -769,6 +769,7 @@ struct BatchDevice {
   int site = 0;
   int shape_pi = 0, shape_nr = 1;
   int autotune = 1;
+  int r_nr = 0;                        // NR of the last residuals written (0: r all zero)
   int tune_k = 0, tune_live = 0;       // autotuner: candidate under trial, sites seen
   std::vector<hipEvent_t> tune_ev;     // two events per launch site
   std::vector<uint8_t> tune_has;       // site launched something
@@ -987,6 +988,9 @@ static void alloc_level_vectors(BatchDevice *dv, BLevel &L) {
   L.x32 = balloc<float>(dv, n);
   L.b32 = balloc<float>(dv, n);
   L.r32 = balloc<float>(dv, n);
+  // the residual kernel never writes the rows of the last colour group (zero after a sweep)
+  HIPCHECK(hipMemset(L.r64, 0, (size_t)std::max<int64_t>(n, 1) * 8));
+  HIPCHECK(hipMemset(L.r32, 0, (size_t)std::max<int64_t>(n, 1) * 4));
 }
 
 // a_ii, 1/a_ii and the first-pass scale id0 (1/a_ii on colour-0 rows, 0 elsewhere and on the
@@ -1411,15 +1415,23 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
 }
 
+// r = b - A x right after a forward sweep. Slice group C-1 holds only rows of the last colour of
+// their mesh, which that sweep's last pass solved with every neighbour final: their residual is
+// zero in exact arithmetic, so the kernel skips the group (r was zeroed at setup there and
+// nothing else writes it). Meshes with fewer colours have their last colour in earlier groups,
+// which are computed.
 template <int NR, class T>
 static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   if (L.nsmooth == 0) return;
   const BSell &S = L.sell;
-  slice_launch(dv, S.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed((kb_sell<1, NR, T>), slice_blocks(S.nslices, th), th, s, e0, e1, 0, S.nslices, S.srow,
-                       S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
+  const int C = (int)S.cslice.size() - 1;
+  const int s1 = C >= 1 ? S.cslice[C - 1] : S.nslices;
+  slice_launch(dv, s1, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed((kb_sell<1, NR, T>), slice_blocks(s1, th), th, s, e0, e1, 0, s1, S.srow, S.soff, S.scol,
+                 bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
   });
-  if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
+  if (dv->count_bytes && S.nslices > 0)
+    dv->bytes += (bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1)) * s1 / S.nslices;
 }
 
 // y = A x (ADD 0) or y += A x (ADD 1); FIRST: y is level Lt's right-hand side and the first colour
@@ -1652,6 +1664,22 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
   }
 }
 
+// The residual kernel leaves the rows of the last colour group unwritten, so they must hold
+// zeros in the [row][NR] layout of this NR: after residuals with another NR, clear r (eagerly,
+// never inside a captured graph).
+static void b_prepare_r(BatchDevice *dv, int nr, hipStream_t s) {
+  if (dv->r_nr != 0 && dv->r_nr != nr) {
+    auto clear = [&](BLevel &L) {
+      const size_t n = (size_t)std::max<int64_t>((int64_t)L.nrows * 4, 1);
+      HIPCHECK(hipMemsetAsync(L.r64, 0, n * 8, s));
+      HIPCHECK(hipMemsetAsync(L.r32, 0, n * 4, s));
+    };
+    clear(dv->fine);
+    for (auto &L : dv->aux) clear(L);
+  }
+  dv->r_nr = nr;
+}
+
 template <int NR>
 static int b_solve_nr(BatchDevice *dv, const double *d_F, double tol, double *d_U, int *iters, double *true_rel,
                       hipStream_t cs) {
@@ -1660,6 +1688,7 @@ static int b_solve_nr(BatchDevice *dv, const double *d_F, double tol, double *d_
   HIPCHECK(hipEventRecord(dv->ev_in, cs));
   HIPCHECK(hipStreamWaitEvent(s, dv->ev_in, 0));
   hipLaunchKernelGGL((kb_gather<NR>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->row_src0[NR], dv->row_stride, d_F, dv->f);
+  b_prepare_r(dv, NR, s);
   const int rc = dv->precision == ASMG_PREC_MIXED ? b_pcg<NR, float>(dv, tol, iters, true_rel, s)
                                                    : b_pcg<NR, double>(dv, tol, iters, true_rel, s);
   hipLaunchKernelGGL((kb_scatter<NR>), dim3(nblk(n)), dim3(BS), 0, s, n, dv->row_src0[NR], dv->row_stride, dv->u, d_U);
@@ -1694,6 +1723,7 @@ int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void 
     }
   };
   HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)dv->fine.nrows * 4 * sizeof(double), s));
+  b_prepare_r(dv, n_rhs == 1 ? 1 : n_rhs == 2 ? 2 : 4, s);
   dv->count_bytes = true;
   dv->bytes = 0;
   one();

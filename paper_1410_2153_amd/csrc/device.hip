@@ -944,6 +944,9 @@ static void alloc_vectors(Device *dv, DLevel &L) {
   L.x32 = dalloc<float>(dv, L.n);
   L.b32 = dalloc<float>(dv, L.n);
   L.r32 = dalloc<float>(dv, L.n);
+  // the residual kernel never writes the last colour's rows (zero after a forward sweep)
+  HIPCHECK(hipMemset(L.r64, 0, (size_t)std::max(L.n, 1) * 8));
+  HIPCHECK(hipMemset(L.r32, 0, (size_t)std::max(L.n, 1) * 4));
 }
 
 // sliced ELL of a host CSR: one slice group per row range (a colour class, or part of one),
@@ -1438,17 +1441,24 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
 }
 
 // r = b - A x on the rows of every slice group (all rows; with local smoothing the rows of N~+,
-// r = b elsewhere having been written with b)
+// r = b elsewhere having been written with b).
+// B_co and the V-cycle take the residual right after a forward sweep, whose last colour pass
+// solved that colour's rows with every neighbour final: their residual is zero in exact
+// arithmetic. With whole-level smoothing the kernel skips that colour's slices; their r entries
+// are zeroed at setup and nothing else writes them. `full` covers every row (the residual of an
+// arbitrary iterate, for the nested iteration).
 template <class T>
-static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s) {
+static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s, bool full = false) {
   const DSell &S = L.sell;
-  slice_launch(dv, S.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed((k_sell<1, T>), slice_blocks(S.nslices, th), th, s, e0, e1, 0, S.nslices, S.srow,
-                       S.soff, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
+  const bool skip = !full && !L.local && L.C >= 1;
+  const int s1 = skip ? S.cslice[L.C - 1] : S.nslices;
+  slice_launch(dv, s1, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed((k_sell<1, T>), slice_blocks(s1, th), th, s, e0, e1, 0, s1, S.srow, S.soff, S.scol,
+                 sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
   });
   if (S.nslices == 0) return;
   if (dv->count_bytes)
-    for (size_t g = 0; g < L.groups.size(); ++g) {
+    for (size_t g = 0; g < (skip ? (size_t)(L.C - 1) : L.groups.size()); ++g) {
       const double rows = L.groups[g].second - L.groups[g].first;
       dv->bytes += (double)L.cnnz[g] * (sizeof(T) + 4) + 4.0 * rows + 4.0 * sizeof(T) * rows;
     }
@@ -1625,7 +1635,7 @@ static void nested_start(Device *dv, hipStream_t s) {
     const T *g = NV<T>::g(dv, l);
     spmv<T, 0>(dv, L.P, NV<T>::e(dv, l - 1), e, s);
     for (int k = 0; k < dv->nested; ++k) {
-      residual<T>(dv, L, g, e, LV<T>::b(L), s);
+      residual<T>(dv, L, g, e, LV<T>::b(L), s, true);
       hipLaunchKernelGGL((k_gs_first<T>), dim3(nblk(L.n)), dim3(BS), 0, s, L.n, L.first_rows,
                          (const T *)LV<T>::b(L), LV<T>::id(L), LV<T>::x(L));
       vcycle<T>(dv, l, s);

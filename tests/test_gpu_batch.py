@@ -76,3 +76,21 @@ def test_batched_zero_rhs_systems(batch):
     U = U.cpu().numpy()
     assert np.all(U[off[1]:off[2]] == 0) and np.all(its[1] == 0)
     assert np.all(its[0] > 0)
+
+
+def test_batched_rhs_count_switch(batch):
+    # one handle solving with 4, 1, 2 and again 4 right-hand sides gives bit for bit what a fresh
+    # handle gives for each count (the residual kernel leaves rows unwritten whose zeros depend
+    # on the [row][NR] layout)
+    meshes, H = batch
+    mk = lambda: A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in meshes])
+    B = mk()
+    fresh = {}
+    for nr in (4, 1, 2, 4):
+        F = torch.from_numpy(_pack(meshes, H, nr)).cuda()
+        U, its, tr = B.solve(F, nr, 1e-8)
+        if nr not in fresh:
+            fresh[nr] = mk().solve(F, nr, 1e-8)
+        U0, its0, tr0 = fresh[nr]
+        assert np.array_equal(its, its0), nr
+        assert torch.equal(U, U0), nr
