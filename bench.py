@@ -48,36 +48,47 @@ def load_workload(scale: float):
     return out
 
 
-def counter_traffic():
-    """HBM traffic per colour-pass launch from the committed counter summary, if the kernel code
-    has not changed since the counters were taken (else None)."""
+def counter_record():
+    """The committed hardware-counter record (HBM bytes per colour-pass launch and per B_co
+    application), if the kernel code has not changed since the counters were taken (else {})."""
     from paper_1410_2153_amd.counters import source_key
     path = os.path.join(ROOT, "profiles", "traffic_k_sell_gs.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
-        return None
-    return rec.get("traffic_bytes_per_launch") if rec.get("kernel_code_key") == source_key() else None
+        return {}
+    return rec if rec.get("kernel_code_key") == source_key() else {}
 
 
 def cpu_baseline(budget_s: float = 20.0):
-    """Oracle solve phase on a bounded sample (graded family, 20k vertices), one thread."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    """Oracle solve phase on a bounded sample (graded family, 20k vertices), one thread (BLAS
+    thread pools limited to 1 for the timed region)."""
+    from threadpoolctl import threadpool_limits
+
     import workloads as W
     from oracle.hierarchy import Hierarchy
     c = W.make_config(1, scale=0.02)
     H = Hierarchy(c["coords"], c["elems"], c["kappa"])
     f = c["f_vertex"][H.dofs]
-    H.solve(f, 1e-8)  # warm-up (builds the per-colour slices)
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        H.solve(f, 1e-8)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=H.n * reps / dt, unit="DOF-solves/s", cores=1, kind="oracle",
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    with threadpool_limits(limits=1):
+        H.solve(f, 1e-8)  # warm-up (builds the per-colour slices)
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            H.solve(f, 1e-8)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    return dict(value=H.n * reps / dt, unit="DOF-solves/s", cores=1, kind="oracle", cpu_model=model,
                 sample=f"graded mesh {len(c['coords'])} vertices ({H.n} unknowns), FP64 oracle PCG to 1e-8, "
                        f"{reps} solves in {dt:.1f} s, 1 thread of {len(os.sched_getaffinity(0))}")
 
@@ -340,12 +351,18 @@ def main():
         ms_spmv, by_spmv = S64.time_kernel(0, reps=50)
         ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
         ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
+    crec = counter_record()
     roof = {"bound": "hbm", "kernel": "asmg::k_sell<0, double> (Gauss-Seidel colour pass, sliced ELL)",
             "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": counter_traffic(),
+            "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": crec.get("traffic_bytes_per_launch"),
             "bytes_per_launch": by_gs, "ms_per_launch": ms_gs}
-    vcyc = {"fp64": {"ms": ms_b64, "model_bytes": by_b64, "GBs": by_b64 / ms_b64 / 1e6},
-            "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6},
+    bco = crec.get("bco_per_application", {})
+    vcyc = {"fp64": {"ms": ms_b64, "model_bytes": by_b64, "GBs": by_b64 / ms_b64 / 1e6,
+                     "frac_of_peak": by_b64 / ms_b64 / 1e6 / HBM_PEAK_GBS,
+                     "counted_hbm_bytes": bco.get("fp64", {}).get("traffic_bytes")},
+            "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6,
+                     "frac_of_peak": by_b32 / ms_b32 / 1e6 / HBM_PEAK_GBS,
+                     "counted_hbm_bytes": bco.get("fp32", {}).get("traffic_bytes")},
             "fine_spmv_fp64": {"ms": ms_spmv, "model_bytes": by_spmv, "GBs": by_spmv / ms_spmv / 1e6}}
     out = {
         "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",

@@ -70,6 +70,47 @@ def _per_dispatch(path, counter):
     return sum(vals) / len(vals), len(vals), copy
 
 
+def _bco_kernel(name, prec):
+    """True for the kernels of one B_co application in precision prec ("double" or "float"):
+    colour passes, residuals, transfers, the bottom GEMV and a first pass run on its own."""
+    if not name.startswith("asmg::"):
+        return False
+    k = name[len("asmg::"):]
+    if k == "k_gs_first_cvt":
+        return prec == "float"
+    # position of the value type among the template arguments
+    pos = {"k_sell": 1, "k_sell_spmv": 2, "k_gemv": 0, "k_gs_first": 0}
+    base, _, args = k.partition("<")
+    if base not in pos or not args:
+        return False
+    targs = args.rstrip(">").replace(" ", "").split(",")
+    return len(targs) > pos[base] and targs[pos[base]] == prec
+
+
+def bco_traffic(fetch_csv, write_csv, f_scale, w_scale):
+    """HBM bytes per B_co application from the counter runs (FP64 and FP32 V-cycle kernels; the
+    number of applications is the number of bottom GEMV dispatches in that precision)."""
+    out = {}
+    for prec, key in (("double", "fp64"), ("float", "fp32")):
+        tot = {}
+        for path, counter, scale in ((fetch_csv, "FETCH_SIZE", f_scale), (write_csv, "WRITE_SIZE", w_scale)):
+            s, napp = 0.0, 0
+            for r in csv.DictReader(open(path)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = _name(r["Kernel_Name"])
+                if _bco_kernel(name, prec):
+                    s += float(r["Counter_Value"]) * 1024.0 * scale
+                if name == f"asmg::k_gemv<{prec}>":
+                    napp += 1
+            tot[counter] = (s, napp)
+        napp = tot["FETCH_SIZE"][1]
+        if napp:
+            fb, wb = tot["FETCH_SIZE"][0] / napp, tot["WRITE_SIZE"][0] / napp
+            out[key] = {"applications": napp, "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb}
+    return out
+
+
 def record(fetch_csv, write_csv):
     f_kib, n, f_copy = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w_kib, n2, w_copy = _per_dispatch(write_csv, "WRITE_SIZE")
@@ -96,6 +137,7 @@ def record(fetch_csv, write_csv):
         "fetch_bytes_per_launch": fb,
         "write_bytes_per_launch": wb,
         "traffic_bytes_per_launch": fb + wb,
+        "bco_per_application": bco_traffic(fetch_csv, write_csv, f_scale, w_scale),
         "commands": [cmd.format(c="FETCH_SIZE", d="fetch"), cmd.format(c="WRITE_SIZE", d="write"),
                      "python -m paper_1410_2153_amd.counters traffic <out>/pmc_fetch/run_counter_collection.csv "
                      "<out>/pmc_write/run_counter_collection.csv profiles/traffic_k_sell_gs.json"],

@@ -34,6 +34,17 @@ def test_traffic_record_scales_by_the_copy(tmp_path):
     assert rec["kernel_code_key"] == C.source_key()
 
 
+def test_bco_kernel_classification():
+    yes64 = ["asmg::k_sell<0, double>", "asmg::k_sell<1, double>", "asmg::k_sell_spmv<0, 1, double, 16>",
+             "asmg::k_sell_spmv<1, 0, double, 32>", "asmg::k_gemv<double>", "asmg::k_gs_first<double>"]
+    yes32 = [n.replace("double", "float") for n in yes64] + ["asmg::k_gs_first_cvt"]
+    no = ["asmg::k_cg_spmv", "asmg::k_cg_rz<double>", "asmg::k_cg_axpy<float>", "asmg::kb_sell<0, 4, double>",
+          "__amd_rocclr_copyBuffer", "asmg::k_true_res<8>"]
+    assert all(C._bco_kernel(n, "double") and not C._bco_kernel(n, "float") for n in yes64)
+    assert all(C._bco_kernel(n, "float") and not C._bco_kernel(n, "double") for n in yes32)
+    assert not any(C._bco_kernel(n, p) for n in no for p in ("double", "float"))
+
+
 def test_source_key_ignores_comments_and_whitespace(tmp_path):
     a, b, c = tmp_path / "a.hip", tmp_path / "b.hip", tmp_path / "c.hip"
     a.write_text("int f(int x) { return x + 1; }\n")
