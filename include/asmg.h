@@ -84,10 +84,11 @@ typedef struct {
                           e_l = P_l e_(l-1) and k V-cycles (Algorithm 2) on A_l e = g_l, in the
                           V-cycle's precision; u_0 = Pi e_J. Single-mesh handles with whole-level
                           smoothing (smoothing = 0) only. */
-  int setup_device;    /* 1 = build the cluster tree (Sections 3.1-3.2: root box, keys, Morton sort,
-                          refinement by cluster size, closure, leaves, kappa~) on the HIP device,
-                          with results identical to the host build; needs device >= 0; single-mesh
-                          handles. 0 = host (default). */
+  int setup_device;    /* 1 = assemble the fine matrix (Section 2) and build the cluster tree
+                          (Sections 3.1-3.2: root box, keys, Morton sort, refinement by cluster
+                          size, closure, leaves, kappa~) on the HIP device, with results identical
+                          to the host setup; the later setup steps stay on the host. Needs
+                          device >= 0; single-mesh handles. 0 = host (default). */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */

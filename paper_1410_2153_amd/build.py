@@ -2,7 +2,8 @@
 
 Sources: csrc/setup.cpp (host setup), csrc/domain.cpp (general-domain predicates),
 csrc/api.cpp (C ABI), csrc/device.hip and csrc/batch.hip (kernels and PCG drivers),
-csrc/tree.hip (the cluster tree built on the device, option setup_device).
+csrc/tree.hip and csrc/assemble.hip (the cluster tree and the fine matrix built on the device,
+option setup_device).
 The host setup is compiled without floating-point contraction, so barycenters, box
 keys and the exact orientation predicates are plain IEEE operations.
 """
@@ -36,9 +37,11 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("device.hip", "batch.hip", "tree.hip"):
+    # the device setup reproduces the host setup's IEEE operations: no contraction there either
+    for src, extra in (("device.hip", []), ("batch.hip", []), ("tree.hip", ["-ffp-contract=off"]),
+                       ("assemble.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"])

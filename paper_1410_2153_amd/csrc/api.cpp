@@ -156,7 +156,10 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
       if (tm) std::fprintf(stderr, "[asmg setup] %-12s %8.3f s\n", what, sec);
       t0 = t1;
     };
-    build_fine(h);
+    if (o.setup_device == 1)
+      build_fine_device(h, o.device);
+    else
+      build_fine(h);
     lap("fine");
     if (o.setup_device == 1)
       build_tree_device(h, o.device);

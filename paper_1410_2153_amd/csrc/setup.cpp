@@ -214,7 +214,7 @@ void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]) {
     }
 }
 
-void build_fine(Hierarchy &h) {
+void fine_dofs(Hierarchy &h) {
   const int d = h.d;
   if (h.dirichlet.empty() && h.opt.domain == 1) {
     // the mesh's own domain: Dirichlet data on its boundary vertices (edges of one triangle)
@@ -256,6 +256,11 @@ void build_fine(Hierarchy &h) {
       h.dof_of_vertex[v] = (int64_t)h.dofs.size();
       h.dofs.push_back(v);
     }
+}
+
+void build_fine(Hierarchy &h) {
+  const int d = h.d;
+  fine_dofs(h);
   pattern_from_elements(h.n(), h.ne, d + 1,
                         [&](int64_t e, int i) { return h.dof_of_vertex[h.elems[e * (d + 1) + i]]; }, h.A);
   assemble_fine_values(h);

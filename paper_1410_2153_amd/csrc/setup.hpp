@@ -98,7 +98,8 @@ struct Hierarchy {
 };
 
 // setup steps (setup.cpp)
-void build_fine(Hierarchy &h);
+void fine_dofs(Hierarchy &h);   // Dirichlet mask (default rules), unknown numbering
+void build_fine(Hierarchy &h);  // fine_dofs, then the pattern and values of A
 void assemble_fine_values(Hierarchy &h);
 void build_tree(Hierarchy &h);
 void build_levels(Hierarchy &h);

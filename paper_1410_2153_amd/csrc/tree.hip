@@ -32,6 +32,9 @@
 #include "setup.hpp"
 #include "tree.hpp"
 
+// every floating-point operation below rounds on its own (no fused multiply-add), as on the host
+#pragma clang fp contract(off)
+
 namespace asmg {
 namespace {
 

@@ -1,4 +1,4 @@
-// Cluster tree on the device (tree.hip).
+// Setup steps on the device (tree.hip, assemble.hip), option setup_device.
 #pragma once
 
 #include "setup.hpp"
@@ -8,5 +8,9 @@ namespace asmg {
 // Root box, element keys, refined sets R0 and R (closure), leaves, J and kappa~ of h, as
 // build_tree computes them on the host, built on HIP device `ordinal`.
 void build_tree_device(Hierarchy &h, int ordinal);
+
+// Dirichlet mask and unknown numbering (host, fine_dofs), then the pattern and values of the
+// fine matrix A on HIP device `ordinal`, bit-identical to build_fine.
+void build_fine_device(Hierarchy &h, int ordinal);
 
 }  // namespace asmg

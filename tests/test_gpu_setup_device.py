@@ -1,9 +1,10 @@
-"""The cluster tree built on the device (option setup_device) against the host build and the
-oracle's tree (Sections 3.1-3.2).
+"""The setup steps built on the device (option setup_device: the fine matrix, Section 2, and
+the cluster tree, Sections 3.1-3.2) against the host setup and the oracle.
 
-Bar: bit-exact. Element keys, the refined set, the leaves (with their order), J and kappa~ per
-leaf equal the host build's; the refined set and the leaves equal the oracle's; and the solve
-that follows is the same (identical iteration count and bit-identical u).
+Bar: bit-exact. The unknown numbering, the fine matrix (pattern and values), element keys, the
+refined set, the leaves (with their order), J and kappa~ per leaf equal the host build's; the
+refined set and the leaves equal the oracle's, and the fine matrix equals the oracle's within
+1e-13; and the solve that follows is the same (identical iteration count and bit-identical u).
 """
 import sys
 
@@ -11,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import cluster
+from oracle import cluster, fem
 
 pytestmark = pytest.mark.gpu
 
@@ -59,9 +60,10 @@ def test_device_tree_matches_host_and_oracle(name):
     kw = dict(device=0)
     Sh = A.Solver(c["coords"], c["elems"], c["kappa"], **kw)
     Sd = A.Solver(c["coords"], c["elems"], c["kappa"], setup_device=1, **kw)
-    for ex in ("keys", "refined", "leaves", "leaf_kappa"):
+    for ex in ("keys", "refined", "leaves", "leaf_kappa", "A_rowptr", "A_col", "A_val"):
         a, b = Sh.export(ex), Sd.export(ex)
         assert a.dtype == b.dtype and np.array_equal(a, b), ex
+    assert np.array_equal(Sh.dof_vertex(), Sd.dof_vertex())
     assert Sh.info() == Sd.info()
     d = c["coords"].shape[1]
     T = cluster.BoxTree(c["coords"], c["elems"])
@@ -69,10 +71,25 @@ def test_device_tree_matches_host_and_oracle(name):
     assert set(map(tuple, ref.tolist())) == set(T.R)
     lv = Sd.export("leaves").reshape(-1, d + 1)
     assert set(map(tuple, lv.tolist())) == set(cluster.leaves(T.R, d))
+    Ao, dofs = fem.assemble(c["coords"], c["elems"], c["kappa"], None)
+    assert np.array_equal(Sd.dof_vertex(), dofs)
+    if Sd.n:
+        Ad = Sd.export_csr("A", shape=Ao.shape)
+        assert abs(Ad - Ao).max() <= 1e-13 * abs(Ao).max()
     if len(c["elems"]) > 2:
         f = np.random.default_rng(5).uniform(-1, 1, Sh.n)
         uh, ih, _ = Sh.solve(f, 1e-8)
         ud, idv, _ = Sd.solve(f, 1e-8)
         assert ih == idv and np.array_equal(uh, ud)
-    _say(name, "tree s: host", round(Sh.setup_seconds()["tree"], 4), "device", round(Sd.setup_seconds()["tree"], 4))
+    th, td = Sh.setup_seconds(), Sd.setup_seconds()
+    _say(name, "fine + tree s: host", round(th["fine"] + th["tree"], 4), "device", round(td["fine"] + td["tree"], 4))
+
+
+def test_device_assembly_rejects_degenerate_elements():
+    c = _tiny()
+    elems = c["elems"].copy()
+    elems[1] = [1, 1, 2]   # zero area
+    with pytest.raises(A.AsmgError) as e:
+        A.Solver(c["coords"], elems, c["kappa"], device=0, setup_device=1)
+    assert e.value.code == A.EINVAL and "degenerate element 1" in str(e.value)
 
