@@ -125,7 +125,9 @@ int asmg_update_coefficient(asmg_handle h, const double *kappa);
  * the last asmg_setup / asmg_update_coefficient. The preconditioner stays SPD
  * (its Gauss-Seidel part uses the new A). Later solves are exact for the new A
  * to the requested tolerance; only the iteration count may change. Host-side
- * exports of A are not updated. Stream-ordered on `stream`.
+ * exports of A are not updated. Stream-ordered on `stream`. The per-entry element
+ * lists this needs are built at the first call (host work proportional to the
+ * mesh, then uploaded), not at setup.
  */
 int asmg_set_coefficient_device(asmg_handle h, const double *d_kappa, void *stream);
 

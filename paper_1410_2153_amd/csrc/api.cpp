@@ -264,7 +264,7 @@ int asmg_apply_preconditioner_device(asmg_handle H, const double *d_r, double *d
 int asmg_set_coefficient_device(asmg_handle H, const double *d_kappa, void *stream) {
   if (int r = need_dev(H)) return r;
   if (!d_kappa) return set_err(ASMG_EINVAL, "null coefficient");
-  ASMG_TRY({ return device_set_coefficient(H->dev, d_kappa, stream); })
+  ASMG_TRY({ return device_set_coefficient(H->dev, H->h, d_kappa, stream); })
 }
 
 int asmg_matvec_device(asmg_handle H, const double *d_x, double *d_y, void *stream) {

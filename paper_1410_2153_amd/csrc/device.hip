@@ -23,6 +23,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -744,6 +747,7 @@ struct Device {
   int *rf_off_ptr = nullptr, *rf_off_el = nullptr, *rf_dg_ptr = nullptr, *rf_dg_el = nullptr, *rf_sell_map = nullptr;
   double *rf_off_w = nullptr, *rf_dg_w = nullptr;
   int rf_nslots = 0;
+  bool rf_ready = false;      // the refresh maps are built at the first device coefficient refresh
   // element data for the gradient
   double *coords = nullptr, *kappa = nullptr;
   int *elems = nullptr, *dof_of_vertex = nullptr;
@@ -1163,6 +1167,14 @@ Device *device_create(Hierarchy &h, int ordinal) {
   if (ordinal < 0 || ordinal >= count) throw AsmgError{ASMG_EDEVICE, "no such HIP device"};
   HIPCHECK(hipSetDevice(ordinal));
   Device *dv = new Device();
+  const bool tm = std::getenv("ASMG_SETUP_TIMING") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char *what) {
+    if (!tm) return;
+    auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[asmg upload] %-16s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  };
   try {
     dv->ordinal = ordinal;
     dv->d = h.d;
@@ -1178,10 +1190,9 @@ Device *device_create(Hierarchy &h, int ordinal) {
     // neighbours in the numbering are neighbours in space, whatever the mesh's own numbering)
     const std::vector<int> mrank = morton_rank(h);
     colour_order(h.colour_fine, dv->fine, &mrank);
-    HCsr Hfine;
-    std::vector<int> fine_slots;
-    upload_level_matrix(dv, dv->fine, h.A, true, &Hfine, &fine_slots);
-    build_refresh(dv, h, Hfine, fine_slots);
+    lap("fine order");
+    upload_level_matrix(dv, dv->fine, h.A, true);
+    lap("fine matrix");
     alloc_vectors(dv, dv->fine);
     dv->perm_d = dupload(dv, dv->fine.perm);
     // auxiliary levels
@@ -1195,6 +1206,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
       upload_level_matrix(dv, L, h.Al.at(l), true);
       alloc_vectors(dv, L);
     }
+    lap("aux levels");
     // prolongations in internal numbering; slices visit the rows in each level's own (Morton)
     // numbering: position k holds internal row iperm[k] (the bottom level keeps its numbering)
     for (int l = h.J; l > h.lc; --l) {
@@ -1205,6 +1217,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
       upload_transfer(dv, P, L.P, &L.iperm);
       upload_transfer(dv, transpose(P), L.PT, cmap);
     }
+    lap("prolongations");
     // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom);
     // Pi's slices visit the original-grid unknowns in Morton order of their vertices
     {
@@ -1215,6 +1228,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
       upload_transfer(dv, Pi, dv->Pi, &forder);
       upload_transfer(dv, transpose(Pi), dv->PiT, cmap);
     }
+    lap("Pi");
     upload_coarse(dv, h, true);
     dv->nested = h.opt.nested;
     if (dv->nested > 0) {
@@ -1835,10 +1849,20 @@ int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *it
   return rc;
 }
 
-int device_set_coefficient(Device *dv, const double *d_kappa, void *stream) {
+int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream) {
   HIPCHECK(hipSetDevice(dv->ordinal));
   hipStream_t s = (hipStream_t)stream;
   DLevel &F = dv->fine;
+  if (!dv->rf_ready) {
+    // element lists of every entry of A and the sliced-ELL slot of every entry: built once, at
+    // the first refresh (they do not depend on kappa), so that setups that never refresh skip them
+    std::vector<double> diag;
+    HCsr H = permute(h.A, F.perm, &F.iperm, true, &diag);
+    std::vector<int> slots;
+    build_sell(dv, F, H, false, &slots);
+    build_refresh(dv, h, H, slots);
+    dv->rf_ready = true;
+  }
   HIPCHECK(hipMemcpyAsync(dv->kappa, d_kappa, (size_t)dv->ne * 8, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_refresh_off, dim3(nblk(F.A.nnz)), dim3(BS), 0, s, (int)F.A.nnz, dv->rf_off_ptr, dv->rf_off_el,
                      dv->rf_off_w, dv->kappa, F.A.v64, F.A.v32);

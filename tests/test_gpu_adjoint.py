@@ -79,3 +79,21 @@ def test_set_coefficient_device_refreshes_operator():
     uv[dofs] = u
     lv[dofs] = lam
     assert np.abs(g - fem.element_gradient_of_energy(coords, elems, k2, uv, lv)).max() <= 1e-12 * np.abs(g).max()
+
+
+def test_set_coefficient_device_twice_after_a_solve():
+    # the refresh maps are built at the first refresh (here after a solve) and reused
+    c = W.make_config(1, scale=0.01)
+    coords, elems = c["coords"], c["elems"]
+    S = A.Solver(coords, elems, c["kappa"])
+    f = c["f_vertex"][S.dof_vertex()]
+    S.solve(f, 1e-8)
+    for seed in (10, 11):
+        k = np.exp(np.random.default_rng(seed).normal(0, 0.7, len(elems)))
+        S.set_coefficient_device(torch.from_numpy(k).cuda())
+        Ak, dofs = fem.assemble(coords, elems, k)
+        x = np.random.default_rng(seed).standard_normal(S.n)
+        y = S.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.linalg.norm(y - Ak @ x) <= 1e-14 * np.linalg.norm(Ak @ x)
+        u, it, tr = S.solve(f, 1e-10)
+        assert np.linalg.norm(f - Ak @ u) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(f)
