@@ -179,7 +179,9 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
  * on `stream` between two HIP events and returns the mean duration in ms and
  * the algorithmic bytes one launch moves.
  *   which: 0 = fine SpMV q = A p (FP64), 1 = fine Gauss-Seidel sweep (all colours),
- *          2 = one full B_co application, 3 = same as 2 in the precision set at setup,
+ *          2 = one full B_co application (captured in a hipGraph; *ms is the median
+ *          over `reps` replays, each between its own events), 3 = same as 2 in the
+ *          precision set at setup,
  *          4 (or 5) = the Gauss-Seidel colour-pass kernel (sliced ELL): inside `reps`
  *          full B_co applications every colour pass is launched once with a pair of HIP
  *          events stamped with that launch's own start and end (hipExtLaunchKernel), so

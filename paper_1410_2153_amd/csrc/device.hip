@@ -1942,12 +1942,13 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   DLevel &F = dv->fine;
   const int n = F.n;
   const bool mixed = which == 3 ? dv->precision == ASMG_PREC_MIXED : precision == ASMG_PREC_MIXED;
-  auto bco = [&]() {
+  auto bco_on = [&](hipStream_t st) {
     if (mixed)
-      apply_Bco<float>(dv, dv->f, false, s);
+      apply_Bco<float>(dv, dv->f, false, st);
     else
-      apply_Bco<double>(dv, dv->f, false, s);
+      apply_Bco<double>(dv, dv->f, false, st);
   };
+  auto bco = [&]() { bco_on(s); };
   auto one = [&]() {
     if (which == 0) {
       with_lpr(F.A.lpr, [&](auto c) {
@@ -2005,6 +2006,39 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
     one();
   dv->count_bytes = false;
   *bytes = dv->bytes;
+  if (which == 2 || which == 3) {
+    // one B_co application captured in a hipGraph, as the solve runs it: median over `reps`
+    // replays, each between its own pair of events (on the handle's stream, after `s` drained)
+    HIPCHECK(hipEventDestroy(e0));
+    HIPCHECK(hipEventDestroy(e1));
+    HIPCHECK(hipStreamSynchronize(s));
+    hipStream_t gs = dv->stream;
+    hipGraph_t g;
+    hipGraphExec_t ge;
+    HIPCHECK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    bco_on(gs);
+    HIPCHECK(hipStreamEndCapture(gs, &g));
+    HIPCHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    HIPCHECK(hipGraphDestroy(g));
+    HIPCHECK(hipGraphLaunch(ge, gs));  // warm-up
+    const int R = std::max(reps, 1);
+    std::vector<hipEvent_t> ev(2 * R);
+    for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+    for (int k = 0; k < R; ++k) {
+      HIPCHECK(hipEventRecord(ev[2 * k], gs));
+      HIPCHECK(hipGraphLaunch(ge, gs));
+      HIPCHECK(hipEventRecord(ev[2 * k + 1], gs));
+    }
+    HIPCHECK(hipStreamSynchronize(gs));
+    std::vector<float> t(R);
+    for (int k = 0; k < R; ++k) HIPCHECK(hipEventElapsedTime(&t[k], ev[2 * k], ev[2 * k + 1]));
+    for (auto &e : ev) HIPCHECK(hipEventDestroy(e));
+    HIPCHECK(hipGraphExecDestroy(ge));
+    std::sort(t.begin(), t.end());
+    *ms = R % 2 ? (double)t[R / 2] : 0.5 * ((double)t[R / 2 - 1] + (double)t[R / 2]);
+    HIPCHECK(hipGetLastError());
+    return ASMG_OK;
+  }
   one();  // warm-up
   HIPCHECK(hipEventRecord(e0, s));
   for (int k = 0; k < reps; ++k) one();

@@ -187,3 +187,18 @@ def test_autotuned_shapes_do_not_change_b_co(case):
     assert len(shapes) > 0 and set(shapes[:, 0].tolist()) <= {128, 256, 512}
     z1 = S.apply_preconditioner(r).cpu().numpy()
     assert np.array_equal(z0, z1)
+
+
+def test_kernel_timing_leaves_the_solver_intact():
+    # asmg_time_kernel: SpMV, B_co as graph replays (both precisions), colour passes with
+    # kernel-stamped events; all positive, and a solve afterwards is unchanged
+    c = W.make_config(1, scale=0.01)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"])
+    f = c["f_vertex"][S.dof_vertex()]
+    u0, it0, _ = S.solve(f, 1e-8)
+    for which, prec in ((0, A.PREC_FP64), (2, A.PREC_FP64), (2, A.PREC_MIXED), (4, A.PREC_FP64)):
+        ms, by = S.time_kernel(which, reps=20, precision=prec)
+        _say("time_kernel", which, prec, f"{ms * 1e3:.1f} us, {by / 1e6:.2f} MB")
+        assert 0 < ms < 1e3 and by > 0
+    u1, it1, _ = S.solve(f, 1e-8)
+    assert it1 == it0 and np.array_equal(u1, u0)
