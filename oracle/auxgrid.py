@@ -76,7 +76,7 @@ def morton_order(X: np.ndarray) -> np.ndarray:
 class LevelMesh:
     """sigma^(l): integer vertices, simplices and unknown numbering of one level."""
 
-    def __init__(self, verts, simp, simp_box, simp_tmpl, boxes, box_fan, J, d, kept=None):
+    def __init__(self, verts, simp, simp_box, simp_tmpl, boxes, box_fan, J, d, kept=None, touch=None):
         self.verts = verts            # (nv, d) int64, Morton order
         self.simp = simp              # (ns, d+1) int64 into verts
         self.simp_box = simp_box      # (ns,) index into boxes
@@ -90,7 +90,15 @@ class LevelMesh:
         # general domain (Section 3.4): only the kept simplices form the grid, and an unknown
         # needs its whole star kept
         self.kept = np.ones(len(simp), dtype=bool) if kept is None else np.asarray(kept, dtype=bool)
-        if kept is not None:
+        if touch is not None:
+            # mixed grids: every vertex of a kept simplex, except the vertices of simplices that
+            # meet Gamma_D (essential conditions there; natural ones elsewhere, root box included)
+            inkept = np.zeros(len(verts), dtype=bool)
+            inkept[simp[self.kept].ravel()] = True
+            bad = np.zeros(len(verts), dtype=bool)
+            bad[simp[np.asarray(touch, dtype=bool)].ravel()] = True
+            self.interior = inkept & ~bad
+        elif kept is not None:
             bad = np.zeros(len(verts), dtype=bool)
             bad[simp[~self.kept].ravel()] = True
             self.interior &= ~bad
@@ -103,7 +111,8 @@ class LevelMesh:
 class AuxMeshes:
     """All level meshes sigma^(1..J) of a closed box tree."""
 
-    def __init__(self, tree, domain=None):
+    def __init__(self, tree, domain=None, mixed=False):
+        self.mixed = mixed            # mixed Dirichlet/Neumann grids (domain must be given)
         self.tree = tree
         self.d = tree.d
         self.J = tree.J
@@ -273,10 +282,14 @@ class AuxMeshes:
         rank[order] = np.arange(len(order))
         verts = uniq[order]
         simp = rank[inv.ravel()].reshape(len(simps), d + 1)
-        kept = None
-        if self.domain is not None:
+        kept = touch = None
+        if self.domain is not None and self.mixed:
+            kt = np.array([self.domain.mixed(self.tree, verts[t]) for t in simp], dtype=bool).reshape(-1, 2)
+            kept, touch = kt[:, 0], kt[:, 1]
+        elif self.domain is not None:
             kept = np.array([self.domain.keeps(self.tree, verts[t]) for t in simp], dtype=bool)
-        lm = LevelMesh(verts, simp, np.array(sbox), np.array(stmpl), boxes, np.array(fan), self.J, d, kept)
+        lm = LevelMesh(verts, simp, np.array(sbox), np.array(stmpl), boxes, np.array(fan), self.J, d, kept,
+                       touch)
         self._cache[level] = lm
         return lm
 

@@ -83,8 +83,11 @@ def simplex_kappa(meshes, lm, w):
 def stiffness(meshes, lm, kappa_s, unit_length):
     """Assemble A_l over the unknowns of level mesh lm (exact zeros dropped)."""
     d = lm.d
-    V = lm.verts[lm.simp]                                   # (ns, d+1, d)
-    box_level = np.array([lm.boxes[i][0] for i in lm.simp_box])
+    sel = lm.kept                                           # the grid's simplices (all, or kept)
+    simp = lm.simp[sel]
+    kappa_s = np.asarray(kappa_s)[sel]
+    V = lm.verts[simp]                                      # (ns, d+1, d)
+    box_level = np.array([lm.boxes[i][0] for i in lm.simp_box[sel]], dtype=np.int64)
     half = (1 << (lm.J - box_level)).astype(np.int64)       # half side in units
     E = (V[:, 1:, :] - V[:, :1, :])
     assert np.all(E % half[:, None, None] == 0)
@@ -98,8 +101,8 @@ def stiffness(meshes, lm, kappa_s, unit_length):
     K = K * kappa_s[:, None, None]
     nv = len(lm.verts)
     k = d + 1
-    rows = np.repeat(lm.simp, k, axis=1).ravel()
-    cols = np.tile(lm.simp, (1, k)).ravel()
+    rows = np.repeat(simp, k, axis=1).ravel()
+    cols = np.tile(simp, (1, k)).ravel()
     A = sp.coo_matrix((K.ravel(), (rows, cols)), shape=(nv, nv)).tocsr()
     A.sum_duplicates()
     A = A[lm.dof_vert][:, lm.dof_vert].tocsr()

@@ -21,6 +21,21 @@ Readings:
   dropped simplex therefore has no unknown among its vertices, and the assembly, the nodal
   P_l and the Scott-Zhang transfer need no other change.
 
+Mixed Dirichlet/Neumann auxiliary grids (the remark of Section 3.5; ``Domain(..., dirichlet)``,
+``mixed``): T^M_l = {tau in sigma^(l) : tau meets Omega and tau does not meet Gamma_D}, with
+natural (Neumann) conditions on the auxiliary boundary except next to Gamma_D. Readings:
+* Gamma_D is the union of the mesh's boundary edges whose two vertices are Dirichlet vertices.
+* "Meets" is between closed sets. A closed triangle meets Omega iff a boundary edge of the
+  mesh meets it, or (no boundary edge meets it, so it lies entirely inside or entirely
+  outside) its interior point (2 v0 + v1 + v2) / 4 lies in Omega.
+* A closed segment and a closed triangle are disjoint iff the line of one edge of the triangle
+  has both segment ends strictly outside, or the segment's line has the three triangle
+  vertices strictly on one side.
+* Essential (Dirichlet) conditions at the "neighbours of boxes meeting Gamma_D": the vertices
+  of every simplex of sigma^(l) that meets Gamma_D. Every other vertex of a kept simplex is an
+  unknown, on the root box boundary too (natural conditions there).
+* The near-boundary correction of Algorithm 3 is not part of this option.
+
 Pins: the 64 x 64 square keeps every simplex and gives the box hierarchy unchanged; on an
 L-shaped domain whose re-entrant corner sits on a dyadic line, the kept simplices are exactly
 those of sigma^(l) outside the removed quadrant; kept simplices pass a dense point-sampling
@@ -57,7 +72,7 @@ def _orient(a, b, c):
 class Domain:
     """The closed union of a 2-D mesh's triangles, with exact membership tests."""
 
-    def __init__(self, coords, elems):
+    def __init__(self, coords, elems, dirichlet=None):
         coords = np.asarray(coords, dtype=np.float64)
         elems = np.asarray(elems, dtype=np.int64)
         if coords.shape[1] != 2:
@@ -68,6 +83,13 @@ class Domain:
         self.tris = elems
         self.ebox = np.stack([coords[self.bedges].min(axis=1), coords[self.bedges].max(axis=1)], axis=1)
         self.tbox = np.stack([coords[elems].min(axis=1), coords[elems].max(axis=1)], axis=1)
+        # Gamma_D: boundary edges with both vertices Dirichlet (mixed grids)
+        self.gd = np.zeros((0, 2), dtype=np.int64)
+        if dirichlet is not None:
+            m = np.asarray(dirichlet, dtype=bool)
+            self.gd = self.bedges[m[self.bedges[:, 0]] & m[self.bedges[:, 1]]]
+        self.gbox = (np.stack([coords[self.gd].min(axis=1), coords[self.gd].max(axis=1)], axis=1)
+                     if len(self.gd) else np.zeros((0, 2, 2)))
 
     def aux_point(self, tree, X):
         """Double coordinates of an integer point of the finest box grid (units 2^-J of L)."""
@@ -84,6 +106,42 @@ class Domain:
         if all(x >= 0 for x in o) or all(x <= 0 for x in o):
             return False
         return True
+
+    @staticmethod
+    def _segment_meets_closed(p, q, T):
+        for i in range(3):
+            a, b, c = T[i], T[(i + 1) % 3], T[(i + 2) % 3]
+            side = _orient(a, b, c)
+            if _orient(a, b, p) * side < 0 and _orient(a, b, q) * side < 0:
+                return False
+        o = [_orient(p, q, v) for v in T]
+        if all(x > 0 for x in o) or all(x < 0 for x in o):
+            return False
+        return True
+
+    def _edges_meet_closed(self, edges, boxes, T, lo, hi):
+        if not len(edges):
+            return False
+        cand = np.nonzero((boxes[:, 0, 0] <= hi[0]) & (lo[0] <= boxes[:, 1, 0]) &
+                          (boxes[:, 0, 1] <= hi[1]) & (lo[1] <= boxes[:, 1, 1]))[0]
+        return any(self._segment_meets_closed(self.F[edges[e][0]], self.F[edges[e][1]], T) for e in cand)
+
+    def mixed(self, tree, Xs):
+        """(kept, meets Gamma_D) of the auxiliary triangle with integer vertices Xs in the mixed
+        grids: kept iff it meets Omega and not Gamma_D (closed sets)."""
+        pts = [self.aux_point(tree, X) for X in Xs]
+        T = [(Fraction(float(p[0])), Fraction(float(p[1]))) for p in pts]
+        lo = np.min(pts, axis=0)
+        hi = np.max(pts, axis=0)
+        if self._edges_meet_closed(self.gd, self.gbox, T, lo, hi):
+            return False, True
+        if self._edges_meet_closed(self.bedges, self.ebox, T, lo, hi):
+            return True, False
+        X = np.asarray(Xs, dtype=np.int64)
+        inner = 2 * X[0] + X[1] + X[2]
+        s = 2.0 ** (-(tree.J + 2))
+        c = np.array([tree.a[k] + tree.L * (float(inner[k]) * s) for k in range(2)])
+        return self.contains_point(c), False
 
     def contains_point(self, x):
         """x (two doubles) in the closed union of the triangles."""

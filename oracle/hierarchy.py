@@ -2,7 +2,8 @@
 
 ``domain="box"`` builds the Dirichlet auxiliary grids on the root box (every simplex of
 sigma^(l)); ``domain="mesh"`` keeps only the simplices inside the mesh's own domain
-(``domain``, 2-D).
+(``domain``, 2-D); ``domain="mixed"`` builds the mixed Dirichlet/Neumann grids (simplices that
+meet the domain and not its Dirichlet boundary, 2-D).
 
 ``Hierarchy(coords, elems, kappa)`` builds the fine matrix (``fem``), the closed
 box tree (``cluster``), the level meshes (``auxgrid``), the auxiliary operators
@@ -25,18 +26,23 @@ class Hierarchy:
         self.elems = elems
         self.kappa = np.asarray(kappa, dtype=np.float64)
         self.d = coords.shape[1]
-        if domain == "mesh" and dirichlet is None:
+        if domain in ("mesh", "mixed") and dirichlet is None:
             from .domain import boundary_vertices
             dirichlet = boundary_vertices(elems, len(coords))
         self.A, self.dofs = fem.assemble(coords, elems, self.kappa, dirichlet)
         self.tree = cluster.BoxTree(coords, elems, n_min, check_literal=check_literal)
-        if domain not in ("box", "mesh"):
+        if domain not in ("box", "mesh", "mixed"):
             raise ValueError(domain)
         dom = None
         if domain == "mesh":       # Section 3.4 on the mesh's own (2-D polygonal) domain
             from .domain import Domain
             dom = Domain(coords, elems)
-        self.meshes = auxgrid.AuxMeshes(self.tree, dom)
+        if domain == "mixed":      # the mixed Dirichlet/Neumann grids (remark of Section 3.5)
+            from .domain import Domain
+            mask = np.zeros(len(coords), dtype=bool)
+            mask[np.setdiff1d(np.arange(len(coords)), self.dofs)] = True
+            dom = Domain(coords, elems, mask)
+        self.meshes = auxgrid.AuxMeshes(self.tree, dom, mixed=(domain == "mixed"))
         self.aux = auxops.AuxOperators(self.tree, self.meshes, self.kappa, coarse_max_dofs)
         self.Pi = transfer.transfer(self.tree, self.meshes, coords, elems, self.dofs)
         self.colour_fine = colour.greedy_colouring(self.A, colour_seed, colouring)
