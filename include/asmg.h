@@ -74,7 +74,12 @@ typedef struct {
                           (default; the domain is the mesh's bounding box); 1 = only the simplices
                           inside the mesh's own domain, the closed union of its triangles (2-D,
                           any polygon, holes allowed); with a null `dirichlet` the Dirichlet
-                          vertices are then the mesh's boundary vertices. */
+                          vertices are then the mesh's boundary vertices. 2 = mixed Dirichlet/
+                          Neumann grids (remark of Section 3.5, 2-D): the simplices that meet the
+                          domain and not its Dirichlet boundary Gamma_D (boundary edges whose two
+                          vertices are Dirichlet); essential conditions at the vertices of
+                          simplices meeting Gamma_D, natural ones elsewhere. Without the
+                          near-boundary correction of Algorithm 3. */
   int autotune;        /* 1 = at the first solve in a precision, time the candidate launch shapes
                           of every V-cycle slice kernel and keep the fastest (default); 0 = fixed
                           256-thread blocks in XCD order. Results do not depend on it. */

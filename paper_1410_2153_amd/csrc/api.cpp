@@ -123,8 +123,8 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
   if (opt) o = *opt;
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 1 ||
-      (o.domain == 1 && dim != 2) || o.nested < 0 || o.nested > 16 || o.setup_device < 0 || o.setup_device > 1 ||
+      o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 2 ||
+      (o.domain >= 1 && dim != 2) || o.nested < 0 || o.nested > 16 || o.setup_device < 0 || o.setup_device > 1 ||
       (o.setup_device == 1 && o.device < 0))
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.nested > 0 && o.smoothing != 0)
@@ -165,7 +165,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
       build_tree_device(h, o.device);
     else
       build_tree(h);
-    if (o.domain == 1) build_domain(h);
+    if (o.domain >= 1) build_domain(h);
     lap("tree");
     build_levels(h);
     lap("levels");
@@ -303,7 +303,7 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
   *out = nullptr;
   if (n_meshes < 1 || (dim != 2 && dim != 3) || !vert_off || !coords || !elem_off || !elems || !kappa)
     return set_err(ASMG_EINVAL, "bad batch arguments");
-  if (opt && opt->domain == 1 && dim != 2) return set_err(ASMG_EINVAL, "general domains are 2-D");
+  if (opt && opt->domain >= 1 && dim != 2) return set_err(ASMG_EINVAL, "general domains are 2-D");
   asmg_options o;
   asmg_default_options(&o);
   if (opt) o = *opt;
@@ -340,7 +340,7 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
           h->kappa.assign(kappa + elem_off[m], kappa + elem_off[m + 1]);
           build_fine(*h);
           build_tree(*h);
-          if (o.domain == 1) build_domain(*h);
+          if (o.domain >= 1) build_domain(*h);
           build_levels(*h);
           build_transfer(*h);
           build_colourings(*h);

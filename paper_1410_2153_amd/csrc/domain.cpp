@@ -148,7 +148,9 @@ struct DomainIndex {
   std::vector<int64_t> bedge;   // boundary edges, 2 vertex ids each
   std::vector<double> ebox;     // lo_x, lo_y, hi_x, hi_y per boundary edge
   std::vector<double> tbox;     // per triangle
-  Grid eg, tg;
+  std::vector<int64_t> gedge;   // Gamma_D: boundary edges with both vertices Dirichlet
+  std::vector<double> gbox;
+  Grid eg, tg, gg;
 };
 
 namespace {
@@ -206,6 +208,19 @@ bool segment_meets_open(const double *p, const double *q, const double T[3][2]) 
   return true;
 }
 
+// does the closed segment pq meet the closed triangle T? (disjoint iff an edge line of T has both
+// ends strictly outside, or the segment's line has the three vertices strictly on one side)
+bool segment_meets_closed(const double *p, const double *q, const double T[3][2]) {
+  for (int i = 0; i < 3; ++i) {
+    const double *a = T[i], *b = T[(i + 1) % 3], *c = T[(i + 2) % 3];
+    const int side = orient2d(a, b, c);
+    if (orient2d(a, b, p) * side < 0 && orient2d(a, b, q) * side < 0) return false;
+  }
+  const int o0 = orient2d(p, q, T[0]), o1 = orient2d(p, q, T[1]), o2 = orient2d(p, q, T[2]);
+  if ((o0 > 0 && o1 > 0 && o2 > 0) || (o0 < 0 && o1 < 0 && o2 < 0)) return false;
+  return true;
+}
+
 void aux_point(const Hierarchy &h, const int64_t *X, int extra_bits, double *x) {
   const double s = std::ldexp(1.0, -(h.J + extra_bits));
   for (int k = 0; k < 2; ++k) x[k] = h.a[k] + h.L * ((double)X[k] * s);
@@ -260,6 +275,14 @@ void build_domain(Hierarchy &h) {
   }
   D->eg = make_grid(h, D->ebox, nb);
   D->tg = make_grid(h, D->tbox, h.ne);
+  if (!h.dirichlet.empty())
+    for (int64_t i = 0; i < nb; ++i)
+      if (h.dirichlet[D->bedge[2 * i]] && h.dirichlet[D->bedge[2 * i + 1]]) {
+        D->gedge.push_back(D->bedge[2 * i]);
+        D->gedge.push_back(D->bedge[2 * i + 1]);
+        for (int k = 0; k < 4; ++k) D->gbox.push_back(D->ebox[i * 4 + k]);
+      }
+  D->gg = make_grid(h, D->gbox, (int64_t)D->gedge.size() / 2);
   h.domain = D;
 }
 
@@ -284,6 +307,80 @@ bool contains_point(const Hierarchy &h, const DomainIndex &D, const double *x, s
 }
 
 }  // namespace
+
+// mixed grids (2-D): kept = the closed simplex meets the domain and not Gamma_D; touch = it
+// meets Gamma_D. A closed simplex that no boundary edge meets lies entirely inside or entirely
+// outside the domain, and its interior point (2 v0 + v1 + v2) / 4 decides which.
+void domain_mixed(const Hierarchy &h, const LevelMesh &lm, std::vector<uint8_t> &kept,
+                  std::vector<uint8_t> &touch) {
+  const DomainIndex &D = *h.domain;
+  const int64_t ns = (int64_t)lm.simp_box.size();
+  kept.assign(ns, 0);
+  touch.assign(ns, 0);
+  std::vector<int64_t> seen_e(D.ebox.size() / 4, -1), seen_g(D.gbox.size() / 4, -1), seen_t(h.ne, -1);
+  int64_t stamp_e = 0, stamp_g = 0, stamp_t = 0;
+  std::vector<int64_t> cand, gcand;
+  const int J = h.J;
+  for (size_t bi = 0; bi < lm.boxes.size(); ++bi) {
+    int64_t idx[3];
+    box_index(lm.boxes[bi], 2, idx);
+    const int64_t S = (int64_t)1 << (J - box_level(lm.boxes[bi], 2) + 1);
+    const int64_t c0[2] = {idx[0] * S, idx[1] * S}, c1[2] = {idx[0] * S + S, idx[1] * S + S};
+    double lo[2], hi[2];
+    aux_point(h, c0, 0, lo);
+    aux_point(h, c1, 0, hi);
+    cand.clear();
+    gcand.clear();
+    ++stamp_e;
+    query(D.eg, lo, hi, seen_e, stamp_e, [&](int64_t i) {
+      if (boxes_meet(&D.ebox[i * 4], lo, hi)) cand.push_back(i);
+      return true;
+    });
+    if (!D.gedge.empty()) {
+      ++stamp_g;
+      query(D.gg, lo, hi, seen_g, stamp_g, [&](int64_t i) {
+        if (boxes_meet(&D.gbox[i * 4], lo, hi)) gcand.push_back(i);
+        return true;
+      });
+    }
+    for (int64_t s = lm.box_simp[bi]; s < lm.box_simp[bi + 1]; ++s) {
+      const int64_t *v = &lm.simp[s * 3];
+      double T[3][2];
+      for (int i = 0; i < 3; ++i) aux_point(h, &lm.verts[v[i] * 2], 0, T[i]);
+      bool gd = false;
+      for (int64_t i : gcand)
+        if (segment_meets_closed(&h.coords[D.gedge[2 * i] * 2], &h.coords[D.gedge[2 * i + 1] * 2], T)) {
+          gd = true;
+          break;
+        }
+      if (gd) {
+        touch[s] = 1;
+        continue;
+      }
+      bool meets = false;
+      for (int64_t i : cand)
+        if (segment_meets_closed(&h.coords[D.bedge[2 * i] * 2], &h.coords[D.bedge[2 * i + 1] * 2], T)) {
+          meets = true;
+          break;
+        }
+      if (meets) {
+        kept[s] = 1;
+        continue;
+      }
+      if (cand.empty() && s > lm.box_simp[bi]) {
+        // no boundary edge meets the closed box: every simplex of the box is on the same side
+        kept[s] = kept[lm.box_simp[bi]];
+        continue;
+      }
+      int64_t inner[2];
+      for (int k = 0; k < 2; ++k)
+        inner[k] = 2 * lm.verts[v[0] * 2 + k] + lm.verts[v[1] * 2 + k] + lm.verts[v[2] * 2 + k];
+      double x[2];
+      aux_point(h, inner, 2, x);
+      kept[s] = contains_point(h, D, x, seen_t, stamp_t) ? 1 : 0;
+    }
+  }
+}
 
 // kept flag of every simplex of a level mesh (2-D)
 std::vector<uint8_t> domain_keeps(const Hierarchy &h, const LevelMesh &lm) {

@@ -216,7 +216,7 @@ void element_unit_stiffness(const Hierarchy &h, int64_t e, double K[4][4]) {
 
 void fine_dofs(Hierarchy &h) {
   const int d = h.d;
-  if (h.dirichlet.empty() && h.opt.domain == 1) {
+  if (h.dirichlet.empty() && h.opt.domain >= 1) {
     // the mesh's own domain: Dirichlet data on its boundary vertices (edges of one triangle)
     std::vector<std::pair<int64_t, int64_t>> e;
     for (int64_t t = 0; t < h.ne; ++t)
@@ -706,7 +706,20 @@ static LevelMesh make_level_mesh(const Hierarchy &h, int level) {
   // general domain (Section 3.4): keep the simplices inside the domain; an unknown needs its
   // whole star kept
   std::vector<uint8_t> outside(nv, 0);
-  if (h.domain) {
+  const bool mixed = h.domain && h.opt.domain == 2;
+  std::vector<uint8_t> inkept;  // mixed grids: vertex of a kept simplex
+  if (mixed) {
+    // mixed Dirichlet/Neumann grids: every vertex of a kept simplex is an unknown (natural
+    // conditions, on the root box too) except the vertices of simplices meeting Gamma_D
+    std::vector<uint8_t> touch;
+    domain_mixed(h, lm, lm.kept, touch);
+    inkept.assign(nv, 0);
+    for (int64_t s = 0; s < ns; ++s)
+      for (int i = 0; i <= d; ++i) {
+        if (lm.kept[s]) inkept[lm.simp[s * (d + 1) + i]] = 1;
+        if (touch[s]) outside[lm.simp[s * (d + 1) + i]] = 1;
+      }
+  } else if (h.domain) {
     lm.kept = domain_keeps(h, lm);
     for (int64_t s = 0; s < ns; ++s)
       if (!lm.kept[s])
@@ -715,9 +728,13 @@ static LevelMesh make_level_mesh(const Hierarchy &h, int level) {
   lm.dof_of_vert.assign(nv, -1);
   for (int64_t v = 0; v < nv; ++v) {
     bool in = !outside[v];
-    for (int q = 0; q < d; ++q) {
-      int64_t x = lm.verts[v * d + q];
-      in = in && x > 0 && x < top;
+    if (mixed) {
+      in = in && inkept[v];
+    } else {
+      for (int q = 0; q < d; ++q) {
+        int64_t x = lm.verts[v * d + q];
+        in = in && x > 0 && x < top;
+      }
     }
     if (in) {
       lm.dof_of_vert[v] = (int64_t)lm.dof_vert.size();
@@ -780,13 +797,18 @@ static void assemble_level(Hierarchy &h, int level, Csr &A, bool pattern) {
   const int d = h.d, k = d + 1;
   const LevelMesh &lm = h.meshes.at(level);
   const int64_t ns = (int64_t)lm.simp_box.size();
+  // the grid is the kept simplices (all of sigma^(l) unless a general domain drops some)
+  auto in_grid = [&](int64_t s) { return lm.kept.empty() || lm.kept[s]; };
   if (pattern)
-    pattern_from_elements(lm.n(), ns, k, [&](int64_t s, int i) { return lm.dof_of_vert[lm.simp[s * k + i]]; }, A);
+    pattern_from_elements(lm.n(), ns, k, [&](int64_t s, int i) {
+      return in_grid(s) ? lm.dof_of_vert[lm.simp[s * k + i]] : (int64_t)-1;
+    }, A);
   else
     std::fill(A.v.begin(), A.v.end(), 0.0);
   const double fact = d == 2 ? 2.0 : 6.0;
   const double unit = std::ldexp(h.L, -h.J);
   for (int64_t s = 0; s < ns; ++s) {
+    if (!in_grid(s)) continue;
     int64_t a[4][3], half;
     const int64_t det = aux_cofactors(h, lm, s, a, &half);
     const double denom = fact * (double)std::llabs(det);

@@ -109,6 +109,9 @@ void build_colourings(Hierarchy &h);
 void build_local_sets(Hierarchy &h);
 void build_domain(Hierarchy &h);
 std::vector<uint8_t> domain_keeps(const Hierarchy &h, const LevelMesh &lm);
+// mixed Dirichlet/Neumann grids: kept (meets the domain, not Gamma_D) and touch (meets Gamma_D)
+void domain_mixed(const Hierarchy &h, const LevelMesh &lm, std::vector<uint8_t> &kept,
+                  std::vector<uint8_t> &touch);
 void build_coarse(Hierarchy &h);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
 // position of every unknown of the original grid in Morton order of its vertex (device layout)

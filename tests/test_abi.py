@@ -47,7 +47,7 @@ def test_rejects_invalid_input():
         A.Solver(coords, elems, k, device=-1, smoothing=2)
     assert e.value.code == A.EINVAL
     with pytest.raises(A.AsmgError) as e:
-        A.Solver(coords, elems, k, device=-1, domain=2)
+        A.Solver(coords, elems, k, device=-1, domain=3)
     assert e.value.code == A.EINVAL
     for bad_nested in (-1, 17):
         with pytest.raises(A.AsmgError) as e:
@@ -64,6 +64,9 @@ def test_rejects_invalid_input():
     c3, e3, _ = W.kuhn_cube_mesh(3, 0.0)
     with pytest.raises(A.AsmgError) as e:   # general domains are 2-D
         A.Solver(c3, e3, np.ones(len(e3)), device=-1, domain=1)
+    assert e.value.code == A.EINVAL
+    with pytest.raises(A.AsmgError) as e:   # so are the mixed grids
+        A.Solver(c3, e3, np.ones(len(e3)), device=-1, domain=2)
     assert e.value.code == A.EINVAL
 
 

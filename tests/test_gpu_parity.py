@@ -38,8 +38,19 @@ def _general(gen):
     return c, 0, 2, 0, 1
 
 
+def _mixed(gen, side):
+    # mixed problem: Dirichlet on the boundary vertices `side` selects, Neumann elsewhere
+    from oracle.domain import boundary_vertices
+    coords, elems, _ = gen()
+    c = dict(coords=coords, elems=elems, kappa=np.exp(np.random.default_rng(2).normal(0, 0.5, len(elems))))
+    c["f_vertex"] = W.rhs_per_vertex(len(coords), 5, 1)
+    c["dirichlet"] = boundary_vertices(elems, len(coords)) & side(coords)
+    return c, 0, 2, 0, 2
+
+
 # name -> (workload, n_min (0 = default), colouring: 0 natural order, 2 smallest-last,
-#          smoothing: 0 whole auxiliary levels, 1 local on N~_l[, domain: 0 root box, 1 mesh domain])
+#          smoothing: 0 whole auxiliary levels, 1 local on N~_l[, domain: 0 root box, 1 mesh domain,
+#          2 mixed Dirichlet/Neumann grids (workload carries the Dirichlet mask)])
 CASES = {
     "square64": lambda: (W.make_config(0), 0, 0, 0),
     "graded20k": lambda: (W.make_config(1, scale=0.01), 0, 0, 0),
@@ -51,6 +62,9 @@ CASES = {
     "graded_cube_local": lambda: _graded_cube()[:2] + (2, 1),
     "lshape_domain": lambda: _general(lambda: W.lshape_mesh(96, 0.3)),
     "annulus_domain": lambda: _general(lambda: W.annulus_mesh(400)),
+    "annulus_mixed": lambda: _mixed(lambda: W.annulus_mesh(300),
+                                    lambda X: np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35),
+    "lshape_mixed": lambda: _mixed(lambda: W.lshape_mesh(96, 0.3), lambda X: (X[:, 0] == 0.0) | (X[:, 1] == 0.0)),
 }
 ORACLE_COLOURING = {0: "natural", 2: "smallest_last"}
 ORACLE_SMOOTHING = {0: "full", 1: "local"}
@@ -79,11 +93,12 @@ def case(request):
     _say(f"[gpu parity] case {request.param}")
     c, n_min, col, sm, *rest = CASES[request.param]()
     dom = rest[0] if rest else 0
-    H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=ORACLE_COLOURING[col],
-                          domain=["box", "mesh"][dom]), ORACLE_SMOOTHING[sm])
-    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, colouring=col, smoothing=sm, domain=dom)
-    S64.kwargs = dict(n_min=n_min, colouring=col, smoothing=sm, domain=dom)
-    S32 = A.Solver(c["coords"], c["elems"], c["kappa"], n_min=n_min, precision=A.PREC_MIXED, colouring=col,
+    dm = c.get("dirichlet")
+    H = _Oracle(Hierarchy(c["coords"], c["elems"], c["kappa"], dirichlet=dm, n_min=n_min,
+                          colouring=ORACLE_COLOURING[col], domain=["box", "mesh", "mixed"][dom]), ORACLE_SMOOTHING[sm])
+    S64 = A.Solver(c["coords"], c["elems"], c["kappa"], dm, n_min=n_min, colouring=col, smoothing=sm, domain=dom)
+    S64.kwargs = dict(n_min=n_min, colouring=col, smoothing=sm, domain=dom, dirichlet=dm)
+    S32 = A.Solver(c["coords"], c["elems"], c["kappa"], dm, n_min=n_min, precision=A.PREC_MIXED, colouring=col,
                    smoothing=sm, domain=dom)
     f = c["f_vertex"][H.dofs]
     return request.param, c, H, S64, S32, f

@@ -24,6 +24,15 @@ def _general(gen):
     return dict(coords=coords, elems=elems, kappa=k), 0, 1
 
 
+def _mixed(gen, side):
+    # mixed Dirichlet/Neumann problem: Dirichlet on the boundary vertices that `side` selects
+    from oracle.domain import boundary_vertices
+    coords, elems, _ = gen()
+    k = np.exp(np.random.default_rng(2).normal(0, 0.5, len(elems)))
+    mask = boundary_vertices(elems, len(coords)) & side(coords)
+    return dict(coords=coords, elems=elems, kappa=k, dirichlet=mask), 0, 2
+
+
 CASES = {
     "square64": lambda: (W.make_config(0), 0, 0),
     "graded": lambda: (W.make_config(1, scale=0.004), 0, 0),
@@ -32,14 +41,20 @@ CASES = {
     "square64_meshdomain": lambda: (W.make_config(0), 0, 1),
     "lshape": lambda: _general(lambda: W.lshape_mesh(24, 0.3)),
     "annulus": lambda: _general(lambda: W.annulus_mesh(64)),
+    "square32_mixed": lambda: _mixed(lambda: W.square_mesh(32, 0.0), lambda X: X[:, 0] == 0.0),
+    "lshape_mixed": lambda: _mixed(lambda: W.lshape_mesh(24, 0.3), lambda X: (X[:, 0] == 0.0) | (X[:, 1] == 0.0)),
+    "annulus_mixed": lambda: _mixed(lambda: W.annulus_mesh(64),
+                                    lambda X: np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
     c, n_min, dom = CASES[request.param]()
-    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min, domain=dom)
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, domain=["box", "mesh"][dom])
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min, domain=dom,
+                 dirichlet=c.get("dirichlet"))
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, domain=["box", "mesh", "mixed"][dom],
+                  dirichlet=c.get("dirichlet"))
     return c, S, H
 
 
