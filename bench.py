@@ -215,6 +215,28 @@ def annulus(steps: int, colouring: int = 2):
         dt = (time.perf_counter() - t) / steps
         res[name] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr}
         log(f"annulus {name}: {dt * 1e3:.2f} ms/solve, {it} iterations ({S.n / dt:.3e} DOF-solves/s)")
+    del S
+    # mixed problem on the same mesh: Dirichlet on the outer circle, Neumann on the hole; the
+    # Dirichlet grids on the mesh domain against the mixed Dirichlet/Neumann grids (FP64)
+    outer = dirichlet & (np.hypot(coords[:, 0] - 0.5, coords[:, 1] - 0.5) > 0.35)
+    mres = {"problem": "Dirichlet on the outer circle, Neumann on the hole"}
+    for key, dom in (("dirichlet_grids", 1), ("mixed_grids", 2)):
+        t0 = time.perf_counter()
+        S = A.Solver(coords, elems, kappa, outer, colouring=colouring, domain=dom)
+        t_setup = time.perf_counter() - t0
+        f = torch.from_numpy(np.ascontiguousarray(f_vertex[S.dof_vertex()])).cuda()
+        u, it, tr = S.solve_device(f, 1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            u, it, tr = S.solve_device(f, 1e-8, out=u)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        mres[key] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr,
+                     "unknowns": S.n, "setup_s": t_setup}
+        log(f"annulus, Neumann hole, {key.replace('_', ' ')}: {dt * 1e3:.2f} ms/solve, {it} iterations")
+        del S
+    res["neumann_hole"] = mres
     return res
 
 
