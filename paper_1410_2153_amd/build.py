@@ -20,7 +20,9 @@ LIB = os.path.join(OUT_DIR, "libasmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+          "-I" + os.path.join(ROCM, "include")]
 # packed FP32 instructions are disabled for device code (hipcc makes them from plain float code)
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -44,7 +46,7 @@ def build(verbose: bool = True) -> str:
         _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     return LIB
 

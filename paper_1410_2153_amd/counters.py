@@ -6,6 +6,7 @@ Usage:
         <write counter_collection.csv> [out.json]
     python -m paper_1410_2153_amd.counters stats <kernel_stats.csv> [top]
     python -m paper_1410_2153_amd.counters phases <kernel_trace.csv> [kernel]
+    python -m paper_1410_2153_amd.counters markers <marker_api_trace.csv>
 
 traffic: HBM bytes per launch from the two `rocprofv3 --pmc` runs of bench.py named in the
 output record. FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch. Each is scaled by the
@@ -17,6 +18,9 @@ The record is keyed by the SHA-256 of the kernel sources with comments and white
 (`source_key`), so bench.py reports it only for the kernel code it was measured on.
 
 stats: markdown table of a `--stats` kernel summary.
+
+markers: the library's named ranges (roctx, `--marker-trace`) in the order they opened, with
+their durations: setup phases, device layout, autotuning, solves.
 
 phases: splits a `--kernel-trace` timeline at idle gaps over 200 us (host work between the
 bench's phases: autotuning, timed solves, per-launch timing, B_co loops) and gives the kernel's
@@ -186,6 +190,14 @@ def phases_table(trace_csv, kernel=KERNEL):
     return "\n".join(out)
 
 
+def markers_table(marker_csv):
+    rows = sorted(csv.DictReader(open(marker_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    out = ["| range | ms |", "|---|---:|"]
+    for r in rows:
+        out.append(f"| `{r['Function']}` | {(int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1e6:.2f} |")
+    return "\n".join(out)
+
+
 def main(argv):
     if len(argv) >= 3 and argv[0] == "traffic":
         out = json.dumps(record(argv[1], argv[2]), indent=1)
@@ -196,6 +208,8 @@ def main(argv):
         print(stats_table(argv[1], int(argv[2]) if len(argv) > 2 else 25))
     elif len(argv) >= 2 and argv[0] == "phases":
         print(phases_table(argv[1], argv[2] if len(argv) > 2 else KERNEL))
+    elif len(argv) >= 2 and argv[0] == "markers":
+        print(markers_table(argv[1]))
     else:
         raise SystemExit(__doc__)
 

@@ -14,6 +14,7 @@
 #include "../../include/asmg.h"
 #include "batch.hpp"
 #include "device.hpp"
+#include "trace.hpp"
 #include "tree.hpp"
 #include "setup.hpp"
 
@@ -156,27 +157,49 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
       if (tm) std::fprintf(stderr, "[asmg setup] %-12s %8.3f s\n", what, sec);
       t0 = t1;
     };
-    if (o.setup_device == 1)
-      build_fine_device(h, o.device);
-    else
-      build_fine(h);
+    TraceRange all("asmg::setup");
+    {
+      TraceRange r("asmg::setup::fine");
+      if (o.setup_device == 1)
+        build_fine_device(h, o.device);
+      else
+        build_fine(h);
+    }
     lap("fine");
-    if (o.setup_device == 1)
-      build_tree_device(h, o.device);
-    else
-      build_tree(h);
-    if (o.domain >= 1) build_domain(h);
+    {
+      TraceRange r("asmg::setup::tree");
+      if (o.setup_device == 1)
+        build_tree_device(h, o.device);
+      else
+        build_tree(h);
+      if (o.domain >= 1) build_domain(h);
+    }
     lap("tree");
-    build_levels(h);
+    {
+      TraceRange r("asmg::setup::levels");
+      build_levels(h);
+    }
     lap("levels");
-    build_transfer(h);
+    {
+      TraceRange r("asmg::setup::transfer");
+      build_transfer(h);
+    }
     lap("transfer");
-    build_colourings(h);
-    build_local_sets(h);
+    {
+      TraceRange r("asmg::setup::colourings");
+      build_colourings(h);
+      build_local_sets(h);
+    }
     lap("colourings");
-    build_coarse(h);
+    {
+      TraceRange r("asmg::setup::coarse");
+      build_coarse(h);
+    }
     lap("coarse");
-    if (o.device >= 0) H->dev = device_create(h, o.device);
+    if (o.device >= 0) {
+      TraceRange r("asmg::setup::device_layout");
+      H->dev = device_create(h, o.device);
+    }
     lap("upload");
     *out = HP.release();
     return ASMG_OK;

@@ -24,6 +24,7 @@
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "trace.hpp"
 
 namespace asmg {
 
@@ -1525,6 +1526,7 @@ template <int NR, class T>
 static void b_tune(BatchDevice *dv, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
   if (dv->tuned[pi][NR] || !dv->autotune) return;
+  TraceRange tr_tune("asmg::batch_autotune");
   const int K = kNumShapes;
   std::vector<std::vector<float>> t;
   dv->tuning = true;
@@ -1683,6 +1685,7 @@ static void b_prepare_r(BatchDevice *dv, int nr, hipStream_t s) {
 template <int NR>
 static int b_solve_nr(BatchDevice *dv, const double *d_F, double tol, double *d_U, int *iters, double *true_rel,
                       hipStream_t cs) {
+  TraceRange tr_solve("asmg::batch_solve");
   hipStream_t s = dv->stream;
   const int n = dv->fine.nrows;
   HIPCHECK(hipEventRecord(dv->ev_in, cs));

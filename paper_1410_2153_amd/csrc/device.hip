@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "trace.hpp"
 #include "device.hpp"
 
 namespace asmg {
@@ -1627,6 +1628,7 @@ struct NV<float> {
 // zero run on its own); finally u = Pi e_J in FP64 (internal order). Whole-level smoothing.
 template <class T>
 static void nested_start(Device *dv, hipStream_t s) {
+  TraceRange tr_nested("asmg::nested_start");
   DLevel &F = dv->fine;
   const int J = dv->J, lc = dv->lc;
   dv->site = -1;  // these launches are not B_co's tuned sites
@@ -1699,6 +1701,7 @@ template <class T>
 static void tune(Device *dv, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
   if (dv->tuned[pi] || !dv->autotune) return;
+  TraceRange tr_tune("asmg::autotune");
   const int K = kNumShapes;
   std::vector<std::vector<float>> t;
   dv->tuning = true;
@@ -1770,6 +1773,7 @@ static void launch_iterations(Device *dv, int k, hipStream_t s) {
 
 template <class T>
 static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t s) {
+  TraceRange tr_pcg(sizeof(T) == 4 ? "asmg::pcg(mixed)" : "asmg::pcg(fp64)");
   const int n = dv->fine.n;
   const int pi = sizeof(T) == 4 ? 1 : 0;
   DLevel &F = dv->fine;
