@@ -31,12 +31,22 @@ def _lshape():
     return c, 1
 
 
-# name -> (workload, domain: 0 root box, 1 mesh domain)
+def _annulus_mixed():
+    from oracle.domain import boundary_vertices
+    coords, elems, _ = W.annulus_mesh(200)
+    c = dict(coords=coords, elems=elems, kappa=np.exp(np.random.default_rng(3).normal(0, 0.5, len(elems))))
+    c["f_vertex"] = W.rhs_per_vertex(len(coords), 6, 1)
+    c["dirichlet"] = boundary_vertices(elems, len(coords)) & (np.hypot(coords[:, 0] - 0.5, coords[:, 1] - 0.5) > 0.35)
+    return c, 2
+
+
+# name -> (workload, domain: 0 root box, 1 mesh domain, 2 mixed Dirichlet/Neumann grids)
 CASES = {
     "square64": lambda: (W.make_config(0), 0),
     "graded20k": lambda: (W.make_config(1, scale=0.01), 0),
     "cube16": lambda: (W.make_config(2, scale=1 / 8), 0),
     "lshape_domain": _lshape,
+    "annulus_mixed": _annulus_mixed,
 }
 
 
@@ -44,7 +54,7 @@ CASES = {
 def case(request):
     _say(f"[gpu nested] case {request.param}")
     c, dom = CASES[request.param]()
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"], domain=["box", "mesh"][dom])
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], dirichlet=c.get("dirichlet"), domain=["box", "mesh", "mixed"][dom])
     f = c["f_vertex"][H.dofs]
     return request.param, c, H, dom, f
 
@@ -56,7 +66,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("cycles", [1, 2])
 def test_nested_fp64(case, cycles):
     name, c, H, dom, f = case
-    S = A.Solver(c["coords"], c["elems"], c["kappa"], domain=dom, nested=cycles)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], c.get("dirichlet"), domain=dom, nested=cycles)
     uo, ito, info = H.solve(f, 1e-8, nested=cycles)
     u, it, tr = S.solve(f, 1e-8)
     u0, it0, _ = H.solve(f, 1e-8)
@@ -73,7 +83,8 @@ def test_nested_fp64(case, cycles):
 
 def test_nested_mixed(case):
     name, c, H, dom, f = case
-    S = A.Solver(c["coords"], c["elems"], c["kappa"], domain=dom, nested=1, precision=A.PREC_MIXED)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], c.get("dirichlet"), domain=dom, nested=1,
+                 precision=A.PREC_MIXED)
     u, it, tr = S.solve(f, 1e-8)
     uo, _, _ = H.solve(f, 1e-12)
     _say(name, f"nested mixed: iterations {it}, true rel residual {tr:.2e}, rel diff {_rel(u, uo):.2e}")

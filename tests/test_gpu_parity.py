@@ -65,6 +65,8 @@ CASES = {
     "annulus_mixed": lambda: _mixed(lambda: W.annulus_mesh(300),
                                     lambda X: np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35),
     "lshape_mixed": lambda: _mixed(lambda: W.lshape_mesh(96, 0.3), lambda X: (X[:, 0] == 0.0) | (X[:, 1] == 0.0)),
+    "annulus_mixed_local": lambda: _mixed(lambda: W.annulus_mesh(200),
+                                          lambda X: np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35)[:3] + (1, 2),
 }
 ORACLE_COLOURING = {0: "natural", 2: "smallest_last"}
 ORACLE_SMOOTHING = {0: "full", 1: "local"}
