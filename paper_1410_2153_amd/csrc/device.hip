@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -30,7 +31,9 @@
 #include <cstring>
 #include <numeric>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -853,14 +856,62 @@ static HCsr transpose(const HCsr &A) {
   return T;
 }
 
+// host image of a sliced ELL: built on host threads, uploaded afterwards
+struct SellHost {
+  std::vector<int> srow, soff, scol, cs;
+  std::vector<double> sv;
+  std::vector<float> sv32;
+  int widest = 0;
+};
+
+static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> *slot_map = nullptr,
+                          int wround = 1, const std::vector<int> *order = nullptr);
+static void sell_upload(Device *dv, DSell &S, const SellHost &X, bool first_time);
+
 static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges &groups, bool first_time,
                               std::vector<int> *slot_map = nullptr, int wround = 1,
-                              const std::vector<int> *order = nullptr);
+                              const std::vector<int> *order = nullptr) {
+  sell_upload(dv, S, sell_host(H, groups, slot_map, wround, order), first_time);
+}
 
-static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
+// run f(i) for i in [0, n) on up to `threads` host threads (0 = all cores); the first error is
+// rethrown. Used for host-only layout work (no HIP calls inside f).
+template <class F>
+static void host_parallel(int threads, int n, F f) {
+  int nt = threads > 0 ? threads : (int)std::thread::hardware_concurrency();
+  nt = std::max(1, std::min(nt, n));
+  std::atomic<int> next{0};
+  std::mutex mu;
+  std::exception_ptr err;
+  auto work = [&]() {
+    try {
+      for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> g(mu);
+      if (!err) err = std::current_exception();
+      next = n;
+    }
+  };
+  if (nt == 1) {
+    work();
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(work);
+    for (auto &t : th) t.join();
+  }
+  if (err) std::rethrow_exception(err);
+}
+
+// sizes only: the kernels read the auxiliary levels and the transfers through their sliced ELL
+// copies; only the original-grid operator keeps a device CSR (PCG products)
+static void csr_shape(const HCsr &H, DCsr &D) {
   D.nrows = H.nrows;
   D.ncols = H.ncols;
   D.nnz = (int64_t)H.ci.size();
+}
+
+static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
+  csr_shape(H, D);
   D.rp = dupload(dv, H.rp);
   D.ci = dupload(dv, H.ci);
   D.v64 = dupload(dv, H.v);
@@ -870,7 +921,7 @@ static void upload_csr(Device *dv, const HCsr &H, DCsr &D) {
 }
 
 static void upload_values(DCsr &D, const HCsr &H) {
-  if (H.v.empty()) return;
+  if (H.v.empty() || !D.v64) return;
   HIPCHECK(hipMemcpy(D.v64, H.v.data(), H.v.size() * sizeof(double), hipMemcpyHostToDevice));
   std::vector<float> f(H.v.begin(), H.v.end());
   HIPCHECK(hipMemcpy(D.v32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -880,11 +931,26 @@ static void upload_values(DCsr &D, const HCsr &H) {
 // follow `order` (rows in a spatially coherent order: the level's Morton numbering, or Morton
 // order of the vertices on the original grid): neighbouring rows then gather neighbouring
 // entries of x, whereas the colour-major numbering would interleave four distant ranges.
-static void upload_transfer(Device *dv, const HCsr &H, DCsr &D, const std::vector<int> *order) {
-  upload_csr(dv, H, D);
+struct TransferStage {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  SellHost sell;
+};
+
+static void stage_transfer(const HCsr &H, const std::vector<int> *order, TransferStage &X) {
+  X.nrows = H.nrows;
+  X.ncols = H.ncols;
+  X.nnz = (int64_t)H.ci.size();
+  X.sell = sell_host(H, Ranges{{0, H.nrows}}, nullptr, 4, order);
+}
+
+static void commit_transfer(Device *dv, const TransferStage &X, DCsr &D) {
+  D.nrows = X.nrows;
+  D.ncols = X.ncols;
+  D.nnz = X.nnz;
   dv->sells.emplace_back(new DSell());
   D.sell = dv->sells.back().get();
-  build_sell_ranges(dv, *D.sell, H, Ranges{{0, H.nrows}}, true, nullptr, 4, order);
+  sell_upload(dv, *D.sell, X.sell, true);
 }
 
 // colour-major numbering: colour classes in order, inside a class ascending (part, rank), with
@@ -959,15 +1025,17 @@ static void alloc_vectors(Device *dv, DLevel &L) {
 // rounded up to a multiple of `wround` (extra zero entries), so that matrices with long, uneven
 // rows use a few of the kernel's straight-line widths rather than many. With `order` (one range
 // only), position i of the range is row order[i].
-static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges &groups, bool first_time,
-                              std::vector<int> *slot_map, int wround, const std::vector<int> *order) {
+static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> *slot_map, int wround,
+                          const std::vector<int> *order) {
   if (slot_map) slot_map->clear();
   const int C = (int)groups.size();
-  std::vector<int> srow, soff{0}, scol;
-  std::vector<double> sv;
-  std::vector<int> cs{0};
+  SellHost X;
+  std::vector<int> &srow = X.srow, &soff = X.soff, &scol = X.scol, &cs = X.cs;
+  std::vector<double> &sv = X.sv;
+  soff.push_back(0);
+  cs.push_back(0);
   std::vector<int> idx;
-  int widest = 0;
+  int &widest = X.widest;
   for (int c = 0; c < C; ++c) {
     for (int w0 = groups[c].first; w0 < groups[c].second; w0 += 256) {
       const int w1 = std::min(w0 + 256, groups[c].second);
@@ -1014,20 +1082,24 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges 
     }
     cs.push_back((int)srow.size() / 64);
   }
-  std::vector<float> sv32(sv.begin(), sv.end());
+  X.sv32.assign(sv.begin(), sv.end());
+  return X;
+}
+
+static void sell_upload(Device *dv, DSell &S, const SellHost &X, bool first_time) {
   if (first_time) {
-    S.nslices = (int)srow.size() / 64;
-    S.wmax = widest;
-    S.cslice = cs;
-    S.entries = (int64_t)sv.size();
-    S.srow = dupload(dv, srow);
-    S.soff = dupload(dv, soff);
-    S.scol = dupload(dv, scol);
-    S.sv64 = dupload(dv, sv);
-    S.sv32 = dupload(dv, sv32);
-  } else if (!sv.empty()) {
-    HIPCHECK(hipMemcpy(S.sv64, sv.data(), sv.size() * 8, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(S.sv32, sv32.data(), sv32.size() * 4, hipMemcpyHostToDevice));
+    S.nslices = (int)X.srow.size() / 64;
+    S.wmax = X.widest;
+    S.cslice = X.cs;
+    S.entries = (int64_t)X.sv.size();
+    S.srow = dupload(dv, X.srow);
+    S.soff = dupload(dv, X.soff);
+    S.scol = dupload(dv, X.scol);
+    S.sv64 = dupload(dv, X.sv);
+    S.sv32 = dupload(dv, X.sv32);
+  } else if (!X.sv.empty()) {
+    HIPCHECK(hipMemcpy(S.sv64, X.sv.data(), X.sv.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(S.sv32, X.sv32.data(), X.sv32.size() * 4, hipMemcpyHostToDevice));
   }
 }
 
@@ -1035,14 +1107,25 @@ static void build_sell(Device *dv, DLevel &L, const HCsr &H, bool first_time, st
   build_sell_ranges(dv, L.sell, H, L.groups, first_time, slot_map);
 }
 
-static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_time, HCsr *keep = nullptr,
-                                std::vector<int> *slot_map = nullptr) {
-  std::vector<double> diag;
-  HCsr H = permute(A, L.perm, &L.iperm, true, &diag);
-  std::vector<double> inv(diag.size());
-  for (size_t i = 0; i < diag.size(); ++i) inv[i] = 1.0 / diag[i];
-  std::vector<float> d32(diag.begin(), diag.end()), i32(diag.size());
-  for (size_t i = 0; i < diag.size(); ++i) i32[i] = 1.0f / (float)diag[i];
+// host image of a level operator in the level's internal numbering: off-diagonal CSR, its sliced
+// ELL, the diagonal and its inverse in both precisions. With first_time it also sets the per-group
+// byte-model counts of L (host-only: safe on a host thread, one level per thread).
+struct LevelStage {
+  HCsr H;
+  SellHost sell;
+  std::vector<double> diag, inv;
+  std::vector<float> d32, i32;
+};
+
+static void stage_level(DLevel &L, const Csr &A, bool first_time, LevelStage &X) {
+  X.H = permute(A, L.perm, &L.iperm, true, &X.diag);
+  const HCsr &H = X.H;
+  const size_t n = X.diag.size();
+  X.inv.resize(n);
+  for (size_t i = 0; i < n; ++i) X.inv[i] = 1.0 / X.diag[i];
+  X.d32.assign(X.diag.begin(), X.diag.end());
+  X.i32.resize(n);
+  for (size_t i = 0; i < n; ++i) X.i32[i] = 1.0f / (float)X.diag[i];
   if (first_time) {
     const int G = (int)L.groups.size();
     L.cnnz.assign(G, 0);
@@ -1057,21 +1140,30 @@ static void upload_level_matrix(Device *dv, DLevel &L, const Csr &A, bool first_
             ++L.ucols[c];
           }
         }
-    upload_csr(dv, H, L.A);
-    build_sell(dv, L, H, true, slot_map);
-    L.dg64 = dupload(dv, diag);
-    L.id64 = dupload(dv, inv);
-    L.dg32 = dupload(dv, d32);
-    L.id32 = dupload(dv, i32);
-  } else {
-    upload_values(L.A, H);
-    build_sell(dv, L, H, false);
-    HIPCHECK(hipMemcpy(L.dg64, diag.data(), diag.size() * 8, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L.id64, inv.data(), inv.size() * 8, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L.dg32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L.id32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice));
   }
-  if (keep) *keep = std::move(H);
+  X.sell = sell_host(H, L.groups);
+}
+
+// upload a staged level; `csr`: also keep a device CSR of the off-diagonal part (original grid)
+static void commit_level(Device *dv, DLevel &L, const LevelStage &X, bool first_time, bool csr) {
+  if (first_time) {
+    if (csr)
+      upload_csr(dv, X.H, L.A);
+    else
+      csr_shape(X.H, L.A);
+    sell_upload(dv, L.sell, X.sell, true);
+    L.dg64 = dupload(dv, X.diag);
+    L.id64 = dupload(dv, X.inv);
+    L.dg32 = dupload(dv, X.d32);
+    L.id32 = dupload(dv, X.i32);
+  } else {
+    upload_values(L.A, X.H);
+    sell_upload(dv, L.sell, X.sell, false);
+    HIPCHECK(hipMemcpy(L.dg64, X.diag.data(), X.diag.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.id64, X.inv.data(), X.inv.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dg32, X.d32.data(), X.d32.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.id32, X.i32.data(), X.i32.size() * 4, hipMemcpyHostToDevice));
+  }
 }
 
 // contribution lists of the original-grid operator (internal numbering): entry value =
@@ -1191,11 +1283,6 @@ Device *device_create(Hierarchy &h, int ordinal) {
     // neighbours in the numbering are neighbours in space, whatever the mesh's own numbering)
     const std::vector<int> mrank = morton_rank(h);
     colour_order(h.colour_fine, dv->fine, &mrank);
-    lap("fine order");
-    upload_level_matrix(dv, dv->fine, h.A, true);
-    lap("fine matrix");
-    alloc_vectors(dv, dv->fine);
-    dv->perm_d = dupload(dv, dv->fine.perm);
     // auxiliary levels
     dv->aux.resize(h.J + 1);
     for (int l = h.J; l > h.lc; --l) {
@@ -1204,32 +1291,60 @@ Device *device_create(Hierarchy &h, int ordinal) {
         local_order(h.colour_aux.at(l), h.local_set.at(l), h.Al.at(l), L);
       else
         colour_order(h.colour_aux.at(l), L);
-      upload_level_matrix(dv, L, h.Al.at(l), true);
-      alloc_vectors(dv, L);
     }
-    lap("aux levels");
-    // prolongations in internal numbering; slices visit the rows in each level's own (Morton)
-    // numbering: position k holds internal row iperm[k] (the bottom level keeps its numbering)
+    lap("orders");
+    // Host images of every matrix, built on host threads (each task writes only its own stage
+    // and, for a level, that level's byte-model counts), then uploaded in a fixed order.
+    // Prolongations are in internal numbering; their slices visit the rows in each level's own
+    // (Morton) numbering: position k holds internal row iperm[k] (the bottom level keeps its
+    // numbering). Pi: rows fine internal, columns level-J internal (or unknown order if J is the
+    // bottom); its slices visit the original-grid unknowns in Morton order of their vertices.
+    const int naux = h.J - h.lc;
+    LevelStage fine_st;
+    std::vector<LevelStage> aux_st(naux);
+    std::vector<TransferStage> p_st(naux), pt_st(naux);
+    TransferStage pi_st, pit_st;
+    const std::vector<int> *pi_cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
+    std::vector<int> forder(mrank.size());
+    for (size_t i = 0; i < mrank.size(); ++i) forder[mrank[i]] = dv->fine.iperm[i];
+    // tasks: Pi and Pi^T first (the largest), then the fine operator, the levels, the prolongations
+    host_parallel(h.threads, 3 + 2 * naux, [&](int t) {
+      if (t == 0) {
+        stage_transfer(permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr), &forder, pi_st);
+      } else if (t == 1) {
+        stage_transfer(transpose(permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr)), pi_cmap, pit_st);
+      } else if (t == 2) {
+        stage_level(dv->fine, h.A, true, fine_st);
+      } else if (t < 3 + naux) {
+        const int l = h.J - (t - 3);
+        stage_level(dv->aux[l], h.Al.at(l), true, aux_st[t - 3]);
+      } else {
+        const int i = t - 3 - naux, l = h.J - i;
+        DLevel &L = dv->aux[l];
+        const std::vector<int> *cmap = l - 1 > h.lc ? &dv->aux[l - 1].iperm : nullptr;
+        HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
+        stage_transfer(P, &L.iperm, p_st[i]);
+        stage_transfer(transpose(P), cmap, pt_st[i]);
+      }
+    });
+    lap("host layout");
+    commit_level(dv, dv->fine, fine_st, true, true);
+    fine_st = LevelStage();
+    alloc_vectors(dv, dv->fine);
+    dv->perm_d = dupload(dv, dv->fine.perm);
     for (int l = h.J; l > h.lc; --l) {
-      DLevel &L = dv->aux[l];
-      const std::vector<int> *cmap = nullptr;
-      if (l - 1 > h.lc) cmap = &dv->aux[l - 1].iperm;
-      HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
-      upload_transfer(dv, P, L.P, &L.iperm);
-      upload_transfer(dv, transpose(P), L.PT, cmap);
+      LevelStage &X = aux_st[h.J - l];
+      commit_level(dv, dv->aux[l], X, true, false);
+      X = LevelStage();
+      alloc_vectors(dv, dv->aux[l]);
     }
-    lap("prolongations");
-    // Pi: rows fine internal, columns level-J internal (or unknown order if J is the bottom);
-    // Pi's slices visit the original-grid unknowns in Morton order of their vertices
-    {
-      const std::vector<int> *cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
-      HCsr Pi = permute(h.Pi, dv->fine.perm, cmap, false, nullptr);
-      std::vector<int> forder(mrank.size());
-      for (size_t i = 0; i < mrank.size(); ++i) forder[mrank[i]] = dv->fine.iperm[i];
-      upload_transfer(dv, Pi, dv->Pi, &forder);
-      upload_transfer(dv, transpose(Pi), dv->PiT, cmap);
+    for (int l = h.J; l > h.lc; --l) {
+      commit_transfer(dv, p_st[h.J - l], dv->aux[l].P);
+      commit_transfer(dv, pt_st[h.J - l], dv->aux[l].PT);
     }
-    lap("Pi");
+    commit_transfer(dv, pi_st, dv->Pi);
+    commit_transfer(dv, pit_st, dv->PiT);
+    lap("upload");
     upload_coarse(dv, h, true);
     dv->nested = h.opt.nested;
     if (dv->nested > 0) {
@@ -1280,8 +1395,16 @@ Device *device_create(Hierarchy &h, int ordinal) {
 
 void device_update_values(Device *dv, Hierarchy &h) {
   HIPCHECK(hipSetDevice(dv->ordinal));
-  upload_level_matrix(dv, dv->fine, h.A, false);
-  for (int l = h.J; l > h.lc; --l) upload_level_matrix(dv, dv->aux[l], h.Al.at(l), false);
+  const int naux = h.J - h.lc;
+  std::vector<LevelStage> st(1 + naux);
+  host_parallel(h.threads, 1 + naux, [&](int t) {
+    if (t == 0)
+      stage_level(dv->fine, h.A, false, st[0]);
+    else
+      stage_level(dv->aux[h.J - (t - 1)], h.Al.at(h.J - (t - 1)), false, st[t]);
+  });
+  commit_level(dv, dv->fine, st[0], false, true);
+  for (int l = h.J; l > h.lc; --l) commit_level(dv, dv->aux[l], st[h.J - l + 1], false, false);
   upload_coarse(dv, h, false);
   HIPCHECK(hipMemcpy(dv->kappa, h.kappa.data(), h.kappa.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipDeviceSynchronize());
