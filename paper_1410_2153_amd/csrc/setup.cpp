@@ -117,6 +117,34 @@ static inline unsigned __int128 morton_point(const int64_t *X, int d, int bits) 
   return m;
 }
 
+// bit b of x moved to bit d*b (x below 2^32 for d = 2, below 2^21 for d = 3): mask-and-shift
+// bit interleaving
+static inline uint64_t spread_bits(uint64_t x, int d) {
+  if (d == 2) {
+    x &= 0xffffffffULL;
+    x = (x | (x << 16)) & 0x0000ffff0000ffffULL;
+    x = (x | (x << 8)) & 0x00ff00ff00ff00ffULL;
+    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+    x = (x | (x << 2)) & 0x3333333333333333ULL;
+    x = (x | (x << 1)) & 0x5555555555555555ULL;
+  } else {
+    x &= 0x1fffffULL;
+    x = (x | (x << 32)) & 0x001f00000000ffffULL;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffULL;
+    x = (x | (x << 8)) & 0x100f00f00f00f00fULL;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
+    x = (x | (x << 2)) & 0x1249249249249249ULL;
+  }
+  return x;
+}
+
+// morton_point for keys of at most 64 bits (same bit layout)
+static inline uint64_t morton_point64(const int64_t *X, int d) {
+  uint64_t m = 0;
+  for (int k = 0; k < d; ++k) m |= spread_bits((uint64_t)X[k], d) << (d - 1 - k);
+  return m;
+}
+
 // ---------------------------------------------------------------------------
 // fine problem (Section 2)
 // ---------------------------------------------------------------------------
@@ -405,17 +433,22 @@ void build_tree(Hierarchy &h) {
         if (!h.R.count(c)) h.leaves.push_back(c);
       }
   }
-  auto tuple_less = [d](BoxCode x, BoxCode y) {
-    int lx = box_level(x, d), ly = box_level(y, d);
-    if (lx != ly) return lx < ly;
-    int64_t ix[3], iy[3];
-    box_index(x, d, ix);
-    box_index(y, d, iy);
-    for (int q = 0; q < d; ++q)
-      if (ix[q] != iy[q]) return ix[q] < iy[q];
-    return false;
-  };
-  std::sort(h.leaves.begin(), h.leaves.end(), tuple_less);
+  // leaves in (level, index tuple) order: one 128-bit key per leaf (level above bit 64, then the
+  // index components, each below 2^(64/d))
+  {
+    std::vector<std::pair<unsigned __int128, BoxCode>> kl(h.leaves.size());
+    for (size_t i = 0; i < h.leaves.size(); ++i) {
+      const BoxCode b = h.leaves[i];
+      int64_t ix[3];
+      box_index(b, d, ix);
+      const int w = 64 / d;
+      unsigned __int128 k = (unsigned __int128)box_level(b, d) << 64;
+      for (int q = 0; q < d; ++q) k |= (unsigned __int128)ix[q] << (w * (d - 1 - q));
+      kl[i] = {k, b};
+    }
+    std::sort(kl.begin(), kl.end());
+    for (size_t i = 0; i < kl.size(); ++i) h.leaves[i] = kl[i].second;
+  }
   h.J = 1;
   for (BoxCode b : h.leaves) h.J = std::max(h.J, box_level(b, d));
   if (h.J > 31 || (d == 3 && h.J > 21)) fail(ASMG_EINVAL, "tree too deep");
@@ -472,17 +505,28 @@ static void compute_kuhn_means(Hierarchy &h) {
       }
     }
   h.kuhn_w.clear();
-  for (auto &kv : h.leaf_kappa) h.kuhn_w[kv.first] = std::vector<double>(nperm, kv.second);
-  std::vector<BoxCode> Rs(h.R.begin(), h.R.end());
-  std::sort(Rs.begin(), Rs.end(), [d](BoxCode x, BoxCode y) { return box_level(x, d) > box_level(y, d); });
-  for (BoxCode b : Rs) {
-    std::vector<double> w(nperm);
+  h.kuhn_w.reserve(h.leaf_kappa.size() + h.R.size());
+  for (auto &kv : h.leaf_kappa) {
+    KuhnW w{};
+    for (int t = 0; t < nperm; ++t) w[t] = kv.second;
+    h.kuhn_w.emplace(kv.first, w);
+  }
+  // finer boxes first (each box's means come from its children's)
+  std::vector<std::pair<int, BoxCode>> Rs;
+  Rs.reserve(h.R.size());
+  for (BoxCode b : h.R) Rs.push_back({box_level(b, d), b});
+  std::sort(Rs.begin(), Rs.end(), [](const std::pair<int, BoxCode> &x, const std::pair<int, BoxCode> &y) {
+    return x.first > y.first;
+  });
+  for (const auto &lb : Rs) {
+    const BoxCode b = lb.second;
+    KuhnW w{};
     for (int t = 0; t < nperm; ++t) {
       double s = 0;
-      for (auto &cs : inside[t]) s += h.kuhn_w[(b << d) | (BoxCode)cs.first][cs.second];
+      for (auto &cs : inside[t]) s += h.kuhn_w.at((b << d) | (BoxCode)cs.first)[cs.second];
       w[t] = s / (double)(1 << d);
     }
-    h.kuhn_w[b] = std::move(w);
+    h.kuhn_w.emplace(b, w);
   }
 }
 
@@ -684,18 +728,57 @@ static LevelMesh make_level_mesh(const Hierarchy &h, int level) {
       fan3(h, b, cor, S, (int32_t)i, sb);
   }
   const int64_t ns = (int64_t)sb.box.size(), nvtx = ns * (d + 1);
-  std::vector<unsigned __int128> vk(nvtx);
-  for (int64_t i = 0; i < nvtx; ++i) vk[i] = morton_point(&sb.pts[i * d], d, J + 1);
-  std::vector<unsigned __int128> uk(vk);
-  std::sort(uk.begin(), uk.end());
-  uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+  // vertex numbering: rank of the vertex's Morton key among the distinct keys
   lm.simp.resize(nvtx);
-  const int64_t nv = (int64_t)uk.size();
-  lm.verts.assign(nv * d, 0);
-  for (int64_t i = 0; i < nvtx; ++i) {
-    int64_t r = std::lower_bound(uk.begin(), uk.end(), vk[i]) - uk.begin();
-    lm.simp[i] = r;
-    for (int q = 0; q < d; ++q) lm.verts[r * d + q] = sb.pts[i * d + q];
+  int64_t nv = 0;
+  if ((J + 1) * d <= 64) {
+    // keys of at most 64 bits: LSD radix sort of (key, position), 11 bits per pass
+    std::vector<uint64_t> key(nvtx), k2(nvtx);
+    std::vector<int64_t> pos(nvtx), p2(nvtx);
+    for (int64_t i = 0; i < nvtx; ++i) {
+      key[i] = morton_point64(&sb.pts[i * d], d);
+      pos[i] = i;
+    }
+    std::vector<int64_t> cnt(2048);
+    for (int sh = 0; sh < (J + 1) * d; sh += 11) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int64_t i = 0; i < nvtx; ++i) cnt[(key[i] >> sh) & 2047]++;
+      int64_t run = 0;
+      for (int64_t &c : cnt) {
+        const int64_t t = c;
+        c = run;
+        run += t;
+      }
+      for (int64_t i = 0; i < nvtx; ++i) {
+        const int64_t o = cnt[(key[i] >> sh) & 2047]++;
+        k2[o] = key[i];
+        p2[o] = pos[i];
+      }
+      key.swap(k2);
+      pos.swap(p2);
+    }
+    std::vector<int64_t> first;  // position of one vertex with each key
+    for (int64_t j = 0; j < nvtx; ++j) {
+      if (j == 0 || key[j] != key[j - 1]) first.push_back(pos[j]);
+      lm.simp[pos[j]] = (int64_t)first.size() - 1;
+    }
+    nv = (int64_t)first.size();
+    lm.verts.assign(nv * d, 0);
+    for (int64_t r = 0; r < nv; ++r)
+      for (int q = 0; q < d; ++q) lm.verts[r * d + q] = sb.pts[first[r] * d + q];
+  } else {
+    std::vector<unsigned __int128> vk(nvtx);
+    for (int64_t i = 0; i < nvtx; ++i) vk[i] = morton_point(&sb.pts[i * d], d, J + 1);
+    std::vector<unsigned __int128> uk(vk);
+    std::sort(uk.begin(), uk.end());
+    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+    nv = (int64_t)uk.size();
+    lm.verts.assign(nv * d, 0);
+    for (int64_t i = 0; i < nvtx; ++i) {
+      int64_t r = std::lower_bound(uk.begin(), uk.end(), vk[i]) - uk.begin();
+      lm.simp[i] = r;
+      for (int q = 0; q < d; ++q) lm.verts[r * d + q] = sb.pts[i * d + q];
+    }
   }
   lm.simp_box = std::move(sb.box);
   lm.simp_tmpl = std::move(sb.tmpl);
@@ -813,7 +896,7 @@ static void assemble_level(Hierarchy &h, int level, Csr &A, bool pattern) {
     const int64_t det = aux_cofactors(h, lm, s, a, &half);
     const double denom = fact * (double)std::llabs(det);
     BoxCode b = lm.boxes[lm.simp_box[s]];
-    const std::vector<double> &w = h.kuhn_w.at(b);
+    const KuhnW &w = h.kuhn_w.at(b);
     const double kap = lm.fan[lm.simp_box[s]] ? w[0] : w[lm.simp_tmpl[s]];
     for (int i = 0; i < k; ++i) {
       int64_t ui = lm.dof_of_vert[lm.simp[s * k + i]];

@@ -2,6 +2,7 @@
 // the device upload and the C ABI. Everything here is plain C++17.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <memory>
 #include <string>
@@ -30,6 +31,7 @@ struct Csr {
 // Box of the regular box tree, encoded as a locational code:
 // (1 << d*(level-1)) | Morton(index), axis 0 most significant in each bit group.
 using BoxCode = uint64_t;
+using KuhnW = std::array<double, 6>;  // one value per Kuhn simplex of a box (2 in 2-D, 6 in 3-D)
 
 // One auxiliary triangulation sigma^(level) (Section 3.3).
 struct LevelMesh {
@@ -77,7 +79,7 @@ struct Hierarchy {
   std::unordered_set<BoxCode> R0, R;  // refined boxes before / after closure
   std::vector<BoxCode> leaves;        // sorted by (level, index)
   std::unordered_map<BoxCode, double> leaf_kappa;
-  std::unordered_map<BoxCode, std::vector<double>> kuhn_w;  // mean coefficient per Kuhn simplex
+  std::unordered_map<BoxCode, KuhnW> kuhn_w;  // mean coefficient per Kuhn simplex of a box
   int J = 1;
 
   // auxiliary hierarchy (Sections 3.3-3.4, 4.1)
