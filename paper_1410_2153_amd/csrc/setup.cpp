@@ -1451,19 +1451,26 @@ void build_coarse(Hierarchy &h) {
     }
     for (int64_t i = 0; i < j; ++i) Lm[i * n + j] = 0.0;
   }
-  // inverse column by column (independent columns on parallel threads): solve L y = e_c, L^T x = y
+  // inverse column by column (independent columns on parallel threads): solve L y = e_c, L^T x = y.
+  // y_i = 0 for i < c (e_c has no entries there), so the forward solve starts at row c; the
+  // backward solve reads L^T by rows (Ut = L^T, row-major) and x from a contiguous vector.
+  std::vector<double> Ut(n * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < n; ++k) Ut[i * n + k] = Lm[k * n + i];
   parallel_for(h, n, [&](int64_t c) {
-    std::vector<double> y(n);
-    for (int64_t i = 0; i < n; ++i) {
+    std::vector<double> y(n, 0.0), x(n);
+    for (int64_t i = c; i < n; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = 0; k < i; ++k) s -= Lm[i * n + k] * y[k];
+      for (int64_t k = c; k < i; ++k) s -= Lm[i * n + k] * y[k];
       y[i] = s / Lm[i * n + i];
     }
     for (int64_t i = n - 1; i >= 0; --i) {
       double s = y[i];
-      for (int64_t k = i + 1; k < n; ++k) s -= Lm[k * n + i] * h.coarse_inv[k * n + c];
-      h.coarse_inv[i * n + c] = s / Lm[i * n + i];
+      const double *u = &Ut[i * n];
+      for (int64_t k = i + 1; k < n; ++k) s -= u[k] * x[k];
+      x[i] = s / Lm[i * n + i];
     }
+    for (int64_t i = 0; i < n; ++i) h.coarse_inv[i * n + c] = x[i];
   });
 }
 
