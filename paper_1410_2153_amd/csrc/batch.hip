@@ -24,6 +24,7 @@
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "host_parallel.hpp"
 #include "trace.hpp"
 
 namespace asmg {
@@ -861,13 +862,23 @@ static void bupload_csr(BatchDevice *dv, const HMat &H, BCsr &D) {
 // through it (transfer products visit their rows in a spatially coherent order). pad_blocks: every group ends on a whole block of
 // 4 slices (at least one block), so blocks never straddle groups; block0 gets the first block
 // of each group.
-static void bsell_build(BatchDevice *dv, const HMat &H, const std::vector<std::vector<std::pair<int, int>>> &groups,
-                        bool pad_blocks, BSell &S, std::vector<int> *block0 = nullptr,
-                        const std::vector<int> *order = nullptr) {
-  std::vector<int> srow, soff{0}, scol, idx;
+using Groups = std::vector<std::vector<std::pair<int, int>>>;
+
+// host image of a BSell (built on host threads, uploaded afterwards)
+struct BSellHost {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  std::vector<int> srow, soff{0}, scol, cslice{0}, block0{0};
   std::vector<double> sv;
-  S.cslice.assign(1, 0);
-  if (block0) block0->assign(1, 0);
+  std::vector<float> sv32;
+};
+
+static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSellHost &X,
+                       const std::vector<int> *order = nullptr) {
+  std::vector<int> &srow = X.srow, &soff = X.soff, &scol = X.scol;
+  std::vector<int> idx;
+  std::vector<double> &sv = X.sv;
+  std::vector<int> *block0 = &X.block0;
   auto len = [&](int r) { return H.rp[r + 1] - H.rp[r]; };
   auto empty_slice = [&]() {
     for (int j = 0; j < 64; ++j) srow.push_back(-1);
@@ -924,19 +935,26 @@ static void bsell_build(BatchDevice *dv, const HMat &H, const std::vector<std::v
       }
       block0->push_back((int)(srow.size() / 64 / (BS / 64)));
     }
-    S.cslice.push_back((int)(srow.size() / 64));
+    X.cslice.push_back((int)(srow.size() / 64));
   }
-  S.nrows = H.nrows;
-  S.ncols = H.ncols;
-  S.nnz = (int64_t)H.ci.size();
-  S.nslices = (int)(srow.size() / 64);
-  S.entries = (int64_t)sv.size();
-  S.srow = bupload(dv, srow);
-  S.soff = bupload(dv, soff);
-  S.scol = bupload(dv, scol);
-  S.sv64 = bupload(dv, sv);
-  std::vector<float> sv32(sv.begin(), sv.end());
-  S.sv32 = bupload(dv, sv32);
+  X.nrows = H.nrows;
+  X.ncols = H.ncols;
+  X.nnz = (int64_t)H.ci.size();
+  X.sv32.assign(sv.begin(), sv.end());
+}
+
+static void bsell_upload(BatchDevice *dv, const BSellHost &X, BSell &S) {
+  S.cslice = X.cslice;
+  S.nrows = X.nrows;
+  S.ncols = X.ncols;
+  S.nnz = X.nnz;
+  S.nslices = (int)(X.srow.size() / 64);
+  S.entries = (int64_t)X.sv.size();
+  S.srow = bupload(dv, X.srow);
+  S.soff = bupload(dv, X.soff);
+  S.scol = bupload(dv, X.scol);
+  S.sv64 = bupload(dv, X.sv);
+  S.sv32 = bupload(dv, X.sv32);
 }
 
 // per-mesh block tables that keep every mesh's rows in blocks of its own (empty meshes keep
@@ -1060,45 +1078,181 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       dv->dof_off[m + 1] = dv->dof_off[m] + h.n();
     }
     if (dv->dof_off[nm] * 4 > INT32_MAX) throw AsmgError{ASMG_EINVAL, "batch too large"};
-    // ---- fine level: mesh-major, colour-major inside a mesh
+    // ---- row layout of every merged level (sequential, cheap): the fine level is mesh-major;
+    // auxiliary level k holds its smoothing meshes, then the meshes whose bottom level it is
+    BLevel &F = dv->fine;
     {
-      BLevel &F = dv->fine;
-      HMat A;
-      std::vector<double> diag;
-      std::vector<uint8_t> c0flag;
-      std::vector<int> r0, r1;
       int off = 0;
-      int C = 0;
       for (int m = 0; m < nm; ++m) {
         F.mesh.push_back(m);
         F.off.push_back(off);
-        append_rows(A, H[m]->A, fine[m].perm, &fine[m].iperm, off, true, &diag);
-        C = std::max(C, (int)fine[m].coff.size() - 1);
-        r0.push_back(off);
-        r1.push_back(off + (int)H[m]->n());
-        for (int64_t i = 0; i < H[m]->n(); ++i) c0flag.push_back(i < fine[m].coff[1]);
         off += (int)H[m]->n();
       }
-      A.ncols = off;
       F.nrows = F.nsmooth = off;
-      bupload_csr(dv, A, dv->fineA);
-      upload_diag(dv, F, diag, c0flag);
-      alloc_level_vectors(dv, F);
-      // Gauss-Seidel passes: group c = colour c of every mesh
-      std::vector<std::vector<std::pair<int, int>>> groups(C);
-      for (int c = 0; c < C; ++c)
+    }
+    dv->aux.resize(K + 1);
+    std::vector<std::vector<int>> smooth_m(K + 1), bottom_m(K + 1);
+    for (int k = 0; k <= K; ++k) {
+      BLevel &L = dv->aux[k];
+      for (int m = 0; m < nm; ++m) {
+        const int D = H[m]->J - H[m]->lc;
+        if (D > k) smooth_m[k].push_back(m);
+        if (D == k) bottom_m[k].push_back(m);
+      }
+      int off = 0;
+      for (int m : smooth_m[k]) {
+        L.mesh.push_back(m);
+        L.off.push_back(off);
+        off += (int)H[m]->Al.at(H[m]->J - k).nrows;
+      }
+      L.nsmooth = off;
+      for (int m : bottom_m[k]) {
+        L.mesh.push_back(m);
+        L.off.push_back(off);
+        off += (int)H[m]->nc;
+      }
+      L.nrows = off;
+      L.nbottom = (int)bottom_m[k].size();
+    }
+    // rows of merged level k in each mesh's own (Morton) numbering: smoothing meshes through their
+    // colour permutation, bottom meshes as they are
+    auto natural_rows = [&](const BLevel &L, int k) {
+      std::vector<int> o;
+      o.reserve(L.nrows);
+      for (size_t i = 0; i < L.mesh.size(); ++i) {
+        const int m = L.mesh[i];
+        const int end = i + 1 < L.mesh.size() ? L.off[i + 1] : L.nrows;
+        if (H[m]->J - H[m]->lc > k)
+          for (int r : lev[m][k].iperm) o.push_back(L.off[i] + r);
+        else
+          for (int r = L.off[i]; r < end; ++r) o.push_back(r);
+      }
+      return o;
+    };
+    // ---- host images of every merged matrix, built on host threads (each task writes only its
+    // own stage), then uploaded in a fixed order
+    struct LevelImage {
+      HMat A;
+      std::vector<double> diag;
+      std::vector<uint8_t> c0flag;
+      BSellHost gs, cg;
+      // bottom meshes
+      std::vector<int> pref{0}, ncs, voff;
+      std::vector<int64_t> moff;
+      std::vector<double> inv;
+      std::vector<float> inv32;
+    };
+    LevelImage fine_img;
+    std::vector<LevelImage> aux_img(K + 1);
+    std::vector<BSellHost> p_img(K), pt_img(K);
+    BSellHost pi_img, pit_img;
+    std::vector<int> r0, r1;
+    for (int m = 0; m < nm; ++m) {
+      r0.push_back(F.off[m]);
+      r1.push_back(F.off[m] + (int)H[m]->n());
+    }
+    // tasks: 0 fine level, 1 Pi and Pi^T, 2..K+2 auxiliary levels, then the prolongations
+    host_parallel(0, K + 3 + K, [&](int t) {
+      if (t == 0) {
+        LevelImage &X = fine_img;
+        int C = 0;
         for (int m = 0; m < nm; ++m) {
-          const auto &co = fine[m].coff;
-          if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
+          append_rows(X.A, H[m]->A, fine[m].perm, &fine[m].iperm, F.off[m], true, &X.diag);
+          C = std::max(C, (int)fine[m].coff.size() - 1);
+          for (int64_t i = 0; i < H[m]->n(); ++i) X.c0flag.push_back(i < fine[m].coff[1]);
         }
-      bsell_build(dv, A, groups, false, F.sell);
-      // CG products: group m = mesh m, whole blocks per mesh
-      std::vector<std::vector<std::pair<int, int>>> mg(nm);
-      for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
-      std::vector<int> b0;
-      bsell_build(dv, A, mg, true, dv->cg_sell, &b0);
-      dv->cg_b0 = bupload(dv, b0);
+        X.A.ncols = F.nrows;
+        // Gauss-Seidel passes: group c = colour c of every mesh
+        Groups groups(C);
+        for (int c = 0; c < C; ++c)
+          for (int m = 0; m < nm; ++m) {
+            const auto &co = fine[m].coff;
+            if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
+          }
+        bsell_host(X.A, groups, false, X.gs);
+        // CG products: group m = mesh m, whole blocks per mesh
+        Groups mg(nm);
+        for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
+        bsell_host(X.A, mg, true, X.cg);
+      } else if (t == 1) {
+        // Pi (fine rows -> merged level 0 rows)
+        HMat Pi;
+        BLevel &L0 = dv->aux[0];
+        for (int m = 0; m < nm; ++m) {
+          const int D = H[m]->J - H[m]->lc;
+          const size_t j = std::find(L0.mesh.begin(), L0.mesh.end(), m) - L0.mesh.begin();
+          const std::vector<int> *cmap = D > 0 ? &lev[m][0].iperm : nullptr;
+          append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
+        }
+        Pi.ncols = L0.nrows;
+        std::vector<int> oPi;
+        for (int m = 0; m < nm; ++m)
+          for (int r : fine[m].morton) oPi.push_back(F.off[m] + r);
+        bsell_host(Pi, {{{0, Pi.nrows}}}, false, pi_img, &oPi);
+        const HMat PiT = htranspose(Pi);
+        const std::vector<int> oPiT = natural_rows(L0, 0);
+        bsell_host(PiT, {{{0, PiT.nrows}}}, false, pit_img, &oPiT);
+      } else if (t < K + 3) {
+        const int k = t - 2;
+        BLevel &L = dv->aux[k];
+        LevelImage &X = aux_img[k];
+        int C = 0;
+        for (size_t i = 0; i < smooth_m[k].size(); ++i) {
+          const int m = smooth_m[k][i];
+          const int l = H[m]->J - k;
+          append_rows(X.A, H[m]->Al.at(l), lev[m][k].perm, &lev[m][k].iperm, L.off[i], true, &X.diag);
+          C = std::max(C, (int)lev[m][k].coff.size() - 1);
+          const int nl = (int)H[m]->Al.at(l).nrows;
+          for (int r = 0; r < nl; ++r) X.c0flag.push_back(r < lev[m][k].coff[1]);
+        }
+        X.A.ncols = L.nsmooth;
+        Groups groups(C);
+        for (int c = 0; c < C; ++c)
+          for (size_t i = 0; i < smooth_m[k].size(); ++i) {
+            const auto &co = lev[smooth_m[k][i]][k].coff;
+            if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
+          }
+        bsell_host(X.A, groups, false, X.gs);
+        for (size_t i = 0; i < bottom_m[k].size(); ++i) {
+          const int m = bottom_m[k][i];
+          const int nc = (int)H[m]->nc;
+          X.ncs.push_back(nc);
+          X.voff.push_back(L.off[smooth_m[k].size() + i]);
+          X.moff.push_back((int64_t)X.inv.size());
+          X.inv.insert(X.inv.end(), H[m]->coarse_inv.begin(), H[m]->coarse_inv.end());
+          X.pref.push_back(X.pref.back() + nc);
+        }
+        X.inv32.assign(X.inv.begin(), X.inv.end());
+      } else {
+        // prolongation P (level k+1 -> k) for the smoothing meshes of level k
+        const int k = t - (K + 3);
+        BLevel &L = dv->aux[k], &Lc = dv->aux[k + 1];
+        HMat P;
+        for (int m : smooth_m[k]) {
+          const int D = H[m]->J - H[m]->lc;
+          const int l = H[m]->J - k;
+          const size_t j = std::find(Lc.mesh.begin(), Lc.mesh.end(), m) - Lc.mesh.begin();
+          const std::vector<int> *cmap = (D > k + 1) ? &lev[m][k + 1].iperm : nullptr;
+          append_rows(P, H[m]->P.at(l), lev[m][k].perm, cmap, Lc.off[j], false, nullptr);
+        }
+        P.ncols = Lc.nrows;
+        const std::vector<int> oP = natural_rows(L, k), oPT = natural_rows(Lc, k + 1);
+        bsell_host(P, {{{0, P.nrows}}}, false, p_img[k], &oP);
+        const HMat PT = htranspose(P);
+        bsell_host(PT, {{{0, PT.nrows}}}, false, pt_img[k], &oPT);
+      }
+    });
+    // ---- uploads
+    {
+      LevelImage &X = fine_img;
+      bupload_csr(dv, X.A, dv->fineA);
+      upload_diag(dv, F, X.diag, X.c0flag);
+      alloc_level_vectors(dv, F);
+      bsell_upload(dv, X.gs, F.sell);
+      bsell_upload(dv, X.cg, dv->cg_sell);
+      dv->cg_b0 = bupload(dv, X.cg.block0);
       dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
+      X = LevelImage();
       // element-wise blocks: 256-row chunks of each mesh (one block for an empty mesh)
       std::vector<int> em, e0, e1, eb{0};
       for (int m = 0; m < nm; ++m) {
@@ -1117,122 +1271,27 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       dv->ew_r1 = bupload(dv, e1);
       dv->ew_b0 = bupload(dv, eb);
     }
-    // ---- auxiliary levels k = 0..K: smoothing meshes (mesh-major, colour-major inside a mesh), then
-    // the meshes whose bottom level this is
-    dv->aux.resize(K + 1);
     for (int k = 0; k <= K; ++k) {
       BLevel &L = dv->aux[k];
-      std::vector<int> sm, bt;
-      for (int m = 0; m < nm; ++m) {
-        const int D = H[m]->J - H[m]->lc;
-        if (D > k) sm.push_back(m);
-        if (D == k) bt.push_back(m);
-      }
-      int off = 0;
-      HMat A;
-      std::vector<double> diag;
-      std::vector<uint8_t> c0flag;
-      int C = 0;
-      for (int m : sm) {
-        L.mesh.push_back(m);
-        L.off.push_back(off);
-        const int l = H[m]->J - k;
-        append_rows(A, H[m]->Al.at(l), lev[m][k].perm, &lev[m][k].iperm, off, true, &diag);
-        C = std::max(C, (int)lev[m][k].coff.size() - 1);
-        const int nl = (int)H[m]->Al.at(l).nrows;
-        for (int i = 0; i < nl; ++i) c0flag.push_back(i < lev[m][k].coff[1]);
-        off += nl;
-      }
-      L.nsmooth = off;
-      A.ncols = off;
-      std::vector<std::vector<std::pair<int, int>>> groups(C);
-      for (int c = 0; c < C; ++c)
-        for (size_t i = 0; i < sm.size(); ++i) {
-          const auto &co = lev[sm[i]][k].coff;
-          if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
-        }
-      bsell_build(dv, A, groups, false, L.sell);
-      // bottom meshes
-      std::vector<int> pref{0}, ncs, voff;
-      std::vector<int64_t> moff;
-      std::vector<double> inv;
-      for (int m : bt) {
-        L.mesh.push_back(m);
-        L.off.push_back(off);
-        const int nc = (int)H[m]->nc;
-        ncs.push_back(nc);
-        voff.push_back(off);
-        moff.push_back((int64_t)inv.size());
-        inv.insert(inv.end(), H[m]->coarse_inv.begin(), H[m]->coarse_inv.end());
-        pref.push_back(pref.back() + nc);
-        off += nc;
-      }
-      L.nrows = off;
-      upload_diag(dv, L, diag, c0flag);
-      L.nbottom = (int)bt.size();
-      L.bottom_rows = pref.back();
-      L.bt_rowpref = bupload(dv, pref);
-      L.bt_nc = bupload(dv, ncs);
-      L.bt_voff = bupload(dv, voff);
-      L.bt_moff = bupload(dv, moff);
-      L.inv64 = bupload(dv, inv);
-      std::vector<float> inv32(inv.begin(), inv.end());
-      L.inv32 = bupload(dv, inv32);
+      LevelImage &X = aux_img[k];
+      bsell_upload(dv, X.gs, L.sell);
+      upload_diag(dv, L, X.diag, X.c0flag);
+      L.bottom_rows = X.pref.back();
+      L.bt_rowpref = bupload(dv, X.pref);
+      L.bt_nc = bupload(dv, X.ncs);
+      L.bt_voff = bupload(dv, X.voff);
+      L.bt_moff = bupload(dv, X.moff);
+      L.inv64 = bupload(dv, X.inv);
+      L.inv32 = bupload(dv, X.inv32);
       alloc_level_vectors(dv, L);
+      X = LevelImage();
     }
-    // rows of merged level k in each mesh's own (Morton) numbering: smoothing meshes through their
-    // colour permutation, bottom meshes as they are
-    auto natural_rows = [&](const BLevel &L, int k) {
-      std::vector<int> o;
-      o.reserve(L.nrows);
-      for (size_t i = 0; i < L.mesh.size(); ++i) {
-        const int m = L.mesh[i];
-        const int end = i + 1 < L.mesh.size() ? L.off[i + 1] : L.nrows;
-        if (H[m]->J - H[m]->lc > k)
-          for (int r : lev[m][k].iperm) o.push_back(L.off[i] + r);
-        else
-          for (int r = L.off[i]; r < end; ++r) o.push_back(r);
-      }
-      return o;
-    };
-    // ---- prolongations P (level k+1 -> k) for the smoothing meshes of level k
     for (int k = 0; k < K; ++k) {
-      BLevel &L = dv->aux[k], &Lc = dv->aux[k + 1];
-      HMat P;
-      for (size_t i = 0; i < L.mesh.size(); ++i) {
-        const int m = L.mesh[i];
-        const int D = H[m]->J - H[m]->lc;
-        if (D <= k) break;  // bottom meshes follow the smoothing ones
-        const int l = H[m]->J - k;
-        const size_t j = std::find(Lc.mesh.begin(), Lc.mesh.end(), m) - Lc.mesh.begin();
-        const std::vector<int> *cmap = (D > k + 1) ? &lev[m][k + 1].iperm : nullptr;
-        append_rows(P, H[m]->P.at(l), lev[m][k].perm, cmap, Lc.off[j], false, nullptr);
-      }
-      P.ncols = Lc.nrows;
-      const HMat PT = htranspose(P);
-      const std::vector<int> oP = natural_rows(L, k), oPT = natural_rows(Lc, k + 1);
-      bsell_build(dv, P, {{{0, P.nrows}}}, false, L.P, nullptr, &oP);
-      bsell_build(dv, PT, {{{0, PT.nrows}}}, false, L.PT, nullptr, &oPT);
+      bsell_upload(dv, p_img[k], dv->aux[k].P);
+      bsell_upload(dv, pt_img[k], dv->aux[k].PT);
     }
-    // ---- Pi (fine rows -> merged level 0 rows)
-    {
-      HMat Pi;
-      BLevel &L0 = dv->aux[0];
-      for (int m = 0; m < nm; ++m) {
-        const int D = H[m]->J - H[m]->lc;
-        const size_t j = std::find(L0.mesh.begin(), L0.mesh.end(), m) - L0.mesh.begin();
-        const std::vector<int> *cmap = D > 0 ? &lev[m][0].iperm : nullptr;
-        append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
-      }
-      Pi.ncols = L0.nrows;
-      const HMat PiT = htranspose(Pi);
-      std::vector<int> oPi;
-      for (int m = 0; m < nm; ++m)
-        for (int r : fine[m].morton) oPi.push_back(dv->fine.off[m] + r);
-      const std::vector<int> oPiT = natural_rows(L0, 0);
-      bsell_build(dv, Pi, {{{0, Pi.nrows}}}, false, dv->Pi, nullptr, &oPi);
-      bsell_build(dv, PiT, {{{0, PiT.nrows}}}, false, dv->PiT, nullptr, &oPiT);
-    }
+    bsell_upload(dv, pi_img, dv->Pi);
+    bsell_upload(dv, pit_img, dv->PiT);
     // ---- gather/scatter maps: internal fine row -> user offset of (mesh, rhs 0, dof), stride n_m
     {
       const int n = dv->fine.nrows;

@@ -23,7 +23,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -31,15 +30,14 @@
 #include <cstring>
 #include <numeric>
 #include <memory>
-#include <mutex>
 #include <string>
-#include <thread>
 #include <type_traits>
 #include <vector>
 
 #include "common.hpp"
-#include "trace.hpp"
 #include "device.hpp"
+#include "host_parallel.hpp"
+#include "trace.hpp"
 
 namespace asmg {
 
@@ -872,34 +870,6 @@ static void build_sell_ranges(Device *dv, DSell &S, const HCsr &H, const Ranges 
                               std::vector<int> *slot_map = nullptr, int wround = 1,
                               const std::vector<int> *order = nullptr) {
   sell_upload(dv, S, sell_host(H, groups, slot_map, wround, order), first_time);
-}
-
-// run f(i) for i in [0, n) on up to `threads` host threads (0 = all cores); the first error is
-// rethrown. Used for host-only layout work (no HIP calls inside f).
-template <class F>
-static void host_parallel(int threads, int n, F f) {
-  int nt = threads > 0 ? threads : (int)std::thread::hardware_concurrency();
-  nt = std::max(1, std::min(nt, n));
-  std::atomic<int> next{0};
-  std::mutex mu;
-  std::exception_ptr err;
-  auto work = [&]() {
-    try {
-      for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
-    } catch (...) {
-      std::lock_guard<std::mutex> g(mu);
-      if (!err) err = std::current_exception();
-      next = n;
-    }
-  };
-  if (nt == 1) {
-    work();
-  } else {
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t) th.emplace_back(work);
-    for (auto &t : th) t.join();
-  }
-  if (err) std::rethrow_exception(err);
 }
 
 // sizes only: the kernels read the auxiliary levels and the transfers through their sliced ELL
