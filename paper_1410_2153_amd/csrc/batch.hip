@@ -89,10 +89,19 @@ __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T 
   const VecR<NR, T> *X = reinterpret_cast<const VecR<NR, T> *>(x);
   int c[W];
   T v[W];
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32: nontemporal matrix loads, as in the single-mesh row products (batched mixed solve
+    // 185 -> 183 ms; FP64 unchanged, so it keeps plain loads)
 #pragma unroll
-  for (int k = 0; k < W; ++k) c[k] = cp[k * 64];
+    for (int k = 0; k < W; ++k) c[k] = __builtin_nontemporal_load(cp + k * 64);
 #pragma unroll
-  for (int k = 0; k < W; ++k) v[k] = vp[k * 64];
+    for (int k = 0; k < W; ++k) v[k] = __builtin_nontemporal_load(vp + k * 64);
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) c[k] = cp[k * 64];
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = vp[k * 64];
+  }
   pre();
   T a0[NR], a1[NR];
 #pragma unroll
