@@ -92,15 +92,17 @@ __device__ __forceinline__ void pin(T &v) {
 // finally calls `post` with the row product. With the row index (srow) loaded before the
 // matrix entries, a slice costs three dependent memory round trips:
 // {soff, srow} -> {columns, values, row data} -> gathers.
-template <int W, class T, class Pre, class Post>
+template <int W, bool NT = false, class T, class Pre, class Post>
 __device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
                                            const T *__restrict__ x, Pre &pre, Post &post) {
   int c[W];
   T v[W];
-  if constexpr (std::is_same<T, float>::value) {
-    // FP32 passes stream the matrix entries with nontemporal loads (each is read once per pass),
-    // leaving more of L2 to the gathered x lines. Measured: mixed solves 1.4 % faster on the
-    // graded and cube workloads; the same loads made the FP64 solve on the graded mesh slower.
+  if constexpr (NT || std::is_same<T, float>::value) {
+    // FP32 passes and the transfers (NT) stream the matrix entries with nontemporal loads (each
+    // is read once per pass), leaving more of L2 to the gathered x lines. Measured: mixed solves
+    // 1.4 % faster on the graded and cube workloads, FP64 B_co 0.6 % (graded) and 1.4 % (cube)
+    // faster with nontemporal transfers; in the FP64 colour passes the same loads made the graded
+    // solve slower, so those keep plain loads.
 #pragma unroll
     for (int k = 0; k < W; ++k) c[k] = __builtin_nontemporal_load(cp + k * 64);
 #pragma unroll
@@ -125,59 +127,59 @@ __device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *
   post(acc);
 }
 
-template <int W, class T>
+template <int W, bool NT, class T>
 __device__ __forceinline__ T sell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
                                         const T *__restrict__ x) {
   T acc = 0;
   auto pre = [] {};
   auto post = [&](T a) { acc = a; };
-  sell_row_w<W>(cp, vp, x, pre, post);
+  sell_row_w<W, NT>(cp, vp, x, pre, post);
   return acc;
 }
 
 // Straight-line cases up to WMAX entries (16, or 32 for matrices with longer rows such as the
 // 3-D transfers); longer rows go in chunks of 8.
-template <class T, int WMAX = 16, class Pre, class Post>
+template <class T, int WMAX = 16, bool NT = false, class Pre, class Post>
 __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
                                          const T *__restrict__ x, Pre &pre, Post &post) {
   switch (w) {
     case 0: pre(); post(T(0)); return;
-    case 1: sell_row_w<1>(cp, vp, x, pre, post); return;
-    case 2: sell_row_w<2>(cp, vp, x, pre, post); return;
-    case 3: sell_row_w<3>(cp, vp, x, pre, post); return;
-    case 4: sell_row_w<4>(cp, vp, x, pre, post); return;
-    case 5: sell_row_w<5>(cp, vp, x, pre, post); return;
-    case 6: sell_row_w<6>(cp, vp, x, pre, post); return;
-    case 7: sell_row_w<7>(cp, vp, x, pre, post); return;
-    case 8: sell_row_w<8>(cp, vp, x, pre, post); return;
-    case 9: sell_row_w<9>(cp, vp, x, pre, post); return;
-    case 10: sell_row_w<10>(cp, vp, x, pre, post); return;
-    case 11: sell_row_w<11>(cp, vp, x, pre, post); return;
-    case 12: sell_row_w<12>(cp, vp, x, pre, post); return;
-    case 13: sell_row_w<13>(cp, vp, x, pre, post); return;
-    case 14: sell_row_w<14>(cp, vp, x, pre, post); return;
-    case 15: sell_row_w<15>(cp, vp, x, pre, post); return;
-    case 16: sell_row_w<16>(cp, vp, x, pre, post); return;
+    case 1: sell_row_w<1, NT>(cp, vp, x, pre, post); return;
+    case 2: sell_row_w<2, NT>(cp, vp, x, pre, post); return;
+    case 3: sell_row_w<3, NT>(cp, vp, x, pre, post); return;
+    case 4: sell_row_w<4, NT>(cp, vp, x, pre, post); return;
+    case 5: sell_row_w<5, NT>(cp, vp, x, pre, post); return;
+    case 6: sell_row_w<6, NT>(cp, vp, x, pre, post); return;
+    case 7: sell_row_w<7, NT>(cp, vp, x, pre, post); return;
+    case 8: sell_row_w<8, NT>(cp, vp, x, pre, post); return;
+    case 9: sell_row_w<9, NT>(cp, vp, x, pre, post); return;
+    case 10: sell_row_w<10, NT>(cp, vp, x, pre, post); return;
+    case 11: sell_row_w<11, NT>(cp, vp, x, pre, post); return;
+    case 12: sell_row_w<12, NT>(cp, vp, x, pre, post); return;
+    case 13: sell_row_w<13, NT>(cp, vp, x, pre, post); return;
+    case 14: sell_row_w<14, NT>(cp, vp, x, pre, post); return;
+    case 15: sell_row_w<15, NT>(cp, vp, x, pre, post); return;
+    case 16: sell_row_w<16, NT>(cp, vp, x, pre, post); return;
     default: break;
   }
   if constexpr (WMAX > 16) {
     switch (w) {
-      case 17: sell_row_w<17>(cp, vp, x, pre, post); return;
-      case 18: sell_row_w<18>(cp, vp, x, pre, post); return;
-      case 19: sell_row_w<19>(cp, vp, x, pre, post); return;
-      case 20: sell_row_w<20>(cp, vp, x, pre, post); return;
-      case 21: sell_row_w<21>(cp, vp, x, pre, post); return;
-      case 22: sell_row_w<22>(cp, vp, x, pre, post); return;
-      case 23: sell_row_w<23>(cp, vp, x, pre, post); return;
-      case 24: sell_row_w<24>(cp, vp, x, pre, post); return;
-      case 25: sell_row_w<25>(cp, vp, x, pre, post); return;
-      case 26: sell_row_w<26>(cp, vp, x, pre, post); return;
-      case 27: sell_row_w<27>(cp, vp, x, pre, post); return;
-      case 28: sell_row_w<28>(cp, vp, x, pre, post); return;
-      case 29: sell_row_w<29>(cp, vp, x, pre, post); return;
-      case 30: sell_row_w<30>(cp, vp, x, pre, post); return;
-      case 31: sell_row_w<31>(cp, vp, x, pre, post); return;
-      case 32: sell_row_w<32>(cp, vp, x, pre, post); return;
+      case 17: sell_row_w<17, NT>(cp, vp, x, pre, post); return;
+      case 18: sell_row_w<18, NT>(cp, vp, x, pre, post); return;
+      case 19: sell_row_w<19, NT>(cp, vp, x, pre, post); return;
+      case 20: sell_row_w<20, NT>(cp, vp, x, pre, post); return;
+      case 21: sell_row_w<21, NT>(cp, vp, x, pre, post); return;
+      case 22: sell_row_w<22, NT>(cp, vp, x, pre, post); return;
+      case 23: sell_row_w<23, NT>(cp, vp, x, pre, post); return;
+      case 24: sell_row_w<24, NT>(cp, vp, x, pre, post); return;
+      case 25: sell_row_w<25, NT>(cp, vp, x, pre, post); return;
+      case 26: sell_row_w<26, NT>(cp, vp, x, pre, post); return;
+      case 27: sell_row_w<27, NT>(cp, vp, x, pre, post); return;
+      case 28: sell_row_w<28, NT>(cp, vp, x, pre, post); return;
+      case 29: sell_row_w<29, NT>(cp, vp, x, pre, post); return;
+      case 30: sell_row_w<30, NT>(cp, vp, x, pre, post); return;
+      case 31: sell_row_w<31, NT>(cp, vp, x, pre, post); return;
+      case 32: sell_row_w<32, NT>(cp, vp, x, pre, post); return;
       default: break;
     }
   }
@@ -185,7 +187,7 @@ __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, cons
   pre();
   T acc = 0;
   int k = 0;
-  for (; k + 8 <= w; k += 8) acc += sell_chunk<8>(cp + k * 64, vp + k * 64, x);
+  for (; k + 8 <= w; k += 8) acc += sell_chunk<8, NT>(cp + k * 64, vp + k * 64, x);
   for (; k < w; ++k) acc += vp[k * 64] * x[cp[k * 64]];
   post(acc);
 }
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(BS_MAX) void k_sell_spmv(int ns, const int *__restr
       if (rc) rc[row] = acc;
     }
   };
-  sell_row<T, WMAX>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  sell_row<T, WMAX, true>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
 }
 
 // dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
