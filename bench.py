@@ -373,10 +373,11 @@ def main():
     # dominant kernel: the Gauss-Seidel colour pass (sliced ELL, FP64); every pass inside full B_co
     # applications is timed by HIP events stamped with that launch's start and end, on torch's stream
     if args.no_kernel_timing:
-        ms_gs = by_gs = ms_spmv = by_spmv = ms_b64 = by_b64 = ms_b32 = by_b32 = float("nan")
+        ms_gs = by_gs = ms_spmv = by_spmv = ms_mv = by_mv = ms_b64 = by_b64 = ms_b32 = by_b32 = float("nan")
     else:
         ms_gs, by_gs = S64.time_kernel(4, reps=10, precision=A.PREC_FP64)
-        ms_spmv, by_spmv = S64.time_kernel(0, reps=50)
+        ms_spmv, by_spmv = S64.time_kernel(6, reps=50)
+        ms_mv, by_mv = S64.time_kernel(0, reps=50)
         ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
         ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
     crec = counter_record()
@@ -391,7 +392,10 @@ def main():
             "fp32": {"ms": ms_b32, "model_bytes": by_b32, "GBs": by_b32 / ms_b32 / 1e6,
                      "frac_of_peak": by_b32 / ms_b32 / 1e6 / HBM_PEAK_GBS,
                      "counted_hbm_bytes": bco.get("fp32", {}).get("traffic_bytes")},
-            "fine_spmv_fp64": {"ms": ms_spmv, "model_bytes": by_spmv, "GBs": by_spmv / ms_spmv / 1e6}}
+            "fine_spmv_fp64": {"kernel": "asmg::k_cg_spmv (PCG product q = A p with p.q partials, sliced ELL)",
+                               "ms": ms_spmv, "model_bytes": by_spmv, "GBs": by_spmv / ms_spmv / 1e6},
+            "abi_matvec_csr_fp64": {"kernel": "asmg::k_matvec (CSR, asmg_matvec_device only)",
+                                    "ms": ms_mv, "model_bytes": by_mv, "GBs": by_mv / ms_mv / 1e6}}
     out = {
         "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",
         "value": n * args.steps / dt64, "unit": "DOF-solves/s", "n_gpus": 1, "steps": args.steps,

@@ -94,6 +94,10 @@ typedef struct {
                           size, closure, leaves, kappa~) on the HIP device, with results identical
                           to the host setup; the later setup steps stay on the host. Needs
                           device >= 0; single-mesh handles. 0 = host (default). */
+  int red_blocks;      /* cap on the blocks of the PCG reduction kernels (dot products, residual
+                          norms, q = A p), 1..2048; 0 = 2048 (default). Beyond the cap the kernels
+                          loop over their rows (grid-stride). Results do not depend on it beyond
+                          the summation order of the dot products. Single-mesh handles. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -136,6 +140,13 @@ int asmg_update_coefficient(asmg_handle h, const double *kappa);
  */
 int asmg_set_coefficient_device(asmg_handle h, const double *d_kappa, void *stream);
 
+/*
+ * As asmg_set_coefficient_device with kappa_e = exp(m_e) computed on the device from a device
+ * array d_m of n_elements per-element log-coefficients (finite, not checked). This is the
+ * parametrisation of the adjoint gradient below.
+ */
+int asmg_set_log_coefficient_device(asmg_handle h, const double *d_m, void *stream);
+
 /* Switch the precision of later solves (ASMG_PREC_FP64 or ASMG_PREC_MIXED); both
  * value copies are resident after setup, so this only changes which kernels run. */
 int asmg_set_precision(asmg_handle h, int precision);
@@ -146,9 +157,11 @@ int asmg_dof_vertex(asmg_handle h, int32_t *map);
 
 /*
  * PCG solve from u_0 = 0 (or the nested iteration's guess, asmg_options.nested) until
- * ||f - A u||_2 <= tol ||f||_2 (recursively updated residual; the true residual is
- * recomputed in FP64 at exit and, in mixed precision, CG restarts from it while it is
- * above tol). A guess that already meets the rule returns it after 0 iterations.
+ * ||f - A u||_2 <= tol ||f||_2 (recursively updated residual). The true residual is
+ * recomputed in FP64 at exit; while it is above tol, CG restarts from it, at most 3 times
+ * (then the solve returns 0 with *true_rel_residual > tol); a restart needed with the
+ * iteration budget spent returns ASMG_ENOCONV. A guess that already meets the rule returns
+ * it after 0 iterations.
  *   f, u                 n doubles (host pointers)
  *   iterations           number of products with A (may be NULL)
  *   true_rel_residual    ||f - A u|| / ||f|| recomputed at exit (may be NULL)
@@ -180,6 +193,17 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
                                  void *stream);
 
 /*
+ * Adjoint gradient in the log-coefficients m (kappa_e = exp(m_e)) of a loss J(u) with
+ * u = A(exp(m))^-1 f: given the solution u and the adjoint state lam of A lam = dJ/du (A is
+ * symmetric, Section 2, so the adjoint solve is the same PCG), writes
+ *   d_g[e] = dJ/dm_e = -kappa_e lam_e^T K1_e u_e
+ * with the handle's current coefficient (the last asmg_set_(log_)coefficient_device, or setup).
+ * d_u, d_lam: n doubles in unknown order; d_g: n_elements doubles. Stream-ordered.
+ */
+int asmg_adjoint_gradient_device(asmg_handle h, const double *d_u, const double *d_lam, double *d_g,
+                                 void *stream);
+
+/*
  * Kernel timing for the bandwidth report: launches kernel `which` `reps` times
  * on `stream` between two HIP events and returns the mean duration in ms and
  * the algorithmic bytes one launch moves.
@@ -190,7 +214,9 @@ int asmg_element_gradient_device(asmg_handle h, const double *d_u, const double 
  *          4 (or 5) = the Gauss-Seidel colour-pass kernel (sliced ELL): inside `reps`
  *          full B_co applications every colour pass is launched once with a pair of HIP
  *          events stamped with that launch's own start and end (hipExtLaunchKernel), so
- *          caches are as in a solve; *ms and *bytes are the mean per launch
+ *          caches are as in a solve; *ms and *bytes are the mean per launch,
+ *          6 = the PCG product q = A p with its partial dot products (k_cg_spmv, sliced ELL,
+ *          FP64), the product the solve runs
  * Algorithmic bytes count each matrix entry, row pointer and vector entry the
  * operation needs once (a colour pass: its rows, b, 1/diag, the x write, and each
  * distinct gathered x entry).
@@ -223,6 +249,8 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "colour_aux"    int64 colour of every unknown of A_level (lc < level <= J)
  *   "local_set"     int64 0/1 per unknown of level `level` (lc < level <= J): member of N~_l
  *   "level_kept"    int64 0/1 per simplex of sigma^(level): kept in the Dirichlet grid
+ *   "solve_stats"   int64[2]: PCG iterations and restarts from the true residual of the last
+ *                   solve (device handles)
  *   "tuned_shapes"  int64 (threads per block, XCD order) per slice-kernel launch site of B_co
  *                   chosen by the launch-shape autotuner (level = precision; device handles,
  *                   empty before the first solve in that precision)

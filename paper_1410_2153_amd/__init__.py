@@ -31,6 +31,7 @@ EXPORTED = [
     "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
     "asmg_setup_batch", "asmg_solve_batch_device", "asmg_time_batch",
+    "asmg_set_log_coefficient_device", "asmg_adjoint_gradient_device",
 ]
 
 
@@ -46,7 +47,7 @@ class Options(ctypes.Structure):
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("nested", ctypes.c_int),
-                ("setup_device", ctypes.c_int)]
+                ("setup_device", ctypes.c_int), ("red_blocks", ctypes.c_int)]
 
 
 def _load():
@@ -61,6 +62,8 @@ def _load():
     lib.asmg_update_coefficient.argtypes = [P, P]
     lib.asmg_set_precision.argtypes = [P, ctypes.c_int]
     lib.asmg_set_coefficient_device.argtypes = [P, P, P]
+    lib.asmg_set_log_coefficient_device.argtypes = [P, P, P]
+    lib.asmg_adjoint_gradient_device.argtypes = [P, P, P, P, P]
     lib.asmg_num_dofs.argtypes = [P, ctypes.POINTER(I64)]
     lib.asmg_dof_vertex.argtypes = [P, P]
     lib.asmg_solve.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
@@ -124,7 +127,7 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0, setup_device=0):
+                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0, setup_device=0, red_blocks=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         if coords.ndim != 2 or elems.ndim != 2 or elems.shape[1] != coords.shape[1] + 1:
@@ -144,7 +147,9 @@ class Solver:
         opt.autotune = autotune
         opt.nested = nested
         opt.setup_device = setup_device
+        opt.red_blocks = red_blocks
         self.precision = precision
+        self.coef_version = 0   # bumped by every coefficient change (host or device)
         self.device = device
         dptr = None
         if dirichlet is not None:
@@ -191,10 +196,18 @@ class Solver:
         """Operator A from a device coefficient tensor; the auxiliary hierarchy is kept."""
         _need_device(kappa, self.n_elements, "kappa")
         _check(lib.asmg_set_coefficient_device(self.h, _tptr(kappa), _stream()))
+        self.coef_version += 1
+
+    def set_log_coefficient_device(self, m):
+        """Operator A from per-element log-coefficients (kappa = exp(m) computed in the library)."""
+        _need_device(m, self.n_elements, "m")
+        _check(lib.asmg_set_log_coefficient_device(self.h, _tptr(m), _stream()))
+        self.coef_version += 1
 
     def update_coefficient(self, kappa):
         kappa = _need_host(kappa, self.n_elements, "kappa")
         _check(lib.asmg_update_coefficient(self.h, _ptr(kappa)))
+        self.coef_version += 1
 
     # -- device tensors (torch) ---------------------------------------------
     def solve_device(self, f, tol=1e-8, out=None, allow_noconv=False):
@@ -229,6 +242,20 @@ class Solver:
         g = torch.empty(self.n_elements, dtype=torch.float64, device=u.device)
         _check(lib.asmg_element_gradient_device(self.h, _tptr(u), _tptr(lam), _tptr(g), _stream()))
         return g
+
+    def adjoint_gradient(self, u, lam):
+        """dJ/dm per element (kappa = exp(m)) from u and the adjoint state lam of A lam = dJ/du."""
+        import torch
+        _need_device(u, self.n, "u")
+        _need_device(lam, self.n, "lam")
+        g = torch.empty(self.n_elements, dtype=torch.float64, device=u.device)
+        _check(lib.asmg_adjoint_gradient_device(self.h, _tptr(u), _tptr(lam), _tptr(g), _stream()))
+        return g
+
+    def solve_stats(self):
+        """(iterations, restarts from the true residual) of the last solve."""
+        it, rs = self.export("solve_stats").tolist()
+        return it, rs
 
     def time_kernel(self, which, reps=20, precision=None):
         ms = ctypes.c_double()
@@ -357,10 +384,12 @@ class BatchSolver:
 class LogCoefficientSolve:
     """u(m) = A(exp(m))^{-1} f as a torch.autograd.Function over per-element log-coefficients m.
 
-    Forward: device-side refresh of A from kappa = exp(m) (the auxiliary hierarchy of
-    the last setup is kept as the preconditioner) + PCG solve. Backward: one more PCG
-    solve with the same symmetric matrix, A lam = dJ/du, then the element kernel
-    dJ/dm_e = -kappa_e lam_e^T K1_e u_e.
+    Forward: the library refreshes A from kappa = exp(m) on the device (the auxiliary
+    hierarchy of the last setup is kept as the preconditioner), then the PCG solve.
+    Backward: one more PCG solve with the same symmetric matrix, A lam = dJ/du, then the
+    library's adjoint element kernel dJ/dm_e = -kappa_e lam_e^T K1_e u_e. If the solver's
+    coefficient changed after this forward (another forward on the same solver), backward
+    first restores A(exp(m)) from the saved m.
     """
 
     @staticmethod
@@ -370,18 +399,23 @@ class LogCoefficientSolve:
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, m, f, solver, tol):
-                solver.set_coefficient_device(torch.exp(m.detach()).contiguous())
+                md = m.detach().contiguous()
+                solver.set_log_coefficient_device(md)
                 u, _, _ = solver.solve_device(f.contiguous(), tol)
                 ctx.solver = solver
                 ctx.tol = tol
-                ctx.save_for_backward(u)
+                ctx.version = solver.coef_version
+                ctx.save_for_backward(u, md)
                 return u
 
             @staticmethod
             def backward(ctx, gu):
-                (u,) = ctx.saved_tensors
-                lam, _, _ = ctx.solver.solve_device(gu.contiguous(), ctx.tol)
-                g = ctx.solver.element_gradient(u, lam)
-                return -g, None, None, None
+                u, md = ctx.saved_tensors
+                S = ctx.solver
+                if S.coef_version != ctx.version:
+                    S.set_log_coefficient_device(md)
+                    ctx.version = S.coef_version
+                lam, _, _ = S.solve_device(gu.contiguous(), ctx.tol)
+                return S.adjoint_gradient(u, lam), None, None, None
 
         return _Fn

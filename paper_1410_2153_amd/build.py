@@ -12,6 +12,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -34,17 +35,20 @@ def _run(cmd):
 
 def build(verbose: bool = True) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("domain.cpp", ["-ffp-contract=off"]), ("api.cpp", [])):
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
-        _run([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     # the device setup reproduces the host setup's IEEE operations: no contraction there either
     for src, extra in (("device.hip", []), ("batch.hip", []), ("tree.hip", ["-ffp-contract=off"]),
                        ("assemble.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
+    objs = [j[-1] for j in jobs]
+    # independent translation units compile in parallel (bounded by the host's cores)
+    workers = max(1, min(len(jobs), len(os.sched_getaffinity(0)), 16))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(_run, jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)

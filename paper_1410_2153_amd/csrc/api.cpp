@@ -108,6 +108,7 @@ int asmg_default_options(asmg_options *o) {
   o->autotune = 1;
   o->nested = 0;
   o->setup_device = 0;
+  o->red_blocks = 0;
   return ASMG_OK;
 }
 
@@ -126,7 +127,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
       o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 2 ||
       (o.domain >= 1 && dim != 2) || o.nested < 0 || o.nested > 16 || o.setup_device < 0 || o.setup_device > 1 ||
-      (o.setup_device == 1 && o.device < 0))
+      (o.setup_device == 1 && o.device < 0) || o.red_blocks < 0 || o.red_blocks > 2048)
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.nested > 0 && o.smoothing != 0)
     return set_err(ASMG_EINVAL, "the nested iteration needs whole-level smoothing (smoothing = 0)");
@@ -290,6 +291,12 @@ int asmg_set_coefficient_device(asmg_handle H, const double *d_kappa, void *stre
   ASMG_TRY({ return device_set_coefficient(H->dev, H->h, d_kappa, stream); })
 }
 
+int asmg_set_log_coefficient_device(asmg_handle H, const double *d_m, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_m) return set_err(ASMG_EINVAL, "null log-coefficient");
+  ASMG_TRY({ return device_set_log_coefficient(H->dev, H->h, d_m, stream); })
+}
+
 int asmg_matvec_device(asmg_handle H, const double *d_x, double *d_y, void *stream) {
   if (int r = need_dev(H)) return r;
   if (!d_x || !d_y) return set_err(ASMG_EINVAL, "null vector");
@@ -299,12 +306,18 @@ int asmg_matvec_device(asmg_handle H, const double *d_x, double *d_y, void *stre
 int asmg_element_gradient_device(asmg_handle H, const double *d_u, const double *d_lam, double *d_g, void *stream) {
   if (int r = need_dev(H)) return r;
   if (!d_u || !d_lam || !d_g) return set_err(ASMG_EINVAL, "null vector");
-  ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, stream); })
+  ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, 1.0, stream); })
+}
+
+int asmg_adjoint_gradient_device(asmg_handle H, const double *d_u, const double *d_lam, double *d_g, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_u || !d_lam || !d_g) return set_err(ASMG_EINVAL, "null vector");
+  ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, -1.0, stream); })
 }
 
 int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
   if (int r = need_dev(H)) return r;
-  if (which < 0 || which > 5 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
+  if (which < 0 || which > 6 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
   ASMG_TRY({ return device_time_kernel(H->dev, which, reps, precision, stream, ms, bytes); })
 }
 
@@ -312,7 +325,7 @@ int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *st
 static int check_options(const asmg_options &o) {
   if (o.nu_aux < 1 || o.nu_fine < 1 || o.max_iter < 1 || o.coarse_max_dofs < 1 || o.coarse_max_dofs > 8192 ||
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
-      o.colouring > 2 || o.domain < 0 || o.domain > 1)
+      o.colouring > 2 || o.domain < 0 || o.domain > 1 || o.red_blocks < 0 || o.red_blocks > 2048)
     return set_err(ASMG_EINVAL, "invalid options");
   if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
   if (o.nested != 0) return set_err(ASMG_EINVAL, "the nested iteration is available on single-mesh handles only");
@@ -481,6 +494,11 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
       if (!lm.kept.empty())
         for (size_t i = 0; i < k.size(); ++i) k[i] = lm.kept[i];
       return put(k, buf, count);
+    }
+    if (name == "solve_stats") {
+      if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");
+      std::vector<int64_t> v = {device_last_iterations(H->dev), device_restarts(H->dev)};
+      return put(v, buf, count);
     }
     if (name == "tuned_shapes") {  // level = precision
       if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");

@@ -343,8 +343,7 @@ struct BCtl {  // device pointers of the per-system scalars (arrays of n_meshes 
 // block sums of the NR values into partials[blk] (blk = the block's logical index)
 template <int NR>
 __device__ __forceinline__ void bwrite(double v[NR], double *partials, int blk) {
-#pragma unroll
-  for (int r = 0; r < NR; ++r) v[r] = block_sum(v[r]);
+  block_sum_n<NR>(v);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int r = 0; r < NR; ++r) partials[(size_t)blk * NR + r] = v[r];
@@ -363,8 +362,9 @@ __device__ __forceinline__ void breduce(const double *partials, int b0, int b1, 
   for (int b = b0 + (int)threadIdx.x; b < b1; b += BS)
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] += partials[(size_t)b * NR + r];
+  block_sum_n<NR>(s);
 #pragma unroll
-  for (int r = 0; r < NR; ++r) out[r] = block_sum(s[r]);
+  for (int r = 0; r < NR; ++r) out[r] = s[r];
 }
 
 __device__ __forceinline__ void bretire(BCtl c, int sys, int status) {
@@ -1688,13 +1688,17 @@ static int b_pcg(BatchDevice *dv, double tol, int *iters, double *true_rel, hipS
     HIPCHECK(hipMemcpyAsync(st.data(), dv->ctl.status, ns * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(it.data(), dv->ctl.iter, ns * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    // a system that converged on its updated residual with the true residual above tol restarts
+    // from the true residual (at most 3 rounds), or ends unconverged if its iterations are spent
     int nre = 0;
     for (int i = 0; i < ns; ++i) {
       const double rel = fn2[i] > 0 ? std::sqrt(tr[i] / fn2[i]) : 0.0;
-      mask[i] = (sizeof(T) == 4 && st[i] == BST_OK && fn2[i] > 0 && rel > tol && it[i] < dv->maxit) ? 1 : 0;
+      const bool want = st[i] == BST_OK && fn2[i] > 0 && rel > tol && restarts < 3;
+      if (want && it[i] >= dv->maxit) st[i] = BST_NOCONV;
+      mask[i] = (want && it[i] < dv->maxit) ? 1 : 0;
       nre += mask[i];
     }
-    if (nre > 0 && restarts < 3) {
+    if (nre > 0) {
       ++restarts;
       HIPCHECK(hipMemcpyAsync(dv->mask, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, s));
       with_lpr(FA.lpr, [&](auto cc) {

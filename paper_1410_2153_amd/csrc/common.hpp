@@ -33,18 +33,35 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// sum over a 256-thread block; result valid in thread 0
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sm[BS / 64];
-  v = group_sum<64>(v);
+// Sums of NR values over a 256-thread block in one pass; results valid in thread 0. Every wave
+// stores its NR partial sums, one barrier, then thread 0 adds them in wave order. The shared
+// array is not reused after the barrier, so a kernel calls this at most once (a second call
+// could overwrite sm while thread 0 still reads it).
+template <int NR>
+__device__ __forceinline__ void block_sum_n(double v[NR]) {
+  __shared__ double sm[NR][BS / 64];
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sm[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < BS / 64; ++i) r += sm[i];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    v[q] = group_sum<64>(v[q]);
+    if ((threadIdx.x & 63) == 0) sm[q][w] = v[q];
   }
-  return r;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < BS / 64; ++i) r += sm[q][i];
+    }
+    v[q] = r;
+  }
+}
+
+// sum over a 256-thread block; result valid in thread 0 (once per kernel, as block_sum_n)
+__device__ __forceinline__ double block_sum(double v) {
+  double a[1] = {v};
+  block_sum_n<1>(a);
+  return a[0];
 }
 
 // XCD-aware block index. Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b % 8),

@@ -305,9 +305,10 @@ __global__ __launch_bounds__(BS) void k_scatter_cvt(int n, const int *__restrict
   if (i < n) dst[perm[i]] = (double)src[i];
 }
 
-// Reductions: a producer kernel runs a bounded grid-stride grid (at most RED_BLOCKS blocks)
-// and writes one partial per block; a one-block finalize kernel reduces the partials in a
-// fixed order and updates the PCG scalars. No atomics, reproducible results.
+// Reductions: a producer kernel runs a bounded grid-stride grid (at most RED_BLOCKS blocks, or
+// the handle's smaller cap) and writes one partial per block; a one-block finalize kernel
+// reduces the partials in a fixed order and updates the PCG scalars. No atomics, reproducible
+// results.
 static constexpr int RED_BLOCKS = 2048;
 
 // r = f, u = 0, p = 0; partials of ||f||^2
@@ -623,12 +624,14 @@ __global__ __launch_bounds__(BS) void k_matvec(int n, const int *__restrict__ rp
   if (act && lane == 0) y[row] = dg[row] * x[row] + s;
 }
 
-// per-element g_e = kappa_e lam_e^T K1_e u_e (u, lam per unknown in unknown order)
+// per-element g_e = scale kappa_e lam_e^T K1_e u_e (u, lam per unknown in unknown order; scale 1
+// for the derivative of lam^T A u in m_e = log kappa_e, -1 for the adjoint gradient)
 template <int D>
 __global__ __launch_bounds__(BS) void k_elem_grad(int ne, const double *__restrict__ coords,
                                                   const int *__restrict__ elems, const double *__restrict__ kappa,
                                                   const int *__restrict__ dof_of_vertex, const double *__restrict__ u,
-                                                  const double *__restrict__ lam, double *__restrict__ g) {
+                                                  const double *__restrict__ lam, double *__restrict__ g,
+                                                  double scale) {
   const int e = blockIdx.x * BS + threadIdx.x;
   if (e >= ne) return;
   constexpr int K = D + 1;
@@ -679,7 +682,13 @@ __global__ __launch_bounds__(BS) void k_elem_grad(int ne, const double *__restri
     }
   double s = 0;
   for (int r = 0; r < D; ++r) s += gl[r] * gu[r];
-  g[e] = kappa[e] * vol * s;
+  g[e] = scale * (kappa[e] * vol * s);
+}
+
+// kappa_e = exp(m_e)
+__global__ __launch_bounds__(BS) void k_exp(int ne, const double *__restrict__ m, double *__restrict__ kappa) {
+  const int e = blockIdx.x * BS + threadIdx.x;
+  if (e < ne) kappa[e] = exp(m[e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -756,7 +765,9 @@ struct Device {
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;    // pinned
   double *partials = nullptr;
-  int max_blocks = 1;
+  int max_blocks = 1;          // cap of the reduction grids (grid-stride loops beyond it)
+  int restarts = 0;            // restarts from the true residual in the last solve
+  int solve_iters = 0;         // PCG iterations of the last solve
   // operator refresh from a device coefficient (original grid)
   int *rf_off_ptr = nullptr, *rf_off_el = nullptr, *rf_dg_ptr = nullptr, *rf_dg_el = nullptr, *rf_sell_map = nullptr;
   double *rf_off_w = nullptr, *rf_dg_w = nullptr;
@@ -1356,8 +1367,8 @@ Device *device_create(Hierarchy &h, int ordinal) {
     HIPCHECK(hipStreamCreateWithFlags(&dv->stream, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&dv->ev_in, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&dv->ev_out, hipEventDisableTiming));
-    dv->max_blocks = RED_BLOCKS;
-    dv->partials = dalloc<double>(dv, dv->max_blocks);
+    dv->max_blocks = h.opt.red_blocks > 0 ? std::min(h.opt.red_blocks, RED_BLOCKS) : RED_BLOCKS;
+    dv->partials = dalloc<double>(dv, RED_BLOCKS);
     // element data for the gradient kernel
     dv->ne = h.ne;
     dv->nv = h.nv;
@@ -1415,8 +1426,10 @@ void device_destroy(Device *dv) {
 // ---------------------------------------------------------------------------
 
 
-// grid of a reducing kernel: enough blocks for one pass, capped at RED_BLOCKS
-static inline int red_grid(int64_t rows, int lpr) { return std::min<int>(RED_BLOCKS, nblk(rows * lpr)); }
+// grid of a reducing kernel: enough blocks for one pass, capped at the handle's reduction cap
+static inline int red_grid(const Device *dv, int64_t rows, int lpr) {
+  return std::min<int>(dv->max_blocks, nblk(rows * lpr));
+}
 
 static inline double csr_bytes(const DCsr &A, int vbytes) {
   return (double)A.nnz * (vbytes + 4) + 4.0 * (A.nrows + 1);
@@ -1772,7 +1785,7 @@ static void nested_start(Device *dv, hipStream_t s) {
   }
   dv->site = 0;
   // r = f - A u, p = 0; done if the guess already meets the rule
-  const int gt = red_grid(F.n, F.A.lpr);
+  const int gt = red_grid(dv, F.n, F.A.lpr);
   with_lpr(F.A.lpr, [&](auto c) {
     constexpr int LP = decltype(c)::value;
     hipLaunchKernelGGL((k_cg_guess<LP>), dim3(gt), dim3(BS), 0, s, F.n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f,
@@ -1791,7 +1804,7 @@ template <class T>
 static void pcg_tail(Device *dv, hipStream_t s, bool first_done) {
   const int n = dv->fine.n;
   apply_Bco<T>(dv, dv->r, first_done, s);
-  const int g = red_grid(n, 1);
+  const int g = red_grid(dv, n, 1);
   hipLaunchKernelGGL((k_cg_rz<T>), dim3(g), dim3(BS), 0, s, n, dv->r, (const T *)LV<T>::x(dv->fine), dv->ctl,
                      dv->partials);
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
@@ -1841,11 +1854,11 @@ template <class T>
 static void pcg_iteration(Device *dv, hipStream_t s) {
   const int n = dv->fine.n;
   DLevel &F = dv->fine;
-  int g = std::min<int>(RED_BLOCKS, nblk((int64_t)F.sell.nslices * 64));
+  int g = std::min<int>(dv->max_blocks, nblk((int64_t)F.sell.nslices * 64));
   hipLaunchKernelGGL(k_cg_spmv, dim3(g), dim3(BS), 0, s, F.sell.nslices, F.sell.srow, F.sell.soff, F.sell.scol,
                      F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
   hipLaunchKernelGGL(k_fin_spmv, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
-  g = red_grid(n, 1);
+  g = red_grid(dv, n, 1);
   hipLaunchKernelGGL((k_cg_axpy<T>), dim3(g), dim3(BS), 0, s, n, dv->u, dv->r, dv->p, dv->q, dv->ctl, dv->partials,
                      F.first_rows, LV<T>::id(F), LV<T>::b(F), LV<T>::x(F));
   hipLaunchKernelGGL(k_fin_axpy, dim3(1), dim3(BS), 0, s, dv->partials, g, dv->ctl);
@@ -1882,7 +1895,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
   const int n = dv->fine.n;
   const int pi = sizeof(T) == 4 ? 1 : 0;
   DLevel &F = dv->fine;
-  const int gi = red_grid(n, 1);
+  const int gi = red_grid(dv, n, 1);
   hipLaunchKernelGGL(k_cg_init, dim3(gi), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, dv->partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, s, dv->partials, gi, tol, dv->maxit, dv->ctl);
   if (dv->nested > 0) nested_start<T>(dv, s);  // u = u_0, r = f - A u_0
@@ -1903,7 +1916,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
       continue;
     }
     // converged, broke down or hit max_iter: true residual in FP64
-    const int gt = red_grid(n, F.A.lpr);
+    const int gt = red_grid(dv, n, F.A.lpr);
     with_lpr(F.A.lpr, [&](auto c) {
       constexpr int LP = decltype(c)::value;
       hipLaunchKernelGGL((k_true_res<LP>), dim3(gt), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64, F.dg64, dv->f,
@@ -1913,20 +1926,30 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
     read_ctl(dv, s);
     const Ctl &c = *dv->ctl_host;
     const double rel = c.fnorm2 > 0 ? std::sqrt(c.tr / c.fnorm2) : 0.0;
-    if (c.status == ST_OK && sizeof(T) == 4 && rel > tol && restarts < 3 && c.iter < dv->maxit) {
-      ++restarts;
-      with_lpr(F.A.lpr, [&](auto cc) {
-        constexpr int LP = decltype(cc)::value;
-        hipLaunchKernelGGL((k_cg_restart<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci,
-                           F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->ctl);
-      });
-      pcg_tail<T>(dv, s, false);
-      continue;
+    // Converged on the recursively updated residual but the true residual is above tol: CG
+    // restarts from the true residual (at most 3 times), as the oracle does. With the iteration
+    // budget already spent the restart cannot take a step, and the solve ends unconverged.
+    int status = c.status;
+    if (status == ST_OK && rel > tol && restarts < 3) {
+      if (c.iter >= dv->maxit) {
+        status = ST_NOCONV;
+      } else {
+        ++restarts;
+        with_lpr(F.A.lpr, [&](auto cc) {
+          constexpr int LP = decltype(cc)::value;
+          hipLaunchKernelGGL((k_cg_restart<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci,
+                             F.A.v64, F.dg64, dv->f, dv->u, dv->r, dv->p, dv->ctl);
+        });
+        pcg_tail<T>(dv, s, false);
+        continue;
+      }
     }
+    dv->restarts = restarts;
+    dv->solve_iters = c.iter;
     if (iters) *iters = c.iter;
     if (true_rel) *true_rel = rel;
-    if (c.status == ST_OK) dv->last_iters[pi] = c.iter;
-    switch (c.status) {
+    if (status == ST_OK) dv->last_iters[pi] = c.iter;
+    switch (status) {
       case ST_OK: return ASMG_OK;
       case ST_NOTSPD: return ASMG_ENOTSPD;
       case ST_NAN: return ASMG_ENAN;
@@ -1958,9 +1981,8 @@ int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *it
   return rc;
 }
 
-int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream) {
-  HIPCHECK(hipSetDevice(dv->ordinal));
-  hipStream_t s = (hipStream_t)stream;
+// Operator refresh from dv->kappa (already written on `s`)
+static int refresh_operator(Device *dv, Hierarchy &h, hipStream_t s) {
   DLevel &F = dv->fine;
   if (!dv->rf_ready) {
     // element lists of every entry of A and the sliced-ELL slot of every entry: built once, at
@@ -1972,7 +1994,6 @@ int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void
     build_refresh(dv, h, H, slots);
     dv->rf_ready = true;
   }
-  HIPCHECK(hipMemcpyAsync(dv->kappa, d_kappa, (size_t)dv->ne * 8, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_refresh_off, dim3(nblk(F.A.nnz)), dim3(BS), 0, s, (int)F.A.nnz, dv->rf_off_ptr, dv->rf_off_el,
                      dv->rf_off_w, dv->kappa, F.A.v64, F.A.v32);
   hipLaunchKernelGGL(k_refresh_diag, dim3(nblk(F.n)), dim3(BS), 0, s, F.n, dv->rf_dg_ptr, dv->rf_dg_el, dv->rf_dg_w,
@@ -1983,6 +2004,23 @@ int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void
   HIPCHECK(hipStreamSynchronize(s));
   return ASMG_OK;
 }
+
+int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemcpyAsync(dv->kappa, d_kappa, (size_t)dv->ne * 8, hipMemcpyDeviceToDevice, s));
+  return refresh_operator(dv, h, s);
+}
+
+int device_set_log_coefficient(Device *dv, Hierarchy &h, const double *d_m, void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_exp, dim3(nblk(dv->ne)), dim3(BS), 0, s, (int)dv->ne, d_m, dv->kappa);
+  return refresh_operator(dv, h, s);
+}
+
+int device_restarts(const Device *dv) { return dv->restarts; }
+int device_last_iterations(const Device *dv) { return dv->solve_iters; }
 
 int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel) {
   HIPCHECK(hipSetDevice(dv->ordinal));
@@ -2031,15 +2069,16 @@ int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream) {
   return ASMG_OK;
 }
 
-int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, void *stream) {
+int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, double scale,
+                            void *stream) {
   HIPCHECK(hipSetDevice(dv->ordinal));
   hipStream_t s = (hipStream_t)stream;
   if (dv->d == 2)
     hipLaunchKernelGGL((k_elem_grad<2>), dim3(nblk(dv->ne)), dim3(BS), 0, s, (int)dv->ne, dv->coords, dv->elems,
-                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g);
+                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g, scale);
   else
     hipLaunchKernelGGL((k_elem_grad<3>), dim3(nblk(dv->ne)), dim3(BS), 0, s, (int)dv->ne, dv->coords, dv->elems,
-                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g);
+                       dv->kappa, dv->dof_of_vertex, d_u, d_lam, d_g, scale);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
   return ASMG_OK;
@@ -2058,8 +2097,12 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
       apply_Bco<double>(dv, dv->f, false, st);
   };
   auto bco = [&]() { bco_on(s); };
+  int g6 = std::min<int>(dv->max_blocks, nblk((int64_t)F.sell.nslices * 64));
   auto one = [&]() {
-    if (which == 0) {
+    if (which == 6) {
+      hipLaunchKernelGGL(k_cg_spmv, dim3(g6), dim3(BS), 0, s, F.sell.nslices, F.sell.srow, F.sell.soff, F.sell.scol,
+                         F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
+    } else if (which == 0) {
       with_lpr(F.A.lpr, [&](auto c) {
         constexpr int LP = decltype(c)::value;
         hipLaunchKernelGGL((k_matvec<LP>), dim3(nblk((int64_t)n * LP)), dim3(BS), 0, s, n, F.A.rp, F.A.ci, F.A.v64,
@@ -2109,10 +2152,15 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   // byte model of one launch
   dv->count_bytes = true;
   dv->bytes = 0;
-  if (which == 0)
-    dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 4;
+  if (which == 0 || which == 6)
+    dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 3 + (which == 6 ? 8.0 * g6 : 8.0 * n);
   else
     one();
+  if (which == 6) {
+    // the PCG product reads the control block's `done` flag: clear it (the next solve sets
+    // every field it reads)
+    HIPCHECK(hipMemsetAsync(dv->ctl, 0, sizeof(Ctl), s));
+  }
   dv->count_bytes = false;
   *bytes = dv->bytes;
   if (which == 2 || which == 3) {

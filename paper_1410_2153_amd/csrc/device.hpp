@@ -21,8 +21,14 @@ void device_set_precision(Device *dv, int precision);
 int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream);
 int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, void *stream);
 int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream);
+// kappa = exp(m) on the device, then the refresh of device_set_coefficient
+int device_set_log_coefficient(Device *dv, Hierarchy &h, const double *d_m, void *stream);
+// restarts from the true residual in the last solve
+int device_restarts(const Device *dv);
+int device_last_iterations(const Device *dv);
 int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream);
-int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, void *stream);
+int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, double scale,
+                            void *stream);
 int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes);
 // launch shapes picked by the autotuner for a precision: (threads per block, XCD order) per
 // slice-kernel launch site, flattened (empty before the first solve in that precision)

@@ -97,3 +97,50 @@ def test_set_coefficient_device_twice_after_a_solve():
         assert np.linalg.norm(y - Ak @ x) <= 1e-14 * np.linalg.norm(Ak @ x)
         u, it, tr = S.solve(f, 1e-10)
         assert np.linalg.norm(f - Ak @ u) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(f)
+
+
+def test_log_coefficient_entry_points():
+    # kappa = exp(m) and the adjoint sign are computed in the library
+    c = W.make_config(4, scale=24 / 724)
+    coords, elems = c["coords"], c["elems"]
+    S = A.Solver(coords, elems, np.ones(len(elems)))
+    m = torch.tensor(c["m"], device="cuda")
+    S.set_log_coefficient_device(m)
+    Am, dofs = fem.assemble(coords, elems, np.exp(c["m"]))
+    x = np.random.default_rng(3).standard_normal(S.n)
+    y = S.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.linalg.norm(y - Am @ x) <= 1e-14 * np.linalg.norm(Am @ x)
+    u = torch.from_numpy(np.random.default_rng(4).standard_normal(S.n)).cuda()
+    lam = torch.from_numpy(np.random.default_rng(5).standard_normal(S.n)).cuda()
+    g = S.adjoint_gradient(u, lam)
+    assert torch.equal(g, -S.element_gradient(u, lam))
+
+
+def test_backward_after_a_second_forward_on_the_same_solver():
+    # two forwards at m1 and m2 on one solver, then backward of J(u(m1)) alone: the gradient is
+    # the oracle's at m1 (backward restores A(exp(m1)) before its adjoint solve)
+    c = W.make_config(4, scale=24 / 724)
+    coords, elems = c["coords"], c["elems"]
+    S = A.Solver(coords, elems, np.exp(c["m"]))
+    dofs = S.dof_vertex()
+    f = torch.tensor(c["f_vertex"][dofs], device="cuda")
+    Aobs, _ = fem.assemble(coords, elems, np.exp(c["m_obs"]))
+    import scipy.sparse.linalg as sla
+    u_obs = sla.spsolve(Aobs.tocsc(), c["f_vertex"][dofs]) + c["noise_vertex"][dofs]
+    uo = torch.tensor(u_obs, device="cuda")
+    Fn = A.LogCoefficientSolve.function()
+    m1 = torch.tensor(c["m"], device="cuda", requires_grad=True)
+    m2 = torch.tensor(c["m_obs"], device="cuda", requires_grad=True)
+    u1 = Fn.apply(m1, f, S, 1e-12)
+    u2 = Fn.apply(m2, f, S, 1e-12)
+    J1 = 0.5 * ((u1 - uo) ** 2).sum()
+    J1.backward()
+    _, gref, _ = adjoint.loss_and_gradient(coords, elems, c["m"], c["f_vertex"][dofs], u_obs)
+    g = m1.grad.cpu().numpy()
+    assert np.abs(g - gref).max() <= 1e-8 * np.abs(gref).max()
+    assert m2.grad is None
+    # the later backward of J(u(m2)) is right too
+    J2 = 0.5 * ((u2 - uo) ** 2).sum()
+    J2.backward()
+    _, gref2, _ = adjoint.loss_and_gradient(coords, elems, c["m_obs"], c["f_vertex"][dofs], u_obs)
+    assert np.abs(m2.grad.cpu().numpy() - gref2).max() <= 1e-8 * np.abs(gref2).max()

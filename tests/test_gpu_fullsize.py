@@ -124,10 +124,15 @@ def test_adjoint_fullsize_finite_differences():
     lv[dofs] = lam.cpu().numpy()
     ref = -fem.element_gradient_of_energy(coords, elems, np.exp(c["m"]), uv, lv)
     assert np.abs(g - ref).max() <= 1e-8 * np.abs(ref).max()
-    for d in c["directions"][:3]:
+    worst = 0.0
+    for k, d in enumerate(c["directions"]):
         eps = 1e-6
         fd = (J(c["m"] + eps * d) - J(c["m"] - eps * d)) / (2 * eps)
-        _say(f"directional derivative: adjoint {g @ d:.10e} fd {fd:.10e}")
-        # central differences at eps = 1e-6 with forward solves to 1e-12: the solve error
-        # (~ tol * J / (eps |g.d|)) dominates, about 1e-5 relative on this mesh
-        assert fd == pytest.approx(g @ d, rel=5e-5)
+        rel = abs(fd - g @ d) / abs(g @ d)
+        worst = max(worst, rel)
+        _say(f"direction {k}: adjoint {g @ d:.10e} fd {fd:.10e} rel {rel:.2e}")
+        # central differences at eps = 1e-6 with forward solves to 1e-12: the error of each
+        # J evaluation is about tol * ||u - u_obs|| * ||u||, divided by 2 eps it reaches about
+        # 1e-5 of g.d on this mesh; the truncation error (eps^2) is far below
+        assert rel <= 5e-5
+    _say(f"all {len(c['directions'])} directions: worst relative difference {worst:.2e}")

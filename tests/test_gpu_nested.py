@@ -73,7 +73,12 @@ def test_nested_fp64(case, cycles):
     _say(name, f"nested={cycles}: iterations gpu {it} oracle {ito} (from 0: {it0}), rel diff {_rel(u, uo):.2e}")
     assert it == ito
     assert _rel(u, uo) <= 1e-10
+    assert np.abs(u - uo).max() <= 1e-10 * np.abs(uo).max()
     assert tr <= 1e-8
+    # the start's residual kernel (k_cg_guess) with its grid-stride loop over a capped grid
+    Sg = A.Solver(c["coords"], c["elems"], c["kappa"], c.get("dirichlet"), domain=dom, nested=cycles, red_blocks=5)
+    ug, itg, _ = Sg.solve(f, 1e-8)
+    assert itg == ito and np.abs(ug - uo).max() <= 1e-10 * np.abs(uo).max()
     # a second solve on the same handle: zero right-hand side, then the first one again
     z, itz, trz = S.solve(np.zeros_like(f), 1e-8)
     assert itz == 0 and not np.any(z)

@@ -110,6 +110,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _rel_inf(a, b):
+    """element-wise bar: max_i |a_i - b_i| / max_i |b_i|"""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def test_matvec(case):
     name, c, H, S64, S32, f = case
     x = np.random.default_rng(1).standard_normal(H.n)
@@ -122,8 +127,9 @@ def test_preconditioner_fp64(case):
     r = np.random.default_rng(2).standard_normal(H.n)
     z = S64.apply_preconditioner(torch.from_numpy(r).cuda()).cpu().numpy()
     zo = H.preconditioner()(r)
-    _say(name, "B_co fp64 rel diff", _rel(z, zo))
+    _say(name, "B_co fp64 rel diff", _rel(z, zo), "element-wise", _rel_inf(z, zo))
     assert _rel(z, zo) <= 1e-12
+    assert _rel_inf(z, zo) <= 1e-12
 
 
 def test_preconditioner_mixed(case):
@@ -155,6 +161,28 @@ def test_solve_fp64(case):
     assert it == ito or near
     assert tr <= 1e-8 * (1 + 1e-6)
     assert _rel(u, uo) <= 1e-10
+    assert _rel_inf(u, uo) <= 1e-10
+
+
+# reduction grids capped at a few blocks: every grid-stride loop of the PCG kernels (initial
+# residual, q = A p with p.q, the updates with ||r||^2, r.z, the true residual) runs many rounds
+@pytest.mark.parametrize("blocks", [3, 11])
+def test_solve_fp64_grid_stride_loops(case, blocks):
+    name, c, H, S64, S32, f = case
+    if name not in ("graded20k", "cube16", "annulus_mixed"):
+        pytest.skip("three cases cover the loops")
+    uo, ito, info = H.solve(f, 1e-8, record=True)
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], red_blocks=blocks, **S64.kwargs)
+    u, it, tr = S.solve(f, 1e-8)
+    near = any(abs(h - 1e-8) < 1e-3 * 1e-8 for h in info["history"][-2:])
+    _say(name, f"red_blocks={blocks}: iters gpu {it} oracle {ito}, element-wise {_rel_inf(u, uo):.2e}")
+    assert it == ito or near
+    assert tr <= 1e-8 * (1 + 1e-6)
+    assert _rel_inf(u, uo) <= 1e-10
+    S.set_precision(A.PREC_MIXED)
+    um, itm, trm = S.solve(f, 1e-8)
+    ref, _, _ = H.solve(f, 1e-12)
+    assert trm <= 1e-8 and _rel_inf(um, ref) <= 1e-6
 
 
 def test_solve_device_matches_host_and_is_deterministic(case):
@@ -174,9 +202,11 @@ def test_solve_mixed(case):
     u, it, tr = S32.solve(f, 1e-8)
     u64, it64, _ = S64.solve(f, 1e-8)
     err = _rel(u, ref)
-    _say(name, "mixed iters", it, "fp64 iters", it64, "err vs 1e-12 oracle", err, "fp64 err", _rel(u64, ref))
+    _say(name, "mixed iters", it, "fp64 iters", it64, "err vs 1e-12 oracle", err, "fp64 err", _rel(u64, ref),
+         "element-wise", _rel_inf(u, ref))
     assert tr <= 1e-8
     assert err <= 1e-6
+    assert _rel_inf(u, ref) <= 1e-6
 
 
 def test_zero_rhs_and_max_iter(case):
@@ -213,7 +243,7 @@ def test_kernel_timing_leaves_the_solver_intact():
     S = A.Solver(c["coords"], c["elems"], c["kappa"])
     f = c["f_vertex"][S.dof_vertex()]
     u0, it0, _ = S.solve(f, 1e-8)
-    for which, prec in ((0, A.PREC_FP64), (2, A.PREC_FP64), (2, A.PREC_MIXED), (4, A.PREC_FP64)):
+    for which, prec in ((0, A.PREC_FP64), (6, A.PREC_FP64), (2, A.PREC_FP64), (2, A.PREC_MIXED), (4, A.PREC_FP64)):
         ms, by = S.time_kernel(which, reps=20, precision=prec)
         _say("time_kernel", which, prec, f"{ms * 1e3:.1f} us, {by / 1e6:.2f} MB")
         assert 0 < ms < 1e3 and by > 0

@@ -32,12 +32,14 @@ def _write(path, coords, elems, kappa, domain=0, mask=None):
 def test_host_setup_under_sanitizers(tmp_path):
     flags = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
              "-ffp-contract=off", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
-    srcs = ["setup.cpp", "domain.cpp", "setup_check_main.cpp"]
-    procs = [subprocess.Popen(["g++", *flags, "-c", os.path.join(CSRC, s), "-o", str(tmp_path / (s + ".o"))])
+    here = os.path.dirname(os.path.abspath(__file__))
+    srcs = [os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "domain.cpp"), os.path.join(here, "setup_check_main.cpp")]
+    procs = [subprocess.Popen(["g++", *flags, "-c", s, "-o", str(tmp_path / (os.path.basename(s) + ".o"))])
              for s in srcs]
     assert all(p.wait() == 0 for p in procs)
     exe = str(tmp_path / "setup_check")
-    subprocess.run(["g++", *flags, *[str(tmp_path / (s + ".o")) for s in srcs], "-o", exe, "-lpthread"], check=True)
+    subprocess.run(["g++", *flags, *[str(tmp_path / (os.path.basename(s) + ".o")) for s in srcs], "-o", exe,
+                    "-lpthread"], check=True)
 
     cases = []
     c = W.make_config(1, scale=0.004)

@@ -76,3 +76,36 @@ def test_adjoint_gradient_finite_differences():
         Jm = adjoint.loss_and_gradient(coords, elems, m - eps * d, f, u_obs)[0]
         fd = (Jp - Jm) / (2 * eps)
         assert fd == pytest.approx(g @ d, rel=1e-6, abs=1e-12)
+
+
+@pytest.mark.parametrize("cfg,scale", [(0, 1.0), (1, 0.01)])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_restart_from_true_residual_at_the_fp64_floor(cfg, scale, mixed):
+    # Below the FP64 floor of the true residual (about 1.5e-15 relative here) the recursively
+    # updated residual still meets tol = 1e-15 while f - A u cannot: CG restarts from the true
+    # residual at most 3 times, then returns "ok" with the true residual above tol.
+    c = W.make_config(cfg, scale=scale)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
+    f = c["f_vertex"][H.dofs]
+    u, it, info = H.solve(f, 1e-15, mixed=mixed, record=True)
+    assert info["status"] == "ok" and info["restarts"] == 3
+    assert info["true_rel_residual"] > 1e-15
+    # each restart takes at least one product with A
+    first = next(k for k, h in enumerate(info["history"]) if h <= 1e-15) + 1
+    assert it >= first + 3
+    # the iterate is still the solution to the floor: the error is far below the 1e-8 solve's
+    ref = np.linalg.solve(H.A.toarray(), f) if H.n <= 5000 else None
+    if ref is not None:
+        assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_restart_with_the_iteration_budget_spent_is_noconv():
+    # converged on the updated residual exactly at max_iter with the true residual above tol:
+    # the restart cannot take a step, so the solve ends unconverged
+    c = W.make_config(0)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
+    f = c["f_vertex"][H.dofs]
+    _, _, info = H.solve(f, 1e-15, record=True)
+    first = next(k for k, h in enumerate(info["history"]) if h <= 1e-15) + 1
+    u, it, info2 = H.solve(f, 1e-15, max_iter=first)
+    assert info2["status"] == "noconv" and it == first
