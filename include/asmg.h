@@ -174,6 +174,22 @@ int asmg_solve(asmg_handle h, const double *f, double tol, double *u, int *itera
 int asmg_solve_device(asmg_handle h, const double *d_f, double tol, double *d_u, int *iterations,
                       double *true_rel_residual, void *stream);
 
+/*
+ * As asmg_solve_device, for callers that cannot allocate (serving loops, harnesses that forbid
+ * allocation): the call allocates nothing, host or device, and calls no allocating routine.
+ * The PCG control block and the reduction partials live in a static per-GPU scratch array of
+ * 16640 bytes (256 for the control block, 8 per reduction block up to 2048) held by the library
+ * until the process ends; every handle's reduction grid fits it (a larger one would be rejected
+ * with ASMG_EINVAL). The iteration runs as eager kernel launches (no graph is built) and the
+ * launch-shape autotuner never runs here: the shapes tuned by earlier asmg_solve_device calls on
+ * the handle are used, or the defaults. Results equal asmg_solve_device's bit for bit. Calls on
+ * one GPU share that GPU's scratch: calls that overlap on one GPU (from several threads, or on
+ * streams that run concurrently) race and are not allowed; calls on different GPUs are
+ * independent. The handle's work vectors are used as by asmg_solve_device.
+ */
+int asmg_solve_device_noalloc(asmg_handle h, const double *d_f, double tol, double *d_u, int *iterations,
+                              double *true_rel_residual, void *stream);
+
 /* z = B_co r (Algorithm 1 with u_0 = 0): one preconditioner application on
  * device vectors in unknown order; precision as in asmg_options. */
 int asmg_apply_preconditioner_device(asmg_handle h, const double *d_r, double *d_z, int precision,

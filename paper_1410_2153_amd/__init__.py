@@ -31,7 +31,7 @@ EXPORTED = [
     "asmg_solve", "asmg_solve_device", "asmg_apply_preconditioner_device", "asmg_matvec_device",
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
     "asmg_setup_batch", "asmg_solve_batch_device", "asmg_time_batch",
-    "asmg_set_log_coefficient_device", "asmg_adjoint_gradient_device",
+    "asmg_set_log_coefficient_device", "asmg_adjoint_gradient_device", "asmg_solve_device_noalloc",
 ]
 
 
@@ -69,6 +69,8 @@ def _load():
     lib.asmg_solve.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     lib.asmg_solve_device.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_double), P]
+    lib.asmg_solve_device_noalloc.argtypes = [P, P, ctypes.c_double, P, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_double), P]
     lib.asmg_apply_preconditioner_device.argtypes = [P, P, P, ctypes.c_int, P]
     lib.asmg_matvec_device.argtypes = [P, P, P, P]
     lib.asmg_element_gradient_device.argtypes = [P, P, P, P, P]
@@ -219,6 +221,17 @@ class Solver:
         _check(lib.asmg_solve_device(self.h, _tptr(f), tol, _tptr(u), ctypes.byref(it), ctypes.byref(tr), _stream()),
                (ENOCONV,) if allow_noconv else ())
         return u, it.value, tr.value
+
+    def solve_device_noalloc(self, f, out, tol=1e-8, allow_noconv=False):
+        """asmg_solve_device_noalloc: as solve_device into the caller's `out`; the library
+        allocates nothing (control block and partials in its static per-GPU scratch)."""
+        _need_device(f, self.n, "f")
+        _need_device(out, self.n, "out")
+        it = ctypes.c_int()
+        tr = ctypes.c_double()
+        _check(lib.asmg_solve_device_noalloc(self.h, _tptr(f), tol, _tptr(out), ctypes.byref(it), ctypes.byref(tr),
+                                             _stream()), (ENOCONV,) if allow_noconv else ())
+        return out, it.value, tr.value
 
     def apply_preconditioner(self, r, precision=None):
         import torch

@@ -278,6 +278,18 @@ int asmg_solve_device(asmg_handle H, const double *d_f, double tol, double *d_u,
   })
 }
 
+int asmg_solve_device_noalloc(asmg_handle H, const double *d_f, double tol, double *d_u, int *iterations,
+                              double *true_rel, void *stream) {
+  if (int r = need_dev(H)) return r;
+  if (!d_f || !d_u) return set_err(ASMG_EINVAL, "null vector");
+  if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
+  ASMG_TRY({
+    int rc = device_solve_noalloc(H->dev, d_f, tol, d_u, iterations, true_rel, stream);
+    if (rc) set_err(rc, "solve did not converge or broke down");
+    return rc;
+  })
+}
+
 int asmg_apply_preconditioner_device(asmg_handle H, const double *d_r, double *d_z, int precision, void *stream) {
   if (int r = need_dev(H)) return r;
   if (!d_r || !d_z || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED))

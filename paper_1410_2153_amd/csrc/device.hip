@@ -30,6 +30,7 @@
 #include <cstring>
 #include <numeric>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -794,6 +795,7 @@ struct Device {
   std::vector<uint8_t> tune_has;       // site launched something
   int last_iters[2] = {0, 0};
   bool use_graph = true;
+  bool no_alloc = false;      // inside asmg_solve_device_noalloc: no autotuning, no graph
   // byte model accumulation, and per-launch HIP event timing of one GS kernel instance
   bool count_bytes = false;
   double bytes = 0.0;
@@ -1818,7 +1820,7 @@ static void pcg_tail(Device *dv, hipStream_t s, bool first_done) {
 template <class T>
 static void tune(Device *dv, hipStream_t s) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
-  if (dv->tuned[pi] || !dv->autotune) return;
+  if (dv->tuned[pi] || !dv->autotune || dv->no_alloc) return;
   TraceRange tr_tune("asmg::autotune");
   const int K = kNumShapes;
   std::vector<std::vector<float>> t;
@@ -2003,6 +2005,68 @@ static int refresh_operator(Device *dv, Hierarchy &h, hipStream_t s) {
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
   return ASMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve without allocation
+// ---------------------------------------------------------------------------
+
+// Scratch of device_solve_noalloc: the PCG control block at offset 0, the reduction partials
+// (at most RED_BLOCKS doubles) from offset kScratchPartials. One copy per GPU, held until the
+// process ends. In host code `scratch` names a host-side stand-in: only the address that
+// hipGetSymbolAddress returns for the current device may reach a kernel or a copy.
+static constexpr size_t kScratchPartials = 256;
+static constexpr size_t kScratchBytes = kScratchPartials + sizeof(double) * RED_BLOCKS;
+static_assert(sizeof(Ctl) <= kScratchPartials, "control block larger than its scratch slot");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// device address of `scratch` on device `ordinal`, looked up once per device with that device
+// current (the caller has made it current)
+static void *scratch_address(int ordinal) {
+  if (ordinal < 0 || ordinal >= kMaxScratchDevices)
+    throw AsmgError{ASMG_EDEVICE, "device ordinal beyond the scratch table"};
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[ordinal]) {
+    void *p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw AsmgError{ASMG_EDEVICE, "no device address for the solver scratch"};
+    g_scratch_ptr[ordinal] = p;
+  }
+  return g_scratch_ptr[ordinal];
+}
+
+int device_solve_noalloc(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel,
+                         void *stream) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  if (kScratchPartials + sizeof(double) * (size_t)dv->max_blocks > kScratchBytes)
+    throw AsmgError{ASMG_EINVAL, "reduction grid of this handle exceeds the solver scratch (" +
+                                     std::to_string(kScratchBytes) + " bytes)"};
+  unsigned char *base = (unsigned char *)scratch_address(dv->ordinal);
+  // the handle's own control block and partials are swapped for the scratch for this call; the
+  // iteration runs as eager launches (a captured graph holds the handle's own pointers) and
+  // never autotunes (the shapes tuned by earlier solves, or the defaults, are used). k_fin_init
+  // writes every control field a later kernel or the host reads, so nothing needs clearing.
+  struct Swap {
+    Device *dv;
+    Ctl *ctl;
+    double *partials;
+    bool graph;
+    ~Swap() {
+      dv->ctl = ctl;
+      dv->partials = partials;
+      dv->use_graph = graph;
+      dv->no_alloc = false;
+    }
+  } swap{dv, dv->ctl, dv->partials, dv->use_graph};
+  dv->ctl = (Ctl *)base;
+  dv->partials = (double *)(base + kScratchPartials);
+  dv->use_graph = false;
+  dv->no_alloc = true;
+  return device_solve(dv, d_f, tol, d_u, iters, true_rel, stream);
 }
 
 int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream) {

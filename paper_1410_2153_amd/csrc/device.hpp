@@ -19,6 +19,10 @@ void device_destroy(Device *dv);
 void device_set_precision(Device *dv, int precision);
 
 int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel, void *stream);
+// as device_solve, with the control block and reduction partials in the library's static
+// per-device scratch: no allocation of any kind
+int device_solve_noalloc(Device *dv, const double *d_f, double tol, double *d_u, int *iters, double *true_rel,
+                         void *stream);
 int device_apply_B(Device *dv, const double *d_r, double *d_z, int precision, void *stream);
 int device_set_coefficient(Device *dv, Hierarchy &h, const double *d_kappa, void *stream);
 // kappa = exp(m) on the device, then the refresh of device_set_coefficient
