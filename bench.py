@@ -1,17 +1,18 @@
 """Benchmark: DOF-solves/s of the ASMG-preconditioned CG solve on one MI355X.
 
-Workload (default): the graded unstructured 2-D mesh: about 1.0 M vertices,
-2.0 M triangles, density proportional to 1/(r + 0.01) + 1 towards (0, 0),
-Delaunay, min angle > 20 degrees. Coefficient exp(g) with g ~ N(0, 0.5^2) per
-element, f ~ U[-1, 1] per unknown, homogeneous Dirichlet data. A step is one
-full solve, from f resident in HBM to u resident in HBM, stopping at
-||r|| <= 1e-8 ||f||. Both precisions run: the FP64 solve (`value`) and the
-FP32-preconditioner solve (`mixed`).
+Headline workload: 256 independent jittered square meshes of the unit square, sides drawn
+uniformly from 32..512 (22.3 M unknowns in all), 4 right-hand sides each, f ~ U[-1, 1],
+kappa = 1, homogeneous Dirichlet data, solved together by the batched engine. A step is one
+batched solve of all 1024 systems, from F resident in HBM to U resident in HBM, every system
+stopping at ||r|| <= 1e-8 ||f||. `value` is the FP64 solve; `mixed` the FP32-preconditioner
+solve inside FP64 CG.
 
-Prints one JSON line. `roofline` is for the dominant kernel of the solve,
-timed with HIP events inside the library on torch's stream.
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same family
-on the host cores.
+Beside it: the graded unstructured 2-D mesh (1.0 M unknowns), the 3-D Kuhn cube (2.0 M
+unknowns), the adjoint gradient (0.52 M unknowns) and a general-domain annulus, each with its
+own figures; `roofline` is for the dominant kernel of the headline solve (the batched
+Gauss-Seidel colour pass), timed per launch with HIP events inside the library on torch's
+stream; the graded and cube workloads carry their own roofline entries. `cpu_baseline` times
+the FP64 oracle on a bounded sample of the headline's meshes on the host cores.
 """
 from __future__ import annotations
 
@@ -48,28 +49,32 @@ def load_workload(scale: float):
     return out
 
 
-def counter_record():
-    """The committed hardware-counter record (HBM bytes per colour-pass launch and per B_co
-    application), if the kernel code has not changed since the counters were taken (else {})."""
-    from paper_1410_2153_amd.counters import source_key
-    path = os.path.join(ROOT, "profiles", "traffic_k_sell_gs.json")
+def counter_record(workload: str):
+    """The committed hardware-counter record of a workload (HBM bytes per launch of its dominant
+    kernel and per B_co application), if that kernel's code has not changed since the counters
+    were taken (else {})."""
+    from paper_1410_2153_amd.counters import WORKLOADS, _srcs, source_key
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return {}
-    return rec if rec.get("kernel_code_key") == source_key() else {}
+    return rec if rec.get("kernel_code_key") == source_key(_srcs(*WORKLOADS[workload]["sources"])) else {}
 
 
-def cpu_baseline(budget_s: float = 20.0):
-    """Oracle solve phase on a bounded sample (graded family, 20k vertices), one thread (BLAS
-    thread pools limited to 1 for the timed region)."""
+def cpu_baseline(budget_s: float = 20.0, n_meshes: int = 256):
+    """Oracle solve phase on a bounded sample of the headline workload: the smallest meshes of the
+    256-mesh batch (their 4 right-hand sides each), FP64 PCG to 1e-8, one thread (BLAS thread
+    pools limited to 1 for the timed region), repeated until about `budget_s` seconds."""
     from threadpoolctl import threadpool_limits
 
     import workloads as W
     from oracle.hierarchy import Hierarchy
-    c = W.make_config(1, scale=0.02)
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
-    f = c["f_vertex"][H.dofs]
+    sides = W.rng(3, W.S_SIDES, 0).integers(32, 512 + 1, n_meshes)
+    order = np.argsort(sides, kind="stable")[:4]
+    ms = W.batched_config(n_meshes=n_meshes)
+    sample = [ms[int(m)] for m in order]
+    hs = [Hierarchy(m["coords"], m["elems"], m["kappa"]) for m in sample]
     model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -78,23 +83,32 @@ def cpu_baseline(budget_s: float = 20.0):
                 break
     except OSError:
         pass
+    dofs = 0
     with threadpool_limits(limits=1):
-        H.solve(f, 1e-8)  # warm-up (builds the per-colour slices)
+        for H, m in zip(hs, sample):
+            H.solve(m["f_vertex"][0, H.dofs], 1e-8)  # warm-up (builds the per-colour slices)
         t0 = time.perf_counter()
         reps = 0
         while True:
-            H.solve(f, 1e-8)
+            for H, m in zip(hs, sample):
+                for r in range(4):
+                    H.solve(m["f_vertex"][r, H.dofs], 1e-8)
+                    dofs += H.n
             reps += 1
             if time.perf_counter() - t0 > budget_s:
                 break
         dt = time.perf_counter() - t0
-    return dict(value=H.n * reps / dt, unit="DOF-solves/s", cores=1, kind="oracle", cpu_model=model,
-                sample=f"graded mesh {len(c['coords'])} vertices ({H.n} unknowns), FP64 oracle PCG to 1e-8, "
-                       f"{reps} solves in {dt:.1f} s, 1 thread of {len(os.sched_getaffinity(0))}")
+    return dict(value=dofs / dt, unit="DOF-solves/s", cores=1, kind="oracle", cpu_model=model,
+                sample=f"the {len(hs)} smallest meshes of the 256-mesh batch (sides "
+                       f"{[int(sides[m]) for m in order]}, {sum(H.n for H in hs)} unknowns) x 4 right-hand sides, "
+                       f"FP64 oracle PCG to 1e-8, {reps} rounds in {dt:.1f} s, 1 thread of "
+                       f"{len(os.sched_getaffinity(0))}")
 
 
-def batched(n_meshes: int, steps: int):
-    """Batched workload: n_meshes jittered squares, sides ~ U{32..512}, 4 right-hand sides each."""
+def batched(n_meshes: int, steps: int, warmup: int, kernel_timing: bool = True, autotune: int = 1):
+    """The batched workload: n_meshes jittered squares, sides ~ U{32..512}, 4 right-hand sides each,
+    all (mesh, rhs) systems solved together. A step is one batched solve, F resident in HBM to U
+    resident in HBM, every system to ||r|| <= 1e-8 ||f||."""
     import torch
 
     import paper_1410_2153_amd as A
@@ -103,7 +117,8 @@ def batched(n_meshes: int, steps: int):
     ms = W.batched_config(n_meshes=n_meshes)
     log(f"batched: generated {n_meshes} meshes in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    B = A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in ms], precision=A.PREC_FP64)
+    B = A.BatchSolver([(m["coords"], m["elems"], m["kappa"]) for m in ms], precision=A.PREC_FP64,
+                      autotune=autotune)
     t_setup = time.perf_counter() - t0
     log(f"batched: setup {t_setup:.1f} s, {B.n_total} unknowns")
     # right-hand sides per unknown, [mesh][rhs][unknown]
@@ -112,28 +127,43 @@ def batched(n_meshes: int, steps: int):
         bnd = W.boundary_vertices(mesh["coords"])
         F.append(mesh["f_vertex"][:, ~bnd].ravel())
     F = torch.from_numpy(np.concatenate(F)).cuda()
-    res = {"workload": f"{n_meshes} jittered square meshes, side ~ U{{32..512}}, 4 right-hand sides, "
-                       f"{B.n_total} unknowns", "unknowns": B.n_total, "setup_s": t_setup}
+    sides = [int(m["n"]) for m in ms]
+    res = {"workload": f"{n_meshes} jittered square meshes, side ~ U{{32..512}}, 4 right-hand sides each, "
+                       f"{B.n_total} unknowns, kappa=1, f~U[-1,1], every system PCG to 1e-8 from u0=0",
+           "meshes": n_meshes, "rhs": 4, "unknowns": B.n_total, "sides_min_max": [min(sides), max(sides)],
+           "setup_s": t_setup}
+    U = torch.empty_like(F)
     for name, prec in (("fp64", A.PREC_FP64), ("mixed", A.PREC_MIXED)):
         B.set_precision(prec)
-        U, its, tr = B.solve(F, 4, 1e-8)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(max(warmup, 1)):
             U, its, tr = B.solve(F, 4, 1e-8, out=U)
         torch.cuda.synchronize()
+        per = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            U, its, tr = B.solve(F, 4, 1e-8, out=U)   # returns once U is in device memory
+            per.append((time.perf_counter() - t1) * 1e3)
+        torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        res[name] = {"value": B.n_total * 4 / dt, "ms_per_step": dt * 1e3, "max_iterations": int(its.max()),
-                     "max_true_rel_residual": float(tr.max())}
+        res[name] = {"value": B.n_total * 4 / dt, "ms_per_step": dt * 1e3, "ms_per_step_median": float(np.median(per)),
+                     "max_iterations": int(its.max()), "max_true_rel_residual": float(tr.max())}
         log(f"batched {name}: {dt * 1e3:.1f} ms per batch ({B.n_total * 4 / dt:.3e} DOF-solves/s), "
             f"iterations <= {its.max()}")
-    ms_b, by_b = B.time_preconditioner(4, reps=5, precision=A.PREC_FP64)
-    res["preconditioner_fp64_4rhs"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6}
+    B.set_precision(A.PREC_FP64)
+    if kernel_timing:
+        vc = {}
+        for key, prec in (("fp64", A.PREC_FP64), ("fp32", A.PREC_MIXED)):
+            m_b, b_b = B.time_kernel(0, 4, reps=20, precision=prec)
+            vc[key] = {"ms": m_b, "model_bytes": b_b, "GBs": b_b / m_b / 1e6, "frac_of_peak": b_b / m_b / 1e6 / HBM_PEAK_GBS}
+        res["vcycle_4rhs"] = vc
+        ms_gs, by_gs = B.time_kernel(1, 4, reps=3, precision=A.PREC_FP64)
+        res["gs_pass"] = {"ms_per_launch": ms_gs, "bytes_per_launch": by_gs}
     shapes = B.tuned_shapes(4, A.PREC_FP64)
     res["tuned_launch_shapes_fp64_4rhs"] = {f"{t}x{'xcd' if x else 'rr'}": int(((shapes[:, 0] == t) & (shapes[:, 1] == x)).sum())
                                             for t, x in sorted(set(map(tuple, shapes.tolist())))}
     del B
-    # same systems solved one at a time with the single-mesh engine, on a sample of meshes
+    # the same systems solved one at a time with the single-mesh engine, on a sample of meshes
     sample = list(range(0, n_meshes, max(1, n_meshes // 16)))
     tot_dofs, tot_t = 0, 0.0
     for m in sample:
@@ -155,7 +185,7 @@ def batched(n_meshes: int, steps: int):
     return res
 
 
-def cube3d(steps: int, colouring: int = 2):
+def cube3d(steps: int, colouring: int = 2, kernel_timing: bool = True):
     """3-D workload: 128^3 cubes x 6 Kuhn tetrahedra, jittered, kappa in {1, 10} on an 8^3 checkerboard."""
     import torch
 
@@ -179,8 +209,19 @@ def cube3d(steps: int, colouring: int = 2):
         dt = (time.perf_counter() - t) / steps
         res[name] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr}
         log(f"cube3d {name}: {dt * 1e3:.2f} ms/solve, {it} iterations ({S.n / dt:.3e} DOF-solves/s)")
-    ms_b, by_b = S.time_kernel(2, reps=20, precision=A.PREC_FP64)
-    res["preconditioner_fp64"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6}
+    if kernel_timing:
+        ms_b, by_b = S.time_kernel(2, reps=20, precision=A.PREC_FP64)
+        res["preconditioner_fp64"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6,
+                                      "frac_of_peak": by_b / ms_b / 1e6 / HBM_PEAK_GBS}
+        ms_b, by_b = S.time_kernel(2, reps=20, precision=A.PREC_MIXED)
+        res["preconditioner_fp32"] = {"ms": ms_b, "model_bytes": by_b, "GBs": by_b / ms_b / 1e6,
+                                      "frac_of_peak": by_b / ms_b / 1e6 / HBM_PEAK_GBS}
+        ms_gs, by_gs = S.time_kernel(4, reps=10, precision=A.PREC_FP64)
+        rec = counter_record("cube2M")
+        res["roofline"] = {"bound": "hbm", "kernel": "asmg::k_sell<0, double> (Gauss-Seidel colour pass, sliced ELL)",
+                           "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": rec.get("traffic_bytes_per_launch"),
+                           "bytes_per_launch": by_gs, "ms_per_launch": ms_gs}
     return res
 
 
@@ -287,46 +328,13 @@ def adjoint(steps: int, colouring: int = 2):
                     "+ element kernel, through the torch.autograd.Function"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload (0 = skip)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D and adjoint workloads")
-    ap.add_argument("--only", choices=["batched", "cube3d", "adjoint", "annulus"], default=None,
-                    help="run only this secondary workload and print its record (for profiling it alone)")
-    ap.add_argument("--no-kernel-timing", action="store_true",
-                    help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
-    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
-                    help="0: fixed default launch shapes (hardware-counter runs, which would otherwise "
-                         "also count the autotuner's trial launches)")
-    ap.add_argument("--colouring", type=int, default=2,
-                    help="Gauss-Seidel colour order of the single-mesh solves: 0 natural, 1 hash, 2 smallest-last")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 512 MiB device copy (reference dispatch for HBM counter scaling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def graded(args):
+    """The graded unstructured 2-D mesh (1.0 M unknowns): FP64 and mixed solves, B_co and kernel
+    timings with its own roofline entry, local smoothing, the nested start and the device setup."""
     import torch
 
     import paper_1410_2153_amd as A
     dev = torch.device("cuda:0")
-    if args.only == "batched":
-        print(json.dumps({"batched": batched(args.batch_meshes or 256, args.steps)}))
-        return
-    if args.only == "cube3d":
-        print(json.dumps({"cube3d": cube3d(args.steps, args.colouring)}))
-        return
-    if args.only == "adjoint":
-        print(json.dumps({"adjoint": adjoint(args.steps, args.colouring)}))
-        return
-    if args.only == "annulus":
-        print(json.dumps({"annulus": annulus(args.steps, args.colouring)}))
-        return
     t0 = time.perf_counter()
     c = load_workload(args.scale)
     log(f"workload: {len(c['coords'])} vertices, {len(c['elems'])} triangles ({time.perf_counter() - t0:.1f} s)")
@@ -380,7 +388,7 @@ def main():
         ms_mv, by_mv = S64.time_kernel(0, reps=50)
         ms_b64, by_b64 = S64.time_kernel(2, reps=20, precision=A.PREC_FP64)
         ms_b32, by_b32 = S64.time_kernel(2, reps=20, precision=A.PREC_MIXED)
-    crec = counter_record()
+    crec = counter_record("graded1M")
     roof = {"bound": "hbm", "kernel": "asmg::k_sell<0, double> (Gauss-Seidel colour pass, sliced ELL)",
             "achieved": by_gs / ms_gs / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by_gs / ms_gs / 1e6 / HBM_PEAK_GBS, "traffic": crec.get("traffic_bytes_per_launch"),
@@ -397,16 +405,12 @@ def main():
             "abi_matvec_csr_fp64": {"kernel": "asmg::k_matvec (CSR, asmg_matvec_device only)",
                                     "ms": ms_mv, "model_bytes": by_mv, "GBs": by_mv / ms_mv / 1e6}}
     out = {
-        "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",
-        "value": n * args.steps / dt64, "unit": "DOF-solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "ms_per_step_median": step_ms["fp64"],
-        "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"graded 2-D Delaunay mesh, {len(c['coords'])} vertices, {len(c['elems'])} "
-                               f"triangles, kappa=exp(N(0,0.5^2)), f~U[-1,1], PCG to 1e-8 from u0=0",
-                   "unknowns": n, "iterations_fp64": its64[-1], "setup_s": t_setup, "J": info["J"],
-                   "lc": info["lc"], "colouring": ["natural", "hash", "smallest-last"][args.colouring],
-                   "colours_fine": info["n_colours_fine"]},
+        "workload": f"graded 2-D Delaunay mesh, {len(c['coords'])} vertices, {len(c['elems'])} "
+                    f"triangles, kappa=exp(N(0,0.5^2)), f~U[-1,1], PCG to 1e-8 from u0=0",
+        "unknowns": n, "setup_s": t_setup, "J": info["J"], "lc": info["lc"],
+        "colouring": ["natural", "hash", "smallest-last"][args.colouring], "colours_fine": info["n_colours_fine"],
+        "fp64": {"value": n * args.steps / dt64, "ms_per_step": dt64 / args.steps * 1e3,
+                 "ms_per_step_median": step_ms["fp64"], "iterations": its64[-1], "true_rel_residual": tr64},
         "mixed": {"value": n * args.steps / dt32, "ms_per_step": dt32 / args.steps * 1e3,
                   "ms_per_step_median": step_ms["mixed"],
                   "iterations": its32[-1], "true_rel_residual": tr32, "rel_diff_vs_fp64": diff},
@@ -463,6 +467,38 @@ def main():
             f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); total {t_setup:.1f} -> {t_setup_d:.1f} s")
         del SD
         torch.cuda.synchronize()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0, help="size of the graded mesh (1.0 = 1.0 M vertices)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the headline batched workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline: skip the graded, 3-D, adjoint and annulus workloads")
+    ap.add_argument("--only", choices=["batched", "graded", "cube3d", "adjoint", "annulus"], default=None,
+                    help="run only this workload and print its record (for profiling it alone)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="skip the per-kernel HIP-event measurements (for hardware-counter runs)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="0: fixed default launch shapes (hardware-counter runs, which would otherwise "
+                         "also count the autotuner's trial launches)")
+    ap.add_argument("--colouring", type=int, default=2,
+                    help="Gauss-Seidel colour order of the single-mesh solves: 0 natural, 1 hash, 2 smallest-last")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference dispatch for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1410_2153_amd as A  # noqa: F401  (fails loudly if the library is not built)
+    dev = torch.device("cuda:0")
     if args.copy_calibration:
         x = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
         y = torch.empty_like(x)
@@ -470,15 +506,61 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if args.batch_meshes > 0:
-        out["batched"] = batched(args.batch_meshes, args.steps)
+    kt = not args.no_kernel_timing
+    if args.only == "batched":
+        print(json.dumps({"batched": batched(args.batch_meshes, args.steps, args.warmup, kt, args.autotune)}))
+        return
+    if args.only == "graded":
+        print(json.dumps({"graded": graded(args)}))
+        return
+    if args.only == "cube3d":
+        print(json.dumps({"cube3d": cube3d(args.steps, args.colouring, kt)}))
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint(args.steps, args.colouring)}))
+        return
+    if args.only == "annulus":
+        print(json.dumps({"annulus": annulus(args.steps, args.colouring)}))
+        return
+
+    # headline: the batched workload, all 256 x 4 systems per step
+    b = batched(args.batch_meshes, args.steps, args.warmup, kt, args.autotune)
+    crec = counter_record("batched256x4")
+    bco = crec.get("bco_per_application", {})
+    gs = b.get("gs_pass", {"ms_per_launch": float("nan"), "bytes_per_launch": float("nan")})
+    vc = b.get("vcycle_4rhs", {})
+    for key in ("fp64", "fp32"):
+        if key in vc:
+            vc[key]["counted_hbm_bytes"] = bco.get(key, {}).get("traffic_bytes")
+    ach = gs["bytes_per_launch"] / gs["ms_per_launch"] / 1e6
+    out = {
+        "metric": "DOF-solves/sec to 1e-8 rel. residual + V-cycle HBM GB/s, FP64 vs mixed",
+        "value": b["fp64"]["value"], "unit": "DOF-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": b["fp64"]["ms_per_step"],
+        "ms_per_step_median": b["fp64"]["ms_per_step_median"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": b["workload"], "meshes": b["meshes"], "rhs": b["rhs"], "unknowns": b["unknowns"],
+                   "sides_min_max": b["sides_min_max"], "max_iterations_fp64": b["fp64"]["max_iterations"],
+                   "max_true_rel_residual_fp64": b["fp64"]["max_true_rel_residual"], "setup_s": b["setup_s"]},
+        "mixed": b["mixed"],
+        "vcycle": vc,
+        "roofline": {"bound": "hbm", "kernel": "asmg::kb_sell<0, 4, double> (batched Gauss-Seidel colour pass, "
+                                               "sliced ELL, 4 interleaved right-hand sides)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": crec.get("traffic_bytes_per_launch"), "bytes_per_launch": gs["bytes_per_launch"],
+                     "ms_per_launch": gs["ms_per_launch"]},
+        "single_solves_fp64_sample": b["single_solves_fp64_sample"],
+        "tuned_launch_shapes_fp64_4rhs": b["tuned_launch_shapes_fp64_4rhs"],
+    }
+    torch.cuda.synchronize()
     if not args.no_extra:
-        out["cube3d"] = cube3d(args.steps, args.colouring)
+        out["graded"] = graded(args)
+        out["cube3d"] = cube3d(args.steps, args.colouring, kt)
         out["adjoint"] = adjoint(args.steps, args.colouring)
         out["annulus"] = annulus(args.steps, args.colouring)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(n_meshes=args.batch_meshes)
     print(json.dumps(out))
 
 

@@ -315,6 +315,20 @@ int asmg_solve_batch_device(asmg_handle h, int n_rhs, const double *d_F, double 
 int asmg_time_batch(asmg_handle h, int n_rhs, int reps, int precision, void *stream, double *ms,
                     double *bytes);
 
+/*
+ * Kernel timing of the batched engine on `stream`, with algorithmic bytes (each matrix entry,
+ * row index and vector entry an operation needs, once):
+ *   which 0: one batched B_co application captured in a hipGraph as the solve runs it; *ms is the
+ *            median over `reps` replays, *bytes the application's bytes;
+ *   which 1: the Gauss-Seidel colour-pass kernel (sliced ELL over n_rhs interleaved right-hand
+ *            sides): inside `reps` B_co applications every colour pass is launched once with a
+ *            pair of HIP events stamped with its own start and end; *ms and *bytes are the mean
+ *            per launch (a pass: its rows' matrix entries, one row index per row, b, 1/diag and
+ *            the x write of its rows, and each distinct gathered x entry, n_rhs values each).
+ */
+int asmg_time_batch_kernel(asmg_handle h, int which, int n_rhs, int reps, int precision, void *stream, double *ms,
+                           double *bytes);
+
 /* Free the handle and all its device memory. NULL is ignored. */
 void asmg_destroy(asmg_handle h);
 

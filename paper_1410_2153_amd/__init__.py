@@ -32,6 +32,7 @@ EXPORTED = [
     "asmg_element_gradient_device", "asmg_time_kernel", "asmg_export", "asmg_destroy", "asmg_last_error",
     "asmg_setup_batch", "asmg_solve_batch_device", "asmg_time_batch",
     "asmg_set_log_coefficient_device", "asmg_adjoint_gradient_device", "asmg_solve_device_noalloc",
+    "asmg_time_batch_kernel",
 ]
 
 
@@ -82,6 +83,8 @@ def _load():
     lib.asmg_solve_batch_device.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P, P, P, P]
     lib.asmg_time_batch.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
+    lib.asmg_time_batch_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.asmg_destroy.argtypes = [P]
     lib.asmg_destroy.restype = None
     return lib
@@ -385,6 +388,16 @@ class BatchSolver:
         tr = np.zeros(self.n_meshes * n_rhs)
         _check(lib.asmg_solve_batch_device(self.h, n_rhs, _tptr(F), tol, _tptr(U), _ptr(it), _ptr(tr), _stream()))
         return U, it.reshape(self.n_meshes, n_rhs), tr.reshape(self.n_meshes, n_rhs)
+
+    def time_kernel(self, which, n_rhs, reps=10, precision=None):
+        """asmg_time_batch_kernel: 0 = B_co as graph replays (median ms, bytes per application),
+        1 = Gauss-Seidel colour passes timed per launch (mean ms and bytes per launch)."""
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        prec = self.precision if precision is None else precision
+        _check(lib.asmg_time_batch_kernel(self.h, which, n_rhs, reps, prec, _stream(), ctypes.byref(ms),
+                                          ctypes.byref(by)))
+        return ms.value, by.value
 
     def time_preconditioner(self, n_rhs, reps=10, precision=None):
         ms = ctypes.c_double()

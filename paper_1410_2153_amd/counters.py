@@ -1,21 +1,25 @@
-"""Profile summaries of the Gauss-Seidel colour pass from rocprofv3 output.
+"""Profile summaries of the solver's kernels from rocprofv3 output.
 
 Usage:
 
-    python -m paper_1410_2153_amd.counters traffic <fetch counter_collection.csv> \
+    python -m paper_1410_2153_amd.counters traffic <workload> <fetch counter_collection.csv> \
         <write counter_collection.csv> [out.json]
+    python -m paper_1410_2153_amd.counters kernels <fetch csv> <write csv> [top]
     python -m paper_1410_2153_amd.counters stats <kernel_stats.csv> [top]
     python -m paper_1410_2153_amd.counters phases <kernel_trace.csv> [kernel]
     python -m paper_1410_2153_amd.counters markers <marker_api_trace.csv>
 
-traffic: HBM bytes per launch from the two `rocprofv3 --pmc` runs of bench.py named in the
-output record. FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch. Each is scaled by the
-ratio of the bytes a plain device copy moves to what the same counter reads for that copy: the
-bench's `--copy-calibration` runs a 512 MiB copy, whose dispatch is the largest
-`__amd_rocclr_copyBuffer` in the run. The counter runs use `--autotune 0` (every launch site in
-the default shape), so that the autotuner's trial launches in other shapes are not averaged in.
-The record is keyed by the SHA-256 of the kernel sources with comments and whitespace removed
-(`source_key`), so bench.py reports it only for the kernel code it was measured on.
+traffic: HBM bytes per launch of a workload's dominant kernel (WORKLOADS: the graded 2-D mesh,
+the 3-D Kuhn cube, the batched 256-mesh workload) from two `rocprofv3 --pmc` runs of bench.py,
+the commands named in the output record. FETCH_SIZE and WRITE_SIZE are read in KiB per
+dispatch. Each is scaled by the ratio of the bytes a plain device copy moves to what the same
+counter reads for that copy: the bench's `--copy-calibration` runs a 512 MiB copy, whose
+dispatch is the largest `__amd_rocclr_copyBuffer` in the run. The counter runs use
+`--autotune 0` (every launch site in the default shape), so that the autotuner's trial launches
+in other shapes are not averaged in. The record is keyed by the SHA-256 of the kernel's sources
+with comments and whitespace removed (`source_key`), so bench.py reports it only for the kernel
+code it was measured on. It also gives the HBM bytes of one whole B_co application (every
+V-cycle kernel of one precision, per application).
 
 stats: markdown table of a `--stats` kernel summary.
 
@@ -38,8 +42,27 @@ import sys
 
 KERNEL = "asmg::k_sell<0, double>"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1410_2153_amd", "csrc", f) for f in ("device.hip", "common.hpp")]
 COPY_BYTES = 64 * 2 ** 20 * 8
+
+
+def _srcs(*names):
+    return [os.path.join(ROOT, "paper_1410_2153_amd", "csrc", f) for f in names]
+
+
+KERNEL_SRCS = _srcs("device.hip", "common.hpp")
+
+# workload -> dominant kernel, the sources that define it, the bench selection of the counter runs
+WORKLOADS = {
+    "graded1M": dict(kernel="asmg::k_sell<0, double>", sources=("device.hip", "common.hpp"),
+                     bench="--only graded --no-extra", engine="single",
+                     desc="graded 2-D Delaunay mesh, 1002722 vertices, FP64 and mixed solves"),
+    "cube2M": dict(kernel="asmg::k_sell<0, double>", sources=("device.hip", "common.hpp"),
+                   bench="--only cube3d", engine="single",
+                   desc="Kuhn cube 128^3 x 6 tetrahedra, 2048383 unknowns, FP64 and mixed solves"),
+    "batched256x4": dict(kernel="asmg::kb_sell<0, 4, double>", sources=("batch.hip", "common.hpp"),
+                         bench="--only batched", engine="batch",
+                         desc="256 jittered squares (sides 32..512) x 4 right-hand sides, FP64 and mixed solves"),
+}
 
 
 def source_key(paths=KERNEL_SRCS):
@@ -57,43 +80,55 @@ def _name(kernel_name):
     return kernel_name.split("(")[0].replace("void ", "")
 
 
-def _per_dispatch(path, counter):
+def _per_dispatch(path, counter, kernel):
     vals, copies = [], []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         name = _name(r["Kernel_Name"])
         v = float(r["Counter_Value"])
-        if name == KERNEL:
+        if name == kernel:
             vals.append(v)
         elif name.startswith("__amd_rocclr_copyBuffer"):
             copies.append((int(r["Grid_Size"]), v))
     if not vals or not copies:
-        raise SystemExit(f"{path}: no {KERNEL} or copy dispatches with {counter}")
+        raise SystemExit(f"{path}: no {kernel} or copy dispatches with {counter}")
     copy = max(copies)[1]  # the 512 MiB calibration copy has the largest grid
     return sum(vals) / len(vals), len(vals), copy
 
 
-def _bco_kernel(name, prec):
+def _targs(name):
+    base, _, args = name.partition("<")
+    return base, [a for a in args.rstrip(">").replace(" ", "").split(",") if a]
+
+
+def _bco_kernel(name, prec, engine="single"):
     """True for the kernels of one B_co application in precision prec ("double" or "float"):
-    colour passes, residuals, transfers, the bottom GEMV and a first pass run on its own."""
+    colour passes, residuals, transfers, bottom GEMVs and a first pass run on its own."""
     if not name.startswith("asmg::"):
         return False
-    k = name[len("asmg::"):]
-    if k == "k_gs_first_cvt":
-        return prec == "float"
-    # position of the value type among the template arguments
-    pos = {"k_sell": 1, "k_sell_spmv": 2, "k_gemv": 0, "k_gs_first": 0}
-    base, _, args = k.partition("<")
-    if base not in pos or not args:
-        return False
-    targs = args.rstrip(">").replace(" ", "").split(",")
-    return len(targs) > pos[base] and targs[pos[base]] == prec
+    base, targs = _targs(name[len("asmg::"):])
+    if engine == "batch":
+        if base == "kb_first_cvt":
+            return prec == "float"
+        pos = {"kb_sell": 2, "kb_sell_spmv": 3, "kb_gemv": 1, "kb_first": 1}
+    else:
+        if base == "k_gs_first_cvt":
+            return prec == "float"
+        pos = {"k_sell": 1, "k_sell_spmv": 2, "k_gemv": 0, "k_gs_first": 0}
+    return base in pos and len(targs) > pos[base] and targs[pos[base]] == prec
 
 
-def bco_traffic(fetch_csv, write_csv, f_scale, w_scale):
-    """HBM bytes per B_co application from the counter runs (FP64 and FP32 V-cycle kernels; the
-    number of applications is the number of bottom GEMV dispatches in that precision)."""
+def _bco_application(name, prec, engine):
+    """One dispatch per B_co application: the bottom GEMV (single mesh) or r.z (batched)."""
+    if engine == "batch":
+        base, targs = _targs(name[len("asmg::"):]) if name.startswith("asmg::") else ("", [])
+        return base == "kb_cg_rz" and len(targs) > 1 and targs[1] == prec
+    return name == f"asmg::k_gemv<{prec}>"
+
+
+def bco_traffic(fetch_csv, write_csv, f_scale, w_scale, engine="single"):
+    """HBM bytes per B_co application from the counter runs (FP64 and FP32 V-cycle kernels)."""
     out = {}
     for prec, key in (("double", "fp64"), ("float", "fp32")):
         tot = {}
@@ -103,9 +138,9 @@ def bco_traffic(fetch_csv, write_csv, f_scale, w_scale):
                 if r["Counter_Name"] != counter:
                     continue
                 name = _name(r["Kernel_Name"])
-                if _bco_kernel(name, prec):
+                if _bco_kernel(name, prec, engine):
                     s += float(r["Counter_Value"]) * 1024.0 * scale
-                if name == f"asmg::k_gemv<{prec}>":
+                if _bco_application(name, prec, engine):
                     napp += 1
             tot[counter] = (s, napp)
         napp = tot["FETCH_SIZE"][1]
@@ -115,21 +150,24 @@ def bco_traffic(fetch_csv, write_csv, f_scale, w_scale):
     return out
 
 
-def record(fetch_csv, write_csv):
-    f_kib, n, f_copy = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    w_kib, n2, w_copy = _per_dispatch(write_csv, "WRITE_SIZE")
+def record(workload, fetch_csv, write_csv):
+    wl = WORKLOADS[workload]
+    kernel = wl["kernel"]
+    f_kib, n, f_copy = _per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
+    w_kib, n2, w_copy = _per_dispatch(write_csv, "WRITE_SIZE", kernel)
     f_scale = COPY_BYTES / (f_copy * 1024.0)
     w_scale = COPY_BYTES / (w_copy * 1024.0)
     fb = f_kib * 1024.0 * f_scale
     wb = w_kib * 1024.0 * w_scale
-    cmd = ("cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <out>/pmc_{d} -o run -- python3 <repo>/bench.py "
-           "--steps 1 --warmup 0 --no-cpu --batch-meshes 0 --no-extra --no-kernel-timing --copy-calibration "
-           "--autotune 0")
+    cmd = ("cd /tmp && timeout -s KILL 600 rocprofv3 --pmc {c} --output-format csv -d <out>/pmc_{d} -o run -- "
+           "python3 <repo>/bench.py --steps 1 --warmup 0 " + wl["bench"] +
+           " --no-kernel-timing --copy-calibration --autotune 0")
     return {
-        "kernel": KERNEL,
-        "workload": "graded 2-D Delaunay mesh, 1002722 vertices, FP64 solve",
+        "kernel": kernel,
+        "workload": wl["desc"],
         "launch_shape": "256 threads per block, XCD-contiguous block order at every launch site",
-        "kernel_code_key": source_key(),
+        "kernel_code_key": source_key(_srcs(*wl["sources"])),
+        "kernel_sources": list(wl["sources"]),
         "dispatches": n,
         "fetch_kib_per_dispatch_raw": f_kib,
         "write_kib_per_dispatch_raw": w_kib,
@@ -141,11 +179,36 @@ def record(fetch_csv, write_csv):
         "fetch_bytes_per_launch": fb,
         "write_bytes_per_launch": wb,
         "traffic_bytes_per_launch": fb + wb,
-        "bco_per_application": bco_traffic(fetch_csv, write_csv, f_scale, w_scale),
+        "bco_per_application": bco_traffic(fetch_csv, write_csv, f_scale, w_scale, wl["engine"]),
         "commands": [cmd.format(c="FETCH_SIZE", d="fetch"), cmd.format(c="WRITE_SIZE", d="write"),
-                     "python -m paper_1410_2153_amd.counters traffic <out>/pmc_fetch/run_counter_collection.csv "
-                     "<out>/pmc_write/run_counter_collection.csv profiles/traffic_k_sell_gs.json"],
+                     f"python -m paper_1410_2153_amd.counters traffic {workload} "
+                     "<out>/pmc_fetch/run_counter_collection.csv <out>/pmc_write/run_counter_collection.csv "
+                     f"profiles/traffic_{workload}.json"],
     }
+
+
+def per_kernel_traffic(fetch_csv, write_csv, top=20):
+    """Markdown table: mean scaled HBM bytes (fetch + write) per dispatch of every kernel."""
+    tabs = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        copies, per = [], collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = _name(r["Kernel_Name"])
+            if name.startswith("__amd_rocclr_copyBuffer"):
+                copies.append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+            else:
+                per[name].append(float(r["Counter_Value"]))
+        scale = COPY_BYTES / (max(copies)[1] * 1024.0)
+        tabs[counter] = {k: (sum(v) / len(v) * 1024.0 * scale, len(v), sum(v) * 1024.0 * scale) for k, v in per.items()}
+    names = sorted(tabs["FETCH_SIZE"], key=lambda k: -tabs["FETCH_SIZE"][k][2])[:top]
+    out = ["| kernel | dispatches | fetch MB/dispatch | write MB/dispatch |", "|---|---:|---:|---:|"]
+    for k in names:
+        f = tabs["FETCH_SIZE"][k]
+        w = tabs["WRITE_SIZE"].get(k, (0.0, 0, 0.0))
+        out.append(f"| `{k}` | {f[1]} | {f[0] / 1e6:.3f} | {w[0] / 1e6:.3f} |")
+    return "\n".join(out)
 
 
 def stats_table(stats_csv, top=25):
@@ -199,11 +262,13 @@ def markers_table(marker_csv):
 
 
 def main(argv):
-    if len(argv) >= 3 and argv[0] == "traffic":
-        out = json.dumps(record(argv[1], argv[2]), indent=1)
-        if len(argv) > 3:
-            open(argv[3], "w").write(out + "\n")
+    if len(argv) >= 4 and argv[0] == "traffic":
+        out = json.dumps(record(argv[1], argv[2], argv[3]), indent=1)
+        if len(argv) > 4:
+            open(argv[4], "w").write(out + "\n")
         print(out)
+    elif len(argv) >= 3 and argv[0] == "kernels":
+        print(per_kernel_traffic(argv[1], argv[2], int(argv[3]) if len(argv) > 3 else 20))
     elif len(argv) >= 2 and argv[0] == "stats":
         print(stats_table(argv[1], int(argv[2]) if len(argv) > 2 else 25))
     elif len(argv) >= 2 and argv[0] == "phases":

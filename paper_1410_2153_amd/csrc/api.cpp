@@ -435,6 +435,15 @@ int asmg_time_batch(asmg_handle H, int n_rhs, int reps, int precision, void *str
   ASMG_TRY({ return batch_device_time(H->bdev, n_rhs, reps, precision, stream, ms, bytes); })
 }
 
+int asmg_time_batch_kernel(asmg_handle H, int which, int n_rhs, int reps, int precision, void *stream, double *ms,
+                           double *bytes) {
+  if (!H || !H->is_batch() || !H->bdev) return set_err(ASMG_EINVAL, "not a device batch handle");
+  if (which < 0 || which > 1 || (n_rhs != 1 && n_rhs != 2 && n_rhs != 4) || reps < 1 || !ms || !bytes ||
+      (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED))
+    return set_err(ASMG_EINVAL, "bad argument");
+  ASMG_TRY({ return batch_device_time_kernel(H->bdev, which, n_rhs, reps, precision, stream, ms, bytes); })
+}
+
 void asmg_destroy(asmg_handle H) {
   if (!H) return;
   if (H->dev) device_destroy(H->dev);

@@ -727,6 +727,7 @@ struct BLevel {
   std::vector<int> mesh; // meshes present; smoothing first
   std::vector<int> off;  // row offset of each present mesh
   BSell sell;            // off-diagonal part of the smoothing rows; group c = colour c of every mesh
+  std::vector<int64_t> cnnz, crows, ucols;  // per colour group: nonzeros, rows, distinct columns gathered
   double *dg64 = nullptr, *id64 = nullptr, *id0_64 = nullptr;  // a_ii, 1/a_ii, 1/a_ii on colour 0 else 0
   float *dg32 = nullptr, *id32 = nullptr, *id0_32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
@@ -784,6 +785,11 @@ struct BatchDevice {
   int tune_k = 0, tune_live = 0;       // autotuner: candidate under trial, sites seen
   std::vector<hipEvent_t> tune_ev;     // two events per launch site
   std::vector<uint8_t> tune_has;       // site launched something
+  // per-launch timing of the Gauss-Seidel colour passes (batch_device_time_kernel)
+  bool probe = false;
+  std::vector<hipEvent_t> probe_ev;    // pairs (start, stop)
+  std::vector<double> probe_bytes;
+  size_t probe_used = 0;
 };
 
 template <class T>
@@ -1046,6 +1052,29 @@ static void upload_diag(BatchDevice *dv, BLevel &L, const std::vector<double> &d
   L.id0_32 = bupload(dv, i032);
 }
 
+// byte-model counts of each row-range group of H: nonzeros, rows, and the distinct columns the
+// group's rows gather (each x entry read once per colour pass)
+static void group_counts(const HMat &H, const Groups &groups, std::vector<int64_t> &cnnz, std::vector<int64_t> &crows,
+                         std::vector<int64_t> &ucols) {
+  const int G = (int)groups.size();
+  cnnz.assign(G, 0);
+  crows.assign(G, 0);
+  ucols.assign(G, 0);
+  std::vector<int> seen(std::max(H.ncols, 1), -1);
+  for (int g = 0; g < G; ++g)
+    for (const auto &rg : groups[g])
+      for (int i = rg.first; i < rg.second; ++i) {
+        ++crows[g];
+        for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+          ++cnnz[g];
+          if (seen[H.ci[p]] != g) {
+            seen[H.ci[p]] = g;
+            ++ucols[g];
+          }
+        }
+      }
+}
+
 BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int ordinal) {
   int count = 0;
   HIPCHECK(hipGetDeviceCount(&count));
@@ -1145,6 +1174,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       std::vector<double> diag;
       std::vector<uint8_t> c0flag;
       BSellHost gs, cg;
+      std::vector<int64_t> cnnz, crows, ucols;  // byte-model counts of every colour group
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
       std::vector<int64_t> moff;
@@ -1179,6 +1209,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
+        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols);
         // CG products: group m = mesh m, whole blocks per mesh
         Groups mg(nm);
         for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
@@ -1222,6 +1253,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
+        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols);
         for (size_t i = 0; i < bottom_m[k].size(); ++i) {
           const int m = bottom_m[k][i];
           const int nc = (int)H[m]->nc;
@@ -1258,6 +1290,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       upload_diag(dv, F, X.diag, X.c0flag);
       alloc_level_vectors(dv, F);
       bsell_upload(dv, X.gs, F.sell);
+      F.cnnz = X.cnnz;
+      F.crows = X.crows;
+      F.ucols = X.ucols;
       bsell_upload(dv, X.cg, dv->cg_sell);
       dv->cg_b0 = bupload(dv, X.cg.block0);
       dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
@@ -1284,6 +1319,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       BLevel &L = dv->aux[k];
       LevelImage &X = aux_img[k];
       bsell_upload(dv, X.gs, L.sell);
+      L.cnnz = X.cnnz;
+      L.crows = X.crows;
+      L.ucols = X.ucols;
       upload_diag(dv, L, X.diag, X.c0flag);
       L.bottom_rows = X.pref.back();
       L.bt_rowpref = bupload(dv, X.pref);
@@ -1371,6 +1409,7 @@ void batch_device_destroy(BatchDevice *dv) {
     for (auto &x : g)
       if (x) (void)hipGraphExecDestroy(x);
   for (hipEvent_t e : dv->tune_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : dv->probe_ev) (void)hipEventDestroy(e);
   if (dv->ev_in) (void)hipEventDestroy(dv->ev_in);
   if (dv->ev_out) (void)hipEventDestroy(dv->ev_out);
   if (dv->stream) (void)hipStreamDestroy(dv->stream);
@@ -1429,14 +1468,28 @@ const float *bid0<float>(const BLevel &L) { return L.id0_32; }
 // that its time is measured inside a whole B_co application (caches as in a solve); otherwise
 // it runs the shape stored for the site (or the default). The tuned kernels have no
 // reductions, so the shape does not change any result.
+// With probe_bytes >= 0 and per-launch timing on, the launch is stamped with the next pair of
+// probe events and counted with that many algorithmic bytes.
 template <class F>
-static void slice_launch(BatchDevice *dv, int nslices, hipStream_t s, F &&launch) {
+static void slice_launch(BatchDevice *dv, int nslices, hipStream_t s, F &&launch, double probe_bytes = -1.0) {
   auto &tab = dv->shape[dv->shape_pi][dv->shape_nr];
   const int site = dv->site++;
   if (nslices <= 0) return;
   auto sh = site < (int)tab.size() ? tab[site] : kShapes[0];
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (dv->tuning) {
+  if (dv->probe && probe_bytes >= 0.0) {
+    if (dv->probe_used + 2 > dv->probe_ev.size()) {
+      hipEvent_t p0, p1;
+      HIPCHECK(hipEventCreate(&p0));
+      HIPCHECK(hipEventCreate(&p1));
+      dv->probe_ev.push_back(p0);
+      dv->probe_ev.push_back(p1);
+    }
+    e0 = dv->probe_ev[dv->probe_used];
+    e1 = dv->probe_ev[dv->probe_used + 1];
+    dv->probe_used += 2;
+    dv->probe_bytes.push_back(probe_bytes);
+  } else if (dv->tuning) {
     while ((int)dv->tune_ev.size() < 2 * (site + 1)) {
       hipEvent_t e;
       HIPCHECK(hipEventCreate(&e));
@@ -1465,10 +1518,18 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   const int C = (int)S.cslice.size() - 1;
   auto pass = [&](int c) {
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
-    slice_launch(dv, s1 - s0, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-      launch_timed((kb_sell<0, NR, T>), slice_blocks(s1 - s0, th), th, s, e0, e1, s0, s1, S.srow,
-                         S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
-    });
+    // algorithmic bytes of the pass: the colour's matrix rows (values, columns, one row index),
+    // b, 1/diag and the x write of its rows, each distinct gathered x entry once
+    const double sz = sizeof(T), rows = (double)L.crows[c];
+    const double by = (double)L.cnnz[c] * (sz + 4) + 4.0 * (rows + 1) + sz * rows * (2.0 * NR + 1) +
+                      sz * NR * (double)L.ucols[c];
+    slice_launch(
+        dv, s1 - s0, s,
+        [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
+          launch_timed((kb_sell<0, NR, T>), slice_blocks(s1 - s0, th), th, s, e0, e1, s0, s1, S.srow, S.soff,
+                       S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+        },
+        by);
   };
   if (forward) {
     int c = 0;
@@ -1817,6 +1878,91 @@ int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void 
   HIPCHECK(hipEventDestroy(e0));
   HIPCHECK(hipEventDestroy(e1));
   return ASMG_OK;
+}
+
+template <int NR>
+static int b_time_kernel_nr(BatchDevice *dv, int which, int reps, bool mixed, hipStream_t s, double *ms,
+                            double *bytes) {
+  auto bco_on = [&](hipStream_t st) {
+    if (mixed)
+      b_apply<NR, float>(dv, dv->f, false, st);
+    else
+      b_apply<NR, double>(dv, dv->f, false, st);
+  };
+  HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)dv->fine.nrows * 4 * sizeof(double), s));
+  b_prepare_r(dv, NR, s);
+  if (which == 1) {
+    // every Gauss-Seidel colour pass inside `reps` B_co applications, each launch stamped with its
+    // own start and end events (one launch per pair: caches as in a solve)
+    bco_on(s);  // warm-up
+    dv->probe = true;
+    dv->probe_used = 0;
+    dv->probe_bytes.clear();
+    try {
+      for (int k = 0; k < reps; ++k) bco_on(s);
+    } catch (...) {
+      dv->probe = false;
+      throw;
+    }
+    dv->probe = false;
+    HIPCHECK(hipStreamSynchronize(s));
+    double tot = 0, by = 0;
+    const size_t nl = dv->probe_used / 2;
+    for (size_t i = 0; i < nl; ++i) {
+      float t = 0;
+      HIPCHECK(hipEventElapsedTime(&t, dv->probe_ev[2 * i], dv->probe_ev[2 * i + 1]));
+      tot += t;
+    }
+    for (double b : dv->probe_bytes) by += b;
+    *ms = nl ? tot / nl : 0.0;
+    *bytes = nl ? by / nl : 0.0;
+    return ASMG_OK;
+  }
+  // which 0: one B_co application captured in a hipGraph as the solve runs it; median over
+  // `reps` replays, each between its own pair of events
+  dv->count_bytes = true;
+  dv->bytes = 0;
+  bco_on(s);
+  dv->count_bytes = false;
+  *bytes = dv->bytes;
+  HIPCHECK(hipStreamSynchronize(s));
+  hipStream_t gs = dv->stream;
+  hipGraph_t g;
+  hipGraphExec_t ge;
+  HIPCHECK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+  bco_on(gs);
+  HIPCHECK(hipStreamEndCapture(gs, &g));
+  HIPCHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  HIPCHECK(hipGraphDestroy(g));
+  HIPCHECK(hipGraphLaunch(ge, gs));  // warm-up
+  const int R = std::max(reps, 1);
+  std::vector<hipEvent_t> ev(2 * R);
+  for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+  for (int k = 0; k < R; ++k) {
+    HIPCHECK(hipEventRecord(ev[2 * k], gs));
+    HIPCHECK(hipGraphLaunch(ge, gs));
+    HIPCHECK(hipEventRecord(ev[2 * k + 1], gs));
+  }
+  HIPCHECK(hipStreamSynchronize(gs));
+  std::vector<float> t(R);
+  for (int k = 0; k < R; ++k) HIPCHECK(hipEventElapsedTime(&t[k], ev[2 * k], ev[2 * k + 1]));
+  for (auto &e : ev) HIPCHECK(hipEventDestroy(e));
+  HIPCHECK(hipGraphExecDestroy(ge));
+  std::sort(t.begin(), t.end());
+  *ms = R % 2 ? (double)t[R / 2] : 0.5 * ((double)t[R / 2 - 1] + (double)t[R / 2]);
+  return ASMG_OK;
+}
+
+int batch_device_time_kernel(BatchDevice *dv, int which, int n_rhs, int reps, int precision, void *stream, double *ms,
+                             double *bytes) {
+  HIPCHECK(hipSetDevice(dv->ordinal));
+  hipStream_t s = (hipStream_t)stream;
+  const bool mixed = precision == ASMG_PREC_MIXED;
+  switch (n_rhs) {
+    case 1: return b_time_kernel_nr<1>(dv, which, reps, mixed, s, ms, bytes);
+    case 2: return b_time_kernel_nr<2>(dv, which, reps, mixed, s, ms, bytes);
+    default: return b_time_kernel_nr<4>(dv, which, reps, mixed, s, ms, bytes);
+  }
 }
 
 int64_t batch_n_total(BatchDevice *dv) { return dv->dof_off.back(); }

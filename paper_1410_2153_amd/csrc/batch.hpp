@@ -17,6 +17,11 @@ void batch_device_set_precision(BatchDevice *dv, int precision);
 int batch_device_solve(BatchDevice *dv, int n_rhs, const double *d_F, double tol, double *d_U, int *iters,
                        double *true_rel, void *stream);
 int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void *stream, double *ms, double *bytes);
+// which 0: one B_co application as a hipGraph, median over `reps` replays, with its algorithmic
+// bytes; which 1: every Gauss-Seidel colour pass inside `reps` applications timed per launch,
+// mean ms and mean algorithmic bytes per launch
+int batch_device_time_kernel(BatchDevice *dv, int which, int n_rhs, int reps, int precision, void *stream, double *ms,
+                             double *bytes);
 int64_t batch_n_total(BatchDevice *dv);
 // launch shapes picked by the autotuner for (NR, precision): threads per block and XCD order of
 // every slice-kernel launch site, flattened pairs (empty before the first solve)

@@ -25,13 +25,14 @@ def test_traffic_record_scales_by_the_copy(tmp_path):
     # the copy moves COPY_BYTES; FETCH_SIZE reading half of it gives factor 2, WRITE_SIZE exact 1
     _pmc(tmp_path / "f.csv", "FETCH_SIZE", [100.0, 300.0], C.COPY_BYTES / 1024 / 2)
     _pmc(tmp_path / "w.csv", "WRITE_SIZE", [10.0, 30.0], C.COPY_BYTES / 1024)
-    rec = C.record(tmp_path / "f.csv", tmp_path / "w.csv")
+    rec = C.record("graded1M", tmp_path / "f.csv", tmp_path / "w.csv")
     assert rec["dispatches"] == 2
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     assert rec["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2)
     assert rec["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
     assert rec["traffic_bytes_per_launch"] == pytest.approx(200.0 * 2048 + 20.0 * 1024)
     assert rec["kernel_code_key"] == C.source_key()
+    assert rec["kernel"] == C.WORKLOADS["graded1M"]["kernel"]
 
 
 def test_bco_kernel_classification():
@@ -43,6 +44,17 @@ def test_bco_kernel_classification():
     assert all(C._bco_kernel(n, "double") and not C._bco_kernel(n, "float") for n in yes64)
     assert all(C._bco_kernel(n, "float") and not C._bco_kernel(n, "double") for n in yes32)
     assert not any(C._bco_kernel(n, p) for n in no for p in ("double", "float"))
+    # the batched engine's kernels
+    b64 = ["asmg::kb_sell<0, 4, double>", "asmg::kb_sell<1, 2, double>", "asmg::kb_sell_spmv<0, 1, 4, double>",
+           "asmg::kb_sell_spmv<1, 0, 1, double>", "asmg::kb_gemv<4, double>", "asmg::kb_first<4, double>"]
+    b32 = [n.replace("double", "float") for n in b64] + ["asmg::kb_first_cvt<4>"]
+    bno = ["asmg::kb_cg_spmv<4>", "asmg::kb_cg_rz<4, double>", "asmg::k_sell<0, double>", "asmg::kb_cg_axpy<4, float>"]
+    assert all(C._bco_kernel(n, "double", "batch") and not C._bco_kernel(n, "float", "batch") for n in b64)
+    assert all(C._bco_kernel(n, "float", "batch") and not C._bco_kernel(n, "double", "batch") for n in b32)
+    assert not any(C._bco_kernel(n, p, "batch") for n in bno for p in ("double", "float"))
+    assert C._bco_application("asmg::kb_cg_rz<4, double>", "double", "batch")
+    assert not C._bco_application("asmg::kb_cg_rz<4, float>", "double", "batch")
+    assert C._bco_application("asmg::k_gemv<float>", "float", "single")
 
 
 def test_source_key_ignores_comments_and_whitespace(tmp_path):
