@@ -160,8 +160,14 @@ def batched(n_meshes: int, steps: int, warmup: int, kernel_timing: bool = True, 
         ms_gs, by_gs = B.time_kernel(1, 4, reps=3, precision=A.PREC_FP64)
         res["gs_pass"] = {"ms_per_launch": ms_gs, "bytes_per_launch": by_gs}
     shapes = B.tuned_shapes(4, A.PREC_FP64)
-    res["tuned_launch_shapes_fp64_4rhs"] = {f"{t}x{'xcd' if x else 'rr'}": int(((shapes[:, 0] == t) & (shapes[:, 1] == x)).sum())
-                                            for t, x in sorted(set(map(tuple, shapes.tolist())))}
+    res["tuned_launch_shapes_fp64_4rhs"] = {
+        f"{t}x{'xcd' if x else 'rr'}/var{o}": int(((shapes[:, 0] == t) & (shapes[:, 1] == x) & (shapes[:, 2] == o)).sum())
+        for t, x, o in sorted(set(map(tuple, shapes.tolist())))}
+    tt = B.tune_times(4, A.PREC_FP64)
+    if len(tt):
+        # per candidate: the sum over launch sites of its best time, against the default's
+        res["tune_sum_ms_fp64_4rhs"] = {f"{t}x{'xcd' if x else 'rr'}/var{o}": float(tt[:, k][tt[:, k] > 0].sum())
+                                        for k, (t, x, o) in enumerate(A.SHAPES)}
     del B
     # the same systems solved one at a time with the single-mesh engine, on a sample of meshes
     sample = list(range(0, n_meshes, max(1, n_meshes // 16)))

@@ -81,8 +81,11 @@ typedef struct {
                           simplices meeting Gamma_D, natural ones elsewhere. Without the
                           near-boundary correction of Algorithm 3. */
   int autotune;        /* 1 = at the first solve in a precision, time the candidate launch shapes
-                          of every V-cycle slice kernel and keep the fastest (default); 0 = fixed
-                          256-thread blocks in XCD order. Results do not depend on it. */
+                          of every V-cycle slice kernel (threads per block, block order, kernel
+                          variant: one slice per wave, or a grid-stride loop over the slices that
+                          loads the next slice's header early) and keep the fastest (default);
+                          0 = fixed 256-thread blocks in XCD order, one slice per wave. Results do
+                          not depend on it. */
   int nested;          /* initial guess of PCG: 0 = u_0 = 0 (default); k in 1..16 = nested iteration
                           over the auxiliary levels (Section 5.2): g_J = Pi^T f, g_(l-1) = P_l^T g_l,
                           e = A_(l_c)^-1 g_(l_c) at the bottom, then on each finer level
@@ -267,13 +270,17 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "level_kept"    int64 0/1 per simplex of sigma^(level): kept in the Dirichlet grid
  *   "solve_stats"   int64[2]: PCG iterations and restarts from the true residual of the last
  *                   solve (device handles)
- *   "tuned_shapes"  int64 (threads per block, XCD order) per slice-kernel launch site of B_co
- *                   chosen by the launch-shape autotuner (level = precision; device handles,
- *                   empty before the first solve in that precision)
- * Batch handles: "batch_n", "batch_J", "batch_lc" (int64 per mesh) and "batch_shapes"
- * (level = n_rhs + 8 * precision): (threads per block, XCD order) pairs chosen by the
- * launch-shape autotuner for every slice-kernel launch site of B_co, empty before the first
- * solve with that n_rhs and precision.
+ *   "tuned_shapes"  int64 (threads per block, XCD order, kernel variant) per slice-kernel launch
+ *                   site of B_co chosen by the launch-shape autotuner (level = precision; device
+ *                   handles, empty before the first solve in that precision); variant 0 = one
+ *                   slice per wave, 1 = grid-stride loop over the slices
+ *   "tune_times"    double: the autotuner's best time in ms of every candidate shape at every
+ *                   launch site, site-major (-1 = not timed; level = precision)
+ * Batch handles: "batch_n", "batch_J", "batch_lc" (int64 per mesh), "batch_shapes"
+ * (level = n_rhs + 8 * precision): (threads per block, XCD order, kernel variant) triples chosen
+ * by the launch-shape autotuner for every slice-kernel launch site of B_co, empty before the
+ * first solve with that n_rhs and precision, and "batch_tune_times" (same level): the tuner's
+ * best time per site and candidate, as "tune_times".
  * Returns ASMG_EINVAL for an unknown name or level.
  */
 int asmg_export(asmg_handle h, const char *name, int level, void *buf, int64_t *count);

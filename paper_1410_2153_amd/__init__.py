@@ -24,6 +24,10 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libasmg.so")
 
 OK, EINVAL, ENOCONV, ENOTSPD, ENAN, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
+# candidate launch shapes of the autotuner: (threads per block, XCD order, kernel variant)
+SHAPES = [(256, 1, 0), (128, 1, 0), (512, 1, 0), (256, 0, 0), (128, 0, 0), (512, 0, 0),
+          (256, 1, 1), (512, 1, 1), (256, 0, 1), (512, 0, 1)]
+N_SHAPES = len(SHAPES)
 
 EXPORTED = [
     "asmg_default_options", "asmg_setup", "asmg_update_coefficient", "asmg_set_precision",
@@ -292,8 +296,14 @@ class Solver:
         return buf
 
     def tuned_shapes(self, precision=PREC_FP64):
-        """(threads per block, XCD order) picked by the autotuner per slice-kernel launch site."""
-        return self.export("tuned_shapes", precision).reshape(-1, 2)
+        """(threads per block, XCD order, kernel variant) picked by the autotuner per slice-kernel
+        launch site."""
+        return self.export("tuned_shapes", precision).reshape(-1, 3)
+
+    def tune_times(self, precision=PREC_FP64):
+        """The autotuner's best ms per (launch site, candidate shape); -1 = not timed."""
+        t = self.export("tune_times", precision, dtype=np.float64)
+        return t.reshape(-1, N_SHAPES) if len(t) else t
 
     def setup_seconds(self):
         """Wall time of the setup phases (s): fine, tree, levels, transfer, colourings, coarse, upload."""
@@ -359,15 +369,23 @@ class BatchSolver:
 
     __del__ = close
 
-    def tuned_shapes(self, n_rhs, precision=PREC_FP64):
-        """(threads per block, XCD order) picked by the autotuner per slice-kernel launch site."""
+    def _export(self, name, level, dtype):
         cnt = ctypes.c_int64()
-        lvl = n_rhs + 8 * precision
-        _check(lib.asmg_export(self.h, b"batch_shapes", lvl, None, ctypes.byref(cnt)))
-        buf = np.empty(cnt.value, dtype=np.int64)
+        _check(lib.asmg_export(self.h, name, level, None, ctypes.byref(cnt)))
+        buf = np.empty(cnt.value, dtype=dtype)
         if cnt.value:
-            _check(lib.asmg_export(self.h, b"batch_shapes", lvl, _ptr(buf), ctypes.byref(cnt)))
-        return buf.reshape(-1, 2)
+            _check(lib.asmg_export(self.h, name, level, _ptr(buf), ctypes.byref(cnt)))
+        return buf
+
+    def tuned_shapes(self, n_rhs, precision=PREC_FP64):
+        """(threads per block, XCD order, kernel variant) picked by the autotuner per slice-kernel
+        launch site."""
+        return self._export(b"batch_shapes", n_rhs + 8 * precision, np.int64).reshape(-1, 3)
+
+    def tune_times(self, n_rhs, precision=PREC_FP64):
+        """The autotuner's best ms per (launch site, candidate shape); -1 = not timed."""
+        t = self._export(b"batch_tune_times", n_rhs + 8 * precision, np.float64)
+        return t.reshape(-1, N_SHAPES) if len(t) else t
 
     def offsets(self, n_rhs):
         o = np.zeros(self.n_meshes + 1, dtype=np.int64)

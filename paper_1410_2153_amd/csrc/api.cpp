@@ -461,12 +461,16 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
         if (!H->bdev) return set_err(ASMG_EINVAL, "host-only batch handle");
         return put(batch_tuned_shapes(H->bdev, level % 8, level / 8), buf, count);
       }
+      if (name == "batch_tune_times") {  // level = NR + 8 * precision
+        if (!H->bdev) return set_err(ASMG_EINVAL, "host-only batch handle");
+        return put(batch_tune_times(H->bdev, level % 8, level / 8), buf, count);
+      }
       if (name == "batch_n" || name == "batch_J" || name == "batch_lc") {
         std::vector<int64_t> v;
         for (auto &hp : H->batch) v.push_back(name == "batch_n" ? hp->n() : name == "batch_J" ? hp->J : hp->lc);
         return put(v, buf, count);
       }
-      return set_err(ASMG_EINVAL, "batch handle exports: batch_n, batch_J, batch_lc, batch_shapes");
+      return set_err(ASMG_EINVAL, "batch handle exports: batch_n, batch_J, batch_lc, batch_shapes, batch_tune_times");
     }
     if (name == "info") {
       std::vector<int64_t> v(16, 0);
@@ -520,6 +524,10 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
       if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");
       std::vector<int64_t> v = {device_last_iterations(H->dev), device_restarts(H->dev)};
       return put(v, buf, count);
+    }
+    if (name == "tune_times") {  // level = precision
+      if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");
+      return put(device_tune_times(H->dev, level), buf, count);
     }
     if (name == "tuned_shapes") {  // level = precision
       if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");

@@ -188,77 +188,71 @@ __device__ __forceinline__ int bwave_slice(int first) {
 // MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j (dv_ = a_ii)
 // over slices [s0, s1), every right-hand side of a row at once
-template <int MODE, int NR, class T>
+template <int MODE, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__restrict__ srow,
                                                   const int *__restrict__ soff, const int *__restrict__ scol,
                                                   const T *__restrict__ sv, const T *__restrict__ dv_,
                                                   const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
                                                   int shape) {
-  const int s = tuned_slice(s0, shape);
-  if (s >= s1) return;
   const int lane = threadIdx.x & 63;
-  const int row = srow[(size_t)s * 64 + lane];
-  const int o0 = soff[s];
-  const int w = (soff[s + 1] - o0) >> 6;
-  VecR<NR, T> bv, xv;
-  T di = 0;
-  auto pre = [&] {
-    const int rr = row < 0 ? 0 : row;
-    bv = reinterpret_cast<const VecR<NR, T> *>(b)[rr];
-    di = dv_[rr];
-    if (MODE == 1) xv = reinterpret_cast<const VecR<NR, T> *>(x)[rr];
-  };
-  auto post = [&](T acc[NR]) {
+  for_slices<VAR>(s0, s1, shape, srow, soff, [&](int row, int o0, int w) {
+    VecR<NR, T> bv, xv;
+    T di = 0;
+    auto pre = [&] {
+      const int rr = row < 0 ? 0 : row;
+      bv = reinterpret_cast<const VecR<NR, T> *>(b)[rr];
+      di = dv_[rr];
+      if (MODE == 1) xv = reinterpret_cast<const VecR<NR, T> *>(x)[rr];
+    };
+    auto post = [&](T acc[NR]) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) bpin(bv.v[q]);
-    bpin(di);
-    if (row < 0) return;
-    VecR<NR, T> o;
+      for (int q = 0; q < NR; ++q) bpin(bv.v[q]);
+      bpin(di);
+      if (row < 0) return;
+      VecR<NR, T> o;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : bv.v[q] - di * xv.v[q] - acc[q];
-    reinterpret_cast<VecR<NR, T> *>(MODE == 0 ? x : r)[row] = o;
-  };
-  bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+      for (int q = 0; q < NR; ++q) o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : bv.v[q] - di * xv.v[q] - acc[q];
+      reinterpret_cast<VecR<NR, T> *>(MODE == 0 ? x : r)[row] = o;
+    };
+    bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  });
 }
 
 // transfer product y = A x (ADD 0) or y += A x (ADD 1). FIRST (ADD 0): y is the right-hand side
 // of a level whose smoothing starts from zero; the kernel also runs its first colour pass,
 // xs_i = y_i * id0_i with id0_i = 1/a_ii on colour-0 rows of their mesh and 0 elsewhere.
-template <int ADD, int FIRST, int NR, class T>
+template <int ADD, int FIRST, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__restrict__ srow,
                                                        const int *__restrict__ soff, const int *__restrict__ scol,
                                                        const T *__restrict__ sv, const T *__restrict__ x,
                                                        T *__restrict__ y, const T *__restrict__ id0,
                                                        T *__restrict__ xs, int shape) {
-  const int s = tuned_slice(0, shape);
-  if (s >= ns) return;
   const int lane = threadIdx.x & 63;
-  const int row = srow[(size_t)s * 64 + lane];
-  const int o0 = soff[s];
-  const int w = (soff[s + 1] - o0) >> 6;
-  VecR<NR, T> yv;
-  T di = 0;
-  auto pre = [&] {
-    const int rr = row < 0 ? 0 : row;
-    if (ADD) yv = reinterpret_cast<const VecR<NR, T> *>(y)[rr];
-    if (FIRST) di = id0[rr];
-  };
-  auto post = [&](T acc[NR]) {
-    if (ADD)
+  for_slices<VAR>(0, ns, shape, srow, soff, [&](int row, int o0, int w) {
+    VecR<NR, T> yv;
+    T di = 0;
+    auto pre = [&] {
+      const int rr = row < 0 ? 0 : row;
+      if (ADD) yv = reinterpret_cast<const VecR<NR, T> *>(y)[rr];
+      if (FIRST) di = id0[rr];
+    };
+    auto post = [&](T acc[NR]) {
+      if (ADD)
 #pragma unroll
-      for (int q = 0; q < NR; ++q) bpin(yv.v[q]);
-    if (FIRST) bpin(di);
-    if (row < 0) return;
-    VecR<NR, T> o, f;
+        for (int q = 0; q < NR; ++q) bpin(yv.v[q]);
+      if (FIRST) bpin(di);
+      if (row < 0) return;
+      VecR<NR, T> o, f;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      o.v[q] = ADD ? yv.v[q] + acc[q] : acc[q];
-      f.v[q] = di != T(0) ? acc[q] * di : T(0);
-    }
-    reinterpret_cast<VecR<NR, T> *>(y)[row] = o;
-    if (FIRST) reinterpret_cast<VecR<NR, T> *>(xs)[row] = f;
-  };
-  bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+      for (int q = 0; q < NR; ++q) {
+        o.v[q] = ADD ? yv.v[q] + acc[q] : acc[q];
+        f.v[q] = di != T(0) ? acc[q] * di : T(0);
+      }
+      reinterpret_cast<VecR<NR, T> *>(y)[row] = o;
+      if (FIRST) reinterpret_cast<VecR<NR, T> *>(xs)[row] = f;
+    };
+    bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  });
 }
 
 // first colour pass of a sweep from zero on its own: x_i = b_i * id0_i (0 off colour 0)
@@ -732,7 +726,9 @@ struct BLevel {
   float *dg32 = nullptr, *id32 = nullptr, *id0_32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
   float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
-  BSell P, PT;           // P: rows = smoothing rows, cols = rows of level k+1
+  BSell P, PT;           // P: rows = smoothing rows, cols = rows of level k+1 (as used in B_co:
+                         // P without each mesh's last colour rows, P^T without the zero-residual
+                         // columns of the last colour group)
   // bottom meshes
   int nbottom = 0;
   int *bt_rowpref = nullptr, *bt_nc = nullptr, *bt_voff = nullptr;
@@ -775,7 +771,8 @@ struct BatchDevice {
   double bytes = 0;
   // launch shapes of the V-cycle slice kernels, per (precision, NR) and launch site (the k-th
   // slice-kernel launch of one B_co application), chosen by `tune`
-  std::vector<std::pair<int, int>> shape[2][5];  // (threads per block, xcd order)
+  std::vector<Shape> shape[2][5];  // (threads per block, xcd order, kernel variant)
+  std::vector<std::vector<float>> tune_times[2][5];  // autotuner: best ms per site and candidate
   bool tuned[2][5] = {{false}};
   bool tuning = false;
   int site = 0;
@@ -1052,6 +1049,54 @@ static void upload_diag(BatchDevice *dv, BLevel &L, const std::vector<double> &d
   L.id0_32 = bupload(dv, i032);
 }
 
+// Transfers inside B_co. The prolongation x += P e need not write the rows of each mesh's last
+// colour: the first backward Gauss-Seidel pass overwrites them without reading them. The
+// restriction P^T r need not read the columns where the residual is zero: the last colour group,
+// whose rows the residual kernel leaves at zero after a forward sweep.
+static std::vector<int> keep_rows(const std::vector<int> &order, const std::vector<uint8_t> &drop) {
+  std::vector<int> out;
+  out.reserve(order.size());
+  for (int i : order) {
+    if (i < 0 || i >= (int)drop.size()) throw AsmgError{ASMG_EINVAL, "transfer row outside its matrix"};
+    if (!drop[i]) out.push_back(i);
+  }
+  return out;
+}
+
+static HMat drop_cols(const HMat &H, const std::vector<uint8_t> &drop) {
+  HMat R;
+  R.nrows = H.nrows;
+  R.ncols = H.ncols;
+  R.rp.assign(H.nrows + 1, 0);
+  for (int i = 0; i < H.nrows; ++i) {
+    for (int p = H.rp[i]; p < H.rp[i + 1]; ++p)
+      if (!drop[H.ci[p]]) {
+        R.ci.push_back(H.ci[p]);
+        R.v.push_back(H.v[p]);
+      }
+    R.rp[i + 1] = (int)R.ci.size();
+  }
+  return R;
+}
+
+// byte-model counts of a transfer image: the rows it holds, their nonzeros, the distinct columns
+static void transfer_stats(const HMat &H, const std::vector<int> &rows, BSellHost &X) {
+  std::vector<uint8_t> seen(std::max(H.ncols, 1), 0);
+  int64_t nnz = 0;
+  int cols = 0;
+  for (int i : rows)
+    for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+      ++nnz;
+      if (!seen[H.ci[p]]) {
+        seen[H.ci[p]] = 1;
+        ++cols;
+      }
+    }
+  X.nrows = (int)rows.size();
+  X.ncols = cols;
+  X.nnz = nnz;
+}
+
 // byte-model counts of each row-range group of H: nonzeros, rows, and the distinct columns the
 // group's rows gather (each x entry read once per colour pass)
 static void group_counts(const HMat &H, const Groups &groups, std::vector<int64_t> &cnnz, std::vector<int64_t> &crows,
@@ -1225,13 +1270,30 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
           append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
         }
         Pi.ncols = L0.nrows;
+        // the rows of each mesh's last colour, and of the last colour group (meshes with the most
+        // colours), on the original grids
+        std::vector<uint8_t> last(F.nrows, 0), zero(F.nrows, 0);
+        int C = 0;
+        for (int m = 0; m < nm; ++m) C = std::max(C, (int)fine[m].coff.size() - 1);
+        for (int m = 0; m < nm; ++m) {
+          const auto &co = fine[m].coff;
+          const int Cm = (int)co.size() - 1;
+          if (Cm < 1) continue;
+          for (int r = F.off[m] + co[Cm - 1]; r < F.off[m] + co[Cm]; ++r) {
+            last[r] = 1;
+            if (Cm == C) zero[r] = 1;
+          }
+        }
         std::vector<int> oPi;
         for (int m = 0; m < nm; ++m)
           for (int r : fine[m].morton) oPi.push_back(F.off[m] + r);
-        bsell_host(Pi, {{{0, Pi.nrows}}}, false, pi_img, &oPi);
-        const HMat PiT = htranspose(Pi);
+        oPi = keep_rows(oPi, last);
+        bsell_host(Pi, {{{0, (int)oPi.size()}}}, false, pi_img, &oPi);
+        transfer_stats(Pi, oPi, pi_img);
+        const HMat PiT = drop_cols(htranspose(Pi), zero);
         const std::vector<int> oPiT = natural_rows(L0, 0);
         bsell_host(PiT, {{{0, PiT.nrows}}}, false, pit_img, &oPiT);
+        transfer_stats(PiT, oPiT, pit_img);
       } else if (t < K + 3) {
         const int k = t - 2;
         BLevel &L = dv->aux[k];
@@ -1277,10 +1339,28 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
           append_rows(P, H[m]->P.at(l), lev[m][k].perm, cmap, Lc.off[j], false, nullptr);
         }
         P.ncols = Lc.nrows;
-        const std::vector<int> oP = natural_rows(L, k), oPT = natural_rows(Lc, k + 1);
-        bsell_host(P, {{{0, P.nrows}}}, false, p_img[k], &oP);
-        const HMat PT = htranspose(P);
+        std::vector<uint8_t> last(P.nrows, 0), zero(P.nrows, 0);
+        int C = 0;
+        for (int m : smooth_m[k]) C = std::max(C, (int)lev[m][k].coff.size() - 1);
+        for (size_t i = 0; i < smooth_m[k].size(); ++i) {
+          const auto &co = lev[smooth_m[k][i]][k].coff;
+          const int Cm = (int)co.size() - 1;
+          if (Cm < 1) continue;
+          for (int r = L.off[i] + co[Cm - 1]; r < L.off[i] + co[Cm]; ++r) {
+            last[r] = 1;
+            if (Cm == C) zero[r] = 1;
+          }
+        }
+        // the level's rows in each mesh's own numbering; P has the smoothing meshes' rows only
+        // (the first P.nrows of the merged level), not those of meshes whose bottom it is
+        std::vector<int> nat = natural_rows(L, k);
+        nat.erase(std::remove_if(nat.begin(), nat.end(), [&](int r) { return r >= P.nrows; }), nat.end());
+        const std::vector<int> oP = keep_rows(nat, last), oPT = natural_rows(Lc, k + 1);
+        bsell_host(P, {{{0, (int)oP.size()}}}, false, p_img[k], &oP);
+        transfer_stats(P, oP, p_img[k]);
+        const HMat PT = drop_cols(htranspose(P), zero);
         bsell_host(PT, {{{0, PT.nrows}}}, false, pt_img[k], &oPT);
+        transfer_stats(PT, oPT, pt_img[k]);
       }
     });
     // ---- uploads
@@ -1502,10 +1582,9 @@ static void slice_launch(BatchDevice *dv, int nslices, hipStream_t s, F &&launch
     dv->tune_has.resize(std::max<size_t>(dv->tune_has.size(), site + 1), 0);
     dv->tune_has[site] = 1;
   }
-  launch(sh.first, sh.second, e0, e1);
+  launch(sh.threads, sh.xcd, sh.var, e0, e1);
 }
 
-static inline int slice_blocks(int nslices, int threads) { return std::max(1, (nslices * 64 + threads - 1) / threads); }
 
 // Gauss-Seidel sweep over the colour groups of L. `first_done`: the sweep starts from zero and
 // its colour-0 pass was run by the kernel that produced b.
@@ -1525,9 +1604,11 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
                       sz * NR * (double)L.ucols[c];
     slice_launch(
         dv, s1 - s0, s,
-        [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-          launch_timed((kb_sell<0, NR, T>), slice_blocks(s1 - s0, th), th, s, e0, e1, s0, s1, S.srow, S.soff,
-                       S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+        [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+          with_var(var, [&](auto vc) {
+            launch_timed((kb_sell<0, NR, T, decltype(vc)::value>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1,
+                         S.srow, S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+          });
         },
         by);
   };
@@ -1556,9 +1637,11 @@ static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   const BSell &S = L.sell;
   const int C = (int)S.cslice.size() - 1;
   const int s1 = C >= 1 ? S.cslice[C - 1] : S.nslices;
-  slice_launch(dv, s1, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed((kb_sell<1, NR, T>), slice_blocks(s1, th), th, s, e0, e1, 0, s1, S.srow, S.soff, S.scol,
-                 bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
+  slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+    with_var(var, [&](auto vc) {
+      launch_timed((kb_sell<1, NR, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
+                   S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
+    });
   });
   if (dv->count_bytes && S.nslices > 0)
     dv->bytes += (bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1)) * s1 / S.nslices;
@@ -1569,10 +1652,12 @@ static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
 template <int NR, int ADD, int FIRST, class T>
 static void b_spmv(BatchDevice *dv, const BSell &A, const T *x, T *y, BLevel *Lt, hipStream_t s) {
   if (A.nrows == 0) return;
-  slice_launch(dv, A.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed((kb_sell_spmv<ADD, FIRST, NR, T>), slice_blocks(A.nslices, th), th, s, e0, e1,
-                       A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y,
-                       FIRST ? bid0<T>(*Lt) : (const T *)nullptr, FIRST ? BV<T>::x(*Lt) : (T *)nullptr, shape_arg(th, xcd));
+  slice_launch(dv, A.nslices, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+    with_var(var, [&](auto vc) {
+      launch_timed((kb_sell_spmv<ADD, FIRST, NR, T, decltype(vc)::value>), slice_blocks(A.nslices, th, var), th, s, e0, e1,
+                   A.nslices, A.srow, A.soff, A.scol, bsv<T>(A), x, y, FIRST ? bid0<T>(*Lt) : (const T *)nullptr,
+                   FIRST ? BV<T>::x(*Lt) : (T *)nullptr, shape_arg(th, xcd));
+    });
   });
   if (dv->count_bytes)
     dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD + FIRST) * (double)A.nrows) +
@@ -1683,6 +1768,7 @@ static void b_tune(BatchDevice *dv, hipStream_t s) {
   tab.assign(t.size(), kShapes[0]);
   for (size_t site = 0; site < t.size(); ++site)
     tab[site] = kShapes[pick_shape(t[site])];
+  dv->tune_times[pi][NR] = t;
   dv->tuned[pi][NR] = true;
 }
 
@@ -1971,9 +2057,18 @@ std::vector<int64_t> batch_tuned_shapes(BatchDevice *dv, int nr, int precision) 
   std::vector<int64_t> out;
   if (nr < 1 || nr > 4 || precision < 0 || precision > 1) return out;
   for (const auto &sh : dv->shape[precision][nr]) {
-    out.push_back(sh.first);
-    out.push_back(sh.second);
+    out.push_back(sh.threads);
+    out.push_back(sh.xcd);
+    out.push_back(sh.var);
   }
+  return out;
+}
+
+std::vector<double> batch_tune_times(BatchDevice *dv, int nr, int precision) {
+  std::vector<double> out;
+  if (nr < 1 || nr > 4 || precision < 0 || precision > 1) return out;
+  for (const auto &row : dv->tune_times[precision][nr])
+    for (float t : row) out.push_back(std::isfinite(t) ? (double)t : -1.0);
   return out;
 }
 

@@ -23,8 +23,10 @@ int batch_device_time(BatchDevice *dv, int n_rhs, int reps, int precision, void 
 int batch_device_time_kernel(BatchDevice *dv, int which, int n_rhs, int reps, int precision, void *stream, double *ms,
                              double *bytes);
 int64_t batch_n_total(BatchDevice *dv);
-// launch shapes picked by the autotuner for (NR, precision): threads per block and XCD order of
-// every slice-kernel launch site, flattened pairs (empty before the first solve)
+// launch shapes picked by the autotuner for (NR, precision): threads per block, XCD order and
+// kernel variant of every slice-kernel launch site, flattened triples (empty before the first solve)
 std::vector<int64_t> batch_tuned_shapes(BatchDevice *dv, int nr, int precision);
+// the autotuner's best time (ms) of every candidate at every launch site, site-major (-1 = not timed)
+std::vector<double> batch_tune_times(BatchDevice *dv, int nr, int precision);
 
 }  // namespace asmg

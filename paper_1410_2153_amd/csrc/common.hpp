@@ -89,16 +89,73 @@ __device__ __forceinline__ int tuned_slice(int first, int shape) {
   return first + blk * (shape >> 1) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 }
 
-// Candidate launch shapes (threads per block, XCD order) of the autotuner; the first is the
-// default. Each candidate is timed kTuneRounds times per launch site (best of), and a site leaves
-// the default only for a candidate faster by kTuneMargin of the default's time and by at least
-// kTuneFloorMs: timings of kernels of a few microseconds are noisy, and a pick on noise costs
-// more than it gains.
-static const std::pair<int, int> kShapes[] = {{256, 1}, {128, 1}, {512, 1}, {256, 0}, {128, 0}, {512, 0}};
+// Candidate launch shapes of the autotuner: threads per block, XCD order, and the kernel variant
+// `var`: 0 = one slice per wave; 1 = a grid of at most kLoopWaves waves loops over the slices
+// (grid-stride), loading the next slice's header (row index per lane, entry offsets) before the
+// current slice's entries, so its latency overlaps the current slice's work. The first candidate
+// is the default. Each candidate is timed kTuneRounds times per launch site (best of), and a site
+// leaves the default only for a candidate faster by kTuneMargin of the default's time and by at
+// least kTuneFloorMs: timings of kernels of a few microseconds are noisy, and a pick on noise
+// costs more than it gains.
+struct Shape {
+  int threads, xcd, var;
+};
+static const Shape kShapes[] = {{256, 1, 0}, {128, 1, 0}, {512, 1, 0}, {256, 0, 0}, {128, 0, 0},
+                                {512, 0, 0}, {256, 1, 1}, {512, 1, 1}, {256, 0, 1}, {512, 0, 1}};
 static constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 static constexpr int kTuneRounds = 3;
 static constexpr float kTuneMargin = 0.02f;
 static constexpr float kTuneFloorMs = 0.0005f;
+// resident waves of one round of the loop variant: 256 CUs x 16 waves
+static constexpr int kLoopWaves = 4096;
+
+// calls f(std::integral_constant<int, var>) for the compiled kernel variants
+template <class F>
+static void with_var(int var, F &&f) {
+  if (var == 1)
+    f(std::integral_constant<int, 1>());
+  else
+    f(std::integral_constant<int, 0>());
+}
+
+// blocks of a slice-kernel launch over `nslices` slices (64 rows each) with `threads`-thread blocks
+static inline int slice_blocks(int nslices, int threads, int var = 0) {
+  const int b = std::max(1, (nslices * 64 + threads - 1) / threads);
+  return var == 1 ? std::min(b, std::max(1, kLoopWaves / (threads / 64))) : b;
+}
+
+// The slices [s0, s1) of a slice-kernel launch, each handed to body(row, o0, w): the lane's row
+// (-1 on empty lanes), the slice's first entry offset and its width. VAR 0: one slice per wave.
+// VAR 1: grid-stride loop, with the next slice's header loaded before body runs on this one.
+template <int VAR, class F>
+__device__ __forceinline__ void for_slices(int s0, int s1, int shape, const int *__restrict__ srow,
+                                           const int *__restrict__ soff, F &&body) {
+  int s = tuned_slice(s0, shape);
+  if (s >= s1) return;
+  const int lane = threadIdx.x & 63;
+  int row = srow[(size_t)s * 64 + lane];
+  int o0 = soff[s], o1 = soff[s + 1];
+  if constexpr (VAR == 0) {
+    body(row, o0, (o1 - o0) >> 6);
+  } else {
+    const int stride = (int)gridDim.x * (shape >> 1);
+    while (true) {
+      const int sn = s + stride;
+      int rn = -1, p0 = 0, p1 = 0;
+      if (sn < s1) {
+        rn = srow[(size_t)sn * 64 + lane];
+        p0 = soff[sn];
+        p1 = soff[sn + 1];
+      }
+      body(row, o0, (o1 - o0) >> 6);
+      if (sn >= s1) break;
+      s = sn;
+      row = rn;
+      o0 = p0;
+      o1 = p1;
+    }
+  }
+}
 
 // Launch of a kernel over `grid` blocks of `threads`; with an event pair (timing runs only, never
 // under stream capture) the events are stamped with the kernel's own start and end

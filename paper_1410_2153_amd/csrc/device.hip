@@ -201,71 +201,65 @@ __device__ __forceinline__ int wave_slice(int first) {
 // MODE 0: Gauss-Seidel pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j
 // (dv_ holds 1/a_ii for MODE 0 and a_ii for MODE 1)
-template <int MODE, class T>
+template <int MODE, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void k_sell(int s0, int s1, const int *__restrict__ srow,
                                                  const int *__restrict__ soff, const int *__restrict__ scol,
                                                  const T *__restrict__ sv, const T *__restrict__ dv_,
                                                  const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
                                                  int shape) {
-  const int s = tuned_slice(s0, shape);
-  if (s >= s1) return;
   const int lane = threadIdx.x & 63;
-  const int row = srow[(size_t)s * 64 + lane];
-  const int o0 = soff[s];
-  const int w = (soff[s + 1] - o0) >> 6;
-  T bi = 0, di = 0, xi = 0;
-  auto pre = [&] {
-    const int rr = row < 0 ? 0 : row;
-    bi = b[rr];
-    di = dv_[rr];
-    if (MODE == 1) xi = x[rr];
-  };
-  auto post = [&](T acc) {
-    pin(bi);
-    pin(di);
-    if (MODE == 1) pin(xi);
-    if (row < 0) return;
-    if (MODE == 0)
-      x[row] = (bi - acc) * di;
-    else
-      r[row] = bi - di * xi - acc;
-  };
-  sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  for_slices<VAR>(s0, s1, shape, srow, soff, [&](int row, int o0, int w) {
+    T bi = 0, di = 0, xi = 0;
+    auto pre = [&] {
+      const int rr = row < 0 ? 0 : row;
+      bi = b[rr];
+      di = dv_[rr];
+      if (MODE == 1) xi = x[rr];
+    };
+    auto post = [&](T acc) {
+      pin(bi);
+      pin(di);
+      if (MODE == 1) pin(xi);
+      if (row < 0) return;
+      if (MODE == 0)
+        x[row] = (bi - acc) * di;
+      else
+        r[row] = bi - di * xi - acc;
+    };
+    sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  });
 }
 
 // transfer products on a sliced ELL (one colour class = all rows): y = A x (ADD = 0) or y += A x.
 // FIRST (with ADD = 0): y is the right-hand side of a level whose smoothing starts from zero, and
 // the kernel also runs that first colour pass: xs_i = y_i / a_ii for rows i < c0 (colour 0),
 // xs_i = 0 for the other rows; with rc it also copies y into rc.
-template <int ADD, int FIRST, class T, int WMAX = 16>
+template <int ADD, int FIRST, class T, int WMAX = 16, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void k_sell_spmv(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
                                                   const int *__restrict__ scol, const T *__restrict__ sv,
                                                   const T *__restrict__ x, T *__restrict__ y, int c0,
                                                   const T *__restrict__ invd, T *__restrict__ xs,
                                                   T *__restrict__ rc, int shape) {
-  const int s = tuned_slice(0, shape);
-  if (s >= ns) return;
   const int lane = threadIdx.x & 63;
-  const int row = srow[(size_t)s * 64 + lane];
-  const int o0 = soff[s];
-  const int w = (soff[s + 1] - o0) >> 6;
-  T yi = 0, di = 0;
-  auto pre = [&] {
-    const int rr = row < 0 ? 0 : row;
-    if (ADD) yi = y[rr];
-    if (FIRST && rr < c0) di = invd[rr];
-  };
-  auto post = [&](T acc) {
-    if (ADD) pin(yi);
-    if (FIRST) pin(di);
-    if (row < 0) return;
-    y[row] = ADD ? yi + acc : acc;
-    if (FIRST) {
-      xs[row] = row < c0 ? acc * di : T(0);
-      if (rc) rc[row] = acc;
-    }
-  };
-  sell_row<T, WMAX, true>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  for_slices<VAR>(0, ns, shape, srow, soff, [&](int row, int o0, int w) {
+    T yi = 0, di = 0;
+    auto pre = [&] {
+      const int rr = row < 0 ? 0 : row;
+      if (ADD) yi = y[rr];
+      if (FIRST && rr < c0) di = invd[rr];
+    };
+    auto post = [&](T acc) {
+      if (ADD) pin(yi);
+      if (FIRST) pin(di);
+      if (row < 0) return;
+      y[row] = ADD ? yi + acc : acc;
+      if (FIRST) {
+        xs[row] = row < c0 ? acc * di : T(0);
+        if (rc) rc[row] = acc;
+      }
+    };
+    sell_row<T, WMAX, true>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+  });
 }
 
 // dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
@@ -706,6 +700,10 @@ struct DCsr {
   float *v32 = nullptr;
   int lpr = 4;
   DSell *sell = nullptr;       // sliced ELL copy used by the transfer products
+  // transfers inside B_co (whole-level smoothing): the prolongation without the rows of the target
+  // level's last colour (the first backward pass overwrites them unread), the restriction without
+  // the columns of the source level's last colour (its residual is zero there); null = use `sell`
+  DSell *vsell = nullptr;
 };
 
 struct DSell {
@@ -716,6 +714,8 @@ struct DSell {
   double *sv64 = nullptr;
   float *sv32 = nullptr;
   int64_t entries = 0;        // stored entries including padding
+  int64_t nnz = 0;            // byte model: nonzeros, rows, distinct columns referenced
+  int nrows = 0, ncols_used = 0;
 };
 
 struct DLevel {
@@ -785,7 +785,8 @@ struct Device {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   // launch shapes of the V-cycle slice kernels per precision and launch site (the k-th slice
   // launch of one B_co application), chosen by the autotuner at the first solve
-  std::vector<std::pair<int, int>> shape[2];  // (threads per block, xcd order)
+  std::vector<Shape> shape[2];  // (threads per block, xcd order, kernel variant)
+  std::vector<std::vector<float>> tune_times[2];  // autotuner: best ms per site and candidate
   bool tuned[2] = {false, false};
   bool tuning = false;
   int site = 0, shape_pi = 0;
@@ -926,26 +927,96 @@ static void upload_values(DCsr &D, const HCsr &H) {
 // follow `order` (rows in a spatially coherent order: the level's Morton numbering, or Morton
 // order of the vertices on the original grid): neighbouring rows then gather neighbouring
 // entries of x, whereas the colour-major numbering would interleave four distant ranges.
+struct SellStats {
+  int64_t nnz = 0;
+  int nrows = 0, ncols_used = 0;
+};
+
 struct TransferStage {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
-  SellHost sell;
+  SellHost sell, vsell;
+  SellStats st, vst;
+  bool has_v = false;
 };
+
+// byte-model counts of the rows `order` (all rows when null) of H
+static SellStats sell_stats(const HCsr &H, const std::vector<int> *order) {
+  SellStats st;
+  std::vector<uint8_t> seen(std::max(H.ncols, 1), 0);
+  auto row = [&](int i) {
+    ++st.nrows;
+    for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+      ++st.nnz;
+      if (!seen[H.ci[p]]) {
+        seen[H.ci[p]] = 1;
+        ++st.ncols_used;
+      }
+    }
+  };
+  if (order)
+    for (int i : *order) row(i);
+  else
+    for (int i = 0; i < H.nrows; ++i) row(i);
+  return st;
+}
 
 static void stage_transfer(const HCsr &H, const std::vector<int> *order, TransferStage &X) {
   X.nrows = H.nrows;
   X.ncols = H.ncols;
   X.nnz = (int64_t)H.ci.size();
   X.sell = sell_host(H, Ranges{{0, H.nrows}}, nullptr, 4, order);
+  X.st = sell_stats(H, nullptr);
+}
+
+// The V-cycle's copy of a prolongation: the rows of `order` outside [skip0, skip1) (the target
+// level's last colour, which the first backward pass overwrites without reading).
+static void stage_prolong_v(const HCsr &H, const std::vector<int> &order, int skip0, int skip1, TransferStage &X) {
+  std::vector<int> keep;
+  keep.reserve(order.size());
+  for (int i : order)
+    if (i < skip0 || i >= skip1) keep.push_back(i);
+  X.vsell = sell_host(H, Ranges{{0, (int)keep.size()}}, nullptr, 4, &keep);
+  X.vst = sell_stats(H, &keep);
+  X.has_v = true;
+}
+
+// The V-cycle's copy of a restriction: without the entries of columns in [skip0, skip1) (the
+// source level's last colour, where the residual it restricts is zero after a forward sweep).
+static void stage_restrict_v(const HCsr &H, const std::vector<int> *order, int skip0, int skip1, TransferStage &X) {
+  HCsr R;
+  R.nrows = H.nrows;
+  R.ncols = H.ncols;
+  R.rp.assign(H.nrows + 1, 0);
+  for (int i = 0; i < H.nrows; ++i) {
+    for (int p = H.rp[i]; p < H.rp[i + 1]; ++p)
+      if (H.ci[p] < skip0 || H.ci[p] >= skip1) {
+        R.ci.push_back(H.ci[p]);
+        R.v.push_back(H.v[p]);
+      }
+    R.rp[i + 1] = (int)R.ci.size();
+  }
+  X.vsell = sell_host(R, Ranges{{0, R.nrows}}, nullptr, 4, order);
+  X.vst = sell_stats(R, nullptr);
+  X.has_v = true;
+}
+
+static DSell *upload_stage_sell(Device *dv, const SellHost &H, const SellStats &st) {
+  dv->sells.emplace_back(new DSell());
+  DSell *S = dv->sells.back().get();
+  sell_upload(dv, *S, H, true);
+  S->nnz = st.nnz;
+  S->nrows = st.nrows;
+  S->ncols_used = st.ncols_used;
+  return S;
 }
 
 static void commit_transfer(Device *dv, const TransferStage &X, DCsr &D) {
   D.nrows = X.nrows;
   D.ncols = X.ncols;
   D.nnz = X.nnz;
-  dv->sells.emplace_back(new DSell());
-  D.sell = dv->sells.back().get();
-  sell_upload(dv, *D.sell, X.sell, true);
+  D.sell = upload_stage_sell(dv, X.sell, X.st);
+  if (X.has_v) D.vsell = upload_stage_sell(dv, X.vsell, X.vst);
 }
 
 // colour-major numbering: colour classes in order, inside a class ascending (part, rank), with
@@ -1303,11 +1374,20 @@ Device *device_create(Hierarchy &h, int ordinal) {
     std::vector<int> forder(mrank.size());
     for (size_t i = 0; i < mrank.size(); ++i) forder[mrank[i]] = dv->fine.iperm[i];
     // tasks: Pi and Pi^T first (the largest), then the fine operator, the levels, the prolongations
+    // last colour of a level with whole-level smoothing, [first row, end) in internal numbering
+    auto last_colour = [&](const DLevel &L) {
+      return (L.local || L.C < 1) ? std::make_pair(0, 0) : std::make_pair(L.coff[L.C - 1], L.coff[L.C]);
+    };
+    const auto fl = last_colour(dv->fine);
     host_parallel(h.threads, 3 + 2 * naux, [&](int t) {
       if (t == 0) {
-        stage_transfer(permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr), &forder, pi_st);
+        const HCsr Pi = permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr);
+        stage_transfer(Pi, &forder, pi_st);
+        if (fl.second > fl.first) stage_prolong_v(Pi, forder, fl.first, fl.second, pi_st);
       } else if (t == 1) {
-        stage_transfer(transpose(permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr)), pi_cmap, pit_st);
+        const HCsr PiT = transpose(permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr));
+        stage_transfer(PiT, pi_cmap, pit_st);
+        if (fl.second > fl.first) stage_restrict_v(PiT, pi_cmap, fl.first, fl.second, pit_st);
       } else if (t == 2) {
         stage_level(dv->fine, h.A, true, fine_st);
       } else if (t < 3 + naux) {
@@ -1318,8 +1398,14 @@ Device *device_create(Hierarchy &h, int ordinal) {
         DLevel &L = dv->aux[l];
         const std::vector<int> *cmap = l - 1 > h.lc ? &dv->aux[l - 1].iperm : nullptr;
         HCsr P = permute(h.P.at(l), L.perm, cmap, false, nullptr);
+        const HCsr PT = transpose(P);
         stage_transfer(P, &L.iperm, p_st[i]);
-        stage_transfer(transpose(P), cmap, pt_st[i]);
+        stage_transfer(PT, cmap, pt_st[i]);
+        const auto ll = last_colour(L);
+        if (ll.second > ll.first) {
+          stage_prolong_v(P, L.iperm, ll.first, ll.second, p_st[i]);
+          stage_restrict_v(PT, cmap, ll.first, ll.second, pt_st[i]);
+        }
       }
     });
     lap("host layout");
@@ -1527,10 +1613,9 @@ static void slice_launch(Device *dv, int nslices, hipStream_t s, F &&launch, dou
     dv->probe_used += 2;
     dv->probe_bytes.push_back(probe_bytes);
   }
-  launch(sh.first, sh.second, e0, e1);
+  launch(sh.threads, sh.xcd, sh.var, e0, e1);
 }
 
-static inline int slice_blocks(int nslices, int threads) { return std::max(1, (nslices * 64 + threads - 1) / threads); }
 
 template <class T>
 static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t s) {
@@ -1539,9 +1624,11 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t 
   const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
   slice_launch(
       dv, s1 - s0, s,
-      [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-        launch_timed((k_sell<0, T>), slice_blocks(s1 - s0, th), th, s, e0, e1, s0, s1, S.srow, S.soff, S.scol,
-                     sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+      [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+        with_var(var, [&](auto vc) {
+          launch_timed((k_sell<0, T, decltype(vc)::value>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1,
+                       S.srow, S.soff, S.scol, sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+        });
       },
       probe ? gs_bytes<T>(L, c) : -1.0);
   if (dv->count_bytes) dv->bytes += gs_bytes<T>(L, c);
@@ -1587,9 +1674,11 @@ static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStr
   const DSell &S = L.sell;
   const bool skip = !full && !L.local && L.C >= 1;
   const int s1 = skip ? S.cslice[L.C - 1] : S.nslices;
-  slice_launch(dv, s1, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed((k_sell<1, T>), slice_blocks(s1, th), th, s, e0, e1, 0, s1, S.srow, S.soff, S.scol,
-                 sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
+  slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+    with_var(var, [&](auto vc) {
+      launch_timed((k_sell<1, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow, S.soff,
+                   S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
+    });
   });
   if (S.nslices == 0) return;
   if (dv->count_bytes)
@@ -1601,21 +1690,25 @@ static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStr
 
 // y = A x (ADD 0) or y += A x (ADD 1) for a transfer matrix A
 template <class T, int ADD>
-static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s) {
+static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s, bool vcyc = false) {
   if (A.nrows == 0) return;
-  const DSell &S = *A.sell;
-  slice_launch(dv, S.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    if (S.wmax > 16)
-      launch_timed((k_sell_spmv<ADD, 0, T, 32>), slice_blocks(S.nslices, th), th, s, e0, e1, S.nslices,
-                         S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr,
-                         (T *)nullptr, shape_arg(th, xcd));
-    else
-      launch_timed((k_sell_spmv<ADD, 0, T>), slice_blocks(S.nslices, th), th, s, e0, e1, S.nslices,
-                         S.srow, S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr,
-                         (T *)nullptr, shape_arg(th, xcd));
+  const DSell &S = vcyc && A.vsell ? *A.vsell : *A.sell;
+  slice_launch(dv, S.nslices, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+    with_var(var, [&](auto vc) {
+      constexpr int O = decltype(vc)::value;
+      if (S.wmax > 16)
+        launch_timed((k_sell_spmv<ADD, 0, T, 32, O>), slice_blocks(S.nslices, th, var), th, s, e0, e1, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr, (T *)nullptr,
+                     shape_arg(th, xcd));
+      else
+        launch_timed((k_sell_spmv<ADD, 0, T, 16, O>), slice_blocks(S.nslices, th, var), th, s, e0, e1, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, y, 0, (const T *)nullptr, (T *)nullptr, (T *)nullptr,
+                     shape_arg(th, xcd));
+    });
   });
   if (dv->count_bytes)
-    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (1 + ADD) * (double)A.nrows * sizeof(T);
+    dv->bytes += (double)S.nnz * (sizeof(T) + 4) + 4.0 * (S.nrows + 1) + (double)S.ncols_used * sizeof(T) +
+                 (1 + ADD) * (double)S.nrows * sizeof(T);
 }
 
 // restriction y = A x into the right-hand side of level L, fused with the colour-0 pass of the
@@ -1624,21 +1717,24 @@ static void spmv(Device *dv, const DCsr &A, const T *x, T *y, hipStream_t s) {
 template <class T>
 static void spmv_first(Device *dv, const DCsr &A, const T *x, DLevel &L, hipStream_t s) {
   if (A.nrows == 0) return;
-  const DSell &S = *A.sell;
+  const DSell &S = A.vsell ? *A.vsell : *A.sell;  // restrictions of residuals inside B_co only
   T *rc = L.local ? LV<T>::r(L) : (T *)nullptr;
-  slice_launch(dv, S.nslices, s, [&](int th, int xcd, hipEvent_t e0, hipEvent_t e1) {
-    if (S.wmax > 16)
-      launch_timed((k_sell_spmv<0, 1, T, 32>), slice_blocks(S.nslices, th), th, s, e0, e1, S.nslices,
-                         S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L),
-                         LV<T>::x(L), rc, shape_arg(th, xcd));
-    else
-      launch_timed((k_sell_spmv<0, 1, T>), slice_blocks(S.nslices, th), th, s, e0, e1, S.nslices,
-                         S.srow, S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L),
-                         LV<T>::x(L), rc, shape_arg(th, xcd));
+  slice_launch(dv, S.nslices, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
+    with_var(var, [&](auto vc) {
+      constexpr int O = decltype(vc)::value;
+      if (S.wmax > 16)
+        launch_timed((k_sell_spmv<0, 1, T, 32, O>), slice_blocks(S.nslices, th, var), th, s, e0, e1, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L), LV<T>::x(L), rc,
+                     shape_arg(th, xcd));
+      else
+        launch_timed((k_sell_spmv<0, 1, T, 16, O>), slice_blocks(S.nslices, th, var), th, s, e0, e1, S.nslices, S.srow,
+                     S.soff, S.scol, sell_vals<T>(S), x, LV<T>::b(L), L.first_rows, LV<T>::id(L), LV<T>::x(L), rc,
+                     shape_arg(th, xcd));
+    });
   });
   if (dv->count_bytes)
-    dv->bytes += csr_bytes(A, sizeof(T)) + (double)A.ncols * sizeof(T) + (2.0 + (rc ? 1 : 0)) * A.nrows * sizeof(T) +
-                 (double)L.first_rows * sizeof(T);
+    dv->bytes += (double)S.nnz * (sizeof(T) + 4) + 4.0 * (S.nrows + 1) + (double)S.ncols_used * sizeof(T) +
+                 (2.0 + (rc ? 1 : 0)) * S.nrows * sizeof(T) + (double)L.first_rows * sizeof(T);
 }
 
 template <class T>
@@ -1670,7 +1766,7 @@ static T *lvl_x(Device *dv, int l) { return l == dv->lc ? cvec_x<T>(dv) : LV<T>:
 template <class T>
 static void restrict_to(Device *dv, const DCsr &A, const T *x, int l, hipStream_t s) {
   if (l == dv->lc)
-    spmv<T, 0>(dv, A, x, cvec_b<T>(dv), s);
+    spmv<T, 0>(dv, A, x, cvec_b<T>(dv), s, true);
   else
     spmv_first<T>(dv, A, x, dv->aux[l], s);
 }
@@ -1694,7 +1790,7 @@ static void vcycle(Device *dv, int l, hipStream_t s) {
   residual<T>(dv, L, b, x, LV<T>::r(L), s);
   restrict_to<T>(dv, L.PT, LV<T>::r(L), l - 1, s);
   vcycle<T>(dv, l - 1, s);
-  spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, s);
+  spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, s, true);
   for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, false, false, false, s);
 }
 
@@ -1723,7 +1819,7 @@ static void apply_Bco(Device *dv, const double *r, bool first_done, hipStream_t 
   residual<T>(dv, F, b, x, LV<T>::r(F), s);
   restrict_to<T>(dv, dv->PiT, LV<T>::r(F), dv->J, s);
   vcycle<T>(dv, dv->J, s);
-  spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, s);
+  spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, s, true);
   for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, false, false, false, s);
 }
 
@@ -1849,6 +1945,7 @@ static void tune(Device *dv, hipStream_t s) {
   tab.assign(t.size(), kShapes[0]);
   for (size_t site = 0; site < t.size(); ++site)
     tab[site] = kShapes[pick_shape(t[site])];
+  dv->tune_times[pi] = t;
   dv->tuned[pi] = true;
 }
 
@@ -2278,9 +2375,18 @@ std::vector<int64_t> device_tuned_shapes(Device *dv, int precision) {
   std::vector<int64_t> out;
   if (precision < 0 || precision > 1) return out;
   for (const auto &sh : dv->shape[precision]) {
-    out.push_back(sh.first);
-    out.push_back(sh.second);
+    out.push_back(sh.threads);
+    out.push_back(sh.xcd);
+    out.push_back(sh.var);
   }
+  return out;
+}
+
+std::vector<double> device_tune_times(Device *dv, int precision) {
+  std::vector<double> out;
+  if (precision < 0 || precision > 1) return out;
+  for (const auto &row : dv->tune_times[precision])
+    for (float t : row) out.push_back(std::isfinite(t) ? (double)t : -1.0);
   return out;
 }
 

@@ -34,9 +34,12 @@ int device_matvec(Device *dv, const double *d_x, double *d_y, void *stream);
 int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, double *d_g, double scale,
                             void *stream);
 int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes);
-// launch shapes picked by the autotuner for a precision: (threads per block, XCD order) per
-// slice-kernel launch site, flattened (empty before the first solve in that precision)
+// launch shapes picked by the autotuner for a precision: (threads per block, XCD order, kernel
+// variant) per slice-kernel launch site, flattened (empty before the first solve in that precision)
 std::vector<int64_t> device_tuned_shapes(Device *dv, int precision);
+// the autotuner's best time (ms) of every candidate shape at every launch site, site-major
+// (kNumShapes values per site; -1 where a candidate was not timed)
+std::vector<double> device_tune_times(Device *dv, int precision);
 // host-pointer solve through device staging buffers
 int device_solve_host(Device *dv, const double *f, double tol, double *u, int *iters, double *true_rel);
 

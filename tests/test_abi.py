@@ -128,3 +128,13 @@ def test_binding_rejects_wrong_sizes():
         A.Solver(coords, elems, np.ones(len(elems) + 1), device=-1)
     with pytest.raises(ValueError):
         A.Solver(coords, elems, np.ones(len(elems)), np.zeros(3, dtype=bool), device=-1)
+
+
+def test_python_shape_list_matches_the_library():
+    # the binding's list of autotuner candidates (used to label the tuning table) is the library's
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(A.__file__), "csrc", "common.hpp")).read()
+    body = re.search(r"kShapes\[\] = \{(.*?)\};", src, re.S).group(1)
+    triples = [tuple(int(v) for v in t) for t in re.findall(r"\{(\d+),\s*(\d+),\s*(\d+)\}", body)]
+    assert triples == [tuple(t) for t in A.SHAPES]

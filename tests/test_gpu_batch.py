@@ -49,6 +49,7 @@ def test_batched_fp64_matches_oracle(batch, nr):
     shapes = B.tuned_shapes(nr, A.PREC_FP64)
     assert len(shapes) > 10
     assert set(shapes[:, 0].tolist()) <= {128, 256, 512} and set(shapes[:, 1].tolist()) <= {0, 1}
+    assert set(shapes[:, 2].tolist()) <= {0, 1}
 
 
 def test_batched_mixed(batch):

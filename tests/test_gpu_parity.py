@@ -232,6 +232,8 @@ def test_autotuned_shapes_do_not_change_b_co(case):
     S.solve_device(torch.from_numpy(f).cuda(), 1e-8)
     shapes = S.tuned_shapes()
     assert len(shapes) > 0 and set(shapes[:, 0].tolist()) <= {128, 256, 512}
+    assert set(shapes[:, 2].tolist()) <= {0, 1}
+    assert S.tune_times().shape == (len(shapes), A.N_SHAPES)
     z1 = S.apply_preconditioner(r).cpu().numpy()
     assert np.array_equal(z0, z1)
 
