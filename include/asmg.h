@@ -101,6 +101,11 @@ typedef struct {
                           norms, q = A p), 1..2048; 0 = 2048 (default). Beyond the cap the kernels
                           loop over their rows (grid-stride). Results do not depend on it beyond
                           the summation order of the dot products. Single-mesh handles. */
+  int nb_layers;       /* near-boundary correction (Section 3.5, Algorithm 3): j > 0 = on every
+                          auxiliary level above the bottom, an exact solve on the unknowns within j
+                          layers of simplices of the level grid's boundary, before and after the
+                          coarse-grid correction (so that the V-cycle stays symmetric); 0 = off
+                          (default). Single-mesh handles with whole-level smoothing. */
 } asmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -268,6 +273,12 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "colour_aux"    int64 colour of every unknown of A_level (lc < level <= J)
  *   "local_set"     int64 0/1 per unknown of level `level` (lc < level <= J): member of N~_l
  *   "level_kept"    int64 0/1 per simplex of sigma^(level): kept in the Dirichlet grid
+ *   "coarse_inv"    double nc*nc: the explicit inverse of the bottom matrix A_lc (row-major),
+ *                   regularised on components whose rows sum to zero (pure Neumann problems)
+ *   "nb_set"        int64: near-boundary set J_{l,j} of level `level` (ascending unknown ids;
+ *                   empty without the option or off the levels above the bottom)
+ *   "nb_info"       int64[4] of level `level`: |J|, 1 = dense inverse / 0 = decomposed solve,
+ *                   interior unknowns, pieces
  *   "solve_stats"   int64[2]: PCG iterations and restarts from the true residual of the last
  *                   solve (device handles)
  *   "tuned_shapes"  int64 (threads per block, XCD order, kernel variant) per slice-kernel launch

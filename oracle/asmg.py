@@ -25,6 +25,10 @@
   proves the multigrid bound. The sweeps visit the same colours in the same
   order, restricted to those rows; residuals and transfers stay whole.
 
+* Near-boundary correction (option ``nb_layers`` = j > 0; Section 3.5, Algorithm 3): on every
+  level above the bottom, an exact solve on the unknowns J_{l,j} within j layers of the level
+  grid's boundary, before and after the coarse-grid correction (``nearbnd``).
+
 * Nested iteration (Section 5.2 starts CG from a nested iteration over the levels of the
   hierarchy, coarsest to finest). Reading: the levels are the auxiliary levels l_c..J and
   then the original grid. The load vector is carried down by the transposed transfers,
@@ -76,8 +80,9 @@ class Smoother:
 class ASMGPreconditioner:
     """B_co of Algorithm 1 with the V-cycle of Algorithm 2 on the auxiliary levels."""
 
-    def __init__(self, hier, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full"):
+    def __init__(self, hier, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full", nb_layers=0):
         from .auxops import local_set
+        from .nearbnd import ExactSolve, NearBoundary, near_boundary_set
         self.h = hier
         self.dtype = dtype
         self.nu_aux = nu_aux
@@ -100,9 +105,14 @@ class ASMGPreconditioner:
         if dtype == np.float64:
             self._coarse = ops.coarse_solve
         else:
-            Ac = ops.A[self.lc].toarray()
-            inv = np.linalg.inv(Ac).astype(dtype) if Ac.shape[0] else np.zeros((0, 0), dtype)
-            self._coarse = lambda g: inv @ g
+            self._coarse = ExactSolve(ops.A[self.lc], dtype)
+        # near-boundary correction (Section 3.5, Algorithm 3) on the levels above the bottom
+        self.nb = {}
+        if nb_layers > 0:
+            for l in range(self.lc + 1, self.J + 1):
+                J = near_boundary_set(hier.meshes.level(l), nb_layers)
+                if len(J):
+                    self.nb[l] = NearBoundary(ops.A[l], J, dtype)
 
     def vcycle(self, level, g):
         """Algorithm 2 (B_l applied to g)."""
@@ -111,10 +121,15 @@ class ASMGPreconditioner:
         S = self.aux[level]
         A = self.Aaux[level]
         e = np.zeros_like(g)
+        nb = self.nb.get(level)
         for _ in range(self.nu_aux):
             S.forward(e, g)
+        if nb is not None:     # before the coarse-grid correction too: B_l stays symmetric
+            nb.correct(e, g)
         r = g - A @ e
         e = e + self.P[level] @ self.vcycle(level - 1, self.PT[level] @ r)
+        if nb is not None:     # Algorithm 3: after the coarse-grid correction
+            nb.correct(e, g)
         for _ in range(self.nu_aux):
             S.backward(e, g)
         return e

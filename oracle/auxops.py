@@ -246,17 +246,11 @@ class AuxOperators:
             self.A[l] = stiffness(meshes, lm, ks, unit)
         for l in range(J, self.lc, -1):
             self.P[l] = prolongation(meshes, meshes.level(l), meshes.level(l - 1))
-        nc = sizes[self.lc]
-        if nc > 0:
-            Ac = self.A[self.lc].toarray()
-            self.chol = np.linalg.cholesky(Ac)   # lower triangular L, Ac = L L^T
-        else:
-            self.chol = np.zeros((0, 0))
+        # B_0 = A_0^{-1} by Cholesky; on a pure Neumann problem A_0 is singular, and each component
+        # with zero row sums is solved with its rank-one regularisation (nearbnd.regularised)
+        from .nearbnd import ExactSolve
+        self.coarse = ExactSolve(self.A[self.lc])
 
     def coarse_solve(self, g):
         """B_0 = A_0^{-1} (Algorithm 2): two triangular solves with the Cholesky factor."""
-        if len(g) == 0:
-            return g.copy()
-        import scipy.linalg as sla
-        y = sla.solve_triangular(self.chol, g, lower=True)
-        return sla.solve_triangular(self.chol.T, y, lower=False)
+        return self.coarse(g)

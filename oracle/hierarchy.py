@@ -30,6 +30,8 @@ class Hierarchy:
             from .domain import boundary_vertices
             dirichlet = boundary_vertices(elems, len(coords))
         self.A, self.dofs = fem.assemble(coords, elems, self.kappa, dirichlet)
+        # no Dirichlet vertex: a pure Neumann problem (A singular, constants in its kernel)
+        self.pure_neumann = len(self.dofs) == len(coords)
         self.tree = cluster.BoxTree(coords, elems, n_min, check_literal=check_literal)
         if domain not in ("box", "mesh", "mixed"):
             raise ValueError(domain)
@@ -54,17 +56,26 @@ class Hierarchy:
     def n(self):
         return len(self.dofs)
 
-    def preconditioner(self, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full"):
-        key = (np.dtype(dtype).name, nu_aux, nu_fine, smoothing)
+    def preconditioner(self, dtype=np.float64, nu_aux=2, nu_fine=1, smoothing="full", nb_layers=0):
+        key = (np.dtype(dtype).name, nu_aux, nu_fine, smoothing, nb_layers)
         if key not in self._B:
-            self._B[key] = asmg.ASMGPreconditioner(self, dtype, nu_aux, nu_fine, smoothing)
+            self._B[key] = asmg.ASMGPreconditioner(self, dtype, nu_aux, nu_fine, smoothing, nb_layers)
         return self._B[key]
 
     def solve(self, f, tol=1e-8, max_iter=1000, mixed=False, record=False, nu_aux=2, nu_fine=1,
-              smoothing="full", nested=0):
+              smoothing="full", nested=0, nb_layers=0):
         """PCG with B_co; ``nested`` > 0 starts from the nested iteration's guess with that many
-        V-cycles per auxiliary level (in the preconditioner's precision)."""
-        B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine, smoothing)
+        V-cycles per auxiliary level (in the preconditioner's precision); ``nb_layers`` > 0 adds
+        the near-boundary correction with that many layers.
+
+        Pure Neumann problem (every vertex an unknown, A singular with the constants as its
+        kernel): the solvable part of f is solved, f minus its mean (the projection onto the
+        range of A), and u is returned with zero mean; the stopping rule is relative to the
+        projected f."""
+        if self.pure_neumann:
+            f = np.asarray(f, dtype=np.float64)
+            f = f - f.mean()
+        B = self.preconditioner(np.float32 if mixed else np.float64, nu_aux, nu_fine, smoothing, nb_layers)
         if mixed:
             def Bm(r):
                 return B(r.astype(np.float32)).astype(np.float64)
@@ -73,7 +84,10 @@ class Hierarchy:
         u0 = None
         if nested > 0 and np.any(np.asarray(f) != 0):
             u0 = np.asarray(B.nested_guess(f, nested)).astype(np.float64)
-        return pcg.pcg(self.A, f, Bm, tol, max_iter, record, u0=u0)
+        u, it, info = pcg.pcg(self.A, f, Bm, tol, max_iter, record, u0=u0)
+        if self.pure_neumann:
+            u = u - u.mean()
+        return u, it, info
 
     def level_sizes(self):
         return {l: self.meshes.level(l).n for l in range(1, self.tree.J + 1)}

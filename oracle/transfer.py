@@ -18,7 +18,9 @@ Scott and Zhang's (d-1)-simplex construction.
   on each piece: Simpson on segments, and the edge-midpoint rule on the
   triangles of a fan of each polygon. A piece lying in a facet of an auxiliary
   simplex is met by the two simplices sharing that facet, and counts 1/2 from
-  each.
+  each; a facet on the boundary of the root box belongs to one simplex, and a piece
+  there counts fully (this matters where boundary vertices are unknowns: the
+  mixed and Neumann grids).
 
 Pins: P1 reproduction (with the nodal values of a linear function on all
 auxiliary vertices, the result equals its values at the original vertices,
@@ -165,6 +167,16 @@ class LeafIndex:
         return out
 
 
+def _facet_weight(lm, s, m):
+    """Weight of a piece of sigma_i lying in the facet of simplex s opposite its vertex m: 1/2 for
+    a facet shared by two simplices (each counts half), 1 for a facet on the boundary of the root
+    box (one simplex has it)."""
+    F = np.delete(lm.verts[lm.simp[s]], m, axis=0)
+    top = 1 << lm.J
+    on_root = any(np.all(F[:, q] == 0) or np.all(F[:, q] == top) for q in range(lm.d))
+    return 1.0 if on_root else 0.5
+
+
 def transfer(tree, meshes, coords, elems, dof_vertices, all_aux_vertices=False):
     """Pi as a sparse matrix (n_fine_unknowns x n_aux), n_aux = unknowns of sigma^(J).
 
@@ -193,8 +205,8 @@ def transfer(tree, meshes, coords, elems, dof_vertices, all_aux_vertices=False):
                 if iv is None:
                     continue
                 t0, t1 = iv
-                on_facet = any(lam[0][m] == 0.0 and lam[1][m] == 0.0 for m in range(3))
-                wgt = 0.5 if on_facet else 1.0
+                on = [m for m in range(3) if lam[0][m] == 0.0 and lam[1][m] == 0.0]
+                wgt = _facet_weight(lm, s, on[0]) if on else 1.0
                 tm = 0.5 * (t0 + t1)
                 for m in range(3):
                     def f(t):
@@ -209,8 +221,8 @@ def transfer(tree, meshes, coords, elems, dof_vertices, all_aux_vertices=False):
                 poly = _clip_polygon([(0.0, 0.0), (1.0, 0.0), (0.0, 1.0)], coef)
                 if len(poly) < 3:
                     continue
-                on_facet = any(c[0] == 0.0 and c[1] == 0.0 and c[2] == 0.0 for c in coef)
-                wgt = 0.5 if on_facet else 1.0
+                on = [m for m in range(4) if coef[m][0] == 0.0 and coef[m][1] == 0.0 and coef[m][2] == 0.0]
+                wgt = _facet_weight(lm, s, on[0]) if on else 1.0
                 for m in range(4):
                     c = col_of_vert[lm.simp[s][m]]
                     if c < 0:

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("colour_seed", ctypes.c_uint32), ("device", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("colouring", ctypes.c_int), ("smoothing", ctypes.c_int), ("domain", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("nested", ctypes.c_int),
-                ("setup_device", ctypes.c_int), ("red_blocks", ctypes.c_int)]
+                ("setup_device", ctypes.c_int), ("red_blocks", ctypes.c_int), ("nb_layers", ctypes.c_int)]
 
 
 def _load():
@@ -136,7 +136,8 @@ class Solver:
 
     def __init__(self, coords, elems, kappa, dirichlet=None, *, device=0, precision=PREC_FP64, n_min=0,
                  nu_aux=2, nu_fine=1, coarse_max_dofs=1024, max_iter=1000, colour_seed=0, check_every=0,
-                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0, setup_device=0, red_blocks=0):
+                 colouring=2, smoothing=0, domain=0, autotune=1, nested=0, setup_device=0, red_blocks=0,
+                 nb_layers=0):
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         elems = np.ascontiguousarray(elems, dtype=np.int32)
         if coords.ndim != 2 or elems.ndim != 2 or elems.shape[1] != coords.shape[1] + 1:
@@ -157,6 +158,7 @@ class Solver:
         opt.nested = nested
         opt.setup_device = setup_device
         opt.red_blocks = red_blocks
+        opt.nb_layers = nb_layers
         self.precision = precision
         self.coef_version = 0   # bumped by every coefficient change (host or device)
         self.device = device
@@ -289,7 +291,8 @@ class Solver:
         cnt = ctypes.c_int64()
         _check(lib.asmg_export(self.h, name.encode(), level, None, ctypes.byref(cnt)))
         if dtype is None:
-            dtype = np.float64 if name.endswith("_val") or name in ("setup_seconds", "leaf_kappa") else np.int64
+            dtype = (np.float64 if name.endswith("_val") or name in ("setup_seconds", "leaf_kappa", "coarse_inv",
+                                                                       "tune_times") else np.int64)
         buf = np.empty(cnt.value, dtype=dtype)
         if cnt.value:
             _check(lib.asmg_export(self.h, name.encode(), level, _ptr(buf), ctypes.byref(cnt)))

@@ -36,7 +36,8 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = []
-    for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("domain.cpp", ["-ffp-contract=off"]), ("api.cpp", [])):
+    for src, extra in (("setup.cpp", ["-ffp-contract=off"]), ("domain.cpp", ["-ffp-contract=off"]),
+                       ("nearbnd.cpp", []), ("api.cpp", [])):
         obj = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
         jobs.append([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     # the device setup reproduces the host setup's IEEE operations: no contraction there either

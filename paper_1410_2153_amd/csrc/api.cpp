@@ -109,6 +109,7 @@ int asmg_default_options(asmg_options *o) {
   o->nested = 0;
   o->setup_device = 0;
   o->red_blocks = 0;
+  o->nb_layers = 0;
   return ASMG_OK;
 }
 
@@ -127,8 +128,11 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
       (o.precision != ASMG_PREC_FP64 && o.precision != ASMG_PREC_MIXED) || o.n_min < 0 || o.colouring < 0 ||
       o.colouring > 2 || o.smoothing < 0 || o.smoothing > 1 || o.domain < 0 || o.domain > 2 ||
       (o.domain >= 1 && dim != 2) || o.nested < 0 || o.nested > 16 || o.setup_device < 0 || o.setup_device > 1 ||
-      (o.setup_device == 1 && o.device < 0) || o.red_blocks < 0 || o.red_blocks > 2048)
+      (o.setup_device == 1 && o.device < 0) || o.red_blocks < 0 || o.red_blocks > 2048 || o.nb_layers < 0 ||
+      o.nb_layers > 16)
     return set_err(ASMG_EINVAL, "invalid options");
+  if (o.nb_layers > 0 && o.smoothing != 0)
+    return set_err(ASMG_EINVAL, "the near-boundary correction needs whole-level smoothing (smoothing = 0)");
   if (o.nested > 0 && o.smoothing != 0)
     return set_err(ASMG_EINVAL, "the nested iteration needs whole-level smoothing (smoothing = 0)");
   for (int64_t i = 0; i < n_vertices * dim; ++i)
@@ -195,6 +199,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     {
       TraceRange r("asmg::setup::coarse");
       build_coarse(h);
+      build_near_boundary(h);
     }
     lap("coarse");
     if (o.device >= 0) {
@@ -217,6 +222,7 @@ int asmg_update_coefficient(asmg_handle H, const double *kappa) {
     assemble_fine_values(h);
     assemble_aux_values(h);
     build_coarse(h);
+    build_near_boundary(h);
     if (H->dev) device_update_values(H->dev, h);
     return ASMG_OK;
   })
@@ -342,6 +348,7 @@ static int check_options(const asmg_options &o) {
   if (o.smoothing != 0) return set_err(ASMG_EINVAL, "local smoothing is available on single-mesh handles only");
   if (o.nested != 0) return set_err(ASMG_EINVAL, "the nested iteration is available on single-mesh handles only");
   if (o.setup_device != 0) return set_err(ASMG_EINVAL, "the device tree build is available on single-mesh handles only");
+  if (o.nb_layers != 0) return set_err(ASMG_EINVAL, "the near-boundary correction is available on single-mesh handles only");
   return ASMG_OK;
 }
 
@@ -520,6 +527,27 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
         for (size_t i = 0; i < k.size(); ++i) k[i] = lm.kept[i];
       return put(k, buf, count);
     }
+    if (name == "nb_set") {  // level: the near-boundary set, ascending unknown ids
+      auto it = h.nb.find(level);
+      std::vector<int64_t> v;
+      if (it != h.nb.end()) {
+        v = it->second.J;
+        std::sort(v.begin(), v.end());
+      }
+      return put(v, buf, count);
+    }
+    if (name == "nb_info") {  // level: |J|, dense (1) or decomposed (0), interior size, pieces
+      auto it = h.nb.find(level);
+      std::vector<int64_t> v(4, 0);
+      if (it != h.nb.end()) {
+        v[0] = (int64_t)it->second.J.size();
+        v[1] = it->second.dense ? 1 : 0;
+        v[2] = it->second.nI;
+        v[3] = it->second.poff.empty() ? 0 : (int64_t)it->second.poff.size() - 1;
+      }
+      return put(v, buf, count);
+    }
+    if (name == "coarse_inv") return put(h.coarse_inv, buf, count);
     if (name == "solve_stats") {
       if (!H->dev) return set_err(ASMG_EINVAL, "host-only handle");
       std::vector<int64_t> v = {device_last_iterations(H->dev), device_restarts(H->dev)};

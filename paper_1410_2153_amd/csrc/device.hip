@@ -47,7 +47,7 @@ namespace asmg {
 // ---------------------------------------------------------------------------
 
 struct Ctl {
-  double rho, pq, rr, alpha, beta, fnorm2, tol2, rz, tr;
+  double rho, pq, rr, alpha, beta, fnorm2, tol2, rz, tr, mean;
   int iter, done, status, maxit, first, pad;
   unsigned ticket;
 };
@@ -687,6 +687,97 @@ __global__ __launch_bounds__(BS) void k_exp(int ne, const double *__restrict__ m
 }
 
 // ---------------------------------------------------------------------------
+// pure Neumann problems: the mean of a vector and its removal
+// ---------------------------------------------------------------------------
+
+// partials of sum_i x_i (grid-stride)
+__global__ __launch_bounds__(BS) void k_sum(int n, const double *__restrict__ x, double *__restrict__ partials) {
+  double v = 0.0;
+  for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) v += x[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(BS) void k_fin_mean(const double *__restrict__ partials, int nb, int n, Ctl *ctl) {
+  const double t = sum_partials(partials, nb);
+  if (threadIdx.x == 0) ctl->mean = t / (double)n;
+}
+
+// x -= mean (the projection onto the vectors with zero sum)
+__global__ __launch_bounds__(BS) void k_sub_mean(int n, double *__restrict__ x, const Ctl *ctl) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) x[i] -= ctl->mean;
+}
+
+// ---------------------------------------------------------------------------
+// near-boundary correction (Section 3.5, Algorithm 3): e|_J += (A|_JJ)^-1 (g - A e)|_J
+// Positions k of J are in the solver's order; jrow[k] is the level's internal row.
+// ---------------------------------------------------------------------------
+
+// rJ_k = g_i - a_ii e_i - sum_{j != i} a_ij e_j, i = jrow[k] (sliced ELL over the positions)
+template <class T>
+__global__ __launch_bounds__(BS) void k_nb_res(int ns, const int *__restrict__ srow, const int *__restrict__ soff,
+                                               const int *__restrict__ scol, const T *__restrict__ sv,
+                                               const int *__restrict__ jrow, const T *__restrict__ dg,
+                                               const T *__restrict__ g, const T *__restrict__ e, T *__restrict__ rJ) {
+  const int lane = threadIdx.x & 63;
+  for_slices<0>(0, ns, 2 * (BS / 64) + 1, srow, soff, [&](int k, int o0, int w) {
+    T gi = 0, di = 0, ei = 0;
+    auto pre = [&] {
+      const int i = jrow[k < 0 ? 0 : k];
+      gi = g[i];
+      di = dg[i];
+      ei = e[i];
+    };
+    auto post = [&](T acc) {
+      pin(gi);
+      pin(di);
+      pin(ei);
+      if (k >= 0) rJ[k] = gi - di * ei - acc;
+    };
+    sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, e, pre, post);
+  });
+}
+
+// one wave per row i of the interiors: s = sum_j B_p[i - q0, j] in[q0 + j] over the dense inverse
+// of row i's piece p; out_i = s, or base_i - s
+template <class T>
+__global__ __launch_bounds__(BS) void k_nb_blk(int nI, const int *__restrict__ rowpiece, const int *__restrict__ poff,
+                                               const int64_t *__restrict__ boff, const T *__restrict__ blk,
+                                               const T *__restrict__ in, const T *__restrict__ base,
+                                               T *__restrict__ out) {
+  const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nI) return;  // the whole wave leaves together
+  const int p = rowpiece[i], q0 = poff[p], m = poff[p + 1] - q0;
+  const T *B = blk + boff[p] + (int64_t)(i - q0) * m;
+  T acc = 0;
+  for (int j = lane; j < m; j += 64) acc += B[j] * in[q0 + j];
+  acc = group_sum<64>(acc);
+  if (lane == 0) out[i] = base ? base[i] - acc : acc;
+}
+
+// one thread per row of a small CSR coupling: out_i = s or base_i - s, s = sum_p v_p x[ci_p]
+template <class T>
+__global__ __launch_bounds__(BS) void k_nb_csr(int nrows, const int *__restrict__ rp, const int *__restrict__ ci,
+                                               const T *__restrict__ v, const T *__restrict__ x,
+                                               const T *__restrict__ base, T *__restrict__ out) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= nrows) return;
+  T acc = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) acc += v[p] * x[ci[p]];
+  out[i] = base ? base[i] - acc : acc;
+}
+
+// e_i += xJ_k, i = jrow[k] (distinct rows)
+template <class T>
+__global__ __launch_bounds__(BS) void k_nb_add(int n, const int *__restrict__ jrow, const T *__restrict__ xJ,
+                                               T *__restrict__ e) {
+  const int k = blockIdx.x * BS + threadIdx.x;
+  if (k < n) e[jrow[k]] += xJ[k];
+}
+
+// ---------------------------------------------------------------------------
 // device data
 // ---------------------------------------------------------------------------
 
@@ -718,6 +809,25 @@ struct DSell {
   int nrows = 0, ncols_used = 0;
 };
 
+// near-boundary set of an auxiliary level on the device (positions in the solver's order)
+struct DNb {
+  int n = 0, nI = 0, nS = 0, P = 0;
+  bool dense = true;
+  int *jrow = nullptr;                 // internal level row of each position
+  DSell sell;                          // off-diagonal rows of A_l at the positions (srow = position)
+  int64_t nnz = 0;                     // byte model
+  double *inv64 = nullptr;             // dense path: n x n inverse
+  float *inv32 = nullptr;
+  int *rowpiece = nullptr, *poff = nullptr;  // decomposition: piece of each interior row, offsets
+  int64_t *boff = nullptr;
+  double *blk64 = nullptr, *asi64 = nullptr, *ais64 = nullptr, *sinv64 = nullptr;
+  float *blk32 = nullptr, *asi32 = nullptr, *ais32 = nullptr, *sinv32 = nullptr;
+  int *asi_rp = nullptr, *asi_ci = nullptr, *ais_rp = nullptr, *ais_ci = nullptr;
+  int64_t nblk = 0, nasi = 0, nais = 0;
+  double *r64 = nullptr, *x64 = nullptr, *y64 = nullptr, *t64 = nullptr;  // work vectors
+  float *r32 = nullptr, *x32 = nullptr, *y32 = nullptr, *t32 = nullptr;
+};
+
 struct DLevel {
   int n = 0;
   DSell sell;                 // off-diagonal part of the smoothed rows, one slice group per range below
@@ -741,6 +851,7 @@ struct DLevel {
   double *ng64 = nullptr, *ne64 = nullptr;  // nested iteration: load vector g_l and iterate e_l
   float *ng32 = nullptr, *ne32 = nullptr;
   DCsr P, PT;                 // from the next coarser level (aux levels only)
+  DNb nb;                     // near-boundary correction (n = 0: none)
 };
 
 struct Device {
@@ -759,6 +870,7 @@ struct Device {
   double *cng64 = nullptr, *cne64 = nullptr;  // nested iteration at the bottom level
   float *cng32 = nullptr, *cne32 = nullptr;
   int nested = 0;             // V-cycles per level of the nested iteration (0 = u_0 = 0)
+  bool pure_neumann = false;  // every vertex an unknown: A singular, f projected, u mean-free
   int *perm_d = nullptr;      // fine internal -> unknown
   // PCG vectors (internal order, FP64)
   double *f = nullptr, *u = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
@@ -1210,6 +1322,129 @@ static void stage_level(DLevel &L, const Csr &A, bool first_time, LevelStage &X)
   X.sell = sell_host(H, L.groups);
 }
 
+// host image of a level's near-boundary solver in the level's internal numbering
+struct NbStage {
+  bool has = false;
+  std::vector<int> jrow, rowpiece, poff, asi_rp, asi_ci, ais_rp, ais_ci;
+  std::vector<int64_t> boff;
+  std::vector<double> inv, blk, asi, ais, sinv;
+  SellHost sell;
+  int64_t nnz = 0;
+  int nI = 0, nS = 0, P = 0;
+  bool dense = true;
+};
+
+static void stage_nb(const NearBnd &nb, const DLevel &L, const HCsr &H, NbStage &X) {
+  const int n = (int)nb.J.size();
+  X.has = n > 0;
+  if (!X.has) return;
+  X.jrow.resize(n);
+  for (int k = 0; k < n; ++k) X.jrow[k] = L.iperm[nb.J[k]];
+  HCsr R;
+  R.nrows = n;
+  R.ncols = H.ncols;
+  R.rp.assign(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    const int i = X.jrow[k];
+    for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+      R.ci.push_back(H.ci[p]);
+      R.v.push_back(H.v[p]);
+    }
+    R.rp[k + 1] = (int)R.ci.size();
+  }
+  X.nnz = (int64_t)R.ci.size();
+  X.sell = sell_host(R, Ranges{{0, n}});
+  X.dense = nb.dense;
+  if (nb.dense) {
+    X.inv = nb.inv;
+    return;
+  }
+  X.nI = nb.nI;
+  X.nS = n - nb.nI;
+  X.P = (int)nb.poff.size() - 1;
+  X.poff.assign(nb.poff.begin(), nb.poff.end());
+  X.boff = nb.boff;
+  X.rowpiece.resize(nb.nI);
+  for (int p = 0; p < X.P; ++p)
+    for (int64_t i = nb.poff[p]; i < nb.poff[p + 1]; ++i) X.rowpiece[i] = p;
+  X.blk = nb.blocks;
+  X.asi_rp.assign(nb.ASI.rp.begin(), nb.ASI.rp.end());
+  X.asi_ci.assign(nb.ASI.ci.begin(), nb.ASI.ci.end());
+  X.asi = nb.ASI.v;
+  X.ais_rp.assign(nb.AIS.rp.begin(), nb.AIS.rp.end());
+  X.ais_ci.assign(nb.AIS.ci.begin(), nb.AIS.ci.end());
+  X.ais = nb.AIS.v;
+  X.sinv = nb.sinv;
+}
+
+static std::vector<float> to32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+
+template <class T>
+static void dcopy(T *d, const std::vector<T> &v) {
+  if (!v.empty()) HIPCHECK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static void commit_nb(Device *dv, DNb &D, const NbStage &X, bool first_time) {
+  if (!X.has) return;
+  if (first_time) {
+    D.n = (int)X.jrow.size();
+    D.dense = X.dense;
+    D.nI = X.nI;
+    D.nS = X.nS;
+    D.P = X.P;
+    D.nnz = X.nnz;
+    D.jrow = dupload(dv, X.jrow);
+    sell_upload(dv, D.sell, X.sell, true);
+    if (X.dense) {
+      D.inv64 = dupload(dv, X.inv);
+      D.inv32 = dupload(dv, to32(X.inv));
+    } else {
+      D.rowpiece = dupload(dv, X.rowpiece);
+      D.poff = dupload(dv, X.poff);
+      D.boff = dupload(dv, X.boff);
+      D.blk64 = dupload(dv, X.blk);
+      D.blk32 = dupload(dv, to32(X.blk));
+      D.asi_rp = dupload(dv, X.asi_rp);
+      D.asi_ci = dupload(dv, X.asi_ci);
+      D.asi64 = dupload(dv, X.asi);
+      D.asi32 = dupload(dv, to32(X.asi));
+      D.ais_rp = dupload(dv, X.ais_rp);
+      D.ais_ci = dupload(dv, X.ais_ci);
+      D.ais64 = dupload(dv, X.ais);
+      D.ais32 = dupload(dv, to32(X.ais));
+      D.sinv64 = dupload(dv, X.sinv);
+      D.sinv32 = dupload(dv, to32(X.sinv));
+      D.nblk = (int64_t)X.blk.size();
+      D.nasi = (int64_t)X.asi.size();
+      D.nais = (int64_t)X.ais.size();
+    }
+    D.r64 = dalloc<double>(dv, D.n);
+    D.x64 = dalloc<double>(dv, D.n);
+    D.y64 = dalloc<double>(dv, D.n);
+    D.t64 = dalloc<double>(dv, D.n);
+    D.r32 = dalloc<float>(dv, D.n);
+    D.x32 = dalloc<float>(dv, D.n);
+    D.y32 = dalloc<float>(dv, D.n);
+    D.t32 = dalloc<float>(dv, D.n);
+    return;
+  }
+  // new coefficient: the same structure, new values
+  sell_upload(dv, D.sell, X.sell, false);
+  if (X.dense) {
+    dcopy(D.inv64, X.inv);
+    dcopy(D.inv32, to32(X.inv));
+  } else {
+    dcopy(D.blk64, X.blk);
+    dcopy(D.blk32, to32(X.blk));
+    dcopy(D.asi64, X.asi);
+    dcopy(D.asi32, to32(X.asi));
+    dcopy(D.ais64, X.ais);
+    dcopy(D.ais32, to32(X.ais));
+    dcopy(D.sinv64, X.sinv);
+    dcopy(D.sinv32, to32(X.sinv));
+  }
+}
+
 // upload a staged level; `csr`: also keep a device CSR of the off-diagonal part (original grid)
 static void commit_level(Device *dv, DLevel &L, const LevelStage &X, bool first_time, bool csr) {
   if (first_time) {
@@ -1368,6 +1603,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
     const int naux = h.J - h.lc;
     LevelStage fine_st;
     std::vector<LevelStage> aux_st(naux);
+    std::vector<NbStage> nb_st(naux);
     std::vector<TransferStage> p_st(naux), pt_st(naux);
     TransferStage pi_st, pit_st;
     const std::vector<int> *pi_cmap = h.J > h.lc ? &dv->aux[h.J].iperm : nullptr;
@@ -1375,10 +1611,13 @@ Device *device_create(Hierarchy &h, int ordinal) {
     for (size_t i = 0; i < mrank.size(); ++i) forder[mrank[i]] = dv->fine.iperm[i];
     // tasks: Pi and Pi^T first (the largest), then the fine operator, the levels, the prolongations
     // last colour of a level with whole-level smoothing, [first row, end) in internal numbering
-    auto last_colour = [&](const DLevel &L) {
-      return (L.local || L.C < 1) ? std::make_pair(0, 0) : std::make_pair(L.coff[L.C - 1], L.coff[L.C]);
+    auto last_colour = [&](const DLevel &L, int l) {
+      // a level with the near-boundary correction computes its residual on every row and
+      // prolongs onto every row (the correction reads them)
+      if (L.local || L.C < 1 || (l > 0 && h.nb.count(l))) return std::make_pair(0, 0);
+      return std::make_pair(L.coff[L.C - 1], L.coff[L.C]);
     };
-    const auto fl = last_colour(dv->fine);
+    const auto fl = last_colour(dv->fine, 0);
     host_parallel(h.threads, 3 + 2 * naux, [&](int t) {
       if (t == 0) {
         const HCsr Pi = permute(h.Pi, dv->fine.perm, pi_cmap, false, nullptr);
@@ -1393,6 +1632,8 @@ Device *device_create(Hierarchy &h, int ordinal) {
       } else if (t < 3 + naux) {
         const int l = h.J - (t - 3);
         stage_level(dv->aux[l], h.Al.at(l), true, aux_st[t - 3]);
+        auto it = h.nb.find(l);
+        if (it != h.nb.end()) stage_nb(it->second, dv->aux[l], aux_st[t - 3].H, nb_st[t - 3]);
       } else {
         const int i = t - 3 - naux, l = h.J - i;
         DLevel &L = dv->aux[l];
@@ -1401,7 +1642,7 @@ Device *device_create(Hierarchy &h, int ordinal) {
         const HCsr PT = transpose(P);
         stage_transfer(P, &L.iperm, p_st[i]);
         stage_transfer(PT, cmap, pt_st[i]);
-        const auto ll = last_colour(L);
+        const auto ll = last_colour(L, l);
         if (ll.second > ll.first) {
           stage_prolong_v(P, L.iperm, ll.first, ll.second, p_st[i]);
           stage_restrict_v(PT, cmap, ll.first, ll.second, pt_st[i]);
@@ -1418,7 +1659,10 @@ Device *device_create(Hierarchy &h, int ordinal) {
       commit_level(dv, dv->aux[l], X, true, false);
       X = LevelStage();
       alloc_vectors(dv, dv->aux[l]);
+      commit_nb(dv, dv->aux[l].nb, nb_st[h.J - l], true);
+      nb_st[h.J - l] = NbStage();
     }
+    dv->pure_neumann = h.n() == h.nv;
     for (int l = h.J; l > h.lc; --l) {
       commit_transfer(dv, p_st[h.J - l], dv->aux[l].P);
       commit_transfer(dv, pt_st[h.J - l], dv->aux[l].PT);
@@ -1478,14 +1722,22 @@ void device_update_values(Device *dv, Hierarchy &h) {
   HIPCHECK(hipSetDevice(dv->ordinal));
   const int naux = h.J - h.lc;
   std::vector<LevelStage> st(1 + naux);
+  std::vector<NbStage> nst(1 + naux);
   host_parallel(h.threads, 1 + naux, [&](int t) {
-    if (t == 0)
+    if (t == 0) {
       stage_level(dv->fine, h.A, false, st[0]);
-    else
-      stage_level(dv->aux[h.J - (t - 1)], h.Al.at(h.J - (t - 1)), false, st[t]);
+    } else {
+      const int l = h.J - (t - 1);
+      stage_level(dv->aux[l], h.Al.at(l), false, st[t]);
+      auto it = h.nb.find(l);
+      if (it != h.nb.end()) stage_nb(it->second, dv->aux[l], st[t].H, nst[t]);
+    }
   });
   commit_level(dv, dv->fine, st[0], false, true);
-  for (int l = h.J; l > h.lc; --l) commit_level(dv, dv->aux[l], st[h.J - l + 1], false, false);
+  for (int l = h.J; l > h.lc; --l) {
+    commit_level(dv, dv->aux[l], st[h.J - l + 1], false, false);
+    commit_nb(dv, dv->aux[l].nb, nst[h.J - l + 1], false);
+  }
   upload_coarse(dv, h, false);
   HIPCHECK(hipMemcpy(dv->kappa, h.kappa.data(), h.kappa.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipDeviceSynchronize());
@@ -1771,8 +2023,86 @@ static void restrict_to(Device *dv, const DCsr &A, const T *x, int l, hipStream_
     spmv_first<T>(dv, A, x, dv->aux[l], s);
 }
 
+// per-precision arrays of a near-boundary set
+template <class T>
+struct NbV;
+template <>
+struct NbV<double> {
+  static const double *inv(const DNb &N) { return N.inv64; }
+  static const double *blk(const DNb &N) { return N.blk64; }
+  static const double *asi(const DNb &N) { return N.asi64; }
+  static const double *ais(const DNb &N) { return N.ais64; }
+  static const double *sinv(const DNb &N) { return N.sinv64; }
+  static double *r(const DNb &N) { return N.r64; }
+  static double *x(const DNb &N) { return N.x64; }
+  static double *t(const DNb &N) { return N.t64; }
+};
+template <>
+struct NbV<float> {
+  static const float *inv(const DNb &N) { return N.inv32; }
+  static const float *blk(const DNb &N) { return N.blk32; }
+  static const float *asi(const DNb &N) { return N.asi32; }
+  static const float *ais(const DNb &N) { return N.ais32; }
+  static const float *sinv(const DNb &N) { return N.sinv32; }
+  static float *r(const DNb &N) { return N.r32; }
+  static float *x(const DNb &N) { return N.x32; }
+  static float *t(const DNb &N) { return N.t32; }
+};
+
+// Near-boundary correction of level L (Section 3.5, Algorithm 3): x|_J += (A|_JJ)^-1 (b - A x)|_J.
+// The solve is a dense inverse, or over the decomposition of J into interiors I (pieces with
+// dense inverses) and separator S: y = A_II^-1 r_I, x_S = S^-1 (r_S - A_SI y),
+// x_I = A_II^-1 (r_I - A_IS x_S), with S = A_SS - A_SI A_II^-1 A_IS inverted at setup.
+template <class T>
+static void nb_correct(Device *dv, DLevel &L, T *x, const T *b, hipStream_t s) {
+  const DNb &N = L.nb;
+  if (N.n == 0) return;
+  T *r = NbV<T>::r(N), *xj = NbV<T>::x(N), *t = NbV<T>::t(N);
+  const DSell &S = N.sell;
+  if (S.nslices > 0)
+    hipLaunchKernelGGL((k_nb_res<T>), dim3(slice_blocks(S.nslices, BS)), dim3(BS), 0, s, S.nslices, S.srow, S.soff,
+                       S.scol, sell_vals<T>(S), N.jrow, LV<T>::dg(L), b, (const T *)x, r);
+  if (N.dense) {
+    hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)N.n * 64)), dim3(BS), 0, s, N.n, NbV<T>::inv(N), (const T *)r,
+                       xj);
+  } else {
+    const int nI = N.nI, nS = N.nS;
+    T *y = sizeof(T) == 8 ? (T *)N.y64 : (T *)N.y32;
+    if (nI > 0)
+      hipLaunchKernelGGL((k_nb_blk<T>), dim3(nblk((int64_t)nI * 64)), dim3(BS), 0, s, nI, N.rowpiece, N.poff, N.boff,
+                         NbV<T>::blk(N), (const T *)r, (const T *)nullptr, y);
+    if (nS > 0) {
+      hipLaunchKernelGGL((k_nb_csr<T>), dim3(nblk(nS)), dim3(BS), 0, s, nS, N.asi_rp, N.asi_ci, NbV<T>::asi(N),
+                         (const T *)y, (const T *)(r + nI), t);
+      hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)nS * 64)), dim3(BS), 0, s, nS, NbV<T>::sinv(N), (const T *)t,
+                         xj + nI);
+    }
+    if (nI > 0) {
+      hipLaunchKernelGGL((k_nb_csr<T>), dim3(nblk(nI)), dim3(BS), 0, s, nI, N.ais_rp, N.ais_ci, NbV<T>::ais(N),
+                         (const T *)(xj + nI), (const T *)r, t);
+      hipLaunchKernelGGL((k_nb_blk<T>), dim3(nblk((int64_t)nI * 64)), dim3(BS), 0, s, nI, N.rowpiece, N.poff, N.boff,
+                         NbV<T>::blk(N), (const T *)t, (const T *)nullptr, xj);
+    }
+  }
+  hipLaunchKernelGGL((k_nb_add<T>), dim3(nblk(N.n)), dim3(BS), 0, s, N.n, N.jrow, (const T *)xj, x);
+  if (dv->count_bytes) {
+    // residual: matrix entries, position and row index, b, diagonal and x at the row, the result;
+    // the solve's matrices once; the add: row index, the correction, x read and written
+    double by = (double)N.nnz * (sizeof(T) + 4) + (double)N.n * (8 + 4 * sizeof(T));
+    if (N.dense)
+      by += (double)N.n * N.n * sizeof(T) + 2.0 * N.n * sizeof(T);
+    else
+      by += 2.0 * N.nblk * sizeof(T) + (double)(N.nasi + N.nais) * (sizeof(T) + 4) + (double)N.nS * N.nS * sizeof(T) +
+            6.0 * N.n * sizeof(T);
+    by += (double)N.n * (4 + 3 * sizeof(T));
+    dv->bytes += by;
+  }
+}
+
 // Algorithm 2: B_l applied to the level's b, result in the level's x. Above the bottom, the
-// colour-0 pass of the first forward sweep has been run by the restriction that wrote b.
+// colour-0 pass of the first forward sweep has been run by the restriction that wrote b. A level
+// with a near-boundary set corrects on it before and after the coarse-grid correction (the
+// symmetric form of Algorithm 3: B_l stays symmetric); its residual then covers every row.
 template <class T>
 static void vcycle(Device *dv, int l, hipStream_t s) {
   if (l == dv->lc) {
@@ -1786,11 +2116,14 @@ static void vcycle(Device *dv, int l, hipStream_t s) {
   DLevel &L = dv->aux[l];
   T *x = LV<T>::x(L);
   T *b = LV<T>::b(L);
+  const bool nb = L.nb.n > 0;
   for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, k == 0, true, true, s);
-  residual<T>(dv, L, b, x, LV<T>::r(L), s);
+  if (nb) nb_correct<T>(dv, L, x, b, s);
+  residual<T>(dv, L, b, x, LV<T>::r(L), s, nb);
   restrict_to<T>(dv, L.PT, LV<T>::r(L), l - 1, s);
   vcycle<T>(dv, l - 1, s);
   spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, s, true);
+  if (nb) nb_correct<T>(dv, L, x, b, s);
   for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, false, false, false, s);
 }
 
@@ -1988,6 +2321,15 @@ static void launch_iterations(Device *dv, int k, hipStream_t s) {
   }
 }
 
+// x -= mean(x) over the fine unknowns (pure Neumann problems: the constants span the kernel of A)
+static void project_mean(Device *dv, double *x, hipStream_t s) {
+  const int n = dv->fine.n;
+  const int g = red_grid(dv, n, 1);
+  hipLaunchKernelGGL(k_sum, dim3(g), dim3(BS), 0, s, n, (const double *)x, dv->partials);
+  hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(BS), 0, s, (const double *)dv->partials, g, n, dv->ctl);
+  hipLaunchKernelGGL(k_sub_mean, dim3(nblk(n)), dim3(BS), 0, s, n, x, (const Ctl *)dv->ctl);
+}
+
 template <class T>
 static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t s) {
   TraceRange tr_pcg(sizeof(T) == 4 ? "asmg::pcg(mixed)" : "asmg::pcg(fp64)");
@@ -1995,6 +2337,7 @@ static int pcg(Device *dv, double tol, int *iters, double *true_rel, hipStream_t
   const int pi = sizeof(T) == 4 ? 1 : 0;
   DLevel &F = dv->fine;
   const int gi = red_grid(dv, n, 1);
+  if (dv->pure_neumann) project_mean(dv, dv->f, s);  // the part of f in the range of A
   hipLaunchKernelGGL(k_cg_init, dim3(gi), dim3(BS), 0, s, n, dv->f, dv->r, dv->u, dv->p, dv->partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, s, dv->partials, gi, tol, dv->maxit, dv->ctl);
   if (dv->nested > 0) nested_start<T>(dv, s);  // u = u_0, r = f - A u_0
@@ -2072,6 +2415,7 @@ int device_solve(Device *dv, const double *d_f, double tol, double *d_u, int *it
   hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, d_f, dv->f);
   const int rc = dv->precision == ASMG_PREC_MIXED ? pcg<float>(dv, tol, iters, true_rel, s)
                                                    : pcg<double>(dv, tol, iters, true_rel, s);
+  if (dv->pure_neumann) project_mean(dv, dv->u, s);  // the solution with zero mean
   hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(BS), 0, s, n, dv->perm_d, dv->u, d_u);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipEventRecord(dv->ev_out, s));

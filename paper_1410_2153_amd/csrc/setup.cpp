@@ -1141,6 +1141,23 @@ void build_transfer(Hierarchy &h) {
   Csr &Pi = h.Pi;
   Pi.nrows = n;
   Pi.ncols = lm.n();
+  // A piece of sigma_i lying in the facet of simplex s opposite its vertex m is met by the two
+  // simplices sharing that facet and counts 1/2 from each; a facet on the boundary of the root
+  // box belongs to one simplex and counts fully.
+  const int64_t top = (int64_t)1 << h.J;
+  auto facet_weight = [&](int64_t s, int m) {
+    for (int q = 0; q < d; ++q) {
+      bool lo_all = true, hi_all = true;
+      for (int a = 0; a < k; ++a) {
+        if (a == m) continue;
+        const int64_t x = lm.verts[lm.simp[s * k + a] * d + q];
+        lo_all = lo_all && x == 0;
+        hi_all = hi_all && x == top;
+      }
+      if (lo_all || hi_all) return 1.0;
+    }
+    return 0.5;
+  };
   // rows in chunks on parallel threads, concatenated in order
   const int64_t CH = 4096;
   const int64_t nch = (n + CH - 1) / CH;
@@ -1195,10 +1212,11 @@ void build_transfer(Hierarchy &h) {
             l[2] = cross(T[0][0] - x, T[0][1] - y, T[1][0] - x, T[1][1] - y) / a2;
           }
           double t0 = 0.0, t1 = 1.0;
-          bool empty = false, on_facet = false;
+          bool empty = false;
+          int on_facet = -1;
           for (int m = 0; m < 3; ++m) {
             const double sl = l1[m] - l0[m];
-            if (l0[m] == 0.0 && l1[m] == 0.0) on_facet = true;
+            if (l0[m] == 0.0 && l1[m] == 0.0 && on_facet < 0) on_facet = m;
             if (sl == 0.0) {
               if (l0[m] < 0.0) empty = true;
               continue;
@@ -1210,7 +1228,7 @@ void build_transfer(Hierarchy &h) {
               t1 = std::min(t1, tc);
           }
           if (empty || !(t1 > t0)) continue;
-          const double wgt = on_facet ? 0.5 : 1.0, tm = 0.5 * (t0 + t1);
+          const double wgt = on_facet >= 0 ? facet_weight(s, on_facet) : 1.0, tm = 0.5 * (t0 + t1);
           for (int m = 0; m < 3; ++m) {
             if (cols[m] < 0) continue;
             auto f = [&](double t) { return (4.0 - 6.0 * t) * (l0[m] + t * (l1[m] - l0[m])); };
@@ -1243,10 +1261,10 @@ void build_transfer(Hierarchy &h) {
             }
           }
           std::vector<std::array<double, 2>> poly{{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}}, out;
-          bool on_facet = false;
+          int on_facet = -1;
           for (int m = 0; m < 4 && poly.size() >= 3; ++m) {
             const double c0 = c[m][0], c1 = c[m][1], c2 = c[m][2];
-            if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) on_facet = true;
+            if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0 && on_facet < 0) on_facet = m;
             auto f = [&](const std::array<double, 2> &p) { return c0 + p[0] * (c1 - c0) + p[1] * (c2 - c0); };
             out.clear();
             const size_t np = poly.size();
@@ -1263,7 +1281,7 @@ void build_transfer(Hierarchy &h) {
             poly.swap(out);
           }
           if (poly.size() < 3) continue;
-          const double wgt = on_facet ? 0.5 : 1.0;
+          const double wgt = on_facet >= 0 ? facet_weight(s, on_facet) : 1.0;
           for (int m = 0; m < 4; ++m) {
             if (cols[m] < 0) continue;
             const double c0 = c[m][0], c1 = c[m][1], c2 = c[m][2];
@@ -1435,43 +1453,11 @@ void build_coarse(Hierarchy &h) {
   h.nc = n;
   h.coarse_inv.assign(n * n, 0.0);
   if (n == 0) return;
-  std::vector<double> Lm(n * n, 0.0);
   for (int64_t i = 0; i < n; ++i)
-    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) Lm[i * n + A.ci[p]] = A.v[p];
-  for (int64_t j = 0; j < n; ++j) {
-    double s = Lm[j * n + j];
-    for (int64_t k = 0; k < j; ++k) s -= Lm[j * n + k] * Lm[j * n + k];
-    if (!(s > 0)) fail(ASMG_ENOTSPD, "coarse matrix is not positive definite");
-    const double djj = std::sqrt(s);
-    Lm[j * n + j] = djj;
-    for (int64_t i = j + 1; i < n; ++i) {
-      double t = Lm[i * n + j];
-      for (int64_t k = 0; k < j; ++k) t -= Lm[i * n + k] * Lm[j * n + k];
-      Lm[i * n + j] = t / djj;
-    }
-    for (int64_t i = 0; i < j; ++i) Lm[i * n + j] = 0.0;
-  }
-  // inverse column by column (independent columns on parallel threads): solve L y = e_c, L^T x = y.
-  // y_i = 0 for i < c (e_c has no entries there), so the forward solve starts at row c; the
-  // backward solve reads L^T by rows (Ut = L^T, row-major) and x from a contiguous vector.
-  std::vector<double> Ut(n * n);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t k = 0; k < n; ++k) Ut[i * n + k] = Lm[k * n + i];
-  parallel_for(h, n, [&](int64_t c) {
-    std::vector<double> y(n, 0.0), x(n);
-    for (int64_t i = c; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = c; k < i; ++k) s -= Lm[i * n + k] * y[k];
-      y[i] = s / Lm[i * n + i];
-    }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double s = y[i];
-      const double *u = &Ut[i * n];
-      for (int64_t k = i + 1; k < n; ++k) s -= u[k] * x[k];
-      x[i] = s / Lm[i * n + i];
-    }
-    for (int64_t i = 0; i < n; ++i) h.coarse_inv[i * n + c] = x[i];
-  });
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) h.coarse_inv[i * n + A.ci[p]] = A.v[p];
+  // Cholesky factor and explicit inverse; a singular component (a pure Neumann problem: rows
+  // summing to zero) is regularised by its rank-one term first
+  spd_inverse(h.coarse_inv, n, h.threads, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,23 @@ struct LevelMesh {
 
 struct DomainIndex;  // boundary edges and bucket grids of a general 2-D domain (domain.cpp)
 
+// Near-boundary set J_{l,j} of one auxiliary level (Section 3.5) and the exact solver of A_l
+// restricted to it (nearbnd.cpp)
+struct NearBnd {
+  std::vector<int64_t> J;        // level unknowns in the solver's order
+  bool dense = true;             // dense: `inv` is the |J|^2 inverse (regularised where singular)
+  std::vector<double> inv;
+  // domain decomposition: interiors of the pieces [poff[p], poff[p+1]) of J, then the separator
+  // [nI, |J|); dense inverses of the interior blocks at boff[p]; couplings A_SI (rows separator,
+  // columns interior position) and A_IS (rows interior, columns separator position); the inverse
+  // of the Schur complement on the separator
+  int nI = 0;
+  std::vector<int64_t> poff, boff;
+  std::vector<double> blocks;
+  Csr ASI, AIS;
+  std::vector<double> sinv;
+};
+
 struct Hierarchy {
   // input
   int d = 2;
@@ -94,7 +111,9 @@ struct Hierarchy {
   std::unordered_map<int, std::vector<int32_t>> colour_aux;  // lc+1..J
   std::unordered_map<int, std::vector<uint8_t>> local_set;   // N~_l, lc+1..J (1 = smoothed locally)
   int64_t nc = 0;
-  std::vector<double> coarse_inv;     // nc * nc, row-major, explicit inverse of A_lc
+  std::vector<double> coarse_inv;     // nc * nc, row-major, explicit inverse of A_lc (regularised
+                                      // on components with zero row sums: pure Neumann problems)
+  std::unordered_map<int, NearBnd> nb;  // near-boundary correction, lc+1..J (option nb_layers)
 
   int64_t n() const { return (int64_t)dofs.size(); }
 };
@@ -115,6 +134,12 @@ std::vector<uint8_t> domain_keeps(const Hierarchy &h, const LevelMesh &lm);
 void domain_mixed(const Hierarchy &h, const LevelMesh &lm, std::vector<uint8_t> &kept,
                   std::vector<uint8_t> &touch);
 void build_coarse(Hierarchy &h);
+// near-boundary correction (nearbnd.cpp): J_{l,j} of a level, and every level's set and solver
+std::vector<int64_t> near_boundary_set(Hierarchy &h, int level, int layers);
+void build_near_boundary(Hierarchy &h);
+// M (n x n symmetric, row-major) replaced by its inverse; with `regularised`, each connected
+// component whose rows sum to zero first gets gamma 1 1^T (gamma = mean diagonal / size)
+void spd_inverse(std::vector<double> &M, int64_t n, int threads, bool regularised);
 const LevelMesh &level_mesh(Hierarchy &h, int level);
 // position of every unknown of the original grid in Morton order of its vertex (device layout)
 std::vector<int> morton_rank(const Hierarchy &h);

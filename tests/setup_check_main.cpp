@@ -1,4 +1,4 @@
-// Host-only driver of the whole host setup (setup.cpp, domain.cpp), for runs under
+// Host-only driver of the whole host setup (setup.cpp, domain.cpp, nearbnd.cpp), for runs under
 // AddressSanitizer and UndefinedBehaviorSanitizer: no HIP code is built into it.
 //
 // Usage: setup_check <mesh.bin>
@@ -54,6 +54,7 @@ int main(int argc, char **argv) {
   h.opt.autotune = 1;
   h.opt.domain = domain;
   h.opt.device = -1;
+  h.opt.nb_layers = 2;  // the near-boundary sets and their exact solvers are built too
   try {
     build_fine(h);
     build_tree(h);
@@ -63,6 +64,7 @@ int main(int argc, char **argv) {
     build_colourings(h);
     build_local_sets(h);
     build_coarse(h);
+    build_near_boundary(h);
   } catch (const AsmgError &e) {
     std::fprintf(stderr, "setup error %d: %s\n", e.code, e.msg.c_str());
     return 1;

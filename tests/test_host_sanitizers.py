@@ -1,7 +1,8 @@
 """The host setup (setup.cpp, domain.cpp) built with AddressSanitizer and UndefinedBehaviorSanitizer
 (g++, host code only; no HIP code is part of this build) and run through the whole pipeline on a
-2-D graded mesh, a 3-D cube, an L-shape with Dirichlet grids on the mesh domain and an annulus
-with the mixed Dirichlet/Neumann grids: no sanitizer report, no leak."""
+2-D graded mesh, a 3-D cube, an L-shape with Dirichlet grids on the mesh domain, an annulus
+with the mixed Dirichlet/Neumann grids and a pure Neumann annulus, each with the near-boundary
+sets and their exact solvers: no sanitizer report, no leak."""
 import os
 import shutil
 import subprocess
@@ -33,7 +34,8 @@ def test_host_setup_under_sanitizers(tmp_path):
     flags = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
              "-ffp-contract=off", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
     here = os.path.dirname(os.path.abspath(__file__))
-    srcs = [os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "domain.cpp"), os.path.join(here, "setup_check_main.cpp")]
+    srcs = [os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "domain.cpp"), os.path.join(CSRC, "nearbnd.cpp"),
+            os.path.join(here, "setup_check_main.cpp")]
     procs = [subprocess.Popen(["g++", *flags, "-c", s, "-o", str(tmp_path / (os.path.basename(s) + ".o"))])
              for s in srcs]
     assert all(p.wait() == 0 for p in procs)
@@ -51,6 +53,7 @@ def test_host_setup_under_sanitizers(tmp_path):
     X, T, _ = W.annulus_mesh(64)
     m = boundary_vertices(T, len(X)) & (np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35)
     cases.append(("annulus_mixed", (X, T, np.ones(len(T))), dict(domain=2, mask=m)))
+    cases.append(("annulus_neumann", (X, T, np.ones(len(T))), dict(domain=2, mask=np.zeros(len(X), bool))))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     for name, args, kw in cases:
         path = str(tmp_path / f"{name}.bin")

@@ -45,6 +45,9 @@ CASES = {
     "lshape_mixed": lambda: _mixed(lambda: W.lshape_mesh(24, 0.3), lambda X: (X[:, 0] == 0.0) | (X[:, 1] == 0.0)),
     "annulus_mixed": lambda: _mixed(lambda: W.annulus_mesh(64),
                                     lambda X: np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35),
+    # pure Neumann problems: no Dirichlet vertex, the Neumann grids (mixed grids with empty Gamma_D)
+    "square32_neumann": lambda: _mixed(lambda: W.square_mesh(32, 0.3, cfg=0, item=1), lambda X: X[:, 0] > 2.0),
+    "annulus_neumann": lambda: _mixed(lambda: W.annulus_mesh(64), lambda X: X[:, 0] > 2.0),
 }
 
 
@@ -140,3 +143,24 @@ def test_local_sets_match(cfg, scale):
     H = Hierarchy(c["coords"], c["elems"], c["kappa"])
     for l in range(H.aux.lc + 1, H.aux.J + 1):
         assert np.array_equal(S.export("local_set", l).astype(bool), auxops.local_set(H.aux.P[l])), l
+
+
+@pytest.mark.parametrize("name", ["square32_neumann", "annulus_neumann", "lshape_mixed", "square64"])
+def test_near_boundary_sets_and_regularised_bottom(name):
+    # J_{l,j} of every level above the bottom (Section 3.5) equals the oracle's, and the bottom
+    # inverse (regularised on singular components) equals the oracle's factorisation's inverse
+    from oracle import nearbnd
+    c, n_min, dom = CASES[name]()
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=-1, n_min=n_min, domain=dom,
+                 dirichlet=c.get("dirichlet"), nb_layers=2)
+    H = Hierarchy(c["coords"], c["elems"], c["kappa"], n_min=n_min, domain=["box", "mesh", "mixed"][dom],
+                  dirichlet=c.get("dirichlet"))
+    for l in range(H.aux.lc + 1, H.tree.J + 1):
+        J = nearbnd.near_boundary_set(H.meshes.level(l), 2)
+        assert np.array_equal(S.export("nb_set", l), J), l
+        info = S.export("nb_info", l)
+        assert info[0] == len(J)
+    nc = H.aux.A[H.aux.lc].shape[0]
+    inv = S.export("coarse_inv").reshape(nc, nc)
+    ref = np.linalg.inv(nearbnd.regularised(H.aux.A[H.aux.lc]))
+    assert np.abs(inv - ref).max() <= 1e-10 * np.abs(ref).max()
