@@ -284,6 +284,28 @@ def annulus(steps: int, colouring: int = 2):
         log(f"annulus, Neumann hole, {key.replace('_', ' ')}: {dt * 1e3:.2f} ms/solve, {it} iterations")
         del S
     res["neumann_hole"] = mres
+    # pure Neumann problem on the same mesh (no Dirichlet vertex: mixed grids with an empty
+    # Dirichlet part, f projected onto the range of A, u mean-free), without and with the
+    # near-boundary correction of Section 3.5 (j = 2 layers), FP64
+    nres = {"problem": "pure Neumann (every vertex an unknown), mixed grids"}
+    for key, nb in (("no_correction", 0), ("near_boundary_j2", 2)):
+        t0 = time.perf_counter()
+        S = A.Solver(coords, elems, kappa, np.zeros(len(coords), dtype=bool), colouring=colouring, domain=2,
+                     nb_layers=nb)
+        t_setup = time.perf_counter() - t0
+        f = torch.from_numpy(np.ascontiguousarray(f_vertex[S.dof_vertex()])).cuda()
+        u, it, tr = S.solve_device(f, 1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            u, it, tr = S.solve_device(f, 1e-8, out=u)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        nres[key] = {"value": S.n / dt, "ms_per_step": dt * 1e3, "iterations": it, "true_rel_residual": tr,
+                     "unknowns": S.n, "setup_s": t_setup}
+        log(f"annulus, pure Neumann, j = {nb}: {dt * 1e3:.2f} ms/solve, {it} iterations, setup {t_setup:.1f} s")
+        del S
+    res["pure_neumann"] = nres
     return res
 
 
