@@ -40,7 +40,7 @@ import os
 import re
 import sys
 
-KERNEL = "asmg::k_sell<0, double>"
+KERNEL = "asmg::k_sell<0, double, 0>"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 64 * 2 ** 20 * 8
 
@@ -53,13 +53,13 @@ KERNEL_SRCS = _srcs("device.hip", "common.hpp")
 
 # workload -> dominant kernel, the sources that define it, the bench selection of the counter runs
 WORKLOADS = {
-    "graded1M": dict(kernel="asmg::k_sell<0, double>", sources=("device.hip", "common.hpp"),
+    "graded1M": dict(kernel="asmg::k_sell<0, double, 0>", sources=("device.hip", "common.hpp"),
                      bench="--only graded --no-extra", engine="single",
                      desc="graded 2-D Delaunay mesh, 1002722 vertices, FP64 and mixed solves"),
-    "cube2M": dict(kernel="asmg::k_sell<0, double>", sources=("device.hip", "common.hpp"),
+    "cube2M": dict(kernel="asmg::k_sell<0, double, 0>", sources=("device.hip", "common.hpp"),
                    bench="--only cube3d", engine="single",
                    desc="Kuhn cube 128^3 x 6 tetrahedra, 2048383 unknowns, FP64 and mixed solves"),
-    "batched256x4": dict(kernel="asmg::kb_sell<0, 4, double>", sources=("batch.hip", "common.hpp"),
+    "batched256x4": dict(kernel="asmg::kb_sell<0, 4, double, 0>", sources=("batch.hip", "common.hpp"),
                          bench="--only batched", engine="batch",
                          desc="256 jittered squares (sides 32..512) x 4 right-hand sides, FP64 and mixed solves"),
 }
