@@ -240,7 +240,12 @@ int asmg_adjoint_gradient_device(asmg_handle h, const double *d_u, const double 
  *          events stamped with that launch's own start and end (hipExtLaunchKernel), so
  *          caches are as in a solve; *ms and *bytes are the mean per launch,
  *          6 = the PCG product q = A p with its partial dot products (k_cg_spmv, sliced ELL,
- *          FP64), the product the solve runs
+ *          FP64), the product the solve runs,
+ *          7 = the same product with the p gathers staged in LDS (per tile of 4 slices, the
+ *          distinct columns loaded once into LDS, entries addressing them by a 16-bit
+ *          position; a measured alternative the solve does not use). Before timing, its
+ *          result on a nonzero p is checked against mode 6's (ASMG_EDEVICE if they differ
+ *          by more than 1e-14 relative). Needs at most 64 KiB of LDS per tile.
  * Algorithmic bytes count each matrix entry, row pointer and vector entry the
  * operation needs once (a colour pass: its rows, b, 1/diag, the x write, and each
  * distinct gathered x entry).

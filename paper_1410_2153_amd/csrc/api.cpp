@@ -335,7 +335,7 @@ int asmg_adjoint_gradient_device(asmg_handle H, const double *d_u, const double 
 
 int asmg_time_kernel(asmg_handle H, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
   if (int r = need_dev(H)) return r;
-  if (which < 0 || which > 6 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
+  if (which < 0 || which > 7 || reps < 1 || !ms || !bytes) return set_err(ASMG_EINVAL, "bad argument");
   ASMG_TRY({ return device_time_kernel(H->dev, which, reps, precision, stream, ms, bytes); })
 }
 

@@ -467,6 +467,94 @@ __global__ __launch_bounds__(BS) void k_cg_spmv(int ns, const int *__restrict__ 
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
+// The PCG product with its x gathers staged in LDS (a measured alternative to k_cg_spmv, reached
+// only through the kernel-timing entry point). A block owns tiles of BS/64 consecutive slices;
+// the distinct columns of a tile's entries are listed at setup (tlist, sorted), the block loads
+// p at those columns into LDS once, and each entry then reads LDS through its 16-bit position in
+// the tile's list (lcol) instead of gathering p from global memory.
+template <int W>
+__device__ __forceinline__ double lds_row_w(const uint16_t *__restrict__ cp, const double *__restrict__ vp,
+                                            const double *xs) {
+  int c[W];
+  double v[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) c[k] = cp[k * 64];
+#pragma unroll
+  for (int k = 0; k < W; ++k) v[k] = vp[k * 64];
+  double a0 = 0, a1 = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    if (k & 1)
+      a1 += v[k] * xs[c[k]];
+    else
+      a0 += v[k] * xs[c[k]];
+  }
+  return a0 + a1;
+}
+
+__device__ __forceinline__ double lds_row(int w, const uint16_t *__restrict__ cp, const double *__restrict__ vp,
+                                          const double *xs) {
+  switch (w) {
+    case 0: return 0.0;
+    case 1: return lds_row_w<1>(cp, vp, xs);
+    case 2: return lds_row_w<2>(cp, vp, xs);
+    case 3: return lds_row_w<3>(cp, vp, xs);
+    case 4: return lds_row_w<4>(cp, vp, xs);
+    case 5: return lds_row_w<5>(cp, vp, xs);
+    case 6: return lds_row_w<6>(cp, vp, xs);
+    case 7: return lds_row_w<7>(cp, vp, xs);
+    case 8: return lds_row_w<8>(cp, vp, xs);
+    case 9: return lds_row_w<9>(cp, vp, xs);
+    case 10: return lds_row_w<10>(cp, vp, xs);
+    case 11: return lds_row_w<11>(cp, vp, xs);
+    case 12: return lds_row_w<12>(cp, vp, xs);
+    case 13: return lds_row_w<13>(cp, vp, xs);
+    case 14: return lds_row_w<14>(cp, vp, xs);
+    case 15: return lds_row_w<15>(cp, vp, xs);
+    case 16: return lds_row_w<16>(cp, vp, xs);
+    default: break;
+  }
+  double acc = 0;
+  int k = 0;
+  for (; k + 8 <= w; k += 8) acc += lds_row_w<8>(cp + k * 64, vp + k * 64, xs);
+  for (; k < w; ++k) acc += vp[k * 64] * xs[cp[k * 64]];
+  return acc;
+}
+
+__global__ __launch_bounds__(BS) void k_cg_spmv_lds(int ntiles, int ns, const int *__restrict__ srow,
+                                                    const int *__restrict__ soff, const uint16_t *__restrict__ lcol,
+                                                    const double *__restrict__ sv, const int *__restrict__ toff,
+                                                    const int *__restrict__ tlist, const double *__restrict__ dg,
+                                                    const double *__restrict__ p, double *__restrict__ q,
+                                                    double *__restrict__ partials) {
+  extern __shared__ double xs[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  double v = 0.0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int b0 = toff[t], m = toff[t + 1] - b0;
+    for (int k = threadIdx.x; k < m; k += BS) xs[k] = p[tlist[b0 + k]];
+    const int sl = t * (BS / 64) + wv;
+    int row = -1, o0 = 0, w = 0;
+    if (sl < ns) {
+      row = srow[(size_t)sl * 64 + lane];
+      o0 = soff[sl];
+      w = (soff[sl + 1] - o0) >> 6;
+    }
+    __syncthreads();
+    const double acc = lds_row(w, lcol + o0 + lane, sv + o0 + lane, xs);
+    if (row >= 0) {
+      const double pi = p[row];
+      const double qi = dg[row] * pi + acc;
+      q[row] = qi;
+      v += pi * qi;
+    }
+    __syncthreads();
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
 // alpha = rho / p.q, iteration count
 __global__ __launch_bounds__(BS) void k_fin_spmv(const double *__restrict__ partials, int nb, Ctl *ctl) {
   if (ctl->done) return;
@@ -917,6 +1005,12 @@ struct Device {
   std::vector<double> probe_bytes;
   size_t probe_used = 0;
   std::string last_kernel;
+  // LDS-staged PCG product (kernel-timing mode 7 only): per tile of BS/64 slices the sorted
+  // distinct columns, their offsets, and each entry's position in its tile's list
+  int *lds_toff = nullptr, *lds_list = nullptr;
+  uint16_t *lds_lcol = nullptr;
+  int lds_ntiles = 0, lds_maxm = 0;
+  int64_t lds_nlist = 0;
 };
 
 template <class T>
@@ -2589,6 +2683,45 @@ int device_element_gradient(Device *dv, const double *d_u, const double *d_lam, 
   return ASMG_OK;
 }
 
+// tile lists of the LDS-staged product, built from the fine sliced ELL on the device (once)
+static void build_lds_tiles(Device *dv) {
+  if (dv->lds_toff) return;
+  const DSell &S = dv->fine.sell;
+  const int ns = S.nslices;
+  std::vector<int> soff(ns + 1), scol(S.entries);
+  HIPCHECK(hipMemcpy(soff.data(), S.soff, (size_t)(ns + 1) * 4, hipMemcpyDeviceToHost));
+  if (S.entries) HIPCHECK(hipMemcpy(scol.data(), S.scol, (size_t)S.entries * 4, hipMemcpyDeviceToHost));
+  const int per = BS / 64;
+  const int nt = (ns + per - 1) / per;
+  std::vector<int> toff(nt + 1, 0), list;
+  std::vector<uint16_t> lcol(S.entries);
+  int maxm = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int e0 = soff[t * per], e1 = soff[std::min(ns, (t + 1) * per)];
+    std::vector<int> u(scol.begin() + e0, scol.begin() + e1);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    if (u.size() > 65535) throw AsmgError{ASMG_EINVAL, "tile with more than 65535 distinct columns"};
+    for (int e = e0; e < e1; ++e)
+      lcol[e] = (uint16_t)(std::lower_bound(u.begin(), u.end(), scol[e]) - u.begin());
+    list.insert(list.end(), u.begin(), u.end());
+    toff[t + 1] = (int)list.size();
+    maxm = std::max(maxm, (int)u.size());
+  }
+  if ((size_t)maxm * 8 > 65536) throw AsmgError{ASMG_EINVAL, "LDS-staged product: a tile needs more than 64 KiB"};
+  dv->lds_toff = dupload(dv, toff);
+  dv->lds_list = dupload(dv, list);
+  dv->lds_lcol = dupload(dv, lcol);
+  dv->lds_ntiles = nt;
+  dv->lds_maxm = maxm;
+  dv->lds_nlist = (int64_t)list.size();
+}
+
+__global__ __launch_bounds__(BS) void k_pattern(int n, double *__restrict__ x) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) x[i] = 1.0 + 0.25 * (double)((i * 7919) % 61) - 0.5 * (double)(i % 3);
+}
+
 int device_time_kernel(Device *dv, int which, int reps, int precision, void *stream, double *ms, double *bytes) {
   HIPCHECK(hipSetDevice(dv->ordinal));
   hipStream_t s = (hipStream_t)stream;
@@ -2603,8 +2736,14 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   };
   auto bco = [&]() { bco_on(s); };
   int g6 = std::min<int>(dv->max_blocks, nblk((int64_t)F.sell.nslices * 64));
+  if (which == 7) build_lds_tiles(dv);
+  const int g7 = std::max(1, std::min(dv->lds_ntiles, 8 * 256));
   auto one = [&]() {
-    if (which == 6) {
+    if (which == 7) {
+      hipLaunchKernelGGL(k_cg_spmv_lds, dim3(g7), dim3(BS), (size_t)std::max(dv->lds_maxm, 1) * 8, s, dv->lds_ntiles,
+                         F.sell.nslices, F.sell.srow, F.sell.soff, dv->lds_lcol, F.sell.sv64, dv->lds_toff,
+                         dv->lds_list, F.dg64, dv->p, dv->q, dv->partials);
+    } else if (which == 6) {
       hipLaunchKernelGGL(k_cg_spmv, dim3(g6), dim3(BS), 0, s, F.sell.nslices, F.sell.srow, F.sell.soff, F.sell.scol,
                          F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
     } else if (which == 0) {
@@ -2622,6 +2761,25 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
       bco();
     }
   };
+  if (which == 7 && n > 0) {
+    // check the staged product against the solve's product on a nonzero p before timing it
+    hipLaunchKernelGGL(k_pattern, dim3(nblk(n)), dim3(BS), 0, s, n, dv->p);
+    HIPCHECK(hipMemsetAsync(dv->ctl, 0, sizeof(Ctl), s));
+    hipLaunchKernelGGL(k_cg_spmv, dim3(g6), dim3(BS), 0, s, F.sell.nslices, F.sell.srow, F.sell.soff, F.sell.scol,
+                       F.sell.sv64, F.dg64, dv->p, dv->q, dv->ctl, dv->partials);
+    std::vector<double> q6(n), q7(n);
+    HIPCHECK(hipMemcpyAsync(q6.data(), dv->q, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    one();
+    HIPCHECK(hipMemcpyAsync(q7.data(), dv->q, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double dmax = 0, qmax = 0;
+    for (int i = 0; i < n; ++i) {
+      dmax = std::max(dmax, std::fabs(q6[i] - q7[i]));
+      qmax = std::max(qmax, std::fabs(q6[i]));
+    }
+    if (dmax > 1e-14 * qmax) throw AsmgError{ASMG_EDEVICE, "LDS-staged product differs from the solve's product"};
+  }
   HIPCHECK(hipMemsetAsync(dv->p, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(dv->f, 0, (size_t)n * 8, s));
   HIPCHECK(hipMemsetAsync(F.b64, 0, (size_t)n * 8, s));
@@ -2659,6 +2817,9 @@ int device_time_kernel(Device *dv, int which, int reps, int precision, void *str
   dv->bytes = 0;
   if (which == 0 || which == 6)
     dv->bytes = csr_bytes(F.A, 8) + 8.0 * n * 3 + (which == 6 ? 8.0 * g6 : 8.0 * n);
+  else if (which == 7)  // entries (8-byte value, 2-byte position), the lists and the staged p, rows
+    dv->bytes = 10.0 * (double)F.A.nnz + 12.0 * (double)dv->lds_nlist + 4.0 * (dv->lds_ntiles + 1) + 8.0 * n * 3 +
+                8.0 * g7;
   else
     one();
   if (which == 6) {

@@ -245,7 +245,9 @@ def test_kernel_timing_leaves_the_solver_intact():
     S = A.Solver(c["coords"], c["elems"], c["kappa"])
     f = c["f_vertex"][S.dof_vertex()]
     u0, it0, _ = S.solve(f, 1e-8)
-    for which, prec in ((0, A.PREC_FP64), (6, A.PREC_FP64), (2, A.PREC_FP64), (2, A.PREC_MIXED), (4, A.PREC_FP64)):
+    # mode 7 (the LDS-staged product) first checks its result against the solve's product
+    for which, prec in ((0, A.PREC_FP64), (6, A.PREC_FP64), (7, A.PREC_FP64), (2, A.PREC_FP64), (2, A.PREC_MIXED),
+                        (4, A.PREC_FP64)):
         ms, by = S.time_kernel(which, reps=20, precision=prec)
         _say("time_kernel", which, prec, f"{ms * 1e3:.1f} us, {by / 1e6:.2f} MB")
         assert 0 < ms < 1e3 and by > 0
