@@ -29,6 +29,10 @@
 
 namespace asmg {
 
+#ifndef LOWER_FIRST_SWEEP
+#define LOWER_FIRST_SWEEP 1
+#endif
+
 enum { BST_OK = 0, BST_NOTSPD = 1, BST_NAN = 2, BST_NOCONV = 3 };
 
 template <int NR, class T>
@@ -190,12 +194,13 @@ __device__ __forceinline__ int bwave_slice(int first) {
 // over slices [s0, s1), every right-hand side of a row at once
 template <int MODE, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__restrict__ srow,
-                                                  const int *__restrict__ soff, const int *__restrict__ scol,
+                                                  const int *__restrict__ soff, const int *__restrict__ send,
+                                                  const int *__restrict__ scol,
                                                   const T *__restrict__ sv, const T *__restrict__ dv_,
                                                   const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
                                                   int shape) {
   const int lane = threadIdx.x & 63;
-  for_slices<VAR>(s0, s1, shape, srow, soff, [&](int row, int o0, int w) {
+  for_slices<VAR>(s0, s1, shape, srow, soff, send, [&](int row, int o0, int w) {
     VecR<NR, T> bv, xv;
     T di = 0;
     auto pre = [&] {
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__rest
                                                        T *__restrict__ y, const T *__restrict__ id0,
                                                        T *__restrict__ xs, int shape) {
   const int lane = threadIdx.x & 63;
-  for_slices<VAR>(0, ns, shape, srow, soff, [&](int row, int o0, int w) {
+  for_slices<VAR>(0, ns, shape, srow, soff, soff + 1, [&](int row, int o0, int w) {
     VecR<NR, T> yv;
     T di = 0;
     auto pre = [&] {
@@ -711,6 +716,7 @@ struct BSell {
   int64_t nnz = 0, entries = 0;
   std::vector<int> cslice{0};
   int *srow = nullptr, *soff = nullptr, *scol = nullptr;
+  int *slo = nullptr;    // per slice: end of its entries before each row's own colour range
   double *sv64 = nullptr;
   float *sv32 = nullptr;
 };
@@ -722,6 +728,7 @@ struct BLevel {
   std::vector<int> off;  // row offset of each present mesh
   BSell sell;            // off-diagonal part of the smoothing rows; group c = colour c of every mesh
   std::vector<int64_t> cnnz, crows, ucols;  // per colour group: nonzeros, rows, distinct columns gathered
+  std::vector<int64_t> cnnz_lo, ucols_lo;   // the same over the columns of earlier colours
   double *dg64 = nullptr, *id64 = nullptr, *id0_64 = nullptr;  // a_ii, 1/a_ii, 1/a_ii on colour 0 else 0
   float *dg32 = nullptr, *id32 = nullptr, *id0_32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
@@ -880,7 +887,9 @@ using Groups = std::vector<std::vector<std::pair<int, int>>>;
 struct BSellHost {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
-  std::vector<int> srow, soff{0}, scol, cslice{0}, block0{0};
+  // slo[s]: end of the entries of slice s before each row's own range (the widest such prefix
+  // over the lanes; rows store their columns in ascending order)
+  std::vector<int> srow, soff{0}, scol, cslice{0}, block0{0}, slo;
   std::vector<double> sv;
   std::vector<float> sv32;
 };
@@ -894,6 +903,7 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
   auto len = [&](int r) { return H.rp[r + 1] - H.rp[r]; };
   auto empty_slice = [&]() {
     for (int j = 0; j < 64; ++j) srow.push_back(-1);
+    X.slo.push_back(soff.back());
     soff.push_back(soff.back());
   };
   for (const auto &g : groups) {
@@ -908,8 +918,14 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
         std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return len(x) > len(y); });
         for (size_t a = 0; a < idx.size(); a += 64) {
           const size_t e = std::min(a + 64, idx.size());
-          int wmax = 0;
-          for (size_t i = a; i < e; ++i) wmax = std::max(wmax, len(idx[i]));
+          int wmax = 0, wlo = 0;
+          for (size_t i = a; i < e; ++i) {
+            const int r = idx[i];
+            wmax = std::max(wmax, len(r));
+            int lo = 0;
+            while (lo < len(r) && H.ci[H.rp[r] + lo] < rg.first) ++lo;
+            wlo = std::max(wlo, lo);
+          }
           const int base = soff.back();
           scol.resize(base + 64 * wmax);
           sv.resize(base + 64 * wmax);
@@ -932,6 +948,7 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
             }
           }
           soff.push_back(base + 64 * wmax);
+          X.slo.push_back(base + 64 * wlo);
         }
       }
     }
@@ -964,6 +981,7 @@ static void bsell_upload(BatchDevice *dv, const BSellHost &X, BSell &S) {
   S.entries = (int64_t)X.sv.size();
   S.srow = bupload(dv, X.srow);
   S.soff = bupload(dv, X.soff);
+  S.slo = bupload(dv, X.slo);
   S.scol = bupload(dv, X.scol);
   S.sv64 = bupload(dv, X.sv);
   S.sv32 = bupload(dv, X.sv32);
@@ -1100,21 +1118,26 @@ static void transfer_stats(const HMat &H, const std::vector<int> &rows, BSellHos
 // byte-model counts of each row-range group of H: nonzeros, rows, and the distinct columns the
 // group's rows gather (each x entry read once per colour pass)
 static void group_counts(const HMat &H, const Groups &groups, std::vector<int64_t> &cnnz, std::vector<int64_t> &crows,
-                         std::vector<int64_t> &ucols) {
+                         std::vector<int64_t> &ucols, std::vector<int64_t> &cnnz_lo, std::vector<int64_t> &ucols_lo) {
   const int G = (int)groups.size();
   cnnz.assign(G, 0);
   crows.assign(G, 0);
   ucols.assign(G, 0);
+  cnnz_lo.assign(G, 0);
+  ucols_lo.assign(G, 0);
   std::vector<int> seen(std::max(H.ncols, 1), -1);
   for (int g = 0; g < G; ++g)
     for (const auto &rg : groups[g])
       for (int i = rg.first; i < rg.second; ++i) {
         ++crows[g];
         for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+          const bool lo = H.ci[p] < rg.first;  // a column of an earlier colour of the row's mesh
           ++cnnz[g];
+          cnnz_lo[g] += lo;
           if (seen[H.ci[p]] != g) {
             seen[H.ci[p]] = g;
             ++ucols[g];
+            ucols_lo[g] += lo;
           }
         }
       }
@@ -1219,7 +1242,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       std::vector<double> diag;
       std::vector<uint8_t> c0flag;
       BSellHost gs, cg;
-      std::vector<int64_t> cnnz, crows, ucols;  // byte-model counts of every colour group
+      std::vector<int64_t> cnnz, crows, ucols, cnnz_lo, ucols_lo;  // byte-model counts of every colour group
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
       std::vector<int64_t> moff;
@@ -1254,7 +1277,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
-        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols);
+        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols, X.cnnz_lo, X.ucols_lo);
         // CG products: group m = mesh m, whole blocks per mesh
         Groups mg(nm);
         for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
@@ -1315,7 +1338,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
-        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols);
+        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols, X.cnnz_lo, X.ucols_lo);
         for (size_t i = 0; i < bottom_m[k].size(); ++i) {
           const int m = bottom_m[k][i];
           const int nc = (int)H[m]->nc;
@@ -1373,6 +1396,8 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       F.cnnz = X.cnnz;
       F.crows = X.crows;
       F.ucols = X.ucols;
+      F.cnnz_lo = X.cnnz_lo;
+      F.ucols_lo = X.ucols_lo;
       bsell_upload(dv, X.cg, dv->cg_sell);
       dv->cg_b0 = bupload(dv, X.cg.block0);
       dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
@@ -1402,6 +1427,8 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       L.cnnz = X.cnnz;
       L.crows = X.crows;
       L.ucols = X.ucols;
+      L.cnnz_lo = X.cnnz_lo;
+      L.ucols_lo = X.ucols_lo;
       upload_diag(dv, L, X.diag, X.c0flag);
       L.bottom_rows = X.pref.back();
       L.bt_rowpref = bupload(dv, X.pref);
@@ -1595,23 +1622,27 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   T *x = BV<T>::x(L);
   const BSell &S = L.sell;
   const int C = (int)S.cslice.size() - 1;
-  auto pass = [&](int c) {
+  // `lower`: the pass belongs to a sweep from zero, where every neighbour of a later colour is
+  // still zero; it reads only the prefix of each row's entries that holds the earlier colours
+  auto pass = [&](int c, bool lower) {
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
     // algorithmic bytes of the pass: the colour's matrix rows (values, columns, one row index),
     // b, 1/diag and the x write of its rows, each distinct gathered x entry once
     const double sz = sizeof(T), rows = (double)L.crows[c];
-    const double by = (double)L.cnnz[c] * (sz + 4) + 4.0 * (rows + 1) + sz * rows * (2.0 * NR + 1) +
-                      sz * NR * (double)L.ucols[c];
+    const double nz = (double)(lower ? L.cnnz_lo[c] : L.cnnz[c]), uc = (double)(lower ? L.ucols_lo[c] : L.ucols[c]);
+    const double by = nz * (sz + 4) + 4.0 * (rows + 1) + sz * rows * (2.0 * NR + 1) + sz * NR * uc;
     slice_launch(
         dv, s1 - s0, s,
         [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
           with_var(var, [&](auto vc) {
             launch_timed((kb_sell<0, NR, T, decltype(vc)::value>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1,
-                         S.srow, S.soff, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+                         S.srow, S.soff, lower ? S.slo : S.soff + 1, S.scol, bsv<T>(S), BV<T>::id(L), b, x,
+                         (T *)nullptr, shape_arg(th, xcd));
           });
         },
         by);
   };
+  const bool lower = LOWER_FIRST_SWEEP && forward && from_zero;
   if (forward) {
     int c = 0;
     if (from_zero) {
@@ -1619,11 +1650,16 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
         hipLaunchKernelGGL((kb_first<NR, T>), dim3(nblk(L.nsmooth)), dim3(BS), 0, s, L.nsmooth, b, bid0<T>(L), x);
       c = 1;
     }
-    for (; c < C; ++c) pass(c);
+    for (; c < C; ++c) pass(c, lower);
   } else {
-    for (int c = C - 1; c >= 0; --c) pass(c);
+    for (int c = C - 1; c >= 0; --c) pass(c, false);
   }
-  if (dv->count_bytes) dv->bytes += bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
+  if (dv->count_bytes) {
+    double by = bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1);
+    if (lower)  // the passes of colours >= 1 read only the earlier colours' entries
+      for (int c = 1; c < C; ++c) by -= (double)(L.cnnz[c] - L.cnnz_lo[c]) * (sizeof(T) + 4);
+    dv->bytes += by;
+  }
 }
 
 // r = b - A x right after a forward sweep. Slice group C-1 holds only rows of the last colour of
@@ -1640,7 +1676,7 @@ static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
   slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
     with_var(var, [&](auto vc) {
       launch_timed((kb_sell<1, NR, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
-                   S.soff, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
+                   S.soff, S.soff + 1, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
     });
   });
   if (dv->count_bytes && S.nslices > 0)

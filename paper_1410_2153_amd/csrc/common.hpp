@@ -125,16 +125,18 @@ static inline int slice_blocks(int nslices, int threads, int var = 0) {
 }
 
 // The slices [s0, s1) of a slice-kernel launch, each handed to body(row, o0, w): the lane's row
-// (-1 on empty lanes), the slice's first entry offset and its width. VAR 0: one slice per wave.
-// VAR 1: grid-stride loop, with the next slice's header loaded before body runs on this one.
+// (-1 on empty lanes), the slice's first entry offset and its width. Slice s's entries end at
+// send[s]: soff + 1 for whole slices, or an array of earlier ends (a prefix of every row's
+// entries). VAR 0: one slice per wave. VAR 1: grid-stride loop, with the next slice's header
+// loaded before body runs on this one.
 template <int VAR, class F>
 __device__ __forceinline__ void for_slices(int s0, int s1, int shape, const int *__restrict__ srow,
-                                           const int *__restrict__ soff, F &&body) {
+                                           const int *__restrict__ soff, const int *__restrict__ send, F &&body) {
   int s = tuned_slice(s0, shape);
   if (s >= s1) return;
   const int lane = threadIdx.x & 63;
   int row = srow[(size_t)s * 64 + lane];
-  int o0 = soff[s], o1 = soff[s + 1];
+  int o0 = soff[s], o1 = send[s];
   if constexpr (VAR == 0) {
     body(row, o0, (o1 - o0) >> 6);
   } else {
@@ -145,7 +147,7 @@ __device__ __forceinline__ void for_slices(int s0, int s1, int shape, const int 
       if (sn < s1) {
         rn = srow[(size_t)sn * 64 + lane];
         p0 = soff[sn];
-        p1 = soff[sn + 1];
+        p1 = send[sn];
       }
       body(row, o0, (o1 - o0) >> 6);
       if (sn >= s1) break;

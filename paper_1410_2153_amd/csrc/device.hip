@@ -42,6 +42,10 @@
 
 namespace asmg {
 
+#ifndef LOWER_FIRST_SWEEP
+#define LOWER_FIRST_SWEEP 1
+#endif
+
 // ---------------------------------------------------------------------------
 // device control block for PCG
 // ---------------------------------------------------------------------------
@@ -203,12 +207,13 @@ __device__ __forceinline__ int wave_slice(int first) {
 // (dv_ holds 1/a_ii for MODE 0 and a_ii for MODE 1)
 template <int MODE, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void k_sell(int s0, int s1, const int *__restrict__ srow,
-                                                 const int *__restrict__ soff, const int *__restrict__ scol,
+                                                 const int *__restrict__ soff, const int *__restrict__ send,
+                                                 const int *__restrict__ scol,
                                                  const T *__restrict__ sv, const T *__restrict__ dv_,
                                                  const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
                                                  int shape) {
   const int lane = threadIdx.x & 63;
-  for_slices<VAR>(s0, s1, shape, srow, soff, [&](int row, int o0, int w) {
+  for_slices<VAR>(s0, s1, shape, srow, soff, send, [&](int row, int o0, int w) {
     T bi = 0, di = 0, xi = 0;
     auto pre = [&] {
       const int rr = row < 0 ? 0 : row;
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(BS_MAX) void k_sell_spmv(int ns, const int *__restr
                                                   const T *__restrict__ invd, T *__restrict__ xs,
                                                   T *__restrict__ rc, int shape) {
   const int lane = threadIdx.x & 63;
-  for_slices<VAR>(0, ns, shape, srow, soff, [&](int row, int o0, int w) {
+  for_slices<VAR>(0, ns, shape, srow, soff, soff + 1, [&](int row, int o0, int w) {
     T yi = 0, di = 0;
     auto pre = [&] {
       const int rr = row < 0 ? 0 : row;
@@ -809,7 +814,7 @@ __global__ __launch_bounds__(BS) void k_nb_res(int ns, const int *__restrict__ s
                                                const int *__restrict__ jrow, const T *__restrict__ dg,
                                                const T *__restrict__ g, const T *__restrict__ e, T *__restrict__ rJ) {
   const int lane = threadIdx.x & 63;
-  for_slices<0>(0, ns, 2 * (BS / 64) + 1, srow, soff, [&](int k, int o0, int w) {
+  for_slices<0>(0, ns, 2 * (BS / 64) + 1, srow, soff, soff + 1, [&](int k, int o0, int w) {
     T gi = 0, di = 0, ei = 0;
     auto pre = [&] {
       const int i = jrow[k < 0 ? 0 : k];
@@ -890,6 +895,7 @@ struct DSell {
   int wmax = 0;               // widest slice (entries per row)
   std::vector<int> cslice;    // slice range of each colour, C + 1 (host)
   int *srow = nullptr, *soff = nullptr, *scol = nullptr;
+  int *slo = nullptr;         // per slice: end of its entries before the group's first row
   double *sv64 = nullptr;
   float *sv32 = nullptr;
   int64_t entries = 0;        // stored entries including padding
@@ -929,6 +935,7 @@ struct DLevel {
   bool local = false;         // local smoothing: r is written only on N~+, elsewhere r = b
   std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each group's rows
   std::vector<int64_t> ucols; // distinct columns referenced by each group's rows
+  std::vector<int64_t> cnnz_lo, ucols_lo;  // the same over columns before the group's first row
   std::vector<int> perm;      // internal -> unknown
   std::vector<int> iperm;     // unknown -> internal
   DCsr A;                     // off-diagonal part
@@ -1088,7 +1095,9 @@ static HCsr transpose(const HCsr &A) {
 
 // host image of a sliced ELL: built on host threads, uploaded afterwards
 struct SellHost {
-  std::vector<int> srow, soff, scol, cs;
+  // slo[s]: end of the entries of slice s that lie before its group's first row in every lane
+  // (the widest such prefix over the lanes; rows store their columns in ascending order)
+  std::vector<int> srow, soff, scol, cs, slo;
   std::vector<double> sv;
   std::vector<float> sv32;
   int widest = 0;
@@ -1320,8 +1329,14 @@ static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> 
       });
       for (size_t s0 = 0; s0 < idx.size(); s0 += 64) {
         const size_t s1 = std::min(s0 + 64, idx.size());
-        int wmax = 0;
-        for (size_t i = s0; i < s1; ++i) wmax = std::max(wmax, H.rp[idx[i] + 1] - H.rp[idx[i]]);
+        int wmax = 0, wlo = 0;
+        for (size_t i = s0; i < s1; ++i) {
+          const int r = idx[i];
+          wmax = std::max(wmax, H.rp[r + 1] - H.rp[r]);
+          int lo = 0;
+          while (H.rp[r] + lo < H.rp[r + 1] && H.ci[H.rp[r] + lo] < groups[c].first) ++lo;
+          wlo = std::max(wlo, lo);
+        }
         if (wmax > 16) wmax = (wmax + wround - 1) / wround * wround;
         const int base = soff.back();
         scol.resize(base + 64 * wmax);
@@ -1349,6 +1364,7 @@ static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> 
           }
         }
         soff.push_back(base + 64 * wmax);
+        X.slo.push_back(base + 64 * std::min(wlo, wmax));
         widest = std::max(widest, wmax);
       }
     }
@@ -1366,6 +1382,7 @@ static void sell_upload(Device *dv, DSell &S, const SellHost &X, bool first_time
     S.entries = (int64_t)X.sv.size();
     S.srow = dupload(dv, X.srow);
     S.soff = dupload(dv, X.soff);
+    S.slo = dupload(dv, X.slo);
     S.scol = dupload(dv, X.scol);
     S.sv64 = dupload(dv, X.sv);
     S.sv32 = dupload(dv, X.sv32);
@@ -1402,14 +1419,19 @@ static void stage_level(DLevel &L, const Csr &A, bool first_time, LevelStage &X)
     const int G = (int)L.groups.size();
     L.cnnz.assign(G, 0);
     L.ucols.assign(G, 0);
+    L.cnnz_lo.assign(G, 0);
+    L.ucols_lo.assign(G, 0);
     std::vector<int> seen(L.n, -1);
     for (int c = 0; c < G; ++c)
       for (int i = L.groups[c].first; i < L.groups[c].second; ++i)
         for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
+          const bool lo = H.ci[p] < L.groups[c].first;
           ++L.cnnz[c];
+          L.cnnz_lo[c] += lo;
           if (seen[H.ci[p]] != c) {
             seen[H.ci[p]] = c;
             ++L.ucols[c];
+            L.ucols_lo[c] += lo;
           }
         }
   }
@@ -1913,10 +1935,11 @@ struct LV<float> {
 // algorithmic bytes of one colour pass: the colour's matrix rows (values, columns, row pointers),
 // b, 1/diag and the x write of its rows, and each distinct x entry it gathers once
 template <class T>
-static double gs_bytes(const DLevel &L, int c) {
+static double gs_bytes(const DLevel &L, int c, bool lower = false) {
   const double rows = L.groups[c].second - L.groups[c].first;
-  return (double)L.cnnz[c] * (sizeof(T) + 4) + 4.0 * (rows + 1) + 3.0 * sizeof(T) * rows +
-         (double)sizeof(T) * L.ucols[c];
+  const double nz = (double)(lower ? L.cnnz_lo[c] : L.cnnz[c]);
+  const double uc = (double)(lower ? L.ucols_lo[c] : L.ucols[c]);
+  return nz * (sizeof(T) + 4) + 4.0 * (rows + 1) + 3.0 * sizeof(T) * rows + (double)sizeof(T) * uc;
 }
 
 // One slice-kernel launch site of B_co: launch(threads, xcd, e0, e1) enqueues the kernel over
@@ -1964,7 +1987,7 @@ static void slice_launch(Device *dv, int nslices, hipStream_t s, F &&launch, dou
 
 
 template <class T>
-static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t s) {
+static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t s, bool lower = false) {
   const bool probe = dv->probe_lpr != 0 && dv->probe_prec == (sizeof(T) == 4 ? 1 : 0);
   const DSell &S = L.sell;
   const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
@@ -1973,11 +1996,12 @@ static void gs_pass(Device *dv, DLevel &L, int c, T *x, const T *b, hipStream_t 
       [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
         with_var(var, [&](auto vc) {
           launch_timed((k_sell<0, T, decltype(vc)::value>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1,
-                       S.srow, S.soff, S.scol, sell_vals<T>(S), LV<T>::id(L), b, x, (T *)nullptr, shape_arg(th, xcd));
+                       S.srow, S.soff, lower ? S.slo : S.soff + 1, S.scol, sell_vals<T>(S), LV<T>::id(L), b, x,
+                       (T *)nullptr, shape_arg(th, xcd));
         });
       },
-      probe ? gs_bytes<T>(L, c) : -1.0);
-  if (dv->count_bytes) dv->bytes += gs_bytes<T>(L, c);
+      probe ? gs_bytes<T>(L, c, lower) : -1.0);
+  if (dv->count_bytes) dv->bytes += gs_bytes<T>(L, c, lower);
 }
 
 // bytes of the first colour pass of a sweep from zero when it runs on its own:
@@ -2002,7 +2026,11 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
       }
       c = 1;
     }
-    for (; c < C; ++c) gs_pass<T>(dv, L, c, x, b, s);
+    // in a sweep from zero, the rows of colour c see zero at every neighbour of a later colour:
+    // their passes read only the prefix of each row's entries that holds the earlier colours
+    // (rows store their columns in ascending order, colours in ascending ranges)
+    const bool lower = LOWER_FIRST_SWEEP && from_zero && !L.local;
+    for (; c < C; ++c) gs_pass<T>(dv, L, c, x, b, s, lower);
   } else {
     for (int c = C - 1; c >= 0; --c) gs_pass<T>(dv, L, c, x, b, s);
   }
@@ -2023,6 +2051,7 @@ static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStr
   slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
     with_var(var, [&](auto vc) {
       launch_timed((k_sell<1, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow, S.soff,
+                   S.soff + 1,
                    S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
     });
   });
