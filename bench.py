@@ -501,6 +501,20 @@ def graded(args):
         log(f"setup: fine matrix + tree on the host {setup_phases['fine'] + setup_phases['tree']:.3f} s, on the "
             f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); total {t_setup:.1f} -> {t_setup_d:.1f} s")
         del SD
+        # colourings in the hash order (Jones-Plassmann rounds on the device with setup_device = 1)
+        hc = {}
+        for key, sd in (("host", 0), ("device", 1)):
+            t0 = time.perf_counter()
+            SC = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64, colouring=1,
+                          setup_device=sd, autotune=args.autotune)
+            hc[key] = {"total_s": time.perf_counter() - t0, "phases_s": SC.setup_seconds(),
+                       "colours": SC.export("colour_fine")}
+            del SC
+        col_same = bool(np.array_equal(hc["host"].pop("colours"), hc["device"].pop("colours")))
+        out["setup"]["hash_colouring"] = {**hc, "identical_fine_colouring": col_same}
+        log(f"setup, hash colouring: colourings on the host {hc['host']['phases_s']['colourings']:.3f} s, on the "
+            f"device {hc['device']['phases_s']['colourings']:.3f} s (identical: {col_same}); total "
+            f"{hc['host']['total_s']:.1f} -> {hc['device']['total_s']:.1f} s")
         torch.cuda.synchronize()
     return out
 

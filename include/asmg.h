@@ -94,9 +94,11 @@ typedef struct {
                           smoothing (smoothing = 0) only. */
   int setup_device;    /* 1 = assemble the fine matrix (Section 2) and build the cluster tree
                           (Sections 3.1-3.2: root box, keys, Morton sort, refinement by cluster
-                          size, closure, leaves, kappa~) on the HIP device, with results identical
-                          to the host setup; the later setup steps stay on the host. Needs
-                          device >= 0; single-mesh handles. 0 = host (default). */
+                          size, closure, leaves, kappa~) on the HIP device, and with
+                          colouring = 1 also the multicolour orderings (Jones-Plassmann rounds,
+                          the same colouring as the host's greedy one in the hash order), with
+                          results identical to the host setup; the other setup steps stay on the
+                          host. Needs device >= 0; single-mesh handles. 0 = host (default). */
   int red_blocks;      /* cap on the blocks of the PCG reduction kernels (dot products, residual
                           norms, q = A p), 1..2048; 0 = 2048 (default). Beyond the cap the kernels
                           loop over their rows (grid-stride). Results do not depend on it beyond

@@ -192,7 +192,10 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     lap("transfer");
     {
       TraceRange r("asmg::setup::colourings");
-      build_colourings(h);
+      if (o.setup_device == 1 && o.colouring == 1)
+        build_colourings_device(h, o.device);
+      else
+        build_colourings(h);
       build_local_sets(h);
     }
     lap("colourings");

@@ -13,4 +13,9 @@ void build_tree_device(Hierarchy &h, int ordinal);
 // fine matrix A on HIP device `ordinal`, bit-identical to build_fine.
 void build_fine_device(Hierarchy &h, int ordinal);
 
+// Colourings of the original grid and the smoothed auxiliary levels in the hash order (option
+// colouring = 1) on HIP device `ordinal` by Jones-Plassmann rounds: identical to
+// build_colourings. Throws ASMG_EINVAL for the other orders.
+void build_colourings_device(Hierarchy &h, int ordinal);
+
 }  // namespace asmg

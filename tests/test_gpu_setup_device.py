@@ -93,3 +93,25 @@ def test_device_assembly_rejects_degenerate_elements():
         A.Solver(c["coords"], elems, c["kappa"], device=0, setup_device=1)
     assert e.value.code == A.EINVAL and "degenerate element 1" in str(e.value)
 
+
+
+@pytest.mark.parametrize("name,seed", [("square64", 0), ("graded200k", 12345), ("cube16", 7), ("graded_cube", 0),
+                                       ("lshape", 3)])
+def test_device_colouring_matches_host(name, seed):
+    # Jones-Plassmann rounds on the device give the host's greedy colouring in the hash order,
+    # on the original grid and every smoothed auxiliary level; the solves are bit-identical
+    _say(f"[gpu colouring] case {name}, seed {seed}")
+    c = CASES[name]()
+    kw = dict(device=0, colouring=1, colour_seed=seed)
+    Sh = A.Solver(c["coords"], c["elems"], c["kappa"], **kw)
+    Sd = A.Solver(c["coords"], c["elems"], c["kappa"], setup_device=1, **kw)
+    assert np.array_equal(Sh.export("colour_fine"), Sd.export("colour_fine"))
+    info = Sh.info()
+    for l in range(info["lc"] + 1, info["J"] + 1):
+        assert np.array_equal(Sh.export("colour_aux", l), Sd.export("colour_aux", l)), l
+    f = np.random.default_rng(6).uniform(-1, 1, Sh.n)
+    uh, ih, _ = Sh.solve(f, 1e-8)
+    ud, idv, _ = Sd.solve(f, 1e-8)
+    assert ih == idv and np.array_equal(uh, ud)
+    th, td = Sh.setup_seconds(), Sd.setup_seconds()
+    _say(name, "colourings s: host", round(th["colourings"], 4), "device", round(td["colourings"], 4))
