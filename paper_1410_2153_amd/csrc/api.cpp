@@ -182,7 +182,13 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     lap("tree");
     {
       TraceRange r("asmg::setup::levels");
-      build_levels(h);
+      if (o.setup_device == 1) {
+        build_level_meshes(h);
+        assemble_levels_device(h, o.device);
+        build_level_operators(h, false);
+      } else {
+        build_levels(h);
+      }
     }
     lap("levels");
     {

@@ -13,6 +13,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -124,6 +125,83 @@ __global__ __launch_bounds__(TB) void k_entries(int64_t m, const uint64_t *__res
   atomicAdd(&rowcnt[(int)(kk >> 32)], 1);
 }
 
+// (row, column) key and value of every local pair of every simplex of a level mesh sigma^(l),
+// simplex-major, as assemble_level computes them on the host: integer cofactors of the simplex
+// in units of half its box side, the Kuhn coefficient of its box (the first one on fan boxes),
+// value = dot / (d! |det|) (times half * unit in 3-D) times kappa~
+__global__ __launch_bounds__(TB) void k_level_contrib(int64_t ns, int d, int J, double unit,
+                                                      const int64_t *__restrict__ verts, const int *__restrict__ simp,
+                                                      const int *__restrict__ sbox, const int8_t *__restrict__ stmpl,
+                                                      const int8_t *__restrict__ blev, const uint8_t *__restrict__ bfan,
+                                                      const double *__restrict__ bw, const uint8_t *__restrict__ kept,
+                                                      const int *__restrict__ dofv, uint64_t *__restrict__ key,
+                                                      double *__restrict__ val) {
+  const int64_t s = blockIdx.x * (int64_t)TB + threadIdx.x;
+  if (s >= ns) return;
+  const int k = d + 1;
+  int u[4];
+  const bool in = kept == nullptr || kept[s];
+  for (int i = 0; i < k; ++i) u[i] = in ? dofv[simp[s * k + i]] : -1;
+  bool any = false;
+  for (int i = 0; i < k; ++i) any |= u[i] >= 0;
+  if (!any) {
+    for (int q = 0; q < k * k; ++q) {
+      key[s * k * k + q] = NONE;
+      val[s * k * k + q] = 0.0;
+    }
+    return;
+  }
+  const int b = sbox[s];
+  const int64_t half = (int64_t)1 << (J - blev[b]);
+  const int64_t *v0 = verts + (int64_t)simp[s * k] * d;
+  int64_t M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int c = 0; c < d; ++c) {
+    const int64_t *vc = verts + (int64_t)simp[s * k + c + 1] * d;
+    for (int r = 0; r < d; ++r) M[r][c] = (vc[r] - v0[r]) / half;
+  }
+  int64_t a[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int64_t det;
+  if (d == 2) {
+    det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    a[1][0] = M[1][1];
+    a[1][1] = -M[0][1];
+    a[2][0] = -M[1][0];
+    a[2][1] = M[0][0];
+  } else {
+    det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+          M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+        a[i + 1][j] = M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0];
+      }
+  }
+  for (int r = 0; r < d; ++r) {
+    int64_t sum = 0;
+    for (int c = 1; c <= d; ++c) sum += a[c][r];
+    a[0][r] = -sum;
+  }
+  const double denom = __dmul_rn(d == 2 ? 2.0 : 6.0, (double)(det < 0 ? -det : det));
+  const double kap = bfan[b] ? bw[(int64_t)b * 6] : bw[(int64_t)b * 6 + stmpl[s]];
+  const double hu = __dmul_rn((double)half, unit);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      const int64_t slot = s * k * k + i * k + j;
+      if (u[i] < 0 || u[j] < 0) {
+        key[slot] = NONE;
+        val[slot] = 0.0;
+        continue;
+      }
+      int64_t dot = 0;
+      for (int r = 0; r < d; ++r) dot += a[i][r] * a[j][r];
+      double v = __ddiv_rn((double)dot, denom);
+      if (d == 3) v = __dmul_rn(v, hu);
+      v = __dmul_rn(v, kap);
+      key[slot] = ((uint64_t)(uint32_t)u[i] << 32) | (uint32_t)u[j];
+      val[slot] = v;
+    }
+}
+
 struct Bufs {
   std::vector<void *> p;
   template <class T>
@@ -220,6 +298,121 @@ void build_fine_device(Hierarchy &h, int ordinal) {
   A.rp.assign((size_t)n + 1, 0);
   for (int64_t i = 0; i < n; ++i) A.rp[i + 1] = A.rp[i] + cnt[i];
   if (A.rp[n] != nnz) throw AsmgError{ASMG_EDEVICE, "device assembly: row counts do not add up"};
+}
+
+// A_l on the device, level by level: contributions, stable sort by (row, column), run sums in
+// simplex order (the host's order), then the host's rule for the pattern: entries that sum to
+// exactly zero off the diagonal (right angles) are dropped.
+void assemble_levels_device(Hierarchy &h, int ordinal) {
+  const int d = h.d, k = d + 1, J = h.J;
+  HIPCHECK(hipSetDevice(ordinal));
+  const double unit = std::ldexp(h.L, -h.J);
+  hipStream_t s;
+  HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  } sg{s};
+  h.Al.clear();
+  for (int l = J; l >= h.lc; --l) {
+    const LevelMesh &lm = h.meshes.at(l);
+    const int64_t ns = (int64_t)lm.simp_box.size(), nb = (int64_t)lm.boxes.size(), nvl = lm.nverts(),
+                  n = lm.n(), m = ns * k * k;
+    if (m >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31) || nvl >= ((int64_t)1 << 31))
+      throw AsmgError{ASMG_EINVAL, "level too large for the device assembly"};
+    Csr &A = h.Al[l];
+    A.nrows = A.ncols = n;
+    if (m == 0 || n == 0) {
+      A.rp.assign((size_t)n + 1, 0);
+      A.ci.clear();
+      A.v.clear();
+      continue;
+    }
+    // host images: simplex vertices, per-box level, fan flag and Kuhn coefficients
+    std::vector<int> simp(lm.simp.begin(), lm.simp.end()), dofv(lm.dof_of_vert.begin(), lm.dof_of_vert.end());
+    std::vector<int8_t> blev((size_t)nb);
+    std::vector<double> bw((size_t)nb * 6);
+    for (int64_t b = 0; b < nb; ++b) {
+      blev[b] = (int8_t)box_level(lm.boxes[b], d);
+      const KuhnW &w = h.kuhn_w.at(lm.boxes[b]);
+      for (int q = 0; q < 6; ++q) bw[b * 6 + q] = w[q];
+    }
+    Bufs B;
+    int64_t *V = B.get<int64_t>(nvl * d);
+    int *S = B.get<int>(ns * k), *SB = B.get<int>(ns), *DV = B.get<int>(nvl);
+    int8_t *ST = B.get<int8_t>(ns), *BL = B.get<int8_t>(nb);
+    uint8_t *BF = B.get<uint8_t>(nb), *KP = lm.kept.empty() ? nullptr : B.get<uint8_t>(ns);
+    double *BW = B.get<double>(nb * 6);
+    HIPCHECK(hipMemcpyAsync(V, lm.verts.data(), (size_t)nvl * d * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(S, simp.data(), (size_t)ns * k * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(SB, lm.simp_box.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(DV, dofv.data(), (size_t)nvl * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ST, lm.simp_tmpl.data(), (size_t)ns, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(BL, blev.data(), (size_t)nb, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(BF, lm.fan.data(), (size_t)nb, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(BW, bw.data(), (size_t)nb * 6 * 8, hipMemcpyHostToDevice, s));
+    if (KP) HIPCHECK(hipMemcpyAsync(KP, lm.kept.data(), (size_t)ns, hipMemcpyHostToDevice, s));
+    uint64_t *key = B.get<uint64_t>(m), *key_s = B.get<uint64_t>(m);
+    double *val = B.get<double>(m), *val_s = B.get<double>(m);
+    hipLaunchKernelGGL(k_level_contrib, dim3(grid(ns)), dim3(TB), 0, s, ns, d, J, unit, (const int64_t *)V,
+                       (const int *)S, (const int *)SB, (const int8_t *)ST, (const int8_t *)BL, (const uint8_t *)BF,
+                       (const double *)BW, (const uint8_t *)KP, (const int *)DV, key, val);
+    {
+      size_t tb = 0;
+      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key_s, val, val_s, (int)m, 0, 64, s));
+      void *tmp = B.get<char>((int64_t)tb);
+      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, val, val_s, (int)m, 0, 64, s));
+    }
+    int *head = B.get<int>(m), *pos = B.get<int>(m);
+    hipLaunchKernelGGL(k_heads, dim3(grid(m)), dim3(TB), 0, s, m, (const uint64_t *)key_s, head);
+    {
+      size_t tb = 0;
+      HIPCHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, head, pos, (int)m, s));
+      void *tmp = B.get<char>((int64_t)tb);
+      HIPCHECK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, head, pos, (int)m, s));
+    }
+    int last_pos = 0, last_head = 0;
+    HIPCHECK(hipMemcpyAsync(&last_pos, pos + (m - 1), 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(&last_head, head + (m - 1), 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const int64_t nnz = (int64_t)last_pos + last_head;
+    int *ci = B.get<int>(nnz);
+    double *v = B.get<double>(nnz);
+    int *rowcnt = B.get<int>(n);
+    HIPCHECK(hipMemsetAsync(rowcnt, 0, (size_t)n * 4, s));
+    hipLaunchKernelGGL(k_entries, dim3(grid(m)), dim3(TB), 0, s, m, (const uint64_t *)key_s, (const double *)val_s,
+                       (const int *)head, (const int *)pos, ci, v, rowcnt);
+    HIPCHECK(hipGetLastError());
+    std::vector<int32_t> hci((size_t)nnz);
+    std::vector<double> hv((size_t)nnz);
+    std::vector<int> cnt((size_t)n);
+    if (nnz) {
+      HIPCHECK(hipMemcpyAsync(hci.data(), ci, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(hv.data(), v, (size_t)nnz * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHECK(hipMemcpyAsync(cnt.data(), rowcnt, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    // the host's pattern rule: drop entries that are exactly zero off the diagonal
+    A.rp.assign((size_t)n + 1, 0);
+    A.ci.clear();
+    A.v.clear();
+    A.ci.reserve((size_t)nnz);
+    A.v.reserve((size_t)nnz);
+    int64_t p = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t e = p; e < p + cnt[i]; ++e)
+        if (hv[e] != 0.0 || hci[e] == i) {
+          A.ci.push_back(hci[e]);
+          A.v.push_back(hv[e]);
+        }
+      p += cnt[i];
+      A.rp[i + 1] = (int64_t)A.ci.size();
+    }
+    if (p != nnz) throw AsmgError{ASMG_EDEVICE, "device level assembly: row counts do not add up"};
+  }
 }
 
 }  // namespace asmg

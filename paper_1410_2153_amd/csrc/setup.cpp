@@ -1007,7 +1007,7 @@ static void build_prolongation(Hierarchy &h, int level, Csr &P) {
   }
 }
 
-void build_levels(Hierarchy &h) {
+void build_level_meshes(Hierarchy &h) {
   compute_kuhn_means(h);
   const int J = h.J;
   const int Nc = h.opt.coarse_max_dofs > 0 ? h.opt.coarse_max_dofs : 1024;
@@ -1042,12 +1042,23 @@ void build_levels(Hierarchy &h) {
   for (auto it = h.meshes.begin(); it != h.meshes.end();)
     it = it->first < h.lc ? h.meshes.erase(it) : std::next(it);
   for (int li = 1; li < h.lc; ++li) h.level_n[li - 1] = -1;
-  h.Al.clear();
+}
+
+void build_level_operators(Hierarchy &h, bool assemble) {
+  const int J = h.J;
+  if (assemble) {
+    h.Al.clear();
+    for (int li = J; li >= h.lc; --li) h.Al[li];
+    parallel_for(h, J - h.lc + 1, [&](int64_t i) { assemble_level(h, J - (int)i, h.Al.at(J - (int)i), true); });
+  }
   h.P.clear();
-  for (int li = J; li >= h.lc; --li) h.Al[li];
   for (int li = J; li > h.lc; --li) h.P[li];
-  parallel_for(h, J - h.lc + 1, [&](int64_t i) { assemble_level(h, J - (int)i, h.Al.at(J - (int)i), true); });
   parallel_for(h, J - h.lc, [&](int64_t i) { build_prolongation(h, J - (int)i, h.P.at(J - (int)i)); });
+}
+
+void build_levels(Hierarchy &h) {
+  build_level_meshes(h);
+  build_level_operators(h, true);
 }
 
 void assemble_aux_values(Hierarchy &h) {

@@ -13,6 +13,11 @@ void build_tree_device(Hierarchy &h, int ordinal);
 // fine matrix A on HIP device `ordinal`, bit-identical to build_fine.
 void build_fine_device(Hierarchy &h, int ordinal);
 
+// A_l of every level l_c..J (Section 4.1: the P1 stiffness matrix of sigma^(l) with the
+// auxiliary coefficient kappa~ per Kuhn simplex) from the level meshes already built on the host
+// (build_level_meshes), assembled on HIP device `ordinal`, bit-identical to the host assembly.
+void assemble_levels_device(Hierarchy &h, int ordinal);
+
 // Colourings of the original grid and the smoothed auxiliary levels in the hash order (option
 // colouring = 1) on HIP device `ordinal` by Jones-Plassmann rounds: identical to
 // build_colourings. Throws ASMG_EINVAL for the other orders.

@@ -1,5 +1,6 @@
-"""The setup steps built on the device (option setup_device: the fine matrix, Section 2, and
-the cluster tree, Sections 3.1-3.2) against the host setup and the oracle.
+"""The setup steps built on the device (option setup_device: the fine matrix, Section 2, the
+cluster tree, Sections 3.1-3.2, the level matrices A_l, Section 4.1, and with the hash order the
+colourings) against the host setup and the oracle.
 
 Bar: bit-exact. The unknown numbering, the fine matrix (pattern and values), element keys, the
 refined set, the leaves (with their order), J and kappa~ per leaf equal the host build's; the
@@ -65,6 +66,12 @@ def test_device_tree_matches_host_and_oracle(name):
         assert a.dtype == b.dtype and np.array_equal(a, b), ex
     assert np.array_equal(Sh.dof_vertex(), Sd.dof_vertex())
     assert Sh.info() == Sd.info()
+    # A_l of every level (assembled on the device) and P_l, bit for bit
+    info = Sh.info()
+    for l in range(info["lc"], info["J"] + 1):
+        for ex in ("Al_rowptr", "Al_col", "Al_val") + (("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
+            a, b = Sh.export(ex, l), Sd.export(ex, l)
+            assert a.dtype == b.dtype and np.array_equal(a, b), (ex, l)
     d = c["coords"].shape[1]
     T = cluster.BoxTree(c["coords"], c["elems"])
     ref = Sd.export("refined").reshape(-1, d + 1)
@@ -82,7 +89,8 @@ def test_device_tree_matches_host_and_oracle(name):
         ud, idv, _ = Sd.solve(f, 1e-8)
         assert ih == idv and np.array_equal(uh, ud)
     th, td = Sh.setup_seconds(), Sd.setup_seconds()
-    _say(name, "fine + tree s: host", round(th["fine"] + th["tree"], 4), "device", round(td["fine"] + td["tree"], 4))
+    _say(name, "fine + tree s: host", round(th["fine"] + th["tree"], 4), "device", round(td["fine"] + td["tree"], 4),
+         "levels s: host", round(th["levels"], 4), "device", round(td["levels"], 4))
 
 
 def test_device_assembly_rejects_degenerate_elements():
@@ -115,3 +123,31 @@ def test_device_colouring_matches_host(name, seed):
     assert ih == idv and np.array_equal(uh, ud)
     th, td = Sh.setup_seconds(), Sd.setup_seconds()
     _say(name, "colourings s: host", round(th["colourings"], 4), "device", round(td["colourings"], 4))
+
+
+@pytest.mark.parametrize("name,domain", [("lshape", 1), ("annulus_mixed", 2)])
+def test_device_level_matrices_on_general_domains(name, domain):
+    # the level grids keep only part of sigma^(l) (a general domain, or the mixed grids): the
+    # device assembly skips the dropped simplices as the host does
+    _say(f"[gpu levels] case {name}, domain {domain}")
+    dm = None
+    if name == "lshape":
+        c = _lshape()
+    else:
+        from oracle.domain import boundary_vertices
+        X, T, _ = W.annulus_mesh(200)
+        c = dict(coords=X, elems=T, kappa=np.exp(np.random.default_rng(2).normal(0, 0.5, len(T))))
+        dm = boundary_vertices(T, len(X)) & (np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35)
+    Sh = A.Solver(c["coords"], c["elems"], c["kappa"], dm, device=0, domain=domain)
+    Sd = A.Solver(c["coords"], c["elems"], c["kappa"], dm, device=0, domain=domain, setup_device=1)
+    info = Sh.info()
+    assert info == Sd.info()
+    assert not np.all(Sh.export("level_kept", info["J"]).astype(bool))   # some simplices dropped
+    for l in range(info["lc"], info["J"] + 1):
+        for ex in ("Al_rowptr", "Al_col", "Al_val"):
+            a, b = Sh.export(ex, l), Sd.export(ex, l)
+            assert a.dtype == b.dtype and np.array_equal(a, b), (ex, l)
+    f = np.random.default_rng(8).uniform(-1, 1, Sh.n)
+    uh, ih, _ = Sh.solve(f, 1e-8)
+    ud, idv, _ = Sd.solve(f, 1e-8)
+    assert ih == idv and np.array_equal(uh, ud)
