@@ -202,6 +202,124 @@ __global__ __launch_bounds__(TB) void k_level_contrib(int64_t ns, int d, int J, 
     }
 }
 
+// box code of level `level` with index tuple idx (the host's box_code: marker bit above the
+// interleaved index bits, axis 0 most significant in each bit group)
+__device__ __forceinline__ uint64_t d_box_code(int level, const int64_t *idx, int d) {
+  uint64_t m = 0;
+  const int bits = level - 1;
+  for (int b = 0; b < bits; ++b)
+    for (int q = 0; q < d; ++q) m |= (uint64_t)((idx[q] >> b) & 1) << (b * d + (d - 1 - q));
+  return m | ((uint64_t)1 << (d * bits));
+}
+
+// determinant of the edge vectors P[1..d] - P[0] (integer; the caller bounds the coordinates so
+// that no intermediate leaves int64)
+__device__ __forceinline__ int64_t d_det(int d, const int64_t *const P[4]) {
+  int64_t E[3][3];
+  for (int c = 0; c < d; ++c)
+    for (int r = 0; r < d; ++r) E[r][c] = P[c + 1][r] - P[0][r];
+  if (d == 2) return E[0][0] * E[1][1] - E[0][1] * E[1][0];
+  return E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) - E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+         E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+}
+
+// row i of P_l (nodal interpolation of level l-1's functions at level l's unknown i): the
+// smallest active box of level l-1 holding the vertex, the first of its simplices that contains
+// it (exact barycentric coordinates), the nonzero coordinates at level l-1's unknowns, sorted by
+// (column, value) as the host does; `bad` gets the row if the point location fails
+__global__ __launch_bounds__(TB) void k_prolong(int n, int d, int J, int level, const int64_t *__restrict__ fverts,
+                                                const int64_t *__restrict__ fdof, const int64_t *__restrict__ cverts,
+                                                const int *__restrict__ csimp, const uint64_t *__restrict__ ccode,
+                                                const int *__restrict__ cidx, int ncb,
+                                                const int64_t *__restrict__ cbox_simp, const int *__restrict__ cdofv,
+                                                int *__restrict__ pcol, double *__restrict__ pval,
+                                                int *__restrict__ pcnt, int *__restrict__ bad) {
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  const int k1 = d + 1;
+  const int64_t *X = fverts + fdof[i] * d;
+  int bi = -1;
+  for (int k = 1; k <= level - 1 && bi < 0; ++k) {
+    int64_t idx[3];
+    const int sh = J - k + 1;
+    const int64_t nmax = ((int64_t)1 << (k - 1)) - 1;
+    for (int q = 0; q < d; ++q) idx[q] = min(X[q] >> sh, nmax);
+    const uint64_t code = d_box_code(k, idx, d);
+    int lo = 0, hi = ncb;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ccode[mid] < code)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < ncb && ccode[lo] == code) bi = cidx[lo];
+  }
+  pcnt[i] = 0;
+  if (bi < 0) {
+    atomicMin(bad, i);
+    return;
+  }
+  int64_t sfound = -1;
+  int64_t num[4] = {0, 0, 0, 0}, tot = 0;
+  for (int64_t sx = cbox_simp[bi]; sx < cbox_simp[bi + 1] && sfound < 0; ++sx) {
+    const int64_t *V[4];
+    for (int m = 0; m < k1; ++m) V[m] = cverts + (int64_t)csimp[sx * k1 + m] * d;
+    int64_t t = d_det(d, V);
+    bool inside = true;
+    for (int m = 0; m < k1 && inside; ++m) {
+      const int64_t *Q[4];
+      for (int r = 0; r < k1; ++r) Q[r] = r == m ? X : V[r];
+      int64_t nm = d_det(d, Q);
+      if (t < 0) nm = -nm;
+      if (nm < 0) inside = false;
+      num[m] = nm;
+    }
+    if (inside) {
+      sfound = sx;
+      tot = t < 0 ? -t : t;
+    }
+  }
+  if (sfound < 0) {
+    atomicMin(bad, i);
+    return;
+  }
+  int cols[4];
+  double vals[4];
+  int c = 0;
+  for (int m = 0; m < k1; ++m) {
+    const double lam = __ddiv_rn((double)num[m], (double)tot);
+    if (lam == 0.0) continue;
+    const int j = cdofv[csimp[sfound * k1 + m]];
+    if (j < 0) continue;
+    // insertion by (column, value)
+    int q = c++;
+    while (q > 0 && (cols[q - 1] > j || (cols[q - 1] == j && vals[q - 1] > lam))) {
+      cols[q] = cols[q - 1];
+      vals[q] = vals[q - 1];
+      --q;
+    }
+    cols[q] = j;
+    vals[q] = lam;
+  }
+  // merge equal columns in that order
+  int w = 0;
+  for (int q = 0; q < c; ++q) {
+    if (w > 0 && cols[w - 1] == cols[q]) {
+      vals[w - 1] = __dadd_rn(vals[w - 1], vals[q]);
+    } else {
+      cols[w] = cols[q];
+      vals[w] = vals[q];
+      ++w;
+    }
+  }
+  for (int q = 0; q < w; ++q) {
+    pcol[(int64_t)i * k1 + q] = cols[q];
+    pval[(int64_t)i * k1 + q] = vals[q];
+  }
+  pcnt[i] = w;
+}
+
 struct Bufs {
   std::vector<void *> p;
   template <class T>
@@ -413,6 +531,91 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     }
     if (p != nnz) throw AsmgError{ASMG_EDEVICE, "device level assembly: row counts do not add up"};
   }
+}
+
+// P_l of every level l_c < l <= J on the device; false (nothing built) where the integer
+// coordinates are too large for exact int64 determinants (2-D: J > 30, 3-D: J > 19)
+bool prolongations_device(Hierarchy &h, int ordinal) {
+  const int d = h.d, k1 = d + 1, J = h.J;
+  if ((d == 2 && J > 30) || (d == 3 && J > 19)) return false;
+  HIPCHECK(hipSetDevice(ordinal));
+  hipStream_t s;
+  HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  } sg{s};
+  h.P.clear();
+  for (int l = J; l > h.lc; --l) {
+    const LevelMesh &fine = h.meshes.at(l), &coarse = h.meshes.at(l - 1);
+    const int64_t n = fine.n(), nc = coarse.n(), ncb = (int64_t)coarse.boxes.size();
+    Csr &P = h.P[l];
+    P.nrows = n;
+    P.ncols = nc;
+    P.rp.assign((size_t)n + 1, 0);
+    P.ci.clear();
+    P.v.clear();
+    if (n == 0) continue;
+    if (n >= ((int64_t)1 << 31) || ncb >= ((int64_t)1 << 31) || coarse.nverts() >= ((int64_t)1 << 31))
+      throw AsmgError{ASMG_EINVAL, "level too large for the device prolongation"};
+    // the coarse level's active boxes sorted by code, with their indices
+    std::vector<std::pair<uint64_t, int>> cb((size_t)ncb);
+    for (int64_t b = 0; b < ncb; ++b) cb[b] = {(uint64_t)coarse.boxes[b], (int)b};
+    std::sort(cb.begin(), cb.end());
+    std::vector<uint64_t> ccode((size_t)ncb);
+    std::vector<int> cidx((size_t)ncb);
+    for (int64_t b = 0; b < ncb; ++b) {
+      ccode[b] = cb[b].first;
+      cidx[b] = cb[b].second;
+    }
+    std::vector<int> csimp(coarse.simp.begin(), coarse.simp.end()), cdofv(coarse.dof_of_vert.begin(), coarse.dof_of_vert.end());
+    Bufs B;
+    int64_t *FV = B.get<int64_t>(fine.nverts() * d), *FD = B.get<int64_t>(n), *CV = B.get<int64_t>(coarse.nverts() * d);
+    int64_t *CBS = B.get<int64_t>(ncb + 1);
+    int *CS = B.get<int>((int64_t)csimp.size()), *CI = B.get<int>(ncb), *CD = B.get<int>(coarse.nverts());
+    uint64_t *CC = B.get<uint64_t>(ncb);
+    int *PC = B.get<int>(n * k1), *PN = B.get<int>(n), *BAD = B.get<int>(1);
+    double *PV = B.get<double>(n * k1);
+    HIPCHECK(hipMemcpyAsync(FV, fine.verts.data(), (size_t)fine.nverts() * d * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(FD, fine.dof_vert.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(CV, coarse.verts.data(), (size_t)coarse.nverts() * d * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(CBS, coarse.box_simp.data(), (size_t)(ncb + 1) * 8, hipMemcpyHostToDevice, s));
+    if (!csimp.empty()) HIPCHECK(hipMemcpyAsync(CS, csimp.data(), csimp.size() * 4, hipMemcpyHostToDevice, s));
+    if (ncb) {
+      HIPCHECK(hipMemcpyAsync(CI, cidx.data(), (size_t)ncb * 4, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(CC, ccode.data(), (size_t)ncb * 8, hipMemcpyHostToDevice, s));
+    }
+    HIPCHECK(hipMemcpyAsync(CD, cdofv.data(), (size_t)coarse.nverts() * 4, hipMemcpyHostToDevice, s));
+    const int big = INT32_MAX;
+    HIPCHECK(hipMemcpyAsync(BAD, &big, 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_prolong, dim3(grid(n)), dim3(TB), 0, s, (int)n, d, J, l, (const int64_t *)FV,
+                       (const int64_t *)FD, (const int64_t *)CV, (const int *)CS, (const uint64_t *)CC, (const int *)CI,
+                       (int)ncb, (const int64_t *)CBS, (const int *)CD, PC, PV, PN, BAD);
+    HIPCHECK(hipGetLastError());
+    std::vector<int> pc((size_t)n * k1), pn((size_t)n);
+    std::vector<double> pv((size_t)n * k1);
+    int hbad = 0;
+    HIPCHECK(hipMemcpyAsync(pc.data(), PC, (size_t)n * k1 * 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(pv.data(), PV, (size_t)n * k1 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(pn.data(), PN, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(&hbad, BAD, 4, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (hbad != INT32_MAX)
+      throw AsmgError{ASMG_EINVAL, "prolongation: point location failed at unknown " + std::to_string(hbad)};
+    P.ci.reserve((size_t)n * 2);
+    P.v.reserve((size_t)n * 2);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int q = 0; q < pn[i]; ++q) {
+        P.ci.push_back(pc[i * k1 + q]);
+        P.v.push_back(pv[i * k1 + q]);
+      }
+      P.rp[i + 1] = (int64_t)P.ci.size();
+    }
+  }
+  return true;
 }
 
 }  // namespace asmg

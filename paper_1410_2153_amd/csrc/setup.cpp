@@ -1044,13 +1044,14 @@ void build_level_meshes(Hierarchy &h) {
   for (int li = 1; li < h.lc; ++li) h.level_n[li - 1] = -1;
 }
 
-void build_level_operators(Hierarchy &h, bool assemble) {
+void build_level_operators(Hierarchy &h, bool assemble, bool prolong) {
   const int J = h.J;
   if (assemble) {
     h.Al.clear();
     for (int li = J; li >= h.lc; --li) h.Al[li];
     parallel_for(h, J - h.lc + 1, [&](int64_t i) { assemble_level(h, J - (int)i, h.Al.at(J - (int)i), true); });
   }
+  if (!prolong) return;
   h.P.clear();
   for (int li = J; li > h.lc; --li) h.P[li];
   parallel_for(h, J - h.lc, [&](int64_t i) { build_prolongation(h, J - (int)i, h.P.at(J - (int)i)); });

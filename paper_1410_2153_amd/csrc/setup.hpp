@@ -126,8 +126,9 @@ void build_tree(Hierarchy &h);
 void build_levels(Hierarchy &h);  // build_level_meshes, then build_level_operators(h, true)
 // kappa~ means per Kuhn simplex, the level meshes sigma^(l) from J down to the bottom level l_c
 void build_level_meshes(Hierarchy &h);
-// A_l (l_c <= l <= J; unless `assemble` is false: already built, e.g. on the device) and P_l
-void build_level_operators(Hierarchy &h, bool assemble);
+// A_l (l_c <= l <= J) and P_l (l_c < l <= J); `assemble` / `prolong` false: that one is
+// already built (on the device)
+void build_level_operators(Hierarchy &h, bool assemble, bool prolong = true);
 void assemble_aux_values(Hierarchy &h);
 void build_transfer(Hierarchy &h);
 void build_colourings(Hierarchy &h);

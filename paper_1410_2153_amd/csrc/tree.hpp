@@ -18,6 +18,11 @@ void build_fine_device(Hierarchy &h, int ordinal);
 // (build_level_meshes), assembled on HIP device `ordinal`, bit-identical to the host assembly.
 void assemble_levels_device(Hierarchy &h, int ordinal);
 
+// P_l of every level l_c < l <= J (nodal interpolation by exact point location) on HIP device
+// `ordinal`, bit-identical to the host's; returns false without building anything when the
+// integer coordinates are too large for exact int64 determinants (2-D: J > 30, 3-D: J > 19).
+bool prolongations_device(Hierarchy &h, int ordinal);
+
 // Colourings of the original grid and the smoothed auxiliary levels in the hash order (option
 // colouring = 1) on HIP device `ordinal` by Jones-Plassmann rounds: identical to
 // build_colourings. Throws ASMG_EINVAL for the other orders.

@@ -1,6 +1,6 @@
 """The setup steps built on the device (option setup_device: the fine matrix, Section 2, the
-cluster tree, Sections 3.1-3.2, the level matrices A_l, Section 4.1, and with the hash order the
-colourings) against the host setup and the oracle.
+cluster tree, Sections 3.1-3.2, the level matrices A_l and the prolongations P_l, Section 4.1, and
+with the hash order the colourings) against the host setup and the oracle.
 
 Bar: bit-exact. The unknown numbering, the fine matrix (pattern and values), element keys, the
 refined set, the leaves (with their order), J and kappa~ per leaf equal the host build's; the
@@ -144,7 +144,7 @@ def test_device_level_matrices_on_general_domains(name, domain):
     assert info == Sd.info()
     assert not np.all(Sh.export("level_kept", info["J"]).astype(bool))   # some simplices dropped
     for l in range(info["lc"], info["J"] + 1):
-        for ex in ("Al_rowptr", "Al_col", "Al_val"):
+        for ex in ("Al_rowptr", "Al_col", "Al_val") + (("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
             a, b = Sh.export(ex, l), Sd.export(ex, l)
             assert a.dtype == b.dtype and np.array_equal(a, b), (ex, l)
     f = np.random.default_rng(8).uniform(-1, 1, Sh.n)
