@@ -375,7 +375,9 @@ def graded(args):
     t_setup = time.perf_counter() - t0
     info = S64.info()
     setup_phases = S64.setup_seconds()
-    host_tree = {k: S64.export(k) for k in ("keys", "refined", "leaves", "leaf_kappa", "A_col", "A_val")}
+    host_tree = {(k, 0): S64.export(k) for k in ("keys", "refined", "leaves", "leaf_kappa", "A_col", "A_val")}
+    for lv in sorted({info["J"], info["lc"] + 1} - set(range(info["lc"] + 1))):  # finest, lowest smoothed level
+        host_tree.update({(k, lv): S64.export(k, lv) for k in ("Al_col", "Al_val", "P_col", "P_val")})
     log(f"setup {t_setup:.1f} s: {info}")
     dofs = S64.dof_vertex()
     f = torch.from_numpy(np.ascontiguousarray(c["f_vertex"][dofs])).to(dev)
@@ -493,13 +495,15 @@ def graded(args):
         SD = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, precision=A.PREC_FP64,
                       colouring=args.colouring, setup_device=1, autotune=args.autotune)
         t_setup_d = time.perf_counter() - t0
-        same = SD.info() == info and all(np.array_equal(SD.export(k), host_tree[k]) for k in host_tree)
+        same = SD.info() == info and all(np.array_equal(SD.export(k, lv), host_tree[(k, lv)]) for k, lv in host_tree)
         dph = SD.setup_seconds()
         out["setup"] = {"host_phases_s": setup_phases, "device_setup_phases_s": dph,
                         "total_s_host": t_setup, "total_s_device_setup": t_setup_d,
                         "device_setup_identical": bool(same)}
         log(f"setup: fine matrix + tree on the host {setup_phases['fine'] + setup_phases['tree']:.3f} s, on the "
-            f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); total {t_setup:.1f} -> {t_setup_d:.1f} s")
+            f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); levels (meshes on the host; A_l, P_l "
+            f"on the device) {setup_phases['levels']:.3f} -> {dph['levels']:.3f} s; total {t_setup:.1f} -> "
+            f"{t_setup_d:.1f} s")
         del SD
         # colourings in the hash order (Jones-Plassmann rounds on the device with setup_device = 1)
         hc = {}
