@@ -376,7 +376,7 @@ def graded(args):
     info = S64.info()
     setup_phases = S64.setup_seconds()
     host_tree = {(k, 0): S64.export(k) for k in ("keys", "refined", "leaves", "leaf_kappa", "A_col", "A_val")}
-    for lv in sorted({info["J"], info["lc"] + 1} - set(range(info["lc"] + 1))):  # finest, lowest smoothed level
+    for lv in sorted({lv for lv in (info["J"], info["lc"] + 1) if info["lc"] < lv <= info["J"]}):  # smoothed levels
         host_tree.update({(k, lv): S64.export(k, lv) for k in ("Al_col", "Al_val", "P_col", "P_val")})
     log(f"setup {t_setup:.1f} s: {info}")
     dofs = S64.dof_vertex()
