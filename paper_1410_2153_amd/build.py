@@ -2,8 +2,9 @@
 
 Sources: csrc/setup.cpp (host setup), csrc/domain.cpp (general-domain predicates),
 csrc/api.cpp (C ABI), csrc/device.hip and csrc/batch.hip (kernels and PCG drivers),
-csrc/tree.hip and csrc/assemble.hip (the cluster tree and the fine matrix built on the device,
-option setup_device).
+csrc/tree.hip, csrc/assemble.hip, csrc/levels.hip and csrc/colour.hip (setup steps built on the
+device, option setup_device: cluster tree, fine and level matrices, prolongations, level meshes,
+hash-order colourings).
 The host setup is compiled without floating-point contraction, so barycenters, box
 keys and the exact orientation predicates are plain IEEE operations.
 """
@@ -42,7 +43,7 @@ def build(verbose: bool = True) -> str:
         jobs.append([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     # the device setup reproduces the host setup's IEEE operations: no contraction there either
     for src, extra in (("device.hip", []), ("batch.hip", []), ("tree.hip", ["-ffp-contract=off"]),
-                       ("assemble.hip", ["-ffp-contract=off"]), ("colour.hip", [])):
+                       ("assemble.hip", ["-ffp-contract=off"]), ("colour.hip", []), ("levels.hip", [])):
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         jobs.append([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     objs = [j[-1] for j in jobs]

@@ -183,7 +183,7 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     {
       TraceRange r("asmg::setup::levels");
       if (o.setup_device == 1) {
-        build_level_meshes(h);
+        if (!build_level_meshes_device(h, o.device)) build_level_meshes(h);
         assemble_levels_device(h, o.device);
         build_level_operators(h, false, !prolongations_device(h, o.device));
       } else {

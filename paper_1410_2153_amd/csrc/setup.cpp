@@ -1007,6 +1007,8 @@ static void build_prolongation(Hierarchy &h, int level, Csr &P) {
   }
 }
 
+void compute_level_means(Hierarchy &h) { compute_kuhn_means(h); }
+
 void build_level_meshes(Hierarchy &h) {
   compute_kuhn_means(h);
   const int J = h.J;

@@ -126,6 +126,8 @@ void build_tree(Hierarchy &h);
 void build_levels(Hierarchy &h);  // build_level_meshes, then build_level_operators(h, true)
 // kappa~ means per Kuhn simplex, the level meshes sigma^(l) from J down to the bottom level l_c
 void build_level_meshes(Hierarchy &h);
+// kappa~ means per Kuhn simplex of every box (the level matrices' coefficients)
+void compute_level_means(Hierarchy &h);
 // A_l (l_c <= l <= J) and P_l (l_c < l <= J); `assemble` / `prolong` false: that one is
 // already built (on the device)
 void build_level_operators(Hierarchy &h, bool assemble, bool prolong = true);

@@ -13,6 +13,11 @@ void build_tree_device(Hierarchy &h, int ordinal);
 // fine matrix A on HIP device `ordinal`, bit-identical to build_fine.
 void build_fine_device(Hierarchy &h, int ordinal);
 
+// Level meshes sigma^(l) from J down to the bottom level l_c (and the kappa~ means per Kuhn
+// simplex) on HIP device `ordinal`, identical to build_level_meshes; returns false without
+// building anything on a general domain or when vertex keys exceed 64 bits ((J+1) d > 64).
+bool build_level_meshes_device(Hierarchy &h, int ordinal);
+
 // A_l of every level l_c..J (Section 4.1: the P1 stiffness matrix of sigma^(l) with the
 // auxiliary coefficient kappa~ per Kuhn simplex) from the level meshes already built on the host
 // (build_level_meshes), assembled on HIP device `ordinal`, bit-identical to the host assembly.

@@ -1,6 +1,7 @@
 """The setup steps built on the device (option setup_device: the fine matrix, Section 2, the
-cluster tree, Sections 3.1-3.2, the level matrices A_l and the prolongations P_l, Section 4.1, and
-with the hash order the colourings) against the host setup and the oracle.
+cluster tree, Sections 3.1-3.2, the level meshes, Section 3.3, the level matrices A_l and the
+prolongations P_l, Section 4.1, and with the hash order the colourings) against the host setup and
+the oracle.
 
 Bar: bit-exact. The unknown numbering, the fine matrix (pattern and values), element keys, the
 refined set, the leaves (with their order), J and kappa~ per leaf equal the host build's; the
@@ -66,10 +67,12 @@ def test_device_tree_matches_host_and_oracle(name):
         assert a.dtype == b.dtype and np.array_equal(a, b), ex
     assert np.array_equal(Sh.dof_vertex(), Sd.dof_vertex())
     assert Sh.info() == Sd.info()
-    # A_l of every level (assembled on the device) and P_l, bit for bit
+    # the level meshes, A_l of every level and P_l (built on the device), bit for bit
     info = Sh.info()
+    assert np.array_equal(Sh.export("level_n"), Sd.export("level_n"))
     for l in range(info["lc"], info["J"] + 1):
-        for ex in ("Al_rowptr", "Al_col", "Al_val") + (("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
+        for ex in ("level_verts", "level_simp", "level_dofs", "level_kept", "Al_rowptr", "Al_col", "Al_val") + (
+                ("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
             a, b = Sh.export(ex, l), Sd.export(ex, l)
             assert a.dtype == b.dtype and np.array_equal(a, b), (ex, l)
     d = c["coords"].shape[1]
