@@ -501,8 +501,8 @@ def graded(args):
                         "total_s_host": t_setup, "total_s_device_setup": t_setup_d,
                         "device_setup_identical": bool(same)}
         log(f"setup: fine matrix + tree on the host {setup_phases['fine'] + setup_phases['tree']:.3f} s, on the "
-            f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); levels (meshes on the host; A_l, P_l "
-            f"on the device) {setup_phases['levels']:.3f} -> {dph['levels']:.3f} s; total {t_setup:.1f} -> "
+            f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); levels (meshes, A_l, P_l on the "
+            f"device) {setup_phases['levels']:.3f} -> {dph['levels']:.3f} s; total {t_setup:.1f} -> "
             f"{t_setup_d:.1f} s")
         del SD
         # colourings in the hash order (Jones-Plassmann rounds on the device with setup_device = 1)

@@ -92,13 +92,16 @@ typedef struct {
                           e_l = P_l e_(l-1) and k V-cycles (Algorithm 2) on A_l e = g_l, in the
                           V-cycle's precision; u_0 = Pi e_J. Single-mesh handles with whole-level
                           smoothing (smoothing = 0) only. */
-  int setup_device;    /* 1 = assemble the fine matrix (Section 2) and build the cluster tree
-                          (Sections 3.1-3.2: root box, keys, Morton sort, refinement by cluster
-                          size, closure, leaves, kappa~) on the HIP device, and with
-                          colouring = 1 also the multicolour orderings (Jones-Plassmann rounds,
-                          the same colouring as the host's greedy one in the hash order), with
-                          results identical to the host setup; the other setup steps stay on the
-                          host. Needs device >= 0; single-mesh handles. 0 = host (default). */
+  int setup_device;    /* 1 = build on the HIP device: the fine matrix (Section 2), the cluster
+                          tree (Sections 3.1-3.2: root box, keys, Morton sort, refinement by
+                          cluster size, closure, leaves, kappa~), the level meshes (Section 3.3;
+                          root-box grids whose vertex keys fit 64 bits, (J+1) dim <= 64), the
+                          level matrices A_l and the prolongations P_l (Section 4.1), and with
+                          colouring = 1 the multicolour orderings (Jones-Plassmann rounds, the
+                          same colouring as the host's greedy one in the hash order); every
+                          result identical to the host setup's. The other setup steps (and the
+                          level meshes of general domains) stay on the host. Needs device >= 0;
+                          single-mesh handles. 0 = host (default). */
   int red_blocks;      /* cap on the blocks of the PCG reduction kernels (dot products, residual
                           norms, q = A p), 1..2048; 0 = 2048 (default). Beyond the cap the kernels
                           loop over their rows (grid-stride). Results do not depend on it beyond
