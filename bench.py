@@ -375,7 +375,8 @@ def graded(args):
     t_setup = time.perf_counter() - t0
     info = S64.info()
     setup_phases = S64.setup_seconds()
-    host_tree = {(k, 0): S64.export(k) for k in ("keys", "refined", "leaves", "leaf_kappa", "A_col", "A_val")}
+    host_tree = {(k, 0): S64.export(k) for k in ("keys", "refined", "leaves", "leaf_kappa", "A_col", "A_val",
+                                                   "Pi_col", "Pi_val")}
     for lv in sorted({lv for lv in (info["J"], info["lc"] + 1) if info["lc"] < lv <= info["J"]}):  # smoothed levels
         host_tree.update({(k, lv): S64.export(k, lv) for k in ("Al_col", "Al_val", "P_col", "P_val")})
     log(f"setup {t_setup:.1f} s: {info}")
@@ -502,7 +503,8 @@ def graded(args):
                         "device_setup_identical": bool(same)}
         log(f"setup: fine matrix + tree on the host {setup_phases['fine'] + setup_phases['tree']:.3f} s, on the "
             f"device {dph['fine'] + dph['tree']:.3f} s (identical: {same}); levels (meshes, A_l, P_l on the "
-            f"device) {setup_phases['levels']:.3f} -> {dph['levels']:.3f} s; total {t_setup:.1f} -> "
+            f"device) {setup_phases['levels']:.3f} -> {dph['levels']:.3f} s; Pi {setup_phases['transfer']:.3f} -> "
+            f"{dph['transfer']:.3f} s; total {t_setup:.1f} -> "
             f"{t_setup_d:.1f} s")
         del SD
         # colourings in the hash order (Jones-Plassmann rounds on the device with setup_device = 1)

@@ -96,7 +96,8 @@ typedef struct {
                           tree (Sections 3.1-3.2: root box, keys, Morton sort, refinement by
                           cluster size, closure, leaves, kappa~), the level meshes (Section 3.3;
                           root-box grids whose vertex keys fit 64 bits, (J+1) dim <= 64), the
-                          level matrices A_l and the prolongations P_l (Section 4.1), and with
+                          level matrices A_l, the prolongations P_l and the Scott-Zhang
+                          transfer Pi (Section 4.1), and with
                           colouring = 1 the multicolour orderings (Jones-Plassmann rounds, the
                           same colouring as the host's greedy one in the hash order); every
                           result identical to the host setup's. The other setup steps (and the
@@ -271,6 +272,9 @@ int asmg_time_kernel(asmg_handle h, int which, int reps, int precision, void *st
  *   "leaf_kappa"    double kappa~ per leaf, in the order of "leaves"
  *   "setup_seconds" double wall time of the setup phases: fine matrix, cluster tree, level
  *                   meshes, transfers, colourings, bottom inverse, device upload
+ *   "device_stages" int64[1] setup stages that ran on the device (option setup_device), bits:
+ *                   1 fine matrix, 2 cluster tree, 4 level meshes, 8 A_l, 16 P_l, 32 Pi,
+ *                   64 colourings
  *   "level_n"       int64 number of unknowns of every level 1..J
  *   "level_verts"   int64 integer coordinates (n_verts*dim) of sigma^(level)
  *   "level_simp"    int64 vertex indices (n_simp*(dim+1)) of sigma^(level)

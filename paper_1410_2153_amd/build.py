@@ -43,7 +43,8 @@ def build(verbose: bool = True) -> str:
         jobs.append([HIPCC, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     # the device setup reproduces the host setup's IEEE operations: no contraction there either
     for src, extra in (("device.hip", []), ("batch.hip", []), ("tree.hip", ["-ffp-contract=off"]),
-                       ("assemble.hip", ["-ffp-contract=off"]), ("colour.hip", []), ("levels.hip", [])):
+                       ("assemble.hip", ["-ffp-contract=off"]), ("colour.hip", []), ("levels.hip", []),
+                       ("transfer.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         jobs.append([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     objs = [j[-1] for j in jobs]

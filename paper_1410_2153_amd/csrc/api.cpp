@@ -165,27 +165,37 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     TraceRange all("asmg::setup");
     {
       TraceRange r("asmg::setup::fine");
-      if (o.setup_device == 1)
+      if (o.setup_device == 1) {
         build_fine_device(h, o.device);
-      else
+        h.device_stages |= 1;
+      } else {
         build_fine(h);
+      }
     }
     lap("fine");
     {
       TraceRange r("asmg::setup::tree");
-      if (o.setup_device == 1)
+      if (o.setup_device == 1) {
         build_tree_device(h, o.device);
-      else
+        h.device_stages |= 2;
+      } else {
         build_tree(h);
+      }
       if (o.domain >= 1) build_domain(h);
     }
     lap("tree");
     {
       TraceRange r("asmg::setup::levels");
       if (o.setup_device == 1) {
-        if (!build_level_meshes_device(h, o.device)) build_level_meshes(h);
+        if (build_level_meshes_device(h, o.device))
+          h.device_stages |= 4;
+        else
+          build_level_meshes(h);
         assemble_levels_device(h, o.device);
-        build_level_operators(h, false, !prolongations_device(h, o.device));
+        h.device_stages |= 8;
+        const bool p_dev = prolongations_device(h, o.device);
+        if (p_dev) h.device_stages |= 16;
+        build_level_operators(h, false, !p_dev);
       } else {
         build_levels(h);
       }
@@ -193,15 +203,20 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
     lap("levels");
     {
       TraceRange r("asmg::setup::transfer");
-      build_transfer(h);
+      if (o.setup_device == 1 && build_transfer_device(h, o.device))
+        h.device_stages |= 32;
+      else
+        build_transfer(h);
     }
     lap("transfer");
     {
       TraceRange r("asmg::setup::colourings");
-      if (o.setup_device == 1 && o.colouring == 1)
+      if (o.setup_device == 1 && o.colouring == 1) {
         build_colourings_device(h, o.device);
-      else
+        h.device_stages |= 64;
+      } else {
         build_colourings(h);
+      }
       build_local_sets(h);
     }
     lap("colourings");
@@ -513,6 +528,7 @@ int asmg_export(asmg_handle H, const char *name_c, int level, void *buf, int64_t
       return put(v, buf, count);
     }
     if (name == "setup_seconds") return put(h.setup_seconds, buf, count);
+    if (name == "device_stages") return put(std::vector<int64_t>{h.device_stages}, buf, count);
     if (name == "level_n") {
       std::vector<int64_t> v(h.J);
       for (int l = 1; l <= h.J; ++l) v[l - 1] = level_mesh(h, l).n();

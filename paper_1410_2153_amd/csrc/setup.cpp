@@ -1319,9 +1319,9 @@ void build_transfer(Hierarchy &h) {
         }
       }
     }
-    std::sort(acc.begin(), acc.end(), [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
-      return x.first < y.first;
-    });
+    // by column, equal columns in the order they were met (summed in that order below)
+    std::stable_sort(acc.begin(), acc.end(), [](const std::pair<int32_t, double> &x,
+                                                const std::pair<int32_t, double> &y) { return x.first < y.first; });
     const size_t before = oci.size();
     for (size_t q = 0; q < acc.size(); ++q) {
       if (q > 0 && acc[q].first == acc[q - 1].first)

@@ -80,6 +80,9 @@ struct Hierarchy {
   std::vector<uint8_t> dirichlet;
   asmg_options opt{};
   int threads = 0;  // host threads for the setup (0 = all cores)
+  // setup stages that ran on the device (bits: 1 fine matrix, 2 cluster tree, 4 level meshes,
+  // 8 A_l, 16 P_l, 32 Pi, 64 colourings)
+  int64_t device_stages = 0;
   std::vector<double> setup_seconds;  // wall time of the setup phases: fine, tree, levels,
                                       // transfer, colourings, coarse, upload
 

@@ -28,6 +28,12 @@ void assemble_levels_device(Hierarchy &h, int ordinal);
 // integer coordinates are too large for exact int64 determinants (2-D: J > 30, 3-D: J > 19).
 bool prolongations_device(Hierarchy &h, int ordinal);
 
+// The Scott-Zhang transfer Pi (one thread per unknown: sigma_i, the leaves meeting it, exact
+// clipping against sigma^(J) and quadrature) on HIP device `ordinal`, identical to
+// build_transfer; returns false without building anything when the sizes exceed 32-bit indices
+// (the caller then builds Pi on the host).
+bool build_transfer_device(Hierarchy &h, int ordinal);
+
 // Colourings of the original grid and the smoothed auxiliary levels in the hash order (option
 // colouring = 1) on HIP device `ordinal` by Jones-Plassmann rounds: identical to
 // build_colourings. Throws ASMG_EINVAL for the other orders.

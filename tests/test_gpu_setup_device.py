@@ -1,7 +1,7 @@
 """The setup steps built on the device (option setup_device: the fine matrix, Section 2, the
-cluster tree, Sections 3.1-3.2, the level meshes, Section 3.3, the level matrices A_l and the
-prolongations P_l, Section 4.1, and with the hash order the colourings) against the host setup and
-the oracle.
+cluster tree, Sections 3.1-3.2, the level meshes, Section 3.3, the level matrices A_l, the
+prolongations P_l and the Scott-Zhang transfer Pi, Section 4.1, and with the hash order the
+colourings) against the host setup and the oracle.
 
 Bar: bit-exact. The unknown numbering, the fine matrix (pattern and values), element keys, the
 refined set, the leaves (with their order), J and kappa~ per leaf equal the host build's; the
@@ -67,9 +67,14 @@ def test_device_tree_matches_host_and_oracle(name):
         assert a.dtype == b.dtype and np.array_equal(a, b), ex
     assert np.array_equal(Sh.dof_vertex(), Sd.dof_vertex())
     assert Sh.info() == Sd.info()
-    # the level meshes, A_l of every level and P_l (built on the device), bit for bit
+    # the level meshes, A_l of every level, P_l and Pi (built on the device), bit for bit
+    assert int(Sh.export("device_stages")[0]) == 0
+    assert int(Sd.export("device_stages")[0]) == 1 | 2 | 4 | 8 | 16 | 32
     info = Sh.info()
     assert np.array_equal(Sh.export("level_n"), Sd.export("level_n"))
+    for ex in ("Pi_rowptr", "Pi_col", "Pi_val"):
+        a, b = Sh.export(ex), Sd.export(ex)
+        assert a.dtype == b.dtype and np.array_equal(a, b), ex
     for l in range(info["lc"], info["J"] + 1):
         for ex in ("level_verts", "level_simp", "level_dofs", "level_kept", "Al_rowptr", "Al_col", "Al_val") + (
                 ("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
@@ -116,6 +121,7 @@ def test_device_colouring_matches_host(name, seed):
     kw = dict(device=0, colouring=1, colour_seed=seed)
     Sh = A.Solver(c["coords"], c["elems"], c["kappa"], **kw)
     Sd = A.Solver(c["coords"], c["elems"], c["kappa"], setup_device=1, **kw)
+    assert int(Sd.export("device_stages")[0]) & 64
     assert np.array_equal(Sh.export("colour_fine"), Sd.export("colour_fine"))
     info = Sh.info()
     for l in range(info["lc"] + 1, info["J"] + 1):
@@ -143,9 +149,14 @@ def test_device_level_matrices_on_general_domains(name, domain):
         dm = boundary_vertices(T, len(X)) & (np.hypot(X[:, 0] - 0.5, X[:, 1] - 0.5) > 0.35)
     Sh = A.Solver(c["coords"], c["elems"], c["kappa"], dm, device=0, domain=domain)
     Sd = A.Solver(c["coords"], c["elems"], c["kappa"], dm, device=0, domain=domain, setup_device=1)
+    # general domains: the level meshes stay on the host, the rest runs on the device
+    assert int(Sd.export("device_stages")[0]) == 1 | 2 | 8 | 16 | 32
     info = Sh.info()
     assert info == Sd.info()
     assert not np.all(Sh.export("level_kept", info["J"]).astype(bool))   # some simplices dropped
+    for ex in ("Pi_rowptr", "Pi_col", "Pi_val"):
+        a, b = Sh.export(ex), Sd.export(ex)
+        assert a.dtype == b.dtype and np.array_equal(a, b), ex
     for l in range(info["lc"], info["J"] + 1):
         for ex in ("Al_rowptr", "Al_col", "Al_val") + (("P_rowptr", "P_col", "P_val") if l > info["lc"] else ()):
             a, b = Sh.export(ex, l), Sd.export(ex, l)
