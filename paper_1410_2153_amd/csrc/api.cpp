@@ -191,11 +191,18 @@ int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elem
           h.device_stages |= 4;
         else
           build_level_meshes(h);
-        assemble_levels_device(h, o.device);
+        {
+          TraceRange r2("asmg::setup::level_matrices");
+          assemble_levels_device(h, o.device);
+        }
         h.device_stages |= 8;
-        const bool p_dev = prolongations_device(h, o.device);
+        bool p_dev = false;
+        {
+          TraceRange r2("asmg::setup::prolongations");
+          p_dev = prolongations_device(h, o.device);
+          if (!p_dev) build_level_operators(h, false, true);
+        }
         if (p_dev) h.device_stages |= 16;
-        build_level_operators(h, false, !p_dev);
       } else {
         build_levels(h);
       }

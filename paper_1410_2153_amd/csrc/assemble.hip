@@ -129,6 +129,30 @@ __global__ __launch_bounds__(TB) void k_entries(int64_t m, const uint64_t *__res
 // simplex-major, as assemble_level computes them on the host: integer cofactors of the simplex
 // in units of half its box side, the Kuhn coefficient of its box (the first one on fan boxes),
 // value = dot / (d! |det|) (times half * unit in 3-D) times kappa~
+// Kuhn coefficients of each active box: binary search of its code in the sorted table of all
+// boxes' codes (wcode, 6 coefficients per box in wtab)
+__global__ __launch_bounds__(TB) void k_box_weights(int64_t nb, const uint64_t *__restrict__ code,
+                                                    const uint64_t *__restrict__ wcode, int64_t nw,
+                                                    const double *__restrict__ wtab, double *__restrict__ bw,
+                                                    int *__restrict__ missing) {
+  const int64_t b = blockIdx.x * (int64_t)TB + threadIdx.x;
+  if (b >= nb) return;
+  const uint64_t c = code[b];
+  int64_t lo = 0, hi = nw;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (wcode[mid] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo >= nw || wcode[lo] != c) {
+    atomicAdd(missing, 1);
+    return;
+  }
+  for (int q = 0; q < 6; ++q) bw[b * 6 + q] = wtab[lo * 6 + q];
+}
+
 __global__ __launch_bounds__(TB) void k_level_contrib(int64_t ns, int d, int J, double unit,
                                                       const int64_t *__restrict__ verts, const int *__restrict__ simp,
                                                       const int *__restrict__ sbox, const int8_t *__restrict__ stmpl,
@@ -425,6 +449,7 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
   const int d = h.d, k = d + 1, J = h.J;
   HIPCHECK(hipSetDevice(ordinal));
   const double unit = std::ldexp(h.L, -h.J);
+  Bufs WB;  // destroyed after the stream guard: the stream has drained before it is freed
   hipStream_t s;
   HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct StreamGuard {
@@ -435,6 +460,29 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     }
   } sg{s};
   h.Al.clear();
+  // the Kuhn coefficients of every box once, sorted by code (looked up per level on the device)
+  std::vector<std::pair<uint64_t, const KuhnW *>> wl;
+  wl.reserve(h.kuhn_w.size());
+  for (const auto &kv : h.kuhn_w) wl.push_back({(uint64_t)kv.first, &kv.second});
+  std::sort(wl.begin(), wl.end(),
+            [](const std::pair<uint64_t, const KuhnW *> &x, const std::pair<uint64_t, const KuhnW *> &y) {
+              return x.first < y.first;
+            });
+  const int64_t nw = (int64_t)wl.size();
+  std::vector<uint64_t> wcode((size_t)nw);
+  std::vector<double> wtab((size_t)nw * 6);
+  for (int64_t i = 0; i < nw; ++i) {
+    wcode[i] = wl[i].first;
+    for (int q = 0; q < 6; ++q) wtab[i * 6 + q] = (*wl[i].second)[q];
+  }
+  uint64_t *WC = WB.get<uint64_t>(nw);
+  double *WT = WB.get<double>(nw * 6);
+  int *missing = WB.get<int>(1);
+  if (nw) {
+    HIPCHECK(hipMemcpyAsync(WC, wcode.data(), (size_t)nw * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(WT, wtab.data(), (size_t)nw * 6 * 8, hipMemcpyHostToDevice, s));
+  }
+  HIPCHECK(hipMemsetAsync(missing, 0, 4, s));
   for (int l = J; l >= h.lc; --l) {
     const LevelMesh &lm = h.meshes.at(l);
     const int64_t ns = (int64_t)lm.simp_box.size(), nb = (int64_t)lm.boxes.size(), nvl = lm.nverts(),
@@ -449,15 +497,10 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
       A.v.clear();
       continue;
     }
-    // host images: simplex vertices, per-box level, fan flag and Kuhn coefficients
+    // host images: simplex vertices, per-box level and fan flag; the Kuhn coefficients by code
     std::vector<int> simp(lm.simp.begin(), lm.simp.end()), dofv(lm.dof_of_vert.begin(), lm.dof_of_vert.end());
     std::vector<int8_t> blev((size_t)nb);
-    std::vector<double> bw((size_t)nb * 6);
-    for (int64_t b = 0; b < nb; ++b) {
-      blev[b] = (int8_t)box_level(lm.boxes[b], d);
-      const KuhnW &w = h.kuhn_w.at(lm.boxes[b]);
-      for (int q = 0; q < 6; ++q) bw[b * 6 + q] = w[q];
-    }
+    for (int64_t b = 0; b < nb; ++b) blev[b] = (int8_t)box_level(lm.boxes[b], d);
     Bufs B;
     int64_t *V = B.get<int64_t>(nvl * d);
     int *S = B.get<int>(ns * k), *SB = B.get<int>(ns), *DV = B.get<int>(nvl);
@@ -471,7 +514,10 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     HIPCHECK(hipMemcpyAsync(ST, lm.simp_tmpl.data(), (size_t)ns, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(BL, blev.data(), (size_t)nb, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(BF, lm.fan.data(), (size_t)nb, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(BW, bw.data(), (size_t)nb * 6 * 8, hipMemcpyHostToDevice, s));
+    uint64_t *BCODE = B.get<uint64_t>(nb);
+    HIPCHECK(hipMemcpyAsync(BCODE, lm.boxes.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_box_weights, dim3(grid(nb)), dim3(TB), 0, s, nb, (const uint64_t *)BCODE,
+                       (const uint64_t *)WC, nw, (const double *)WT, BW, missing);
     if (KP) HIPCHECK(hipMemcpyAsync(KP, lm.kept.data(), (size_t)ns, hipMemcpyHostToDevice, s));
     uint64_t *key = B.get<uint64_t>(m), *key_s = B.get<uint64_t>(m);
     double *val = B.get<double>(m), *val_s = B.get<double>(m);
@@ -531,6 +577,10 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     }
     if (p != nnz) throw AsmgError{ASMG_EDEVICE, "device level assembly: row counts do not add up"};
   }
+  int hmiss = 0;
+  HIPCHECK(hipMemcpyAsync(&hmiss, missing, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (hmiss) throw AsmgError{ASMG_EDEVICE, "device level assembly: a box without Kuhn coefficients"};
 }
 
 // P_l of every level l_c < l <= J on the device; false (nothing built) where the integer

@@ -19,6 +19,7 @@
 
 #include "common.hpp"
 #include "setup.hpp"
+#include "trace.hpp"
 #include "tree.hpp"
 
 namespace asmg {
@@ -479,7 +480,11 @@ bool build_level_meshes_device(Hierarchy &h, int ordinal) {
   const int d = h.d, J = h.J;
   if (h.domain || (J + 1) * d > 64) return false;
   HIPCHECK(hipSetDevice(ordinal));
-  compute_level_means(h);
+  {
+    TraceRange r("asmg::setup::level_means");
+    compute_level_means(h);
+  }
+  TraceRange r("asmg::setup::level_meshes");
   std::vector<uint64_t> Rs(h.R.begin(), h.R.end());
   std::sort(Rs.begin(), Rs.end());
   std::vector<uint64_t> leaves(h.leaves.begin(), h.leaves.end());
