@@ -179,7 +179,9 @@ int asmg_dof_vertex(asmg_handle h, int32_t *map);
  *   f, u                 n doubles (host pointers)
  *   iterations           number of products with A (may be NULL)
  *   true_rel_residual    ||f - A u|| / ||f|| recomputed at exit (may be NULL)
- * f = 0 returns u = 0 and 0 iterations. Returns ASMG_ENOCONV if max_iter is hit.
+ * f = 0 returns u = 0 and 0 iterations. Returns ASMG_ENOCONV if max_iter is hit. A mesh with
+ * no unknown (every vertex Dirichlet, n = 0) returns at once with 0 iterations; its vector
+ * arguments, here and in the other single-mesh vector entry points, may then be NULL.
  */
 int asmg_solve(asmg_handle h, const double *f, double tol, double *u, int *iterations,
                double *true_rel_residual);

@@ -292,9 +292,12 @@ static int need_dev(asmg_handle H) {
   return ASMG_OK;
 }
 
+// vectors of n = 0 unknowns (every vertex Dirichlet) may be null
+static bool bad_vec(asmg_handle H, const void *p) { return !p && H->h.n() > 0; }
+
 int asmg_solve(asmg_handle H, const double *f, double tol, double *u, int *iterations, double *true_rel) {
   if (int r = need_dev(H)) return r;
-  if (!f || !u) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, f) || bad_vec(H, u)) return set_err(ASMG_EINVAL, "null vector");
   if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
   ASMG_TRY({
     int rc = device_solve_host(H->dev, f, tol, u, iterations, true_rel);
@@ -306,7 +309,7 @@ int asmg_solve(asmg_handle H, const double *f, double tol, double *u, int *itera
 int asmg_solve_device(asmg_handle H, const double *d_f, double tol, double *d_u, int *iterations, double *true_rel,
                       void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_f || !d_u) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, d_f) || bad_vec(H, d_u)) return set_err(ASMG_EINVAL, "null vector");
   if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
   ASMG_TRY({
     int rc = device_solve(H->dev, d_f, tol, d_u, iterations, true_rel, stream);
@@ -318,7 +321,7 @@ int asmg_solve_device(asmg_handle H, const double *d_f, double tol, double *d_u,
 int asmg_solve_device_noalloc(asmg_handle H, const double *d_f, double tol, double *d_u, int *iterations,
                               double *true_rel, void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_f || !d_u) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, d_f) || bad_vec(H, d_u)) return set_err(ASMG_EINVAL, "null vector");
   if (!(tol > 0) || !std::isfinite(tol)) return set_err(ASMG_EINVAL, "tol must be > 0");
   ASMG_TRY({
     int rc = device_solve_noalloc(H->dev, d_f, tol, d_u, iterations, true_rel, stream);
@@ -329,7 +332,7 @@ int asmg_solve_device_noalloc(asmg_handle H, const double *d_f, double tol, doub
 
 int asmg_apply_preconditioner_device(asmg_handle H, const double *d_r, double *d_z, int precision, void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_r || !d_z || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED))
+  if (bad_vec(H, d_r) || bad_vec(H, d_z) || (precision != ASMG_PREC_FP64 && precision != ASMG_PREC_MIXED))
     return set_err(ASMG_EINVAL, "bad argument");
   ASMG_TRY({ return device_apply_B(H->dev, d_r, d_z, precision, stream); })
 }
@@ -348,19 +351,19 @@ int asmg_set_log_coefficient_device(asmg_handle H, const double *d_m, void *stre
 
 int asmg_matvec_device(asmg_handle H, const double *d_x, double *d_y, void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_x || !d_y) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, d_x) || bad_vec(H, d_y)) return set_err(ASMG_EINVAL, "null vector");
   ASMG_TRY({ return device_matvec(H->dev, d_x, d_y, stream); })
 }
 
 int asmg_element_gradient_device(asmg_handle H, const double *d_u, const double *d_lam, double *d_g, void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_u || !d_lam || !d_g) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, d_u) || bad_vec(H, d_lam) || !d_g) return set_err(ASMG_EINVAL, "null vector");
   ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, 1.0, stream); })
 }
 
 int asmg_adjoint_gradient_device(asmg_handle H, const double *d_u, const double *d_lam, double *d_g, void *stream) {
   if (int r = need_dev(H)) return r;
-  if (!d_u || !d_lam || !d_g) return set_err(ASMG_EINVAL, "null vector");
+  if (bad_vec(H, d_u) || bad_vec(H, d_lam) || !d_g) return set_err(ASMG_EINVAL, "null vector");
   ASMG_TRY({ return device_element_gradient(H->dev, d_u, d_lam, d_g, -1.0, stream); })
 }
 

@@ -165,3 +165,20 @@ def test_device_level_matrices_on_general_domains(name, domain):
     uh, ih, _ = Sh.solve(f, 1e-8)
     ud, idv, _ = Sd.solve(f, 1e-8)
     assert ih == idv and np.array_equal(uh, ud)
+
+
+@pytest.mark.parametrize("setup_device", [0, 1])
+def test_mesh_without_unknowns(setup_device):
+    # every vertex Dirichlet (n = 0): the solve, B_co, the product and the gradient return at once
+    c = _tiny()
+    S = A.Solver(c["coords"], c["elems"], c["kappa"], device=0, setup_device=setup_device)
+    assert S.n == 0
+    u, it, tr = S.solve(np.zeros(0), 1e-8)
+    assert u.shape == (0,) and it == 0
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    ud, itd, _ = S.solve_device(e, 1e-8)
+    assert ud.numel() == 0 and itd == 0
+    assert S.apply_preconditioner(e).numel() == 0
+    assert S.matvec(e).numel() == 0
+    g = S.element_gradient(e, e).cpu().numpy()
+    assert g.shape == (len(c["elems"]),) and np.all(g == 0)
