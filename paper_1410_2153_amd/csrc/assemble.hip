@@ -154,18 +154,18 @@ __global__ __launch_bounds__(TB) void k_box_weights(int64_t nb, const uint64_t *
 }
 
 __global__ __launch_bounds__(TB) void k_level_contrib(int64_t ns, int d, int J, double unit,
-                                                      const int64_t *__restrict__ verts, const int *__restrict__ simp,
+                                                      const int64_t *__restrict__ verts, const int64_t *__restrict__ simp,
                                                       const int *__restrict__ sbox, const int8_t *__restrict__ stmpl,
-                                                      const int8_t *__restrict__ blev, const uint8_t *__restrict__ bfan,
+                                                      const uint64_t *__restrict__ bcode, const uint8_t *__restrict__ bfan,
                                                       const double *__restrict__ bw, const uint8_t *__restrict__ kept,
-                                                      const int *__restrict__ dofv, uint64_t *__restrict__ key,
+                                                      const int64_t *__restrict__ dofv, uint64_t *__restrict__ key,
                                                       double *__restrict__ val) {
   const int64_t s = blockIdx.x * (int64_t)TB + threadIdx.x;
   if (s >= ns) return;
   const int k = d + 1;
   int u[4];
   const bool in = kept == nullptr || kept[s];
-  for (int i = 0; i < k; ++i) u[i] = in ? dofv[simp[s * k + i]] : -1;
+  for (int i = 0; i < k; ++i) u[i] = in ? (int)dofv[simp[s * k + i]] : -1;
   bool any = false;
   for (int i = 0; i < k; ++i) any |= u[i] >= 0;
   if (!any) {
@@ -176,7 +176,8 @@ __global__ __launch_bounds__(TB) void k_level_contrib(int64_t ns, int d, int J, 
     return;
   }
   const int b = sbox[s];
-  const int64_t half = (int64_t)1 << (J - blev[b]);
+  const int blev = (63 - __clzll((long long)bcode[b])) / d + 1;  // level of the box's code
+  const int64_t half = (int64_t)1 << (J - blev);
   const int64_t *v0 = verts + (int64_t)simp[s * k] * d;
   int64_t M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int c = 0; c < d; ++c) {
@@ -251,11 +252,16 @@ __device__ __forceinline__ int64_t d_det(int d, const int64_t *const P[4]) {
 // smallest active box of level l-1 holding the vertex, the first of its simplices that contains
 // it (exact barycentric coordinates), the nonzero coordinates at level l-1's unknowns, sorted by
 // (column, value) as the host does; `bad` gets the row if the point location fails
+__global__ __launch_bounds__(TB) void k_iota(int64_t n, int *__restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x;
+  if (i < n) x[i] = (int)i;
+}
+
 __global__ __launch_bounds__(TB) void k_prolong(int n, int d, int J, int level, const int64_t *__restrict__ fverts,
                                                 const int64_t *__restrict__ fdof, const int64_t *__restrict__ cverts,
-                                                const int *__restrict__ csimp, const uint64_t *__restrict__ ccode,
+                                                const int64_t *__restrict__ csimp, const uint64_t *__restrict__ ccode,
                                                 const int *__restrict__ cidx, int ncb,
-                                                const int64_t *__restrict__ cbox_simp, const int *__restrict__ cdofv,
+                                                const int64_t *__restrict__ cbox_simp, const int64_t *__restrict__ cdofv,
                                                 int *__restrict__ pcol, double *__restrict__ pval,
                                                 int *__restrict__ pcnt, int *__restrict__ bad) {
   const int i = blockIdx.x * TB + threadIdx.x;
@@ -314,7 +320,7 @@ __global__ __launch_bounds__(TB) void k_prolong(int n, int d, int J, int level, 
   for (int m = 0; m < k1; ++m) {
     const double lam = __ddiv_rn((double)num[m], (double)tot);
     if (lam == 0.0) continue;
-    const int j = cdofv[csimp[sfound * k1 + m]];
+    const int j = (int)cdofv[csimp[sfound * k1 + m]];
     if (j < 0) continue;
     // insertion by (column, value)
     int q = c++;
@@ -483,12 +489,37 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     HIPCHECK(hipMemcpyAsync(WT, wtab.data(), (size_t)nw * 6 * 8, hipMemcpyHostToDevice, s));
   }
   HIPCHECK(hipMemsetAsync(missing, 0, 4, s));
+  // work arrays sized once for the largest level
+  int64_t mns = 1, mnb = 1, mnv = 1, mn = 1;
+  for (int l = J; l >= h.lc; --l) {
+    const LevelMesh &lm = h.meshes.at(l);
+    mns = std::max<int64_t>(mns, (int64_t)lm.simp_box.size());
+    mnb = std::max<int64_t>(mnb, (int64_t)lm.boxes.size());
+    mnv = std::max<int64_t>(mnv, lm.nverts());
+    mn = std::max<int64_t>(mn, lm.n());
+  }
+  const int64_t mm = mns * k * k;
+  if (mm >= ((int64_t)1 << 31) || mn >= ((int64_t)1 << 31) || mnv >= ((int64_t)1 << 31))
+    throw AsmgError{ASMG_EINVAL, "level too large for the device assembly"};
+  int64_t *V = WB.get<int64_t>(mnv * d), *S = WB.get<int64_t>(mns * k), *DV = WB.get<int64_t>(mnv);
+  int *SB = WB.get<int>(mns);
+  int8_t *ST = WB.get<int8_t>(mns);
+  uint8_t *BF = WB.get<uint8_t>(mnb), *KP = WB.get<uint8_t>(mns);
+  uint64_t *BCODE = WB.get<uint64_t>(mnb);
+  double *BW = WB.get<double>(mnb * 6);
+  uint64_t *key = WB.get<uint64_t>(mm), *key_s = WB.get<uint64_t>(mm);
+  double *val = WB.get<double>(mm), *val_s = WB.get<double>(mm);
+  int *head = WB.get<int>(mm), *pos = WB.get<int>(mm), *ci = WB.get<int>(mm), *rowcnt = WB.get<int>(mn);
+  double *v = WB.get<double>(mm);
+  size_t tb_sort = 0, tb_scan = 0;
+  HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_sort, key, key_s, val, val_s, (int)mm, 0, 64, s));
+  HIPCHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb_scan, head, pos, (int)mm, s));
+  const size_t tb = std::max(tb_sort, tb_scan);
+  void *tmp = WB.get<char>((int64_t)tb);
   for (int l = J; l >= h.lc; --l) {
     const LevelMesh &lm = h.meshes.at(l);
     const int64_t ns = (int64_t)lm.simp_box.size(), nb = (int64_t)lm.boxes.size(), nvl = lm.nverts(),
                   n = lm.n(), m = ns * k * k;
-    if (m >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31) || nvl >= ((int64_t)1 << 31))
-      throw AsmgError{ASMG_EINVAL, "level too large for the device assembly"};
     Csr &A = h.Al[l];
     A.nrows = A.ncols = n;
     if (m == 0 || n == 0) {
@@ -497,59 +528,34 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
       A.v.clear();
       continue;
     }
-    // host images: simplex vertices, per-box level and fan flag; the Kuhn coefficients by code
-    std::vector<int> simp(lm.simp.begin(), lm.simp.end()), dofv(lm.dof_of_vert.begin(), lm.dof_of_vert.end());
-    std::vector<int8_t> blev((size_t)nb);
-    for (int64_t b = 0; b < nb; ++b) blev[b] = (int8_t)box_level(lm.boxes[b], d);
-    Bufs B;
-    int64_t *V = B.get<int64_t>(nvl * d);
-    int *S = B.get<int>(ns * k), *SB = B.get<int>(ns), *DV = B.get<int>(nvl);
-    int8_t *ST = B.get<int8_t>(ns), *BL = B.get<int8_t>(nb);
-    uint8_t *BF = B.get<uint8_t>(nb), *KP = lm.kept.empty() ? nullptr : B.get<uint8_t>(ns);
-    double *BW = B.get<double>(nb * 6);
     HIPCHECK(hipMemcpyAsync(V, lm.verts.data(), (size_t)nvl * d * 8, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(S, simp.data(), (size_t)ns * k * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(S, lm.simp.data(), (size_t)ns * k * 8, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(SB, lm.simp_box.data(), (size_t)ns * 4, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(DV, dofv.data(), (size_t)nvl * 4, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(DV, lm.dof_of_vert.data(), (size_t)nvl * 8, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(ST, lm.simp_tmpl.data(), (size_t)ns, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(BL, blev.data(), (size_t)nb, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(BF, lm.fan.data(), (size_t)nb, hipMemcpyHostToDevice, s));
-    uint64_t *BCODE = B.get<uint64_t>(nb);
     HIPCHECK(hipMemcpyAsync(BCODE, lm.boxes.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
+    if (!lm.kept.empty()) HIPCHECK(hipMemcpyAsync(KP, lm.kept.data(), (size_t)ns, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_box_weights, dim3(grid(nb)), dim3(TB), 0, s, nb, (const uint64_t *)BCODE,
                        (const uint64_t *)WC, nw, (const double *)WT, BW, missing);
-    if (KP) HIPCHECK(hipMemcpyAsync(KP, lm.kept.data(), (size_t)ns, hipMemcpyHostToDevice, s));
-    uint64_t *key = B.get<uint64_t>(m), *key_s = B.get<uint64_t>(m);
-    double *val = B.get<double>(m), *val_s = B.get<double>(m);
     hipLaunchKernelGGL(k_level_contrib, dim3(grid(ns)), dim3(TB), 0, s, ns, d, J, unit, (const int64_t *)V,
-                       (const int *)S, (const int *)SB, (const int8_t *)ST, (const int8_t *)BL, (const uint8_t *)BF,
-                       (const double *)BW, (const uint8_t *)KP, (const int *)DV, key, val);
-    {
-      size_t tb = 0;
-      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key_s, val, val_s, (int)m, 0, 64, s));
-      void *tmp = B.get<char>((int64_t)tb);
-      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, val, val_s, (int)m, 0, 64, s));
-    }
-    int *head = B.get<int>(m), *pos = B.get<int>(m);
+                       (const int64_t *)S, (const int *)SB, (const int8_t *)ST, (const uint64_t *)BCODE,
+                       (const uint8_t *)BF, (const double *)BW, lm.kept.empty() ? (const uint8_t *)nullptr : KP,
+                       (const int64_t *)DV, key, val);
+    size_t tbs = tb;
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tbs, key, key_s, val, val_s, (int)m, 0, 64, s));
     hipLaunchKernelGGL(k_heads, dim3(grid(m)), dim3(TB), 0, s, m, (const uint64_t *)key_s, head);
-    {
-      size_t tb = 0;
-      HIPCHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, head, pos, (int)m, s));
-      void *tmp = B.get<char>((int64_t)tb);
-      HIPCHECK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, head, pos, (int)m, s));
-    }
+    tbs = tb;
+    HIPCHECK(hipcub::DeviceScan::ExclusiveSum(tmp, tbs, head, pos, (int)m, s));
     int last_pos = 0, last_head = 0;
     HIPCHECK(hipMemcpyAsync(&last_pos, pos + (m - 1), 4, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(&last_head, head + (m - 1), 4, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    const int64_t nnz = (int64_t)last_pos + last_head;
-    int *ci = B.get<int>(nnz);
-    double *v = B.get<double>(nnz);
-    int *rowcnt = B.get<int>(n);
     HIPCHECK(hipMemsetAsync(rowcnt, 0, (size_t)n * 4, s));
     hipLaunchKernelGGL(k_entries, dim3(grid(m)), dim3(TB), 0, s, m, (const uint64_t *)key_s, (const double *)val_s,
                        (const int *)head, (const int *)pos, ci, v, rowcnt);
     HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    const int64_t nnz = (int64_t)last_pos + last_head;
     std::vector<int32_t> hci((size_t)nnz);
     std::vector<double> hv((size_t)nnz);
     std::vector<int> cnt((size_t)n);
@@ -561,20 +567,21 @@ void assemble_levels_device(Hierarchy &h, int ordinal) {
     HIPCHECK(hipStreamSynchronize(s));
     // the host's pattern rule: drop entries that are exactly zero off the diagonal
     A.rp.assign((size_t)n + 1, 0);
-    A.ci.clear();
-    A.v.clear();
-    A.ci.reserve((size_t)nnz);
-    A.v.reserve((size_t)nnz);
-    int64_t p = 0;
+    A.ci.resize((size_t)nnz);
+    A.v.resize((size_t)nnz);
+    int64_t p = 0, w = 0;
     for (int64_t i = 0; i < n; ++i) {
       for (int64_t e = p; e < p + cnt[i]; ++e)
         if (hv[e] != 0.0 || hci[e] == i) {
-          A.ci.push_back(hci[e]);
-          A.v.push_back(hv[e]);
+          A.ci[w] = hci[e];
+          A.v[w] = hv[e];
+          ++w;
         }
       p += cnt[i];
-      A.rp[i + 1] = (int64_t)A.ci.size();
+      A.rp[i + 1] = w;
     }
+    A.ci.resize((size_t)w);
+    A.v.resize((size_t)w);
     if (p != nnz) throw AsmgError{ASMG_EDEVICE, "device level assembly: row counts do not add up"};
   }
   int hmiss = 0;
@@ -611,39 +618,35 @@ bool prolongations_device(Hierarchy &h, int ordinal) {
     if (n == 0) continue;
     if (n >= ((int64_t)1 << 31) || ncb >= ((int64_t)1 << 31) || coarse.nverts() >= ((int64_t)1 << 31))
       throw AsmgError{ASMG_EINVAL, "level too large for the device prolongation"};
-    // the coarse level's active boxes sorted by code, with their indices
-    std::vector<std::pair<uint64_t, int>> cb((size_t)ncb);
-    for (int64_t b = 0; b < ncb; ++b) cb[b] = {(uint64_t)coarse.boxes[b], (int)b};
-    std::sort(cb.begin(), cb.end());
-    std::vector<uint64_t> ccode((size_t)ncb);
-    std::vector<int> cidx((size_t)ncb);
-    for (int64_t b = 0; b < ncb; ++b) {
-      ccode[b] = cb[b].first;
-      cidx[b] = cb[b].second;
-    }
-    std::vector<int> csimp(coarse.simp.begin(), coarse.simp.end()), cdofv(coarse.dof_of_vert.begin(), coarse.dof_of_vert.end());
     Bufs B;
     int64_t *FV = B.get<int64_t>(fine.nverts() * d), *FD = B.get<int64_t>(n), *CV = B.get<int64_t>(coarse.nverts() * d);
-    int64_t *CBS = B.get<int64_t>(ncb + 1);
-    int *CS = B.get<int>((int64_t)csimp.size()), *CI = B.get<int>(ncb), *CD = B.get<int>(coarse.nverts());
-    uint64_t *CC = B.get<uint64_t>(ncb);
+    int64_t *CBS = B.get<int64_t>(ncb + 1), *CS = B.get<int64_t>((int64_t)coarse.simp.size());
+    int64_t *CD = B.get<int64_t>(coarse.nverts());
+    uint64_t *CB0 = B.get<uint64_t>(ncb), *CC = B.get<uint64_t>(ncb);
+    int *CI0 = B.get<int>(ncb), *CI = B.get<int>(ncb);
     int *PC = B.get<int>(n * k1), *PN = B.get<int>(n), *BAD = B.get<int>(1);
     double *PV = B.get<double>(n * k1);
     HIPCHECK(hipMemcpyAsync(FV, fine.verts.data(), (size_t)fine.nverts() * d * 8, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(FD, fine.dof_vert.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(CV, coarse.verts.data(), (size_t)coarse.nverts() * d * 8, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(CBS, coarse.box_simp.data(), (size_t)(ncb + 1) * 8, hipMemcpyHostToDevice, s));
-    if (!csimp.empty()) HIPCHECK(hipMemcpyAsync(CS, csimp.data(), csimp.size() * 4, hipMemcpyHostToDevice, s));
+    if (!coarse.simp.empty())
+      HIPCHECK(hipMemcpyAsync(CS, coarse.simp.data(), coarse.simp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(CD, coarse.dof_of_vert.data(), (size_t)coarse.nverts() * 8, hipMemcpyHostToDevice, s));
+    // the coarse level's active boxes sorted by code, with their indices (radix sort on the device)
     if (ncb) {
-      HIPCHECK(hipMemcpyAsync(CI, cidx.data(), (size_t)ncb * 4, hipMemcpyHostToDevice, s));
-      HIPCHECK(hipMemcpyAsync(CC, ccode.data(), (size_t)ncb * 8, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(CB0, coarse.boxes.data(), (size_t)ncb * 8, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_iota, dim3(grid(ncb)), dim3(TB), 0, s, ncb, CI0);
+      size_t tb = 0;
+      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, CB0, CC, CI0, CI, (int)ncb, 0, 64, s));
+      void *tmp = B.get<char>((int64_t)tb);
+      HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, CB0, CC, CI0, CI, (int)ncb, 0, 64, s));
     }
-    HIPCHECK(hipMemcpyAsync(CD, cdofv.data(), (size_t)coarse.nverts() * 4, hipMemcpyHostToDevice, s));
     const int big = INT32_MAX;
     HIPCHECK(hipMemcpyAsync(BAD, &big, 4, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_prolong, dim3(grid(n)), dim3(TB), 0, s, (int)n, d, J, l, (const int64_t *)FV,
-                       (const int64_t *)FD, (const int64_t *)CV, (const int *)CS, (const uint64_t *)CC, (const int *)CI,
-                       (int)ncb, (const int64_t *)CBS, (const int *)CD, PC, PV, PN, BAD);
+                       (const int64_t *)FD, (const int64_t *)CV, (const int64_t *)CS, (const uint64_t *)CC,
+                       (const int *)CI, (int)ncb, (const int64_t *)CBS, (const int64_t *)CD, PC, PV, PN, BAD);
     HIPCHECK(hipGetLastError());
     std::vector<int> pc((size_t)n * k1), pn((size_t)n);
     std::vector<double> pv((size_t)n * k1);

@@ -314,6 +314,11 @@ __global__ __launch_bounds__(TT) void k_transfer(TrArgs A) {
   if (!A.off) A.cnt[i] = ncontrib;
 }
 
+__global__ __launch_bounds__(TT) void k_tr_iota(int64_t n, int *__restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)TT + threadIdx.x;
+  if (i < n) x[i] = (int)i;
+}
+
 // first position of each run of equal keys
 __global__ __launch_bounds__(TT) void k_tr_heads(int64_t m, const uint64_t *__restrict__ key, int *__restrict__ head) {
   const int64_t i = blockIdx.x * (int64_t)TT + threadIdx.x;
@@ -348,7 +353,7 @@ bool build_transfer_device(Hierarchy &h, int ordinal) {
   const int d = h.d, k = d + 1;
   const LevelMesh &lm = h.meshes.at(h.J);
   const int64_t n = h.n(), nb = (int64_t)lm.boxes.size(), ns = (int64_t)lm.simp_box.size();
-  if (n >= ((int64_t)1 << 31) || h.nv >= ((int64_t)1 << 31)) return false;
+  if (n >= ((int64_t)1 << 31) || h.nv >= ((int64_t)1 << 31) || nb >= ((int64_t)1 << 31)) return false;
   HIPCHECK(hipSetDevice(ordinal));
   std::vector<void *> keep;
   hipStream_t s = nullptr;
@@ -366,15 +371,6 @@ bool build_transfer_device(Hierarchy &h, int ordinal) {
   HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   std::vector<uint64_t> Rs(h.R.begin(), h.R.end());
   std::sort(Rs.begin(), Rs.end());
-  std::vector<std::pair<uint64_t, int>> cb((size_t)nb);
-  for (int64_t b = 0; b < nb; ++b) cb[b] = {(uint64_t)lm.boxes[b], (int)b};
-  std::sort(cb.begin(), cb.end());
-  std::vector<uint64_t> bcode((size_t)nb);
-  std::vector<int> bidx((size_t)nb);
-  for (int64_t b = 0; b < nb; ++b) {
-    bcode[b] = cb[b].first;
-    bidx[b] = cb[b].second;
-  }
   int *E = tr_alloc<int>(keep, h.ne * k);
   unsigned long long *sig = tr_alloc<unsigned long long>(keep, h.nv);
   int64_t *dofs = tr_alloc<int64_t>(keep, n);
@@ -389,8 +385,17 @@ bool build_transfer_device(Hierarchy &h, int ordinal) {
   HIPCHECK(hipMemcpyAsync(dofs, h.dofs.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(X, h.coords.data(), (size_t)h.nv * d * 8, hipMemcpyHostToDevice, s));
   if (!Rs.empty()) HIPCHECK(hipMemcpyAsync(R, Rs.data(), Rs.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(BC, bcode.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(BI, bidx.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s));
+  // level J's active boxes sorted by code, with their indices (radix sort on the device)
+  if (nb) {
+    uint64_t *BC0 = tr_alloc<uint64_t>(keep, nb);
+    int *BI0 = tr_alloc<int>(keep, nb);
+    HIPCHECK(hipMemcpyAsync(BC0, lm.boxes.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_tr_iota, dim3((unsigned)((nb + TT - 1) / TT)), dim3(TT), 0, s, nb, BI0);
+    size_t tb = 0;
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, BC0, BC, BI0, BI, (int)nb, 0, 64, s));
+    void *tmp = tr_alloc<char>(keep, (int64_t)tb);
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, BC0, BC, BI0, BI, (int)nb, 0, 64, s));
+  }
   HIPCHECK(hipMemcpyAsync(BS, lm.box_simp.data(), (size_t)(nb + 1) * 8, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(SI, lm.simp.data(), (size_t)ns * k * 8, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(V, lm.verts.data(), lm.verts.size() * 8, hipMemcpyHostToDevice, s));
