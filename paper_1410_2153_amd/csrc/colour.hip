@@ -140,6 +140,7 @@ void build_colourings_device(Hierarchy &h, int ordinal) {
   int *d_rp = nullptr, *d_ci = nullptr, *d_c0 = nullptr, *d_c1 = nullptr, *d_left = nullptr;
   hipStream_t s = nullptr;
   auto release = [&]() {
+    if (s) (void)hipStreamSynchronize(s);  // nothing in flight reads the buffers below
     if (d_rp) (void)hipFree(d_rp);
     if (d_ci) (void)hipFree(d_ci);
     if (d_c0) (void)hipFree(d_c0);

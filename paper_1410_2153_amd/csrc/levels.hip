@@ -488,6 +488,7 @@ bool build_level_meshes_device(Hierarchy &h, int ordinal) {
   std::vector<uint64_t> Rs(h.R.begin(), h.R.end());
   std::sort(Rs.begin(), Rs.end());
   std::vector<uint64_t> leaves(h.leaves.begin(), h.leaves.end());
+  LvBufs B;  // destroyed after the stream guard: the stream has drained before it is freed
   hipStream_t s;
   HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct StreamGuard {
@@ -497,7 +498,6 @@ bool build_level_meshes_device(Hierarchy &h, int ordinal) {
       (void)hipStreamDestroy(s);
     }
   } sg{s};
-  LvBufs B;
   uint64_t *dR = B.get<uint64_t>((int64_t)Rs.size()), *dL = B.get<uint64_t>((int64_t)leaves.size());
   if (!Rs.empty()) HIPCHECK(hipMemcpyAsync(dR, Rs.data(), Rs.size() * 8, hipMemcpyHostToDevice, s));
   if (!leaves.empty()) HIPCHECK(hipMemcpyAsync(dL, leaves.data(), leaves.size() * 8, hipMemcpyHostToDevice, s));
