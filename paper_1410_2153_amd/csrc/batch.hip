@@ -15,6 +15,7 @@
 // block straddles two meshes, and the last block of a mesh reduces its partials.
 // Converged systems are frozen; the launch sequence stops when all are done.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -31,6 +32,9 @@ namespace asmg {
 
 #ifndef LOWER_FIRST_SWEEP
 #define LOWER_FIRST_SWEEP 1
+#endif
+#ifndef UPPER_RESIDUAL
+#define UPPER_RESIDUAL 1
 #endif
 
 enum { BST_OK = 0, BST_NOTSPD = 1, BST_NAN = 2, BST_NOCONV = 3 };
@@ -87,9 +91,10 @@ __device__ __forceinline__ void bpin(T &v) {
   asm volatile("" : "+v"(v));
 }
 
-template <int W, int NR, class T, class Pre, class Post>
+// UP: only the entries with a column above `urow` (the row's later colours) are gathered and added
+template <int W, int NR, bool UP = false, class T, class Pre, class Post>
 __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
-                                            const T *__restrict__ x, Pre &pre, Post &post) {
+                                            const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   const VecR<NR, T> *X = reinterpret_cast<const VecR<NR, T> *>(x);
   int c[W];
   T v[W];
@@ -112,6 +117,7 @@ __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T 
   for (int r = 0; r < NR; ++r) a0[r] = a1[r] = 0;
 #pragma unroll
   for (int k = 0; k < W; ++k) {
+    if (UP && c[k] <= urow) continue;
     const VecR<NR, T> xv = X[c[k]];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -130,20 +136,20 @@ __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T 
   post(acc);
 }
 
-template <int NR, class T>
+template <int NR, bool UP, class T>
 __device__ __forceinline__ void bsell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
-                                            const T *__restrict__ x, T acc[NR]) {
+                                            const T *__restrict__ x, T acc[NR], int urow) {
   auto pre = [] {};
   auto post = [&](T a[NR]) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] += a[r];
   };
-  bsell_row_w<8, NR>(cp, vp, x, pre, post);
+  bsell_row_w<8, NR, UP>(cp, vp, x, pre, post, urow);
 }
 
-template <int NR, class T, class Pre, class Post>
+template <int NR, class T, bool UP = false, class Pre, class Post>
 __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
-                                          const T *__restrict__ x, Pre &pre, Post &post) {
+                                          const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   switch (w) {
     case 0: {
       pre();
@@ -153,18 +159,18 @@ __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, con
       post(z);
       break;
     }
-    case 1: bsell_row_w<1, NR>(cp, vp, x, pre, post); break;
-    case 2: bsell_row_w<2, NR>(cp, vp, x, pre, post); break;
-    case 3: bsell_row_w<3, NR>(cp, vp, x, pre, post); break;
-    case 4: bsell_row_w<4, NR>(cp, vp, x, pre, post); break;
-    case 5: bsell_row_w<5, NR>(cp, vp, x, pre, post); break;
-    case 6: bsell_row_w<6, NR>(cp, vp, x, pre, post); break;
-    case 7: bsell_row_w<7, NR>(cp, vp, x, pre, post); break;
-    case 8: bsell_row_w<8, NR>(cp, vp, x, pre, post); break;
-    case 9: bsell_row_w<9, NR>(cp, vp, x, pre, post); break;
-    case 10: bsell_row_w<10, NR>(cp, vp, x, pre, post); break;
-    case 11: bsell_row_w<11, NR>(cp, vp, x, pre, post); break;
-    case 12: bsell_row_w<12, NR>(cp, vp, x, pre, post); break;
+    case 1: bsell_row_w<1, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 2: bsell_row_w<2, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 3: bsell_row_w<3, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 4: bsell_row_w<4, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 5: bsell_row_w<5, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 6: bsell_row_w<6, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 7: bsell_row_w<7, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 8: bsell_row_w<8, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 9: bsell_row_w<9, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 10: bsell_row_w<10, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 11: bsell_row_w<11, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 12: bsell_row_w<12, NR, UP>(cp, vp, x, pre, post, urow); break;
     default: {
       // long rows: chunks of 8 entries, each with its loads issued together
       pre();
@@ -173,10 +179,12 @@ __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, con
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = 0;
       int k = 0;
-      for (; k + 8 <= w; k += 8) bsell_chunk<NR>(cp + k * 64, vp + k * 64, x, acc);
+      for (; k + 8 <= w; k += 8) bsell_chunk<NR, UP>(cp + k * 64, vp + k * 64, x, acc, urow);
       for (; k < w; ++k) {
+        const int ck = cp[k * 64];
+        if (UP && ck <= urow) continue;
         const T a = vp[k * 64];
-        const VecR<NR, T> xv = X[cp[k * 64]];
+        const VecR<NR, T> xv = X[ck];
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r] += a * xv.v[r];
       }
@@ -191,6 +199,10 @@ __device__ __forceinline__ int bwave_slice(int first) {
 
 // MODE 0: Gauss-Seidel colour pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii (dv_ = 1/a_ii)
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j (dv_ = a_ii)
+// MODE 2: residual right after a single forward sweep from x = 0, r_i = -sum_{j > i} a_ij x_j:
+// when row i's colour was solved its later colours were zero and its earlier ones final, so only
+// the later colours' terms remain (each mesh numbers its rows colour by colour). Slice s starts
+// at shi[s] (passed as soff); b, dv_ and x at the row are not read.
 // over slices [s0, s1), every right-hand side of a row at once
 template <int MODE, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__restrict__ srow,
@@ -204,22 +216,26 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__r
     VecR<NR, T> bv, xv;
     T di = 0;
     auto pre = [&] {
+      if (MODE == 2) return;
       const int rr = row < 0 ? 0 : row;
       bv = reinterpret_cast<const VecR<NR, T> *>(b)[rr];
       di = dv_[rr];
       if (MODE == 1) xv = reinterpret_cast<const VecR<NR, T> *>(x)[rr];
     };
     auto post = [&](T acc[NR]) {
+      if (MODE != 2) {
 #pragma unroll
-      for (int q = 0; q < NR; ++q) bpin(bv.v[q]);
-      bpin(di);
+        for (int q = 0; q < NR; ++q) bpin(bv.v[q]);
+        bpin(di);
+      }
       if (row < 0) return;
       VecR<NR, T> o;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : bv.v[q] - di * xv.v[q] - acc[q];
+      for (int q = 0; q < NR; ++q)
+        o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : MODE == 1 ? bv.v[q] - di * xv.v[q] - acc[q] : -acc[q];
       reinterpret_cast<VecR<NR, T> *>(MODE == 0 ? x : r)[row] = o;
     };
-    bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+    bsell_row<NR, T, MODE == 2>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post, row);
   });
 }
 
@@ -717,6 +733,7 @@ struct BSell {
   std::vector<int> cslice{0};
   int *srow = nullptr, *soff = nullptr, *scol = nullptr;
   int *slo = nullptr;    // per slice: end of its entries before each row's own colour range
+  int *shi = nullptr;    // per slice: end of the narrowest such prefix over its rows
   double *sv64 = nullptr;
   float *sv32 = nullptr;
 };
@@ -729,6 +746,7 @@ struct BLevel {
   BSell sell;            // off-diagonal part of the smoothing rows; group c = colour c of every mesh
   std::vector<int64_t> cnnz, crows, ucols;  // per colour group: nonzeros, rows, distinct columns gathered
   std::vector<int64_t> cnnz_lo, ucols_lo;   // the same over the columns of earlier colours
+  std::vector<int64_t> cnnz_up, ucols_up;   // the same over the columns of later colours
   double *dg64 = nullptr, *id64 = nullptr, *id0_64 = nullptr;  // a_ii, 1/a_ii, 1/a_ii on colour 0 else 0
   float *dg32 = nullptr, *id32 = nullptr, *id0_32 = nullptr;
   double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
@@ -888,8 +906,8 @@ struct BSellHost {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
   // slo[s]: end of the entries of slice s before each row's own range (the widest such prefix
-  // over the lanes; rows store their columns in ascending order)
-  std::vector<int> srow, soff{0}, scol, cslice{0}, block0{0}, slo;
+  // over the lanes; rows store their columns in ascending order); shi[s]: the narrowest one
+  std::vector<int> srow, soff{0}, scol, cslice{0}, block0{0}, slo, shi;
   std::vector<double> sv;
   std::vector<float> sv32;
 };
@@ -904,6 +922,7 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
   auto empty_slice = [&]() {
     for (int j = 0; j < 64; ++j) srow.push_back(-1);
     X.slo.push_back(soff.back());
+    X.shi.push_back(soff.back());
     soff.push_back(soff.back());
   };
   for (const auto &g : groups) {
@@ -918,13 +937,14 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
         std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return len(x) > len(y); });
         for (size_t a = 0; a < idx.size(); a += 64) {
           const size_t e = std::min(a + 64, idx.size());
-          int wmax = 0, wlo = 0;
+          int wmax = 0, wlo = 0, whi = INT_MAX;
           for (size_t i = a; i < e; ++i) {
             const int r = idx[i];
             wmax = std::max(wmax, len(r));
             int lo = 0;
             while (lo < len(r) && H.ci[H.rp[r] + lo] < rg.first) ++lo;
             wlo = std::max(wlo, lo);
+            whi = std::min(whi, lo);
           }
           const int base = soff.back();
           scol.resize(base + 64 * wmax);
@@ -949,6 +969,7 @@ static void bsell_host(const HMat &H, const Groups &groups, bool pad_blocks, BSe
           }
           soff.push_back(base + 64 * wmax);
           X.slo.push_back(base + 64 * wlo);
+          X.shi.push_back(base + 64 * std::min(whi, wmax));
         }
       }
     }
@@ -982,6 +1003,7 @@ static void bsell_upload(BatchDevice *dv, const BSellHost &X, BSell &S) {
   S.srow = bupload(dv, X.srow);
   S.soff = bupload(dv, X.soff);
   S.slo = bupload(dv, X.slo);
+  S.shi = bupload(dv, X.shi);
   S.scol = bupload(dv, X.scol);
   S.sv64 = bupload(dv, X.sv);
   S.sv32 = bupload(dv, X.sv32);
@@ -1117,30 +1139,42 @@ static void transfer_stats(const HMat &H, const std::vector<int> &rows, BSellHos
 
 // byte-model counts of each row-range group of H: nonzeros, rows, and the distinct columns the
 // group's rows gather (each x entry read once per colour pass)
-static void group_counts(const HMat &H, const Groups &groups, std::vector<int64_t> &cnnz, std::vector<int64_t> &crows,
-                         std::vector<int64_t> &ucols, std::vector<int64_t> &cnnz_lo, std::vector<int64_t> &ucols_lo) {
+struct GroupCounts {
+  std::vector<int64_t> cnnz, crows, ucols, cnnz_lo, ucols_lo, cnnz_up, ucols_up;
+};
+
+static void group_counts(const HMat &H, const Groups &groups, GroupCounts &K) {
   const int G = (int)groups.size();
-  cnnz.assign(G, 0);
-  crows.assign(G, 0);
-  ucols.assign(G, 0);
-  cnnz_lo.assign(G, 0);
-  ucols_lo.assign(G, 0);
+  for (auto *v : {&K.cnnz, &K.crows, &K.ucols, &K.cnnz_lo, &K.ucols_lo, &K.cnnz_up, &K.ucols_up}) v->assign(G, 0);
   std::vector<int> seen(std::max(H.ncols, 1), -1);
   for (int g = 0; g < G; ++g)
     for (const auto &rg : groups[g])
       for (int i = rg.first; i < rg.second; ++i) {
-        ++crows[g];
+        ++K.crows[g];
         for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
-          const bool lo = H.ci[p] < rg.first;  // a column of an earlier colour of the row's mesh
-          ++cnnz[g];
-          cnnz_lo[g] += lo;
+          // a column of an earlier / a later colour of the row's mesh
+          const bool lo = H.ci[p] < rg.first, up = H.ci[p] >= rg.second;
+          ++K.cnnz[g];
+          K.cnnz_lo[g] += lo;
+          K.cnnz_up[g] += up;
           if (seen[H.ci[p]] != g) {
             seen[H.ci[p]] = g;
-            ++ucols[g];
-            ucols_lo[g] += lo;
+            ++K.ucols[g];
+            K.ucols_lo[g] += lo;
+            K.ucols_up[g] += up;
           }
         }
       }
+}
+
+static void set_counts(BLevel &L, GroupCounts &&K) {
+  L.cnnz = std::move(K.cnnz);
+  L.crows = std::move(K.crows);
+  L.ucols = std::move(K.ucols);
+  L.cnnz_lo = std::move(K.cnnz_lo);
+  L.ucols_lo = std::move(K.ucols_lo);
+  L.cnnz_up = std::move(K.cnnz_up);
+  L.ucols_up = std::move(K.ucols_up);
 }
 
 BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int ordinal) {
@@ -1242,7 +1276,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       std::vector<double> diag;
       std::vector<uint8_t> c0flag;
       BSellHost gs, cg;
-      std::vector<int64_t> cnnz, crows, ucols, cnnz_lo, ucols_lo;  // byte-model counts of every colour group
+      GroupCounts counts;  // byte-model counts of every colour group
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
       std::vector<int64_t> moff;
@@ -1277,7 +1311,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
-        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols, X.cnnz_lo, X.ucols_lo);
+        group_counts(X.A, groups, X.counts);
         // CG products: group m = mesh m, whole blocks per mesh
         Groups mg(nm);
         for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
@@ -1338,7 +1372,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
             if (c + 1 < (int)co.size()) groups[c].push_back({L.off[i] + co[c], L.off[i] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
-        group_counts(X.A, groups, X.cnnz, X.crows, X.ucols, X.cnnz_lo, X.ucols_lo);
+        group_counts(X.A, groups, X.counts);
         for (size_t i = 0; i < bottom_m[k].size(); ++i) {
           const int m = bottom_m[k][i];
           const int nc = (int)H[m]->nc;
@@ -1393,11 +1427,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       upload_diag(dv, F, X.diag, X.c0flag);
       alloc_level_vectors(dv, F);
       bsell_upload(dv, X.gs, F.sell);
-      F.cnnz = X.cnnz;
-      F.crows = X.crows;
-      F.ucols = X.ucols;
-      F.cnnz_lo = X.cnnz_lo;
-      F.ucols_lo = X.ucols_lo;
+      set_counts(F, std::move(X.counts));
       bsell_upload(dv, X.cg, dv->cg_sell);
       dv->cg_b0 = bupload(dv, X.cg.block0);
       dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
@@ -1424,11 +1454,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       BLevel &L = dv->aux[k];
       LevelImage &X = aux_img[k];
       bsell_upload(dv, X.gs, L.sell);
-      L.cnnz = X.cnnz;
-      L.crows = X.crows;
-      L.ucols = X.ucols;
-      L.cnnz_lo = X.cnnz_lo;
-      L.ucols_lo = X.ucols_lo;
+      set_counts(L, std::move(X.counts));
       upload_diag(dv, L, X.diag, X.c0flag);
       L.bottom_rows = X.pref.back();
       L.bt_rowpref = bupload(dv, X.pref);
@@ -1667,20 +1693,37 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
 // zero in exact arithmetic, so the kernel skips the group (r was zeroed at setup there and
 // nothing else writes it). Meshes with fewer colours have their last colour in earlier groups,
 // which are computed.
+// `upper`: x is the result of a single forward sweep from zero, and the kernel computes each row's
+// residual from its later colours' terms alone (kb_sell MODE 2).
 template <int NR, class T>
-static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s) {
+static void b_residual(BatchDevice *dv, BLevel &L, const T *b, hipStream_t s, bool upper) {
   if (L.nsmooth == 0) return;
   const BSell &S = L.sell;
   const int C = (int)S.cslice.size() - 1;
   const int s1 = C >= 1 ? S.cslice[C - 1] : S.nslices;
   slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
     with_var(var, [&](auto vc) {
-      launch_timed((kb_sell<1, NR, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
-                   S.soff, S.soff + 1, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L), shape_arg(th, xcd));
+      if (upper)
+        launch_timed((kb_sell<2, NR, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
+                     S.shi, S.soff + 1, S.scol, bsv<T>(S), (const T *)nullptr, (const T *)nullptr, BV<T>::x(L),
+                     BV<T>::r(L), shape_arg(th, xcd));
+      else
+        launch_timed((kb_sell<1, NR, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
+                     S.soff, S.soff + 1, S.scol, bsv<T>(S), BV<T>::dg(L), b, BV<T>::x(L), BV<T>::r(L),
+                     shape_arg(th, xcd));
     });
   });
-  if (dv->count_bytes && S.nslices > 0)
-    dv->bytes += (bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1)) * s1 / S.nslices;
+  if (dv->count_bytes && S.nslices > 0) {
+    if (upper) {
+      // the later colours' entries, the row indices, r written, each gathered x entry once
+      const double sz = sizeof(T);
+      for (int c = 0; c + 1 < C; ++c)
+        dv->bytes += (double)L.cnnz_up[c] * (sz + 4) + 4.0 * (double)L.crows[c] +
+                     sz * NR * (double)(L.crows[c] + L.ucols_up[c]);
+    } else {
+      dv->bytes += (bsell_bytes(S, sizeof(T)) + (double)L.nsmooth * sizeof(T) * (3.0 * NR + 1)) * s1 / S.nslices;
+    }
+  }
 }
 
 // y = A x (ADD 0) or y += A x (ADD 1); FIRST: y is level Lt's right-hand side and the first colour
@@ -1710,7 +1753,7 @@ static void b_vcycle(BatchDevice *dv, int k, hipStream_t s) {
   }
   if (L.nsmooth == 0) return;
   for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, it == 0, true, true, s);
-  b_residual<NR, T>(dv, L, b, s);
+  b_residual<NR, T>(dv, L, b, s, UPPER_RESIDUAL && dv->nu_aux == 1);
   BLevel &Lc = dv->aux[k + 1];
   b_spmv<NR, 0, 1, T>(dv, L.PT, BV<T>::r(L), BV<T>::b(Lc), &Lc, s);
   b_vcycle<NR, T>(dv, k + 1, s);
@@ -1737,7 +1780,7 @@ static void b_apply(BatchDevice *dv, const double *r, bool first_done, hipStream
     b = F.b32;
   }
   for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, it == 0, first_done, true, s);
-  b_residual<NR, T>(dv, F, b, s);
+  b_residual<NR, T>(dv, F, b, s, UPPER_RESIDUAL && dv->nu_fine == 1);
   b_spmv<NR, 0, 1, T>(dv, dv->PiT, BV<T>::r(F), BV<T>::b(dv->aux[0]), &dv->aux[0], s);
   b_vcycle<NR, T>(dv, 0, s);
   b_spmv<NR, 1, 0, T>(dv, dv->Pi, BV<T>::x(dv->aux[0]), BV<T>::x(F), nullptr, s);

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -44,6 +45,9 @@ namespace asmg {
 
 #ifndef LOWER_FIRST_SWEEP
 #define LOWER_FIRST_SWEEP 1
+#endif
+#ifndef UPPER_RESIDUAL
+#define UPPER_RESIDUAL 1
 #endif
 
 // ---------------------------------------------------------------------------
@@ -97,9 +101,11 @@ __device__ __forceinline__ void pin(T &v) {
 // finally calls `post` with the row product. With the row index (srow) loaded before the
 // matrix entries, a slice costs three dependent memory round trips:
 // {soff, srow} -> {columns, values, row data} -> gathers.
-template <int W, bool NT = false, class T, class Pre, class Post>
+// UP: only the entries with a column above `urow` (the row's later colours) take part; the others
+// are neither gathered nor added.
+template <int W, bool NT = false, bool UP = false, class T, class Pre, class Post>
 __device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
-                                           const T *__restrict__ x, Pre &pre, Post &post) {
+                                           const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   int c[W];
   T v[W];
   if constexpr (NT || std::is_same<T, float>::value) {
@@ -122,6 +128,7 @@ __device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *
   T a0 = 0, a1 = 0;
 #pragma unroll
   for (int k = 0; k < W; ++k) {
+    if (UP && c[k] <= urow) continue;
     if (k & 1)
       a1 += v[k] * x[c[k]];
     else
@@ -132,59 +139,59 @@ __device__ __forceinline__ void sell_row_w(const int *__restrict__ cp, const T *
   post(acc);
 }
 
-template <int W, bool NT, class T>
+template <int W, bool NT, bool UP, class T>
 __device__ __forceinline__ T sell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
-                                        const T *__restrict__ x) {
+                                        const T *__restrict__ x, int urow) {
   T acc = 0;
   auto pre = [] {};
   auto post = [&](T a) { acc = a; };
-  sell_row_w<W, NT>(cp, vp, x, pre, post);
+  sell_row_w<W, NT, UP>(cp, vp, x, pre, post, urow);
   return acc;
 }
 
 // Straight-line cases up to WMAX entries (16, or 32 for matrices with longer rows such as the
 // 3-D transfers); longer rows go in chunks of 8.
-template <class T, int WMAX = 16, bool NT = false, class Pre, class Post>
+template <class T, int WMAX = 16, bool NT = false, bool UP = false, class Pre, class Post>
 __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
-                                         const T *__restrict__ x, Pre &pre, Post &post) {
+                                         const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   switch (w) {
     case 0: pre(); post(T(0)); return;
-    case 1: sell_row_w<1, NT>(cp, vp, x, pre, post); return;
-    case 2: sell_row_w<2, NT>(cp, vp, x, pre, post); return;
-    case 3: sell_row_w<3, NT>(cp, vp, x, pre, post); return;
-    case 4: sell_row_w<4, NT>(cp, vp, x, pre, post); return;
-    case 5: sell_row_w<5, NT>(cp, vp, x, pre, post); return;
-    case 6: sell_row_w<6, NT>(cp, vp, x, pre, post); return;
-    case 7: sell_row_w<7, NT>(cp, vp, x, pre, post); return;
-    case 8: sell_row_w<8, NT>(cp, vp, x, pre, post); return;
-    case 9: sell_row_w<9, NT>(cp, vp, x, pre, post); return;
-    case 10: sell_row_w<10, NT>(cp, vp, x, pre, post); return;
-    case 11: sell_row_w<11, NT>(cp, vp, x, pre, post); return;
-    case 12: sell_row_w<12, NT>(cp, vp, x, pre, post); return;
-    case 13: sell_row_w<13, NT>(cp, vp, x, pre, post); return;
-    case 14: sell_row_w<14, NT>(cp, vp, x, pre, post); return;
-    case 15: sell_row_w<15, NT>(cp, vp, x, pre, post); return;
-    case 16: sell_row_w<16, NT>(cp, vp, x, pre, post); return;
+    case 1: sell_row_w<1, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 2: sell_row_w<2, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 3: sell_row_w<3, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 4: sell_row_w<4, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 5: sell_row_w<5, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 6: sell_row_w<6, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 7: sell_row_w<7, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 8: sell_row_w<8, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 9: sell_row_w<9, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 10: sell_row_w<10, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 11: sell_row_w<11, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 12: sell_row_w<12, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 13: sell_row_w<13, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 14: sell_row_w<14, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 15: sell_row_w<15, NT, UP>(cp, vp, x, pre, post, urow); return;
+    case 16: sell_row_w<16, NT, UP>(cp, vp, x, pre, post, urow); return;
     default: break;
   }
   if constexpr (WMAX > 16) {
     switch (w) {
-      case 17: sell_row_w<17, NT>(cp, vp, x, pre, post); return;
-      case 18: sell_row_w<18, NT>(cp, vp, x, pre, post); return;
-      case 19: sell_row_w<19, NT>(cp, vp, x, pre, post); return;
-      case 20: sell_row_w<20, NT>(cp, vp, x, pre, post); return;
-      case 21: sell_row_w<21, NT>(cp, vp, x, pre, post); return;
-      case 22: sell_row_w<22, NT>(cp, vp, x, pre, post); return;
-      case 23: sell_row_w<23, NT>(cp, vp, x, pre, post); return;
-      case 24: sell_row_w<24, NT>(cp, vp, x, pre, post); return;
-      case 25: sell_row_w<25, NT>(cp, vp, x, pre, post); return;
-      case 26: sell_row_w<26, NT>(cp, vp, x, pre, post); return;
-      case 27: sell_row_w<27, NT>(cp, vp, x, pre, post); return;
-      case 28: sell_row_w<28, NT>(cp, vp, x, pre, post); return;
-      case 29: sell_row_w<29, NT>(cp, vp, x, pre, post); return;
-      case 30: sell_row_w<30, NT>(cp, vp, x, pre, post); return;
-      case 31: sell_row_w<31, NT>(cp, vp, x, pre, post); return;
-      case 32: sell_row_w<32, NT>(cp, vp, x, pre, post); return;
+      case 17: sell_row_w<17, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 18: sell_row_w<18, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 19: sell_row_w<19, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 20: sell_row_w<20, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 21: sell_row_w<21, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 22: sell_row_w<22, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 23: sell_row_w<23, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 24: sell_row_w<24, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 25: sell_row_w<25, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 26: sell_row_w<26, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 27: sell_row_w<27, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 28: sell_row_w<28, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 29: sell_row_w<29, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 30: sell_row_w<30, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 31: sell_row_w<31, NT, UP>(cp, vp, x, pre, post, urow); return;
+      case 32: sell_row_w<32, NT, UP>(cp, vp, x, pre, post, urow); return;
       default: break;
     }
   }
@@ -192,8 +199,11 @@ __device__ __forceinline__ void sell_row(int w, const int *__restrict__ cp, cons
   pre();
   T acc = 0;
   int k = 0;
-  for (; k + 8 <= w; k += 8) acc += sell_chunk<8, NT>(cp + k * 64, vp + k * 64, x);
-  for (; k < w; ++k) acc += vp[k * 64] * x[cp[k * 64]];
+  for (; k + 8 <= w; k += 8) acc += sell_chunk<8, NT, UP>(cp + k * 64, vp + k * 64, x, urow);
+  for (; k < w; ++k) {
+    const int ck = cp[k * 64];
+    if (!UP || ck > urow) acc += vp[k * 64] * x[ck];
+  }
   post(acc);
 }
 
@@ -205,6 +215,11 @@ __device__ __forceinline__ int wave_slice(int first) {
 // MODE 0: Gauss-Seidel pass x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii
 // MODE 1: residual r_i = b_i - a_ii x_i - sum_{j != i} a_ij x_j
 // (dv_ holds 1/a_ii for MODE 0 and a_ii for MODE 1)
+// MODE 2: residual after a single forward sweep from x = 0, r_i = -sum_{j > i} a_ij x_j. When the
+// pass of row i's colour ran, every later colour was still zero and every earlier one final, so
+// b_i - a_ii x_i - sum_{j < i} a_ij x_j = 0 from then on (rows are numbered colour by colour);
+// only the later colours' terms remain. Slice s starts at shi[s] (passed as soff), the widest
+// prefix of entries that lie before the row in every lane; b, dv_ and x_i are not read.
 template <int MODE, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void k_sell(int s0, int s1, const int *__restrict__ srow,
                                                  const int *__restrict__ soff, const int *__restrict__ send,
@@ -216,22 +231,27 @@ __global__ __launch_bounds__(BS_MAX) void k_sell(int s0, int s1, const int *__re
   for_slices<VAR>(s0, s1, shape, srow, soff, send, [&](int row, int o0, int w) {
     T bi = 0, di = 0, xi = 0;
     auto pre = [&] {
+      if (MODE == 2) return;
       const int rr = row < 0 ? 0 : row;
       bi = b[rr];
       di = dv_[rr];
       if (MODE == 1) xi = x[rr];
     };
     auto post = [&](T acc) {
-      pin(bi);
-      pin(di);
+      if (MODE != 2) {
+        pin(bi);
+        pin(di);
+      }
       if (MODE == 1) pin(xi);
       if (row < 0) return;
       if (MODE == 0)
         x[row] = (bi - acc) * di;
-      else
+      else if (MODE == 1)
         r[row] = bi - di * xi - acc;
+      else
+        r[row] = -acc;
     };
-    sell_row<T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
+    sell_row<T, 16, false, MODE == 2>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post, row);
   });
 }
 
@@ -896,6 +916,7 @@ struct DSell {
   std::vector<int> cslice;    // slice range of each colour, C + 1 (host)
   int *srow = nullptr, *soff = nullptr, *scol = nullptr;
   int *slo = nullptr;         // per slice: end of its entries before the group's first row
+  int *shi = nullptr;         // per slice: end of the narrowest such prefix over its rows
   double *sv64 = nullptr;
   float *sv32 = nullptr;
   int64_t entries = 0;        // stored entries including padding
@@ -936,6 +957,7 @@ struct DLevel {
   std::vector<int64_t> cnnz;  // off-diagonal nonzeros of each group's rows
   std::vector<int64_t> ucols; // distinct columns referenced by each group's rows
   std::vector<int64_t> cnnz_lo, ucols_lo;  // the same over columns before the group's first row
+  std::vector<int64_t> cnnz_up, ucols_up;  // the same over columns after the group's last row
   std::vector<int> perm;      // internal -> unknown
   std::vector<int> iperm;     // unknown -> internal
   DCsr A;                     // off-diagonal part
@@ -1096,8 +1118,10 @@ static HCsr transpose(const HCsr &A) {
 // host image of a sliced ELL: built on host threads, uploaded afterwards
 struct SellHost {
   // slo[s]: end of the entries of slice s that lie before its group's first row in every lane
-  // (the widest such prefix over the lanes; rows store their columns in ascending order)
-  std::vector<int> srow, soff, scol, cs, slo;
+  // (the widest such prefix over the lanes; rows store their columns in ascending order);
+  // shi[s]: end of the narrowest such prefix over the slice's rows (entries beyond it may still
+  // lie before some lanes' group)
+  std::vector<int> srow, soff, scol, cs, slo, shi;
   std::vector<double> sv;
   std::vector<float> sv32;
   int widest = 0;
@@ -1329,13 +1353,14 @@ static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> 
       });
       for (size_t s0 = 0; s0 < idx.size(); s0 += 64) {
         const size_t s1 = std::min(s0 + 64, idx.size());
-        int wmax = 0, wlo = 0;
+        int wmax = 0, wlo = 0, whi = INT_MAX;
         for (size_t i = s0; i < s1; ++i) {
           const int r = idx[i];
           wmax = std::max(wmax, H.rp[r + 1] - H.rp[r]);
           int lo = 0;
           while (H.rp[r] + lo < H.rp[r + 1] && H.ci[H.rp[r] + lo] < groups[c].first) ++lo;
           wlo = std::max(wlo, lo);
+          whi = std::min(whi, lo);
         }
         if (wmax > 16) wmax = (wmax + wround - 1) / wround * wround;
         const int base = soff.back();
@@ -1365,6 +1390,7 @@ static SellHost sell_host(const HCsr &H, const Ranges &groups, std::vector<int> 
         }
         soff.push_back(base + 64 * wmax);
         X.slo.push_back(base + 64 * std::min(wlo, wmax));
+        X.shi.push_back(base + 64 * std::min(whi, wmax));
         widest = std::max(widest, wmax);
       }
     }
@@ -1383,6 +1409,7 @@ static void sell_upload(Device *dv, DSell &S, const SellHost &X, bool first_time
     S.srow = dupload(dv, X.srow);
     S.soff = dupload(dv, X.soff);
     S.slo = dupload(dv, X.slo);
+    S.shi = dupload(dv, X.shi);
     S.scol = dupload(dv, X.scol);
     S.sv64 = dupload(dv, X.sv);
     S.sv32 = dupload(dv, X.sv32);
@@ -1421,17 +1448,21 @@ static void stage_level(DLevel &L, const Csr &A, bool first_time, LevelStage &X)
     L.ucols.assign(G, 0);
     L.cnnz_lo.assign(G, 0);
     L.ucols_lo.assign(G, 0);
+    L.cnnz_up.assign(G, 0);
+    L.ucols_up.assign(G, 0);
     std::vector<int> seen(L.n, -1);
     for (int c = 0; c < G; ++c)
       for (int i = L.groups[c].first; i < L.groups[c].second; ++i)
         for (int p = H.rp[i]; p < H.rp[i + 1]; ++p) {
-          const bool lo = H.ci[p] < L.groups[c].first;
+          const bool lo = H.ci[p] < L.groups[c].first, up = H.ci[p] >= L.groups[c].second;
           ++L.cnnz[c];
           L.cnnz_lo[c] += lo;
+          L.cnnz_up[c] += up;
           if (seen[H.ci[p]] != c) {
             seen[H.ci[p]] = c;
             ++L.ucols[c];
             L.ucols_lo[c] += lo;
+            L.ucols_up[c] += up;
           }
         }
   }
@@ -2043,23 +2074,35 @@ static void sweep(Device *dv, DLevel &L, T *x, const T *b, bool from_zero, bool 
 // arithmetic. With whole-level smoothing the kernel skips that colour's slices; their r entries
 // are zeroed at setup and nothing else writes them. `full` covers every row (the residual of an
 // arbitrary iterate, for the nested iteration).
+// `upper`: x is the result of a single forward sweep from zero over the whole level, so each row's
+// residual is minus its later colours' terms (k_sell MODE 2), which reads neither b, the diagonal
+// nor x at the row, and only the entries after each slice's shi.
 template <class T>
-static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s, bool full = false) {
+static void residual(Device *dv, DLevel &L, const T *b, const T *x, T *r, hipStream_t s, bool full = false,
+                     bool upper = false) {
   const DSell &S = L.sell;
   const bool skip = !full && !L.local && L.C >= 1;
+  upper = upper && skip;
   const int s1 = skip ? S.cslice[L.C - 1] : S.nslices;
   slice_launch(dv, s1, s, [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
     with_var(var, [&](auto vc) {
-      launch_timed((k_sell<1, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow, S.soff,
-                   S.soff + 1,
-                   S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
+      if (upper)
+        launch_timed((k_sell<2, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
+                     S.shi, S.soff + 1, S.scol, sell_vals<T>(S), (const T *)nullptr, (const T *)nullptr, (T *)x, r,
+                     shape_arg(th, xcd));
+      else
+        launch_timed((k_sell<1, T, decltype(vc)::value>), slice_blocks(s1, th, var), th, s, e0, e1, 0, s1, S.srow,
+                     S.soff, S.soff + 1, S.scol, sell_vals<T>(S), LV<T>::dg(L), b, (T *)x, r, shape_arg(th, xcd));
     });
   });
   if (S.nslices == 0) return;
   if (dv->count_bytes)
     for (size_t g = 0; g < (skip ? (size_t)(L.C - 1) : L.groups.size()); ++g) {
       const double rows = L.groups[g].second - L.groups[g].first;
-      dv->bytes += (double)L.cnnz[g] * (sizeof(T) + 4) + 4.0 * rows + 4.0 * sizeof(T) * rows;
+      if (upper)  // the later colours' entries, row index, r written, each gathered x entry once
+        dv->bytes += (double)L.cnnz_up[g] * (sizeof(T) + 4) + 4.0 * rows + sizeof(T) * (rows + (double)L.ucols_up[g]);
+      else
+        dv->bytes += (double)L.cnnz[g] * (sizeof(T) + 4) + 4.0 * rows + 4.0 * sizeof(T) * rows;
     }
 }
 
@@ -2242,7 +2285,7 @@ static void vcycle(Device *dv, int l, hipStream_t s) {
   const bool nb = L.nb.n > 0;
   for (int k = 0; k < dv->nu_aux; ++k) sweep<T>(dv, L, x, b, k == 0, true, true, s);
   if (nb) nb_correct<T>(dv, L, x, b, s);
-  residual<T>(dv, L, b, x, LV<T>::r(L), s, nb);
+  residual<T>(dv, L, b, x, LV<T>::r(L), s, nb, UPPER_RESIDUAL && dv->nu_aux == 1 && !nb);
   restrict_to<T>(dv, L.PT, LV<T>::r(L), l - 1, s);
   vcycle<T>(dv, l - 1, s);
   spmv<T, 1>(dv, L.P, lvl_x<T>(dv, l - 1), x, s, true);
@@ -2272,7 +2315,7 @@ static void apply_Bco(Device *dv, const double *r, bool first_done, hipStream_t 
     b = F.b32;
   }
   for (int k = 0; k < dv->nu_fine; ++k) sweep<T>(dv, F, x, b, k == 0, first_done, true, s);
-  residual<T>(dv, F, b, x, LV<T>::r(F), s);
+  residual<T>(dv, F, b, x, LV<T>::r(F), s, false, UPPER_RESIDUAL && dv->nu_fine == 1);
   restrict_to<T>(dv, dv->PiT, LV<T>::r(F), dv->J, s);
   vcycle<T>(dv, dv->J, s);
   spmv<T, 1>(dv, dv->Pi, lvl_x<T>(dv, dv->J), x, s, true);
