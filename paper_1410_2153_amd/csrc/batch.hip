@@ -773,6 +773,8 @@ struct BatchDevice {
   BCsr fineA;                     // CSR of the original grids (true residual, restart)
   SegTable fine_sp;               // per-mesh row-group blocks for the CSR kernels
   BSell cg_sell;                  // mesh-major sliced ELL (whole 4-slice blocks per mesh) for q = A p
+  BSell fine_up;                  // the later colours' entries of every row, negated (r = U x after
+                                  // a single fine sweep from zero), rows that have any
   int *cg_b0 = nullptr;           // first block of each mesh in cg_sell (nm + 1)
   int ew_blocks = 0;              // element-wise blocks: (mesh, 256-row chunk)
   int *ew_m = nullptr, *ew_r0 = nullptr, *ew_r1 = nullptr, *ew_b0 = nullptr;
@@ -1275,7 +1277,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       HMat A;
       std::vector<double> diag;
       std::vector<uint8_t> c0flag;
-      BSellHost gs, cg;
+      BSellHost gs, cg, up;
       GroupCounts counts;  // byte-model counts of every colour group
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
@@ -1312,10 +1314,41 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
           }
         bsell_host(X.A, groups, false, X.gs);
         group_counts(X.A, groups, X.counts);
-        // CG products: group m = mesh m, whole blocks per mesh
+        // CG products: group m = mesh m, whole blocks per mesh, each mesh's rows in Morton order of
+        // their vertices: a slice's rows of every colour gather neighbouring lines of p, so each line
+        // is fetched about once per product (in colour order, once per colour that gathers it)
+        std::vector<int> mo;
+        mo.reserve(F.nrows);
+        for (int m = 0; m < nm; ++m)
+          for (int r : fine[m].morton) mo.push_back(F.off[m] + r);
         Groups mg(nm);
         for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
-        bsell_host(X.A, mg, true, X.cg);
+        bsell_host(X.A, mg, true, X.cg, &mo);
+        // residual after a single forward sweep from zero: r = U x with U the later colours' entries
+        // of each row (columns above the row: each mesh numbers its rows colour by colour), negated;
+        // the rows that have such entries, in Morton order. The other rows' r stays zero.
+        HMat U;
+        U.nrows = X.A.nrows;
+        U.ncols = X.A.ncols;
+        U.rp.assign((size_t)X.A.nrows + 1, 0);
+        std::vector<uint8_t> used(std::max(X.A.ncols, 1), 0);
+        int ucols = 0;
+        for (int i = 0; i < X.A.nrows; ++i) {
+          for (int q = X.A.rp[i]; q < X.A.rp[i + 1]; ++q)
+            if (X.A.ci[q] > i) {
+              U.ci.push_back(X.A.ci[q]);
+              U.v.push_back(-X.A.v[q]);
+              ucols += !used[X.A.ci[q]];
+              used[X.A.ci[q]] = 1;
+            }
+          U.rp[i + 1] = (int)U.ci.size();
+        }
+        std::vector<int> uo;
+        for (int r : mo)
+          if (U.rp[r + 1] > U.rp[r]) uo.push_back(r);
+        bsell_host(U, {{{0, (int)uo.size()}}}, false, X.up, &uo);
+        X.up.nrows = (int)uo.size();  // byte model: rows written, distinct x entries gathered
+        X.up.ncols = ucols;
       } else if (t == 1) {
         // Pi (fine rows -> merged level 0 rows)
         HMat Pi;
@@ -1429,6 +1462,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       bsell_upload(dv, X.gs, F.sell);
       set_counts(F, std::move(X.counts));
       bsell_upload(dv, X.cg, dv->cg_sell);
+      bsell_upload(dv, X.up, dv->fine_up);
       dv->cg_b0 = bupload(dv, X.cg.block0);
       dv->fine_sp = make_mesh_blocks(dv, r0, r1, BS / dv->fineA.lpr);
       X = LevelImage();
@@ -1780,7 +1814,10 @@ static void b_apply(BatchDevice *dv, const double *r, bool first_done, hipStream
     b = F.b32;
   }
   for (int it = 0; it < dv->nu_fine; ++it) b_sweep<NR, T>(dv, F, b, it == 0, first_done, true, s);
-  b_residual<NR, T>(dv, F, b, s, UPPER_RESIDUAL && dv->nu_fine == 1);
+  if (UPPER_RESIDUAL && dv->nu_fine == 1)
+    b_spmv<NR, 0, 0, T>(dv, dv->fine_up, BV<T>::x(F), BV<T>::r(F), nullptr, s);  // r = U x (U negated)
+  else
+    b_residual<NR, T>(dv, F, b, s, false);
   b_spmv<NR, 0, 1, T>(dv, dv->PiT, BV<T>::r(F), BV<T>::b(dv->aux[0]), &dv->aux[0], s);
   b_vcycle<NR, T>(dv, 0, s);
   b_spmv<NR, 1, 0, T>(dv, dv->Pi, BV<T>::x(dv->aux[0]), BV<T>::x(F), nullptr, s);
