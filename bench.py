@@ -599,9 +599,10 @@ def main():
                    "max_true_rel_residual_fp64": b["fp64"]["max_true_rel_residual"], "setup_s": b["setup_s"]},
         "mixed": b["mixed"],
         "vcycle": vc,
-        "roofline": {"bound": "hbm", "kernel": "asmg::kb_sell<0, 4, double, VAR> (batched Gauss-Seidel colour pass, "
-                                               "sliced ELL, 4 interleaved right-hand sides; VAR = the variant "
-                                               "tuned per launch site; traffic from a run with the default, VAR 0)",
+        "roofline": {"bound": "hbm", "kernel": "asmg::kb_sell<MODE, 4, double, VAR> (batched Gauss-Seidel colour "
+                                               "pass, sliced ELL, 4 interleaved right-hand sides; MODE 3 in sweeps "
+                                               "from zero, 0 otherwise; VAR = the variant tuned per launch site; "
+                                               "traffic from a run with the default, VAR 0)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": crec.get("traffic_bytes_per_launch"), "bytes_per_launch": gs["bytes_per_launch"],
                      "ms_per_launch": gs["ms_per_launch"]},

@@ -59,7 +59,8 @@ WORKLOADS = {
     "cube2M": dict(kernel="asmg::k_sell<0, double, 0>", sources=("device.hip", "common.hpp"),
                    bench="--only cube3d", engine="single",
                    desc="Kuhn cube 128^3 x 6 tetrahedra, 2048383 unknowns, FP64 and mixed solves"),
-    "batched256x4": dict(kernel="asmg::kb_sell<0, 4, double, 0>", sources=("batch.hip", "common.hpp"),
+    "batched256x4": dict(kernel=("asmg::kb_sell<0, 4, double, 0>", "asmg::kb_sell<3, 4, double, 0>"),
+                         sources=("batch.hip", "common.hpp"),
                          bench="--only batched", engine="batch",
                          desc="256 jittered squares (sides 32..512) x 4 right-hand sides, FP64 and mixed solves"),
 }
@@ -81,13 +82,16 @@ def _name(kernel_name):
 
 
 def _per_dispatch(path, counter, kernel):
+    """Mean counter value over the dispatches of `kernel` (a name, or a tuple of names averaged
+    together), and the value for the calibration copy."""
+    names = kernel if isinstance(kernel, tuple) else (kernel,)
     vals, copies = [], []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         name = _name(r["Kernel_Name"])
         v = float(r["Counter_Value"])
-        if name == kernel:
+        if name in names:
             vals.append(v)
         elif name.startswith("__amd_rocclr_copyBuffer"):
             copies.append((int(r["Grid_Size"]), v))
@@ -163,7 +167,7 @@ def record(workload, fetch_csv, write_csv):
            "python3 <repo>/bench.py --steps 1 --warmup 0 " + wl["bench"] +
            " --no-kernel-timing --copy-calibration --autotune 0")
     return {
-        "kernel": kernel,
+        "kernel": " and ".join(kernel) if isinstance(kernel, tuple) else kernel,
         "workload": wl["desc"],
         "launch_shape": "256 threads per block, XCD-contiguous block order at every launch site",
         "kernel_code_key": source_key(_srcs(*wl["sources"])),

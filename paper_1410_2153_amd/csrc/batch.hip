@@ -91,8 +91,9 @@ __device__ __forceinline__ void bpin(T &v) {
   asm volatile("" : "+v"(v));
 }
 
-// UP: only the entries with a column above `urow` (the row's later colours) are gathered and added
-template <int W, int NR, bool UP = false, class T, class Pre, class Post>
+// MASK 1: only the entries with a column above `urow` (the row's later colours) are gathered and
+// added; MASK 2: only those with a column below it (its earlier colours); MASK 0: every entry
+template <int W, int NR, int MASK = 0, class T, class Pre, class Post>
 __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T *__restrict__ vp,
                                             const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   const VecR<NR, T> *X = reinterpret_cast<const VecR<NR, T> *>(x);
@@ -117,7 +118,7 @@ __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T 
   for (int r = 0; r < NR; ++r) a0[r] = a1[r] = 0;
 #pragma unroll
   for (int k = 0; k < W; ++k) {
-    if (UP && c[k] <= urow) continue;
+    if ((MASK == 1 && c[k] <= urow) || (MASK == 2 && c[k] >= urow)) continue;
     const VecR<NR, T> xv = X[c[k]];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -136,7 +137,7 @@ __device__ __forceinline__ void bsell_row_w(const int *__restrict__ cp, const T 
   post(acc);
 }
 
-template <int NR, bool UP, class T>
+template <int NR, int MASK, class T>
 __device__ __forceinline__ void bsell_chunk(const int *__restrict__ cp, const T *__restrict__ vp,
                                             const T *__restrict__ x, T acc[NR], int urow) {
   auto pre = [] {};
@@ -144,10 +145,10 @@ __device__ __forceinline__ void bsell_chunk(const int *__restrict__ cp, const T 
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] += a[r];
   };
-  bsell_row_w<8, NR, UP>(cp, vp, x, pre, post, urow);
+  bsell_row_w<8, NR, MASK>(cp, vp, x, pre, post, urow);
 }
 
-template <int NR, class T, bool UP = false, class Pre, class Post>
+template <int NR, class T, int MASK = 0, class Pre, class Post>
 __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, const T *__restrict__ vp,
                                           const T *__restrict__ x, Pre &pre, Post &post, int urow = 0) {
   switch (w) {
@@ -159,18 +160,18 @@ __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, con
       post(z);
       break;
     }
-    case 1: bsell_row_w<1, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 2: bsell_row_w<2, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 3: bsell_row_w<3, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 4: bsell_row_w<4, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 5: bsell_row_w<5, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 6: bsell_row_w<6, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 7: bsell_row_w<7, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 8: bsell_row_w<8, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 9: bsell_row_w<9, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 10: bsell_row_w<10, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 11: bsell_row_w<11, NR, UP>(cp, vp, x, pre, post, urow); break;
-    case 12: bsell_row_w<12, NR, UP>(cp, vp, x, pre, post, urow); break;
+    case 1: bsell_row_w<1, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 2: bsell_row_w<2, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 3: bsell_row_w<3, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 4: bsell_row_w<4, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 5: bsell_row_w<5, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 6: bsell_row_w<6, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 7: bsell_row_w<7, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 8: bsell_row_w<8, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 9: bsell_row_w<9, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 10: bsell_row_w<10, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 11: bsell_row_w<11, NR, MASK>(cp, vp, x, pre, post, urow); break;
+    case 12: bsell_row_w<12, NR, MASK>(cp, vp, x, pre, post, urow); break;
     default: {
       // long rows: chunks of 8 entries, each with its loads issued together
       pre();
@@ -179,10 +180,10 @@ __device__ __forceinline__ void bsell_row(int w, const int *__restrict__ cp, con
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = 0;
       int k = 0;
-      for (; k + 8 <= w; k += 8) bsell_chunk<NR, UP>(cp + k * 64, vp + k * 64, x, acc, urow);
+      for (; k + 8 <= w; k += 8) bsell_chunk<NR, MASK>(cp + k * 64, vp + k * 64, x, acc, urow);
       for (; k < w; ++k) {
         const int ck = cp[k * 64];
-        if (UP && ck <= urow) continue;
+        if ((MASK == 1 && ck <= urow) || (MASK == 2 && ck >= urow)) continue;
         const T a = vp[k * 64];
         const VecR<NR, T> xv = X[ck];
 #pragma unroll
@@ -203,6 +204,9 @@ __device__ __forceinline__ int bwave_slice(int first) {
 // when row i's colour was solved its later colours were zero and its earlier ones final, so only
 // the later colours' terms remain (each mesh numbers its rows colour by colour). Slice s starts
 // at shi[s] (passed as soff); b, dv_ and x at the row are not read.
+// MODE 3: the Gauss-Seidel pass of MODE 0 in a sweep from x = 0, reading only each row's earlier
+// colours (columns below the row; slices end at slo[s], passed as send). The later colours are
+// zero at that point in exact terms but are not read, so x need not be cleared beforehand.
 // over slices [s0, s1), every right-hand side of a row at once
 template <int MODE, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__restrict__ srow,
@@ -232,16 +236,20 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell(int s0, int s1, const int *__r
       VecR<NR, T> o;
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        o.v[q] = MODE == 0 ? (bv.v[q] - acc[q]) * di : MODE == 1 ? bv.v[q] - di * xv.v[q] - acc[q] : -acc[q];
-      reinterpret_cast<VecR<NR, T> *>(MODE == 0 ? x : r)[row] = o;
+        o.v[q] = MODE == 0 || MODE == 3 ? (bv.v[q] - acc[q]) * di
+                 : MODE == 1           ? bv.v[q] - di * xv.v[q] - acc[q]
+                                       : -acc[q];
+      reinterpret_cast<VecR<NR, T> *>(MODE == 0 || MODE == 3 ? x : r)[row] = o;
     };
-    bsell_row<NR, T, MODE == 2>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post, row);
+    bsell_row<NR, T, MODE == 2 ? 1 : MODE == 3 ? 2 : 0>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post, row);
   });
 }
 
 // transfer product y = A x (ADD 0) or y += A x (ADD 1). FIRST (ADD 0): y is the right-hand side
 // of a level whose smoothing starts from zero; the kernel also runs its first colour pass,
-// xs_i = y_i * id0_i with id0_i = 1/a_ii on colour-0 rows of their mesh and 0 elsewhere.
+// xs_i = y_i * id0_i on the colour-0 rows of their mesh (id0_i = 1/a_ii there, 0 elsewhere).
+// The other rows of xs are left as they are: the sweep's later passes read only earlier colours
+// (kb_sell MODE 3), and each of them writes its own rows.
 template <int ADD, int FIRST, int NR, class T, int VAR = 0>
 __global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__restrict__ srow,
                                                        const int *__restrict__ soff, const int *__restrict__ scol,
@@ -267,26 +275,28 @@ __global__ __launch_bounds__(BS_MAX) void kb_sell_spmv(int ns, const int *__rest
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
         o.v[q] = ADD ? yv.v[q] + acc[q] : acc[q];
-        f.v[q] = di != T(0) ? acc[q] * di : T(0);
+        f.v[q] = acc[q] * di;
       }
       reinterpret_cast<VecR<NR, T> *>(y)[row] = o;
-      if (FIRST) reinterpret_cast<VecR<NR, T> *>(xs)[row] = f;
+      if (FIRST && di != T(0)) reinterpret_cast<VecR<NR, T> *>(xs)[row] = f;
     };
     bsell_row<NR, T>(w, scol + o0 + lane, sv + o0 + lane, x, pre, post);
   });
 }
 
-// first colour pass of a sweep from zero on its own: x_i = b_i * id0_i (0 off colour 0)
+// first colour pass of a sweep from zero on its own: x_i = b_i * id0_i on colour 0 (other rows
+// are written by the later passes, which do not read them before)
 template <int NR, class T>
 __global__ __launch_bounds__(BS) void kb_first(int n, const T *__restrict__ b, const T *__restrict__ id0,
                                                T *__restrict__ x) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i >= n) return;
   const T d = id0[i];
+  if (d == T(0)) return;
   const VecR<NR, T> bv = reinterpret_cast<const VecR<NR, T> *>(b)[i];
   VecR<NR, T> o;
 #pragma unroll
-  for (int q = 0; q < NR; ++q) o.v[q] = d != T(0) ? bv.v[q] * d : T(0);
+  for (int q = 0; q < NR; ++q) o.v[q] = bv.v[q] * d;
   reinterpret_cast<VecR<NR, T> *>(x)[i] = o;
 }
 
@@ -301,10 +311,10 @@ __global__ __launch_bounds__(BS) void kb_first_cvt(int n, const double *__restri
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     bo.v[q] = (float)r[(size_t)i * NR + q];
-    o.v[q] = d != 0.0f ? bo.v[q] * d : 0.0f;
+    o.v[q] = bo.v[q] * d;
   }
   reinterpret_cast<VecR<NR, float> *>(b32)[i] = bo;
-  reinterpret_cast<VecR<NR, float> *>(x)[i] = o;
+  if (d != 0.0f) reinterpret_cast<VecR<NR, float> *>(x)[i] = o;
 }
 
 // bottom solves of the meshes whose V-cycle ends on this level: y = M_m g, one wave per row
@@ -498,8 +508,8 @@ __global__ __launch_bounds__(BS) void kb_fin_spmv(const int *__restrict__ m_b0, 
 }
 
 // u += alpha p, r -= alpha q per system; partials of ||r||^2. The same pass runs the first
-// colour pass of the next B_co on the new r in precision T: xf = r * id0 (0 off colour 0),
-// and in FP32 also bf = (float) r.
+// colour pass of the next B_co on the new r in precision T: xf = r * id0 on colour 0 (the other
+// rows of xf are written by the sweep's later passes), and in FP32 also bf = (float) r.
 template <int NR, class T>
 __global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ ew_m, const int *__restrict__ ew_r0,
                                                  const int *__restrict__ ew_r1, double *__restrict__ u,
@@ -531,12 +541,12 @@ __global__ __launch_bounds__(BS) void kb_cg_axpy(const int *__restrict__ ew_m, c
         v[k] = rv.v[k] * rv.v[k];
       }
       bo.v[k] = (T)rv.v[k];
-      xo.v[k] = d != T(0) ? bo.v[k] * d : T(0);
+      xo.v[k] = bo.v[k] * d;
     }
     reinterpret_cast<V *>(u)[row] = uv;
     reinterpret_cast<V *>(r)[row] = rv;
     if constexpr (sizeof(T) == 4) reinterpret_cast<VecR<NR, T> *>(bf)[row] = bo;
-    reinterpret_cast<VecR<NR, T> *>(xf)[row] = xo;
+    if (d != T(0)) reinterpret_cast<VecR<NR, T> *>(xf)[row] = xo;  // colour 0 only, as kb_first
   }
   bwrite<NR>(v, partials);
 }
@@ -1682,9 +1692,12 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
   T *x = BV<T>::x(L);
   const BSell &S = L.sell;
   const int C = (int)S.cslice.size() - 1;
-  // `lower`: the pass belongs to a sweep from zero, where every neighbour of a later colour is
-  // still zero; it reads only the prefix of each row's entries that holds the earlier colours
-  auto pass = [&](int c, bool lower) {
+  // `from0`: the pass belongs to a sweep from zero, where every neighbour of a later colour is
+  // still zero in exact terms but may hold anything in memory: it adds only the earlier colours'
+  // entries (kb_sell MODE 3) and, with LOWER_FIRST_SWEEP, reads only the prefix of each slice's
+  // entries that holds them (`lower`)
+  auto pass = [&](int c, bool from0) {
+    const bool lower = LOWER_FIRST_SWEEP && from0;
     const int s0 = S.cslice[c], s1 = S.cslice[c + 1];
     // algorithmic bytes of the pass: the colour's matrix rows (values, columns, one row index),
     // b, 1/diag and the x write of its rows, each distinct gathered x entry once
@@ -1695,9 +1708,15 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
         dv, s1 - s0, s,
         [&](int th, int xcd, int var, hipEvent_t e0, hipEvent_t e1) {
           with_var(var, [&](auto vc) {
-            launch_timed((kb_sell<0, NR, T, decltype(vc)::value>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1,
-                         S.srow, S.soff, lower ? S.slo : S.soff + 1, S.scol, bsv<T>(S), BV<T>::id(L), b, x,
-                         (T *)nullptr, shape_arg(th, xcd));
+            constexpr int V = decltype(vc)::value;
+            if (from0)
+              launch_timed((kb_sell<3, NR, T, V>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1, S.srow,
+                           S.soff, lower ? S.slo : S.soff + 1, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr,
+                           shape_arg(th, xcd));
+            else
+              launch_timed((kb_sell<0, NR, T, V>), slice_blocks(s1 - s0, th, var), th, s, e0, e1, s0, s1, S.srow,
+                           S.soff, S.soff + 1, S.scol, bsv<T>(S), BV<T>::id(L), b, x, (T *)nullptr,
+                           shape_arg(th, xcd));
           });
         },
         by);
@@ -1710,7 +1729,7 @@ static void b_sweep(BatchDevice *dv, BLevel &L, const T *b, bool from_zero, bool
         hipLaunchKernelGGL((kb_first<NR, T>), dim3(nblk(L.nsmooth)), dim3(BS), 0, s, L.nsmooth, b, bid0<T>(L), x);
       c = 1;
     }
-    for (; c < C; ++c) pass(c, lower);
+    for (; c < C; ++c) pass(c, from_zero);
   } else {
     for (int c = C - 1; c >= 0; --c) pass(c, false);
   }
@@ -1772,9 +1791,13 @@ static void b_spmv(BatchDevice *dv, const BSell &A, const T *x, T *y, BLevel *Lt
                    FIRST ? BV<T>::x(*Lt) : (T *)nullptr, shape_arg(th, xcd));
     });
   });
-  if (dv->count_bytes)
-    dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD + FIRST) * (double)A.nrows) +
+  if (dv->count_bytes) {
+    // matrix, x gathered, y written (and read with ADD); FIRST: 1/a_ii read on every row, the
+    // first pass's x written on the colour-0 rows
+    const double c0 = FIRST && Lt && !Lt->crows.empty() ? (double)Lt->crows[0] : 0.0;
+    dv->bytes += bsell_bytes(A, sizeof(T)) + (double)sizeof(T) * NR * (A.ncols + (1 + ADD) * (double)A.nrows + c0) +
                  (FIRST ? (double)sizeof(T) * A.nrows : 0.0);
+  }
 }
 
 template <int NR, class T>
