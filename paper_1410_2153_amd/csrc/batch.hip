@@ -317,34 +317,51 @@ __global__ __launch_bounds__(BS) void kb_first_cvt(int n, const double *__restri
   if (d != 0.0f) reinterpret_cast<VecR<NR, float> *>(x)[i] = o;
 }
 
-// bottom solves of the meshes whose V-cycle ends on this level: y = M_m g, one wave per row
+// bottom solves of the meshes whose V-cycle ends on this level: y = M_m g. A wave computes
+// kGemvRows consecutive rows of one mesh, so that each gathered g entry (NR values) serves all of
+// them: per row the wave streams n entries of M from HBM and n / kGemvRows entries of g from L2
+// (one row per wave read g once per row, four times the bytes of M with four right-hand sides).
+constexpr int kGemvRows = 4;
+
 template <int NR, class T>
-__global__ __launch_bounds__(BS) void kb_gemv(const int *__restrict__ rowpref, int nb, const int *__restrict__ nc,
+__global__ __launch_bounds__(BS) void kb_gemv(const int *__restrict__ wavepref, int nb, const int *__restrict__ nc,
                                               const int64_t *__restrict__ moff, const int *__restrict__ voff,
                                               const T *__restrict__ M, const T *__restrict__ g, T *__restrict__ y) {
   const int w = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (w >= rowpref[nb]) return;  // whole wave leaves together
-  const int s = find_seg(rowpref, nb, w);
-  const int i = w - rowpref[s], n = nc[s];
-  const T *m = M + moff[s] + (int64_t)i * n;
+  if (w >= wavepref[nb]) return;  // whole wave leaves together
+  const int s = find_seg(wavepref, nb, w);
+  const int n = nc[s];
+  const int i0 = (w - wavepref[s]) * kGemvRows;
+  const int nr = min(kGemvRows, n - i0);
+  const T *m = M + moff[s] + (int64_t)i0 * n;
   const VecR<NR, T> *G = reinterpret_cast<const VecR<NR, T> *>(g) + voff[s];
-  T acc[NR];
+  T acc[kGemvRows][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0;
+  for (int k = 0; k < kGemvRows; ++k)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[k][r] = 0;
   for (int j = lane; j < n; j += 64) {
-    const T a = m[j];
     const VecR<NR, T> gv = G[j];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] += a * gv.v[r];
+    for (int k = 0; k < kGemvRows; ++k) {
+      const T a = k < nr ? m[(int64_t)k * n + j] : T(0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[k][r] += a * gv.v[r];
+    }
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = group_sum<64>(acc[r]);
-  if (lane == 0) {
+  for (int k = 0; k < kGemvRows; ++k)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[k][r] = group_sum<64>(acc[k][r]);
+  if (lane < nr) {
     VecR<NR, T> o;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) o.v[r] = acc[r];
-    reinterpret_cast<VecR<NR, T> *>(y)[voff[s] + i] = o;
+    for (int k = 0; k < kGemvRows; ++k)
+      if (k == lane)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) o.v[r] = acc[k][r];
+    reinterpret_cast<VecR<NR, T> *>(y)[voff[s] + i0 + lane] = o;
   }
 }
 
@@ -766,11 +783,12 @@ struct BLevel {
                          // columns of the last colour group)
   // bottom meshes
   int nbottom = 0;
-  int *bt_rowpref = nullptr, *bt_nc = nullptr, *bt_voff = nullptr;
+  int *bt_wavepref = nullptr, *bt_nc = nullptr, *bt_voff = nullptr;  // waves of kb_gemv per mesh (prefix)
   int64_t *bt_moff = nullptr;
   double *inv64 = nullptr;
   float *inv32 = nullptr;
-  int bottom_rows = 0;
+  int bottom_waves = 0;
+  double bt_entries = 0, bt_rows = 0;  // byte model: inverse entries, rows of the bottom meshes
 };
 
 struct BatchDevice {
@@ -1291,6 +1309,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       GroupCounts counts;  // byte-model counts of every colour group
       // bottom meshes
       std::vector<int> pref{0}, ncs, voff;
+      double bt_entries = 0, bt_rows = 0;
       std::vector<int64_t> moff;
       std::vector<double> inv;
       std::vector<float> inv32;
@@ -1423,7 +1442,9 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
           X.voff.push_back(L.off[smooth_m[k].size() + i]);
           X.moff.push_back((int64_t)X.inv.size());
           X.inv.insert(X.inv.end(), H[m]->coarse_inv.begin(), H[m]->coarse_inv.end());
-          X.pref.push_back(X.pref.back() + nc);
+          X.pref.push_back(X.pref.back() + (nc + kGemvRows - 1) / kGemvRows);  // waves of kb_gemv
+          X.bt_entries += (double)nc * nc;
+          X.bt_rows += nc;
         }
         X.inv32.assign(X.inv.begin(), X.inv.end());
       } else {
@@ -1500,8 +1521,10 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       bsell_upload(dv, X.gs, L.sell);
       set_counts(L, std::move(X.counts));
       upload_diag(dv, L, X.diag, X.c0flag);
-      L.bottom_rows = X.pref.back();
-      L.bt_rowpref = bupload(dv, X.pref);
+      L.bottom_waves = X.pref.back();
+      L.bt_entries = X.bt_entries;
+      L.bt_rows = X.bt_rows;
+      L.bt_wavepref = bupload(dv, X.pref);
       L.bt_nc = bupload(dv, X.ncs);
       L.bt_voff = bupload(dv, X.voff);
       L.bt_moff = bupload(dv, X.moff);
@@ -1804,9 +1827,11 @@ template <int NR, class T>
 static void b_vcycle(BatchDevice *dv, int k, hipStream_t s) {
   BLevel &L = dv->aux[k];
   const T *b = BV<T>::b(L);
-  if (L.nbottom > 0 && L.bottom_rows > 0) {
-    hipLaunchKernelGGL((kb_gemv<NR, T>), dim3(nblk((int64_t)L.bottom_rows * 64)), dim3(BS), 0, s, L.bt_rowpref,
+  if (L.nbottom > 0 && L.bottom_waves > 0) {
+    hipLaunchKernelGGL((kb_gemv<NR, T>), dim3(nblk((int64_t)L.bottom_waves * 64)), dim3(BS), 0, s, L.bt_wavepref,
                        L.nbottom, L.bt_nc, L.bt_moff, L.bt_voff, BV<T>::inv(L), b, BV<T>::x(L));
+    // the bottom inverses, g read and y written
+    if (dv->count_bytes) dv->bytes += L.bt_entries * sizeof(T) + 2.0 * NR * sizeof(T) * L.bt_rows;
   }
   if (L.nsmooth == 0) return;
   for (int it = 0; it < dv->nu_aux; ++it) b_sweep<NR, T>(dv, L, b, it == 0, true, true, s);

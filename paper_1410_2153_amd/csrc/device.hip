@@ -287,19 +287,33 @@ __global__ __launch_bounds__(BS_MAX) void k_sell_spmv(int ns, const int *__restr
   });
 }
 
-// dense y = M g at the bottom of the V-cycle (M = A_lc^{-1}, row-major n x n), one wave per row
+// dense y = M g (M row-major n x n: the bottom inverse A_lc^{-1}, or a near-boundary set's
+// inverse). One block per row: its 256 threads stride over the row with up to four loads in
+// flight each, so that some 4n waves share the memory system (one wave per row, about a
+// thousand waves at the bottom level, left most of the chip idle); a fixed-order block sum
+// finishes the row. Launch with gemv() (grid = n blocks).
 template <class T>
 __global__ __launch_bounds__(BS) void k_gemv(int n, const T *__restrict__ M, const T *__restrict__ g,
                                              T *__restrict__ y) {
-  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  T s = 0;
-  if (row < n) {
-    const T *m = M + (size_t)row * n;
-    for (int j = lane; j < n; j += 64) s += m[j] * g[j];
+  const int row = blockIdx.x;
+  const T *m = M + (size_t)row * n;
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int j = threadIdx.x;
+  for (; j + 3 * BS < n; j += 4 * BS) {
+    s0 += m[j] * g[j];
+    s1 += m[j + BS] * g[j + BS];
+    s2 += m[j + 2 * BS] * g[j + 2 * BS];
+    s3 += m[j + 3 * BS] * g[j + 3 * BS];
   }
-  s = group_sum<64>(s);
-  if (row < n && lane == 0) y[row] = s;
+  for (; j < n; j += BS) s0 += m[j] * g[j];
+  double v[1] = {(double)((s0 + s1) + (s2 + s3))};
+  block_sum_n<1>(v);
+  if (threadIdx.x == 0) y[row] = (T)v[0];
+}
+
+template <class T>
+static void gemv(int n, const T *M, const T *g, T *y, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_gemv<T>), dim3(n), dim3(BS), 0, s, n, M, g, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -2229,8 +2243,7 @@ static void nb_correct(Device *dv, DLevel &L, T *x, const T *b, hipStream_t s) {
     hipLaunchKernelGGL((k_nb_res<T>), dim3(slice_blocks(S.nslices, BS)), dim3(BS), 0, s, S.nslices, S.srow, S.soff,
                        S.scol, sell_vals<T>(S), N.jrow, LV<T>::dg(L), b, (const T *)x, r);
   if (N.dense) {
-    hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)N.n * 64)), dim3(BS), 0, s, N.n, NbV<T>::inv(N), (const T *)r,
-                       xj);
+    gemv<T>(N.n, NbV<T>::inv(N), (const T *)r, xj, s);
   } else {
     const int nI = N.nI, nS = N.nS;
     T *y = sizeof(T) == 8 ? (T *)N.y64 : (T *)N.y32;
@@ -2240,8 +2253,7 @@ static void nb_correct(Device *dv, DLevel &L, T *x, const T *b, hipStream_t s) {
     if (nS > 0) {
       hipLaunchKernelGGL((k_nb_csr<T>), dim3(nblk(nS)), dim3(BS), 0, s, nS, N.asi_rp, N.asi_ci, NbV<T>::asi(N),
                          (const T *)y, (const T *)(r + nI), t);
-      hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)nS * 64)), dim3(BS), 0, s, nS, NbV<T>::sinv(N), (const T *)t,
-                         xj + nI);
+      gemv<T>(nS, NbV<T>::sinv(N), (const T *)t, xj + nI, s);
     }
     if (nI > 0) {
       hipLaunchKernelGGL((k_nb_csr<T>), dim3(nblk(nI)), dim3(BS), 0, s, nI, N.ais_rp, N.ais_ci, NbV<T>::ais(N),
@@ -2273,8 +2285,7 @@ template <class T>
 static void vcycle(Device *dv, int l, hipStream_t s) {
   if (l == dv->lc) {
     if (dv->nc > 0) {
-      hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)dv->nc * 64)), dim3(BS), 0, s, dv->nc, cinv<T>(dv),
-                         cvec_b<T>(dv), cvec_x<T>(dv));
+      gemv<T>(dv->nc, cinv<T>(dv), cvec_b<T>(dv), cvec_x<T>(dv), s);
       if (dv->count_bytes) dv->bytes += (double)dv->nc * dv->nc * sizeof(T) + 2.0 * dv->nc * sizeof(T);
     }
     return;
@@ -2358,8 +2369,7 @@ static void nested_start(Device *dv, hipStream_t s) {
   spmv<T, 0>(dv, dv->PiT, fT, NV<T>::g(dv, J), s);
   for (int l = J; l > lc; --l) spmv<T, 0>(dv, dv->aux[l].PT, NV<T>::g(dv, l), NV<T>::g(dv, l - 1), s);
   if (dv->nc > 0)
-    hipLaunchKernelGGL((k_gemv<T>), dim3(nblk((int64_t)dv->nc * 64)), dim3(BS), 0, s, dv->nc, cinv<T>(dv),
-                       (const T *)NV<T>::g(dv, lc), NV<T>::e(dv, lc));
+    gemv<T>(dv->nc, cinv<T>(dv), (const T *)NV<T>::g(dv, lc), NV<T>::e(dv, lc), s);
   for (int l = lc + 1; l <= J; ++l) {
     DLevel &L = dv->aux[l];
     T *e = NV<T>::e(dv, l);
