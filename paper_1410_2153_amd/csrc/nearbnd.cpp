@@ -73,23 +73,35 @@ static void regularise(std::vector<double> &M, int64_t n) {
   }
 }
 
+// sum_k a[k] b[k] over k < n in four interleaved partial sums (independent chains that the
+// compiler can keep in vector registers), combined in a fixed order
+static inline double dot4(const double *a, const double *b, int64_t n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t k = 0;
+  for (; k + 4 <= n; k += 4) {
+    s0 += a[k] * b[k];
+    s1 += a[k + 1] * b[k + 1];
+    s2 += a[k + 2] * b[k + 2];
+    s3 += a[k + 3] * b[k + 3];
+  }
+  for (; k < n; ++k) s0 += a[k] * b[k];
+  return (s0 + s1) + (s2 + s3);
+}
+
 void spd_inverse(std::vector<double> &M, int64_t n, int threads, bool regularised) {
   if (n == 0) return;
   if (regularised) regularise(M, n);
   std::vector<double> Lm(n * n, 0.0);
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j <= i; ++j) Lm[i * n + j] = M[i * n + j];
+  // Cholesky, row by row of L: the entries left of the diagonal are dot products of rows
   for (int64_t j = 0; j < n; ++j) {
-    double s = Lm[j * n + j];
-    for (int64_t k = 0; k < j; ++k) s -= Lm[j * n + k] * Lm[j * n + k];
+    const double *lj = &Lm[j * n];
+    const double s = Lm[j * n + j] - dot4(lj, lj, j);
     if (!(s > 0)) throw AsmgError{ASMG_ENOTSPD, "matrix of an exact subsystem solve is not positive definite"};
     const double djj = std::sqrt(s);
     Lm[j * n + j] = djj;
-    for (int64_t i = j + 1; i < n; ++i) {
-      double t = Lm[i * n + j];
-      for (int64_t k = 0; k < j; ++k) t -= Lm[i * n + k] * Lm[j * n + k];
-      Lm[i * n + j] = t / djj;
-    }
+    for (int64_t i = j + 1; i < n; ++i) Lm[i * n + j] = (Lm[i * n + j] - dot4(&Lm[i * n], lj, j)) / djj;
   }
   // inverse column by column (independent columns on host threads): L y = e_c, L^T x = y;
   // y_i = 0 for i < c, and the backward solve reads L^T by rows
@@ -99,17 +111,9 @@ void spd_inverse(std::vector<double> &M, int64_t n, int threads, bool regularise
   host_parallel(threads, (int)std::min<int64_t>(n, 1 << 30), [&](int cc) {
     const int64_t c = cc;
     std::vector<double> y(n, 0.0), x(n);
-    for (int64_t i = c; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = c; k < i; ++k) s -= Lm[i * n + k] * y[k];
-      y[i] = s / Lm[i * n + i];
-    }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double s = y[i];
-      const double *u = &Ut[i * n];
-      for (int64_t k = i + 1; k < n; ++k) s -= u[k] * x[k];
-      x[i] = s / Lm[i * n + i];
-    }
+    for (int64_t i = c; i < n; ++i)
+      y[i] = ((i == c ? 1.0 : 0.0) - dot4(&Lm[i * n + c], &y[c], i - c)) / Lm[i * n + i];
+    for (int64_t i = n - 1; i >= 0; --i) x[i] = (y[i] - dot4(&Ut[i * n + i + 1], &x[i + 1], n - 1 - i)) / Lm[i * n + i];
     for (int64_t i = 0; i < n; ++i) M[i * n + c] = x[i];
   });
 }
