@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <atomic>
@@ -410,13 +411,20 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
   ASMG_TRY({
     std::unique_ptr<asmg_s> HP(new asmg_s());
     HP->batch.resize(n_meshes);
+    // largest meshes first, so that the last ones to finish are small
+    std::vector<int> order(n_meshes);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return elem_off[a + 1] - elem_off[a] > elem_off[b + 1] - elem_off[b];
+    });
     std::atomic<int> next{0};
     std::vector<AsmgError> errs;
     std::mutex mu;
     auto work = [&]() {
       while (true) {
-        const int m = next.fetch_add(1);
-        if (m >= n_meshes) return;
+        const int i = next.fetch_add(1);
+        if (i >= n_meshes) return;
+        const int m = order[i];
         try {
           auto h = std::make_unique<Hierarchy>();
           h->d = dim;
@@ -444,14 +452,23 @@ int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const doubl
         }
       }
     };
+    const bool tm = std::getenv("ASMG_SETUP_TIMING") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
     const int nt = std::max(1, std::min<int>(n_meshes, (int)std::thread::hardware_concurrency()));
     std::vector<std::thread> th;
     for (int t = 0; t < nt; ++t) th.emplace_back(work);
     for (auto &t : th) t.join();
     if (!errs.empty()) throw errs.front();
+    auto t1 = std::chrono::steady_clock::now();
+    if (tm)
+      std::fprintf(stderr, "[asmg batch setup] meshes (%d threads) %8.3f s\n", nt,
+                   std::chrono::duration<double>(t1 - t0).count());
     HP->h.d = dim;
     HP->h.opt = o;
     if (o.device >= 0) HP->bdev = batch_device_create(HP->batch, o.device);
+    if (tm)
+      std::fprintf(stderr, "[asmg batch setup] device layout %8.3f s\n",
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
     *out = HP.release();
     return ASMG_OK;
   })

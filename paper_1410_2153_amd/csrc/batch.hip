@@ -1323,39 +1323,74 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
       r0.push_back(F.off[m]);
       r1.push_back(F.off[m] + (int)H[m]->n());
     }
-    // tasks: 0 fine level, 1 Pi and Pi^T, 2..K+2 auxiliary levels, then the prolongations
-    host_parallel(0, K + 3 + K, [&](int t) {
+    // ---- the merged original-grid matrix and Pi (inputs of several images below)
+    HMat Pi;
+    BLevel &L0 = dv->aux[0];
+    int Cf = 0;  // colours of the original grids (most over the meshes)
+    host_parallel(0, 2, [&](int t) {
       if (t == 0) {
         LevelImage &X = fine_img;
-        int C = 0;
         for (int m = 0; m < nm; ++m) {
           append_rows(X.A, H[m]->A, fine[m].perm, &fine[m].iperm, F.off[m], true, &X.diag);
-          C = std::max(C, (int)fine[m].coff.size() - 1);
           for (int64_t i = 0; i < H[m]->n(); ++i) X.c0flag.push_back(i < fine[m].coff[1]);
         }
         X.A.ncols = F.nrows;
+      } else {
+        // Pi (fine rows -> merged level 0 rows)
+        for (int m = 0; m < nm; ++m) {
+          const int D = H[m]->J - H[m]->lc;
+          const size_t j = std::find(L0.mesh.begin(), L0.mesh.end(), m) - L0.mesh.begin();
+          const std::vector<int> *cmap = D > 0 ? &lev[m][0].iperm : nullptr;
+          append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
+        }
+        Pi.ncols = L0.nrows;
+      }
+    });
+    for (int m = 0; m < nm; ++m) Cf = std::max(Cf, (int)fine[m].coff.size() - 1);
+    // each mesh's original-grid rows in Morton order of their vertices
+    std::vector<int> mo;
+    mo.reserve(F.nrows);
+    for (int m = 0; m < nm; ++m)
+      for (int r : fine[m].morton) mo.push_back(F.off[m] + r);
+    // the rows of each mesh's last colour, and of the last colour group (meshes with the most
+    // colours), on the original grids
+    std::vector<uint8_t> last(F.nrows, 0), zero(F.nrows, 0);
+    for (int m = 0; m < nm; ++m) {
+      const auto &co = fine[m].coff;
+      const int Cm = (int)co.size() - 1;
+      if (Cm < 1) continue;
+      for (int r = F.off[m] + co[Cm - 1]; r < F.off[m] + co[Cm]; ++r) {
+        last[r] = 1;
+        if (Cm == Cf) zero[r] = 1;
+      }
+    }
+    // tasks: 0-2 the original grids' smoothing, product and residual images, 3-4 Pi and Pi^T,
+    // 5..K+5 the auxiliary levels, then the prolongations
+    host_parallel(0, 2 * K + 6, [&](int t) {
+      if (t == 0) {
+        LevelImage &X = fine_img;
         // Gauss-Seidel passes: group c = colour c of every mesh
-        Groups groups(C);
-        for (int c = 0; c < C; ++c)
+        Groups groups(Cf);
+        for (int c = 0; c < Cf; ++c)
           for (int m = 0; m < nm; ++m) {
             const auto &co = fine[m].coff;
             if (c + 1 < (int)co.size()) groups[c].push_back({F.off[m] + co[c], F.off[m] + co[c + 1]});
           }
         bsell_host(X.A, groups, false, X.gs);
         group_counts(X.A, groups, X.counts);
+      } else if (t == 1) {
         // CG products: group m = mesh m, whole blocks per mesh, each mesh's rows in Morton order of
         // their vertices: a slice's rows of every colour gather neighbouring lines of p, so each line
         // is fetched about once per product (in colour order, once per colour that gathers it)
-        std::vector<int> mo;
-        mo.reserve(F.nrows);
-        for (int m = 0; m < nm; ++m)
-          for (int r : fine[m].morton) mo.push_back(F.off[m] + r);
+        LevelImage &X = fine_img;
         Groups mg(nm);
         for (int m = 0; m < nm; ++m) mg[m].push_back({r0[m], r1[m]});
         bsell_host(X.A, mg, true, X.cg, &mo);
+      } else if (t == 2) {
         // residual after a single forward sweep from zero: r = U x with U the later colours' entries
         // of each row (columns above the row: each mesh numbers its rows colour by colour), negated;
         // the rows that have such entries, in Morton order. The other rows' r stays zero.
+        LevelImage &X = fine_img;
         HMat U;
         U.nrows = X.A.nrows;
         U.ncols = X.A.ncols;
@@ -1378,43 +1413,17 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         bsell_host(U, {{{0, (int)uo.size()}}}, false, X.up, &uo);
         X.up.nrows = (int)uo.size();  // byte model: rows written, distinct x entries gathered
         X.up.ncols = ucols;
-      } else if (t == 1) {
-        // Pi (fine rows -> merged level 0 rows)
-        HMat Pi;
-        BLevel &L0 = dv->aux[0];
-        for (int m = 0; m < nm; ++m) {
-          const int D = H[m]->J - H[m]->lc;
-          const size_t j = std::find(L0.mesh.begin(), L0.mesh.end(), m) - L0.mesh.begin();
-          const std::vector<int> *cmap = D > 0 ? &lev[m][0].iperm : nullptr;
-          append_rows(Pi, H[m]->Pi, fine[m].perm, cmap, L0.off[j], false, nullptr);
-        }
-        Pi.ncols = L0.nrows;
-        // the rows of each mesh's last colour, and of the last colour group (meshes with the most
-        // colours), on the original grids
-        std::vector<uint8_t> last(F.nrows, 0), zero(F.nrows, 0);
-        int C = 0;
-        for (int m = 0; m < nm; ++m) C = std::max(C, (int)fine[m].coff.size() - 1);
-        for (int m = 0; m < nm; ++m) {
-          const auto &co = fine[m].coff;
-          const int Cm = (int)co.size() - 1;
-          if (Cm < 1) continue;
-          for (int r = F.off[m] + co[Cm - 1]; r < F.off[m] + co[Cm]; ++r) {
-            last[r] = 1;
-            if (Cm == C) zero[r] = 1;
-          }
-        }
-        std::vector<int> oPi;
-        for (int m = 0; m < nm; ++m)
-          for (int r : fine[m].morton) oPi.push_back(F.off[m] + r);
-        oPi = keep_rows(oPi, last);
+      } else if (t == 3) {
+        const std::vector<int> oPi = keep_rows(mo, last);
         bsell_host(Pi, {{{0, (int)oPi.size()}}}, false, pi_img, &oPi);
         transfer_stats(Pi, oPi, pi_img);
+      } else if (t == 4) {
         const HMat PiT = drop_cols(htranspose(Pi), zero);
         const std::vector<int> oPiT = natural_rows(L0, 0);
         bsell_host(PiT, {{{0, PiT.nrows}}}, false, pit_img, &oPiT);
         transfer_stats(PiT, oPiT, pit_img);
-      } else if (t < K + 3) {
-        const int k = t - 2;
+      } else if (t < K + 6) {
+        const int k = t - 5;
         BLevel &L = dv->aux[k];
         LevelImage &X = aux_img[k];
         int C = 0;
@@ -1449,7 +1458,7 @@ BatchDevice *batch_device_create(std::vector<std::unique_ptr<Hierarchy>> &H, int
         X.inv32.assign(X.inv.begin(), X.inv.end());
       } else {
         // prolongation P (level k+1 -> k) for the smoothing meshes of level k
-        const int k = t - (K + 3);
+        const int k = t - (K + 6);
         BLevel &L = dv->aux[k], &Lc = dv->aux[k + 1];
         HMat P;
         for (int m : smooth_m[k]) {
