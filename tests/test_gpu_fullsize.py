@@ -126,13 +126,15 @@ def test_adjoint_fullsize_finite_differences():
     assert np.abs(g - ref).max() <= 1e-8 * np.abs(ref).max()
     worst = 0.0
     for k, d in enumerate(c["directions"]):
-        eps = 1e-6
+        eps = 1e-4
         fd = (J(c["m"] + eps * d) - J(c["m"] - eps * d)) / (2 * eps)
         rel = abs(fd - g @ d) / abs(g @ d)
         worst = max(worst, rel)
         _say(f"direction {k}: adjoint {g @ d:.10e} fd {fd:.10e} rel {rel:.2e}")
-        # central differences at eps = 1e-6 with forward solves to 1e-12: the error of each
-        # J evaluation is about tol * ||u - u_obs|| * ||u||, divided by 2 eps it reaches about
-        # 1e-5 of g.d on this mesh; the truncation error (eps^2) is far below
-        assert rel <= 5e-5
+        # central differences with forward solves to 1e-12: the error of each J evaluation is
+        # about tol * ||u - u_obs|| * ||u||, which divided by 2 eps reached up to 6e-5 of g.d at
+        # eps = 1e-6 on this mesh, so it is below 1e-6 at eps = 1e-4; the truncation error
+        # (eps^2) stays below 1e-6 there (exact solves on the 362^2 mesh of this recipe: at most
+        # 9e-7 at eps = 1e-4, 4e-7 at 1e-5)
+        assert rel <= 1e-5
     _say(f"all {len(c['directions'])} directions: worst relative difference {worst:.2e}")
