@@ -78,14 +78,19 @@ def test_adjoint_gradient_finite_differences():
         assert fd == pytest.approx(g @ d, rel=1e-6, abs=1e-12)
 
 
+_HIER = {}  # (cfg, scale) -> (workload, hierarchy), shared by the precision cases below
+
+
 @pytest.mark.parametrize("cfg,scale", [(0, 1.0), (1, 0.01)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_restart_from_true_residual_at_the_fp64_floor(cfg, scale, mixed):
     # Below the FP64 floor of the true residual (about 1.5e-15 relative here) the recursively
     # updated residual still meets tol = 1e-15 while f - A u cannot: CG restarts from the true
     # residual at most 3 times, then returns "ok" with the true residual above tol.
-    c = W.make_config(cfg, scale=scale)
-    H = Hierarchy(c["coords"], c["elems"], c["kappa"])
+    if (cfg, scale) not in _HIER:
+        c = W.make_config(cfg, scale=scale)
+        _HIER[(cfg, scale)] = (c, Hierarchy(c["coords"], c["elems"], c["kappa"]))
+    c, H = _HIER[(cfg, scale)]
     f = c["f_vertex"][H.dofs]
     u, it, info = H.solve(f, 1e-15, mixed=mixed, record=True)
     assert info["status"] == "ok" and info["restarts"] == 3
