@@ -130,6 +130,8 @@ int asmg_default_options(asmg_options *opt);
  *   out          receives the handle (NULL on failure)
  * The auxiliary Dirichlet grids cover the root box, so the domain is expected
  * to be the bounding box (square/cube), as in the paper's test problem.
+ * With the environment variable ASMG_SETUP_TIMING set, the time of each setup
+ * phase is printed on stderr (also asmg_export("setup_seconds")).
  */
 int asmg_setup(int dim, int64_t n_vertices, const double *coords, int64_t n_elements,
                const int32_t *elems, const double *kappa, const uint8_t *dirichlet,
@@ -322,7 +324,8 @@ int asmg_export(asmg_handle h, const char *name, int level, void *buf, int64_t *
  * level by level (level k = k-th auxiliary level below each mesh's finest).
  * Single-mesh entry points return ASMG_EINVAL on a batch handle; asmg_num_dofs
  * returns the total number of unknowns. Exports: "batch_n", "batch_J",
- * "batch_lc" (int64 per mesh).
+ * "batch_lc" (int64 per mesh). With ASMG_SETUP_TIMING set, the times of the
+ * per-mesh setups and of the merged device layout are printed on stderr.
  */
 int asmg_setup_batch(int n_meshes, int dim, const int64_t *vert_off, const double *coords,
                      const int64_t *elem_off, const int32_t *elems, const double *kappa,
