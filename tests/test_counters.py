@@ -35,8 +35,33 @@ def test_traffic_record_scales_by_the_copy(tmp_path):
     assert rec["kernel"] == C.WORKLOADS["graded1M"]["kernel"]
 
 
+def test_batched_record_averages_both_pass_kernels(tmp_path):
+    # the batched colour pass runs as two kernels (sweeps from zero and the others): the record
+    # averages the dispatches of both, and ignores the other kernels
+    names = C.WORKLOADS["batched256x4"]["kernel"]
+    assert isinstance(names, tuple) and len(names) == 2
+    for path, counter, vals, copy in ((tmp_path / "f.csv", "FETCH_SIZE", (100.0, 300.0, 500.0), C.COPY_BYTES / 2048),
+                                      (tmp_path / "w.csv", "WRITE_SIZE", (10.0, 20.0, 60.0), C.COPY_BYTES / 1024)):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, ["Kernel_Name", "Counter_Name", "Counter_Value", "Grid_Size"])
+            w.writeheader()
+            w.writerow({"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": counter, "Counter_Value": copy,
+                        "Grid_Size": 1 << 20})
+            for name, v in zip((names[0], names[1], names[1]), vals):
+                w.writerow({"Kernel_Name": f"void {name}(int, int)", "Counter_Name": counter, "Counter_Value": v,
+                            "Grid_Size": 4096})
+            w.writerow({"Kernel_Name": "void asmg::kb_sell<1, 4, double, 0>(int)", "Counter_Name": counter,
+                        "Counter_Value": 1e9, "Grid_Size": 4096})
+    rec = C.record("batched256x4", tmp_path / "f.csv", tmp_path / "w.csv")
+    assert rec["dispatches"] == 3
+    assert rec["fetch_bytes_per_launch"] == pytest.approx(300.0 * 1024 * 2)
+    assert rec["write_bytes_per_launch"] == pytest.approx(30.0 * 1024)
+    assert rec["kernel"] == " and ".join(names)
+
+
 def test_bco_kernel_classification():
-    yes64 = ["asmg::k_sell<0, double>", "asmg::k_sell<1, double>", "asmg::k_sell_spmv<0, 1, double, 16>",
+    yes64 = ["asmg::k_sell<0, double>", "asmg::k_sell<1, double>", "asmg::k_sell<2, double, 1>",
+             "asmg::k_sell_spmv<0, 1, double, 16>",
              "asmg::k_sell_spmv<1, 0, double, 32>", "asmg::k_gemv<double>", "asmg::k_gs_first<double>"]
     yes32 = [n.replace("double", "float") for n in yes64] + ["asmg::k_gs_first_cvt"]
     no = ["asmg::k_cg_spmv", "asmg::k_cg_rz<double>", "asmg::k_cg_axpy<float>", "asmg::kb_sell<0, 4, double>",
@@ -46,7 +71,8 @@ def test_bco_kernel_classification():
     assert not any(C._bco_kernel(n, p) for n in no for p in ("double", "float"))
     # the batched engine's kernels
     b64 = ["asmg::kb_sell<0, 4, double>", "asmg::kb_sell<1, 2, double>", "asmg::kb_sell_spmv<0, 1, 4, double>",
-           "asmg::kb_sell_spmv<1, 0, 1, double>", "asmg::kb_gemv<4, double>", "asmg::kb_first<4, double>"]
+           "asmg::kb_sell_spmv<1, 0, 1, double>", "asmg::kb_gemv<4, double>", "asmg::kb_first<4, double>",
+           "asmg::kb_sell<2, 4, double, 0>", "asmg::kb_sell<3, 4, double, 1>", "asmg::kb_sell_spmv<0, 0, 4, double, 0>"]
     b32 = [n.replace("double", "float") for n in b64] + ["asmg::kb_first_cvt<4>"]
     bno = ["asmg::kb_cg_spmv<4>", "asmg::kb_cg_rz<4, double>", "asmg::k_sell<0, double>", "asmg::kb_cg_axpy<4, float>"]
     assert all(C._bco_kernel(n, "double", "batch") and not C._bco_kernel(n, "float", "batch") for n in b64)
